@@ -1,0 +1,265 @@
+"""ctypes driver for libhmgen: builds an H-matrix and exposes its leaves.
+
+Every vector index here is in cluster order (the order of the cluster tree's
+leaves); ``perm[i]`` is the original point index at cluster position i.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .geometry import mean_nn_distance
+
+DT_F64, DT_F32, DT_F16, DT_BF16 = 0, 1, 2, 3
+DT_BYTES = {DT_F64: 8, DT_F32: 4, DT_F16: 2, DT_BF16: 2}
+DT_NAMES = {DT_F64: "f64", DT_F32: "f32", DT_F16: "f16", DT_BF16: "bf16"}
+
+KERNEL_LAPLACE, KERNEL_EXP, KERNEL_SEPARABLE = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmgen.so")
+
+_lib = None
+
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run hmgen.build.build()")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.hmg_build_tree.argtypes = [_f64p, C.c_int64, C.c_int32, C.c_double, C.POINTER(vp)]
+    L.hmg_build_tree.restype = C.c_int
+    L.hmg_destroy.argtypes = [vp]
+    L.hmg_num_clusters.argtypes = [vp]
+    L.hmg_num_clusters.restype = C.c_int64
+    L.hmg_num_blocks.argtypes = [vp]
+    L.hmg_num_blocks.restype = C.c_int64
+    L.hmg_get_perm.argtypes = [vp, _i64p]
+    L.hmg_get_clusters.argtypes = [vp, _i64p, _i64p, _i32p, _i32p, _i32p, _f64p]
+    L.hmg_get_blocks.argtypes = [vp, _i64p, _i64p, _i64p, _i64p, _i32p, _i32p, _i32p, _i32p]
+    L.hmg_fill.argtypes = [vp, C.c_int32, _f64p, C.c_double, C.c_double, C.c_int32, C.c_int32]
+    L.hmg_fill.restype = C.c_int
+    L.hmg_get_factor_ptrs.argtypes = [vp, _u64p, _u64p, _u64p]
+    L.hmg_get_ranks.argtypes = [vp, _i32p]
+    L.hmg_eval.argtypes = [vp, _i64p, _i64p, C.c_int64, _f64p]
+    L.hmg_select_precision.argtypes = [vp, C.c_double, C.c_int32, _i32p, _i32p, _i32p, _f64p]
+    L.hmg_select_precision.restype = C.c_int
+    L.hmg_round.argtypes = [_f64p, C.c_int64, C.c_int32, _f64p]
+    L.hmg_truncate.argtypes = [_f64p, _f64p, C.c_int64, C.c_int64, C.c_int32, C.c_double,
+                               _f64p, _f64p, _f64p]
+    L.hmg_truncate.restype = C.c_int
+    _lib = L
+    return L
+
+
+def _view(ptr: int, count: int) -> np.ndarray:
+    if ptr == 0 or count == 0:
+        return np.zeros(0)
+    buf = (C.c_double * count).from_address(int(ptr))
+    return np.ctypeslib.as_array(buf)
+
+
+@dataclass
+class HMatrix:
+    """A constructed H-matrix: block table plus per-block FP64 factors.
+
+    Dense leaf b: ``a`` is D_b (m x n_b, column-major).
+    Low-rank leaf b: ``a`` is U_b (m x k) and ``b`` is V_b (n_b x k),
+    column-major, with M_b = U_b V_b^T; when ``keep_sigma`` the form is
+    W_b diag(s_b) X_b^T with ``a`` = W_b, ``b`` = X_b, ``s`` = s_b.
+    """
+
+    n: int
+    points: np.ndarray
+    kernel: int
+    kparams: np.ndarray
+    leaf: int
+    eta: float
+    eps: float
+    keep_sigma: bool
+    perm: np.ndarray = field(repr=False)
+    rb: np.ndarray = field(repr=False)
+    re: np.ndarray = field(repr=False)
+    cb: np.ndarray = field(repr=False)
+    ce: np.ndarray = field(repr=False)
+    adm: np.ndarray = field(repr=False)
+    rank: np.ndarray = field(repr=False)
+    a_ptr: np.ndarray = field(repr=False)
+    b_ptr: np.ndarray = field(repr=False)
+    s_ptr: np.ndarray = field(repr=False)
+    handle: int = field(repr=False, default=0)
+    build_seconds: float = 0.0
+    ngroups: np.ndarray | None = field(repr=False, default=None)
+    group_cols: np.ndarray | None = field(repr=False, default=None)
+    group_dtype: np.ndarray | None = field(repr=False, default=None)
+    store_err_bound: np.ndarray | None = field(repr=False, default=None)
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.hmg_destroy(C.c_void_p(self.handle))
+            self.handle = 0
+
+    # ------------------------------------------------------------ access
+    @property
+    def nblocks(self) -> int:
+        return int(self.rb.shape[0])
+
+    def shape(self, i: int):
+        return int(self.re[i] - self.rb[i]), int(self.ce[i] - self.cb[i])
+
+    def factors(self, i: int):
+        """numpy views (no copy) of block i's factors: (a, b, s)."""
+        m, nb = self.shape(i)
+        if not self.adm[i]:
+            return _view(self.a_ptr[i], m * nb).reshape(nb, m).T, None, None
+        k = int(self.rank[i])
+        a = _view(self.a_ptr[i], m * k).reshape(k, m).T
+        b = _view(self.b_ptr[i], nb * k).reshape(k, nb).T
+        s = _view(self.s_ptr[i], k) if self.keep_sigma else None
+        return a, b, s
+
+    def kernel_entries(self, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        cols = np.ascontiguousarray(cols, dtype=np.int64)
+        out = np.empty(rows.shape[0])
+        lib().hmg_eval(C.c_void_p(self.handle), rows, cols, rows.shape[0], out)
+        return out
+
+    def points_cluster_order(self) -> np.ndarray:
+        return self.points[self.perm]
+
+    # ------------------------------------------------------------ precision
+    def select_precision(self, tol: float, allow_f64: bool = False) -> int:
+        """Choose per-block storage formats (see hmg_select_precision)."""
+        if not self.keep_sigma:
+            raise ValueError("precision selection needs keep_sigma=True")
+        nb = self.nblocks
+        self.ngroups = np.zeros(nb, np.int32)
+        self.group_cols = np.zeros((nb, 4), np.int32)
+        self.group_dtype = np.zeros((nb, 4), np.int32)
+        self.store_err_bound = np.zeros(nb)
+        bad = lib().hmg_select_precision(
+            C.c_void_p(self.handle), tol, int(allow_f64), self.ngroups,
+            self.group_cols.reshape(-1), self.group_dtype.reshape(-1), self.store_err_bound)
+        return int(bad)
+
+    def set_uniform_dtype(self, dt: int) -> None:
+        """Store every block (all columns) in one format."""
+        nb = self.nblocks
+        self.ngroups = np.ones(nb, np.int32)
+        self.group_cols = np.zeros((nb, 4), np.int32)
+        self.group_cols[:, 0] = np.where(self.adm != 0, self.rank, 0)
+        self.group_dtype = np.zeros((nb, 4), np.int32)
+        self.group_dtype[:, 0] = dt
+
+    # ------------------------------------------------------------ statistics
+    def stats(self) -> dict:
+        m = (self.re - self.rb).astype(np.int64)
+        nb = (self.ce - self.cb).astype(np.int64)
+        dense = self.adm == 0
+        k = self.rank.astype(np.int64)
+        d_el = int((m * nb)[dense].sum())
+        lr_el = int(((m + nb) * k)[~dense].sum())
+        return {
+            "n": self.n, "blocks": self.nblocks, "dense_blocks": int(dense.sum()),
+            "lowrank_blocks": int((~dense).sum()), "dense_elems": d_el,
+            "lowrank_elems": lr_el, "max_rank": int(k.max()) if k.size else 0,
+            "mean_rank": float(k[~dense].mean()) if (~dense).any() else 0.0,
+            "fp64_bytes": 8 * (d_el + lr_el),
+            "lowrank_not_smaller": int(((m + nb) * k >= m * nb)[~dense].sum()),
+            "build_seconds": self.build_seconds,
+        }
+
+
+def build_hmatrix(points: np.ndarray, kernel: int, *, leaf: int = 64, eta: float = 2.0,
+                  eps: float = 1e-6, eps_aca: float | None = None, keep_sigma: bool = False,
+                  diag: float | None = None, length: float = 0.1, nthreads: int | None = None,
+                  kparams=None) -> HMatrix:
+    """Construct the H-matrix of ``kernel`` over ``points`` (n x 3, FP64).
+
+    kernel: KERNEL_LAPLACE (1/(4 pi r), diagonal 1/(4 pi h) with h the mean
+    nearest-neighbour distance unless ``diag`` gives h), KERNEL_EXP
+    (exp(-r/length), diagonal + ``diag`` (default 1e-3)), KERNEL_SEPARABLE.
+    ACA runs at ``eps_aca`` (default eps/10), then Algorithm 1 at ``eps``.
+    """
+    L = lib()
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n = pts.shape[0]
+    t0 = time.perf_counter()
+    if kparams is None:
+        if kernel == KERNEL_LAPLACE:
+            h = mean_nn_distance(pts) if diag is None else float(diag)
+            kparams = np.array([h, 0.0, 0.0, 0.0])
+        elif kernel == KERNEL_EXP:
+            kparams = np.array([length, 1e-3 if diag is None else float(diag), 0.0, 0.0])
+        else:
+            kparams = np.zeros(4)
+    kparams = np.ascontiguousarray(kparams, dtype=np.float64)
+    handle = C.c_void_p()
+    rc = L.hmg_build_tree(pts.reshape(-1), n, leaf, eta, C.byref(handle))
+    if rc != 0:
+        raise RuntimeError(f"hmg_build_tree failed ({rc})")
+    nthr = nthreads if nthreads else len(os.sched_getaffinity(0))
+    rc = L.hmg_fill(handle, kernel, kparams, eps / 10 if eps_aca is None else eps_aca, eps,
+                    int(keep_sigma), nthr)
+    if rc != 0:
+        L.hmg_destroy(handle)
+        raise RuntimeError(f"hmg_fill failed ({rc})")
+    nb = L.hmg_num_blocks(handle)
+    perm = np.empty(n, np.int64)
+    L.hmg_get_perm(handle, perm)
+    rb, re, cb, ce = (np.empty(nb, np.int64) for _ in range(4))
+    adm, tau, sig, rank = (np.empty(nb, np.int32) for _ in range(4))
+    L.hmg_get_blocks(handle, rb, re, cb, ce, adm, tau, sig, rank)
+    ap, bp, sp = (np.empty(nb, np.uint64) for _ in range(3))
+    L.hmg_get_factor_ptrs(handle, ap, bp, sp)
+    H = HMatrix(n=n, points=pts, kernel=kernel, kparams=kparams, leaf=leaf, eta=eta, eps=eps,
+                keep_sigma=bool(keep_sigma), perm=perm, rb=rb, re=re, cb=cb, ce=ce, adm=adm,
+                rank=rank, a_ptr=ap, b_ptr=bp, s_ptr=sp, handle=handle.value)
+    H.build_seconds = time.perf_counter() - t0
+    return H
+
+
+def round_to(x: np.ndarray, dt: int) -> np.ndarray:
+    """Generator-side RNE rounding of FP64 values to a storage format."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    out = np.empty_like(x)
+    lib().hmg_round(x, x.shape[0], dt, out)
+    return out
+
+
+def truncate(U: np.ndarray, V: np.ndarray, eps: float):
+    """Algorithm 1 (QR + SVD truncation) on U (m x r), V (n x r): returns
+    W (m x k), S (k), X (n x k) with U V^T ~ W diag(S) X^T."""
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    m, r = U.shape
+    n = V.shape[0]
+    W = np.zeros(m * r)
+    X = np.zeros(n * r)
+    S = np.zeros(r)
+    k = lib().hmg_truncate(np.ascontiguousarray(U.T).reshape(-1),
+                           np.ascontiguousarray(V.T).reshape(-1), m, n, r, eps, W, X, S)
+    return W[: m * k].reshape(k, m).T, S[:k].copy(), X[: n * k].reshape(k, n).T
+
+
+def dtype_bytes(dt: int) -> int:
+    return DT_BYTES[dt]
+
+
+def frob(x) -> float:
+    return math.sqrt(float(np.sum(np.square(x))))

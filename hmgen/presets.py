@@ -1,0 +1,70 @@
+"""Named workloads (synthetic stand-ins for the paper's model problems, Sec. 5.1).
+
+sphere-laplace: Fibonacci-lattice points on the unit sphere, kernel
+  1/(4 pi |x-y|) with diagonal 1/(4 pi h), h = mean nearest-neighbour distance
+  (stand-in for the Laplace single-layer BEM matrix).
+cube-exp: uniform random points in the unit cube (seed 0), kernel
+  exp(-|x-y|/0.1) with 1e-3 added on the diagonal; this is the Matern
+  covariance of Sec. 5.1 at nu = 1/2, length 0.1 (stand-in for the paper's
+  nu = 1/3 problem).
+All use a binary geometric-bisection cluster tree with leaf size 64 and
+standard admissibility with eta = 2.
+"""
+
+from __future__ import annotations
+
+from .geometry import fibonacci_sphere, cube_points
+from .hmatrix import build_hmatrix, KERNEL_LAPLACE, KERNEL_EXP, DT_F64, DT_F32
+
+PRESETS = {
+    # small parity case
+    "sphere4k": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-6, dtype="f64"),
+    # throughput point: n = 2^18, eps = 1e-6, plain FP64
+    "sphere256k": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-6, dtype="f64"),
+    # high-accuracy FP64 point: n = 2^18, eps = 1e-8
+    "sphere256k_e8": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-8, dtype="f64"),
+    # mixed-precision storage, FP32 accumulation
+    "sphere256k_mixed": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-6, dtype="mixed"),
+    # batched multi-RHS: n = 2^20 cube, FP32 factors, 32 right-hand sides
+    "cube1m": dict(geometry="cube", n=1048576, kernel="exp", eps=1e-6, dtype="f32", nrhs=32),
+    # small mixed case for parity
+    "sphere4k_mixed": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-6, dtype="mixed"),
+    "cube4k": dict(geometry="cube", n=4096, kernel="exp", eps=1e-6, dtype="f32"),
+}
+
+SEED_POINTS, SEED_X, SEED_RHS, SEED_REQUESTS = 0, 1, 2, 3
+MIXED_TOL = 1e-6
+
+
+def preset(name: str) -> dict:
+    return dict(PRESETS[name])
+
+
+def make_points(geometry: str, n: int):
+    if geometry == "sphere":
+        return fibonacci_sphere(n)
+    if geometry == "cube":
+        return cube_points(n, SEED_POINTS)
+    raise ValueError(geometry)
+
+
+def build_preset(name: str, *, n: int | None = None, eps: float | None = None,
+                 dtype: str | None = None, nthreads: int | None = None, leaf: int = 64,
+                 eta: float = 2.0):
+    """Build a preset's H-matrix; n / eps / dtype override the preset."""
+    p = preset(name)
+    n = p["n"] if n is None else n
+    eps = p["eps"] if eps is None else eps
+    dtype = p["dtype"] if dtype is None else dtype
+    pts = make_points(p["geometry"], n)
+    kern = KERNEL_LAPLACE if p["kernel"] == "laplace" else KERNEL_EXP
+    mixed = dtype == "mixed"
+    H = build_hmatrix(pts, kern, leaf=leaf, eta=eta, eps=eps, keep_sigma=mixed,
+                      nthreads=nthreads)
+    if mixed:
+        H.select_precision(MIXED_TOL / 2)
+    else:
+        H.set_uniform_dtype(DT_F64 if dtype == "f64" else DT_F32)
+    H.dtype_mode = dtype
+    H.preset = name
+    return H

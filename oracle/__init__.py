@@ -1,0 +1,12 @@
+"""CPU oracle for the H-matrix-vector product (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may use this package.  It shares no code with the GPU library
+and never calls it.
+"""
+
+from .oracle import (build, hmvm, hmvm_multi, decoded_factors, round_f32, round_f16, F64, F32, F16, BF16,
+                     round_bf16, round_to, UNIT_ROUNDOFF, FORMAT_LIMITS, dynamic_range)
+
+__all__ = ["F64", "F32", "F16", "BF16", "build", "hmvm", "hmvm_multi", "decoded_factors", "round_f32", "round_f16",
+           "round_bf16", "round_to", "UNIT_ROUNDOFF", "FORMAT_LIMITS", "dynamic_range"]

@@ -1,0 +1,222 @@
+"""Oracle: plain FP64 H-matrix-vector product plus decoding of stored formats.
+
+TEST INFRASTRUCTURE ONLY.  The product definition follows Sec. 2.1
+(Definitions "Block Tree", "H-Matrix") and Eq. (1); see hm_oracle.c.
+
+Format rounding (for the mixed-precision "decoded" oracle) follows the
+IEEE-754 binary formats of Table 1 with round-to-nearest-even applied once,
+directly from FP64:
+  FP32 and FP16 use numpy's own conversions (correctly rounded from double);
+  BF16 (1-8-7, Table 1) is rounded here from its definition.
+Parity pins for every function live in tests/test_oracle_*.py.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+
+# Table 1: unit roundoff u = 2^-(m+1) for m explicit mantissa bits.
+UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "tf32": 2.0 ** -11,
+                 "bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "fp8": 2.0 ** -4}
+
+# (exponent bits, explicit mantissa bits) per format, Table 1.
+FORMAT_BITS = {"fp64": (11, 52), "fp32": (8, 23), "tf32": (8, 10), "bf16": (8, 7),
+               "fp16": (5, 10), "fp8": (4, 3)}
+
+
+def _limits(e: int, m: int):
+    bias = 2 ** (e - 1) - 1
+    emax = bias
+    emin = 1 - bias
+    fmax = (2.0 - 2.0 ** -m) * 2.0 ** emax
+    tiny = 2.0 ** (emin - m)          # smallest subnormal
+    return fmax, tiny
+
+
+FORMAT_LIMITS = {k: _limits(*v) for k, v in FORMAT_BITS.items()}
+
+
+def dynamic_range(fmt: str) -> float:
+    """log10(largest finite / smallest positive subnormal) (Table 2)."""
+    fmax, tiny = FORMAT_LIMITS[fmt]
+    return math.log10(fmax) - math.log10(tiny)
+
+
+# ------------------------------------------------------------------ rounding
+
+def round_f32(x) -> np.ndarray:
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def round_f16(x) -> np.ndarray:
+    return np.asarray(x, dtype=np.float64).astype(np.float16).astype(np.float64)
+
+
+def round_bf16(x) -> np.ndarray:
+    """RNE of FP64 values to BF16 (8 exponent bits, 7 explicit mantissa bits).
+
+    Written from the format definition: the kept significand has 8 bits, the
+    smallest normal exponent is -126, subnormals are spaced 2^-133, values
+    that round beyond the largest finite value become infinite.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    out = x.copy()
+    fin = np.isfinite(x) & (x != 0)
+    xf = x[fin]
+    _, e = np.frexp(xf)                          # |x| = f 2^e, f in [0.5, 1)
+    lsb = np.maximum(e - 1, -126) - 7            # exponent of the last kept bit
+    q = np.rint(np.ldexp(xf, -lsb))              # rint: ties to even
+    r = np.ldexp(q, lsb)
+    fmax = FORMAT_LIMITS["bf16"][0]
+    r = np.where(np.abs(r) > fmax, np.copysign(np.inf, xf), r)
+    out[fin] = r
+    return out
+
+
+def round_to(x, dt: int) -> np.ndarray:
+    if dt == F64:
+        return np.asarray(x, dtype=np.float64)
+    if dt == F32:
+        return round_f32(x)
+    if dt == F16:
+        return round_f16(x)
+    if dt == BF16:
+        return round_bf16(x)
+    raise ValueError(dt)
+
+
+# ------------------------------------------------------------------ C oracle
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        L.oracle_hmvm.argtypes = [C.c_int64, C.c_int64, C.c_int64, i64p, i64p, i64p, i64p,
+                                  i32p, i32p, u64p, u64p, u64p, C.c_double, f64p, f64p]
+        L.oracle_hmvm.restype = C.c_int
+        L.oracle_hmvm_multi.argtypes = [C.c_int64, C.c_int64, C.c_int64, i64p, i64p, i64p,
+                                        i64p, i32p, i32p, u64p, u64p, u64p, C.c_double,
+                                        C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                        C.c_int64]
+        L.oracle_hmvm_multi.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _table(H, factors=None):
+    i64 = lambda v: np.ascontiguousarray(v, dtype=np.int64)
+    i32 = lambda v: np.ascontiguousarray(v, dtype=np.int32)
+    kind = i32(H.adm != 0)
+    rank = i32(np.where(H.adm != 0, H.rank, 0))
+    if factors is None:
+        ap, bp, sp = (np.ascontiguousarray(p, dtype=np.uint64) for p in (H.a_ptr, H.b_ptr, H.s_ptr))
+        keep = None
+    else:
+        keep = factors
+        ap = np.array([f[0].ctypes.data if f[0] is not None and f[0].size else 0 for f in factors], np.uint64)
+        bp = np.array([f[1].ctypes.data if f[1] is not None and f[1].size else 0 for f in factors], np.uint64)
+        sp = np.array([f[2].ctypes.data if f[2] is not None and f[2].size else 0 for f in factors], np.uint64)
+    return (i64(H.rb), i64(H.re), i64(H.cb), i64(H.ce), kind, rank, ap, bp, sp, keep)
+
+
+def hmvm(H, x, y=None, alpha: float = 1.0, factors=None, n_rows=None, n_cols=None) -> np.ndarray:
+    """y + alpha * A_H x in FP64 (returns a new array; y defaults to zero).
+
+    ``H`` is any object with block-table arrays rb, re, cb, ce, adm, rank and
+    per-block factor pointers a_ptr, b_ptr, s_ptr (FP64, column-major); or
+    ``factors`` gives per-block (a, b, s) FP64 arrays (Fortran order) instead.
+    """
+    L = _load()
+    n_rows = H.n if n_rows is None else n_rows
+    n_cols = H.n if n_cols is None else n_cols
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(n_rows) if y is None else np.array(y, dtype=np.float64, copy=True)
+    rb, re, cb, ce, kind, rank, ap, bp, sp, keep = _table(H, factors)
+    rc = L.oracle_hmvm(n_rows, n_cols, rb.shape[0], rb, re, cb, ce, kind, rank, ap, bp, sp,
+                       float(alpha), x, out)
+    if rc != 0:
+        raise RuntimeError(f"oracle_hmvm failed ({rc})")
+    del keep
+    return out
+
+
+def hmvm_multi(H, X, Y=None, alpha: float = 1.0, factors=None) -> np.ndarray:
+    """Column-by-column product for X (n x r, any layout)."""
+    L = _load()
+    X = np.asfortranarray(X, dtype=np.float64)
+    n, r = X.shape
+    out = np.zeros((H.n, r), order="F") if Y is None else np.array(Y, dtype=np.float64, order="F", copy=True)
+    rb, re, cb, ce, kind, rank, ap, bp, sp, keep = _table(H, factors)
+    rc = L.oracle_hmvm_multi(H.n, n, rb.shape[0], rb, re, cb, ce, kind, rank, ap, bp, sp,
+                             float(alpha), r, X.ctypes.data, n, out.ctypes.data, H.n)
+    if rc != 0:
+        raise RuntimeError(f"oracle_hmvm_multi failed ({rc})")
+    del keep
+    return out
+
+
+def _fview(ptr: int, rows: int, cols: int) -> np.ndarray:
+    if ptr == 0 or rows * cols == 0:
+        return np.zeros((rows, cols), order="F")
+    buf = (C.c_double * (rows * cols)).from_address(int(ptr))
+    return np.ctypeslib.as_array(buf).reshape(cols, rows).T
+
+
+def decoded_factors(H, sigma_dtype: int = F32):
+    """Per-block FP64 copies of the factors after rounding to their storage
+    formats (groups of columns per Sec. 3.3; one format per dense block).
+    Singular values are rounded to ``sigma_dtype``.  Returns a list of
+    (a, b, s) Fortran-ordered FP64 arrays usable as ``factors=``."""
+    out = []
+    for i in range(H.rb.shape[0]):
+        m = int(H.re[i] - H.rb[i])
+        nb = int(H.ce[i] - H.cb[i])
+        dts = H.group_dtype[i]
+        if not H.adm[i]:
+            D = _fview(H.a_ptr[i], m, nb)
+            out.append((np.asfortranarray(round_to(D, int(dts[0]))), None, None))
+            continue
+        k = int(H.rank[i])
+        W = _fview(H.a_ptr[i], m, k)
+        X = _fview(H.b_ptr[i], nb, k)
+        Wd = np.empty((m, k), order="F")
+        Xd = np.empty((nb, k), order="F")
+        c0 = 0
+        for g in range(int(H.ngroups[i])):
+            kc = int(H.group_cols[i][g])
+            dt = int(dts[g])
+            Wd[:, c0:c0 + kc] = round_to(W[:, c0:c0 + kc], dt)
+            Xd[:, c0:c0 + kc] = round_to(X[:, c0:c0 + kc], dt)
+            c0 += kc
+        s = None
+        if H.keep_sigma and k:
+            s = np.ascontiguousarray(round_to(_fview(H.s_ptr[i], k, 1)[:, 0], sigma_dtype))
+        out.append((Wd, Xd, s))
+    return out
