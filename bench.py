@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the H-matrix-vector product on one MI355X.
+
+Default workload: Fibonacci-sphere Laplace matrix, n = 2^18, leaf 64, eta 2,
+ACA + SVD recompression at eps = 1e-6, plain FP64 storage and accumulation,
+one right-hand side (synthetic, seeded).  A step is one full product
+y += A x (column tiles, partial reduction, row panels) with the matrix and
+the vectors resident in HBM.  Prints one JSON line.
+
+value = algorithmic bytes per product / time per product (effective GB/s);
+the algorithmic bytes are the stored factor bytes plus x read once and y
+read and written once.  The roofline entry is for the kernel with the
+largest measured time, timed with HIP events on its own stream over the
+timed region.  cpu_baseline times the CPU oracle (single thread) on full
+products of the same matrix.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNELS = ["k_col", "k_reduce", "k_row"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(H, info, vs):
+    """Algorithmic bytes each kernel must move in one product."""
+    m = (H.re - H.rb).astype(np.float64)
+    nb = (H.ce - H.cb).astype(np.float64)
+    dense = H.adm == 0
+    sz = np.array([8, 4, 2, 2], np.float64)
+    d_bytes = float((m * nb * sz[H.group_dtype[:, 0]])[dense].sum())
+    gcols = H.group_cols.astype(np.float64)
+    gbytes = (gcols * sz[H.group_dtype]).sum(1)          # bytes per row of U / V
+    u_bytes = float((m * gbytes)[~dense].sum())
+    v_bytes = float((nb * gbytes)[~dense].sum())
+    n = float(H.n)
+    n_t, n_p = float(info["n_t"]), float(info["n_partials"])
+    sig = n_t * vs if getattr(H, "keep_sigma", False) else 0.0
+    return {
+        "k_col": v_bytes + vs * (n + n_p),
+        "k_reduce": vs * (n_p + n_t) + sig,
+        "k_row": d_bytes + u_bytes + vs * (n + n_t + 2 * n),
+    }
+
+
+def kernels_source_hash():
+    h = hashlib.sha256()
+    for f in ("hm_kernels.hip", "hm_layout.hpp"):
+        with open(os.path.join(ROOT, "paper_2308_10960_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernels_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="sphere256k")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the row-panel sharding over GPUs is described in DESIGN.md, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import hmgen
+    from paper_2308_10960_amd import hm, DeviceHMatrix
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    torch.cuda.set_device(0)
+    p = hmgen.preset(args.workload)
+    log("building", args.workload, p)
+    H = hmgen.build_preset(args.workload)
+    st = H.stats()
+    log("built in %.1fs: %s" % (H.build_seconds, st))
+    mixed = p["dtype"] != "f64"
+    acc = hm.HM_F32 if mixed else hm.HM_F64
+    vs = 4 if mixed else 8
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        D = DeviceHMatrix(H, acc, stream=stream)
+    info = D.info
+    log("uploaded: store %.3f GB, alg %.3f GB" % (info["store_bytes"] / 1e9, info["alg_bytes"] / 1e9))
+    x = D.vector(hmgen.uniform_vector(H.n, seed=hmgen.presets.SEED_X))
+    y = D.vector()
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        D.mvm(x, y, 1.0, stream=stream)
+    torch.cuda.synchronize()
+    hm.hm_profile_begin(D.handle, args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        D.mvm(x, y, 1.0, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_k, calls = hm.hm_profile_end(D.handle)
+    assert calls == args.steps
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    alg = info["alg_bytes"]
+    value = alg / (ms_per_step * 1e-3) / 1e9
+    log("%.4f ms/step, %.1f GB/s effective (%.1f%% of 8 TB/s)" % (ms_per_step, value, value / 80.0))
+
+    kb = kernel_bytes(H, info, vs)
+    avg_ms = {k: ms_k[i] / calls for i, k in enumerate(KERNELS)}
+    dom = max(avg_ms, key=avg_ms.get)
+    achieved = kb[dom] / (avg_ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": read_traffic(dom, args.workload),
+                "alg_bytes_per_launch": kb[dom], "avg_ms": round(avg_ms[dom], 5)}
+    kernels = {k: {"avg_ms": round(avg_ms[k], 5), "alg_bytes": kb[k],
+                   "gbs": round(kb[k] / (avg_ms[k] * 1e-3) / 1e9, 1) if avg_ms[k] > 0 else None}
+               for k in KERNELS}
+    log("kernels", kernels)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        xh = x.cpu().numpy().astype(np.float64)
+        runs, t_cpu = 0, 0.0
+        while runs == 0 or t_cpu < args.cpu_seconds:
+            a = time.perf_counter()
+            oracle.hmvm(H, xh)
+            t_cpu += time.perf_counter() - a
+            runs += 1
+        cpu = {"value": round(alg / (t_cpu / runs) / 1e9, 3), "unit": "GB/s", "cores": 1,
+               "kind": "oracle", "seconds_per_matvec": round(t_cpu / runs, 4),
+               "sample": f"{runs} full single-RHS products of the same n={H.n} matrix, "
+                         "single-threaded FP64 oracle"}
+        log("cpu baseline", cpu)
+
+    out = {
+        "metric": "H-MVM effective GB/s & % HBM peak at n=2^18 eps=1e-6; p50/p99 req latency",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{p['geometry']}-{p['kernel']} n={H.n} eps={p['eps']} "
+                               f"{p['dtype']} 1rhs leaf64 eta2",
+                   "n": H.n, "eps": p["eps"], "storage": p["dtype"], "nrhs": 1,
+                   "blocks": st["blocks"], "dense_blocks": st["dense_blocks"],
+                   "lowrank_blocks": st["lowrank_blocks"], "mean_rank": round(st["mean_rank"], 2),
+                   "alg_bytes": alg, "store_bytes": info["store_bytes"]},
+        "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    D.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * hm.h -- C-ABI of the MI355X H-matrix-vector product library (libhm.so).
+ *
+ * The operation (Kriemann, "Hierarchical Lowrank Arithmetic with Binary
+ * Compression"):
+ *
+ *   y := y + alpha * A x,   A = sum_{b=(tau,sigma) in L(T)} E_tau M_b E_sigma^T
+ *
+ * over the leaves L(T) of a block tree (Sec. 2.1, Definition "Block Tree").
+ * Inadmissible leaves hold a dense block M_b = D_b; admissible leaves hold a
+ * low-rank block M_b = U_b V_b^T of fixed accuracy (Eq. (1), Definition
+ * "H-Matrix"), optionally in the form W_b diag(s_b) X_b^T whose columns are
+ * split into groups stored in different floating-point formats (Sec. 3.3).
+ * U and V are stored independently of each other (Sec. 3).  The product only
+ * needs the blocks decoded from their storage formats (Sec. 1, Sec. 5.4);
+ * here the decoding happens in registers inside the GPU kernels.
+ *
+ * All index ranges and vectors are in cluster order (the order in which the
+ * cluster tree's leaves enumerate the index set).
+ *
+ * Conventions for every entry point:
+ *  - Return value: HM_OK (0) or a negative hm_status.  No C++ exception
+ *    crosses this boundary.  hm_last_error() gives a text for the last
+ *    failure on the calling thread.
+ *  - Arguments, shapes and the partition are validated synchronously before
+ *    anything is enqueued; on error nothing is enqueued and outputs are
+ *    untouched.
+ *  - Device memory (store, vectors, workspace, server arena) is allocated by
+ *    the caller and borrowed; it must outlive the handles that use it.
+ *  - Streams are hipStream_t passed as void* (NULL = the null stream).
+ *    Compute calls are stream-ordered and return after enqueueing.
+ */
+#ifndef HM_H
+#define HM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hm_status;
+#define HM_OK 0
+#define HM_EINVAL (-1)      /* bad argument (NULL pointer, negative size, bad option) */
+#define HM_EPARTITION (-2)  /* blocks do not tile [0,n_rows) x [0,n_cols) exactly once */
+#define HM_ESHAPE (-3)      /* inconsistent block shape, rank or column groups */
+#define HM_EDTYPE (-4)      /* unsupported storage / accumulation / vector dtype combination */
+#define HM_ENOMEM (-5)      /* caller buffer (store, workspace, arena) too small, or host allocation failed */
+#define HM_EDEVICE (-6)     /* HIP runtime error (text via hm_last_error) */
+#define HM_EBUSY (-7)       /* server queue full */
+#define HM_ESTATE (-8)      /* object in the wrong state (e.g. server stopped, unknown ticket) */
+#define HM_ETIMEOUT (-9)    /* hm_wait timed out */
+
+typedef enum { HM_F64 = 0, HM_F32 = 1, HM_F16 = 2, HM_BF16 = 3 } hm_dtype;
+typedef enum { HM_DENSE = 0, HM_LOWRANK = 1 } hm_kind;
+
+/* One leaf block b = tau x sigma of the block tree (Sec. 2.1).
+ * Ranges are half-open, in cluster order.
+ * DENSE:   rank = 0, ngroups = 1, group_dtype[0] = storage dtype of D_b.
+ * LOWRANK: rank = k >= 0 (0 = zero block, contributes nothing);
+ *          columns 0..k-1 are split into ngroups (1..4) consecutive groups of
+ *          group_cols[g] columns stored in group_dtype[g] (Sec. 3.3);
+ *          sum(group_cols) == k.  has_sigma = 1: M_b = W diag(s) X^T with
+ *          s applied in the accumulation dtype; 0: M_b = U V^T. */
+typedef struct {
+  int64_t row_begin, row_end, col_begin, col_end;
+  int32_t kind, rank;
+  int32_t ngroups, group_cols[4], group_dtype[4];
+  int32_t has_sigma;
+} hm_block_desc;
+
+/* acc_dtype: HM_F64 or HM_F32, the accumulation type of every sum.
+ * vec_dtype: must equal acc_dtype (x, y, X, Y are stored in it).
+ * Storage dtypes allowed: any with HM_F64 accumulation; F32/F16/BF16 with
+ * HM_F32 accumulation.
+ * max_nrhs: largest nrhs passed to hm_mvm_batch (>= 1); sizes the workspace.
+ * tune: 0 = built-in launch parameters; 1 = read tune_cache (a text file of
+ * autotuned launch parameters written by the tuner), falling back to the
+ * built-ins for missing keys.  tune_cache may be NULL when tune = 0. */
+typedef struct {
+  int32_t acc_dtype, vec_dtype, max_nrhs, tune;
+  const char* tune_cache;
+} hm_plan_opts;
+
+/* Sizes and byte accounting of a plan (all counts exact).
+ * store_bytes: device bytes hm_upload needs (factors + descriptors).
+ * work_bytes_per_rhs: workspace bytes hm_mvm needs (x nrhs for hm_mvm_batch).
+ * alg_bytes: algorithmic bytes of one single-RHS product: stored factor
+ *   elements at their storage width, s_b values, x read once, y read and
+ *   written once.  alg_flops: 2 (sum_dense m n + sum_lowrank (m + n) k).
+ * overhead_bytes: index/descriptor bytes and padding streamed per product
+ *   beyond alg_bytes (reported separately; not counted as algorithmic).
+ * bytes_by_dtype: stored factor bytes per storage dtype (index = hm_dtype). */
+typedef struct {
+  size_t store_bytes, work_bytes_per_rhs;
+  double alg_bytes, alg_flops, overhead_bytes;
+  int64_t n_dense, n_lowrank, n_row_panels, n_col_tiles, n_partials, n_t;
+  size_t bytes_by_dtype[4];
+} hm_plan_info_t;
+
+typedef struct hm_plan hm_plan;
+typedef struct hm_matrix hm_matrix;
+typedef struct hm_server hm_server;
+
+/* Block scheduler (host only).  Validates the block table -- shapes, ranks,
+ * groups, dtypes, and that the leaves tile [0,n_rows) x [0,n_cols) exactly
+ * once, the defining property of the block tree's leaf set (Sec. 2.1) --
+ * then groups every block's rows by elementary row interval and columns by
+ * elementary column interval into dtype-homogeneous panels and work lists.
+ * Copies what it needs from `blocks`.  opts may be NULL (F64, 1 RHS). */
+hm_status hm_build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks,
+                        int64_t n_blocks, const hm_plan_opts* opts, hm_plan** out);
+hm_status hm_plan_info(const hm_plan* p, hm_plan_info_t* out);
+void hm_plan_destroy(hm_plan* p);
+
+/* Where entry (i, j) of a block's first factor (which = 0: D_b or U_b / W_b,
+ * j < n_b resp. k) or second factor (which = 1: V_b / X_b, i < n_b, j < k)
+ * lives in the store: byte offset and storage dtype.  For tests of the
+ * packing and conversion done by hm_upload. */
+hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t i, int64_t j,
+                         size_t* byte_offset, int32_t* dtype);
+
+/* Device block store.  Converts every factor from FP64 to its storage dtype
+ * with round-to-nearest-even (rounded once, directly from FP64), packs it
+ * into the plan's panel layout with its descriptors, and copies the result
+ * to d_store (device, >= store_bytes, 256-byte aligned) on `stream`; the
+ * call returns after the copy has completed.  Per block b (host, FP64,
+ * column-major): a[b] = D_b (m x n_b) or U_b / W_b (m x k); bf[b] = NULL or
+ * V_b / X_b (n_b x k); s[b] = NULL or s_b (k values, when has_sigma).
+ * Converting each block after assembly follows Sec. 5.3. */
+hm_status hm_upload(const hm_plan* p, const double* const* a, const double* const* bf,
+                    const double* const* s, void* d_store, size_t store_bytes, void* stream,
+                    hm_matrix** out);
+void hm_matrix_destroy(hm_matrix* A);
+
+/* The packing half of hm_upload into host memory h_buf (>= store_bytes),
+ * with no device involved; the bytes are exactly what hm_upload copies to
+ * the device.  For inspection and tests of the store layout. */
+hm_status hm_pack_host(const hm_plan* p, const double* const* a, const double* const* bf,
+                       const double* const* s, void* h_buf, size_t buf_bytes);
+
+/* y := y + alpha A x (single right-hand side).  d_x: n_cols vector, d_y:
+ * n_rows vector, both device memory in vec_dtype; x must not alias y.
+ * d_work: device workspace of >= work_bytes_per_rhs bytes, 256-byte aligned;
+ * concurrent calls on one matrix need distinct workspaces.  The result is
+ * deterministic: every sum has a fixed order independent of timing. */
+hm_status hm_mvm(const hm_matrix* A, double alpha, const void* d_x, void* d_y, void* d_work,
+                 size_t work_bytes, void* stream);
+
+/* Y := Y + alpha A X for nrhs right-hand sides (1 <= nrhs <= max_nrhs).
+ * X is n_cols x nrhs, Y is n_rows x nrhs, column-major with leading
+ * dimensions ldx >= n_cols, ldy >= n_rows; workspace >= nrhs *
+ * work_bytes_per_rhs.  Each column equals what hm_mvm gives for it up to
+ * the rounding of the accumulation order. */
+hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const void* d_X,
+                       int64_t ldx, void* d_Y, int64_t ldy, void* d_work, size_t work_bytes,
+                       void* stream);
+
+/* Kernel timing for measurement.  While enabled, each hm_mvm / hm_mvm_batch
+ * call on A records HIP events around each of its kernels on the call's
+ * stream, for up to max_calls calls (later calls are not recorded).
+ * hm_profile_end waits for the recorded events, returns the summed
+ * milliseconds per kernel -- ms[0] column tiles (far field, phase 1), ms[1]
+ * partial reduction, ms[2] row panels (near field and far field, phase 2) --
+ * and the number of calls recorded, and stops recording.  Events are owned
+ * by the library. */
+hm_status hm_profile_begin(hm_matrix* A, int32_t max_calls);
+hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls);
+
+/* Request loop with continuous batching over device-resident matrices.
+ * mats: matrices to serve (borrowed).  d_arena: device memory (arena_bytes)
+ * from which request vectors and workspaces are carved; a request is
+ * admitted when its footprint fits in the free part of the arena (HBM-budget
+ * admission) and otherwise waits.  streams: n_streams HIP streams the loop
+ * may use concurrently (borrowed).  A host thread batches queued requests
+ * of the same matrix into one hm_mvm_batch call per stream slot. */
+hm_status hm_server_create(hm_matrix* const* mats, int32_t n_mats, void* d_arena,
+                           size_t arena_bytes, void* const* streams, int32_t n_streams,
+                           hm_server** out);
+/* Queue Y := A_mat X (Y overwritten) for host buffers X (n_cols x nrhs,
+ * leading dimension ldx) and Y (n_rows x nrhs, ldy) in the matrix's
+ * vec_dtype; both must stay valid until the ticket completes. */
+hm_status hm_submit(hm_server* s, int32_t mat, int32_t nrhs, const void* h_X, int64_t ldx,
+                    void* h_Y, int64_t ldy, uint64_t* ticket);
+hm_status hm_poll(hm_server* s, uint64_t ticket, int32_t* done, hm_status* result);
+hm_status hm_wait(hm_server* s, uint64_t ticket, int64_t timeout_us, hm_status* result);
+/* Latency percentiles (microseconds, completion minus submission) and
+ * throughput (right-hand sides completed per second) since creation. */
+hm_status hm_server_stats(hm_server* s, double* p50_us, double* p99_us, double* matvecs_per_s);
+void hm_server_destroy(hm_server* s);
+
+/* Text of the last error on the calling thread (valid until the next hm_*
+ * call on this thread); "" when the last call succeeded. */
+const char* hm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HM_H */

@@ -1,0 +1,844 @@
+// Host side of libhm: block-table validation, the block scheduler (panel
+// and work-list construction), the store layout, packing with RNE format
+// conversion, and the C-ABI entry points that enqueue the HIP kernels.
+//
+// Paper references (Kriemann, "Hierarchical Lowrank Arithmetic with Binary
+// Compression"): leaf partition of I x J (Sec. 2.1, Definition "Block
+// Tree"); dense and low-rank leaves (Definition "H-Matrix", Eq. (1)); U and
+// V stored separately (Sec. 3); column groups per format with singular
+// values (Sec. 3.3); formats of Table 1; conversion after assembly
+// (Sec. 5.3).
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "../../include/hm.h"
+#include "hm_internal.hpp"
+
+namespace hm {
+
+thread_local std::string g_err;
+
+hm_status fail(hm_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+hm_status ok() {
+  g_err.clear();
+  return HM_OK;
+}
+
+static inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ rounding
+// Round-to-nearest-even from FP64 straight to the storage format (one
+// rounding), on the IEEE-754 bit patterns.  Formats per Table 1.
+
+static uint16_t round_bits(double d, int man_bits, int bias, int exp_max_field) {
+  uint64_t b;
+  std::memcpy(&b, &d, 8);
+  const int total = 1 + (exp_max_field == 31 ? 5 : 8) + man_bits;
+  const uint16_t sign = (uint16_t)((b >> 63) << (total - 1));
+  const int e = (int)((b >> 52) & 0x7ff);
+  const uint64_t man = b & ((1ull << 52) - 1);
+  const uint16_t inf = (uint16_t)(exp_max_field << man_bits);
+  if (e == 0x7ff) return sign | inf | (man ? (uint16_t)(1u << (man_bits - 1)) : 0);
+  if (e == 0) return sign;                       // FP64 subnormal: far below any target
+  const int E = e - 1023;
+  const int emin = 1 - bias;
+  const uint64_t sig = man | (1ull << 52);
+  int shift, field;
+  if (E >= emin) { shift = 52 - man_bits; field = E + bias; }
+  else { shift = 52 - man_bits + (emin - E); field = 0; }
+  if (shift > 63) return sign;
+  uint64_t kept = sig >> shift;
+  const uint64_t rem = sig & ((1ull << shift) - 1);
+  const uint64_t half = 1ull << (shift - 1);
+  if (rem > half || (rem == half && (kept & 1))) ++kept;
+  if (field == 0) return sign | (uint16_t)kept;  // subnormal (a carry gives the min normal)
+  if (kept == (1ull << (man_bits + 1))) { kept >>= 1; ++field; }
+  if (field >= exp_max_field) return sign | inf;
+  return sign | (uint16_t)(field << man_bits) | (uint16_t)(kept & ((1ull << man_bits) - 1));
+}
+
+uint16_t f64_to_f16(double d) { return round_bits(d, 10, 15, 31); }
+uint16_t f64_to_bf16(double d) { return round_bits(d, 7, 127, 255); }
+
+static inline void put(uint8_t* dst, int dt, double v) {
+  switch (dt) {
+    case HM_F64: std::memcpy(dst, &v, 8); break;
+    case HM_F32: { float f = (float)v; std::memcpy(dst, &f, 4); break; }
+    case HM_F16: { uint16_t h = f64_to_f16(v); std::memcpy(dst, &h, 2); break; }
+    default: { uint16_t h = f64_to_bf16(v); std::memcpy(dst, &h, 2); break; }
+  }
+}
+
+// ------------------------------------------------------------------ plan
+
+static hm_status validate_block(const hm_block_desc& b, int64_t i, int64_t n_rows, int64_t n_cols,
+                                int acc) {
+  if (b.row_begin < 0 || b.row_end > n_rows || b.row_begin >= b.row_end || b.col_begin < 0 ||
+      b.col_end > n_cols || b.col_begin >= b.col_end)
+    return fail(HM_ESHAPE, "block %lld: range [%lld,%lld)x[%lld,%lld) outside or empty",
+                (long long)i, (long long)b.row_begin, (long long)b.row_end,
+                (long long)b.col_begin, (long long)b.col_end);
+  if (b.row_end - b.row_begin > INT32_MAX / 2 || b.col_end - b.col_begin > INT32_MAX / 2)
+    return fail(HM_ESHAPE, "block %lld too large", (long long)i);
+  auto dt_ok = [&](int dt) {
+    if (dt < HM_F64 || dt > HM_BF16) return false;
+    if (acc == HM_F32 && dt == HM_F64) return false;
+    return true;
+  };
+  if (b.kind == HM_DENSE) {
+    if (b.rank != 0) return fail(HM_ESHAPE, "block %lld: dense block with rank %d", (long long)i, b.rank);
+    if (b.ngroups != 1) return fail(HM_ESHAPE, "block %lld: dense block needs ngroups = 1", (long long)i);
+    if (!dt_ok(b.group_dtype[0]))
+      return fail(HM_EDTYPE, "block %lld: storage dtype %d not allowed", (long long)i, b.group_dtype[0]);
+    if (b.has_sigma) return fail(HM_ESHAPE, "block %lld: dense block with has_sigma", (long long)i);
+    return HM_OK;
+  }
+  if (b.kind != HM_LOWRANK) return fail(HM_EINVAL, "block %lld: unknown kind %d", (long long)i, b.kind);
+  if (b.rank < 0) return fail(HM_ESHAPE, "block %lld: negative rank", (long long)i);
+  const int64_t m = b.row_end - b.row_begin, n = b.col_end - b.col_begin;
+  if (b.rank > std::min(m, n)) return fail(HM_ESHAPE, "block %lld: rank %d exceeds min(m,n)", (long long)i, b.rank);
+  if (b.ngroups < 0 || b.ngroups > 4 || (b.rank > 0 && b.ngroups < 1))
+    return fail(HM_ESHAPE, "block %lld: ngroups %d", (long long)i, b.ngroups);
+  int64_t sum = 0;
+  for (int g = 0; g < b.ngroups; ++g) {
+    if (b.group_cols[g] < 0) return fail(HM_ESHAPE, "block %lld: negative group size", (long long)i);
+    if (!dt_ok(b.group_dtype[g]))
+      return fail(HM_EDTYPE, "block %lld: storage dtype %d not allowed", (long long)i, b.group_dtype[g]);
+    sum += b.group_cols[g];
+  }
+  if (sum != b.rank) return fail(HM_ESHAPE, "block %lld: group sizes sum to %lld, rank %d",
+                                 (long long)i, (long long)sum, b.rank);
+  if (b.has_sigma != 0 && b.has_sigma != 1) return fail(HM_EINVAL, "block %lld: has_sigma", (long long)i);
+  return HM_OK;
+}
+
+// Elementary intervals from sorted unique breakpoints, split to <= cap.
+static void split_intervals(const std::vector<int64_t>& bp, int cap, std::vector<int64_t>& out,
+                            std::vector<int32_t>& parent) {
+  out.clear();
+  parent.clear();
+  for (size_t q = 0; q + 1 < bp.size(); ++q) {
+    int64_t a = bp[q], len = bp[q + 1] - bp[q];
+    int64_t pieces = (len + cap - 1) / cap;
+    for (int64_t p = 0; p < pieces; ++p) {
+      out.push_back(a + len * p / pieces);
+      parent.push_back((int32_t)q);
+    }
+  }
+  out.push_back(bp.back());
+}
+
+hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks, int64_t nb,
+                     const hm_plan_opts* o, hm_plan** out) {
+  if (!out) return fail(HM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_rows <= 0 || n_cols <= 0 || n_rows > INT32_MAX / 4 || n_cols > INT32_MAX / 4)
+    return fail(HM_EINVAL, "bad matrix size %lld x %lld", (long long)n_rows, (long long)n_cols);
+  if (nb <= 0 || !blocks) return fail(HM_EINVAL, "empty block table");
+  hm_plan_opts opts{HM_F64, HM_F64, 1, 0, nullptr};
+  if (o) opts = *o;
+  if (opts.acc_dtype != HM_F64 && opts.acc_dtype != HM_F32)
+    return fail(HM_EDTYPE, "acc_dtype must be HM_F64 or HM_F32");
+  if (opts.vec_dtype != opts.acc_dtype) return fail(HM_EDTYPE, "vec_dtype must equal acc_dtype");
+  if (opts.max_nrhs < 1 || opts.max_nrhs > 4096) return fail(HM_EINVAL, "max_nrhs out of range");
+  const int acc = opts.acc_dtype;
+
+  auto P = std::make_unique<hm_plan>();
+  P->n_rows = n_rows;
+  P->n_cols = n_cols;
+  P->opts = opts;
+  P->tune_path = opts.tune_cache ? opts.tune_cache : "";
+  P->opts.tune_cache = nullptr;
+  P->blocks.assign(blocks, blocks + nb);
+  for (int64_t i = 0; i < nb; ++i) {
+    hm_status st = validate_block(P->blocks[i], i, n_rows, n_cols, acc);
+    if (st) return st;
+  }
+
+  // ---- elementary row intervals and the tiling proof
+  std::vector<int64_t> rbp;
+  rbp.reserve(2 * nb + 2);
+  for (auto& b : P->blocks) { rbp.push_back(b.row_begin); rbp.push_back(b.row_end); }
+  std::sort(rbp.begin(), rbp.end());
+  rbp.erase(std::unique(rbp.begin(), rbp.end()), rbp.end());
+  if (rbp.front() != 0 || rbp.back() != n_rows)
+    return fail(HM_EPARTITION, "rows [0,%lld) are not covered", (long long)n_rows);
+  const int64_t nri = (int64_t)rbp.size() - 1;
+  std::vector<int64_t> cnt(nri + 1, 0);
+  std::vector<int32_t> bi0(nb), bi1(nb);
+  for (int64_t i = 0; i < nb; ++i) {
+    bi0[i] = (int32_t)(std::lower_bound(rbp.begin(), rbp.end(), P->blocks[i].row_begin) - rbp.begin());
+    bi1[i] = (int32_t)(std::lower_bound(rbp.begin(), rbp.end(), P->blocks[i].row_end) - rbp.begin());
+    for (int32_t q = bi0[i]; q < bi1[i]; ++q) cnt[q + 1]++;
+  }
+  for (int64_t q = 0; q < nri; ++q) cnt[q + 1] += cnt[q];
+  std::vector<int32_t> cover(cnt[nri]);
+  {
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < nb; ++i)
+      for (int32_t q = bi0[i]; q < bi1[i]; ++q) cover[fill[q]++] = (int32_t)i;
+  }
+  for (int64_t q = 0; q < nri; ++q) {
+    auto first = cover.begin() + cnt[q], last = cover.begin() + cnt[q + 1];
+    std::sort(first, last, [&](int32_t a, int32_t b) {
+      return P->blocks[a].col_begin < P->blocks[b].col_begin;
+    });
+    int64_t c = 0;
+    for (auto it = first; it != last; ++it) {
+      const auto& b = P->blocks[*it];
+      if (b.col_begin != c)
+        return fail(HM_EPARTITION, "rows [%lld,%lld): columns %s at %lld (block %d)",
+                    (long long)rbp[q], (long long)rbp[q + 1],
+                    b.col_begin < c ? "overlap" : "gap", (long long)c, *it);
+      c = b.col_end;
+    }
+    if (c != n_cols)
+      return fail(HM_EPARTITION, "rows [%lld,%lld): columns [%lld,%lld) not covered",
+                  (long long)rbp[q], (long long)rbp[q + 1], (long long)c, (long long)n_cols);
+  }
+
+  // ---- low-rank blocks: column intervals, t and partial offsets
+  std::vector<int64_t> cbp;
+  for (auto& b : P->blocks)
+    if (b.kind == HM_LOWRANK && b.rank > 0) { cbp.push_back(b.col_begin); cbp.push_back(b.col_end); }
+  std::sort(cbp.begin(), cbp.end());
+  cbp.erase(std::unique(cbp.begin(), cbp.end()), cbp.end());
+  std::vector<int32_t> cparent;
+  if (!cbp.empty()) split_intervals(cbp, kMaxTileRows, P->cint, cparent);
+  const int64_t nci = P->cint.empty() ? 0 : (int64_t)P->cint.size() - 1;
+
+  P->binfo.assign(nb, BlockInfo{});
+  std::vector<int32_t> lr_large, lr_small;
+  for (int64_t i = 0; i < nb; ++i) {
+    const auto& b = P->blocks[i];
+    BlockInfo& bi = P->binfo[i];
+    if (b.kind != HM_LOWRANK || b.rank == 0) continue;
+    bi.seg0 = (int32_t)(std::lower_bound(P->cint.begin(), P->cint.end(), b.col_begin) - P->cint.begin());
+    int32_t seg1 = (int32_t)(std::lower_bound(P->cint.begin(), P->cint.end(), b.col_end) - P->cint.begin());
+    bi.nseg = seg1 - bi.seg0;
+    (bi.nseg > kLargeSeg ? lr_large : lr_small).push_back((int32_t)i);
+  }
+  int64_t toff = 0, pst = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int32_t i : pass == 0 ? lr_large : lr_small) {
+      BlockInfo& bi = P->binfo[i];
+      bi.toff = toff;
+      bi.pst = pst;
+      toff += P->blocks[i].rank;
+      pst += (int64_t)bi.nseg * P->blocks[i].rank;
+    }
+  if (toff + n_cols > INT32_MAX || pst > INT32_MAX)
+    return fail(HM_ENOMEM, "too many low-rank entries for 32-bit indices");
+  P->n_t = toff;
+  P->n_partials = pst;
+  P->n_large = (int64_t)lr_large.size();
+  P->n_large_t = 0;
+  for (int32_t i : lr_large) P->n_large_t += P->blocks[i].rank;
+  P->lr_order.reserve(lr_large.size() + lr_small.size());
+  P->lr_order.insert(P->lr_order.end(), lr_large.begin(), lr_large.end());
+  P->lr_order.insert(P->lr_order.end(), lr_small.begin(), lr_small.end());
+  P->has_sigma = 0;
+  for (auto& b : P->blocks)
+    if (b.kind == HM_LOWRANK && b.rank > 0 && b.has_sigma) P->has_sigma = 1;
+
+  // ---- row panels
+  std::vector<int32_t> rparent;
+  split_intervals(rbp, kMaxPanelRows, P->rint, rparent);
+  const int64_t nrp = (int64_t)P->rint.size() - 1;
+  P->rps.resize(nrp);
+  for (int64_t p = 0; p < nrp; ++p) {
+    RowPanelHost& R = P->rps[p];
+    R.row0 = P->rint[p];
+    R.m = (int32_t)(P->rint[p + 1] - P->rint[p]);
+    const int32_t q = rparent[p];
+    std::vector<Seg> segs;
+    for (int64_t c = cnt[q]; c < cnt[q + 1]; ++c) {
+      const int32_t i = cover[c];
+      const auto& b = P->blocks[i];
+      if (b.kind == HM_DENSE) {
+        segs.push_back(Seg{i, 0, (int32_t)(b.col_end - b.col_begin), (int32_t)b.col_begin,
+                           b.group_dtype[0], 0});
+      } else if (b.rank > 0) {
+        int32_t c0 = 0;
+        for (int g = 0; g < b.ngroups; ++g) {
+          if (b.group_cols[g] > 0)
+            segs.push_back(Seg{i, c0, b.group_cols[g],
+                               (int32_t)(n_cols + P->binfo[i].toff + c0), b.group_dtype[g], 0});
+          c0 += b.group_cols[g];
+        }
+      }
+    }
+    // sections in dtype order; each starts at a multiple of 8 source slots
+    int32_t slot = 0;
+    for (int dt = 0; dt < 4; ++dt) {
+      int32_t cols = 0;
+      for (auto& s : segs)
+        if (s.dtype == dt) { s.seccol = cols; cols += s.ncols; }
+      if (cols == 0) continue;
+      const int G = group_width(dt);
+      RowSectionHost S;
+      S.dtype = dt;
+      S.ngroups = (cols + G - 1) / G;
+      S.col0 = slot;
+      slot += align_up(S.ngroups * G, 8);
+      R.secs.push_back(S);
+    }
+    R.ncols = slot;
+    R.segs = std::move(segs);
+  }
+
+  // ---- column panels (one per column interval) and their tiles
+  std::vector<int64_t> ccnt(nci + 1, 0);
+  for (int32_t i : P->lr_order) {
+    const BlockInfo& bi = P->binfo[i];
+    for (int32_t s = bi.seg0; s < bi.seg0 + bi.nseg; ++s) ccnt[s + 1]++;
+  }
+  for (int64_t q = 0; q < nci; ++q) ccnt[q + 1] += ccnt[q];
+  std::vector<int32_t> ccover(nci ? ccnt[nci] : 0);
+  {
+    std::vector<int64_t> fill(ccnt.begin(), ccnt.end() - 1);
+    // ascending block index keeps a stable, reproducible column order
+    std::vector<int32_t> lr_sorted(P->lr_order);
+    std::sort(lr_sorted.begin(), lr_sorted.end());
+    for (int32_t i : lr_sorted) {
+      const BlockInfo& bi = P->binfo[i];
+      for (int32_t s = bi.seg0; s < bi.seg0 + bi.nseg; ++s) ccover[fill[s]++] = i;
+    }
+  }
+  P->cps.resize(nci);
+  for (int64_t q = 0; q < nci; ++q) {
+    ColPanelHost& Cp = P->cps[q];
+    Cp.x0 = P->cint[q];
+    Cp.nrows = (int32_t)(P->cint[q + 1] - P->cint[q]);
+    for (int64_t c = ccnt[q]; c < ccnt[q + 1]; ++c) {
+      const int32_t i = ccover[c];
+      const auto& b = P->blocks[i];
+      const BlockInfo& bi = P->binfo[i];
+      const int32_t seg = (int32_t)q - bi.seg0;
+      int32_t c0 = 0;
+      for (int g = 0; g < b.ngroups; ++g) {
+        if (b.group_cols[g] > 0)
+          Cp.segs.push_back(Seg{i, c0, b.group_cols[g],
+                                (int32_t)(bi.pst + (int64_t)seg * b.rank + c0), b.group_dtype[g], 0});
+        c0 += b.group_cols[g];
+      }
+    }
+    for (int dt = 0; dt < 4; ++dt) {
+      int32_t cols = 0;
+      for (auto& s : Cp.segs)
+        if (s.dtype == dt) { s.seccol = cols; cols += s.ncols; }
+      if (cols == 0) continue;
+      const int G = group_width(dt);
+      ColSectionHost S;
+      S.dtype = dt;
+      S.ld = (int32_t)align_up(cols, G);
+      Cp.secs.push_back(S);
+    }
+  }
+
+  return layout_store(P.release(), out);
+}
+
+hm_status layout_store(hm_plan* Pp, hm_plan** out) {
+  std::unique_ptr<hm_plan> P(Pp);
+  const int acc_sz = P->opts.acc_dtype == HM_F64 ? 8 : 4;
+  StoreHeader& H = P->hdr;
+  std::memset(&H, 0, sizeof H);
+  H.magic = kStoreMagic;
+  H.n_rows = P->n_rows;
+  H.n_cols = P->n_cols;
+  H.n_row_panels = (int64_t)P->rps.size();
+  H.acc_dtype = P->opts.acc_dtype;
+  H.has_sigma = P->has_sigma;
+  H.n_t = P->n_t;
+  H.n_partials = P->n_partials;
+  H.n_large = P->n_large;
+  H.n_large_t = P->n_large_t;
+  H.n_tblocks = (int64_t)P->lr_order.size();
+  int64_t nsec = 0, nsrc = 0;
+  for (auto& R : P->rps) { nsec += (int64_t)R.secs.size(); nsrc += R.ncols; }
+  H.n_row_sections = nsec;
+  int64_t ntiles = 0, ndst = 0;
+  for (auto& Cp : P->cps)
+    for (auto& S : Cp.secs) {
+      const int G = group_width(S.dtype);
+      ntiles += (S.ld / G + kTileGroups - 1) / kTileGroups;
+      ndst += S.ld;
+    }
+  H.n_col_tiles = ntiles;
+
+  int64_t off = align_up(sizeof(StoreHeader), kAlign);
+  auto take = [&](int64_t bytes) { int64_t o = off; off = align_up(off + bytes, kAlign); return o; };
+  H.off_row_panels = take(H.n_row_panels * (int64_t)sizeof(RowPanel));
+  H.off_row_sections = take(nsec * (int64_t)sizeof(RowSection));
+  H.off_row_order = take(H.n_row_panels * 4);
+  H.off_row_src = take(nsrc * 4);
+  H.off_col_tiles = take(ntiles * (int64_t)sizeof(ColTile));
+  H.off_col_dst = take(ndst * 4);
+  H.off_tblocks = take(H.n_tblocks * (int64_t)sizeof(TBlock));
+  H.off_large = take(H.n_large * 4);
+  H.off_owner = take((H.n_t - H.n_large_t) * 4);
+  H.off_sigma = take(P->has_sigma ? H.n_t * acc_sz : 0);
+  const int64_t meta_end = off;
+
+  // data: row sections, then column sections
+  int64_t src_off = 0;
+  double factor_bytes = 0, pad_bytes = 0;
+  for (int d = 0; d < 4; ++d) P->bytes_by_dtype[d] = 0;
+  for (auto& R : P->rps) {
+    R.src_off = src_off;
+    src_off += R.ncols;
+    for (auto& S : R.secs) {
+      const int64_t bytes = (int64_t)S.ngroups * R.m * 16;
+      S.data_off = take(bytes);
+      int64_t real = 0;
+      for (auto& s : R.segs)
+        if (s.dtype == S.dtype) real += s.ncols;
+      const int64_t real_bytes = real * R.m * dtype_size(S.dtype);
+      factor_bytes += (double)real_bytes;
+      pad_bytes += (double)(bytes - real_bytes);
+      P->bytes_by_dtype[S.dtype] += (size_t)real_bytes;
+    }
+  }
+  for (auto& Cp : P->cps)
+    for (auto& S : Cp.secs) {
+      const int64_t bytes = (int64_t)S.ld * Cp.nrows * dtype_size(S.dtype);
+      S.data_off = take(bytes);
+      int64_t real = 0;
+      for (auto& s : Cp.segs)
+        if (s.dtype == S.dtype) real += s.ncols;
+      const int64_t real_bytes = real * Cp.nrows * dtype_size(S.dtype);
+      factor_bytes += (double)real_bytes;
+      pad_bytes += (double)(bytes - real_bytes);
+      P->bytes_by_dtype[S.dtype] += (size_t)real_bytes;
+    }
+  P->store_bytes = (size_t)off;
+  P->meta_bytes = (size_t)meta_end;
+  P->factor_bytes = factor_bytes;
+
+  // work: partials then t, each aligned
+  P->work_part_off = 0;
+  P->work_t_off = align_up(P->n_partials * acc_sz, kAlign);
+  P->work_bytes_per_rhs = (size_t)align_up(P->work_t_off + P->n_t * acc_sz, kAlign);
+
+  // accounting
+  const int vec_sz = acc_sz;
+  double alg = factor_bytes + (double)P->n_cols * vec_sz + 2.0 * (double)P->n_rows * vec_sz;
+  if (P->has_sigma) alg += (double)P->n_t * acc_sz;
+  double flops = 0;
+  int64_t nd = 0, nl = 0;
+  for (auto& b : P->blocks) {
+    const double m = (double)(b.row_end - b.row_begin), n = (double)(b.col_end - b.col_begin);
+    if (b.kind == HM_DENSE) { flops += 2 * m * n; ++nd; }
+    else { flops += 2 * (m + n) * b.rank; ++nl; }
+  }
+  P->alg_bytes = alg;
+  P->alg_flops = flops;
+  P->n_dense = nd;
+  P->n_lowrank = nl;
+  P->overhead_bytes = (double)(nsrc + ndst) * 4 + pad_bytes +
+                      (double)H.n_row_panels * (sizeof(RowPanel) + 4) + nsec * sizeof(RowSection) +
+                      ntiles * sizeof(ColTile) + H.n_tblocks * sizeof(TBlock) +
+                      (double)(H.n_t - H.n_large_t) * 4 + 2.0 * P->n_partials * acc_sz +
+                      2.0 * P->n_t * acc_sz;
+  *out = P.release();
+  return ok();
+}
+
+// ------------------------------------------------------------------ packing
+
+static const double* fac(const double* const* arr, int64_t i) { return arr ? arr[i] : nullptr; }
+
+hm_status pack_store(const hm_plan* P, const double* const* a, const double* const* bf,
+                     const double* const* s, uint8_t* buf) {
+  const StoreHeader& H = P->hdr;
+  std::memcpy(buf, &H, sizeof H);
+  const int acc_sz = P->opts.acc_dtype == HM_F64 ? 8 : 4;
+  // check that every needed factor pointer is present
+  for (size_t i = 0; i < P->blocks.size(); ++i) {
+    const auto& b = P->blocks[i];
+    if (!fac(a, (int64_t)i) && (b.kind == HM_DENSE || b.rank > 0))
+      return fail(HM_EINVAL, "block %zu: missing first factor", i);
+    if (b.kind == HM_LOWRANK && b.rank > 0 && !fac(bf, (int64_t)i))
+      return fail(HM_EINVAL, "block %zu: missing second factor", i);
+    if (b.kind == HM_LOWRANK && b.rank > 0 && b.has_sigma && !fac(s, (int64_t)i))
+      return fail(HM_EINVAL, "block %zu: missing singular values", i);
+  }
+  // descriptor tables
+  auto* rp = reinterpret_cast<RowPanel*>(buf + H.off_row_panels);
+  auto* rs = reinterpret_cast<RowSection*>(buf + H.off_row_sections);
+  auto* ro = reinterpret_cast<int32_t*>(buf + H.off_row_order);
+  auto* rsrc = reinterpret_cast<int32_t*>(buf + H.off_row_src);
+  int32_t sec = 0;
+  for (size_t p = 0; p < P->rps.size(); ++p) {
+    const RowPanelHost& R = P->rps[p];
+    RowPanel& d = rp[p];
+    d.src_off = R.src_off;
+    d.row0 = (int32_t)R.row0;
+    d.m = R.m;
+    d.ncols = R.ncols;
+    d.sec0 = sec;
+    d.nsec = (int32_t)R.secs.size();
+    d.pad_ = 0;
+    for (auto& S : R.secs) {
+      RowSection& e = rs[sec++];
+      e.data_off = S.data_off;
+      e.dtype = S.dtype;
+      e.ngroups = S.ngroups;
+      e.col0 = S.col0;
+      e.pad_[0] = e.pad_[1] = e.pad_[2] = 0;
+    }
+    int32_t* src = rsrc + R.src_off;
+    for (int32_t c = 0; c < R.ncols; ++c) src[c] = 0;   // padding slots read x[0] (times 0)
+    for (auto& sg : R.segs) {
+      const RowSectionHost* S = nullptr;
+      for (auto& x : R.secs) if (x.dtype == sg.dtype) S = &x;
+      for (int32_t c = 0; c < sg.ncols; ++c) src[S->col0 + sg.seccol + c] = sg.src0 + c;
+    }
+  }
+  // launch order of row panels: largest first (longest-processing-time order)
+  {
+    std::vector<int32_t> ord(P->rps.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    auto bytes = [&](int32_t p) {
+      int64_t s = 0;
+      for (auto& S : P->rps[p].secs) s += (int64_t)S.ngroups * P->rps[p].m;
+      return s;
+    };
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return bytes(x) > bytes(y); });
+    std::copy(ord.begin(), ord.end(), ro);
+  }
+  // column tiles and destinations
+  auto* ct = reinterpret_cast<ColTile*>(buf + H.off_col_tiles);
+  auto* cdst = reinterpret_cast<int32_t*>(buf + H.off_col_dst);
+  int64_t tile = 0, dsto = 0;
+  for (auto& Cp : P->cps)
+    for (auto& S : Cp.secs) {
+      const int G = group_width(S.dtype);
+      const int ngr = S.ld / G;
+      int32_t* dst = cdst + dsto;
+      for (int32_t c = 0; c < S.ld; ++c) dst[c] = -1;
+      for (auto& sg : Cp.segs)
+        if (sg.dtype == S.dtype)
+          for (int32_t c = 0; c < sg.ncols; ++c) dst[sg.seccol + c] = sg.src0 + c;
+      for (int g0 = 0; g0 < ngr; g0 += kTileGroups) {
+        ColTile& T = ct[tile++];
+        T.data_off = S.data_off + (int64_t)g0 * G * dtype_size(S.dtype);
+        T.ld = S.ld;
+        T.nrows = Cp.nrows;
+        T.x0 = (int32_t)Cp.x0;
+        T.dtype = S.dtype;
+        T.ngroups = std::min(kTileGroups, ngr - g0);
+        T.dst_off = (int32_t)(dsto + (int64_t)g0 * G);
+      }
+      dsto += S.ld;
+    }
+  // reduction tables
+  auto* tb = reinterpret_cast<TBlock*>(buf + H.off_tblocks);
+  auto* lg = reinterpret_cast<int32_t*>(buf + H.off_large);
+  auto* own = reinterpret_cast<int32_t*>(buf + H.off_owner);
+  for (size_t q = 0; q < P->lr_order.size(); ++q) {
+    const int32_t i = P->lr_order[q];
+    const BlockInfo& bi = P->binfo[i];
+    TBlock& T = tb[q];
+    T.pst = (int32_t)bi.pst;
+    T.k = P->blocks[i].rank;
+    T.nseg = bi.nseg;
+    T.toff = (int32_t)bi.toff;
+    if ((int64_t)q < H.n_large) lg[q] = (int32_t)q;
+    else
+      for (int32_t l = 0; l < T.k; ++l) own[bi.toff - H.n_large_t + l] = (int32_t)q;
+    if (P->has_sigma) {
+      const auto& b = P->blocks[i];
+      for (int32_t l = 0; l < T.k; ++l) {
+        double v = b.has_sigma ? s[i][l] : 1.0;
+        put(buf + H.off_sigma + (bi.toff + l) * acc_sz, P->opts.acc_dtype, v);
+      }
+    }
+  }
+
+  // factor data, in parallel over panels
+  const size_t nrp = P->rps.size(), ncp = P->cps.size();
+  std::atomic<size_t> next{0};
+  auto worker = [&]() {
+    for (;;) {
+      size_t job = next.fetch_add(1);
+      if (job >= nrp + ncp) return;
+      if (job < nrp) {
+        const RowPanelHost& R = P->rps[job];
+        for (auto& sg : R.segs) {
+          const RowSectionHost* S = nullptr;
+          for (auto& x : R.secs) if (x.dtype == sg.dtype) S = &x;
+          const int G = group_width(S->dtype), sz = dtype_size(S->dtype);
+          const auto& b = P->blocks[sg.block];
+          const int64_t mb = b.row_end - b.row_begin;
+          const int64_t r_local = R.row0 - b.row_begin;
+          const double* A = a[sg.block];
+          uint8_t* base = buf + S->data_off;
+          for (int32_t c = 0; c < sg.ncols; ++c) {
+            const int32_t sc = sg.seccol + c;
+            const int32_t g = sc / G, cc = sc % G;
+            const double* col = A + (int64_t)(sg.c_first + c) * mb + r_local;
+            for (int32_t i = 0; i < R.m; ++i)
+              put(base + (((int64_t)g * R.m + i) * G + cc) * sz, S->dtype, col[i]);
+          }
+        }
+      } else {
+        const ColPanelHost& Cp = P->cps[job - nrp];
+        for (auto& sg : Cp.segs) {
+          const ColSectionHost* S = nullptr;
+          for (auto& x : Cp.secs) if (x.dtype == sg.dtype) S = &x;
+          const int sz = dtype_size(S->dtype);
+          const auto& b = P->blocks[sg.block];
+          const int64_t nbk = b.col_end - b.col_begin;
+          const int64_t c_local = Cp.x0 - b.col_begin;
+          const double* V = bf[sg.block];
+          uint8_t* base = buf + S->data_off;
+          for (int32_t c = 0; c < sg.ncols; ++c) {
+            const double* col = V + (int64_t)(sg.c_first + c) * nbk + c_local;
+            for (int32_t i = 0; i < Cp.nrows; ++i)
+              put(base + ((int64_t)i * S->ld + sg.seccol + c) * sz, S->dtype, col[i]);
+          }
+        }
+      }
+    }
+  };
+  unsigned nthr = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nthr; ++t) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+  return HM_OK;
+}
+
+}  // namespace hm
+
+using namespace hm;
+
+// ====================================================================== C-ABI
+extern "C" {
+
+hm_status hm_build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks,
+                        int64_t n_blocks, const hm_plan_opts* opts, hm_plan** out) {
+  try {
+    return build_plan(n_rows, n_cols, blocks, n_blocks, opts, out);
+  } catch (const std::bad_alloc&) {
+    return fail(HM_ENOMEM, "host allocation failed while building the plan");
+  } catch (...) {
+    return fail(HM_EINVAL, "unexpected error while building the plan");
+  }
+}
+
+hm_status hm_plan_info(const hm_plan* p, hm_plan_info_t* out) {
+  if (!p || !out) return fail(HM_EINVAL, "NULL argument");
+  std::memset(out, 0, sizeof *out);
+  out->store_bytes = p->store_bytes;
+  out->work_bytes_per_rhs = p->work_bytes_per_rhs;
+  out->alg_bytes = p->alg_bytes;
+  out->alg_flops = p->alg_flops;
+  out->overhead_bytes = p->overhead_bytes;
+  out->n_dense = p->n_dense;
+  out->n_lowrank = p->n_lowrank;
+  out->n_row_panels = p->hdr.n_row_panels;
+  out->n_col_tiles = p->hdr.n_col_tiles;
+  out->n_partials = p->n_partials;
+  out->n_t = p->n_t;
+  for (int d = 0; d < 4; ++d) out->bytes_by_dtype[d] = p->bytes_by_dtype[d];
+  return ok();
+}
+
+void hm_plan_destroy(hm_plan* p) { delete p; }
+
+hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t i, int64_t j,
+                         size_t* byte_offset, int32_t* dtype) {
+  if (!p || !byte_offset || !dtype) return fail(HM_EINVAL, "NULL argument");
+  if (block < 0 || block >= (int64_t)p->blocks.size()) return fail(HM_EINVAL, "block out of range");
+  const auto& b = p->blocks[block];
+  const int64_t m = b.row_end - b.row_begin, n = b.col_end - b.col_begin;
+  if (which == 0) {
+    const int64_t ncol = b.kind == HM_DENSE ? n : b.rank;
+    if (i < 0 || i >= m || j < 0 || j >= ncol) return fail(HM_EINVAL, "entry out of range");
+    const int64_t row = b.row_begin + i;
+    const int64_t pi = std::upper_bound(p->rint.begin(), p->rint.end(), row) - p->rint.begin() - 1;
+    const RowPanelHost& R = p->rps[pi];
+    for (auto& sg : R.segs)
+      if (sg.block == block && j >= sg.c_first && j < sg.c_first + sg.ncols) {
+        for (auto& S : R.secs)
+          if (S.dtype == sg.dtype) {
+            const int G = group_width(S.dtype);
+            const int64_t sc = sg.seccol + (j - sg.c_first);
+            *byte_offset = (size_t)(S.data_off + (((sc / G) * R.m + (row - R.row0)) * G + sc % G) *
+                                                     dtype_size(S.dtype));
+            *dtype = S.dtype;
+            return ok();
+          }
+      }
+    return fail(HM_EINVAL, "entry not stored (zero-rank block?)");
+  }
+  if (which == 1) {
+    if (b.kind != HM_LOWRANK || i < 0 || i >= n || j < 0 || j >= b.rank)
+      return fail(HM_EINVAL, "entry out of range");
+    const int64_t col = b.col_begin + i;
+    const int64_t ci = std::upper_bound(p->cint.begin(), p->cint.end(), col) - p->cint.begin() - 1;
+    const ColPanelHost& Cp = p->cps[ci];
+    for (auto& sg : Cp.segs)
+      if (sg.block == block && j >= sg.c_first && j < sg.c_first + sg.ncols) {
+        for (auto& S : Cp.secs)
+          if (S.dtype == sg.dtype) {
+            *byte_offset = (size_t)(S.data_off + ((col - Cp.x0) * S.ld + sg.seccol + (j - sg.c_first)) *
+                                                     dtype_size(S.dtype));
+            *dtype = S.dtype;
+            return ok();
+          }
+      }
+    return fail(HM_EINVAL, "entry not stored");
+  }
+  return fail(HM_EINVAL, "which must be 0 or 1");
+}
+
+hm_status hm_upload(const hm_plan* p, const double* const* a, const double* const* bf,
+                    const double* const* s, void* d_store, size_t store_bytes, void* stream,
+                    hm_matrix** out) {
+  if (!p || !out || !d_store) return fail(HM_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (store_bytes < p->store_bytes)
+    return fail(HM_ENOMEM, "store has %zu bytes, plan needs %zu", store_bytes, p->store_bytes);
+  if (((uintptr_t)d_store) % kAlign) return fail(HM_EINVAL, "store must be 256-byte aligned");
+  uint8_t* buf = (uint8_t*)std::calloc(p->store_bytes, 1);
+  if (!buf) return fail(HM_ENOMEM, "host staging allocation of %zu bytes failed", p->store_bytes);
+  hm_status st;
+  try {
+    st = pack_store(p, a, bf, s, buf);
+  } catch (...) {
+    st = fail(HM_ENOMEM, "packing failed");
+  }
+  if (st) { std::free(buf); return st; }
+  hipStream_t hs = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(d_store, buf, p->store_bytes, hipMemcpyHostToDevice, hs);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  std::free(buf);
+  if (e != hipSuccess) return fail(HM_EDEVICE, "upload copy failed: %s", hipGetErrorString(e));
+  auto* M = new (std::nothrow) hm_matrix();
+  if (!M) return fail(HM_ENOMEM, "host allocation failed");
+  M->hdr = p->hdr;
+  M->d_store = (const uint8_t*)d_store;
+  M->store_bytes = p->store_bytes;
+  M->work_bytes_per_rhs = p->work_bytes_per_rhs;
+  M->work_t_off = p->work_t_off;
+  M->acc_dtype = p->opts.acc_dtype;
+  M->max_nrhs = p->opts.max_nrhs;
+  M->launch = p->launch;
+  *out = M;
+  return ok();
+}
+
+hm_status hm_pack_host(const hm_plan* p, const double* const* a, const double* const* bf,
+                       const double* const* s, void* h_buf, size_t buf_bytes) {
+  if (!p || !h_buf) return fail(HM_EINVAL, "NULL argument");
+  if (buf_bytes < p->store_bytes)
+    return fail(HM_ENOMEM, "buffer has %zu bytes, plan needs %zu", buf_bytes, p->store_bytes);
+  std::memset(h_buf, 0, p->store_bytes);
+  hm_status st;
+  try {
+    st = pack_store(p, a, bf, s, (uint8_t*)h_buf);
+  } catch (...) {
+    st = fail(HM_ENOMEM, "packing failed");
+  }
+  return st ? st : ok();
+}
+
+void hm_matrix_destroy(hm_matrix* A) {
+  if (!A) return;
+  for (auto e : A->prof.ev) (void)hipEventDestroy(e);
+  delete A;
+}
+
+hm_status hm_profile_begin(hm_matrix* A, int32_t max_calls) {
+  if (!A || max_calls < 1 || max_calls > 1 << 16) return fail(HM_EINVAL, "bad profile arguments");
+  const size_t need = 4 * (size_t)max_calls;
+  while (A->prof.ev.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return fail(HM_EDEVICE, "event creation failed");
+    A->prof.ev.push_back(e);
+  }
+  A->prof.max_calls = max_calls;
+  A->prof.calls = 0;
+  A->prof.on = true;
+  return ok();
+}
+
+hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls) {
+  if (!A || !ms) return fail(HM_EINVAL, "NULL argument");
+  A->prof.on = false;
+  ms[0] = ms[1] = ms[2] = 0;
+  for (int32_t c = 0; c < A->prof.calls; ++c) {
+    hipEvent_t* e = &A->prof.ev[4 * (size_t)c];
+    if (hipEventSynchronize(e[3]) != hipSuccess) return fail(HM_EDEVICE, "event wait failed");
+    for (int k = 0; k < 3; ++k) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, e[k], e[k + 1]) != hipSuccess)
+        return fail(HM_EDEVICE, "event timing failed");
+      ms[k] += t;
+    }
+  }
+  if (calls) *calls = A->prof.calls;
+  return ok();
+}
+
+hm_status hm_mvm(const hm_matrix* A, double alpha, const void* d_x, void* d_y, void* d_work,
+                 size_t work_bytes, void* stream) {
+  if (!A || !d_x || !d_y) return fail(HM_EINVAL, "NULL argument");
+  if (d_x == d_y) return fail(HM_EINVAL, "x must not alias y");
+  if (work_bytes < A->work_bytes_per_rhs || (A->work_bytes_per_rhs > 0 && !d_work))
+    return fail(HM_ENOMEM, "workspace has %zu bytes, needs %zu", work_bytes, A->work_bytes_per_rhs);
+  if (d_work && ((uintptr_t)d_work) % kAlign) return fail(HM_EINVAL, "workspace must be 256-byte aligned");
+  hipError_t e = launch_mvm(*A, alpha, d_x, d_y, d_work, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(HM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const void* d_X,
+                       int64_t ldx, void* d_Y, int64_t ldy, void* d_work, size_t work_bytes,
+                       void* stream) {
+  if (!A || !d_X || !d_Y) return fail(HM_EINVAL, "NULL argument");
+  if (nrhs < 1 || nrhs > A->max_nrhs) return fail(HM_EINVAL, "nrhs %d outside [1, %d]", nrhs, A->max_nrhs);
+  if (ldx < A->hdr.n_cols || ldy < A->hdr.n_rows) return fail(HM_EINVAL, "leading dimension too small");
+  const size_t need = (size_t)nrhs * A->work_bytes_per_rhs;
+  if (work_bytes < need || (need > 0 && !d_work))
+    return fail(HM_ENOMEM, "workspace has %zu bytes, needs %zu", work_bytes, need);
+  if (d_work && ((uintptr_t)d_work) % kAlign) return fail(HM_EINVAL, "workspace must be 256-byte aligned");
+  const int vs = A->acc_dtype == HM_F64 ? 8 : 4;
+  const uint8_t* X = (const uint8_t*)d_X;
+  uint8_t* Y = (uint8_t*)d_Y;
+  if (X < Y + (size_t)ldy * vs * nrhs && Y < X + (size_t)ldx * vs * nrhs)
+    return fail(HM_EINVAL, "X must not overlap Y");
+  hipError_t e = launch_mvm_batch(*A, nrhs, alpha, d_X, ldx, d_Y, ldy, d_work, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(HM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+const char* hm_last_error(void) { return hm::g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Host-side plan and matrix objects of libhm (not part of the C-ABI).
+#pragma once
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "../../include/hm.h"
+#include "hm_layout.hpp"
+
+namespace hm {
+
+// Launch parameters (chosen by the tuner or built-in defaults).
+struct LaunchParams {
+  int row_cap = 2048;     // source slots staged in LDS per chunk (row kernel)
+  int row_unroll = 4;     // groups in flight per wave (row kernel)
+  int col_waves = 4;      // column tiles (waves) per workgroup
+};
+
+struct BlockInfo {
+  int64_t toff = 0;       // first entry of t_b
+  int64_t pst = 0;        // first partial
+  int32_t seg0 = 0, nseg = 0;   // column intervals covered by sigma_b
+};
+
+// A run of consecutive columns of one block inside a panel section.
+struct Seg {
+  int32_t block;
+  int32_t c_first;        // first column of the block (dense col or low-rank l)
+  int32_t ncols;
+  int32_t src0;           // row panels: source slot of the first column;
+                          // column panels: partial index of the first column
+  int32_t dtype;
+  int32_t seccol;         // column within its section
+};
+
+struct RowSectionHost { int32_t dtype = 0, ngroups = 0, col0 = 0; int64_t data_off = 0; };
+struct RowPanelHost {
+  int64_t row0 = 0;
+  int32_t m = 0, ncols = 0;
+  int64_t src_off = 0;
+  std::vector<Seg> segs;
+  std::vector<RowSectionHost> secs;
+};
+struct ColSectionHost { int32_t dtype = 0, ld = 0; int64_t data_off = 0; };
+struct ColPanelHost {
+  int64_t x0 = 0;
+  int32_t nrows = 0;
+  std::vector<Seg> segs;
+  std::vector<ColSectionHost> secs;
+};
+
+}  // namespace hm
+
+struct hm_plan {
+  int64_t n_rows = 0, n_cols = 0;
+  hm_plan_opts opts{};
+  std::string tune_path;
+  std::vector<hm_block_desc> blocks;
+  std::vector<hm::BlockInfo> binfo;
+  std::vector<int64_t> rint, cint;        // elementary interval boundaries (after splitting)
+  std::vector<hm::RowPanelHost> rps;
+  std::vector<hm::ColPanelHost> cps;
+  std::vector<int32_t> lr_order;          // low-rank blocks in t order (large first)
+  int64_t n_t = 0, n_partials = 0, n_large = 0, n_large_t = 0;
+  int32_t has_sigma = 0;
+  hm::StoreHeader hdr{};
+  size_t store_bytes = 0, meta_bytes = 0, work_bytes_per_rhs = 0;
+  int64_t work_part_off = 0, work_t_off = 0;
+  double factor_bytes = 0, alg_bytes = 0, alg_flops = 0, overhead_bytes = 0;
+  int64_t n_dense = 0, n_lowrank = 0;
+  size_t bytes_by_dtype[4] = {0, 0, 0, 0};
+  hm::LaunchParams launch;
+};
+
+namespace hm {
+// Per-call kernel events for hm_profile_begin / hm_profile_end.
+struct Profile {
+  bool on = false;
+  int32_t max_calls = 0, calls = 0;
+  std::vector<hipEvent_t> ev;   // 4 per call: before col, before reduce, before row, after row
+};
+}  // namespace hm
+
+struct hm_matrix {
+  hm::StoreHeader hdr{};
+  mutable hm::Profile prof;
+  const uint8_t* d_store = nullptr;
+  size_t store_bytes = 0, work_bytes_per_rhs = 0;
+  int64_t work_t_off = 0;
+  int32_t acc_dtype = 0, max_nrhs = 1;
+  hm::LaunchParams launch;
+};
+
+namespace hm {
+hm_status fail(hm_status code, const char* fmt, ...);
+hm_status ok();
+hm_status layout_store(hm_plan* P, hm_plan** out);
+uint16_t f64_to_f16(double d);
+uint16_t f64_to_bf16(double d);
+
+// Kernel launchers (hm_kernels.hip).
+hipError_t launch_mvm(const hm_matrix& A, double alpha, const void* x, void* y, void* work,
+                      hipStream_t s, hipEvent_t* ev = nullptr);
+hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const void* X, int64_t ldx,
+                            void* Y, int64_t ldy, void* work, hipStream_t s);
+}  // namespace hm

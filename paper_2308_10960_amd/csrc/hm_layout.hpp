@@ -1,0 +1,90 @@
+// Device-side layout of a packed H-matrix store (shared by the host packer
+// and the HIP kernels; plain structs, no HIP types).
+//
+// The product y += alpha * sum_b E_tau M_b E_sigma^T x is regrouped so that
+// every kernel streams contiguous, dtype-homogeneous panels:
+//
+//  * Row panels.  The row breakpoints of all leaf blocks cut [0, n_rows) into
+//    elementary row intervals (at most 64 rows after splitting).  For one
+//    such interval rho, every leaf block whose row cluster contains rho
+//    contributes its rows restricted to rho: all n_b columns of a dense D_b
+//    (source x[sigma]) and the k columns of U_b / W_b (source t_b).  The
+//    panel is stored per storage dtype ("section") in column groups of G
+//    columns, element (i, c) of group g at ((g*m + i)*G + c): one 16-byte
+//    load per lane (lane = row) covers G columns.  The kernel owns y[rho]:
+//    y[rho] += alpha * P_rho z_rho, with z the gathered sources.
+//  * Column tiles.  The column breakpoints of the low-rank blocks cut
+//    [0, n_cols) into elementary column intervals kappa (<= 64 columns).
+//    For each, the rows of V_b / X_b restricted to kappa are concatenated
+//    over all low-rank blocks whose column cluster contains kappa, row-major
+//    (row i of the section holds ld contiguous values); a lane owns G
+//    adjacent columns and accumulates them over the interval's rows:
+//    partial(b, kappa, l) = sum_{i in kappa} V_b[i, l] x[i].
+//  * Reduction.  t_b[l] = s_b[l] * sum over the column intervals of
+//    sigma_b of the partials, in ascending interval order.
+//
+// All offsets are in bytes from the start of the store unless noted.
+
+#pragma once
+#include <stdint.h>
+
+namespace hm {
+
+constexpr int kMaxPanelRows = 64;   // rows per row panel (one wave's lanes)
+constexpr int kMaxTileRows = 64;    // rows per column interval
+constexpr int kTileGroups = 64;     // column groups per column tile (one per lane)
+constexpr int kLargeSeg = 16;       // blocks with more intervals reduce per workgroup
+constexpr int kAlign = 256;
+
+// Columns per 16-byte group for a storage dtype (F64, F32, F16, BF16).
+inline constexpr int group_width(int dt) { return dt == 0 ? 2 : dt == 1 ? 4 : 8; }
+inline constexpr int dtype_size(int dt) { return dt == 0 ? 8 : dt == 1 ? 4 : 2; }
+
+struct RowPanel {        // 32 bytes
+  int64_t src_off;       // first entry (int32 units) in the row-source table
+  int32_t row0, m;       // rows [row0, row0 + m), m <= 64
+  int32_t ncols;         // source slots over all sections (each section starts at a multiple of 8)
+  int32_t sec0, nsec;    // sections [sec0, sec0 + nsec) in the section table
+  int32_t pad_;
+};
+
+struct RowSection {      // 32 bytes
+  int64_t data_off;      // byte offset of group 0
+  int32_t dtype;         // storage dtype (hm_dtype)
+  int32_t ngroups;       // groups of group_width(dtype) columns
+  int32_t col0;          // first source slot of the section (a multiple of 8)
+  int32_t pad_[3];
+};
+
+struct ColTile {         // 32 bytes: one wave streams nrows rows x ngroups*G columns
+  int64_t data_off;      // byte offset of (row 0, first column of the tile)
+  int32_t ld;            // row stride of the section, in elements
+  int32_t nrows;         // rows of the column interval (<= 64)
+  int32_t x0;            // first x index of the interval
+  int32_t dtype;
+  int32_t ngroups;       // groups in this tile (<= 64)
+  int32_t dst_off;       // first entry (int32 units) of this tile in the destination table
+};
+
+struct TBlock {          // 16 bytes: reduction of one low-rank block's partials
+  int32_t pst;           // first partial (acc units); partial (seg, l) at pst + seg*k + l
+  int32_t k;             // rank
+  int32_t nseg;          // column intervals in sigma_b
+  int32_t toff;          // first entry of t_b in t
+};
+
+// Header at offset 0 of the store; every table offset is a byte offset.
+struct StoreHeader {
+  uint64_t magic;
+  int64_t n_rows, n_cols;
+  int64_t n_row_panels, n_row_sections, n_col_tiles, n_tblocks;
+  int64_t n_large, n_large_t, n_t, n_partials;
+  int64_t off_row_panels, off_row_sections, off_row_order, off_row_src;
+  int64_t off_col_tiles, off_col_dst;
+  int64_t off_tblocks, off_large, off_owner, off_sigma;
+  int64_t acc_dtype, has_sigma;
+};
+
+constexpr uint64_t kStoreMagic = 0x484d53544f524531ull;  // "HMSTORE1"
+
+}  // namespace hm

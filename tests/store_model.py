@@ -1,0 +1,89 @@
+"""Test-only numpy interpretation of a packed store (no GPU).
+
+Reads the header and descriptor tables that hm_pack_host wrote and evaluates
+the product the way the store's layout defines it (row panels, column tiles,
+partial reduction).  Used to check the block scheduler and the packer on the
+CPU against the oracle; it shares no code with either.
+"""
+
+import numpy as np
+
+HDR = np.dtype([("magic", "<u8"), ("n_rows", "<i8"), ("n_cols", "<i8"),
+                ("n_row_panels", "<i8"), ("n_row_sections", "<i8"), ("n_col_tiles", "<i8"),
+                ("n_tblocks", "<i8"), ("n_large", "<i8"), ("n_large_t", "<i8"), ("n_t", "<i8"),
+                ("n_partials", "<i8"), ("off_row_panels", "<i8"), ("off_row_sections", "<i8"),
+                ("off_row_order", "<i8"), ("off_row_src", "<i8"), ("off_col_tiles", "<i8"),
+                ("off_col_dst", "<i8"), ("off_tblocks", "<i8"), ("off_large", "<i8"),
+                ("off_owner", "<i8"), ("off_sigma", "<i8"), ("acc_dtype", "<i8"),
+                ("has_sigma", "<i8")])
+RP = np.dtype([("src_off", "<i8"), ("row0", "<i4"), ("m", "<i4"), ("ncols", "<i4"),
+               ("sec0", "<i4"), ("nsec", "<i4"), ("pad", "<i4")])
+RS = np.dtype([("data_off", "<i8"), ("dtype", "<i4"), ("ngroups", "<i4"), ("col0", "<i4"),
+               ("pad", "<i4", (3,))])
+CT = np.dtype([("data_off", "<i8"), ("ld", "<i4"), ("nrows", "<i4"), ("x0", "<i4"),
+               ("dtype", "<i4"), ("ngroups", "<i4"), ("dst_off", "<i4")])
+TB = np.dtype([("pst", "<i4"), ("k", "<i4"), ("nseg", "<i4"), ("toff", "<i4")])
+G = {0: 2, 1: 4, 2: 8, 3: 8}
+SZ = {0: 8, 1: 4, 2: 2, 3: 2}
+
+
+def decode(buf: np.ndarray, off: int, count: int, dt: int) -> np.ndarray:
+    raw = buf[off: off + count * SZ[dt]]
+    if dt == 0:
+        return raw.view("<f8").astype(np.float64)
+    if dt == 1:
+        return raw.view("<f4").astype(np.float64)
+    if dt == 2:
+        return raw.view("<f2").astype(np.float64)
+    return (raw.view("<u2").astype(np.uint32) << 16).view("<f4").astype(np.float64)
+
+
+def tables(buf: np.ndarray):
+    h = buf[:HDR.itemsize].view(HDR)[0]
+    def arr(dt, off, n):
+        return buf[off: off + n * dt.itemsize].view(dt) if n else np.zeros(0, dt)
+    return h, dict(
+        rp=arr(RP, h["off_row_panels"], h["n_row_panels"]),
+        rs=arr(RS, h["off_row_sections"], h["n_row_sections"]),
+        order=arr(np.dtype("<i4"), h["off_row_order"], h["n_row_panels"]),
+        ct=arr(CT, h["off_col_tiles"], h["n_col_tiles"]),
+        tb=arr(TB, h["off_tblocks"], h["n_tblocks"]),
+    )
+
+
+def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> np.ndarray:
+    h, T = tables(buf)
+    n_cols = int(h["n_cols"])
+    part = np.zeros(int(h["n_partials"]))
+    dst_all = buf[h["off_col_dst"]:].view("<i4")
+    for t in T["ct"]:
+        g, nr, ld, dt = G[int(t["dtype"])], int(t["nrows"]), int(t["ld"]), int(t["dtype"])
+        cols = int(t["ngroups"]) * g
+        rows = [decode(buf, int(t["data_off"]) + i * ld * SZ[dt], cols, dt) for i in range(nr)]
+        V = np.stack(rows)                                   # nr x cols
+        p = V.T @ x[int(t["x0"]): int(t["x0"]) + nr]
+        d = dst_all[int(t["dst_off"]): int(t["dst_off"]) + cols]
+        part[d[d >= 0]] = p[d >= 0]
+    t_vec = np.zeros(int(h["n_t"]))
+    sig = None
+    if h["has_sigma"]:
+        sig = decode(buf, int(h["off_sigma"]), int(h["n_t"]), 0 if h["acc_dtype"] == 0 else 1)
+    for b in T["tb"]:
+        k, ns, pst, toff = int(b["k"]), int(b["nseg"]), int(b["pst"]), int(b["toff"])
+        s = part[pst: pst + ns * k].reshape(ns, k).sum(0)
+        t_vec[toff: toff + k] = s if sig is None else s * sig[toff: toff + k]
+    z = np.concatenate([x, t_vec])
+    src_all = buf[h["off_row_src"]:].view("<i4")
+    y = np.array(y0, dtype=np.float64, copy=True)
+    for p in T["rp"]:
+        m = int(p["m"])
+        src = src_all[int(p["src_off"]): int(p["src_off"]) + int(p["ncols"])]
+        acc = np.zeros(m)
+        for s in T["rs"][int(p["sec0"]): int(p["sec0"]) + int(p["nsec"])]:
+            dt, ng, c0 = int(s["dtype"]), int(s["ngroups"]), int(s["col0"])
+            g = G[dt]
+            vals = decode(buf, int(s["data_off"]), ng * m * g, dt).reshape(ng, m, g)
+            M = vals.transpose(1, 0, 2).reshape(m, ng * g)       # m x cols
+            acc += M @ z[src[c0: c0 + ng * g]]
+        y[int(p["row0"]): int(p["row0"]) + m] += alpha * acc
+    return y

@@ -1,0 +1,202 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+FP64 path: relative 2-norm error <= 1e-12 against the oracle (plus an
+elementwise bound), at n = 4096 and at the full n = 2^18 sizes (eps 1e-6 and
+1e-8, the configuration the benchmark times).  Mixed storage with FP32
+accumulation: against the decoded oracle within the rigorous FP32 summation
+bound, and against the unrounded FP64 oracle within 1e-6.  Edge cases:
+all-dense and single-block partitions, tiny and non-square tilings, y0 / alpha
+handling, x = 0, determinism, linearity, batched right-hand sides.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import hmgen
+import oracle
+from hmgen import hmatrix as hmm
+from paper_2308_10960_amd import hm, DeviceHMatrix
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    assert os.path.exists(hm.LIB_PATH), "libhm.so must be built before the GPU tests"
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def run(D, x, y0=None, alpha=1.0):
+    xd = D.vector(x)
+    yd = D.vector(y0) if y0 is not None else D.vector()
+    D.mvm(xd, yd, alpha)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy().astype(np.float64)
+
+
+def abs_bound(H, x, factors=None):
+    """|A| |x| with |U| |V|^T for low-rank blocks: scale of the summands."""
+    fac = []
+    for i in range(H.nblocks):
+        a, b, s = factors[i] if factors is not None else H.factors(i)
+        fac.append((np.abs(np.asfortranarray(a)), None if b is None else np.abs(np.asfortranarray(b)),
+                    None if s is None else np.abs(np.asarray(s))))
+    return oracle.hmvm(H, np.abs(x), factors=fac)
+
+
+def check_f64(y, ref, scale, tol=F64_TOL):
+    rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    say(f"relative error {rel:.3e}")
+    assert rel <= tol
+    assert np.all(np.abs(y - ref) <= 1e-13 * scale + 1e-300)
+
+
+@pytest.fixture(scope="module")
+def sphere4k():
+    return hmgen.build_preset("sphere4k")
+
+
+def test_sphere4k_f64(sphere4k):
+    H = sphere4k
+    say("sphere4k f64")
+    D = DeviceHMatrix(H, hm.HM_F64)
+    x = hmgen.uniform_vector(H.n)
+    y0 = hmgen.uniform_vector(H.n, seed=9)
+    ref = oracle.hmvm(H, x)
+    y = run(D, x)
+    check_f64(y, ref, abs_bound(H, x))
+    # y += alpha A x with nonzero y0
+    ref2 = oracle.hmvm(H, x, y0, alpha=-0.625)
+    y2 = run(D, x, y0, alpha=-0.625)
+    check_f64(y2, ref2, 0.625 * abs_bound(H, x) + np.abs(y0))
+    # x = 0 leaves y unchanged, bit for bit
+    y3 = run(D, np.zeros(H.n), y0)
+    np.testing.assert_array_equal(y3, y0)
+    # determinism: repeated calls agree bit for bit
+    for _ in range(3):
+        np.testing.assert_array_equal(run(D, x), y)
+    # linearity
+    z = hmgen.uniform_vector(H.n, seed=4)
+    lin = run(D, 2.0 * x - 3.0 * z)
+    assert np.linalg.norm(lin - (2 * y - 3 * run(D, z))) <= 1e-13 * np.linalg.norm(lin)
+    D.close()
+
+
+def test_store_upload_matches_host_packing(sphere4k):
+    H = sphere4k
+    D = DeviceHMatrix(H, hm.HM_F64)
+    buf = np.zeros(D.info["store_bytes"], np.uint8)
+    hm.hm_pack_host(D.plan, H.a_ptr, H.b_ptr, None, buf)
+    dev = D.store.cpu().numpy()
+    np.testing.assert_array_equal(dev, buf)
+    D.close()
+
+
+@pytest.mark.parametrize("case", ["eta0", "one_block", "tiny5", "tiny1"])
+def test_degenerate_partitions(case):
+    say("degenerate", case)
+    if case == "eta0":
+        H = hmm.build_hmatrix(hmgen.fibonacci_sphere(1000), hmm.KERNEL_LAPLACE, leaf=32, eta=0.0)
+    elif case == "one_block":
+        H = hmm.build_hmatrix(hmgen.fibonacci_sphere(300), hmm.KERNEL_LAPLACE, leaf=512)
+    elif case == "tiny5":
+        H = hmm.build_hmatrix(hmgen.cube_points(5, 1), hmm.KERNEL_EXP, leaf=2)
+    else:
+        H = hmm.build_hmatrix(hmgen.cube_points(1, 1), hmm.KERNEL_EXP, leaf=64)
+    H.set_uniform_dtype(hmm.DT_F64)
+    D = DeviceHMatrix(H, hm.HM_F64)
+    x = hmgen.uniform_vector(H.n, seed=2)
+    check_f64(run(D, x), oracle.hmvm(H, x), abs_bound(H, x))
+    D.close()
+
+
+def test_ragged_leaf_sizes_and_eta():
+    """Several tiles per panel, ragged panel heights, and a ragged tail."""
+    for n, leaf, eta in [(3001, 37, 1.0), (2500, 64, 0.5), (4099, 16, 2.0)]:
+        say("ragged", n, leaf, eta)
+        H = hmm.build_hmatrix(hmgen.cube_points(n, 7), hmm.KERNEL_EXP, leaf=leaf, eta=eta, eps=1e-7)
+        H.set_uniform_dtype(hmm.DT_F64)
+        D = DeviceHMatrix(H, hm.HM_F64)
+        x = hmgen.uniform_vector(n, seed=3)
+        check_f64(run(D, x), oracle.hmvm(H, x), abs_bound(H, x))
+        D.close()
+
+
+def test_batched_rhs_equal_single(sphere4k):
+    H = sphere4k
+    D = DeviceHMatrix(H, hm.HM_F64, max_nrhs=5)
+    X = hmgen.gaussian_block(H.n, 5)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()      # (r, n) = column-major n x r
+    Yd = torch.zeros_like(Xd)
+    hm.hm_mvm_batch(D.handle, 5, 1.0, Xd, H.n, Yd, H.n, D.work, D.work.numel())
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy().T
+    ref = oracle.hmvm_multi(H, X)
+    for c in range(5):
+        np.testing.assert_array_equal(Y[:, c], run(D, X[:, c]))
+        check_f64(Y[:, c], ref[:, c], abs_bound(H, X[:, c]))
+    D.close()
+
+
+@pytest.mark.parametrize("name", ["sphere256k", "sphere256k_e8"])
+def test_full_size_f64(name):
+    say("building", name)
+    H = hmgen.build_preset(name)
+    say("built", H.stats())
+    D = DeviceHMatrix(H, hm.HM_F64)
+    say("uploaded", D.info["store_bytes"])
+    x = hmgen.uniform_vector(H.n)
+    y = run(D, x)
+    say("gpu done; oracle")
+    ref = oracle.hmvm(H, x)
+    rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    say(f"{name}: relative error {rel:.3e}")
+    assert rel <= F64_TOL
+    # elementwise on a sample of rows, against the summand scale
+    idx = np.random.default_rng(0).choice(H.n, 2000, replace=False)
+    scale = abs_bound(H, x)
+    assert np.all(np.abs(y[idx] - ref[idx]) <= 1e-13 * scale[idx])
+    D.close()
+
+
+def _mixed(H, name):
+    D = DeviceHMatrix(H, hm.HM_F32)
+    x64 = hmgen.uniform_vector(H.n)
+    x = x64.astype(np.float32).astype(np.float64)        # the vector the GPU sees
+    y = run(D, x)
+    dec = oracle.decoded_factors(H, sigma_dtype=oracle.F32)
+    ref_dec = oracle.hmvm(H, x, factors=dec)
+    truth = oracle.hmvm(H, x)
+    # rigorous FP32 summation bound: |err| <= gamma_K * (|A_dec| |x|), K = longest sum
+    K = 4096 + 64
+    gam = K * U32 / (1 - K * U32)
+    scale = abs_bound(H, x, dec)
+    err = np.abs(y - ref_dec)
+    say(f"{name}: max err/scale {np.max(err / scale):.3e}, "
+        f"rel vs decoded {np.linalg.norm(y - ref_dec) / np.linalg.norm(ref_dec):.3e}, "
+        f"rel vs truth {np.linalg.norm(y - truth) / np.linalg.norm(truth):.3e}")
+    assert np.all(err <= gam * scale)
+    assert np.linalg.norm(y - truth) / np.linalg.norm(truth) <= 1e-6
+    D.close()
+
+
+def test_mixed_sphere4k():
+    _mixed(hmgen.build_preset("sphere4k_mixed"), "sphere4k_mixed")
+
+
+def test_mixed_full_size():
+    say("building sphere256k_mixed")
+    _mixed(hmgen.build_preset("sphere256k_mixed"), "sphere256k_mixed")

@@ -1,0 +1,211 @@
+"""Block scheduler, store packing and C-ABI checks that need no GPU.
+
+* libhm.so loads and exports every function include/hm.h declares.
+* Malformed block tables are rejected with the documented status codes.
+* Storage conversion (FP64 -> FP32/FP16/BF16, RNE, one rounding) is bit-exact
+  against the oracle's own rounding, at positions hm_plan_locate reports.
+* A numpy reading of the packed store reproduces the oracle's product.
+"""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import hmgen
+import oracle
+from paper_2308_10960_amd import hm, blocks_from_table
+from conftest import ROOT
+from store_model import model_mvm, SZ
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib_built():
+    if not os.path.exists(hm.LIB_PATH):
+        from paper_2308_10960_amd import build
+        build.build()
+
+
+def test_exports_every_declared_symbol():
+    text = open(os.path.join(ROOT, "include", "hm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(hm_[a-z_0-9]+)\s*\(", text))
+    assert len(names) >= 16
+    L = hm.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert names <= set(hm.PROTOTYPES), names - set(hm.PROTOTYPES)
+
+
+def _table(n=40):
+    """A tiny hand-made partition of [0,n) x [0,n): 2x2 blocks, one low rank."""
+    h = n // 2
+    return hm.make_blocks(
+        rb=[0, 0, h, h], re=[h, h, n, n], cb=[0, h, 0, h], ce=[h, n, h, n],
+        kind=[0, 1, 1, 0], rank=[0, 3, 2, 0], ngroups=[1, 1, 1, 1],
+        group_cols=[[0, 0, 0, 0], [3, 0, 0, 0], [2, 0, 0, 0], [0, 0, 0, 0]],
+        group_dtype=[[0] * 4] * 4, has_sigma=[0, 0, 0, 0])
+
+
+def _expect(status, blocks, n_rows=40, n_cols=40, acc=hm.HM_F64):
+    with pytest.raises(hm.HMError) as e:
+        hm.hm_build_plan(n_rows, n_cols, blocks, acc)
+    assert e.value.status == status, str(e.value)
+
+
+def test_valid_table_builds():
+    p = hm.hm_build_plan(40, 40, _table())
+    info = hm.hm_plan_info(p)
+    assert info["n_dense"] == 2 and info["n_lowrank"] == 2
+    assert info["alg_bytes"] == 8 * (2 * 400 + (20 + 20) * 5) + 8 * 40 * 3
+    assert info["alg_flops"] == 2 * (2 * 400 + (20 + 20) * 5)
+    hm.hm_plan_destroy(p)
+
+
+def test_rejects_malformed_tables():
+    t = _table()
+    b = t.copy(); b["col_end"][0] = 21
+    _expect(hm.HM_EPARTITION, b)                          # overlap
+    b = t.copy(); b["col_begin"][1] = 21
+    _expect(hm.HM_EPARTITION, b)                          # gap
+    _expect(hm.HM_EPARTITION, t[:3])                      # missing block
+    b = t.copy(); b["row_end"][3] = 41
+    _expect(hm.HM_ESHAPE, b)                              # out of range
+    b = t.copy(); b["rank"][1] = -1
+    _expect(hm.HM_ESHAPE, b)                              # negative rank
+    b = t.copy(); b["rank"][1] = 21; b["group_cols"][1][0] = 21
+    _expect(hm.HM_ESHAPE, b)                              # rank > min(m, n)
+    b = t.copy(); b["group_cols"][1][0] = 2
+    _expect(hm.HM_ESHAPE, b)                              # groups do not sum to rank
+    b = t.copy(); b["group_dtype"][0][0] = 7
+    _expect(hm.HM_EDTYPE, b)                              # unknown dtype
+    _expect(hm.HM_EDTYPE, t, acc=hm.HM_F32)               # FP64 storage, FP32 accumulation
+    b = t.copy(); b["kind"][1] = 5
+    _expect(hm.HM_EINVAL, b)                              # unknown kind
+    b = t.copy(); b["rank"][0] = 2
+    _expect(hm.HM_ESHAPE, b)                              # dense with rank
+    _expect(hm.HM_EINVAL, t, n_rows=0)
+    with pytest.raises(hm.HMError) as e:
+        hm.hm_build_plan(40, 40, t, acc_dtype=5)
+    assert e.value.status == hm.HM_EDTYPE
+
+
+@pytest.fixture(scope="module")
+def mixed4k():
+    return hmgen.build_preset("sphere4k_mixed")
+
+
+@pytest.fixture(scope="module")
+def f64_4k():
+    return hmgen.build_preset("sphere4k")
+
+
+def _pack(H, acc):
+    blocks = blocks_from_table(H)
+    p = hm.hm_build_plan(H.n, H.n, blocks, acc)
+    info = hm.hm_plan_info(p)
+    buf = np.zeros(info["store_bytes"], np.uint8)
+    hm.hm_pack_host(p, H.a_ptr, H.b_ptr, H.s_ptr if H.keep_sigma else None, buf)
+    return p, info, buf
+
+
+def test_storage_conversion_bit_exact(mixed4k):
+    H = mixed4k
+    p, info, buf = _pack(H, hm.HM_F32)
+    rng = np.random.default_rng(0)
+    seen = set()
+    for bi in rng.choice(H.nblocks, 400, replace=False):
+        a, b, s = H.factors(bi)
+        for which, F in ((0, a), (1, b)):
+            if F is None or F.size == 0:
+                continue
+            for _ in range(6):
+                i, j = int(rng.integers(F.shape[0])), int(rng.integers(F.shape[1]))
+                off, dt = hm.hm_plan_locate(p, int(bi), which, i, j)
+                if H.adm[bi]:
+                    g = np.searchsorted(np.cumsum(H.group_cols[bi][:H.ngroups[bi]]), j, side="right")
+                    assert dt == H.group_dtype[bi][g]
+                else:
+                    assert dt == H.group_dtype[bi][0]
+                stored = buf[off: off + SZ[dt]]
+                want = oracle.round_to(np.array([F[i, j]]), dt)
+                exp_bytes = {1: want.astype("<f4"), 2: want.astype("<f2"),
+                             3: (want.astype("<f4").view("<u4") >> 16).astype("<u2"),
+                             0: want.astype("<f8")}[dt].view(np.uint8)
+                assert bytes(stored) == bytes(exp_bytes), (bi, which, i, j, dt)
+                seen.add(dt)
+    assert {1, 2} <= seen
+    hm.hm_plan_destroy(p)
+
+
+@pytest.mark.parametrize("which", ["f64", "mixed"])
+def test_store_model_matches_oracle(which, f64_4k, mixed4k):
+    H = f64_4k if which == "f64" else mixed4k
+    acc = hm.HM_F64 if which == "f64" else hm.HM_F32
+    p, info, buf = _pack(H, acc)
+    x = hmgen.uniform_vector(H.n)
+    y0 = hmgen.uniform_vector(H.n, seed=5)
+    if which == "f64":
+        ref = oracle.hmvm(H, x, y0, alpha=0.75)
+    else:
+        ref = oracle.hmvm(H, x, y0, alpha=0.75,
+                          factors=oracle.decoded_factors(H, sigma_dtype=oracle.F32))
+    y = model_mvm(buf, x, y0, 0.75)
+    assert np.linalg.norm(y - ref) <= 1e-13 * np.linalg.norm(ref)
+    assert info["store_bytes"] == buf.nbytes
+    assert info["alg_bytes"] < info["store_bytes"]
+    hm.hm_plan_destroy(p)
+
+
+def test_nonsquare_random_partition():
+    """A non-square, non-hierarchical tiling with ragged sizes and all formats."""
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([[0, 157], rng.integers(1, 157, 6)]))
+    cols = np.unique(np.concatenate([[0, 211], rng.integers(1, 211, 5)]))
+    blocks, facs = [], []
+    for r0, r1 in zip(rows[:-1], rows[1:]):
+        for c0, c1 in zip(cols[:-1], cols[1:]):
+            m, n = r1 - r0, c1 - c0
+            if rng.random() < 0.4 or min(m, n) < 2:
+                blocks.append((r0, r1, c0, c1, 0, 0, 1, [0, 0, 0, 0], [int(rng.integers(1, 4))] + [0] * 3))
+                facs.append((np.asfortranarray(rng.standard_normal((m, n))), None, None))
+            else:
+                k = int(rng.integers(1, min(m, n) + 1))
+                k1 = int(rng.integers(0, k + 1))
+                gc = [k1, k - k1, 0, 0] if 0 < k1 < k else [k, 0, 0, 0]
+                ng = 2 if 0 < k1 < k else 1
+                gd = [1, int(rng.integers(2, 4)), 0, 0]
+                blocks.append((r0, r1, c0, c1, 1, k, ng, gc, gd))
+                facs.append((np.asfortranarray(rng.standard_normal((m, k))),
+                             np.asfortranarray(rng.standard_normal((n, k))), None))
+    B = np.array(blocks, dtype=object)
+    desc = hm.make_blocks(B[:, 0].astype(int), B[:, 1].astype(int), B[:, 2].astype(int),
+                          B[:, 3].astype(int), B[:, 4].astype(int), B[:, 5].astype(int),
+                          B[:, 6].astype(int), np.array(list(B[:, 7])), np.array(list(B[:, 8])),
+                          np.zeros(len(blocks), int))
+    p = hm.hm_build_plan(157, 211, desc, hm.HM_F32)
+    info = hm.hm_plan_info(p)
+    buf = np.zeros(info["store_bytes"], np.uint8)
+    ap = np.array([f[0].ctypes.data for f in facs], np.uint64)
+    bp = np.array([f[1].ctypes.data if f[1] is not None else 0 for f in facs], np.uint64)
+    hm.hm_pack_host(p, ap, bp, None, buf)
+    x = rng.uniform(-1, 1, 211)
+    y = model_mvm(buf, x, np.zeros(157), 1.0)
+    # dense reference from the rounded factors
+    A = np.zeros((157, 211))
+    for blk, f in zip(blocks, facs):
+        r0, r1, c0, c1, kind, k, ng, gc, gd = blk
+        if kind == 0:
+            A[r0:r1, c0:c1] = oracle.round_to(f[0], gd[0])
+        else:
+            U, V = f[0].copy(), f[1].copy()
+            c = 0
+            for g in range(ng):
+                U[:, c:c + gc[g]] = oracle.round_to(U[:, c:c + gc[g]], gd[g])
+                V[:, c:c + gc[g]] = oracle.round_to(V[:, c:c + gc[g]], gd[g])
+                c += gc[g]
+            A[r0:r1, c0:c1] = U @ V.T
+    ref = A @ x
+    assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+    hm.hm_plan_destroy(p)
