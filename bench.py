@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--workload", default="sphere256k")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -100,6 +102,16 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(3)
     torch.cuda.set_device(0)
+    if args.copy_gib > 0:
+        nbytes = int(args.copy_gib * 2 ** 30) // 16 * 16
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                          "launches": max(1, args.steps)}), flush=True)
+        return
     p = hmgen.preset(args.workload)
     log("building", args.workload, p)
     H = hmgen.build_preset(args.workload)
