@@ -28,15 +28,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["k_col", "k_reduce", "k_row"]
+# per-call kernel phases reported by hm_profile_end: single RHS (hm_mvm) and
+# batched (hm_mvm_batch) schedules
+KERNELS = {0: ["k_col", "k_reduce", "k_row"], 1: ["k_p1", "k_reduce", "k_p2"]}
+KERNELS_BATCH = ["k_xpose+k_col_b", "k_reduce_b", "k_row_b"]
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(H, info, vs):
-    """Algorithmic bytes each kernel must move in one product."""
+def kernel_bytes(H, info, vs, R=1, schedule=0):
+    """Algorithmic bytes each kernel must move in one product of R
+    right-hand sides (factors once, vectors and partial sums per column)."""
     m = (H.re - H.rb).astype(np.float64)
     nb = (H.ce - H.cb).astype(np.float64)
     dense = H.adm == 0
@@ -49,10 +53,27 @@ def kernel_bytes(H, info, vs):
     n = float(H.n)
     n_t, n_p = float(info["n_t"]), float(info["n_partials"])
     sig = n_t * vs if getattr(H, "keep_sigma", False) else 0.0
+    if R == 1 and schedule == 0:
+        return {
+            "k_col": v_bytes + vs * (n + n_p),
+            "k_reduce": vs * (n_p + n_t) + sig,
+            "k_row": d_bytes + u_bytes + vs * (n + n_t + 2 * n),
+        }
+    if R == 1:
+        return {
+            # dense row-panel sections and column tiles: D and V bytes, x, y read+write,
+            # partial sums written
+            "k_p1": d_bytes + v_bytes + vs * (n + 2 * n + n_p),
+            "k_reduce": vs * (n_p + n_t) + sig,
+            # U sections: U bytes, t, y read+write
+            "k_p2": u_bytes + vs * (n_t + 2 * n),
+        }
     return {
-        "k_col": v_bytes + vs * (n + n_p),
-        "k_reduce": vs * (n_p + n_t) + sig,
-        "k_row": d_bytes + u_bytes + vs * (n + n_t + 2 * n),
+        # X transposed (read + write) then V bytes, X rows, partials written
+        "k_xpose+k_col_b": v_bytes + R * vs * (2 * n + n + n_p),
+        "k_reduce_b": R * vs * (n_p + n_t) + sig,
+        # D and U bytes, X and t rows, Y read+write
+        "k_row_b": d_bytes + u_bytes + R * vs * (n + n_t + 2 * n),
     }
 
 
@@ -77,6 +98,71 @@ def read_traffic(kernel, workload):
     return d.get("bytes_per_launch")
 
 
+SERVE_SET = [("sphere", 16384), ("cube", 16384), ("sphere", 32768), ("cube", 32768),
+             ("sphere", 65536), ("cube", 65536), ("sphere", 131072), ("cube", 131072)]
+
+
+def serve_bench(args, torch, hmgen, hm, DeviceHMatrix):
+    """Request loop under Poisson arrivals: 8 resident mixed-precision
+    matrices, requests of 1-64 right-hand sides, matrix chosen uniformly.
+    First a closed-loop burst measures the saturation rate; then an
+    open-loop Poisson stream at 0.8 x that rate gives p50 / p99 latency."""
+    mats, Ds = [], []
+    for geo, n in SERVE_SET:
+        name = "sphere4k_mixed" if geo == "sphere" else "cube4k"
+        H = hmgen.build_preset(name, n=n, dtype="mixed")
+        mats.append(H)
+        Ds.append(DeviceHMatrix(H, hm.HM_F32, max_nrhs=64))
+        log(f"serve: built {geo} n={n} in {H.build_seconds:.1f}s, store {Ds[-1].info['store_bytes'] / 1e9:.2f} GB")
+    arena_bytes = args.serve_arena_gb << 30
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    streams = [torch.cuda.Stream() for _ in range(args.serve_streams)]
+    rng = np.random.default_rng(hmgen.presets.SEED_REQUESTS)
+
+    def make(count):
+        reqs = []
+        for _ in range(count):
+            m = int(rng.integers(len(mats)))
+            r = int(rng.integers(1, 65))
+            X = np.asfortranarray(rng.standard_normal((mats[m].n, r)).astype(np.float32))
+            reqs.append((m, r, X, np.zeros((mats[m].n, r), np.float32, order="F")))
+        return reqs
+
+    def run(reqs, rate):
+        s = hm.hm_server_create([D.handle for D in Ds], arena, arena_bytes, streams)
+        tickets = []
+        t0 = time.perf_counter()
+        gaps = rng.exponential(1.0 / rate, len(reqs)) if rate else np.zeros(len(reqs))
+        t_next = t0
+        for (m, r, X, Y), g in zip(reqs, gaps):
+            t_next += g
+            while time.perf_counter() < t_next:
+                pass
+            tickets.append(hm.hm_submit(s, m, r, X, X.shape[0], Y, Y.shape[0]))
+        res = [hm.hm_wait(s, t, 600_000_000) for t in tickets]
+        wall = time.perf_counter() - t0
+        p50, p99, mps = hm.hm_server_stats(s)
+        hm.hm_server_destroy(s)
+        assert all(r == hm.HM_OK for r in res), res
+        rhs = sum(r for _, r, _, _ in reqs)
+        return {"p50_us": round(p50, 1), "p99_us": round(p99, 1), "matvecs_per_s": round(rhs / wall, 1),
+                "requests": len(reqs), "rhs": rhs, "wall_s": round(wall, 3)}
+
+    run(make(32), None)                                   # warm-up
+    sat = run(make(args.serve_requests), None)
+    req_rate = 0.8 * sat["matvecs_per_s"] / 32.5          # mean r of U{1..64} is 32.5
+    pois = run(make(args.serve_requests), req_rate)
+    pois["arrival_rate_per_s"] = round(req_rate, 2)
+    pois["saturation_matvecs_per_s"] = sat["matvecs_per_s"]
+    pois["load"] = 0.8
+    pois["matrices"] = [f"{g}-n{n}" for g, n in SERVE_SET]
+    pois["arena_gb"] = args.serve_arena_gb
+    pois["streams"] = args.serve_streams
+    for D in Ds:
+        D.close()
+    return pois
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +171,15 @@ def main():
     ap.add_argument("--workload", default="sphere256k")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nrhs", type=int, default=1,
+                    help="right-hand sides per product (> 1: hm_mvm_batch; reported separately)")
+    ap.add_argument("--n", type=int, default=0, help="override the workload size (not the default line)")
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in launch parameters")
+    ap.add_argument("--no-stream-probe", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-arena-gb", type=int, default=16)
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -114,7 +209,7 @@ def main():
         return
     p = hmgen.preset(args.workload)
     log("building", args.workload, p)
-    H = hmgen.build_preset(args.workload)
+    H = hmgen.build_preset(args.workload, n=args.n or None)
     st = H.stats()
     log("built in %.1fs: %s" % (H.build_seconds, st))
     mixed = p["dtype"] != "f64"
@@ -122,32 +217,53 @@ def main():
     vs = 4 if mixed else 8
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        D = DeviceHMatrix(H, acc, stream=stream)
+        D = DeviceHMatrix(H, acc, stream=stream, max_nrhs=args.nrhs)
     info = D.info
     log("uploaded: store %.3f GB, alg %.3f GB" % (info["store_bytes"] / 1e9, info["alg_bytes"] / 1e9))
-    x = D.vector(hmgen.uniform_vector(H.n, seed=hmgen.presets.SEED_X))
-    y = D.vector()
+    R = args.nrhs
+    if R == 1:
+        x = D.vector(hmgen.uniform_vector(H.n, seed=hmgen.presets.SEED_X))
+        y = D.vector()
+        step = lambda: D.mvm(x, y, 1.0, stream=stream)
+    else:
+        Xh = hmgen.gaussian_block(H.n, R, seed=hmgen.presets.SEED_RHS)
+        X = torch.from_numpy(np.ascontiguousarray(Xh.T)).to(D.vec_torch).cuda()
+        Y = torch.zeros_like(X)
+        x = X[0]
+        step = lambda: hm.hm_mvm_batch(D.handle, R, 1.0, X, H.n, Y, H.n, D.work, D.work.numel(),
+                                       stream)
     torch.cuda.synchronize()
 
+    tuned = None
+    if R == 1 and not args.no_tune:
+        from paper_2308_10960_amd import tune
+        best, times = tune.tune(D, step)
+        tuned = {"chosen": best, "avg_ms": {k: round(v, 5) for k, v in times.items()}}
+        log("tuned launch parameters:", tuned)
+
     for _ in range(args.warmup):
-        D.mvm(x, y, 1.0, stream=stream)
+        step()
     torch.cuda.synchronize()
     hm.hm_profile_begin(D.handle, args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        D.mvm(x, y, 1.0, stream=stream)
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_k, calls = hm.hm_profile_end(D.handle)
     assert calls == args.steps
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    alg = info["alg_bytes"]
+    # factors once per product, vectors once per right-hand side
+    alg = info["alg_bytes"] + (R - 1) * vs * (H.n + 2 * H.n)
     value = alg / (ms_per_step * 1e-3) / 1e9
+    log("%d right-hand sides: %.1f matvecs/s" % (R, R / (ms_per_step * 1e-3)))
     log("%.4f ms/step, %.1f GB/s effective (%.1f%% of 8 TB/s)" % (ms_per_step, value, value / 80.0))
 
-    kb = kernel_bytes(H, info, vs)
-    avg_ms = {k: ms_k[i] / calls for i, k in enumerate(KERNELS)}
+    schedule = int(hm.hm_matrix_get_launch(D.handle).split()[0].split("=")[1])
+    kb = kernel_bytes(H, info, vs, R, schedule)
+    names = KERNELS[schedule] if R == 1 else KERNELS_BATCH
+    avg_ms = {k: ms_k[i] / calls for i, k in enumerate(names)}
     dom = max(avg_ms, key=avg_ms.get)
     achieved = kb[dom] / (avg_ms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
@@ -156,24 +272,46 @@ def main():
                 "alg_bytes_per_launch": kb[dom], "avg_ms": round(avg_ms[dom], 5)}
     kernels = {k: {"avg_ms": round(avg_ms[k], 5), "alg_bytes": kb[k],
                    "gbs": round(kb[k] / (avg_ms[k] * 1e-3) / 1e9, 1) if avg_ms[k] > 0 else None}
-               for k in KERNELS}
+               for k in names}
     log("kernels", kernels)
+
+    stream_gbs = None
+    if not args.no_stream_probe:
+        nbytes = 4 << 30
+        buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        scratch = torch.zeros(4, dtype=torch.int32, device="cuda")
+        for _ in range(3):
+            hm.hm_stream_read(buf, nbytes, scratch, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            hm.hm_stream_read(buf, nbytes, scratch, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        stream_gbs = nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del buf
+        log("stream-read probe: %.1f GB/s" % stream_gbs)
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        xh = x.cpu().numpy().astype(np.float64)
+        xh = x.cpu().numpy().astype(np.float64)   # one right-hand side
         runs, t_cpu = 0, 0.0
         while runs == 0 or t_cpu < args.cpu_seconds:
             a = time.perf_counter()
             oracle.hmvm(H, xh)
             t_cpu += time.perf_counter() - a
             runs += 1
-        cpu = {"value": round(alg / (t_cpu / runs) / 1e9, 3), "unit": "GB/s", "cores": 1,
+        cpu = {"value": round(info["alg_bytes"] / (t_cpu / runs) / 1e9, 3), "unit": "GB/s", "cores": 1,
                "kind": "oracle", "seconds_per_matvec": round(t_cpu / runs, 4),
                "sample": f"{runs} full single-RHS products of the same n={H.n} matrix, "
                          "single-threaded FP64 oracle"}
         log("cpu baseline", cpu)
+
+    serving = None
+    if not args.no_serve:
+        serving = serve_bench(args, torch, hmgen, hm, DeviceHMatrix)
+        log("serving", serving)
 
     out = {
         "metric": "H-MVM effective GB/s & % HBM peak at n=2^18 eps=1e-6; p50/p99 req latency",
@@ -182,15 +320,21 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": f"{p['geometry']}-{p['kernel']} n={H.n} eps={p['eps']} "
-                               f"{p['dtype']} 1rhs leaf64 eta2",
-                   "n": H.n, "eps": p["eps"], "storage": p["dtype"], "nrhs": 1,
+                               f"{p['dtype']} {R}rhs leaf64 eta2",
+                   "n": H.n, "eps": p["eps"], "storage": p["dtype"], "nrhs": R,
+                   "matvecs_per_s": round(R / (ms_per_step * 1e-3), 1),
                    "blocks": st["blocks"], "dense_blocks": st["dense_blocks"],
                    "lowrank_blocks": st["lowrank_blocks"], "mean_rank": round(st["mean_rank"], 2),
                    "alg_bytes": alg, "store_bytes": info["store_bytes"]},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "stream_read_gbs": round(stream_gbs, 1) if stream_gbs else None,
+        "pct_of_stream_read": round(100 * value / stream_gbs, 2) if stream_gbs else None,
+        "launch": hm.hm_matrix_get_launch(D.handle),
+        "tuning": tuned,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     D.close()

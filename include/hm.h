@@ -75,9 +75,10 @@ typedef struct {
  * Storage dtypes allowed: any with HM_F64 accumulation; F32/F16/BF16 with
  * HM_F32 accumulation.
  * max_nrhs: largest nrhs passed to hm_mvm_batch (>= 1); sizes the workspace.
- * tune: 0 = built-in launch parameters; 1 = read tune_cache (a text file of
- * autotuned launch parameters written by the tuner), falling back to the
- * built-ins for missing keys.  tune_cache may be NULL when tune = 0. */
+ * tune: 0 = built-in launch parameters; 1 = read tune_cache, a text file
+ * written by the tuner with one "key params" line per kind of matrix (see
+ * hm_matrix_tune_key and hm_matrix_set_launch); a key that is missing
+ * falls back to the built-ins.  tune_cache may be NULL when tune = 0. */
 typedef struct {
   int32_t acc_dtype, vec_dtype, max_nrhs, tune;
   const char* tune_cache;
@@ -85,7 +86,7 @@ typedef struct {
 
 /* Sizes and byte accounting of a plan (all counts exact).
  * store_bytes: device bytes hm_upload needs (factors + descriptors).
- * work_bytes_per_rhs: workspace bytes hm_mvm needs (x nrhs for hm_mvm_batch).
+ * work_bytes_per_rhs: workspace bytes hm_mvm needs (hm_mvm_batch: see there).
  * alg_bytes: algorithmic bytes of one single-RHS product: stored factor
  *   elements at their storage width, s_b values, x read once, y read and
  *   written once.  alg_flops: 2 (sum_dense m n + sum_lowrank (m + n) k).
@@ -150,9 +151,15 @@ hm_status hm_mvm(const hm_matrix* A, double alpha, const void* d_x, void* d_y, v
 
 /* Y := Y + alpha A X for nrhs right-hand sides (1 <= nrhs <= max_nrhs).
  * X is n_cols x nrhs, Y is n_rows x nrhs, column-major with leading
- * dimensions ldx >= n_cols, ldy >= n_rows; workspace >= nrhs *
- * work_bytes_per_rhs.  Each column equals what hm_mvm gives for it up to
- * the rounding of the accumulation order. */
+ * dimensions ldx >= n_cols, ldy >= n_rows; X must not overlap Y.
+ * Workspace: at least slots * work_bytes_per_rhs bytes, where slots = 32 for
+ * nrhs <= 32 and 64 otherwise with HM_F32 accumulation (right-hand sides run
+ * in groups of up to 64 on the matrix cores), and slots = 1 with HM_F64
+ * accumulation (right-hand sides run one after another).
+ * HM_F32: every result column depends only on its own right-hand side, so a
+ * column's result is bitwise the same whatever else is in the batch; it
+ * agrees with hm_mvm up to the rounding of the accumulation order.
+ * HM_F64: each column is computed exactly as hm_mvm computes it. */
 hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const void* d_X,
                        int64_t ldx, void* d_Y, int64_t ldy, void* d_work, size_t work_bytes,
                        void* stream);
@@ -167,6 +174,27 @@ hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const voi
  * by the library. */
 hm_status hm_profile_begin(hm_matrix* A, int32_t max_calls);
 hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls);
+
+/* Launch parameters of one matrix, as text "schedule=S unroll=U":
+ *   schedule 0: column tiles, partial reduction, whole row panels;
+ *   schedule 1: one grouped launch of the dense row-panel sections with the
+ *               column tiles, the reduction, then the U sections;
+ *   unroll 4 or 8: 16-byte groups each wave keeps in flight in row panels.
+ * The unroll depth does not change any sum's order (results are identical
+ * bit for bit); schedule 1 adds the near-field and far-field parts to y in
+ * two steps, so it differs from schedule 0 by rounding only.  Each choice is
+ * deterministic.  hm_matrix_tune_key writes the key under which the
+ * tuner stores the best choice for matrices of this kind (accumulation type,
+ * storage formats present, size class) into buf (NUL-terminated, <= len). */
+hm_status hm_matrix_set_launch(hm_matrix* A, const char* params);
+hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len);
+hm_status hm_matrix_tune_key(const hm_matrix* A, char* buf, size_t len);
+
+/* Streaming-read probe for measurement: reads `bytes` (a multiple of 16) of
+ * device memory at d_buf with the 16-byte loads the kernels use, on stream.
+ * d_out: device memory of >= 4 bytes (written only in a case that does not
+ * occur for real data; it keeps the reads from being removed). */
+hm_status hm_stream_read(const void* d_buf, size_t bytes, void* d_out, void* stream);
 
 /* Request loop with continuous batching over device-resident matrices.
  * mats: matrices to serve (borrowed).  d_arena: device memory (arena_bytes)

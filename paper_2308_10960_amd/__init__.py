@@ -6,6 +6,6 @@ torch-allocated device memory.
 """
 
 from . import hm
-from .matrix import DeviceHMatrix, blocks_from_table
+from .matrix import DeviceHMatrix, blocks_from_table, batch_slots
 
-__all__ = ["hm", "DeviceHMatrix", "blocks_from_table"]
+__all__ = ["hm", "DeviceHMatrix", "blocks_from_table", "batch_slots"]

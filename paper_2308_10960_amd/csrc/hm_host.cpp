@@ -150,6 +150,17 @@ static void split_intervals(const std::vector<int64_t>& bp, int cap, std::vector
   out.push_back(bp.back());
 }
 
+// Byte offset of element (row i, section column sc) of a column section.
+// The section is stored tile by tile (tiles of 64 groups of G columns, the
+// last one narrower); inside a tile, row i holds the tile's groups
+// contiguously, so one wave streams one contiguous block.
+static int64_t col_elem_offset(const ColSectionHost& S, int32_t nrows, int64_t i, int64_t sc) {
+  const int G = group_width(S.dtype), sz = dtype_size(S.dtype);
+  const int64_t ngr = S.ld / G, gg = sc / G, t = gg / kTileGroups, gl = gg % kTileGroups;
+  const int64_t ngt = std::min<int64_t>(kTileGroups, ngr - t * kTileGroups);
+  return S.data_off + t * kTileGroups * 16 * (int64_t)nrows + (i * ngt + gl) * 16 + (sc % G) * sz;
+}
+
 hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks, int64_t nb,
                      const hm_plan_opts* o, hm_plan** out) {
   if (!out) return fail(HM_EINVAL, "out is NULL");
@@ -279,32 +290,37 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
       const auto& b = P->blocks[i];
       if (b.kind == HM_DENSE) {
         segs.push_back(Seg{i, 0, (int32_t)(b.col_end - b.col_begin), (int32_t)b.col_begin,
-                           b.group_dtype[0], 0});
+                           b.group_dtype[0], 0, HM_DENSE});
       } else if (b.rank > 0) {
         int32_t c0 = 0;
         for (int g = 0; g < b.ngroups; ++g) {
           if (b.group_cols[g] > 0)
             segs.push_back(Seg{i, c0, b.group_cols[g],
-                               (int32_t)(n_cols + P->binfo[i].toff + c0), b.group_dtype[g], 0});
+                               (int32_t)(n_cols + P->binfo[i].toff + c0), b.group_dtype[g], 0,
+                               HM_LOWRANK});
           c0 += b.group_cols[g];
         }
       }
     }
-    // sections in dtype order; each starts at a multiple of 8 source slots
+    // sections: dense blocks first, then U factors, each by dtype; every
+    // section starts at a multiple of 8 source slots
     int32_t slot = 0;
-    for (int dt = 0; dt < 4; ++dt) {
-      int32_t cols = 0;
-      for (auto& s : segs)
-        if (s.dtype == dt) { s.seccol = cols; cols += s.ncols; }
-      if (cols == 0) continue;
-      const int G = group_width(dt);
-      RowSectionHost S;
-      S.dtype = dt;
-      S.ngroups = (cols + G - 1) / G;
-      S.col0 = slot;
-      slot += align_up(S.ngroups * G, 8);
-      R.secs.push_back(S);
-    }
+    for (int kind = 0; kind < 2; ++kind)
+      for (int dt = 0; dt < 4; ++dt) {
+        int32_t cols = 0;
+        for (auto& s : segs)
+          if (s.kind == kind && s.dtype == dt) { s.seccol = cols; cols += s.ncols; }
+        if (cols == 0) continue;
+        const int G = group_width(dt);
+        RowSectionHost S;
+        S.kind = kind;
+        S.dtype = dt;
+        S.ngroups = (cols + G - 1) / G;
+        S.col0 = slot;
+        slot += align_up(S.ngroups * G, 8);
+        R.secs.push_back(S);
+        if (kind == 0) R.nsec_dense++;
+      }
     R.ncols = slot;
     R.segs = std::move(segs);
   }
@@ -341,7 +357,8 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
       for (int g = 0; g < b.ngroups; ++g) {
         if (b.group_cols[g] > 0)
           Cp.segs.push_back(Seg{i, c0, b.group_cols[g],
-                                (int32_t)(bi.pst + (int64_t)seg * b.rank + c0), b.group_dtype[g], 0});
+                                (int32_t)(bi.pst + (int64_t)seg * b.rank + c0), b.group_dtype[g], 0,
+                                HM_LOWRANK});
         c0 += b.group_cols[g];
       }
     }
@@ -358,7 +375,64 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
     }
   }
 
-  return layout_store(P.release(), out);
+  hm_status st = layout_store(P.release(), out);
+  if (st == HM_OK && (*out)->opts.tune && !(*out)->tune_path.empty()) read_tune_cache(*out);
+  return st;
+}
+
+// ------------------------------------------------------------------ tuning
+
+static bool parse_launch(const char* text, LaunchParams& lp) {
+  if (!text) return false;
+  LaunchParams r = lp;
+  std::string t(text);
+  size_t i = 0;
+  while (i < t.size()) {
+    while (i < t.size() && (t[i] == ' ' || t[i] == '\t')) ++i;
+    size_t j = i;
+    while (j < t.size() && t[j] != ' ' && t[j] != '\t' && t[j] != '\n') ++j;
+    if (j == i) break;
+    const std::string kv = t.substr(i, j - i);
+    const size_t eq = kv.find('=');
+    if (eq == std::string::npos) return false;
+    const std::string k = kv.substr(0, eq);
+    char* end = nullptr;
+    const long v = std::strtol(kv.c_str() + eq + 1, &end, 10);
+    if (!end || *end) return false;
+    if (k == "schedule" && (v == 0 || v == 1)) r.schedule = (int)v;
+    else if (k == "unroll" && (v == 4 || v == 8)) r.row_unroll = (int)v;
+    else return false;
+    i = j;
+  }
+  lp = r;
+  return true;
+}
+
+static std::string tune_key(int acc, const size_t* bytes_by_dtype, int64_t n_rows) {
+  int mask = 0;
+  for (int d = 0; d < 4; ++d) if (bytes_by_dtype[d]) mask |= 1 << d;
+  int lg = 0;
+  while ((int64_t(1) << (lg + 1)) <= n_rows) ++lg;
+  char buf[64];
+  std::snprintf(buf, sizeof buf, "acc%d-fmt%d-n2^%d", acc, mask, lg);
+  return buf;
+}
+
+void read_tune_cache(hm_plan* P) {
+  FILE* f = std::fopen(P->tune_path.c_str(), "r");
+  if (!f) return;
+  const std::string key = tune_key(P->opts.acc_dtype, P->bytes_by_dtype, P->n_rows);
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    std::string l(line);
+    const size_t sp = l.find(' ');
+    if (sp == std::string::npos || l[0] == '#') continue;
+    if (l.substr(0, sp) == key) {
+      LaunchParams lp = P->launch;
+      if (parse_launch(l.c_str() + sp + 1, lp)) P->launch = lp;
+    }
+  }
+  std::fclose(f);
 }
 
 hm_status layout_store(hm_plan* Pp, hm_plan** out) {
@@ -399,8 +473,19 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   H.off_col_dst = take(ndst * 4);
   H.off_tblocks = take(H.n_tblocks * (int64_t)sizeof(TBlock));
   H.off_large = take(H.n_large * 4);
-  H.off_owner = take((H.n_t - H.n_large_t) * 4);
+  H.off_owner = take(H.n_t * 4);
   H.off_sigma = take(P->has_sigma ? H.n_t * acc_sz : 0);
+  {
+    int64_t nd = 0, nu = 0;
+    for (auto& R : P->rps) {
+      nd += R.nsec_dense > 0;
+      nu += (int32_t)R.secs.size() > R.nsec_dense;
+    }
+    H.n_p1 = nd + (ntiles + 3) / 4;
+    H.n_p2 = nu;
+  }
+  H.off_p1_order = take(H.n_p1 * 4);
+  H.off_p2_order = take(H.n_p2 * 4);
   const int64_t meta_end = off;
 
   // data: row sections, then column sections
@@ -415,7 +500,7 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
       S.data_off = take(bytes);
       int64_t real = 0;
       for (auto& s : R.segs)
-        if (s.dtype == S.dtype) real += s.ncols;
+        if (s.dtype == S.dtype && s.kind == S.kind) real += s.ncols;
       const int64_t real_bytes = real * R.m * dtype_size(S.dtype);
       factor_bytes += (double)real_bytes;
       pad_bytes += (double)(bytes - real_bytes);
@@ -438,10 +523,14 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   P->meta_bytes = (size_t)meta_end;
   P->factor_bytes = factor_bytes;
 
-  // work: partials then t, each aligned
+  // work per right-hand side: partials, t, and a slot for the transposed
+  // right-hand sides of the batched path, each 256-byte aligned
+  P->work_part_bytes = align_up(P->n_partials * acc_sz, kAlign);
+  P->work_t_bytes = align_up(P->n_t * acc_sz, kAlign);
+  P->work_x_bytes = align_up(P->n_cols * acc_sz, kAlign);
   P->work_part_off = 0;
-  P->work_t_off = align_up(P->n_partials * acc_sz, kAlign);
-  P->work_bytes_per_rhs = (size_t)align_up(P->work_t_off + P->n_t * acc_sz, kAlign);
+  P->work_t_off = P->work_part_bytes;
+  P->work_bytes_per_rhs = (size_t)(P->work_part_bytes + P->work_t_bytes + P->work_x_bytes);
 
   // accounting
   const int vec_sz = acc_sz;
@@ -461,7 +550,7 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   P->overhead_bytes = (double)(nsrc + ndst) * 4 + pad_bytes +
                       (double)H.n_row_panels * (sizeof(RowPanel) + 4) + nsec * sizeof(RowSection) +
                       ntiles * sizeof(ColTile) + H.n_tblocks * sizeof(TBlock) +
-                      (double)(H.n_t - H.n_large_t) * 4 + 2.0 * P->n_partials * acc_sz +
+                      (double)H.n_t * 4 + 2.0 * P->n_partials * acc_sz +
                       2.0 * P->n_t * acc_sz;
   *out = P.release();
   return ok();
@@ -501,7 +590,7 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
     d.ncols = R.ncols;
     d.sec0 = sec;
     d.nsec = (int32_t)R.secs.size();
-    d.pad_ = 0;
+    d.nsec_dense = R.nsec_dense;
     for (auto& S : R.secs) {
       RowSection& e = rs[sec++];
       e.data_off = S.data_off;
@@ -514,7 +603,7 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
     for (int32_t c = 0; c < R.ncols; ++c) src[c] = 0;   // padding slots read x[0] (times 0)
     for (auto& sg : R.segs) {
       const RowSectionHost* S = nullptr;
-      for (auto& x : R.secs) if (x.dtype == sg.dtype) S = &x;
+      for (auto& x : R.secs) if (x.dtype == sg.dtype && x.kind == sg.kind) S = &x;
       for (int32_t c = 0; c < sg.ncols; ++c) src[S->col0 + sg.seccol + c] = sg.src0 + c;
     }
   }
@@ -529,6 +618,32 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
     };
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return bytes(x) > bytes(y); });
     std::copy(ord.begin(), ord.end(), ro);
+    // phase orders: bytes of the dense part and of the U part of each panel
+    auto part_bytes = [&](int32_t p, int kind) {
+      int64_t s = 0;
+      for (auto& S : P->rps[p].secs)
+        if (S.kind == kind) s += (int64_t)S.ngroups * P->rps[p].m * 16;
+      return s;
+    };
+    std::vector<int32_t> dense, upart;
+    for (int32_t p = 0; p < (int32_t)P->rps.size(); ++p) {
+      if (P->rps[p].nsec_dense > 0) dense.push_back(p);
+      if ((int32_t)P->rps[p].secs.size() > P->rps[p].nsec_dense) upart.push_back(p);
+    }
+    std::stable_sort(dense.begin(), dense.end(),
+                     [&](int32_t x, int32_t y) { return part_bytes(x, 0) > part_bytes(y, 0); });
+    std::stable_sort(upart.begin(), upart.end(),
+                     [&](int32_t x, int32_t y) { return part_bytes(x, 1) > part_bytes(y, 1); });
+    // interleave dense panels (largest first) with tile groups evenly
+    auto* p1 = reinterpret_cast<int32_t*>(buf + H.off_p1_order);
+    const int64_t A = (int64_t)dense.size(), B = H.n_p1 - A;
+    int64_t ia = 0, ib = 0;
+    for (int64_t k = 0; k < H.n_p1; ++k) {
+      const bool take_panel = ib >= B || (ia < A && ia * B <= ib * A);
+      p1[k] = take_panel ? dense[ia++] : (int32_t)(-(ib++) - 1);
+    }
+    auto* p2 = reinterpret_cast<int32_t*>(buf + H.off_p2_order);
+    std::copy(upart.begin(), upart.end(), p2);
   }
   // column tiles and destinations
   auto* ct = reinterpret_cast<ColTile*>(buf + H.off_col_tiles);
@@ -545,8 +660,9 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
           for (int32_t c = 0; c < sg.ncols; ++c) dst[sg.seccol + c] = sg.src0 + c;
       for (int g0 = 0; g0 < ngr; g0 += kTileGroups) {
         ColTile& T = ct[tile++];
-        T.data_off = S.data_off + (int64_t)g0 * G * dtype_size(S.dtype);
-        T.ld = S.ld;
+        const int ngt = std::min(kTileGroups, ngr - g0);
+        T.data_off = S.data_off + (int64_t)g0 * 16 * Cp.nrows;   // tiles stored one after another
+        T.ld = ngt * G;                                        // elements per tile row
         T.nrows = Cp.nrows;
         T.x0 = (int32_t)Cp.x0;
         T.dtype = S.dtype;
@@ -568,8 +684,7 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
     T.nseg = bi.nseg;
     T.toff = (int32_t)bi.toff;
     if ((int64_t)q < H.n_large) lg[q] = (int32_t)q;
-    else
-      for (int32_t l = 0; l < T.k; ++l) own[bi.toff - H.n_large_t + l] = (int32_t)q;
+    for (int32_t l = 0; l < T.k; ++l) own[bi.toff + l] = (int32_t)q;
     if (P->has_sigma) {
       const auto& b = P->blocks[i];
       for (int32_t l = 0; l < T.k; ++l) {
@@ -590,7 +705,7 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
         const RowPanelHost& R = P->rps[job];
         for (auto& sg : R.segs) {
           const RowSectionHost* S = nullptr;
-          for (auto& x : R.secs) if (x.dtype == sg.dtype) S = &x;
+          for (auto& x : R.secs) if (x.dtype == sg.dtype && x.kind == sg.kind) S = &x;
           const int G = group_width(S->dtype), sz = dtype_size(S->dtype);
           const auto& b = P->blocks[sg.block];
           const int64_t mb = b.row_end - b.row_begin;
@@ -615,11 +730,10 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
           const int64_t nbk = b.col_end - b.col_begin;
           const int64_t c_local = Cp.x0 - b.col_begin;
           const double* V = bf[sg.block];
-          uint8_t* base = buf + S->data_off;
           for (int32_t c = 0; c < sg.ncols; ++c) {
             const double* col = V + (int64_t)(sg.c_first + c) * nbk + c_local;
             for (int32_t i = 0; i < Cp.nrows; ++i)
-              put(base + ((int64_t)i * S->ld + sg.seccol + c) * sz, S->dtype, col[i]);
+              put(buf + col_elem_offset(*S, Cp.nrows, i, sg.seccol + c), S->dtype, col[i]);
           }
         }
       }
@@ -686,7 +800,7 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
     for (auto& sg : R.segs)
       if (sg.block == block && j >= sg.c_first && j < sg.c_first + sg.ncols) {
         for (auto& S : R.secs)
-          if (S.dtype == sg.dtype) {
+          if (S.dtype == sg.dtype && S.kind == sg.kind) {
             const int G = group_width(S.dtype);
             const int64_t sc = sg.seccol + (j - sg.c_first);
             *byte_offset = (size_t)(S.data_off + (((sc / G) * R.m + (row - R.row0)) * G + sc % G) *
@@ -707,8 +821,7 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
       if (sg.block == block && j >= sg.c_first && j < sg.c_first + sg.ncols) {
         for (auto& S : Cp.secs)
           if (S.dtype == sg.dtype) {
-            *byte_offset = (size_t)(S.data_off + ((col - Cp.x0) * S.ld + sg.seccol + (j - sg.c_first)) *
-                                                     dtype_size(S.dtype));
+            *byte_offset = (size_t)col_elem_offset(S, Cp.nrows, col - Cp.x0, sg.seccol + (j - sg.c_first));
             *dtype = S.dtype;
             return ok();
           }
@@ -747,9 +860,13 @@ hm_status hm_upload(const hm_plan* p, const double* const* a, const double* cons
   M->store_bytes = p->store_bytes;
   M->work_bytes_per_rhs = p->work_bytes_per_rhs;
   M->work_t_off = p->work_t_off;
+  M->work_part_bytes = p->work_part_bytes;
+  M->work_t_bytes = p->work_t_bytes;
+  M->work_x_bytes = p->work_x_bytes;
   M->acc_dtype = p->opts.acc_dtype;
   M->max_nrhs = p->opts.max_nrhs;
   M->launch = p->launch;
+  std::memcpy(M->bytes_by_dtype, p->bytes_by_dtype, sizeof M->bytes_by_dtype);
   *out = M;
   return ok();
 }
@@ -825,7 +942,7 @@ hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const voi
   if (!A || !d_X || !d_Y) return fail(HM_EINVAL, "NULL argument");
   if (nrhs < 1 || nrhs > A->max_nrhs) return fail(HM_EINVAL, "nrhs %d outside [1, %d]", nrhs, A->max_nrhs);
   if (ldx < A->hdr.n_cols || ldy < A->hdr.n_rows) return fail(HM_EINVAL, "leading dimension too small");
-  const size_t need = (size_t)nrhs * A->work_bytes_per_rhs;
+  const size_t need = (size_t)batch_slots(A->acc_dtype, nrhs) * A->work_bytes_per_rhs;
   if (work_bytes < need || (need > 0 && !d_work))
     return fail(HM_ENOMEM, "workspace has %zu bytes, needs %zu", work_bytes, need);
   if (d_work && ((uintptr_t)d_work) % kAlign) return fail(HM_EINVAL, "workspace must be 256-byte aligned");
@@ -835,6 +952,34 @@ hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const voi
   if (X < Y + (size_t)ldy * vs * nrhs && Y < X + (size_t)ldx * vs * nrhs)
     return fail(HM_EINVAL, "X must not overlap Y");
   hipError_t e = launch_mvm_batch(*A, nrhs, alpha, d_X, ldx, d_Y, ldy, d_work, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(HM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+hm_status hm_matrix_set_launch(hm_matrix* A, const char* params) {
+  if (!A || !params) return fail(HM_EINVAL, "NULL argument");
+  LaunchParams lp = A->launch;
+  if (!parse_launch(params, lp)) return fail(HM_EINVAL, "bad launch parameters '%s'", params);
+  A->launch = lp;
+  return ok();
+}
+
+hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len) {
+  if (!A || !buf || len == 0) return fail(HM_EINVAL, "NULL argument");
+  std::snprintf(buf, len, "schedule=%d unroll=%d", A->launch.schedule, A->launch.row_unroll);
+  return ok();
+}
+
+hm_status hm_matrix_tune_key(const hm_matrix* A, char* buf, size_t len) {
+  if (!A || !buf || len == 0) return fail(HM_EINVAL, "NULL argument");
+  std::snprintf(buf, len, "%s", tune_key(A->acc_dtype, A->bytes_by_dtype, A->hdr.n_rows).c_str());
+  return ok();
+}
+
+hm_status hm_stream_read(const void* d_buf, size_t bytes, void* d_out, void* stream) {
+  if (!d_buf || !d_out || bytes % 16) return fail(HM_EINVAL, "bad stream-read arguments");
+  if (((uintptr_t)d_buf) % 16) return fail(HM_EINVAL, "buffer must be 16-byte aligned");
+  hipError_t e = launch_stream_read(d_buf, bytes, d_out, (hipStream_t)stream);
   if (e != hipSuccess) return fail(HM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
   return ok();
 }

@@ -13,10 +13,13 @@
 namespace hm {
 
 // Launch parameters (chosen by the tuner or built-in defaults).
+//  schedule 0: column tiles, reduction, whole row panels;
+//  schedule 1: grouped launch of dense row-panel sections with the column
+//              tiles, reduction, then the U sections.
+//  row_unroll: 16-byte groups in flight per wave in the row-panel loop (4, 8).
 struct LaunchParams {
-  int row_cap = 2048;     // source slots staged in LDS per chunk (row kernel)
-  int row_unroll = 4;     // groups in flight per wave (row kernel)
-  int col_waves = 4;      // column tiles (waves) per workgroup
+  int schedule = 0;
+  int row_unroll = 4;
 };
 
 struct BlockInfo {
@@ -34,12 +37,13 @@ struct Seg {
                           // column panels: partial index of the first column
   int32_t dtype;
   int32_t seccol;         // column within its section
+  int32_t kind;           // HM_DENSE or HM_LOWRANK
 };
 
-struct RowSectionHost { int32_t dtype = 0, ngroups = 0, col0 = 0; int64_t data_off = 0; };
+struct RowSectionHost { int32_t kind = 0, dtype = 0, ngroups = 0, col0 = 0; int64_t data_off = 0; };
 struct RowPanelHost {
   int64_t row0 = 0;
-  int32_t m = 0, ncols = 0;
+  int32_t m = 0, ncols = 0, nsec_dense = 0;
   int64_t src_off = 0;
   std::vector<Seg> segs;
   std::vector<RowSectionHost> secs;
@@ -69,6 +73,7 @@ struct hm_plan {
   hm::StoreHeader hdr{};
   size_t store_bytes = 0, meta_bytes = 0, work_bytes_per_rhs = 0;
   int64_t work_part_off = 0, work_t_off = 0;
+  int64_t work_part_bytes = 0, work_t_bytes = 0, work_x_bytes = 0;
   double factor_bytes = 0, alg_bytes = 0, alg_flops = 0, overhead_bytes = 0;
   int64_t n_dense = 0, n_lowrank = 0;
   size_t bytes_by_dtype[4] = {0, 0, 0, 0};
@@ -90,14 +95,24 @@ struct hm_matrix {
   const uint8_t* d_store = nullptr;
   size_t store_bytes = 0, work_bytes_per_rhs = 0;
   int64_t work_t_off = 0;
+  int64_t work_part_bytes = 0, work_t_bytes = 0, work_x_bytes = 0;
   int32_t acc_dtype = 0, max_nrhs = 1;
   hm::LaunchParams launch;
+  size_t bytes_by_dtype[4] = {0, 0, 0, 0};
 };
 
 namespace hm {
+// Workspace slots (multiples of work_bytes_per_rhs) hm_mvm_batch needs: the
+// FP32 path runs right-hand sides in groups of 32 (one group of up to 64 at a
+// time); the FP64 path runs them one by one in a single slot.
+inline int batch_slots(int acc_dtype, int nrhs) {
+  if (acc_dtype == HM_F64) return 1;
+  return nrhs <= 32 ? 32 : 64;
+}
 hm_status fail(hm_status code, const char* fmt, ...);
 hm_status ok();
 hm_status layout_store(hm_plan* P, hm_plan** out);
+void read_tune_cache(hm_plan* P);
 uint16_t f64_to_f16(double d);
 uint16_t f64_to_bf16(double d);
 
@@ -106,4 +121,5 @@ hipError_t launch_mvm(const hm_matrix& A, double alpha, const void* x, void* y, 
                       hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const void* X, int64_t ldx,
                             void* Y, int64_t ldy, void* work, hipStream_t s);
+hipError_t launch_stream_read(const void* buf, size_t bytes, void* out, hipStream_t s);
 }  // namespace hm

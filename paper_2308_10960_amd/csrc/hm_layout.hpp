@@ -16,12 +16,19 @@
 //  * Column tiles.  The column breakpoints of the low-rank blocks cut
 //    [0, n_cols) into elementary column intervals kappa (<= 64 columns).
 //    For each, the rows of V_b / X_b restricted to kappa are concatenated
-//    over all low-rank blocks whose column cluster contains kappa, row-major
-//    (row i of the section holds ld contiguous values); a lane owns G
-//    adjacent columns and accumulates them over the interval's rows:
+//    over all low-rank blocks whose column cluster contains kappa.  The
+//    section is cut into tiles of 64 groups of G columns, stored one after
+//    another; inside a tile the rows follow each other, each holding the
+//    tile's groups contiguously, so a wave (lane = group) streams one
+//    contiguous block and accumulates its G columns over the rows:
 //    partial(b, kappa, l) = sum_{i in kappa} V_b[i, l] x[i].
 //  * Reduction.  t_b[l] = s_b[l] * sum over the column intervals of
 //    sigma_b of the partials, in ascending interval order.
+//  * Single-RHS schedule: phase 1 streams the dense sections of the row
+//    panels (y += alpha D x) together with the column tiles in one grouped
+//    launch; after the reduction, phase 2 streams the U sections
+//    (y += alpha U t).  Each row of y is written by one workgroup per phase,
+//    in phase order.
 //
 // All offsets are in bytes from the start of the store unless noted.
 
@@ -45,7 +52,8 @@ struct RowPanel {        // 32 bytes
   int32_t row0, m;       // rows [row0, row0 + m), m <= 64
   int32_t ncols;         // source slots over all sections (each section starts at a multiple of 8)
   int32_t sec0, nsec;    // sections [sec0, sec0 + nsec) in the section table
-  int32_t pad_;
+  int32_t nsec_dense;    // the first nsec_dense sections hold dense blocks (source x),
+                         // the rest U factors (source t); dense slots come first
 };
 
 struct RowSection {      // 32 bytes
@@ -57,8 +65,8 @@ struct RowSection {      // 32 bytes
 };
 
 struct ColTile {         // 32 bytes: one wave streams nrows rows x ngroups*G columns
-  int64_t data_off;      // byte offset of (row 0, first column of the tile)
-  int32_t ld;            // row stride of the section, in elements
+  int64_t data_off;      // byte offset of the tile (row 0, first column)
+  int32_t ld;            // row stride inside the tile, in elements (= ngroups*G)
   int32_t nrows;         // rows of the column interval (<= 64)
   int32_t x0;            // first x index of the interval
   int32_t dtype;
@@ -83,8 +91,12 @@ struct StoreHeader {
   int64_t off_col_tiles, off_col_dst;
   int64_t off_tblocks, off_large, off_owner, off_sigma;
   int64_t acc_dtype, has_sigma;
+  // single-RHS work orders: phase 1 mixes the dense parts of row panels
+  // (entry >= 0: panel index) with groups of 4 column tiles (entry < 0:
+  // group -entry-1); phase 2 lists the row panels with U sections
+  int64_t off_p1_order, n_p1, off_p2_order, n_p2;
 };
 
-constexpr uint64_t kStoreMagic = 0x484d53544f524531ull;  // "HMSTORE1"
+constexpr uint64_t kStoreMagic = 0x484d53544f524532ull;  // "HMSTORE2"
 
 }  // namespace hm

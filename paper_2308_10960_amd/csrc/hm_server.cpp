@@ -136,7 +136,7 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 size_t footprint(const hm_matrix* A, int32_t r) {
   const size_t vs = A->acc_dtype == HM_F64 ? 8 : 4;
   return align256((size_t)A->hdr.n_cols * r * vs) + align256((size_t)A->hdr.n_rows * r * vs) +
-         (size_t)r * A->work_bytes_per_rhs + 256;
+         (size_t)hm::batch_slots(A->acc_dtype, r) * A->work_bytes_per_rhs + 256;
 }
 
 void finish(hm_server* S, const std::shared_ptr<Request>& q, hm_status st, Clock::time_point now) {
@@ -175,7 +175,7 @@ hm_status launch_batch(hm_server* S, Slot& sl) {
   uint8_t* dX = base;
   uint8_t* dY = base + align256(xbytes);
   uint8_t* dW = dY + align256(ybytes);
-  const size_t wbytes = (size_t)sl.nrhs * A->work_bytes_per_rhs;
+  const size_t wbytes = (size_t)hm::batch_slots(A->acc_dtype, sl.nrhs) * A->work_bytes_per_rhs;
   if (hipMemcpyAsync(dX, px, xbytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
       hipMemsetAsync(dY, 0, ybytes, sl.stream) != hipSuccess)
     return HM_EDEVICE;

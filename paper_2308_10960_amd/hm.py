@@ -72,6 +72,10 @@ PROTOTYPES = {
     "hm_mvm_batch": (_i32, [_vp, _i32, _dbl, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
     "hm_profile_begin": (_i32, [_vp, _i32]),
     "hm_profile_end": (_i32, [_vp, _P(_dbl), _P(_i64)]),
+    "hm_matrix_set_launch": (_i32, [_vp, C.c_char_p]),
+    "hm_matrix_get_launch": (_i32, [_vp, C.c_char_p, _sz]),
+    "hm_matrix_tune_key": (_i32, [_vp, C.c_char_p, _sz]),
+    "hm_stream_read": (_i32, [_vp, _sz, _vp, _vp]),
     "hm_server_create": (_i32, [_P(_vp), _i32, _vp, _sz, _P(_vp), _i32, _P(_vp)]),
     "hm_submit": (_i32, [_vp, _i32, _i32, _vp, _i64, _vp, _i64, _P(C.c_uint64)]),
     "hm_poll": (_i32, [_vp, C.c_uint64, _P(_i32), _P(_i32)]),
@@ -212,6 +216,27 @@ def hm_profile_end(mat: int):
     calls = C.c_int64()
     _check(lib().hm_profile_end(mat, ms, C.byref(calls)), "hm_profile_end")
     return list(ms), calls.value
+
+
+def hm_matrix_set_launch(mat: int, params: str) -> None:
+    _check(lib().hm_matrix_set_launch(mat, params.encode()), "hm_matrix_set_launch")
+
+
+def hm_matrix_get_launch(mat: int) -> str:
+    buf = C.create_string_buffer(128)
+    _check(lib().hm_matrix_get_launch(mat, buf, 128), "hm_matrix_get_launch")
+    return buf.value.decode()
+
+
+def hm_matrix_tune_key(mat: int) -> str:
+    buf = C.create_string_buffer(128)
+    _check(lib().hm_matrix_tune_key(mat, buf, 128), "hm_matrix_tune_key")
+    return buf.value.decode()
+
+
+def hm_stream_read(d_buf, nbytes: int, d_out, stream=None) -> None:
+    _check(lib().hm_stream_read(_ptr(d_buf), nbytes, _ptr(d_out), _stream(stream)),
+           "hm_stream_read")
 
 
 def hm_server_create(mats, d_arena, arena_bytes: int, streams) -> int:

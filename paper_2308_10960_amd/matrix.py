@@ -13,6 +13,13 @@ import numpy as np
 from . import hm
 
 
+def batch_slots(acc_dtype: int, nrhs: int) -> int:
+    """Workspace slots (x work_bytes_per_rhs) hm_mvm_batch needs (see hm.h)."""
+    if acc_dtype == hm.HM_F64:
+        return 1
+    return 32 if nrhs <= 32 else 64
+
+
 def blocks_from_table(T) -> np.ndarray:
     adm = np.asarray(T.adm) != 0
     has_sigma = adm & bool(getattr(T, "keep_sigma", False))
@@ -39,7 +46,8 @@ class DeviceHMatrix:
         s_ptr = T.s_ptr if getattr(T, "keep_sigma", False) else None
         self.handle = hm.hm_upload(self.plan, T.a_ptr, T.b_ptr, s_ptr, self.store,
                                    self.info["store_bytes"], stream)
-        self.work_bytes = max(256, self.info["work_bytes_per_rhs"] * max_nrhs)
+        slots = batch_slots(acc_dtype, max_nrhs) if max_nrhs > 1 else 1
+        self.work_bytes = max(256, self.info["work_bytes_per_rhs"] * slots)
         self.work = torch.empty(self.work_bytes, dtype=torch.uint8, device=device)
         self.device = device
 

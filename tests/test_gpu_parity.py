@@ -200,3 +200,75 @@ def test_mixed_sphere4k():
 def test_mixed_full_size():
     say("building sphere256k_mixed")
     _mixed(hmgen.build_preset("sphere256k_mixed"), "sphere256k_mixed")
+
+
+def _batch(D, X, alpha=1.0, Y0=None):
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T.astype(np.float32))).cuda()
+    Yd = torch.zeros_like(Xd) if Y0 is None else torch.from_numpy(
+        np.ascontiguousarray(Y0.T.astype(np.float32))).cuda()
+    r = X.shape[1]
+    hm.hm_mvm_batch(D.handle, r, alpha, Xd, X.shape[0], Yd, X.shape[0], D.work, D.work.numel())
+    torch.cuda.synchronize()
+    return Yd.cpu().numpy().T.astype(np.float64)
+
+
+@pytest.mark.parametrize("name", ["sphere4k_mixed", "cube4k"])
+def test_batched_f32_mfma(name):
+    """FP32 batched product on the matrix cores: every column within the
+    rigorous FP32 bound of the decoded oracle; a column's result does not
+    depend on the other columns of the batch (bitwise); ragged batch sizes
+    across the 32- and 64-column groups."""
+    H = hmgen.build_preset(name)
+    D = DeviceHMatrix(H, hm.HM_F32, max_nrhs=70)
+    dec = oracle.decoded_factors(H, sigma_dtype=oracle.F32)
+    X = hmgen.gaussian_block(H.n, 70).astype(np.float32).astype(np.float64)
+    Y0 = hmgen.gaussian_block(H.n, 70, seed=7).astype(np.float32).astype(np.float64)
+    Y = _batch(D, X, -0.5, Y0)
+    ref = oracle.hmvm_multi(H, X, Y0, alpha=-0.5, factors=dec)
+    K = 4096 + 64
+    gam = K * U32 / (1 - K * U32)
+    worst = 0.0
+    for c in range(70):
+        scale = 0.5 * abs_bound(H, X[:, c], dec) + np.abs(Y0[:, c])
+        err = np.abs(Y[:, c] - ref[:, c])
+        worst = max(worst, float(np.max(err / scale)))
+        assert np.all(err <= gam * scale), c
+    say(f"{name} batch max err/scale {worst:.3e}")
+    # batch independence: the same right-hand side in other batches
+    for r, pick in [(1, [5]), (7, [5, 0, 69, 33, 2, 40, 11]), (33, list(range(33))), (64, list(range(64)))]:
+        Yb = _batch(D, X[:, pick], -0.5, Y0[:, pick])
+        for q, c in enumerate(pick):
+            np.testing.assert_array_equal(Yb[:, q], Y[:, c])
+    D.close()
+
+
+def test_launch_variants_and_tune_cache(sphere4k, tmp_path):
+    """Every schedule/unroll meets parity; unroll depth never changes a bit;
+    the tune cache written by the tuner is read back by hm_build_plan."""
+    from paper_2308_10960_amd import tune
+    H = sphere4k
+    D = DeviceHMatrix(H, hm.HM_F64)
+    x = hmgen.uniform_vector(H.n)
+    ref = oracle.hmvm(H, x)
+    scale = abs_bound(H, x)
+    out = {}
+    for c in tune.CANDIDATES:
+        hm.hm_matrix_set_launch(D.handle, c)
+        assert hm.hm_matrix_get_launch(D.handle) == c
+        out[c] = run(D, x)
+        check_f64(out[c], ref, scale)
+    np.testing.assert_array_equal(out["schedule=0 unroll=4"], out["schedule=0 unroll=8"])
+    np.testing.assert_array_equal(out["schedule=1 unroll=4"], out["schedule=1 unroll=8"])
+    with pytest.raises(hm.HMError):
+        hm.hm_matrix_set_launch(D.handle, "schedule=7")
+    xd, yd = D.vector(x), D.vector()
+    best, times = tune.tune(D, lambda: D.mvm(xd, yd), reps=3, warmup=1)
+    assert best in tune.CANDIDATES and set(times) == set(tune.CANDIDATES)
+    key = hm.hm_matrix_tune_key(D.handle)
+    path = str(tmp_path / "tune.txt")
+    tune.write_cache(path, key, "schedule=1 unroll=8")
+    tune.write_cache(path, "acc9-fmt0-n2^0", "schedule=0 unroll=4")
+    D2 = DeviceHMatrix(H, hm.HM_F64, tune_cache=path)
+    assert hm.hm_matrix_get_launch(D2.handle) == "schedule=1 unroll=8"
+    D2.close()
+    D.close()
