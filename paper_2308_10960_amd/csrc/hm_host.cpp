@@ -15,6 +15,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <memory>
 #include <new>
 #include <numeric>
@@ -230,26 +232,97 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
                   (long long)rbp[q], (long long)rbp[q + 1], (long long)c, (long long)n_cols);
   }
 
-  // ---- low-rank blocks: column intervals, t and partial offsets
-  std::vector<int64_t> cbp;
-  for (auto& b : P->blocks)
-    if (b.kind == HM_LOWRANK && b.rank > 0) { cbp.push_back(b.col_begin); cbp.push_back(b.col_end); }
-  std::sort(cbp.begin(), cbp.end());
-  cbp.erase(std::unique(cbp.begin(), cbp.end()), cbp.end());
-  std::vector<int32_t> cparent;
-  if (!cbp.empty()) split_intervals(cbp, kMaxTileRows, P->cint, cparent);
-  const int64_t nci = P->cint.empty() ? 0 : (int64_t)P->cint.size() - 1;
-
+  // ---- low-rank blocks: column chunks, t and partial offsets
+  // The rows of each V_b are cut into chunks: sigma_b itself when it has at
+  // most kSegRows rows, else the largest sub-ranges of sigma_b with at most
+  // kSegRows rows among the block ranges (for a block tree these are the
+  // clusters of the cluster tree), recursively.  A range that has no
+  // sub-ranges covering it, or a family of ranges that is not nested, falls
+  // back to near-equal pieces of at most 64 rows.  Equal ranges always get
+  // equal chunks, so every chunk is shared by all blocks over it.
+  std::vector<std::pair<int64_t, int64_t>> rng;
+  rng.reserve(2 * nb);
+  for (auto& b : P->blocks) {
+    rng.push_back({b.row_begin, b.row_end});
+    rng.push_back({b.col_begin, b.col_end});
+  }
+  std::sort(rng.begin(), rng.end(), [](const std::pair<int64_t, int64_t>& x,
+                                       const std::pair<int64_t, int64_t>& y) {
+    return x.first != y.first ? x.first < y.first : x.second > y.second;
+  });
+  rng.erase(std::unique(rng.begin(), rng.end()), rng.end());
+  std::vector<std::vector<int32_t>> kids(rng.size());
+  bool laminar = true;
+  {
+    std::vector<int32_t> stack;
+    for (int32_t r = 0; r < (int32_t)rng.size(); ++r) {
+      while (!stack.empty() && !(rng[stack.back()].second >= rng[r].second)) {
+        if (rng[stack.back()].second > rng[r].first) laminar = false;   // crossing ranges
+        stack.pop_back();
+      }
+      if (!stack.empty()) kids[stack.back()].push_back(r);
+      stack.push_back(r);
+    }
+  }
+  auto find_range = [&](int64_t b0, int64_t e0) -> int32_t {
+    auto it = std::lower_bound(rng.begin(), rng.end(), std::make_pair(b0, e0),
+                               [](const std::pair<int64_t, int64_t>& x, const std::pair<int64_t, int64_t>& y) {
+                                 return x.first != y.first ? x.first < y.first : x.second > y.second;
+                               });
+    return (it != rng.end() && *it == std::make_pair(b0, e0)) ? (int32_t)(it - rng.begin()) : -1;
+  };
+  std::map<std::pair<int64_t, int64_t>, int32_t> chunk_id;
+  std::vector<std::pair<int64_t, int64_t>> chunks;
+  auto add_chunk = [&](int64_t b0, int64_t e0) {
+    auto key = std::make_pair(b0, e0);
+    auto it = chunk_id.find(key);
+    if (it != chunk_id.end()) return it->second;
+    const int32_t id = (int32_t)chunks.size();
+    chunk_id.emplace(key, id);
+    chunks.push_back(key);
+    return id;
+  };
+  std::function<void(int64_t, int64_t, std::vector<int32_t>&)> chunk_range =
+      [&](int64_t b0, int64_t e0, std::vector<int32_t>& out) {
+        if (e0 - b0 <= kSegRows) { out.push_back(add_chunk(b0, e0)); return; }
+        const int32_t r = laminar ? find_range(b0, e0) : -1;
+        if (r >= 0 && !kids[r].empty()) {
+          int64_t covered = b0;
+          for (int32_t c : kids[r]) {
+            if (rng[c].first != covered) { covered = -1; break; }
+            covered = rng[c].second;
+          }
+          if (covered == e0) {
+            for (int32_t c : kids[r]) chunk_range(rng[c].first, rng[c].second, out);
+            return;
+          }
+        }
+        const int64_t pieces = (e0 - b0 + kMaxTileRows - 1) / kMaxTileRows;
+        for (int64_t q = 0; q < pieces; ++q)
+          out.push_back(add_chunk(b0 + (e0 - b0) * q / pieces, b0 + (e0 - b0) * (q + 1) / pieces));
+      };
   P->binfo.assign(nb, BlockInfo{});
+  P->chunk_off.assign(nb + 1, 0);
   std::vector<int32_t> lr_large, lr_small;
-  for (int64_t i = 0; i < nb; ++i) {
-    const auto& b = P->blocks[i];
-    BlockInfo& bi = P->binfo[i];
-    if (b.kind != HM_LOWRANK || b.rank == 0) continue;
-    bi.seg0 = (int32_t)(std::lower_bound(P->cint.begin(), P->cint.end(), b.col_begin) - P->cint.begin());
-    int32_t seg1 = (int32_t)(std::lower_bound(P->cint.begin(), P->cint.end(), b.col_end) - P->cint.begin());
-    bi.nseg = seg1 - bi.seg0;
-    (bi.nseg > kLargeSeg ? lr_large : lr_small).push_back((int32_t)i);
+  {
+    std::map<std::pair<int64_t, int64_t>, std::vector<int32_t>> memo;   // sigma -> chunk list
+    for (int64_t i = 0; i < nb; ++i) {
+      const auto& b = P->blocks[i];
+      P->chunk_off[i + 1] = P->chunk_off[i];
+      if (b.kind != HM_LOWRANK || b.rank == 0) continue;
+      auto key = std::make_pair(b.col_begin, b.col_end);
+      auto it = memo.find(key);
+      if (it == memo.end()) {
+        std::vector<int32_t> out;
+        chunk_range(b.col_begin, b.col_end, out);
+        it = memo.emplace(key, std::move(out)).first;
+      }
+      P->chunk_list.insert(P->chunk_list.end(), it->second.begin(), it->second.end());
+      P->chunk_off[i + 1] = (int64_t)P->chunk_list.size();
+      BlockInfo& bi = P->binfo[i];
+      bi.nseg = (int32_t)it->second.size();
+      (bi.nseg > kLargeSeg ? lr_large : lr_small).push_back((int32_t)i);
+    }
   }
   int64_t toff = 0, pst = 0;
   for (int pass = 0; pass < 2; ++pass)
@@ -325,34 +398,32 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
     R.segs = std::move(segs);
   }
 
-  // ---- column panels (one per column interval) and their tiles
-  std::vector<int64_t> ccnt(nci + 1, 0);
-  for (int32_t i : P->lr_order) {
-    const BlockInfo& bi = P->binfo[i];
-    for (int32_t s = bi.seg0; s < bi.seg0 + bi.nseg; ++s) ccnt[s + 1]++;
-  }
-  for (int64_t q = 0; q < nci; ++q) ccnt[q + 1] += ccnt[q];
-  std::vector<int32_t> ccover(nci ? ccnt[nci] : 0);
+  // ---- column panels (one per chunk) and their sections
+  const int64_t nck = (int64_t)chunks.size();
+  std::vector<int64_t> ccnt(nck + 1, 0);
+  for (int64_t i = 0; i < nb; ++i)
+    for (int64_t q = P->chunk_off[i]; q < P->chunk_off[i + 1]; ++q) ccnt[P->chunk_list[q] + 1]++;
+  for (int64_t q = 0; q < nck; ++q) ccnt[q + 1] += ccnt[q];
+  std::vector<int32_t> ccover(nck ? ccnt[nck] : 0), cseg(nck ? ccnt[nck] : 0);
   {
     std::vector<int64_t> fill(ccnt.begin(), ccnt.end() - 1);
-    // ascending block index keeps a stable, reproducible column order
-    std::vector<int32_t> lr_sorted(P->lr_order);
-    std::sort(lr_sorted.begin(), lr_sorted.end());
-    for (int32_t i : lr_sorted) {
-      const BlockInfo& bi = P->binfo[i];
-      for (int32_t s = bi.seg0; s < bi.seg0 + bi.nseg; ++s) ccover[fill[s]++] = i;
-    }
+    for (int64_t i = 0; i < nb; ++i)               // ascending block index: reproducible order
+      for (int64_t q = P->chunk_off[i]; q < P->chunk_off[i + 1]; ++q) {
+        const int32_t c = P->chunk_list[q];
+        ccover[fill[c]] = (int32_t)i;
+        cseg[fill[c]++] = (int32_t)(q - P->chunk_off[i]);
+      }
   }
-  P->cps.resize(nci);
-  for (int64_t q = 0; q < nci; ++q) {
+  P->cps.resize(nck);
+  for (int64_t q = 0; q < nck; ++q) {
     ColPanelHost& Cp = P->cps[q];
-    Cp.x0 = P->cint[q];
-    Cp.nrows = (int32_t)(P->cint[q + 1] - P->cint[q]);
+    Cp.x0 = chunks[q].first;
+    Cp.nrows = (int32_t)(chunks[q].second - chunks[q].first);
     for (int64_t c = ccnt[q]; c < ccnt[q + 1]; ++c) {
       const int32_t i = ccover[c];
       const auto& b = P->blocks[i];
       const BlockInfo& bi = P->binfo[i];
-      const int32_t seg = (int32_t)q - bi.seg0;
+      const int32_t seg = cseg[c];
       int32_t c0 = 0;
       for (int g = 0; g < b.ngroups; ++g) {
         if (b.group_cols[g] > 0)
@@ -481,7 +552,7 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
       nd += R.nsec_dense > 0;
       nu += (int32_t)R.secs.size() > R.nsec_dense;
     }
-    H.n_p1 = nd + (ntiles + 3) / 4;
+    H.n_p1 = nd + ntiles;
     H.n_p2 = nu;
   }
   H.off_p1_order = take(H.n_p1 * 4);
@@ -671,6 +742,10 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
       }
       dsto += S.ld;
     }
+  // tiles largest first (longest-processing-time order against the tail)
+  std::stable_sort(ct, ct + H.n_col_tiles, [](const ColTile& x, const ColTile& y) {
+    return (int64_t)x.nrows * x.ngroups > (int64_t)y.nrows * y.ngroups;
+  });
   // reduction tables
   auto* tb = reinterpret_cast<TBlock*>(buf + H.off_tblocks);
   auto* lg = reinterpret_cast<int32_t*>(buf + H.off_large);
@@ -815,8 +890,13 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
     if (b.kind != HM_LOWRANK || i < 0 || i >= n || j < 0 || j >= b.rank)
       return fail(HM_EINVAL, "entry out of range");
     const int64_t col = b.col_begin + i;
-    const int64_t ci = std::upper_bound(p->cint.begin(), p->cint.end(), col) - p->cint.begin() - 1;
-    const ColPanelHost& Cp = p->cps[ci];
+    const ColPanelHost* found = nullptr;
+    for (int64_t q = p->chunk_off[block]; q < p->chunk_off[block + 1]; ++q) {
+      const ColPanelHost& Cq = p->cps[p->chunk_list[q]];
+      if (col >= Cq.x0 && col < Cq.x0 + Cq.nrows) found = &Cq;
+    }
+    if (!found) return fail(HM_EINVAL, "entry not stored");
+    const ColPanelHost& Cp = *found;
     for (auto& sg : Cp.segs)
       if (sg.block == block && j >= sg.c_first && j < sg.c_first + sg.ncols) {
         for (auto& S : Cp.secs)

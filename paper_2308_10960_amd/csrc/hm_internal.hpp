@@ -25,7 +25,7 @@ struct LaunchParams {
 struct BlockInfo {
   int64_t toff = 0;       // first entry of t_b
   int64_t pst = 0;        // first partial
-  int32_t seg0 = 0, nseg = 0;   // column intervals covered by sigma_b
+  int32_t nseg = 0;       // column chunks of sigma_b
 };
 
 // A run of consecutive columns of one block inside a panel section.
@@ -64,7 +64,9 @@ struct hm_plan {
   std::string tune_path;
   std::vector<hm_block_desc> blocks;
   std::vector<hm::BlockInfo> binfo;
-  std::vector<int64_t> rint, cint;        // elementary interval boundaries (after splitting)
+  std::vector<int64_t> rint;              // elementary row interval boundaries (after splitting)
+  std::vector<int64_t> chunk_off;         // per block: [chunk_off[b], chunk_off[b+1]) into chunk_list
+  std::vector<int32_t> chunk_list;        // column panel (chunk) of each segment of each block
   std::vector<hm::RowPanelHost> rps;
   std::vector<hm::ColPanelHost> cps;
   std::vector<int32_t> lr_order;          // low-rank blocks in t order (large first)

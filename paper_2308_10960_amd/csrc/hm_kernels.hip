@@ -112,51 +112,63 @@ struct ColArgs {
   int64_t n_tiles;
 };
 
-// One wave streams one column tile: lane l owns the G columns of group l and
-// accumulates them over the interval's rows (x broadcast by readlane).  The
-// destinations are fetched first and all row loads are issued in batches of
-// 8, so a tile costs about ceil(rows / 8) memory latencies.
+// One workgroup streams one column tile.  Lane l of every wave owns the G
+// columns of group l; the tile's rows go to the four waves in interleaved
+// batches of 8 (wave w takes batches w, w + 4, ...), x of 64 rows at a time
+// sits in one register per lane and is broadcast by readlane.  The four
+// waves' sums are added in a fixed order through LDS (red: 4 x 64 x G).
 template <typename AccT, int DT>
-__device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, int lane) {
+__device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, AccT* red) {
   constexpr int G = group_width(DT);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool act = lane < T.ngroups;
-  int32_t dst[G];
-#pragma unroll
-  for (int c = 0; c < G; ++c) dst[c] = act ? a.dst[T.dst_off + lane * G + c] : -1;
-  const AccT xv = lane < T.nrows ? a.x[T.x0 + lane] : AccT(0);
   AccT acc[G];
 #pragma unroll
   for (int c = 0; c < G; ++c) acc[c] = AccT(0);
   const int rstride = T.ld * dtype_size(DT) / 16;
   const u32x4* p = reinterpret_cast<const u32x4*>(a.store + T.data_off) + lane;
-  for (int i = 0; i < T.nrows; i += 8) {
-    u32x4 r[8];
+  for (int i0 = 0; i0 < T.nrows; i0 += 64) {
+    const int nr = min(64, T.nrows - i0);
+    const AccT xv = lane < nr ? a.x[T.x0 + i0 + lane] : AccT(0);
+    for (int i = 8 * wave; i < nr; i += 32) {
+      u32x4 r[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (act && i + u < T.nrows) r[u] = ld16(p + (size_t)(i + u) * rstride);
+      for (int u = 0; u < 8; ++u)
+        if (act && i + u < nr) r[u] = ld16(p + (size_t)(i0 + i + u) * rstride);
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (i + u < T.nrows) {                      // uniform across the wave
-        const AccT xi = bcast(xv, i + u);
-        if (act) axpy_group<AccT, DT>(r[u], xi, acc);
-      }
+      for (int u = 0; u < 8; ++u)
+        if (i + u < nr) {                           // uniform across the wave
+          const AccT xi = bcast(xv, i + u);
+          if (act) axpy_group<AccT, DT>(r[u], xi, acc);
+        }
+    }
   }
 #pragma unroll
-  for (int c = 0; c < G; ++c)
-    if (dst[c] >= 0) a.part[dst[c]] = acc[c];
+  for (int c = 0; c < G; ++c) red[(wave * 64 + lane) * G + c] = acc[c];
+  __syncthreads();
+  if (wave == 0 && act) {
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      const int32_t d = a.dst[T.dst_off + lane * G + c];
+      if (d >= 0)
+        a.part[d] = (red[lane * G + c] + red[(64 + lane) * G + c]) +
+                    (red[(128 + lane) * G + c] + red[(192 + lane) * G + c]);
+    }
+  }
 }
 
+// A whole workgroup on tile ti (it synchronizes).  red: 4 * 64 * 8 values
+// (four waves x 64 lanes x at most 8 columns per lane).
 template <typename AccT>
-__device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti, int lane) {
-  if (ti >= a.n_tiles) return;
+__device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti, AccT* red) {
   const ColTile T = a.tiles[ti];
   switch (T.dtype) {
     case HM_F64:
-      if constexpr (sizeof(AccT) == 8) col_tile<AccT, HM_F64>(a, T, lane);
+      if constexpr (sizeof(AccT) == 8) col_tile<AccT, HM_F64>(a, T, red);
       break;
-    case HM_F32: col_tile<AccT, HM_F32>(a, T, lane); break;
-    case HM_F16: col_tile<AccT, HM_F16>(a, T, lane); break;
-    default: col_tile<AccT, HM_BF16>(a, T, lane); break;
+    case HM_F32: col_tile<AccT, HM_F32>(a, T, red); break;
+    case HM_F16: col_tile<AccT, HM_F16>(a, T, red); break;
+    default: col_tile<AccT, HM_BF16>(a, T, red); break;
   }
 }
 
@@ -234,15 +246,16 @@ __device__ __forceinline__ AccT row_section(const uint8_t* base, int m, int g_lo
                                             const AccT* z, int lane, int wave, AccT acc) {
   constexpr int G = group_width(DT);
   const u32x4* p = reinterpret_cast<const u32x4*>(base) + lane;
-  for (int g = g_lo + wave; g < g_hi; g += 4 * U) {
+  int g = g_lo + wave;
+  // U groups per wave in flight, all loads issued before the arithmetic
+  for (; g + 4 * (U - 1) < g_hi; g += 4 * U) {
     u32x4 r[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (g + 4 * u < g_hi) r[u] = ld16(p + (size_t)(g + 4 * u) * m);
+    for (int u = 0; u < U; ++u) r[u] = ld16(p + (size_t)(g + 4 * u) * m);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (g + 4 * u < g_hi) acc = dot_group<AccT, DT>(r[u], z + (g + 4 * u) * G, acc);
+    for (int u = 0; u < U; ++u) acc = dot_group<AccT, DT>(r[u], z + (g + 4 * u) * G, acc);
   }
+  for (; g < g_hi; g += 4) acc = dot_group<AccT, DT>(ld16(p + (size_t)g * m), z + g * G, acc);
   return acc;
 }
 
@@ -301,10 +314,10 @@ __device__ __forceinline__ int dense_slot_end(const RowArgs<AccT>& a, const RowP
 }
 
 // Phase 1: the dense parts of the row panels and the column tiles in one
-// grouped launch.  Entry >= 0: a row panel for the whole workgroup; entry < 0:
-// a group of four column tiles, one per wave.
+// grouped launch.  Entry >= 0: a row panel; entry < 0: column tile -entry-1.
 template <typename AccT, int CAP, int U>
 __global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, const int32_t* order) {
+  static_assert(CAP >= 4 * 64 * 8, "staging buffer doubles as the tile reduction buffer");
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
   const int item = order[blockIdx.x];
@@ -312,8 +325,7 @@ __global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, 
     const RowPanel P = ra.rp[item];
     row_panel_part<AccT, CAP, U>(ra, P, 0, P.nsec_dense, 0, dense_slot_end(ra, P), zs, red);
   } else {
-    const int64_t g = -(int64_t)item - 1;
-    col_tile_any<AccT>(ca, 4 * g + (threadIdx.x >> 6), threadIdx.x & 63);
+    col_tile_any<AccT>(ca, -(int64_t)item - 1, zs);
   }
 }
 
@@ -330,7 +342,8 @@ __global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* ord
 // (dense and U sections in one pass).
 template <typename AccT>
 __global__ __launch_bounds__(256) void k_col(ColArgs<AccT> ca) {
-  col_tile_any<AccT>(ca, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
+  __shared__ AccT cred[4 * 64 * 8];
+  col_tile_any<AccT>(ca, blockIdx.x, cred);
 }
 
 template <typename AccT, int CAP, int U>
@@ -704,7 +717,7 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
       hipLaunchKernelGGL((k_p1<AccT, CAP, U>), dim3((unsigned)h.n_p1), dim3(256), 0, s, ra, ca,
                          reinterpret_cast<const int32_t*>(st + h.off_p1_order));
   } else if (h.n_col_tiles > 0) {
-    hipLaunchKernelGGL(k_col<AccT>, dim3((unsigned)((h.n_col_tiles + 3) / 4)), dim3(256), 0, s, ca);
+    hipLaunchKernelGGL(k_col<AccT>, dim3((unsigned)h.n_col_tiles), dim3(256), 0, s, ca);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
   if (h.n_col_tiles > 0) {

@@ -13,17 +13,18 @@
 //    columns, element (i, c) of group g at ((g*m + i)*G + c): one 16-byte
 //    load per lane (lane = row) covers G columns.  The kernel owns y[rho]:
 //    y[rho] += alpha * P_rho z_rho, with z the gathered sources.
-//  * Column tiles.  The column breakpoints of the low-rank blocks cut
-//    [0, n_cols) into elementary column intervals kappa (<= 64 columns).
-//    For each, the rows of V_b / X_b restricted to kappa are concatenated
-//    over all low-rank blocks whose column cluster contains kappa.  The
+//  * Column tiles.  The rows of every V_b / X_b are cut into chunks kappa of
+//    at most 512 rows: sigma_b itself if small, else its largest sub-clusters
+//    of at most 512 rows (the block ranges form the cluster tree).  For each
+//    chunk, the rows of V_b restricted to kappa are concatenated over all
+//    low-rank blocks that have kappa as a chunk.  The
 //    section is cut into tiles of 64 groups of G columns, stored one after
 //    another; inside a tile the rows follow each other, each holding the
 //    tile's groups contiguously, so a wave (lane = group) streams one
 //    contiguous block and accumulates its G columns over the rows:
 //    partial(b, kappa, l) = sum_{i in kappa} V_b[i, l] x[i].
-//  * Reduction.  t_b[l] = s_b[l] * sum over the column intervals of
-//    sigma_b of the partials, in ascending interval order.
+//  * Reduction.  t_b[l] = s_b[l] * sum over the chunks of sigma_b of the
+//    partials, in ascending chunk order.
 //  * Single-RHS schedule: phase 1 streams the dense sections of the row
 //    panels (y += alpha D x) together with the column tiles in one grouped
 //    launch; after the reduction, phase 2 streams the U sections
@@ -38,7 +39,8 @@
 namespace hm {
 
 constexpr int kMaxPanelRows = 64;   // rows per row panel (one wave's lanes)
-constexpr int kMaxTileRows = 64;    // rows per column interval
+constexpr int kMaxTileRows = 64;    // rows per fallback column piece
+constexpr int kSegRows = 512;       // rows per column chunk (cluster sub-ranges up to this size)
 constexpr int kTileGroups = 64;     // column groups per column tile (one per lane)
 constexpr int kLargeSeg = 16;       // blocks with more intervals reduce per workgroup
 constexpr int kAlign = 256;
@@ -67,7 +69,7 @@ struct RowSection {      // 32 bytes
 struct ColTile {         // 32 bytes: one wave streams nrows rows x ngroups*G columns
   int64_t data_off;      // byte offset of the tile (row 0, first column)
   int32_t ld;            // row stride inside the tile, in elements (= ngroups*G)
-  int32_t nrows;         // rows of the column interval (<= 64)
+  int32_t nrows;         // rows of the column chunk (<= 512)
   int32_t x0;            // first x index of the interval
   int32_t dtype;
   int32_t ngroups;       // groups in this tile (<= 64)
@@ -77,7 +79,7 @@ struct ColTile {         // 32 bytes: one wave streams nrows rows x ngroups*G co
 struct TBlock {          // 16 bytes: reduction of one low-rank block's partials
   int32_t pst;           // first partial (acc units); partial (seg, l) at pst + seg*k + l
   int32_t k;             // rank
-  int32_t nseg;          // column intervals in sigma_b
+  int32_t nseg;          // column chunks of sigma_b
   int32_t toff;          // first entry of t_b in t
 };
 
@@ -92,8 +94,8 @@ struct StoreHeader {
   int64_t off_tblocks, off_large, off_owner, off_sigma;
   int64_t acc_dtype, has_sigma;
   // single-RHS work orders: phase 1 mixes the dense parts of row panels
-  // (entry >= 0: panel index) with groups of 4 column tiles (entry < 0:
-  // group -entry-1); phase 2 lists the row panels with U sections
+  // (entry >= 0: panel index) with column tiles (entry < 0: tile -entry-1);
+  // phase 2 lists the row panels with U sections
   int64_t off_p1_order, n_p1, off_p2_order, n_p2;
 };
 
