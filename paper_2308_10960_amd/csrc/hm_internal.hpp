@@ -19,7 +19,7 @@ namespace hm {
 //  row_unroll: 16-byte groups in flight per wave in the row-panel loop (4, 8).
 struct LaunchParams {
   int schedule = 0;
-  int row_unroll = 4;
+  int row_unroll = 8;
 };
 
 struct BlockInfo {
