@@ -235,9 +235,9 @@ def main():
     torch.cuda.synchronize()
 
     tuned = None
-    if R == 1 and not args.no_tune:
+    if not args.no_tune:
         from paper_2308_10960_amd import tune
-        best, times = tune.tune(D, step)
+        best, times = tune.tune(D, step, tune.CANDIDATES if R == 1 else tune.BATCH_CANDIDATES)
         tuned = {"chosen": best, "avg_ms": {k: round(v, 5) for k, v in times.items()}}
         log("tuned launch parameters:", tuned)
 

@@ -175,15 +175,20 @@ hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const voi
 hm_status hm_profile_begin(hm_matrix* A, int32_t max_calls);
 hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls);
 
-/* Launch parameters of one matrix, as text "schedule=S unroll=U":
+/* Launch parameters of one matrix, as text "schedule=S unroll=U order=O"
+ * (any subset of the keys):
  *   schedule 0: column tiles, partial reduction, whole row panels;
  *   schedule 1: one grouped launch of the dense row-panel sections with the
  *               column tiles, the reduction, then the U sections;
- *   unroll 4 or 8: 16-byte groups each wave keeps in flight in row panels.
- * The unroll depth does not change any sum's order (results are identical
- * bit for bit); schedule 1 adds the near-field and far-field parts to y in
- * two steps, so it differs from schedule 0 by rounding only.  Each choice is
- * deterministic.  hm_matrix_tune_key writes the key under which the
+ *   unroll 4 or 8: 16-byte groups each wave keeps in flight in row panels;
+ *   order 0: row panels largest first; order 1: row panels in cluster order,
+ *            cut into 8 contiguous ranges, one per XCD, so that neighbouring
+ *            panels share one L2 (whole-panel kernels: schedule 0 and the
+ *            batched path).
+ * Unroll depth and order do not change any sum's order (results are
+ * identical bit for bit); schedule 1 adds the near-field and far-field parts
+ * to y in two steps, so it differs from schedule 0 by rounding only.  Each
+ * choice is deterministic.  hm_matrix_tune_key writes the key under which the
  * tuner stores the best choice for matrices of this kind (accumulation type,
  * storage formats present, size class) into buf (NUL-terminated, <= len). */
 hm_status hm_matrix_set_launch(hm_matrix* A, const char* params);

@@ -472,6 +472,7 @@ static bool parse_launch(const char* text, LaunchParams& lp) {
     if (!end || *end) return false;
     if (k == "schedule" && (v == 0 || v == 1)) r.schedule = (int)v;
     else if (k == "unroll" && (v == 4 || v == 8)) r.row_unroll = (int)v;
+    else if (k == "order" && (v == 0 || v == 1)) r.order = (int)v;
     else return false;
     i = j;
   }
@@ -1046,7 +1047,8 @@ hm_status hm_matrix_set_launch(hm_matrix* A, const char* params) {
 
 hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len) {
   if (!A || !buf || len == 0) return fail(HM_EINVAL, "NULL argument");
-  std::snprintf(buf, len, "schedule=%d unroll=%d", A->launch.schedule, A->launch.row_unroll);
+  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d", A->launch.schedule, A->launch.row_unroll,
+                A->launch.order);
   return ok();
 }
 

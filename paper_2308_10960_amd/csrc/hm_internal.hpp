@@ -17,9 +17,12 @@ namespace hm {
 //  schedule 1: grouped launch of dense row-panel sections with the column
 //              tiles, reduction, then the U sections.
 //  row_unroll: 16-byte groups in flight per wave in the row-panel loop (4, 8).
+//  order 0: row panels largest first; order 1: cluster order in 8
+//           contiguous ranges, one per XCD (whole-panel kernels).
 struct LaunchParams {
   int schedule = 0;
   int row_unroll = 8;
+  int order = 0;
 };
 
 struct BlockInfo {

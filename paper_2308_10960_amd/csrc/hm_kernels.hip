@@ -228,6 +228,24 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs<AccT> a) {
 
 // ---------------------------------------------------------------- row panels
 
+// Workgroup -> row panel.  order != nullptr: the plan's largest-first list.
+// order == nullptr: cluster order cut into 8 contiguous ranges, one per XCD
+// (workgroups are dispatched to the 8 XCDs round-robin), so neighbouring
+// panels, which share most sources, run under the same L2.  Returns -1 for
+// the padding workgroups of that mapping.
+__device__ __forceinline__ int panel_of(const int32_t* order, int64_t n_panels) {
+  const int b = blockIdx.x;
+  if (order) return order[b];
+  const int64_t per = (n_panels + 7) / 8;
+  const int64_t p = (int64_t)(b & 7) * per + (b >> 3);
+  return p < n_panels ? (int)p : -1;
+}
+
+// Grid size for panel_of.
+inline int64_t panel_grid(bool xcd, int64_t n_panels) {
+  return xcd ? 8 * ((n_panels + 7) / 8) : n_panels;
+}
+
 template <typename AccT>
 struct RowArgs {
   const uint8_t* store;
@@ -347,10 +365,12 @@ __global__ __launch_bounds__(256) void k_col(ColArgs<AccT> ca) {
 }
 
 template <typename AccT, int CAP, int U>
-__global__ __launch_bounds__(256) void k_row(RowArgs<AccT> ra, const int32_t* order) {
+__global__ __launch_bounds__(256) void k_row(RowArgs<AccT> ra, const int32_t* order, int64_t n_panels) {
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
-  const RowPanel P = ra.rp[order[blockIdx.x]];
+  const int pi = panel_of(order, n_panels);
+  if (pi < 0) return;                               // uniform: whole workgroup
+  const RowPanel P = ra.rp[pi];
   row_panel_part<AccT, CAP, U>(ra, P, 0, P.nsec, 0, P.ncols, zs, red);
 }
 
@@ -553,7 +573,8 @@ struct RowBArgs {
   const uint8_t* store;
   const RowPanel* rp;
   const RowSection* rs;
-  const int32_t* order;
+  const int32_t* order;      // nullptr: XCD-contiguous cluster order
+  int64_t n_panels;
   const int32_t* src;
   const float* xr;
   const float* t;
@@ -627,7 +648,9 @@ __global__ __launch_bounds__(256) void k_row_b(RowBArgs a) {
   // CAPB = 256 source columns per LDS chunk; TPC threads per column, CPP columns per pass
   constexpr int RS = 32 * NH, CAPB = 256, TPC = RS / 4, CPP = 256 / TPC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const RowPanel P = a.rp[a.order[blockIdx.x]];
+  const int pi = panel_of(a.order, a.n_panels);
+  if (pi < 0) return;                               // uniform: whole workgroup
+  const RowPanel P = a.rp[pi];
   f32x32 acc[NH];
 #pragma unroll
   for (int h = 0; h < NH; ++h) acc[h] = (f32x32)(0.f);
@@ -734,8 +757,10 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
       hipLaunchKernelGGL((k_p2<AccT, CAP, U>), dim3((unsigned)h.n_p2), dim3(256), 0, s, ra,
                          reinterpret_cast<const int32_t*>(st + h.off_p2_order));
   } else if (h.n_row_panels > 0) {
-    hipLaunchKernelGGL((k_row<AccT, CAP, U>), dim3((unsigned)h.n_row_panels), dim3(256), 0, s, ra,
-                       reinterpret_cast<const int32_t*>(st + h.off_row_order));
+    const bool xcd = A.launch.order == 1;
+    hipLaunchKernelGGL((k_row<AccT, CAP, U>), dim3((unsigned)panel_grid(xcd, h.n_row_panels)), dim3(256),
+                       0, s, ra, xcd ? nullptr : reinterpret_cast<const int32_t*>(st + h.off_row_order),
+                       h.n_row_panels);
   }
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError();
@@ -808,19 +833,21 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
       (void)hipEventRecord(ev[1], s);
     }
     if (ev && r0 == 0) (void)hipEventRecord(ev[2], s);
+    const bool xcd = A.launch.order == 1;
     RowBArgs ra{st,
                 reinterpret_cast<const RowPanel*>(st + h.off_row_panels),
                 reinterpret_cast<const RowSection*>(st + h.off_row_sections),
-                reinterpret_cast<const int32_t*>(st + h.off_row_order),
+                xcd ? nullptr : reinterpret_cast<const int32_t*>(st + h.off_row_order), h.n_row_panels,
                 reinterpret_cast<const int32_t*>(st + h.off_row_src),
                 xr, t, Yc, ldy, (float)alpha, (int32_t)h.n_cols, nr};
     // 256 rows of RS floats: the 256-column source chunk, reused for the
     // 4 waves x 64 rows reduction
     const size_t lds = (size_t)RS * 256 * sizeof(float);
+    const unsigned grid = (unsigned)panel_grid(xcd, h.n_row_panels);
     if (RH == 1)
-      hipLaunchKernelGGL(k_row_b<1>, dim3((unsigned)h.n_row_panels), dim3(256), lds, s, ra);
+      hipLaunchKernelGGL(k_row_b<1>, dim3(grid), dim3(256), lds, s, ra);
     else
-      hipLaunchKernelGGL(k_row_b<2>, dim3((unsigned)h.n_row_panels), dim3(256), lds, s, ra);
+      hipLaunchKernelGGL(k_row_b<2>, dim3(grid), dim3(256), lds, s, ra);
   }
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError();

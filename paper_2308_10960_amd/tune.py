@@ -12,8 +12,11 @@ import os
 
 from . import hm
 
-CANDIDATES = ["schedule=0 unroll=4", "schedule=0 unroll=8",
-              "schedule=1 unroll=4", "schedule=1 unroll=8"]
+CANDIDATES = ["schedule=0 unroll=4 order=0", "schedule=0 unroll=8 order=0",
+              "schedule=0 unroll=8 order=1", "schedule=1 unroll=4 order=0",
+              "schedule=1 unroll=8 order=0"]
+# the batched path only depends on the row-panel order
+BATCH_CANDIDATES = ["schedule=0 unroll=8 order=0", "schedule=0 unroll=8 order=1"]
 
 
 def _time(D, step, reps: int) -> float:

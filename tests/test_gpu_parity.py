@@ -239,6 +239,9 @@ def test_batched_f32_mfma(name):
         Yb = _batch(D, X[:, pick], -0.5, Y0[:, pick])
         for q, c in enumerate(pick):
             np.testing.assert_array_equal(Yb[:, q], Y[:, c])
+    # XCD-contiguous row-panel order: same sums, padding workgroups idle
+    hm.hm_matrix_set_launch(D.handle, "order=1")
+    np.testing.assert_array_equal(_batch(D, X, -0.5, Y0), Y)
     D.close()
 
 
@@ -257,8 +260,9 @@ def test_launch_variants_and_tune_cache(sphere4k, tmp_path):
         assert hm.hm_matrix_get_launch(D.handle) == c
         out[c] = run(D, x)
         check_f64(out[c], ref, scale)
-    np.testing.assert_array_equal(out["schedule=0 unroll=4"], out["schedule=0 unroll=8"])
-    np.testing.assert_array_equal(out["schedule=1 unroll=4"], out["schedule=1 unroll=8"])
+    np.testing.assert_array_equal(out["schedule=0 unroll=4 order=0"], out["schedule=0 unroll=8 order=0"])
+    np.testing.assert_array_equal(out["schedule=0 unroll=4 order=0"], out["schedule=0 unroll=8 order=1"])
+    np.testing.assert_array_equal(out["schedule=1 unroll=4 order=0"], out["schedule=1 unroll=8 order=0"])
     with pytest.raises(hm.HMError):
         hm.hm_matrix_set_launch(D.handle, "schedule=7")
     xd, yd = D.vector(x), D.vector()
@@ -266,9 +270,9 @@ def test_launch_variants_and_tune_cache(sphere4k, tmp_path):
     assert best in tune.CANDIDATES and set(times) == set(tune.CANDIDATES)
     key = hm.hm_matrix_tune_key(D.handle)
     path = str(tmp_path / "tune.txt")
-    tune.write_cache(path, key, "schedule=1 unroll=8")
+    tune.write_cache(path, key, "schedule=1 unroll=8 order=0")
     tune.write_cache(path, "acc9-fmt0-n2^0", "schedule=0 unroll=4")
     D2 = DeviceHMatrix(H, hm.HM_F64, tune_cache=path)
-    assert hm.hm_matrix_get_launch(D2.handle) == "schedule=1 unroll=8"
+    assert hm.hm_matrix_get_launch(D2.handle) == "schedule=1 unroll=8 order=0"
     D2.close()
     D.close()
