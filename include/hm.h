@@ -164,6 +164,27 @@ hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const voi
                        int64_t ldx, void* d_Y, int64_t ldy, void* d_work, size_t work_bytes,
                        void* stream);
 
+/* HIP graph of one product.  hm_graph_create records into a graph the
+ * kernel launches that hm_mvm (nrhs == 1; ldx and ldy are ignored) or
+ * hm_mvm_batch (nrhs > 1) would enqueue with these arguments and the
+ * matrix's current launch parameters, checks the arguments as those calls
+ * do, and instantiates the graph on the current device (which must be the
+ * matrix's).  hm_graph_launch enqueues one replay on `stream`: the same
+ * product, y += alpha A x, on the same buffers, bit for bit what the eager
+ * call gives.  The graph holds the device addresses of A's store, x, y and
+ * the workspace: they must stay allocated until hm_graph_destroy; their
+ * contents may change between replays.  Replays that overlap in time (on
+ * different streams) race on y and the workspace.  The graph contains
+ * kernels only (no memory set, copy or allocation nodes).  Later changes
+ * of the launch parameters do not affect an existing graph.  Errors:
+ * HM_EINVAL (arguments, wrong device), HM_ENOMEM (workspace), HM_EDEVICE
+ * (capture or instantiation failed; text via hm_last_error). */
+typedef struct hm_graph hm_graph;
+hm_status hm_graph_create(const hm_matrix* A, int32_t nrhs, double alpha, const void* d_X, int64_t ldx,
+                          void* d_Y, int64_t ldy, void* d_work, size_t work_bytes, hm_graph** out);
+hm_status hm_graph_launch(hm_graph* g, void* stream);
+void hm_graph_destroy(hm_graph* g);
+
 /* Kernel timing for measurement.  While enabled, each hm_mvm / hm_mvm_batch
  * call on A records HIP events around each of its kernels on the call's
  * stream, for up to max_calls calls (later calls are not recorded).
@@ -184,9 +205,13 @@ hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls);
  *   order 0: row panels largest first; order 1: row panels in cluster order,
  *            cut into 8 contiguous ranges, one per XCD, so that neighbouring
  *            panels share one L2 (whole-panel kernels: schedule 0 and the
- *            batched path).
- * Unroll depth and order do not change any sum's order (results are
- * identical bit for bit); schedule 1 adds the near-field and far-field parts
+ *            batched path);
+ *   persist 0: one workgroup per work item (row panel, column tile);
+ *   persist 1, 2, 4 or 8: single-right-hand-side kernels run persistent
+ *            grids of at most that many workgroups per compute unit, each
+ *            looping over work items in the same order.
+ * Unroll depth, order and persistence do not change any sum's order (results
+ * are identical bit for bit); schedule 1 adds the near-field and far-field parts
  * to y in two steps, so it differs from schedule 0 by rounding only.  Each
  * choice is deterministic.  hm_matrix_tune_key writes the key under which the
  * tuner stores the best choice for matrices of this kind (accumulation type,

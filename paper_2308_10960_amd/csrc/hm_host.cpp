@@ -473,6 +473,7 @@ static bool parse_launch(const char* text, LaunchParams& lp) {
     if (k == "schedule" && (v == 0 || v == 1)) r.schedule = (int)v;
     else if (k == "unroll" && (v == 4 || v == 8)) r.row_unroll = (int)v;
     else if (k == "order" && (v == 0 || v == 1)) r.order = (int)v;
+    else if (k == "persist" && (v == 0 || v == 1 || v == 2 || v == 4 || v == 8)) r.persist = (int)v;
     else return false;
     i = j;
   }
@@ -920,6 +921,10 @@ hm_status hm_upload(const hm_plan* p, const double* const* a, const double* cons
   if (store_bytes < p->store_bytes)
     return fail(HM_ENOMEM, "store has %zu bytes, plan needs %zu", store_bytes, p->store_bytes);
   if (((uintptr_t)d_store) % kAlign) return fail(HM_EINVAL, "store must be 256-byte aligned");
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    return fail(HM_EDEVICE, "no usable HIP device");
   uint8_t* buf = (uint8_t*)std::calloc(p->store_bytes, 1);
   if (!buf) return fail(HM_ENOMEM, "host staging allocation of %zu bytes failed", p->store_bytes);
   hm_status st;
@@ -947,6 +952,8 @@ hm_status hm_upload(const hm_plan* p, const double* const* a, const double* cons
   M->acc_dtype = p->opts.acc_dtype;
   M->max_nrhs = p->opts.max_nrhs;
   M->launch = p->launch;
+  M->device = dev;
+  M->n_cu = ncu;
   std::memcpy(M->bytes_by_dtype, p->bytes_by_dtype, sizeof M->bytes_by_dtype);
   *out = M;
   return ok();
@@ -1005,21 +1012,18 @@ hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls) {
   return ok();
 }
 
-hm_status hm_mvm(const hm_matrix* A, double alpha, const void* d_x, void* d_y, void* d_work,
-                 size_t work_bytes, void* stream) {
+static hm_status check_mvm(const hm_matrix* A, const void* d_x, const void* d_y, const void* d_work,
+                           size_t work_bytes) {
   if (!A || !d_x || !d_y) return fail(HM_EINVAL, "NULL argument");
   if (d_x == d_y) return fail(HM_EINVAL, "x must not alias y");
   if (work_bytes < A->work_bytes_per_rhs || (A->work_bytes_per_rhs > 0 && !d_work))
     return fail(HM_ENOMEM, "workspace has %zu bytes, needs %zu", work_bytes, A->work_bytes_per_rhs);
   if (d_work && ((uintptr_t)d_work) % kAlign) return fail(HM_EINVAL, "workspace must be 256-byte aligned");
-  hipError_t e = launch_mvm(*A, alpha, d_x, d_y, d_work, (hipStream_t)stream);
-  if (e != hipSuccess) return fail(HM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
   return ok();
 }
 
-hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const void* d_X,
-                       int64_t ldx, void* d_Y, int64_t ldy, void* d_work, size_t work_bytes,
-                       void* stream) {
+static hm_status check_batch(const hm_matrix* A, int32_t nrhs, const void* d_X, int64_t ldx,
+                             const void* d_Y, int64_t ldy, const void* d_work, size_t work_bytes) {
   if (!A || !d_X || !d_Y) return fail(HM_EINVAL, "NULL argument");
   if (nrhs < 1 || nrhs > A->max_nrhs) return fail(HM_EINVAL, "nrhs %d outside [1, %d]", nrhs, A->max_nrhs);
   if (ldx < A->hdr.n_cols || ldy < A->hdr.n_rows) return fail(HM_EINVAL, "leading dimension too small");
@@ -1029,11 +1033,84 @@ hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const voi
   if (d_work && ((uintptr_t)d_work) % kAlign) return fail(HM_EINVAL, "workspace must be 256-byte aligned");
   const int vs = A->acc_dtype == HM_F64 ? 8 : 4;
   const uint8_t* X = (const uint8_t*)d_X;
-  uint8_t* Y = (uint8_t*)d_Y;
+  const uint8_t* Y = (const uint8_t*)d_Y;
   if (X < Y + (size_t)ldy * vs * nrhs && Y < X + (size_t)ldx * vs * nrhs)
     return fail(HM_EINVAL, "X must not overlap Y");
+  return ok();
+}
+
+hm_status hm_mvm(const hm_matrix* A, double alpha, const void* d_x, void* d_y, void* d_work,
+                 size_t work_bytes, void* stream) {
+  if (hm_status st = check_mvm(A, d_x, d_y, d_work, work_bytes)) return st;
+  hipError_t e = launch_mvm(*A, alpha, d_x, d_y, d_work, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(HM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const void* d_X,
+                       int64_t ldx, void* d_Y, int64_t ldy, void* d_work, size_t work_bytes,
+                       void* stream) {
+  if (hm_status st = check_batch(A, nrhs, d_X, ldx, d_Y, ldy, d_work, work_bytes)) return st;
   hipError_t e = launch_mvm_batch(*A, nrhs, alpha, d_X, ldx, d_Y, ldy, d_work, (hipStream_t)stream);
   if (e != hipSuccess) return fail(HM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+// ------------------------------------------------------------------ graphs
+
+struct hm_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int32_t device = 0;
+};
+
+void hm_graph_destroy(hm_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+hm_status hm_graph_create(const hm_matrix* A, int32_t nrhs, double alpha, const void* d_X, int64_t ldx,
+                          void* d_Y, int64_t ldy, void* d_work, size_t work_bytes, hm_graph** out) {
+  if (!out) return fail(HM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nrhs == 1) {
+    if (hm_status st = check_mvm(A, d_X, d_Y, d_work, work_bytes)) return st;
+  } else if (hm_status st = check_batch(A, nrhs, d_X, ldx, d_Y, ldy, d_work, work_bytes)) {
+    return st;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != A->device)
+    return fail(HM_EINVAL, "the current device is not the matrix's device");
+  auto* G = new (std::nothrow) hm_graph();
+  if (!G) return fail(HM_ENOMEM, "host allocation failed");
+  G->device = dev;
+  // a private stream in capture mode: the launches become graph nodes
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t le = nrhs == 1
+        ? launch_mvm(*A, alpha, d_X, d_Y, d_work, cs, nullptr, false)
+        : launch_mvm_batch(*A, nrhs, alpha, d_X, ldx, d_Y, ldy, d_work, cs, false);
+    e = hipStreamEndCapture(cs, &G->graph);
+    if (e == hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    hm_graph_destroy(G);
+    return fail(HM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  *out = G;
+  return ok();
+}
+
+hm_status hm_graph_launch(hm_graph* g, void* stream) {
+  if (!g) return fail(HM_EINVAL, "NULL argument");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(HM_EDEVICE, "graph launch failed: %s", hipGetErrorString(e));
   return ok();
 }
 
@@ -1047,8 +1124,8 @@ hm_status hm_matrix_set_launch(hm_matrix* A, const char* params) {
 
 hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len) {
   if (!A || !buf || len == 0) return fail(HM_EINVAL, "NULL argument");
-  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d", A->launch.schedule, A->launch.row_unroll,
-                A->launch.order);
+  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d persist=%d", A->launch.schedule,
+                A->launch.row_unroll, A->launch.order, A->launch.persist);
   return ok();
 }
 

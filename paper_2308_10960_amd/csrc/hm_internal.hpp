@@ -19,10 +19,13 @@ namespace hm {
 //  row_unroll: 16-byte groups in flight per wave in the row-panel loop (4, 8).
 //  order 0: row panels largest first; order 1: cluster order in 8
 //           contiguous ranges, one per XCD (whole-panel kernels).
+//  persist 0: one workgroup per work item; P > 0: persistent grids of at
+//           most P workgroups per CU looping over the items (single RHS).
 struct LaunchParams {
   int schedule = 0;
   int row_unroll = 8;
   int order = 0;
+  int persist = 0;
 };
 
 struct BlockInfo {
@@ -102,6 +105,7 @@ struct hm_matrix {
   int64_t work_t_off = 0;
   int64_t work_part_bytes = 0, work_t_bytes = 0, work_x_bytes = 0;
   int32_t acc_dtype = 0, max_nrhs = 1;
+  int32_t device = 0, n_cu = 256;       // device of the store and its compute units
   hm::LaunchParams launch;
   size_t bytes_by_dtype[4] = {0, 0, 0, 0};
 };
@@ -121,10 +125,11 @@ void read_tune_cache(hm_plan* P);
 uint16_t f64_to_f16(double d);
 uint16_t f64_to_bf16(double d);
 
-// Kernel launchers (hm_kernels.hip).
+// Kernel launchers (hm_kernels.hip).  profile = false: never record the
+// matrix's timing events (used while a stream is being captured).
 hipError_t launch_mvm(const hm_matrix& A, double alpha, const void* x, void* y, void* work,
-                      hipStream_t s, hipEvent_t* ev = nullptr);
+                      hipStream_t s, hipEvent_t* ev = nullptr, bool profile = true);
 hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const void* X, int64_t ldx,
-                            void* Y, int64_t ldy, void* work, hipStream_t s);
+                            void* Y, int64_t ldy, void* work, hipStream_t s, bool profile = true);
 hipError_t launch_stream_read(const void* buf, size_t bytes, void* out, hipStream_t s);
 }  // namespace hm

@@ -228,22 +228,35 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs<AccT> a) {
 
 // ---------------------------------------------------------------- row panels
 
-// Workgroup -> row panel.  order != nullptr: the plan's largest-first list.
+// Work items.  A plain launch has one workgroup per item; a persistent one
+// has a fixed grid whose workgroup b takes items b, b + grid, b + 2 grid, ...
+// in the same item order (a persistent grid is a multiple of 8, so every item
+// keeps the XCD its index maps to).  The sums of an item do not depend on the
+// workgroup that runs it.
+//
+// Item -> row panel.  order != nullptr: the plan's largest-first list.
 // order == nullptr: cluster order cut into 8 contiguous ranges, one per XCD
 // (workgroups are dispatched to the 8 XCDs round-robin), so neighbouring
 // panels, which share most sources, run under the same L2.  Returns -1 for
-// the padding workgroups of that mapping.
-__device__ __forceinline__ int panel_of(const int32_t* order, int64_t n_panels) {
-  const int b = blockIdx.x;
-  if (order) return order[b];
+// the padding items of that mapping.
+__device__ __forceinline__ int panel_of(const int32_t* order, int64_t n_panels, int64_t it) {
+  if (order) return order[it];
   const int64_t per = (n_panels + 7) / 8;
-  const int64_t p = (int64_t)(b & 7) * per + (b >> 3);
+  const int64_t p = (it & 7) * per + (it >> 3);
   return p < n_panels ? (int)p : -1;
 }
 
-// Grid size for panel_of.
-inline int64_t panel_grid(bool xcd, int64_t n_panels) {
+// Items of a row-panel launch under panel_of.
+inline int64_t panel_items(bool xcd, int64_t n_panels) {
   return xcd ? 8 * ((n_panels + 7) / 8) : n_panels;
+}
+
+// Grid of a launch over n_items: one workgroup per item, or with persist > 0
+// at most persist workgroups per CU, rounded down to a multiple of 8.
+inline unsigned item_grid(int64_t n_items, int persist, int n_cu) {
+  if (persist <= 0) return (unsigned)n_items;
+  const int64_t cap = std::max<int64_t>(8, (int64_t)persist * n_cu / 8 * 8);
+  return (unsigned)std::min<int64_t>(n_items, cap);
 }
 
 template <typename AccT>
@@ -334,44 +347,58 @@ __device__ __forceinline__ int dense_slot_end(const RowArgs<AccT>& a, const RowP
 // Phase 1: the dense parts of the row panels and the column tiles in one
 // grouped launch.  Entry >= 0: a row panel; entry < 0: column tile -entry-1.
 template <typename AccT, int CAP, int U>
-__global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, const int32_t* order) {
+__global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, const int32_t* order,
+                                            int64_t n_items) {
   static_assert(CAP >= 4 * 64 * 8, "staging buffer doubles as the tile reduction buffer");
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
-  const int item = order[blockIdx.x];
-  if (item >= 0) {
-    const RowPanel P = ra.rp[item];
-    row_panel_part<AccT, CAP, U>(ra, P, 0, P.nsec_dense, 0, dense_slot_end(ra, P), zs, red);
-  } else {
-    col_tile_any<AccT>(ca, -(int64_t)item - 1, zs);
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    if (it != blockIdx.x) __syncthreads();          // LDS of the previous item
+    const int item = order[it];
+    if (item >= 0) {
+      const RowPanel P = ra.rp[item];
+      row_panel_part<AccT, CAP, U>(ra, P, 0, P.nsec_dense, 0, dense_slot_end(ra, P), zs, red);
+    } else {
+      col_tile_any<AccT>(ca, -(int64_t)item - 1, zs);
+    }
   }
 }
 
 // Phase 2: the U sections of the row panels (after t is complete).
 template <typename AccT, int CAP, int U>
-__global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* order) {
+__global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* order, int64_t n_items) {
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
-  const RowPanel P = ra.rp[order[blockIdx.x]];
-  row_panel_part<AccT, CAP, U>(ra, P, P.nsec_dense, P.nsec, dense_slot_end(ra, P), P.ncols, zs, red);
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    if (it != blockIdx.x) __syncthreads();
+    const RowPanel P = ra.rp[order[it]];
+    row_panel_part<AccT, CAP, U>(ra, P, P.nsec_dense, P.nsec, dense_slot_end(ra, P), P.ncols, zs, red);
+  }
 }
 
-// Schedule 0: all column tiles (one per wave), then whole row panels
-// (dense and U sections in one pass).
+// Schedule 0: all column tiles (one per workgroup item), then whole row
+// panels (dense and U sections in one pass).
 template <typename AccT>
 __global__ __launch_bounds__(256) void k_col(ColArgs<AccT> ca) {
   __shared__ AccT cred[4 * 64 * 8];
-  col_tile_any<AccT>(ca, blockIdx.x, cred);
+  for (int64_t it = blockIdx.x; it < ca.n_tiles; it += gridDim.x) {
+    if (it != blockIdx.x) __syncthreads();
+    col_tile_any<AccT>(ca, it, cred);
+  }
 }
 
 template <typename AccT, int CAP, int U>
-__global__ __launch_bounds__(256) void k_row(RowArgs<AccT> ra, const int32_t* order, int64_t n_panels) {
+__global__ __launch_bounds__(256) void k_row(RowArgs<AccT> ra, const int32_t* order, int64_t n_panels,
+                                             int64_t n_items) {
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
-  const int pi = panel_of(order, n_panels);
-  if (pi < 0) return;                               // uniform: whole workgroup
-  const RowPanel P = ra.rp[pi];
-  row_panel_part<AccT, CAP, U>(ra, P, 0, P.nsec, 0, P.ncols, zs, red);
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int pi = panel_of(order, n_panels, it);
+    if (pi < 0) continue;                           // uniform: whole workgroup
+    __syncthreads();                                // LDS of the previous item
+    const RowPanel P = ra.rp[pi];
+    row_panel_part<AccT, CAP, U>(ra, P, 0, P.nsec, 0, P.ncols, zs, red);
+  }
 }
 
 // Streaming-read probe: reads n16 16-byte words with the same loads the
@@ -648,7 +675,7 @@ __global__ __launch_bounds__(256) void k_row_b(RowBArgs a) {
   // CAPB = 256 source columns per LDS chunk; TPC threads per column, CPP columns per pass
   constexpr int RS = 32 * NH, CAPB = 256, TPC = RS / 4, CPP = 256 / TPC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int pi = panel_of(a.order, a.n_panels);
+  const int pi = panel_of(a.order, a.n_panels, blockIdx.x);
   if (pi < 0) return;                               // uniform: whole workgroup
   const RowPanel P = a.rp[pi];
   f32x32 acc[NH];
@@ -734,13 +761,14 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
                    reinterpret_cast<const int32_t*>(st + h.off_col_dst),
                    reinterpret_cast<const AccT*>(x), part, h.n_col_tiles};
   const bool grouped = A.launch.schedule == 1;
+  const int ps = A.launch.persist, ncu = A.n_cu;
   if (ev) (void)hipEventRecord(ev[0], s);
   if (grouped) {
     if (h.n_p1 > 0)
-      hipLaunchKernelGGL((k_p1<AccT, CAP, U>), dim3((unsigned)h.n_p1), dim3(256), 0, s, ra, ca,
-                         reinterpret_cast<const int32_t*>(st + h.off_p1_order));
+      hipLaunchKernelGGL((k_p1<AccT, CAP, U>), dim3(item_grid(h.n_p1, ps, ncu)), dim3(256), 0, s, ra,
+                         ca, reinterpret_cast<const int32_t*>(st + h.off_p1_order), h.n_p1);
   } else if (h.n_col_tiles > 0) {
-    hipLaunchKernelGGL(k_col<AccT>, dim3((unsigned)h.n_col_tiles), dim3(256), 0, s, ca);
+    hipLaunchKernelGGL(k_col<AccT>, dim3(item_grid(h.n_col_tiles, ps, ncu)), dim3(256), 0, s, ca);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
   if (h.n_col_tiles > 0) {
@@ -754,13 +782,14 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
   if (ev) (void)hipEventRecord(ev[2], s);
   if (grouped) {
     if (h.n_p2 > 0)
-      hipLaunchKernelGGL((k_p2<AccT, CAP, U>), dim3((unsigned)h.n_p2), dim3(256), 0, s, ra,
-                         reinterpret_cast<const int32_t*>(st + h.off_p2_order));
+      hipLaunchKernelGGL((k_p2<AccT, CAP, U>), dim3(item_grid(h.n_p2, ps, ncu)), dim3(256), 0, s, ra,
+                         reinterpret_cast<const int32_t*>(st + h.off_p2_order), h.n_p2);
   } else if (h.n_row_panels > 0) {
     const bool xcd = A.launch.order == 1;
-    hipLaunchKernelGGL((k_row<AccT, CAP, U>), dim3((unsigned)panel_grid(xcd, h.n_row_panels)), dim3(256),
-                       0, s, ra, xcd ? nullptr : reinterpret_cast<const int32_t*>(st + h.off_row_order),
-                       h.n_row_panels);
+    const int64_t items = panel_items(xcd, h.n_row_panels);
+    hipLaunchKernelGGL((k_row<AccT, CAP, U>), dim3(item_grid(items, ps, ncu)), dim3(256), 0, s, ra,
+                       xcd ? nullptr : reinterpret_cast<const int32_t*>(st + h.off_row_order),
+                       h.n_row_panels, items);
   }
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError();
@@ -776,8 +805,9 @@ hipError_t launch_typed(const hm_matrix& A, double alpha, const void* x, void* y
 }  // namespace
 
 hipError_t launch_mvm(const hm_matrix& A, double alpha, const void* x, void* y, void* work,
-                      hipStream_t s, hipEvent_t* ev) {
-  if (!ev && A.prof.on && A.prof.calls < A.prof.max_calls) ev = &A.prof.ev[4 * (size_t)A.prof.calls++];
+                      hipStream_t s, hipEvent_t* ev, bool profile) {
+  if (profile && !ev && A.prof.on && A.prof.calls < A.prof.max_calls)
+    ev = &A.prof.ev[4 * (size_t)A.prof.calls++];
   return A.acc_dtype == HM_F64 ? launch_typed<double>(A, alpha, x, y, work, s, ev)
                                : launch_typed<float>(A, alpha, x, y, work, s, ev);
 }
@@ -792,18 +822,18 @@ hipError_t launch_stream_read(const void* buf, size_t bytes, void* out, hipStrea
 }
 
 hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const void* X, int64_t ldx,
-                            void* Y, int64_t ldy, void* work, hipStream_t s) {
+                            void* Y, int64_t ldy, void* work, hipStream_t s, bool profile) {
   const StoreHeader& h = A.hdr;
   if (A.acc_dtype == HM_F64) {
     for (int c = 0; c < nrhs; ++c) {
       hipError_t e = launch_mvm(A, alpha, static_cast<const uint8_t*>(X) + (size_t)c * ldx * 8,
-                                static_cast<uint8_t*>(Y) + (size_t)c * ldy * 8, work, s);
+                                static_cast<uint8_t*>(Y) + (size_t)c * ldy * 8, work, s, nullptr, profile);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   }
   hipEvent_t* ev = nullptr;
-  if (A.prof.on && A.prof.calls < A.prof.max_calls) ev = &A.prof.ev[4 * (size_t)A.prof.calls++];
+  if (profile && A.prof.on && A.prof.calls < A.prof.max_calls) ev = &A.prof.ev[4 * (size_t)A.prof.calls++];
   const uint8_t* st = A.d_store;
   uint8_t* w = static_cast<uint8_t*>(work);
   for (int r0 = 0; r0 < nrhs; r0 += 64) {
@@ -843,7 +873,7 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
     // 256 rows of RS floats: the 256-column source chunk, reused for the
     // 4 waves x 64 rows reduction
     const size_t lds = (size_t)RS * 256 * sizeof(float);
-    const unsigned grid = (unsigned)panel_grid(xcd, h.n_row_panels);
+    const unsigned grid = (unsigned)panel_items(xcd, h.n_row_panels);
     if (RH == 1)
       hipLaunchKernelGGL(k_row_b<1>, dim3(grid), dim3(256), lds, s, ra);
     else

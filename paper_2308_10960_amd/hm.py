@@ -70,6 +70,9 @@ PROTOTYPES = {
     "hm_pack_host": (_i32, [_vp, _vp, _vp, _vp, _vp, _sz]),
     "hm_mvm": (_i32, [_vp, _dbl, _vp, _vp, _vp, _sz, _vp]),
     "hm_mvm_batch": (_i32, [_vp, _i32, _dbl, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
+    "hm_graph_create": (_i32, [_vp, _i32, _dbl, _vp, _i64, _vp, _i64, _vp, _sz, _P(_vp)]),
+    "hm_graph_launch": (_i32, [_vp, _vp]),
+    "hm_graph_destroy": (None, [_vp]),
     "hm_profile_begin": (_i32, [_vp, _i32]),
     "hm_profile_end": (_i32, [_vp, _P(_dbl), _P(_i64)]),
     "hm_matrix_set_launch": (_i32, [_vp, C.c_char_p]),
@@ -204,6 +207,22 @@ def hm_mvm_batch(mat: int, nrhs: int, alpha: float, d_X, ldx: int, d_Y, ldy: int
                  work_bytes: int, stream=None) -> None:
     _check(lib().hm_mvm_batch(mat, nrhs, alpha, _ptr(d_X), ldx, _ptr(d_Y), ldy, _ptr(d_work),
                               work_bytes, _stream(stream)), "hm_mvm_batch")
+
+
+def hm_graph_create(mat: int, nrhs: int, alpha: float, d_X, ldx: int, d_Y, ldy: int, d_work,
+                    work_bytes: int) -> int:
+    g = C.c_void_p()
+    _check(lib().hm_graph_create(mat, nrhs, alpha, _ptr(d_X), ldx, _ptr(d_Y), ldy, _ptr(d_work),
+                                 work_bytes, C.byref(g)), "hm_graph_create")
+    return g.value
+
+
+def hm_graph_launch(graph: int, stream=None) -> None:
+    _check(lib().hm_graph_launch(graph, _stream(stream)), "hm_graph_launch")
+
+
+def hm_graph_destroy(graph: int) -> None:
+    lib().hm_graph_destroy(graph)
 
 
 def hm_profile_begin(mat: int, max_calls: int) -> None:

@@ -1,4 +1,5 @@
-"""Autotuner of the launch parameters (schedule, row-panel unroll depth).
+"""Autotuner of the launch parameters (schedule, unroll depth, panel order,
+persistent grids).
 
 For one device-resident matrix it times every candidate with the library's
 own HIP-event kernel timing, keeps the fastest, and can store the choice in
@@ -12,11 +13,12 @@ import os
 
 from . import hm
 
-CANDIDATES = ["schedule=0 unroll=4 order=0", "schedule=0 unroll=8 order=0",
-              "schedule=0 unroll=8 order=1", "schedule=1 unroll=4 order=0",
-              "schedule=1 unroll=8 order=0"]
+CANDIDATES = ["schedule=0 unroll=4 order=0 persist=0", "schedule=0 unroll=8 order=0 persist=0",
+              "schedule=0 unroll=8 order=1 persist=0", "schedule=0 unroll=8 order=1 persist=4",
+              "schedule=0 unroll=8 order=1 persist=8", "schedule=1 unroll=4 order=0 persist=0",
+              "schedule=1 unroll=8 order=0 persist=0", "schedule=1 unroll=8 order=0 persist=8"]
 # the batched path only depends on the row-panel order
-BATCH_CANDIDATES = ["schedule=0 unroll=8 order=0", "schedule=0 unroll=8 order=1"]
+BATCH_CANDIDATES = ["schedule=0 unroll=8 order=0 persist=0", "schedule=0 unroll=8 order=1 persist=0"]
 
 
 def _time(D, step, reps: int) -> float:
