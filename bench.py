@@ -77,9 +77,19 @@ def kernel_bytes(H, info, vs, R=1, schedule=0):
     }
 
 
-def kernels_source_hash():
+# launch parameters chosen by the autotuner (bench.py --tune), per kind of matrix
+TUNE_CACHE = os.path.join(ROOT, "paper_2308_10960_amd", "tune_cache.txt")
+
+BATCH_KERNELS = ("k_xpose", "k_col_b", "k_reduce_b", "k_row_b")
+
+
+def kernels_source_hash(kernel="k_row"):
+    """Hash of the sources a kernel is built from (the single- or the
+    multi-right-hand-side kernel file, the shared device header, the store
+    layout)."""
+    batch = any(k in kernel for k in BATCH_KERNELS)
     h = hashlib.sha256()
-    for f in ("hm_kernels.hip", "hm_layout.hpp"):
+    for f in ("hm_kernels_batch.hip" if batch else "hm_kernels.hip", "hm_device.hpp", "hm_layout.hpp"):
         with open(os.path.join(ROOT, "paper_2308_10960_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -93,7 +103,7 @@ def read_traffic(kernel, workload):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_source_hash") != kernels_source_hash():
+    if d.get("kernel_source_hash") != kernels_source_hash(kernel):
         return None
     return d.get("bytes_per_launch")
 
@@ -112,7 +122,8 @@ def serve_bench(args, torch, hmgen, hm, DeviceHMatrix):
         name = "sphere4k_mixed" if geo == "sphere" else "cube4k"
         H = hmgen.build_preset(name, n=n, dtype="mixed")
         mats.append(H)
-        Ds.append(DeviceHMatrix(H, hm.HM_F32, max_nrhs=64))
+        cache = None if args.no_tune_cache or not os.path.exists(args.tune_cache) else args.tune_cache
+        Ds.append(DeviceHMatrix(H, hm.HM_F32, max_nrhs=64, tune_cache=cache))
         log(f"serve: built {geo} n={n} in {H.build_seconds:.1f}s, store {Ds[-1].info['store_bytes'] / 1e9:.2f} GB")
     arena_bytes = args.serve_arena_gb << 30
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
@@ -174,7 +185,13 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1,
                     help="right-hand sides per product (> 1: hm_mvm_batch; reported separately)")
     ap.add_argument("--n", type=int, default=0, help="override the workload size (not the default line)")
-    ap.add_argument("--no-tune", action="store_true", help="use the built-in launch parameters")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner on this matrix before the timed region and store its "
+                         "choice in the tune cache (default: read the cache, no tuning)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="tune cache to read (and, with --tune, to update)")
+    ap.add_argument("--no-tune-cache", action="store_true",
+                    help="ignore the tune cache: built-in launch parameters")
     ap.add_argument("--no-stream-probe", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -216,8 +233,9 @@ def main():
     acc = hm.HM_F32 if mixed else hm.HM_F64
     vs = 4 if mixed else 8
     stream = torch.cuda.Stream()
+    cache = None if args.no_tune_cache or not os.path.exists(args.tune_cache) else args.tune_cache
     with torch.cuda.stream(stream):
-        D = DeviceHMatrix(H, acc, stream=stream, max_nrhs=args.nrhs)
+        D = DeviceHMatrix(H, acc, stream=stream, max_nrhs=args.nrhs, tune_cache=cache)
     info = D.info
     log("uploaded: store %.3f GB, alg %.3f GB" % (info["store_bytes"] / 1e9, info["alg_bytes"] / 1e9))
     R = args.nrhs
@@ -234,12 +252,17 @@ def main():
                                        stream)
     torch.cuda.synchronize()
 
-    tuned = None
-    if not args.no_tune:
+    key = hm.hm_matrix_tune_key(D.handle)
+    if args.tune:
         from paper_2308_10960_amd import tune
         best, times = tune.tune(D, step, tune.CANDIDATES if R == 1 else tune.BATCH_CANDIDATES)
-        tuned = {"chosen": best, "avg_ms": {k: round(v, 5) for k, v in times.items()}}
-        log("tuned launch parameters:", tuned)
+        tune.write_cache(args.tune_cache, key, best)
+        tuned = {"source": "autotuner, this run (written to the tune cache)", "key": key,
+                 "chosen": best, "avg_ms": {k: round(v, 5) for k, v in times.items()}}
+    else:
+        tuned = {"source": "tune cache" if cache else "built-in", "key": key,
+                 "chosen": hm.hm_matrix_get_launch(D.handle)}
+    log("launch parameters:", tuned)
 
     for _ in range(args.warmup):
         step()
@@ -274,6 +297,37 @@ def main():
                    "gbs": round(kb[k] / (avg_ms[k] * 1e-3) / 1e9, 1) if avg_ms[k] > 0 else None}
                for k in names}
     log("kernels", kernels)
+
+    # distribution of single steps (HIP events on the product's stream)
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(args.steps)]
+    for e0, e1 in pairs:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    each = np.array([e0.elapsed_time(e1) for e0, e1 in pairs])
+    step_ms = {"median": round(float(np.median(each)), 5),
+               "p10": round(float(np.percentile(each, 10)), 5),
+               "p90": round(float(np.percentile(each, 90)), 5)}
+    log("step ms", step_ms)
+
+    # the same product replayed from a HIP graph
+    if R == 1:
+        g = hm.hm_graph_create(D.handle, 1, 1.0, x, H.n, y, H.n, D.work, D.work.numel())
+    else:
+        g = hm.hm_graph_create(D.handle, R, 1.0, X, H.n, Y, H.n, D.work, D.work.numel())
+    for _ in range(args.warmup):
+        hm.hm_graph_launch(g, stream)
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for _ in range(args.steps):
+        hm.hm_graph_launch(g, stream)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    hm.hm_graph_destroy(g)
+    log("graph replay: %.4f ms/step" % graph_ms)
 
     stream_gbs = None
     if not args.no_stream_probe:
@@ -329,6 +383,8 @@ def main():
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "stream_read_gbs": round(stream_gbs, 1) if stream_gbs else None,
         "pct_of_stream_read": round(100 * value / stream_gbs, 2) if stream_gbs else None,
+        "step_ms": step_ms,
+        "graph_ms_per_step": round(graph_ms, 5),
         "launch": hm.hm_matrix_get_launch(D.handle),
         "tuning": tuned,
         "roofline": roofline,

@@ -492,12 +492,18 @@ void hmg_get_blocks(const hmg_tree* t, int64_t* rb, int64_t* re, int64_t* cb, in
 // eps_aca) followed by Algorithm 1 at eps for admissible ones.  With
 // keep_sigma = 0 the singular values are folded into the first factor
 // (U = W diag(S), V = X); otherwise W, S, X are kept separately.
-int hmg_fill(hmg_tree* t, int32_t kernel, const double* params, double eps_aca, double eps,
-             int32_t keep_sigma, int32_t nthreads) {
-  if (!t || kernel < 0 || kernel > 2) return -1;
-  t->kernel = kernel;
-  for (int i = 0; i < 4; ++i) t->kp[i] = params ? params[i] : 0.0;
-  t->keep_sigma = keep_sigma;
+// hmg_fill_part fills share `part` of `nparts` (blocks in size order, dealt
+// round-robin, so every share has the same mix of sizes); calling it for
+// part = 0 .. nparts-1 fills every block, exactly as hmg_fill does.
+int hmg_fill_part(hmg_tree* t, int32_t kernel, const double* params, double eps_aca, double eps,
+                  int32_t keep_sigma, int32_t nthreads, int32_t part, int32_t nparts) {
+  if (!t || kernel < 0 || kernel > 2 || nparts < 1 || part < 0 || part >= nparts) return -1;
+  if (part == 0) {
+    t->kernel = kernel;
+    for (int i = 0; i < 4; ++i) t->kp[i] = params ? params[i] : 0.0;
+    t->keep_sigma = keep_sigma;
+    t->filled = false;
+  }
   Eval ev{*t};
   const int64_t nb = (int64_t)t->blocks.size();
   // Largest blocks first for load balance.
@@ -508,14 +514,15 @@ int hmg_fill(hmg_tree* t, int32_t kernel, const double* params, double eps_aca, 
     const Block& b = t->blocks[y];
     return (a.re - a.rb) + (a.ce - a.cb) > (b.re - b.rb) + (b.ce - b.cb);
   });
+  const int64_t nmine = nb > part ? (nb - part + nparts - 1) / nparts : 0;
   if (nthreads > 0) omp_set_num_threads(nthreads);
   std::atomic<int> err{0};
 #pragma omp parallel
   {
     std::vector<double> U, V, W, X, S;
 #pragma omp for schedule(dynamic, 1)
-    for (int64_t oi = 0; oi < nb; ++oi) {
-      Block& b = t->blocks[order[oi]];
+    for (int64_t q = 0; q < nmine; ++q) {
+      Block& b = t->blocks[order[part + q * nparts]];
       const int64_t m = b.re - b.rb, n = b.ce - b.cb;
       b.a.clear(); b.b.clear(); b.s.clear();
       if (!b.adm) {
@@ -536,8 +543,13 @@ int hmg_fill(hmg_tree* t, int32_t kernel, const double* params, double eps_aca, 
       if (keep_sigma) b.s = S;
     }
   }
-  t->filled = err.load() == 0;
+  if (part == nparts - 1) t->filled = err.load() == 0;
   return err.load();
+}
+
+int hmg_fill(hmg_tree* t, int32_t kernel, const double* params, double eps_aca, double eps,
+             int32_t keep_sigma, int32_t nthreads) {
+  return hmg_fill_part(t, kernel, params, eps_aca, eps, keep_sigma, nthreads, 0, 1);
 }
 
 // Per-block factor pointers (0 where absent) as integers, for marshalling.

@@ -53,6 +53,9 @@ def lib():
     L.hmg_get_blocks.argtypes = [vp, _i64p, _i64p, _i64p, _i64p, _i32p, _i32p, _i32p, _i32p]
     L.hmg_fill.argtypes = [vp, C.c_int32, _f64p, C.c_double, C.c_double, C.c_int32, C.c_int32]
     L.hmg_fill.restype = C.c_int
+    L.hmg_fill_part.argtypes = [vp, C.c_int32, _f64p, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                C.c_int32, C.c_int32]
+    L.hmg_fill_part.restype = C.c_int
     L.hmg_get_factor_ptrs.argtypes = [vp, _u64p, _u64p, _u64p]
     L.hmg_get_ranks.argtypes = [vp, _i32p]
     L.hmg_eval.argtypes = [vp, _i64p, _i64p, C.c_int64, _f64p]
@@ -185,16 +188,30 @@ class HMatrix:
         }
 
 
+def default_threads() -> int:
+    """Host threads for construction: the CPUs this process may run on,
+    capped by OMP_NUM_THREADS when that is set (the CPU share of a machine
+    can be smaller than what the affinity mask shows)."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        cap = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        cap = 0
+    return max(1, min(n, cap) if cap > 0 else n)
+
+
 def build_hmatrix(points: np.ndarray, kernel: int, *, leaf: int = 64, eta: float = 2.0,
                   eps: float = 1e-6, eps_aca: float | None = None, keep_sigma: bool = False,
                   diag: float | None = None, length: float = 0.1, nthreads: int | None = None,
-                  kparams=None) -> HMatrix:
+                  kparams=None, progress: bool | None = None) -> HMatrix:
     """Construct the H-matrix of ``kernel`` over ``points`` (n x 3, FP64).
 
     kernel: KERNEL_LAPLACE (1/(4 pi r), diagonal 1/(4 pi h) with h the mean
     nearest-neighbour distance unless ``diag`` gives h), KERNEL_EXP
     (exp(-r/length), diagonal + ``diag`` (default 1e-3)), KERNEL_SEPARABLE.
     ACA runs at ``eps_aca`` (default eps/10), then Algorithm 1 at ``eps``.
+    With ``progress`` (default: n >= 2^19) the leaves are filled in 16 shares
+    and a line is printed after each.
     """
     L = lib()
     pts = np.ascontiguousarray(points, dtype=np.float64)
@@ -213,9 +230,18 @@ def build_hmatrix(points: np.ndarray, kernel: int, *, leaf: int = 64, eta: float
     rc = L.hmg_build_tree(pts.reshape(-1), n, leaf, eta, C.byref(handle))
     if rc != 0:
         raise RuntimeError(f"hmg_build_tree failed ({rc})")
-    nthr = nthreads if nthreads else len(os.sched_getaffinity(0))
-    rc = L.hmg_fill(handle, kernel, kparams, eps / 10 if eps_aca is None else eps_aca, eps,
-                    int(keep_sigma), nthr)
+    nthr = nthreads if nthreads else default_threads()
+    if progress is None:
+        progress = n >= 2 ** 19
+    nparts = 16 if progress else 1
+    for part in range(nparts):
+        rc = L.hmg_fill_part(handle, kernel, kparams, eps / 10 if eps_aca is None else eps_aca, eps,
+                             int(keep_sigma), nthr, part, nparts)
+        if rc != 0:
+            break
+        if progress:
+            print(f"[hmgen] n={n}: filled share {part + 1}/{nparts} of {L.hmg_num_blocks(handle)} "
+                  f"blocks, {time.perf_counter() - t0:.0f}s", flush=True)
     if rc != 0:
         L.hmg_destroy(handle)
         raise RuntimeError(f"hmg_fill failed ({rc})")

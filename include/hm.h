@@ -196,8 +196,9 @@ void hm_graph_destroy(hm_graph* g);
 hm_status hm_profile_begin(hm_matrix* A, int32_t max_calls);
 hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls);
 
-/* Launch parameters of one matrix, as text "schedule=S unroll=U order=O"
- * (any subset of the keys):
+/* Launch parameters of one matrix, as text
+ * "schedule=S unroll=U order=O persist=P" (any subset of the keys; the
+ * built-in choice is schedule=0 unroll=8 order=1 persist=0):
  *   schedule 0: column tiles, partial reduction, whole row panels;
  *   schedule 1: one grouped launch of the dense row-panel sections with the
  *               column tiles, the reduction, then the U sections;
@@ -215,7 +216,8 @@ hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls);
  * to y in two steps, so it differs from schedule 0 by rounding only.  Each
  * choice is deterministic.  hm_matrix_tune_key writes the key under which the
  * tuner stores the best choice for matrices of this kind (accumulation type,
- * storage formats present, size class) into buf (NUL-terminated, <= len). */
+ * storage formats present, size class, and whether the plan was made for
+ * several right-hand sides) into buf (NUL-terminated, <= len). */
 hm_status hm_matrix_set_launch(hm_matrix* A, const char* params);
 hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len);
 hm_status hm_matrix_tune_key(const hm_matrix* A, char* buf, size_t len);

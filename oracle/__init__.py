@@ -5,8 +5,8 @@ Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 and never calls it.
 """
 
-from .oracle import (build, hmvm, hmvm_multi, decoded_factors, round_f32, round_f16, F64, F32, F16, BF16,
+from .oracle import (build, hmvm, hmvm_multi, blocks_in_rows, decoded_factors, round_f32, round_f16, F64, F32, F16, BF16,
                      round_bf16, round_to, UNIT_ROUNDOFF, FORMAT_LIMITS, dynamic_range)
 
-__all__ = ["F64", "F32", "F16", "BF16", "build", "hmvm", "hmvm_multi", "decoded_factors", "round_f32", "round_f16",
+__all__ = ["F64", "F32", "F16", "BF16", "build", "hmvm", "hmvm_multi", "blocks_in_rows", "decoded_factors", "round_f32", "round_f16",
            "round_bf16", "round_to", "UNIT_ROUNDOFF", "FORMAT_LIMITS", "dynamic_range"]

@@ -130,35 +130,55 @@ def _load():
     return _lib
 
 
-def _table(H, factors=None):
+def blocks_in_rows(H, rows) -> np.ndarray:
+    """Indices (ascending) of the leaves whose row cluster contains one of
+    ``rows``: by the definition of the H-matrix (a sum over the leaves of
+    the block partition, Sec. 2.1), y at those rows is the sum over these
+    leaves alone."""
+    rows = np.unique(np.asarray(rows, dtype=np.int64))
+    first = np.searchsorted(rows, np.asarray(H.rb, dtype=np.int64), side="left")
+    return np.nonzero((first < rows.shape[0]) &
+                      (rows[np.minimum(first, rows.shape[0] - 1)] < np.asarray(H.re)))[0]
+
+
+def _table(H, factors=None, blocks=None):
+    """Block table for the C routines; ``blocks`` restricts it to those
+    leaf indices (then ``factors``, if given, lists only those leaves)."""
     i64 = lambda v: np.ascontiguousarray(v, dtype=np.int64)
     i32 = lambda v: np.ascontiguousarray(v, dtype=np.int32)
-    kind = i32(H.adm != 0)
-    rank = i32(np.where(H.adm != 0, H.rank, 0))
+    sel = slice(None) if blocks is None else np.asarray(blocks, dtype=np.int64)
+    adm = np.asarray(H.adm)[sel]
+    kind = i32(adm != 0)
+    rank = i32(np.where(adm != 0, np.asarray(H.rank)[sel], 0))
+    rb, re, cb, ce = (i64(np.asarray(v)[sel]) for v in (H.rb, H.re, H.cb, H.ce))
     if factors is None:
-        ap, bp, sp = (np.ascontiguousarray(p, dtype=np.uint64) for p in (H.a_ptr, H.b_ptr, H.s_ptr))
+        ap, bp, sp = (np.ascontiguousarray(np.asarray(p)[sel], dtype=np.uint64)
+                      for p in (H.a_ptr, H.b_ptr, H.s_ptr))
         keep = None
     else:
         keep = factors
         ap = np.array([f[0].ctypes.data if f[0] is not None and f[0].size else 0 for f in factors], np.uint64)
         bp = np.array([f[1].ctypes.data if f[1] is not None and f[1].size else 0 for f in factors], np.uint64)
         sp = np.array([f[2].ctypes.data if f[2] is not None and f[2].size else 0 for f in factors], np.uint64)
-    return (i64(H.rb), i64(H.re), i64(H.cb), i64(H.ce), kind, rank, ap, bp, sp, keep)
+    return (rb, re, cb, ce, kind, rank, ap, bp, sp, keep)
 
 
-def hmvm(H, x, y=None, alpha: float = 1.0, factors=None, n_rows=None, n_cols=None) -> np.ndarray:
+def hmvm(H, x, y=None, alpha: float = 1.0, factors=None, n_rows=None, n_cols=None,
+         blocks=None) -> np.ndarray:
     """y + alpha * A_H x in FP64 (returns a new array; y defaults to zero).
 
     ``H`` is any object with block-table arrays rb, re, cb, ce, adm, rank and
     per-block factor pointers a_ptr, b_ptr, s_ptr (FP64, column-major); or
     ``factors`` gives per-block (a, b, s) FP64 arrays (Fortran order) instead.
+    ``blocks`` (e.g. from blocks_in_rows) sums over those leaves only: exact
+    at the rows they cover, partial elsewhere.
     """
     L = _load()
     n_rows = H.n if n_rows is None else n_rows
     n_cols = H.n if n_cols is None else n_cols
     x = np.ascontiguousarray(x, dtype=np.float64)
     out = np.zeros(n_rows) if y is None else np.array(y, dtype=np.float64, copy=True)
-    rb, re, cb, ce, kind, rank, ap, bp, sp, keep = _table(H, factors)
+    rb, re, cb, ce, kind, rank, ap, bp, sp, keep = _table(H, factors, blocks)
     rc = L.oracle_hmvm(n_rows, n_cols, rb.shape[0], rb, re, cb, ce, kind, rank, ap, bp, sp,
                        float(alpha), x, out)
     if rc != 0:
@@ -167,13 +187,14 @@ def hmvm(H, x, y=None, alpha: float = 1.0, factors=None, n_rows=None, n_cols=Non
     return out
 
 
-def hmvm_multi(H, X, Y=None, alpha: float = 1.0, factors=None) -> np.ndarray:
-    """Column-by-column product for X (n x r, any layout)."""
+def hmvm_multi(H, X, Y=None, alpha: float = 1.0, factors=None, blocks=None) -> np.ndarray:
+    """Column-by-column product for X (n x r, any layout); ``blocks`` as in
+    hmvm."""
     L = _load()
     X = np.asfortranarray(X, dtype=np.float64)
     n, r = X.shape
     out = np.zeros((H.n, r), order="F") if Y is None else np.array(Y, dtype=np.float64, order="F", copy=True)
-    rb, re, cb, ce, kind, rank, ap, bp, sp, keep = _table(H, factors)
+    rb, re, cb, ce, kind, rank, ap, bp, sp, keep = _table(H, factors, blocks)
     rc = L.oracle_hmvm_multi(H.n, n, rb.shape[0], rb, re, cb, ce, kind, rank, ap, bp, sp,
                              float(alpha), r, X.ctypes.data, n, out.ctypes.data, H.n)
     if rc != 0:
@@ -189,13 +210,14 @@ def _fview(ptr: int, rows: int, cols: int) -> np.ndarray:
     return np.ctypeslib.as_array(buf).reshape(cols, rows).T
 
 
-def decoded_factors(H, sigma_dtype: int = F32):
+def decoded_factors(H, sigma_dtype: int = F32, blocks=None):
     """Per-block FP64 copies of the factors after rounding to their storage
     formats (groups of columns per Sec. 3.3; one format per dense block).
     Singular values are rounded to ``sigma_dtype``.  Returns a list of
-    (a, b, s) Fortran-ordered FP64 arrays usable as ``factors=``."""
+    (a, b, s) Fortran-ordered FP64 arrays usable as ``factors=`` (for the
+    leaves ``blocks`` only, if given, in that order)."""
     out = []
-    for i in range(H.rb.shape[0]):
+    for i in (range(H.rb.shape[0]) if blocks is None else blocks):
         m = int(H.re[i] - H.rb[i])
         nb = int(H.ce[i] - H.cb[i])
         dts = H.group_dtype[i]

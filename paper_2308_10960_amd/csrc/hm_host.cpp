@@ -481,20 +481,23 @@ static bool parse_launch(const char* text, LaunchParams& lp) {
   return true;
 }
 
-static std::string tune_key(int acc, const size_t* bytes_by_dtype, int64_t n_rows) {
+// Kind of matrix a tuned choice applies to: accumulation type, storage
+// formats present, size class, and "-batch" for plans made for several
+// right-hand sides (their products run the multi-right-hand-side kernels).
+static std::string tune_key(int acc, const size_t* bytes_by_dtype, int64_t n_rows, int max_nrhs) {
   int mask = 0;
   for (int d = 0; d < 4; ++d) if (bytes_by_dtype[d]) mask |= 1 << d;
   int lg = 0;
   while ((int64_t(1) << (lg + 1)) <= n_rows) ++lg;
   char buf[64];
-  std::snprintf(buf, sizeof buf, "acc%d-fmt%d-n2^%d", acc, mask, lg);
+  std::snprintf(buf, sizeof buf, "acc%d-fmt%d-n2^%d%s", acc, mask, lg, max_nrhs > 1 ? "-batch" : "");
   return buf;
 }
 
 void read_tune_cache(hm_plan* P) {
   FILE* f = std::fopen(P->tune_path.c_str(), "r");
   if (!f) return;
-  const std::string key = tune_key(P->opts.acc_dtype, P->bytes_by_dtype, P->n_rows);
+  const std::string key = tune_key(P->opts.acc_dtype, P->bytes_by_dtype, P->n_rows, P->opts.max_nrhs);
   char line[512];
   while (std::fgets(line, sizeof line, f)) {
     std::string l(line);
@@ -633,8 +636,9 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
 
 static const double* fac(const double* const* arr, int64_t i) { return arr ? arr[i] : nullptr; }
 
-hm_status pack_store(const hm_plan* P, const double* const* a, const double* const* bf,
-                     const double* const* s, uint8_t* buf) {
+// Header and descriptor tables: bytes [0, meta_bytes) of the store.
+hm_status pack_meta(const hm_plan* P, const double* const* a, const double* const* bf,
+                    const double* const* s, uint8_t* buf) {
   const StoreHeader& H = P->hdr;
   std::memcpy(buf, &H, sizeof H);
   const int acc_sz = P->opts.acc_dtype == HM_F64 ? 8 : 4;
@@ -770,14 +774,42 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
       }
     }
   }
+  return HM_OK;
+}
 
-  // factor data, in parallel over panels
-  const size_t nrp = P->rps.size(), ncp = P->cps.size();
-  std::atomic<size_t> next{0};
+size_t pack_jobs_count(const hm_plan* P) { return P->rps.size() + P->cps.size(); }
+
+// Store bytes [lo, hi) of packing job j (row panels, then column panels):
+// its sections, which are contiguous; jobs follow each other without gaps.
+void pack_job_range(const hm_plan* P, size_t j, int64_t* lo, int64_t* hi) {
+  const size_t nrp = P->rps.size();
+  auto span = [&](auto& secs, auto bytes_of) {
+    if (secs.empty()) { *lo = *hi = -1; return; }
+    *lo = secs.front().data_off;
+    *hi = align_up(secs.back().data_off + bytes_of(secs.back()), kAlign);
+  };
+  if (j < nrp) {
+    const RowPanelHost& R = P->rps[j];
+    span(R.secs, [&](const RowSectionHost& S) { return (int64_t)S.ngroups * R.m * 16; });
+  } else {
+    const ColPanelHost& Cp = P->cps[j - nrp];
+    span(Cp.secs, [&](const ColSectionHost& S) {
+      return (int64_t)S.ld * Cp.nrows * dtype_size(S.dtype);
+    });
+  }
+}
+
+// Factor data of packing jobs [j_begin, j_end), in parallel; store byte o
+// goes to out[o - out_off] (out covers the jobs' byte ranges).
+void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf, size_t j_begin,
+               size_t j_end, uint8_t* out, int64_t out_off) {
+  auto at = [&](int64_t o) { return out + (o - out_off); };
+  const size_t nrp = P->rps.size();
+  std::atomic<size_t> next{j_begin};
   auto worker = [&]() {
     for (;;) {
       size_t job = next.fetch_add(1);
-      if (job >= nrp + ncp) return;
+      if (job >= j_end) return;
       if (job < nrp) {
         const RowPanelHost& R = P->rps[job];
         for (auto& sg : R.segs) {
@@ -788,7 +820,7 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
           const int64_t mb = b.row_end - b.row_begin;
           const int64_t r_local = R.row0 - b.row_begin;
           const double* A = a[sg.block];
-          uint8_t* base = buf + S->data_off;
+          uint8_t* base = at(S->data_off);
           for (int32_t c = 0; c < sg.ncols; ++c) {
             const int32_t sc = sg.seccol + c;
             const int32_t g = sc / G, cc = sc % G;
@@ -810,17 +842,28 @@ hm_status pack_store(const hm_plan* P, const double* const* a, const double* con
           for (int32_t c = 0; c < sg.ncols; ++c) {
             const double* col = V + (int64_t)(sg.c_first + c) * nbk + c_local;
             for (int32_t i = 0; i < Cp.nrows; ++i)
-              put(buf + col_elem_offset(*S, Cp.nrows, i, sg.seccol + c), S->dtype, col[i]);
+              put(at(col_elem_offset(*S, Cp.nrows, i, sg.seccol + c)), S->dtype, col[i]);
           }
         }
       }
     }
   };
   unsigned nthr = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) {    // the process's CPU share, if stated
+    const int v = std::atoi(e);
+    if (v > 0) nthr = std::min(nthr, (unsigned)v);
+  }
+  nthr = (unsigned)std::min<size_t>(nthr, std::max<size_t>(1, j_end - j_begin));
   std::vector<std::thread> th;
   for (unsigned t = 1; t < nthr; ++t) th.emplace_back(worker);
   worker();
   for (auto& t : th) t.join();
+}
+
+hm_status pack_store(const hm_plan* P, const double* const* a, const double* const* bf,
+                     const double* const* s, uint8_t* buf) {
+  if (hm_status st = pack_meta(P, a, bf, s, buf)) return st;
+  pack_jobs(P, a, bf, 0, pack_jobs_count(P), buf, 0);
   return HM_OK;
 }
 
@@ -913,6 +956,82 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
   return fail(HM_EINVAL, "which must be 0 or 1");
 }
 
+// Bytes of one upload window: HM_UPLOAD_WINDOW_BYTES if set (>= 4096),
+// else 256 MiB.
+static size_t upload_window_bytes() {
+  if (const char* e = std::getenv("HM_UPLOAD_WINDOW_BYTES")) {
+    const long long v = std::atoll(e);
+    if (v >= 4096) return (size_t)v;
+  }
+  return (size_t)256 << 20;
+}
+
+// Factor data of the store, packed window by window into two pinned host
+// buffers and copied on `hs` while the next window is packed.
+static hm_status upload_factor_data(const hm_plan* p, const double* const* a, const double* const* bf,
+                                    uint8_t* d_store, hipStream_t hs) {
+  const size_t njobs = pack_jobs_count(p);
+  int64_t max_job = 0;
+  for (size_t j = 0; j < njobs; ++j) {
+    int64_t lo, hi;
+    pack_job_range(p, j, &lo, &hi);
+    max_job = std::max(max_job, hi - lo);
+  }
+  const size_t wbytes = std::max(upload_window_bytes(), (size_t)max_job);
+  uint8_t* stage[2] = {nullptr, nullptr};
+  hipEvent_t done[2] = {nullptr, nullptr};
+  hm_status st = HM_OK;
+  for (int b = 0; b < 2 && st == HM_OK; ++b) {
+    if (hipHostMalloc((void**)&stage[b], wbytes, hipHostMallocDefault) != hipSuccess) {
+      stage[b] = nullptr;
+      st = fail(HM_ENOMEM, "pinned staging allocation of %zu bytes failed", wbytes);
+    } else if (hipEventCreateWithFlags(&done[b], hipEventDisableTiming) != hipSuccess) {
+      done[b] = nullptr;
+      st = fail(HM_EDEVICE, "event creation failed");
+    }
+  }
+  int64_t cursor = (int64_t)p->meta_bytes;
+  size_t j = 0;
+  for (int k = 0; st == HM_OK && j < njobs; ++k) {
+    // the window: whole jobs [j, j2) covering store bytes [lo, hi)
+    const int64_t lo = cursor;
+    int64_t hi = cursor;
+    size_t j2 = j;
+    for (; j2 < njobs; ++j2) {
+      int64_t l, h;
+      pack_job_range(p, j2, &l, &h);
+      if (l < 0) continue;                         // job without data
+      if (l != hi) { st = fail(HM_EINVAL, "internal error: store layout is not contiguous"); break; }
+      if (hi > lo && h - lo > (int64_t)wbytes) break;
+      hi = h;
+    }
+    if (st != HM_OK) break;
+    const int b = k & 1;
+    if (k >= 2 && hipEventSynchronize(done[b]) != hipSuccess) {
+      st = fail(HM_EDEVICE, "upload copy failed");
+      break;
+    }
+    std::memset(stage[b], 0, (size_t)(hi - lo));
+    pack_jobs(p, a, bf, j, j2, stage[b], lo);
+    if (hi > lo && (hipMemcpyAsync(d_store + lo, stage[b], (size_t)(hi - lo), hipMemcpyHostToDevice, hs) !=
+                        hipSuccess ||
+                    hipEventRecord(done[b], hs) != hipSuccess)) {
+      st = fail(HM_EDEVICE, "upload copy failed: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    cursor = hi;
+    j = j2;
+  }
+  if (hipStreamSynchronize(hs) != hipSuccess && st == HM_OK) st = fail(HM_EDEVICE, "upload copy failed");
+  if (st == HM_OK && cursor != (int64_t)p->store_bytes)
+    st = fail(HM_EINVAL, "internal error: packed %lld of %zu store bytes", (long long)cursor, p->store_bytes);
+  for (int b = 0; b < 2; ++b) {
+    if (done[b]) (void)hipEventDestroy(done[b]);
+    if (stage[b]) (void)hipHostFree(stage[b]);
+  }
+  return st;
+}
+
 hm_status hm_upload(const hm_plan* p, const double* const* a, const double* const* bf,
                     const double* const* s, void* d_store, size_t store_bytes, void* stream,
                     hm_matrix** out) {
@@ -925,20 +1044,29 @@ hm_status hm_upload(const hm_plan* p, const double* const* a, const double* cons
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
     return fail(HM_EDEVICE, "no usable HIP device");
-  uint8_t* buf = (uint8_t*)std::calloc(p->store_bytes, 1);
-  if (!buf) return fail(HM_ENOMEM, "host staging allocation of %zu bytes failed", p->store_bytes);
+  hipStream_t hs = (hipStream_t)stream;
+  // header and tables (validates the factor pointers), then the factor data
+  {
+    std::vector<uint8_t> meta;
+    hm_status st;
+    try {
+      meta.assign(p->meta_bytes, 0);
+      st = pack_meta(p, a, bf, s, meta.data());
+    } catch (...) {
+      st = fail(HM_ENOMEM, "packing failed");
+    }
+    if (st) return st;
+    hipError_t e = hipMemcpyAsync(d_store, meta.data(), p->meta_bytes, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return fail(HM_EDEVICE, "upload copy failed: %s", hipGetErrorString(e));
+  }
   hm_status st;
   try {
-    st = pack_store(p, a, bf, s, buf);
+    st = upload_factor_data(p, a, bf, (uint8_t*)d_store, hs);
   } catch (...) {
     st = fail(HM_ENOMEM, "packing failed");
   }
-  if (st) { std::free(buf); return st; }
-  hipStream_t hs = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(d_store, buf, p->store_bytes, hipMemcpyHostToDevice, hs);
-  if (e == hipSuccess) e = hipStreamSynchronize(hs);
-  std::free(buf);
-  if (e != hipSuccess) return fail(HM_EDEVICE, "upload copy failed: %s", hipGetErrorString(e));
+  if (st) return st;
   auto* M = new (std::nothrow) hm_matrix();
   if (!M) return fail(HM_ENOMEM, "host allocation failed");
   M->hdr = p->hdr;
@@ -1131,7 +1259,8 @@ hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len) {
 
 hm_status hm_matrix_tune_key(const hm_matrix* A, char* buf, size_t len) {
   if (!A || !buf || len == 0) return fail(HM_EINVAL, "NULL argument");
-  std::snprintf(buf, len, "%s", tune_key(A->acc_dtype, A->bytes_by_dtype, A->hdr.n_rows).c_str());
+  std::snprintf(buf, len, "%s",
+                tune_key(A->acc_dtype, A->bytes_by_dtype, A->hdr.n_rows, A->max_nrhs).c_str());
   return ok();
 }
 

@@ -24,7 +24,7 @@ namespace hm {
 struct LaunchParams {
   int schedule = 0;
   int row_unroll = 8;
-  int order = 0;
+  int order = 1;
   int persist = 0;
 };
 

@@ -125,3 +125,19 @@ def test_precision_groups_are_well_formed():
     # FP16 carries the trailing singular vectors of many blocks
     has16 = [hm.DT_F16 in H.group_dtype[i][:H.ngroups[i]] for i in np.flatnonzero(lr)]
     assert np.mean(has16) > 0.5
+
+
+def test_fill_in_shares_equals_fill_at_once(capsys):
+    """Filling the leaves in 16 shares (with progress lines) gives the same
+    ranks and factors, bit for bit, as one fill."""
+    pts = hmgen.cube_points(3000, 0)
+    H1 = hm.build_hmatrix(pts, hm.KERNEL_EXP, eps=1e-6, progress=False)
+    H2 = hm.build_hmatrix(pts, hm.KERNEL_EXP, eps=1e-6, progress=True)
+    assert capsys.readouterr().out.count("filled share") == 16
+    np.testing.assert_array_equal(H1.rank, H2.rank)
+    for i in range(H1.nblocks):
+        for f1, f2 in zip(H1.factors(i), H2.factors(i)):
+            if f1 is None:
+                assert f2 is None
+            else:
+                np.testing.assert_array_equal(f1, f2)

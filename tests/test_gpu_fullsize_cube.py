@@ -1,0 +1,86 @@
+"""Full-size batched product: the n = 2^20 uniform-cube exponential-kernel
+matrix (leaf 64, eta 2, eps 1e-6, FP32 factors) with 32 Gaussian right-hand
+sides through hm_mvm_batch, in the launch configuration the benchmark times
+(parameters from the tuner's candidate list; they change no bit).
+
+The oracle cannot afford all n rows for 32 right-hand sides, so it computes
+sampled rows exactly: y at a row is the sum over the leaves whose row cluster
+contains it (blocks_in_rows), with the factors rounded to FP32 as stored
+(decoded oracle) and unrounded (FP64 truth).  Whole leaf clusters of rows are
+sampled, plus the first and last row.
+
+Constructing the matrix takes minutes of host time and about 130 GB of host
+memory, so the test runs only with HM_TEST_CUBE1M=1.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import hmgen
+import oracle
+from paper_2308_10960_amd import hm, DeviceHMatrix, tune
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("HM_TEST_CUBE1M") != "1",
+                                 reason="n=2^20 cube: minutes of host construction and ~130 GB of "
+                                        "host memory; set HM_TEST_CUBE1M=1")]
+U32 = 2.0 ** -24
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def test_cube1m_batched_sampled_rows():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("building cube1m")
+    H = hmgen.build_preset("cube1m")
+    say("built", H.stats())
+    R = 32
+    D = DeviceHMatrix(H, hm.HM_F32, max_nrhs=R)
+    say("uploaded", D.info["store_bytes"], "work", D.work_bytes)
+    Xh = hmgen.gaussian_block(H.n, R, seed=hmgen.presets.SEED_RHS).astype(np.float32)
+    Xd = torch.from_numpy(np.ascontiguousarray(Xh.T)).cuda()
+    outs = {}
+    for c in tune.BATCH_CANDIDATES:
+        hm.hm_matrix_set_launch(D.handle, c)
+        Yd = torch.zeros_like(Xd)
+        hm.hm_mvm_batch(D.handle, R, 1.0, Xd, H.n, Yd, H.n, D.work, D.work.numel())
+        torch.cuda.synchronize()
+        outs[c] = Yd.cpu().numpy().T
+        say("gpu done", c)
+    Y = outs[tune.BATCH_CANDIDATES[0]]
+    for c in tune.BATCH_CANDIDATES[1:]:
+        np.testing.assert_array_equal(outs[c], Y)
+    assert np.all(np.isfinite(Y))
+    D.close()
+
+    rng = np.random.default_rng(11)
+    leaves = rng.choice(H.n // 64, 12, replace=False)
+    rows = np.unique(np.concatenate([[0, H.n - 1]] + [np.arange(64 * l, 64 * l + 64) for l in leaves]))
+    blk = oracle.blocks_in_rows(H, rows)
+    say(f"oracle on {rows.size} rows, {blk.size} leaves")
+    X = Xh.astype(np.float64)
+    dec = oracle.decoded_factors(H, sigma_dtype=oracle.F32, blocks=blk)
+    ref = oracle.hmvm_multi(H, X, factors=dec, blocks=blk)[rows]
+    truth = oracle.hmvm_multi(H, X, blocks=blk)[rows]
+    absf = [(np.abs(a), None if b is None else np.abs(b), s) for a, b, s in dec]
+    scale = oracle.hmvm_multi(H, np.abs(X), factors=absf, blocks=blk)[rows]
+    Ys = Y[rows]
+    # rigorous elementwise FP32 bound (K = all summands of a row, nested)
+    K = H.n + int(np.sum(np.where(H.adm[blk] != 0, H.rank[blk], 0)))
+    gam = K * U32 / (1 - K * U32)
+    assert np.all(np.abs(Ys - ref) <= gam * scale)
+    rel_dec = np.linalg.norm(Ys - ref) / np.linalg.norm(ref)
+    rel_truth = np.linalg.norm(Ys - truth) / np.linalg.norm(truth)
+    worst = float(np.max(np.abs(Ys - ref) / scale))
+    say(f"cube1m: rel vs decoded {rel_dec:.3e}, rel vs FP64 truth {rel_truth:.3e}, "
+        f"max err/scale {worst:.3e}")
+    assert rel_dec <= 1e-5
+    assert rel_truth <= 1e-5

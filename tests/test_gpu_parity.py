@@ -95,14 +95,22 @@ def test_sphere4k_f64(sphere4k):
     D.close()
 
 
-def test_store_upload_matches_host_packing(sphere4k):
-    H = sphere4k
-    D = DeviceHMatrix(H, hm.HM_F64)
-    buf = np.zeros(D.info["store_bytes"], np.uint8)
-    hm.hm_pack_host(D.plan, H.a_ptr, H.b_ptr, None, buf)
-    dev = D.store.cpu().numpy()
-    np.testing.assert_array_equal(dev, buf)
-    D.close()
+@pytest.mark.parametrize("window", [None, 4096, 65536])
+def test_store_upload_matches_host_packing(sphere4k, window, monkeypatch):
+    """The device store equals the host packing byte for byte, also when the
+    upload streams the factor data in many small windows (the window grows
+    to the largest packing job where that is larger)."""
+    if window is not None:
+        monkeypatch.setenv("HM_UPLOAD_WINDOW_BYTES", str(window))
+    for name, H, acc in [("sphere4k", sphere4k, hm.HM_F64),
+                         ("sphere4k_mixed", hmgen.build_preset("sphere4k_mixed"), hm.HM_F32)]:
+        say("upload", name, window)
+        D = DeviceHMatrix(H, acc)
+        buf = np.zeros(D.info["store_bytes"], np.uint8)
+        hm.hm_pack_host(D.plan, H.a_ptr, H.b_ptr, H.s_ptr if H.keep_sigma else None, buf)
+        dev = D.store.cpu().numpy()
+        np.testing.assert_array_equal(dev, buf)
+        D.close()
 
 
 @pytest.mark.parametrize("case", ["eta0", "one_block", "tiny5", "tiny1"])

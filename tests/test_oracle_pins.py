@@ -157,6 +157,33 @@ def test_multi_rhs_is_columnwise(sphere4k):
         np.testing.assert_array_equal(Y[:, c], oracle.hmvm(H, X[:, c]))
 
 
+def test_sampled_rows_from_covering_leaves(sphere4k):
+    """Rows of y from the leaves that cover them: against the densely
+    assembled matrix at those rows (P2), and bit for bit the full sum there
+    (same leaves in the same order); the subset is exactly the leaves that
+    touch a sampled row."""
+    H = sphere4k
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([[0, H.n - 1], rng.choice(H.n, 40, replace=False)])
+    blk = oracle.blocks_in_rows(H, rows)
+    touch = [i for i in range(H.nblocks) if np.any((rows >= H.rb[i]) & (rows < H.re[i]))]
+    np.testing.assert_array_equal(blk, touch)
+    assert 0 < blk.size < H.nblocks
+    X = hmgen.gaussian_block(H.n, 3)
+    part = oracle.hmvm_multi(H, X, blocks=blk)
+    full = oracle.hmvm_multi(H, X)
+    np.testing.assert_array_equal(part[rows], full[rows])
+    At = assemble(H)
+    ref = At[rows] @ X
+    assert np.linalg.norm(part[rows] - ref) <= 1e-13 * np.linalg.norm(ref)
+    dec_all = oracle.decoded_factors(H, sigma_dtype=oracle.F64)
+    dec_sub = oracle.decoded_factors(H, sigma_dtype=oracle.F64, blocks=blk)
+    for q, i in enumerate(blk):
+        np.testing.assert_array_equal(dec_sub[q][0], dec_all[i][0])
+    np.testing.assert_array_equal(oracle.hmvm(H, X[:, 0], factors=dec_sub, blocks=blk)[rows],
+                                  oracle.hmvm(H, X[:, 0], factors=dec_all)[rows])
+
+
 def test_decoded_oracle_within_storage_accuracy():
     H = hmgen.build_preset("sphere4k_mixed")
     tol = hmgen.presets.MIXED_TOL / 2
