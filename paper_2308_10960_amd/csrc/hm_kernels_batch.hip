@@ -7,8 +7,10 @@
 //             products per column chunk;
 //  k_reduce_b t_b = s_b * (sum of the partials in chunk order) per column;
 //  k_row_b    near field and far field, phase 2: row panels as the A operand
-//             of v_mfma_f32_32x32x1_2b_f32, sources staged in LDS, a
-//             fixed-order four-wave reduction, one update of Y per row.
+//             of v_mfma_f32_32x32x2_f32 (column pairs exchanged between
+//             lane halves by v_permlane32_swap), source rows as the B
+//             operand straight from memory, a fixed-order four-wave
+//             reduction, one update of Y per row.
 // Every sum has a fixed order, so results are bitwise reproducible and do not
 // depend on the other right-hand sides of the batch.
 
@@ -40,6 +42,9 @@ typedef float f32x32 __attribute__((ext_vector_type(32)));
 __device__ __forceinline__ f32x32 mfma32(float a, float b, f32x32 c) {
   return __builtin_amdgcn_mfma_f32_32x32x1f32(a, b, c, 0, 0, 0);
 }
+
+// Column (right-hand side within a group of 32) of the results in lane l.
+__device__ __forceinline__ int l32of(int lane) { return lane & 31; }
 
 // Row (0..63) of the 64-row A operand held by result register v of lane l.
 __device__ __forceinline__ int mfma_row(int lane, int v) {
@@ -212,13 +217,14 @@ struct RowBArgs {
   int32_t n_cols, nrhs;
 };
 
-template <int DT>
-__device__ __forceinline__ void decode_group(u32x4 r, float* v) {
-  if constexpr (DT == HM_F32) {
+// Decode one 16-byte group of storage format dt (FP32: 4 values; FP16 or
+// BF16: 8) into v.
+__device__ __forceinline__ void decode_any(int dt, u32x4 r, float (&v)[8]) {
+  if (dt == HM_F32) {
     const f32x4 f = __builtin_bit_cast(f32x4, r);
 #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] = f[c];
-  } else if constexpr (DT == HM_F16) {
+  } else if (dt == HM_F16) {
     const f16x8 h = __builtin_bit_cast(f16x8, r);
 #pragma unroll
     for (int c = 0; c < 8; ++c) v[c] = (float)h[c];
@@ -231,113 +237,174 @@ __device__ __forceinline__ void decode_group(u32x4 r, float* v) {
   }
 }
 
-// Groups g_lo + wave, + 4, ... of one section; U groups per step with the
-// next step's loads issued before this step's matrix-core work.
-template <int NH, int DT>
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// D (32 x 32) += A (32 x 2) B (2 x 32) on v_mfma_f32_32x32x2_f32: lane l
+// gives A[l % 32][l / 32] and B[l / 32][l % 32]; D[i][j] is in lane
+// j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
+__device__ __forceinline__ f32x16 mfma32x2(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// Row (0..31) of D held by register v of lane l in mfma32x2.
+__device__ __forceinline__ int mfma32x2_row(int lane, int v) {
+  return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+}
+
+// One section of a row panel for the groups g = wave, wave + 4, ...: per
+// group a 16-byte load of the panel (lane = row, G columns).  Columns go in
+// pairs: v_permlane32_swap turns the pair (c, c+1) into the A operands of
+// rows 0-31 (lanes 0-31: column c, lanes 32-63: column c+1) and of rows
+// 32-63; one load brings the two source rows (lanes 0-31: the source of
+// column c, lanes 32-63: that of column c+1) as the B operand.  Panels of at
+// most 32 rows skip the second MFMA.  Groups go in steps of U; the loads of
+// the next step are in flight while this step's MFMAs run, and the source
+// slots of the step after that are read (scalar loads) meanwhile.
+template <int NH, int U>
 __device__ __forceinline__ void rowb_section(const RowBArgs& a, const RowSection& S, int m,
-                                             int g_lo, int g_hi, const float* zs, int lane,
-                                             int wave, f32x32 (&acc)[NH]) {
-  constexpr int G = group_width(DT), RS = 32 * NH, U = 4;
+                                             const int32_t* src, int lane, int wave,
+                                             f32x16 (&top)[NH], f32x16 (&bot)[NH]) {
+  constexpr int RS = 32 * NH;
+  const int dt = S.dtype, G = group_width(dt);
   const u32x4* p = reinterpret_cast<const u32x4*>(a.store + S.data_off) + lane;
-  const bool act = lane < m;
-  u32x4 nxt[U];
-  int g = g_lo + wave;
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int gg = g + 4 * u;
-    nxt[u] = (act && gg < g_hi) ? ld16(p + (size_t)gg * m) : (u32x4)(0u);
-  }
-  for (; g < g_hi; g += 4 * U) {
-    u32x4 cur[U];
+  const int32_t* sc = src + S.col0;                // source slot of every column of the section
+  const bool act = lane < m, two = m > 32;
+  const int ng = S.ngroups, l32 = lane & 31, hi = lane >> 5;
+  u32x4 an[U];
+  float bn[U][4][NH];                              // B operands of up to 4 column pairs
+  int sn[U][8];                                    // source slots of the step after this one
+  auto load_slots = [&](int g0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      cur[u] = nxt[u];
-      const int gg = g + 4 * (u + U);
-      nxt[u] = (act && gg < g_hi) ? ld16(p + (size_t)gg * m) : (u32x4)(0u);
+      const int gg = g0 + 4 * u;
+      if (gg >= ng) break;                          // uniform across the wave
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < G) sn[u][c] = sc[gg * G + c];
     }
+  };
+  auto srow = [&](int sl) {
+    return sl < a.n_cols ? a.xr + (size_t)sl * RS : a.t + (size_t)(sl - a.n_cols) * RS;
+  };
+  auto issue = [&](int g0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int gg = g + 4 * u;
-      if (gg >= g_hi) break;                    // uniform across the wave
-      float v[G];
-      decode_group<DT>(cur[u], v);
-      const float* zrow = zs + (size_t)gg * G * RS + (lane & 31);
+      const int gg = g0 + 4 * u;
+      if (gg >= ng) break;                          // uniform across the wave
+      an[u] = act ? ld16(p + (size_t)gg * m) : (u32x4)(0u);
 #pragma unroll
-      for (int c = 0; c < G; ++c)
+      for (int q = 0; q < 4; ++q) {
+        if (2 * q < G) {
+          const float* r0 = srow(sn[u][2 * q]);
+          const float* r1 = srow(sn[u][2 * q + 1]);
+          const float* row = hi ? r1 : r0;
 #pragma unroll
-        for (int h = 0; h < NH; ++h) acc[h] = mfma32(v[c], zrow[c * RS + 32 * h], acc[h]);
+          for (int h = 0; h < NH; ++h) bn[u][q][h] = row[32 * h + l32];
+        }
+      }
+    }
+  };
+  load_slots(wave);
+  issue(wave);
+  load_slots(wave + 4 * U);
+  for (int g = wave; g < ng; g += 4 * U) {
+    u32x4 ac[U];
+    float bc[U][4][NH];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ac[u] = an[u];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) bc[u][q][h] = bn[u][q][h];
+    }
+    issue(g + 4 * U);
+    load_slots(g + 8 * U);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (g + 4 * u >= ng) break;                   // uniform across the wave
+      float v[8];
+      decode_any(dt, ac[u], v);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (2 * q < G) {
+          const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * q]),
+                                                           __float_as_uint(v[2 * q + 1]), false, false);
+          const float at = __uint_as_float(sw[0]), ab = __uint_as_float(sw[1]);
+#pragma unroll
+          for (int h = 0; h < NH; ++h) {
+            top[h] = mfma32x2(at, bc[u][q][h], top[h]);
+            if (two) bot[h] = mfma32x2(ab, bc[u][q][h], bot[h]);
+          }
+        }
+      }
     }
   }
 }
 
+// Groups per pipeline step in k_row_b (2 measured fastest; deeper steps
+// cost occupancy).
+constexpr int kRowBStep = 2;
+
+// One workgroup per row panel: the four waves take interleaved groups of
+// every section, then their sums are added in a fixed order through LDS
+// ((w0 + w2) + (w1 + w3)) and each row of Y is updated once.
 template <int NH>
 __global__ __launch_bounds__(256) void k_row_b(RowBArgs a) {
-  extern __shared__ float lds[];
-  // CAPB = 256 source columns per LDS chunk; TPC threads per column, CPP columns per pass
-  constexpr int RS = 32 * NH, CAPB = 256, TPC = RS / 4, CPP = 256 / TPC;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int RS = 32 * NH;
+  __shared__ float red[2 * 64 * RS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int pi = panel_of(a.order, a.n_panels, blockIdx.x);
   if (pi < 0) return;                               // uniform: whole workgroup
   const RowPanel P = a.rp[pi];
-  f32x32 acc[NH];
+  f32x16 top[NH], bot[NH];
 #pragma unroll
-  for (int h = 0; h < NH; ++h) acc[h] = (f32x32)(0.f);
+  for (int h = 0; h < NH; ++h) top[h] = bot[h] = (f32x16)(0.f);
   const int32_t* src = a.src + P.src_off;
-  for (int c_lo = 0; c_lo < P.ncols; c_lo += CAPB) {
-    const int c_hi = min(P.ncols, c_lo + CAPB);
-    // stage source rows: TPC threads per column, 16 bytes each; all loads of
-    // a thread are issued before its LDS writes
-    {
-      constexpr int PASSES = CAPB / CPP;
-      f32x4 val[PASSES];
-      const int q = tid % TPC, cq = tid / TPC;
-#pragma unroll
-      for (int ps = 0; ps < PASSES; ++ps) {
-        const int c = c_lo + ps * CPP + cq;
-        val[ps] = (f32x4)(0.f);
-        if (c < c_hi) {
-          const int s = src[c];
-          const float* row = s < a.n_cols ? a.xr + (size_t)s * RS : a.t + (size_t)(s - a.n_cols) * RS;
-          val[ps] = *reinterpret_cast<const f32x4*>(row + 4 * q);
-        }
-      }
-#pragma unroll
-      for (int ps = 0; ps < PASSES; ++ps) {
-        const int c = c_lo + ps * CPP + cq;
-        if (c < c_hi) *reinterpret_cast<f32x4*>(lds + (size_t)(c - c_lo) * RS + 4 * q) = val[ps];
-      }
-    }
-    __syncthreads();
-    for (int qs = 0; qs < P.nsec; ++qs) {
-      const RowSection S = a.rs[P.sec0 + qs];
-      const int G = group_width(S.dtype);
-      const int g_lo = max(0, c_lo - S.col0) / G;
-      const int g_hi = min(S.ngroups, max(0, c_hi - S.col0) / G);
-      if (g_hi <= g_lo) continue;
-      const float* z = lds + (ptrdiff_t)(S.col0 - c_lo) * RS;
-      switch (S.dtype) {
-        case HM_F32: rowb_section<NH, HM_F32>(a, S, P.m, g_lo, g_hi, z, lane, wave, acc); break;
-        case HM_F16: rowb_section<NH, HM_F16>(a, S, P.m, g_lo, g_hi, z, lane, wave, acc); break;
-        case HM_BF16: rowb_section<NH, HM_BF16>(a, S, P.m, g_lo, g_hi, z, lane, wave, acc); break;
-        default: break;
-      }
-    }
-    __syncthreads();
+  for (int qs = 0; qs < P.nsec; ++qs) {
+    const RowSection S = a.rs[P.sec0 + qs];
+    if (S.dtype != HM_F64) rowb_section<NH, kRowBStep>(a, S, P.m, src, lane, wave, top, bot);
   }
-  // fixed-order reduction of the four waves through LDS, then one update of Y
+  // fixed-order sum of the four waves through LDS: waves 2 and 3 store,
+  // waves 0 and 1 add (w0 + w2, w1 + w3), wave 1 stores, wave 0 adds and
+  // stores the panel's sums; then every thread updates rows of Y (row-contiguous)
+  const int l32 = lane & 31;
+  auto put = [&](int slot) {
 #pragma unroll
-  for (int h = 0; h < NH; ++h)
+    for (int h = 0; h < NH; ++h)
 #pragma unroll
-    for (int v = 0; v < 32; ++v)
-      lds[(size_t)(wave * 64 + mfma_row(lane, v)) * RS + h * 32 + (lane & 31)] = acc[h][v];
+      for (int v = 0; v < 16; ++v) {
+        const int r = mfma32x2_row(lane, v);
+        red[(size_t)(slot * 64 + r) * RS + h * 32 + l32] = top[h][v];
+        red[(size_t)(slot * 64 + 32 + r) * RS + h * 32 + l32] = bot[h][v];
+      }
+  };
+  auto add = [&](int slot) {
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = mfma32x2_row(lane, v);
+        top[h][v] += red[(size_t)(slot * 64 + r) * RS + h * 32 + l32];
+        bot[h][v] += red[(size_t)(slot * 64 + 32 + r) * RS + h * 32 + l32];
+      }
+  };
+  if (wave >= 2) put(wave - 2);
+  __syncthreads();
+  if (wave < 2) add(wave);
+  __syncthreads();
+  if (wave == 1) put(1);
+  __syncthreads();
+  if (wave == 0) {
+    add(1);
+    put(0);
+  }
   __syncthreads();
   for (int e = tid; e < 64 * RS; e += 256) {
     const int R = e & 63, j = e >> 6;
     if (R < P.m && j < a.nrhs) {
-      const float s = (lds[(size_t)R * RS + j] + lds[(size_t)(64 + R) * RS + j]) +
-                      (lds[(size_t)(128 + R) * RS + j] + lds[(size_t)(192 + R) * RS + j]);
       float* yp = a.Y + (size_t)j * a.ldy + P.row0 + R;
-      *yp += a.alpha * s;
+      *yp += a.alpha * red[(size_t)R * RS + j];
     }
   }
 }
@@ -393,14 +460,11 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
                 xcd ? nullptr : reinterpret_cast<const int32_t*>(st + h.off_row_order), h.n_row_panels,
                 reinterpret_cast<const int32_t*>(st + h.off_row_src),
                 xr, t, Yc, ldy, (float)alpha, (int32_t)h.n_cols, nr};
-    // 256 rows of RS floats: the 256-column source chunk, reused for the
-    // 4 waves x 64 rows reduction
-    const size_t lds = (size_t)RS * 256 * sizeof(float);
     const unsigned grid = (unsigned)panel_items(xcd, h.n_row_panels);
     if (RH == 1)
-      hipLaunchKernelGGL(k_row_b<1>, dim3(grid), dim3(256), lds, s, ra);
+      hipLaunchKernelGGL(k_row_b<1>, dim3(grid), dim3(256), 0, s, ra);
     else
-      hipLaunchKernelGGL(k_row_b<2>, dim3(grid), dim3(256), lds, s, ra);
+      hipLaunchKernelGGL(k_row_b<2>, dim3(grid), dim3(256), 0, s, ra);
   }
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError();
