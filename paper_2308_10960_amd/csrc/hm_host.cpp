@@ -303,7 +303,7 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
       };
   P->binfo.assign(nb, BlockInfo{});
   P->chunk_off.assign(nb + 1, 0);
-  std::vector<int32_t> lr_large, lr_small;
+  std::vector<int32_t> lr_large, lr_multi, lr_single;
   {
     std::map<std::pair<int64_t, int64_t>, std::vector<int32_t>> memo;   // sigma -> chunk list
     for (int64_t i = 0; i < nb; ++i) {
@@ -321,17 +321,23 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
       P->chunk_off[i + 1] = (int64_t)P->chunk_list.size();
       BlockInfo& bi = P->binfo[i];
       bi.nseg = (int32_t)it->second.size();
-      (bi.nseg > kLargeSeg ? lr_large : lr_small).push_back((int32_t)i);
+      (bi.nseg > kLargeSeg ? lr_large : bi.nseg > 1 ? lr_multi : lr_single).push_back((int32_t)i);
     }
   }
+  // t: blocks over many chunks, over a few, inside one; partials only for
+  // the first two classes (a block inside one chunk gets t from its tiles)
   int64_t toff = 0, pst = 0;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int32_t i : pass == 0 ? lr_large : lr_small) {
+  for (const auto* cls : {&lr_large, &lr_multi, &lr_single})
+    for (int32_t i : *cls) {
       BlockInfo& bi = P->binfo[i];
       bi.toff = toff;
-      bi.pst = pst;
       toff += P->blocks[i].rank;
-      pst += (int64_t)bi.nseg * P->blocks[i].rank;
+      if (cls == &lr_single) {
+        bi.pst = -1;
+      } else {
+        bi.pst = pst;
+        pst += (int64_t)bi.nseg * P->blocks[i].rank;
+      }
     }
   if (toff + n_cols > INT32_MAX || pst > INT32_MAX)
     return fail(HM_ENOMEM, "too many low-rank entries for 32-bit indices");
@@ -340,9 +346,11 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
   P->n_large = (int64_t)lr_large.size();
   P->n_large_t = 0;
   for (int32_t i : lr_large) P->n_large_t += P->blocks[i].rank;
-  P->lr_order.reserve(lr_large.size() + lr_small.size());
-  P->lr_order.insert(P->lr_order.end(), lr_large.begin(), lr_large.end());
-  P->lr_order.insert(P->lr_order.end(), lr_small.begin(), lr_small.end());
+  P->n_red_t = P->n_large_t;
+  for (int32_t i : lr_multi) P->n_red_t += P->blocks[i].rank;
+  P->lr_order.reserve(lr_large.size() + lr_multi.size() + lr_single.size());
+  for (const auto* cls : {&lr_large, &lr_multi, &lr_single})
+    P->lr_order.insert(P->lr_order.end(), cls->begin(), cls->end());
   P->has_sigma = 0;
   for (auto& b : P->blocks)
     if (b.kind == HM_LOWRANK && b.rank > 0 && b.has_sigma) P->has_sigma = 1;
@@ -425,11 +433,12 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
       const BlockInfo& bi = P->binfo[i];
       const int32_t seg = cseg[c];
       int32_t c0 = 0;
+      const bool direct = bi.nseg == 1;
       for (int g = 0; g < b.ngroups; ++g) {
         if (b.group_cols[g] > 0)
           Cp.segs.push_back(Seg{i, c0, b.group_cols[g],
-                                (int32_t)(bi.pst + (int64_t)seg * b.rank + c0), b.group_dtype[g], 0,
-                                HM_LOWRANK});
+                                (int32_t)(direct ? bi.toff + c0 : bi.pst + (int64_t)seg * b.rank + c0),
+                                b.group_dtype[g], 0, HM_LOWRANK, direct ? 1 : 0});
         c0 += b.group_cols[g];
       }
     }
@@ -526,6 +535,7 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   H.n_partials = P->n_partials;
   H.n_large = P->n_large;
   H.n_large_t = P->n_large_t;
+  H.n_red_t = P->n_red_t;
   H.n_tblocks = (int64_t)P->lr_order.size();
   int64_t nsec = 0, nsrc = 0;
   for (auto& R : P->rps) { nsec += (int64_t)R.secs.size(); nsrc += R.ncols; }
@@ -607,6 +617,9 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   P->work_part_off = 0;
   P->work_t_off = P->work_part_bytes;
   P->work_bytes_per_rhs = (size_t)(P->work_part_bytes + P->work_t_bytes + P->work_x_bytes);
+  // the batched column kernel addresses partials and t as one table of rows
+  if (P->work_part_bytes / 4 + P->n_t > INT32_MAX)
+    return fail(HM_ENOMEM, "too many partials and t entries for 32-bit indices");
 
   // accounting
   const int vec_sz = acc_sz;
@@ -731,10 +744,11 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
       const int G = group_width(S.dtype);
       const int ngr = S.ld / G;
       int32_t* dst = cdst + dsto;
-      for (int32_t c = 0; c < S.ld; ++c) dst[c] = -1;
+      for (int32_t c = 0; c < S.ld; ++c) dst[c] = kDstPad;
       for (auto& sg : Cp.segs)
         if (sg.dtype == S.dtype)
-          for (int32_t c = 0; c < sg.ncols; ++c) dst[sg.seccol + c] = sg.src0 + c;
+          for (int32_t c = 0; c < sg.ncols; ++c)
+            dst[sg.seccol + c] = sg.direct ? dst_direct(sg.src0 + c) : sg.src0 + c;
       for (int g0 = 0; g0 < ngr; g0 += kTileGroups) {
         ColTile& T = ct[tile++];
         const int ngt = std::min(kTileGroups, ngr - g0);

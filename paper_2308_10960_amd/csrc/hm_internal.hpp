@@ -40,10 +40,13 @@ struct Seg {
   int32_t c_first;        // first column of the block (dense col or low-rank l)
   int32_t ncols;
   int32_t src0;           // row panels: source slot of the first column;
-                          // column panels: partial index of the first column
+                          // column panels: partial index of the first column,
+                          // or its t index when direct
   int32_t dtype;
   int32_t seccol;         // column within its section
   int32_t kind;           // HM_DENSE or HM_LOWRANK
+  int32_t direct = 0;     // column panels: the block lies in one column chunk,
+                          // so its column sums are t itself
 };
 
 struct RowSectionHost { int32_t kind = 0, dtype = 0, ngroups = 0, col0 = 0; int64_t data_off = 0; };
@@ -76,7 +79,7 @@ struct hm_plan {
   std::vector<hm::RowPanelHost> rps;
   std::vector<hm::ColPanelHost> cps;
   std::vector<int32_t> lr_order;          // low-rank blocks in t order (large first)
-  int64_t n_t = 0, n_partials = 0, n_large = 0, n_large_t = 0;
+  int64_t n_t = 0, n_partials = 0, n_large = 0, n_large_t = 0, n_red_t = 0;
   int32_t has_sigma = 0;
   hm::StoreHeader hdr{};
   size_t store_bytes = 0, meta_bytes = 0, work_bytes_per_rhs = 0;

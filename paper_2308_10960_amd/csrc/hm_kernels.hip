@@ -8,8 +8,10 @@
 //  k_col     far field, phase 1: one workgroup per column tile streams the
 //            rows of V_b restricted to a column chunk, for all low-rank
 //            blocks covering it (lane = group of columns, x broadcast by
-//            readlane), and writes one partial dot product per column;
-//  k_reduce  t_b[l] = s_b[l] * sum of the block's partials in chunk order;
+//            readlane), and writes one partial dot product per column (for
+//            a block inside one chunk that sum, times s_b[l], is t_b[l]);
+//  k_reduce  t_b[l] = s_b[l] * sum of the block's partials in chunk order,
+//            for the blocks over several chunks;
 //  k_row     near field and far field, phase 2: one workgroup per row panel
 //            gathers its sources (x and t) into LDS, streams the panel's
 //            dense and U sections with 16-byte loads (lane = row), and
@@ -103,6 +105,8 @@ struct ColArgs {
   const int32_t* dst;
   const AccT* x;
   AccT* part;
+  AccT* t;                // column sums of blocks inside one chunk go here
+  const AccT* sigma;      // nullptr when no block keeps singular values
   int64_t n_tiles;
 };
 
@@ -141,12 +145,21 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
   for (int c = 0; c < G; ++c) red[(wave * 64 + lane) * G + c] = acc[c];
   __syncthreads();
   if (wave == 0 && act) {
+    // all destinations and factors first, then the stores
+    int32_t d[G];
+    AccT f[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) d[c] = a.dst[T.dst_off + lane * G + c];
+#pragma unroll
+    for (int c = 0; c < G; ++c) f[c] = (d[c] <= -2 && a.sigma) ? a.sigma[dst_t_index(d[c])] : AccT(1);
 #pragma unroll
     for (int c = 0; c < G; ++c) {
-      const int32_t d = a.dst[T.dst_off + lane * G + c];
-      if (d >= 0)
-        a.part[d] = (red[lane * G + c] + red[(64 + lane) * G + c]) +
-                    (red[(128 + lane) * G + c] + red[(192 + lane) * G + c]);
+      const AccT sum = (red[lane * G + c] + red[(64 + lane) * G + c]) +
+                       (red[(128 + lane) * G + c] + red[(192 + lane) * G + c]);
+      if (d[c] >= 0)
+        a.part[d[c]] = sum;
+      else if (d[c] != kDstPad)
+        a.t[dst_t_index(d[c])] = a.sigma ? sum * f[c] : sum;
     }
   }
 }
@@ -175,7 +188,7 @@ struct RedArgs {
   const AccT* sigma;      // nullptr when no block keeps singular values
   const AccT* part;
   AccT* t;
-  int64_t n_large, n_large_t, n_t;
+  int64_t n_large, n_large_t, n_red_t;
 };
 
 template <typename AccT>
@@ -212,7 +225,7 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs<AccT> a) {
     return;
   }
   const int64_t o = a.n_large_t + ((int64_t)blockIdx.x - a.n_large) * 256 + tid;
-  if (o >= a.n_t) return;
+  if (o >= a.n_red_t) return;
   const TBlock B = a.tb[a.owner[o]];
   const int l = (int)(o - B.toff);
   AccT s = AccT(0);
@@ -400,9 +413,10 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
                    reinterpret_cast<const int32_t*>(st + h.off_row_src),
                    reinterpret_cast<const AccT*>(x), t, reinterpret_cast<AccT*>(y), (AccT)alpha,
                    (int32_t)h.n_cols};
+  const AccT* sigma = h.has_sigma ? reinterpret_cast<const AccT*>(st + h.off_sigma) : nullptr;
   ColArgs<AccT> ca{st, reinterpret_cast<const ColTile*>(st + h.off_col_tiles),
                    reinterpret_cast<const int32_t*>(st + h.off_col_dst),
-                   reinterpret_cast<const AccT*>(x), part, h.n_col_tiles};
+                   reinterpret_cast<const AccT*>(x), part, t, sigma, h.n_col_tiles};
   const bool grouped = A.launch.schedule == 1;
   const int ps = A.launch.persist, ncu = A.n_cu;
   if (ev) (void)hipEventRecord(ev[0], s);
@@ -416,10 +430,9 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
   if (ev) (void)hipEventRecord(ev[1], s);
   if (h.n_col_tiles > 0) {
     RedArgs<AccT> rd{reinterpret_cast<const TBlock*>(st + h.off_tblocks),
-                     reinterpret_cast<const int32_t*>(st + h.off_owner),
-                     h.has_sigma ? reinterpret_cast<const AccT*>(st + h.off_sigma) : nullptr,
-                     part, t, h.n_large, h.n_large_t, h.n_t};
-    const int64_t nred = h.n_large + (h.n_t - h.n_large_t + 255) / 256;
+                     reinterpret_cast<const int32_t*>(st + h.off_owner), sigma, part, t, h.n_large,
+                     h.n_large_t, h.n_red_t};
+    const int64_t nred = h.n_large + (h.n_red_t - h.n_large_t + 255) / 256;
     if (nred > 0) hipLaunchKernelGGL(k_reduce<AccT>, dim3((unsigned)nred), dim3(256), 0, s, rd);
   }
   if (ev) (void)hipEventRecord(ev[2], s);

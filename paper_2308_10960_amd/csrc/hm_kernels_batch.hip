@@ -71,21 +71,38 @@ __global__ __launch_bounds__(256) void k_xpose(const float* __restrict__ X, int6
   }
 }
 
-// Two consecutive stored values (8 bytes of FP32, 4 bytes of FP16/BF16) as floats.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// D (32 x 32) += A (32 x 2) B (2 x 32) on v_mfma_f32_32x32x2_f32: lane l
+// gives A[l % 32][l / 32] and B[l / 32][l % 32]; D[i][j] is in lane
+// j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
+__device__ __forceinline__ f32x16 mfma32x2(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// Row (0..31) of D held by register v of lane l in mfma32x2.
+__device__ __forceinline__ int mfma32x2_row(int lane, int v) {
+  return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+}
+
+// The 8 stored bytes at p as floats: 2 FP32 or 4 FP16/BF16 values.
 template <int DT>
-__device__ __forceinline__ void load2(const uint8_t* p, float (&v)[2]) {
+__device__ __forceinline__ void load8(const uint8_t* p, float (&v)[8 / dtype_size(DT)]) {
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  const u32x2 r = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
   if constexpr (DT == HM_F32) {
-    typedef float f32x2 __attribute__((ext_vector_type(2)));
-    const f32x2 r = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
-    v[0] = r[0]; v[1] = r[1];
+    v[0] = __uint_as_float(r[0]);
+    v[1] = __uint_as_float(r[1]);
+  } else if constexpr (DT == HM_F16) {
+    typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+    const f16x4 h = __builtin_bit_cast(f16x4, r);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = (float)h[c];
   } else {
-    const unsigned r = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p));
-    if constexpr (DT == HM_F16) {
-      typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-      const f16x2 h = __builtin_bit_cast(f16x2, r);
-      v[0] = (float)h[0]; v[1] = (float)h[1];
-    } else {
-      v[0] = __uint_as_float(r << 16); v[1] = __uint_as_float(r & 0xffff0000u);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      v[2 * c] = __uint_as_float(r[c] << 16);
+      v[2 * c + 1] = __uint_as_float(r[c] & 0xffff0000u);
     }
   }
 }
@@ -95,83 +112,127 @@ struct ColBArgs {
   const ColTile* tiles;
   const int32_t* dst;
   const float* xr;
-  float* part;
+  float* part;            // rows of RS values; t follows at row t_row0
+  int32_t t_row0;         // column sums of blocks inside one chunk go to row t_row0 + o
+  const float* sigma;     // nullptr when no block keeps singular values
   int64_t n_tiles;
   int RS, RH;
 };
 
-// One wave: 128 columns [c0, c0 + 128) of a column tile (lane l owns columns
-// c0 + 2l and c0 + 2l + 1) for 32 right-hand sides (group rh of RS).
-// wd: this wave's 128-entry LDS table of destination indices.
-template <int DT>
-__device__ __forceinline__ void colb_part(const ColBArgs& a, const ColTile& T, int c0, int rh,
-                                          int lane, int32_t* wd) {
-  constexpr int SZ = dtype_size(DT);
+// One wave (a workgroup of its own): a quarter of a column tile -- 32 x CPL
+// columns, CPL = 8 bytes / storage size -- for 32 right-hand sides (group rh
+// of RS).  Lane l owns columns c0 + CPL (l % 32) + q, q < CPL, of row
+// i + l / 32: one v_mfma_f32_32x32x2_f32 per q takes two rows at a time (A:
+// the lane's value of column q; B: the x rows i and i + 1 of the 32
+// right-hand sides, one load for both).  Rows go in batches of S steps (2S
+// rows); with DB the next batch's loads are in flight while this batch's
+// MFMAs run.  wd, ws: the wave's LDS tables of destination rows (in part,
+// whose rows from t_row0 on are t) and factors (s_b[l] for a column that
+// writes t directly, else 1).
+template <int DT, int S, bool DB>
+__device__ __forceinline__ void colb_part(const ColBArgs& a, const ColTile& T, int quarter, int rh,
+                                          int lane, int32_t* wd, float* ws) {
+  constexpr int SZ = dtype_size(DT), CPL = 8 / SZ;
   const int ncols = T.ngroups * group_width(DT);
-  const int cb = c0 + 2 * lane;
-  const bool act = cb < ncols;
-  // each lane fetches the destinations of its own two columns once
-  int32_t d0 = -1, d1 = -1;
-  if (act) { d0 = a.dst[T.dst_off + cb]; d1 = a.dst[T.dst_off + cb + 1]; }
-  wd[2 * lane] = d0;
-  wd[2 * lane + 1] = d1;
+  const int c0 = quarter * 32 * CPL;
+  if (c0 >= ncols) return;                          // uniform: nothing in this quarter
+  const int l32 = lane & 31, hi = lane >> 5;
+  const int cb = c0 + CPL * l32;
+  const bool act = cb < ncols;                      // all CPL columns or none
+  if (lane < 32) {
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      // row of part (partials, then t) the column's sum goes to, and its factor
+      const int32_t e = act ? a.dst[T.dst_off + cb + q] : kDstPad;
+      const bool direct = e <= -2;
+      wd[CPL * lane + q] = direct ? a.t_row0 + dst_t_index(e) : e;
+      ws[CPL * lane + q] = (direct && a.sigma) ? a.sigma[dst_t_index(e)] : 1.f;
+    }
+  }
   __builtin_amdgcn_wave_barrier();
-  f32x32 acc[2];
-  acc[0] = (f32x32)(0.f);
-  acc[1] = (f32x32)(0.f);
-  const uint8_t* base = a.store + T.data_off + (size_t)cb * SZ;
+  f32x16 acc[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q] = (f32x16)(0.f);
   const size_t rstride = (size_t)T.ld * SZ;
-  const float* xb = a.xr + (size_t)T.x0 * a.RS + rh * 32 + (lane & 31);
-  int i = 0;
-  for (; i + 8 <= T.nrows; i += 8) {
-    float v[8][2];
-    float b[8];
+  const uint8_t* base = a.store + T.data_off + (size_t)hi * rstride + (size_t)cb * SZ;
+  const float* xb = a.xr + ((size_t)T.x0 + hi) * a.RS + rh * 32 + l32;
+  const int nr = T.nrows;
+  // step k covers rows 2k, 2k + 1; lanes of a missing row give zeros
+  const int nsteps = (nr + 1) / 2;
+  float an[S][CPL], bn[S];
+  auto issue = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      v[u][0] = v[u][1] = 0.f;
-      if (act) load2<DT>(base + (i + u) * rstride, v[u]);
-      b[u] = xb[(size_t)(i + u) * a.RS];
+    for (int u = 0; u < S; ++u) {
+      const int r = 2 * (k0 + u) + hi;
+      const bool ok = r < nr;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) an[u][q] = 0.f;
+      if (act && ok) load8<DT>(base + (size_t)(2 * (k0 + u)) * rstride, an[u]);
+      bn[u] = ok ? xb[(size_t)(2 * (k0 + u)) * a.RS] : 0.f;
     }
+  };
+  auto compute = [&](int k, const float (&av)[S][CPL], const float (&bv)[S]) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      acc[0] = mfma32(v[u][0], b[u], acc[0]);
-      acc[1] = mfma32(v[u][1], b[u], acc[1]);
+    for (int u = 0; u < S; ++u) {
+      if (k + u >= nsteps) break;                   // uniform across the wave
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) acc[q] = mfma32x2(av[u][q], bv[u], acc[q]);
+    }
+  };
+  if constexpr (DB) {
+    issue(0);
+    for (int k = 0; k < nsteps; k += S) {
+      float ac[S][CPL], bc[S];
+#pragma unroll
+      for (int u = 0; u < S; ++u) {
+        bc[u] = bn[u];
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) ac[u][q] = an[u][q];
+      }
+      if (k + S < nsteps) issue(k + S);
+      compute(k, ac, bc);
+    }
+  } else {
+    for (int k = 0; k < nsteps; k += S) {
+      issue(k);
+      compute(k, an, bn);
     }
   }
-  for (; i < T.nrows; ++i) {
-    float v[2] = {0.f, 0.f};
-    if (act) load2<DT>(base + i * rstride, v);
-    const float b = xb[(size_t)i * a.RS];
-    acc[0] = mfma32(v[0], b, acc[0]);
-    acc[1] = mfma32(v[1], b, acc[1]);
-  }
-  const int j = rh * 32 + (lane & 31);
+  const int j = rh * 32 + l32;
 #pragma unroll
-  for (int v = 0; v < 32; ++v) {
-    const int R = mfma_row(lane, v);
-    const int32_t e0 = wd[2 * R], e1 = wd[2 * R + 1];   // -1: padding or no column
-    if (e0 >= 0) a.part[(size_t)e0 * a.RS + j] = acc[0][v];
-    if (e1 >= 0) a.part[(size_t)e1 * a.RS + j] = acc[1][v];
+  for (int v = 0; v < 16; ++v) {
+    const int col = CPL * mfma32x2_row(lane, v);    // first column of that D row
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int32_t e = wd[col + q];                // -1: padding or no column
+      if (e >= 0) a.part[(size_t)e * a.RS + j] = acc[q][v] * ws[col + q];
+    }
   }
 }
 
-// Wave w -> (tile, 128-column part, right-hand-side group).
-__global__ __launch_bounds__(256) void k_col_b(ColBArgs a) {
-  __shared__ int32_t sdst[4][128];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t w = (int64_t)blockIdx.x * 4 + wave;
+#ifndef COLB_STEPS
+#define COLB_STEPS 4
+#define COLB_DOUBLE true
+#endif
+constexpr int kColBSteps = COLB_STEPS;
+constexpr bool kColBDouble = COLB_DOUBLE;
+
+// Workgroup (one wave) w -> (tile, quarter, right-hand-side group).
+__global__ __launch_bounds__(64) void k_col_b(ColBArgs a) {
+  __shared__ int32_t sdst[128];
+  __shared__ float ssig[128];
+  const int lane = threadIdx.x;
+  const int64_t w = blockIdx.x;
   const int rh = (int)(w % a.RH);
   const int64_t rest = w / a.RH;
-  const int part = (int)(rest & 3);
+  const int quarter = (int)(rest & 3);
   const int64_t ti = rest >> 2;
   if (ti >= a.n_tiles) return;
   const ColTile T = a.tiles[ti];
-  const int c0 = 128 * part;
-  if (c0 >= T.ngroups * group_width(T.dtype)) return;
   switch (T.dtype) {
-    case HM_F32: colb_part<HM_F32>(a, T, c0, rh, lane, sdst[wave]); break;
-    case HM_F16: colb_part<HM_F16>(a, T, c0, rh, lane, sdst[wave]); break;
-    case HM_BF16: colb_part<HM_BF16>(a, T, c0, rh, lane, sdst[wave]); break;
+    case HM_F32: colb_part<HM_F32, kColBSteps, kColBDouble>(a, T, quarter, rh, lane, sdst, ssig); break;
+    case HM_F16: colb_part<HM_F16, kColBSteps, kColBDouble>(a, T, quarter, rh, lane, sdst, ssig); break;
+    case HM_BF16: colb_part<HM_BF16, kColBSteps, kColBDouble>(a, T, quarter, rh, lane, sdst, ssig); break;
     default: break;
   }
 }
@@ -182,24 +243,37 @@ struct RedBArgs {
   const float* sigma;
   const float* part;
   float* t;
-  int64_t n_t;
+  int64_t n_red_t;        // t entries [0, n_red_t) come from partials
   int RS;
 };
 
-// t[o][j] = s_o * sum over the block's intervals (ascending) of its partials.
+// t[o][j] = s_o * sum over the block's intervals (ascending) of its partials,
+// for the blocks over several column chunks (t entries [0, n_red_t)); one
+// thread per t entry o and four right-hand sides j (16-byte accesses).
+template <int RS>
 __global__ __launch_bounds__(256) void k_reduce_b(RedBArgs a) {
+  constexpr int Q = RS / 4;                          // threads per t entry
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t o = e / a.RS;
-  const int j = (int)(e % a.RS);
-  if (o >= a.n_t) return;
+  const int64_t o = e / Q;                           // division by a power of two
+  const int j = 4 * (int)(e % Q);
+  if (o >= a.n_red_t) return;
   const TBlock B = a.tb[a.owner[o]];
   const int l = (int)(o - B.toff);
-  float s = 0.f;
-  const float* pp = a.part + ((size_t)B.pst + l) * a.RS + j;
-  const size_t step = (size_t)B.k * a.RS;
+  f32x4 s = (f32x4)(0.f);
+  const f32x4* pp = reinterpret_cast<const f32x4*>(a.part + ((size_t)B.pst + l) * RS + j);
+  const size_t step = (size_t)B.k * Q;               // f32x4 units between intervals
 #pragma unroll 4
-  for (int g = 0; g < B.nseg; ++g) s += pp[g * step];
-  a.t[o * a.RS + j] = a.sigma ? s * a.sigma[o] : s;
+  for (int g = 0; g < B.nseg; ++g) {
+    const f32x4 v = pp[g * step];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] += v[c];
+  }
+  if (a.sigma) {
+    const float sg = a.sigma[o];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] *= sg;
+  }
+  *reinterpret_cast<f32x4*>(a.t + o * RS + j) = s;
 }
 
 struct RowBArgs {
@@ -235,20 +309,6 @@ __device__ __forceinline__ void decode_any(int dt, u32x4 r, float (&v)[8]) {
       v[2 * c + 1] = __uint_as_float(r[c] & 0xffff0000u);
     }
   }
-}
-
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-// D (32 x 32) += A (32 x 2) B (2 x 32) on v_mfma_f32_32x32x2_f32: lane l
-// gives A[l % 32][l / 32] and B[l / 32][l % 32]; D[i][j] is in lane
-// j + 32 ((i / 4) % 2), register 4 (i / 8) + i % 4.
-__device__ __forceinline__ f32x16 mfma32x2(float a, float b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-}
-
-// Row (0..31) of D held by register v of lane l in mfma32x2.
-__device__ __forceinline__ int mfma32x2_row(int lane, int v) {
-  return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
 }
 
 // One section of a row panel for the groups g = wave, wave + 4, ...: per
@@ -438,17 +498,22 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
     hipLaunchKernelGGL(k_xpose, dim3((unsigned)((h.n_cols + 63) / 64), (unsigned)RH), dim3(256), 0, s,
                        Xc, ldx, (int)h.n_cols, nr, RS, xr);
     if (h.n_col_tiles > 0) {
+      const float* sigma = h.has_sigma ? reinterpret_cast<const float*>(st + h.off_sigma) : nullptr;
       ColBArgs ca{st, reinterpret_cast<const ColTile*>(st + h.off_col_tiles),
-                  reinterpret_cast<const int32_t*>(st + h.off_col_dst), xr, part, h.n_col_tiles, RS, RH};
+                  reinterpret_cast<const int32_t*>(st + h.off_col_dst), xr, part,
+                  (int32_t)(A.work_part_bytes / (int64_t)sizeof(float)), sigma, h.n_col_tiles, RS, RH};
       const int64_t waves = h.n_col_tiles * 4 * RH;
-      hipLaunchKernelGGL(k_col_b, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ca);
+      hipLaunchKernelGGL(k_col_b, dim3((unsigned)waves), dim3(64), 0, s, ca);
       if (ev && r0 == 0) (void)hipEventRecord(ev[1], s);
       RedBArgs rb{reinterpret_cast<const TBlock*>(st + h.off_tblocks),
-                  reinterpret_cast<const int32_t*>(st + h.off_owner),
-                  h.has_sigma ? reinterpret_cast<const float*>(st + h.off_sigma) : nullptr, part, t,
-                  h.n_t, RS};
-      const int64_t nthr = h.n_t * RS;
-      if (nthr > 0) hipLaunchKernelGGL(k_reduce_b, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, rb);
+                  reinterpret_cast<const int32_t*>(st + h.off_owner), sigma, part, t, h.n_red_t, RS};
+      const int64_t nthr = h.n_red_t * (RS / 4);
+      if (nthr > 0) {
+        if (RS == 32)
+          hipLaunchKernelGGL(k_reduce_b<32>, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, rb);
+        else
+          hipLaunchKernelGGL(k_reduce_b<64>, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, rb);
+      }
     } else if (ev && r0 == 0) {
       (void)hipEventRecord(ev[1], s);
     }

@@ -76,6 +76,13 @@ struct ColTile {         // 32 bytes: one wave streams nrows rows x ngroups*G co
   int32_t dst_off;       // first entry (int32 units) of this tile in the destination table
 };
 
+// Destination of a column sum (one int32 per tile column): e >= 0 is the
+// partial e; e == -1 is a padding column; e <= -2 is t entry -e - 2 (the
+// block lies in one column chunk; the sum, times s_b when kept, is t).
+constexpr int32_t kDstPad = -1;
+inline constexpr int32_t dst_direct(int32_t t_index) { return -t_index - 2; }
+inline constexpr int32_t dst_t_index(int32_t e) { return -e - 2; }
+
 struct TBlock {          // 16 bytes: reduction of one low-rank block's partials
   int32_t pst;           // first partial (acc units); partial (seg, l) at pst + seg*k + l
   int32_t k;             // rank
@@ -97,6 +104,11 @@ struct StoreHeader {
   // (entry >= 0: panel index) with column tiles (entry < 0: tile -entry-1);
   // phase 2 lists the row panels with U sections
   int64_t off_p1_order, n_p1, off_p2_order, n_p2;
+  // t entries [0, n_red_t) come from partials (blocks over several column
+  // chunks: the n_large largest first, whose entries are [0, n_large_t));
+  // the blocks inside one column chunk, [n_red_t, n_t), get t directly from
+  // the column tiles
+  int64_t n_red_t;
 };
 
 constexpr uint64_t kStoreMagic = 0x484d53544f524532ull;  // "HMSTORE2"

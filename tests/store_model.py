@@ -2,7 +2,8 @@
 
 Reads the header and descriptor tables that hm_pack_host wrote and evaluates
 the product the way the store's layout defines it (row panels, column tiles,
-partial reduction).  Used to check the block scheduler and the packer on the
+partial reduction for blocks over several column chunks, t straight from the
+tiles for blocks inside one).  Used to check the block scheduler and the packer on the
 CPU against the oracle; it shares no code with either.
 """
 
@@ -15,7 +16,8 @@ HDR = np.dtype([("magic", "<u8"), ("n_rows", "<i8"), ("n_cols", "<i8"),
                 ("off_row_order", "<i8"), ("off_row_src", "<i8"), ("off_col_tiles", "<i8"),
                 ("off_col_dst", "<i8"), ("off_tblocks", "<i8"), ("off_large", "<i8"),
                 ("off_owner", "<i8"), ("off_sigma", "<i8"), ("acc_dtype", "<i8"),
-                ("has_sigma", "<i8")])
+                ("has_sigma", "<i8"), ("off_p1_order", "<i8"), ("n_p1", "<i8"),
+                ("off_p2_order", "<i8"), ("n_p2", "<i8"), ("n_red_t", "<i8")])
 RP = np.dtype([("src_off", "<i8"), ("row0", "<i4"), ("m", "<i4"), ("ncols", "<i4"),
                ("sec0", "<i4"), ("nsec", "<i4"), ("pad", "<i4")])
 RS = np.dtype([("data_off", "<i8"), ("dtype", "<i4"), ("ngroups", "<i4"), ("col0", "<i4"),
@@ -55,6 +57,8 @@ def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> n
     h, T = tables(buf)
     n_cols = int(h["n_cols"])
     part = np.zeros(int(h["n_partials"]))
+    t_direct = np.zeros(int(h["n_t"]))
+    written = np.zeros(int(h["n_t"]), bool)
     dst_all = buf[h["off_col_dst"]:].view("<i4")
     for t in T["ct"]:
         g, nr, ld, dt = G[int(t["dtype"])], int(t["nrows"]), int(t["ld"]), int(t["dtype"])
@@ -64,13 +68,23 @@ def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> n
         p = V.T @ x[int(t["x0"]): int(t["x0"]) + nr]
         d = dst_all[int(t["dst_off"]): int(t["dst_off"]) + cols]
         part[d[d >= 0]] = p[d >= 0]
-    t_vec = np.zeros(int(h["n_t"]))
+        direct = d <= -2                                     # t entry -d - 2 of a one-chunk block
+        assert not np.any(written[-d[direct] - 2])
+        t_direct[-d[direct] - 2] = p[direct]
+        written[-d[direct] - 2] = True
     sig = None
     if h["has_sigma"]:
         sig = decode(buf, int(h["off_sigma"]), int(h["n_t"]), 0 if h["acc_dtype"] == 0 else 1)
+    t_vec = np.zeros(int(h["n_t"]))
+    n_red_t = int(h["n_red_t"])
     for b in T["tb"]:
         k, ns, pst, toff = int(b["k"]), int(b["nseg"]), int(b["pst"]), int(b["toff"])
-        s = part[pst: pst + ns * k].reshape(ns, k).sum(0)
+        if ns == 1:                                          # from the column tiles
+            assert toff >= n_red_t and pst == -1 and np.all(written[toff: toff + k])
+            s = t_direct[toff: toff + k]
+        else:
+            assert toff + k <= n_red_t
+            s = part[pst: pst + ns * k].reshape(ns, k).sum(0)
         t_vec[toff: toff + k] = s if sig is None else s * sig[toff: toff + k]
     z = np.concatenate([x, t_vec])
     src_all = buf[h["off_row_src"]:].view("<i4")
