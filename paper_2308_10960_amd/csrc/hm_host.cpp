@@ -152,15 +152,15 @@ static void split_intervals(const std::vector<int64_t>& bp, int cap, std::vector
   out.push_back(bp.back());
 }
 
-// Byte offset of element (row i, section column sc) of a column section.
-// The section is stored tile by tile (tiles of 64 groups of G columns, the
-// last one narrower); inside a tile, row i holds the tile's groups
-// contiguously, so one wave streams one contiguous block.
-static int64_t col_elem_offset(const ColSectionHost& S, int32_t nrows, int64_t i, int64_t sc) {
+// Byte offset of element (row i, column sc of run S) of column panel Cp.
+// The panel's groups (run by run) are stored tile by tile (tiles of 64
+// groups, the last one narrower); inside a tile, row i holds the tile's
+// groups contiguously, so a tile row is one contiguous block.
+static int64_t col_elem_offset(const ColPanelHost& Cp, const ColSectionHost& S, int64_t i, int64_t sc) {
   const int G = group_width(S.dtype), sz = dtype_size(S.dtype);
-  const int64_t ngr = S.ld / G, gg = sc / G, t = gg / kTileGroups, gl = gg % kTileGroups;
-  const int64_t ngt = std::min<int64_t>(kTileGroups, ngr - t * kTileGroups);
-  return S.data_off + t * kTileGroups * 16 * (int64_t)nrows + (i * ngt + gl) * 16 + (sc % G) * sz;
+  const int64_t g = S.g0 + sc / G, t = g / kTileGroups, gl = g % kTileGroups;
+  const int64_t ngt = std::min<int64_t>(kTileGroups, Cp.ngroups - t * kTileGroups);
+  return Cp.data_off + t * kTileGroups * 16 * (int64_t)Cp.nrows + (i * ngt + gl) * 16 + (sc % G) * sz;
 }
 
 hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks, int64_t nb,
@@ -442,7 +442,7 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
         c0 += b.group_cols[g];
       }
     }
-    for (int dt = 0; dt < 4; ++dt) {
+    for (int dt = 0; dt < 4; ++dt) {             // one run per format, formats ascending
       int32_t cols = 0;
       for (auto& s : Cp.segs)
         if (s.dtype == dt) { s.seccol = cols; cols += s.ncols; }
@@ -451,6 +451,10 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
       ColSectionHost S;
       S.dtype = dt;
       S.ld = (int32_t)align_up(cols, G);
+      S.g0 = Cp.ngroups;
+      S.c0 = Cp.ncols;
+      Cp.ngroups += S.ld / G;
+      Cp.ncols += S.ld;
       Cp.secs.push_back(S);
     }
   }
@@ -541,13 +545,27 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   for (auto& R : P->rps) { nsec += (int64_t)R.secs.size(); nsrc += R.ncols; }
   H.n_row_sections = nsec;
   int64_t ntiles = 0, ndst = 0;
-  for (auto& Cp : P->cps)
-    for (auto& S : Cp.secs) {
-      const int G = group_width(S.dtype);
-      ntiles += (S.ld / G + kTileGroups - 1) / kTileGroups;
-      ndst += S.ld;
-    }
+  for (auto& Cp : P->cps) {
+    ntiles += (Cp.ngroups + kTileGroups - 1) / kTileGroups;
+    ndst += Cp.ncols;
+  }
   H.n_col_tiles = ntiles;
+  {
+    // tiles per class (one format, or several: runs of a panel that meet in a tile)
+    int64_t cnt[5] = {0, 0, 0, 0, 0};
+    for (auto& Cp : P->cps)
+      for (int32_t g0 = 0; g0 < Cp.ngroups; g0 += kTileGroups) {
+        const int32_t g1 = std::min(Cp.ngroups, g0 + kTileGroups);
+        int runs = 0, fmt = 0;
+        for (auto& S : Cp.secs) {
+          const int32_t a = S.g0, b = S.g0 + S.ld / group_width(S.dtype);
+          if (std::max(a, g0) < std::min(b, g1)) { ++runs; fmt = S.dtype; }
+        }
+        ++cnt[runs == 1 ? fmt : 4];
+      }
+    int64_t acc_end = 0;
+    for (int c = 0; c < 5; ++c) H.tile_class_end[c] = (acc_end += cnt[c]);
+  }
 
   int64_t off = align_up(sizeof(StoreHeader), kAlign);
   auto take = [&](int64_t bytes) { int64_t o = off; off = align_up(off + bytes, kAlign); return o; };
@@ -593,10 +611,10 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
       P->bytes_by_dtype[S.dtype] += (size_t)real_bytes;
     }
   }
-  for (auto& Cp : P->cps)
+  for (auto& Cp : P->cps) {
+    Cp.data_off = take((int64_t)Cp.ngroups * 16 * Cp.nrows);
     for (auto& S : Cp.secs) {
       const int64_t bytes = (int64_t)S.ld * Cp.nrows * dtype_size(S.dtype);
-      S.data_off = take(bytes);
       int64_t real = 0;
       for (auto& s : Cp.segs)
         if (s.dtype == S.dtype) real += s.ncols;
@@ -605,6 +623,7 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
       pad_bytes += (double)(bytes - real_bytes);
       P->bytes_by_dtype[S.dtype] += (size_t)real_bytes;
     }
+  }
   P->store_bytes = (size_t)off;
   P->meta_bytes = (size_t)meta_end;
   P->factor_bytes = factor_bytes;
@@ -735,35 +754,51 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
     auto* p2 = reinterpret_cast<int32_t*>(buf + H.off_p2_order);
     std::copy(upart.begin(), upart.end(), p2);
   }
-  // column tiles and destinations
+  // column tiles and destinations: per panel, the destination of every
+  // column in the panel's column order (run by run), and tiles of 64 groups
   auto* ct = reinterpret_cast<ColTile*>(buf + H.off_col_tiles);
   auto* cdst = reinterpret_cast<int32_t*>(buf + H.off_col_dst);
   int64_t tile = 0, dsto = 0;
-  for (auto& Cp : P->cps)
-    for (auto& S : Cp.secs) {
-      const int G = group_width(S.dtype);
-      const int ngr = S.ld / G;
-      int32_t* dst = cdst + dsto;
-      for (int32_t c = 0; c < S.ld; ++c) dst[c] = kDstPad;
-      for (auto& sg : Cp.segs)
-        if (sg.dtype == S.dtype)
-          for (int32_t c = 0; c < sg.ncols; ++c)
-            dst[sg.seccol + c] = sg.direct ? dst_direct(sg.src0 + c) : sg.src0 + c;
-      for (int g0 = 0; g0 < ngr; g0 += kTileGroups) {
-        ColTile& T = ct[tile++];
-        const int ngt = std::min(kTileGroups, ngr - g0);
-        T.data_off = S.data_off + (int64_t)g0 * 16 * Cp.nrows;   // tiles stored one after another
-        T.ld = ngt * G;                                        // elements per tile row
-        T.nrows = Cp.nrows;
-        T.x0 = (int32_t)Cp.x0;
-        T.dtype = S.dtype;
-        T.ngroups = std::min(kTileGroups, ngr - g0);
-        T.dst_off = (int32_t)(dsto + (int64_t)g0 * G);
-      }
-      dsto += S.ld;
+  for (auto& Cp : P->cps) {
+    int32_t* dst = cdst + dsto;
+    for (int32_t c = 0; c < Cp.ncols; ++c) dst[c] = kDstPad;
+    for (auto& sg : Cp.segs) {
+      const ColSectionHost* S = nullptr;
+      for (auto& x : Cp.secs) if (x.dtype == sg.dtype) S = &x;
+      for (int32_t c = 0; c < sg.ncols; ++c)
+        dst[S->c0 + sg.seccol + c] = sg.direct ? dst_direct(sg.src0 + c) : sg.src0 + c;
     }
+    for (int32_t g0 = 0; g0 < Cp.ngroups; g0 += kTileGroups) {
+      ColTile& T = ct[tile++];
+      const int32_t ngt = std::min(kTileGroups, Cp.ngroups - g0);
+      T.data_off = Cp.data_off + (int64_t)g0 * 16 * Cp.nrows;   // tiles stored one after another
+      T.nrows = Cp.nrows;
+      T.x0 = (int32_t)Cp.x0;
+      T.ngroups = ngt;
+      // runs of the tile: the panel's runs cut to groups [g0, g0 + ngt)
+      int nr = 0, first_col = -1;
+      for (auto& S : Cp.secs) {
+        const int32_t G = group_width(S.dtype);
+        const int32_t lo = std::max(S.g0, g0), hi = std::min(S.g0 + S.ld / G, g0 + ngt);
+        if (hi <= lo) continue;
+        if (first_col < 0) first_col = S.c0 + (lo - S.g0) * G;
+        T.dtype[nr] = (uint8_t)S.dtype;
+        T.end[nr] = (uint8_t)(hi - g0);
+        ++nr;
+      }
+      for (int r = nr; r < 4; ++r) {               // empty runs at the end
+        T.dtype[r] = T.dtype[nr - 1];
+        T.end[r] = (uint8_t)ngt;
+      }
+      T.dst_off = (int32_t)(dsto + first_col);
+    }
+    dsto += Cp.ncols;
+  }
   // tiles largest first (longest-processing-time order against the tail)
+  // (grouped by class: each class can run in a launch of its own)
   std::stable_sort(ct, ct + H.n_col_tiles, [](const ColTile& x, const ColTile& y) {
+    const int cx = tile_class(x), cy = tile_class(y);
+    if (cx != cy) return cx < cy;
     return (int64_t)x.nrows * x.ngroups > (int64_t)y.nrows * y.ngroups;
   });
   // reduction tables
@@ -807,9 +842,12 @@ void pack_job_range(const hm_plan* P, size_t j, int64_t* lo, int64_t* hi) {
     span(R.secs, [&](const RowSectionHost& S) { return (int64_t)S.ngroups * R.m * 16; });
   } else {
     const ColPanelHost& Cp = P->cps[j - nrp];
-    span(Cp.secs, [&](const ColSectionHost& S) {
-      return (int64_t)S.ld * Cp.nrows * dtype_size(S.dtype);
-    });
+    if (Cp.ngroups == 0) {
+      *lo = *hi = -1;
+    } else {
+      *lo = Cp.data_off;
+      *hi = align_up(Cp.data_off + (int64_t)Cp.ngroups * 16 * Cp.nrows, kAlign);
+    }
   }
 }
 
@@ -856,7 +894,7 @@ void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf
           for (int32_t c = 0; c < sg.ncols; ++c) {
             const double* col = V + (int64_t)(sg.c_first + c) * nbk + c_local;
             for (int32_t i = 0; i < Cp.nrows; ++i)
-              put(at(col_elem_offset(*S, Cp.nrows, i, sg.seccol + c)), S->dtype, col[i]);
+              put(at(col_elem_offset(Cp, *S, i, sg.seccol + c)), S->dtype, col[i]);
           }
         }
       }
@@ -960,7 +998,7 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
       if (sg.block == block && j >= sg.c_first && j < sg.c_first + sg.ncols) {
         for (auto& S : Cp.secs)
           if (S.dtype == sg.dtype) {
-            *byte_offset = (size_t)col_elem_offset(S, Cp.nrows, col - Cp.x0, sg.seccol + (j - sg.c_first));
+            *byte_offset = (size_t)col_elem_offset(Cp, S, col - Cp.x0, sg.seccol + (j - sg.c_first));
             *dtype = S.dtype;
             return ok();
           }

@@ -57,12 +57,18 @@ struct RowPanelHost {
   std::vector<Seg> segs;
   std::vector<RowSectionHost> secs;
 };
-struct ColSectionHost { int32_t dtype = 0, ld = 0; int64_t data_off = 0; };
+// A column panel (one column chunk) stores the groups of all its low-rank
+// columns as one sequence ordered by storage format: run r holds the ld
+// columns (a multiple of the group width) of one format, from group g0 and
+// from column c0 of the panel's column order.
+struct ColSectionHost { int32_t dtype = 0, ld = 0, g0 = 0, c0 = 0; };
 struct ColPanelHost {
   int64_t x0 = 0;
   int32_t nrows = 0;
+  int32_t ngroups = 0, ncols = 0;    // all runs (ncols counts padding)
+  int64_t data_off = 0;
   std::vector<Seg> segs;
-  std::vector<ColSectionHost> secs;
+  std::vector<ColSectionHost> secs;  // the runs, by format
 };
 
 }  // namespace hm

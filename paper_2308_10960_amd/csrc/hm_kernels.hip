@@ -110,20 +110,24 @@ struct ColArgs {
   int64_t n_tiles;
 };
 
-// One workgroup streams one column tile.  Lane l of every wave owns the G
+// One workgroup streams one column tile.  Lane l of every wave owns the
 // columns of group l; the tile's rows go to the four waves in interleaved
 // batches of 8 (wave w takes batches w, w + 4, ...), x of 64 rows at a time
 // sits in one register per lane and is broadcast by readlane.  The four
-// waves' sums are added in a fixed order through LDS (red: 4 x 64 x G).
+// waves' sums are added in a fixed order through LDS (red: 4 x 64 x 8), and
+// wave 0 writes each column's sum to its destination (a partial, or t).
+// DT >= 0: every group of the tile has format DT; DT < 0: the tile holds
+// runs of several formats and each lane decodes its own (T.dtype, T.end).
 template <typename AccT, int DT>
 __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, AccT* red) {
-  constexpr int G = group_width(DT);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool act = lane < T.ngroups;
-  AccT acc[G];
+  const TileGroup tg = tile_group(T, act ? lane : 0);
+  const int dt = DT >= 0 ? DT : tg.dtype;
+  AccT acc[8];
 #pragma unroll
-  for (int c = 0; c < G; ++c) acc[c] = AccT(0);
-  const int rstride = T.ld * dtype_size(DT) / 16;
+  for (int c = 0; c < 8; ++c) acc[c] = AccT(0);
+  const int rstride = T.ngroups;                    // 16-byte groups per tile row
   const u32x4* p = reinterpret_cast<const u32x4*>(a.store + T.data_off) + lane;
   for (int i0 = 0; i0 < T.nrows; i0 += 64) {
     const int nr = min(64, T.nrows - i0);
@@ -137,25 +141,39 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
       for (int u = 0; u < 8; ++u)
         if (i + u < nr) {                           // uniform across the wave
           const AccT xi = bcast(xv, i + u);
-          if (act) axpy_group<AccT, DT>(r[u], xi, acc);
+          if (act) {
+            if constexpr (DT >= 0) {
+              axpy_group<AccT, DT>(r[u], xi, acc);
+            } else if (dt == HM_F32) {
+              axpy_group<AccT, HM_F32>(r[u], xi, acc);
+            } else if (dt == HM_F16) {
+              axpy_group<AccT, HM_F16>(r[u], xi, acc);
+            } else if (dt == HM_BF16) {
+              axpy_group<AccT, HM_BF16>(r[u], xi, acc);
+            } else {
+              if constexpr (sizeof(AccT) == 8) axpy_group<AccT, HM_F64>(r[u], xi, acc);
+            }
+          }
         }
     }
   }
+  constexpr int GW = DT >= 0 ? group_width(DT) : 8;   // red stride per lane
 #pragma unroll
-  for (int c = 0; c < G; ++c) red[(wave * 64 + lane) * G + c] = acc[c];
+  for (int c = 0; c < GW; ++c) red[(wave * 64 + lane) * GW + c] = acc[c];
   __syncthreads();
   if (wave == 0 && act) {
+    const int G = group_width(dt);
     // all destinations and factors first, then the stores
-    int32_t d[G];
-    AccT f[G];
+    int32_t d[GW];
+    AccT f[GW];
 #pragma unroll
-    for (int c = 0; c < G; ++c) d[c] = a.dst[T.dst_off + lane * G + c];
+    for (int c = 0; c < GW; ++c) d[c] = c < G ? a.dst[T.dst_off + tg.col + c] : kDstPad;
 #pragma unroll
-    for (int c = 0; c < G; ++c) f[c] = (d[c] <= -2 && a.sigma) ? a.sigma[dst_t_index(d[c])] : AccT(1);
+    for (int c = 0; c < GW; ++c) f[c] = (d[c] <= -2 && a.sigma) ? a.sigma[dst_t_index(d[c])] : AccT(1);
 #pragma unroll
-    for (int c = 0; c < G; ++c) {
-      const AccT sum = (red[lane * G + c] + red[(64 + lane) * G + c]) +
-                       (red[(128 + lane) * G + c] + red[(192 + lane) * G + c]);
+    for (int c = 0; c < GW; ++c) {
+      const AccT sum = (red[lane * GW + c] + red[(64 + lane) * GW + c]) +
+                       (red[(128 + lane) * GW + c] + red[(192 + lane) * GW + c]);
       if (d[c] >= 0)
         a.part[d[c]] = sum;
       else if (d[c] != kDstPad)
@@ -165,11 +183,19 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
 }
 
 // A whole workgroup on tile ti (it synchronizes).  red: 4 * 64 * 8 values
-// (four waves x 64 lanes x at most 8 columns per lane).
-template <typename AccT>
+// (four waves x 64 lanes x at most 8 columns per lane).  MIXED: the tile
+// may hold several formats (tiles from n_tiles_uniform on); else it holds
+// one (the format is dispatched once per tile).
+template <typename AccT, bool MIXED = true>
 __device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti, AccT* red) {
   const ColTile T = a.tiles[ti];
-  switch (T.dtype) {
+  if constexpr (MIXED) {
+    if (T.end[0] < T.ngroups) {                     // several formats in the tile
+      col_tile<AccT, -1>(a, T, red);
+      return;
+    }
+  }
+  switch (T.dtype[0]) {
     case HM_F64:
       if constexpr (sizeof(AccT) == 8) col_tile<AccT, HM_F64>(a, T, red);
       break;
@@ -354,12 +380,13 @@ __global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* ord
 
 // Schedule 0: all column tiles (one per workgroup item), then whole row
 // panels (dense and U sections in one pass).
-template <typename AccT>
-__global__ __launch_bounds__(256) void k_col(ColArgs<AccT> ca) {
+// Tiles [t0, t1): MIXED = false for the one-format tiles, true for the rest.
+template <typename AccT, bool MIXED>
+__global__ __launch_bounds__(256, MIXED ? 3 : 4) void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
   __shared__ AccT cred[4 * 64 * 8];
-  for (int64_t it = blockIdx.x; it < ca.n_tiles; it += gridDim.x) {
-    if (it != blockIdx.x) __syncthreads();
-    col_tile_any<AccT>(ca, it, cred);
+  for (int64_t it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
+    if (it != t0 + blockIdx.x) __syncthreads();
+    col_tile_any<AccT, MIXED>(ca, it, cred);
   }
 }
 
@@ -424,8 +451,14 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
     if (h.n_p1 > 0)
       hipLaunchKernelGGL((k_p1<AccT, CAP, U>), dim3(item_grid(h.n_p1, ps, ncu)), dim3(256), 0, s, ra,
                          ca, reinterpret_cast<const int32_t*>(st + h.off_p1_order), h.n_p1);
-  } else if (h.n_col_tiles > 0) {
-    hipLaunchKernelGGL(k_col<AccT>, dim3(item_grid(h.n_col_tiles, ps, ncu)), dim3(256), 0, s, ca);
+  } else {
+    const int64_t nu = h.tile_class_end[3], nm = h.n_col_tiles - nu;
+    if (nu > 0)
+      hipLaunchKernelGGL((k_col<AccT, false>), dim3(item_grid(nu, ps, ncu)), dim3(256), 0, s, ca,
+                         int64_t(0), nu);
+    if (nm > 0)
+      hipLaunchKernelGGL((k_col<AccT, true>), dim3(item_grid(nm, ps, ncu)), dim3(256), 0, s, ca, nu,
+                         h.n_col_tiles);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
   if (h.n_col_tiles > 0) {

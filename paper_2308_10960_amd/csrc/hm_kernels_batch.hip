@@ -85,15 +85,28 @@ __device__ __forceinline__ int mfma32x2_row(int lane, int v) {
   return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
 }
 
-// The 8 stored bytes at p as floats: 2 FP32 or 4 FP16/BF16 values.
-template <int DT>
-__device__ __forceinline__ void load8(const uint8_t* p, float (&v)[8 / dtype_size(DT)]) {
+struct ColBArgs {
+  const uint8_t* store;
+  const ColTile* tiles;
+  const int32_t* dst;
+  const float* xr;
+  float* part;            // rows of RS values; t follows at row t_row0
+  int32_t t_row0;         // column sums of blocks inside one chunk go to row t_row0 + o
+  const float* sigma;     // nullptr when no block keeps singular values
+  int64_t n_tiles;
+  int RS, RH;
+};
+
+// The 8 bytes at p as floats: 2 FP32 values (v[2], v[3] = 0) or 4 FP16 or
+// BF16 values.
+__device__ __forceinline__ void load_slot(const uint8_t* p, int dt, float (&v)[4]) {
   typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
   const u32x2 r = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
-  if constexpr (DT == HM_F32) {
+  if (dt == HM_F32) {
     v[0] = __uint_as_float(r[0]);
     v[1] = __uint_as_float(r[1]);
-  } else if constexpr (DT == HM_F16) {
+    v[2] = v[3] = 0.f;
+  } else if (dt == HM_F16) {
     typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
     const f16x4 h = __builtin_bit_cast(f16x4, r);
 #pragma unroll
@@ -107,71 +120,59 @@ __device__ __forceinline__ void load8(const uint8_t* p, float (&v)[8 / dtype_siz
   }
 }
 
-struct ColBArgs {
-  const uint8_t* store;
-  const ColTile* tiles;
-  const int32_t* dst;
-  const float* xr;
-  float* part;            // rows of RS values; t follows at row t_row0
-  int32_t t_row0;         // column sums of blocks inside one chunk go to row t_row0 + o
-  const float* sigma;     // nullptr when no block keeps singular values
-  int64_t n_tiles;
-  int RS, RH;
-};
-
-// One wave (a workgroup of its own): a quarter of a column tile -- 32 x CPL
-// columns, CPL = 8 bytes / storage size -- for 32 right-hand sides (group rh
-// of RS).  Lane l owns columns c0 + CPL (l % 32) + q, q < CPL, of row
-// i + l / 32: one v_mfma_f32_32x32x2_f32 per q takes two rows at a time (A:
-// the lane's value of column q; B: the x rows i and i + 1 of the 32
-// right-hand sides, one load for both).  Rows go in batches of S steps (2S
-// rows); with DB the next batch's loads are in flight while this batch's
-// MFMAs run.  wd, ws: the wave's LDS tables of destination rows (in part,
-// whose rows from t_row0 on are t) and factors (s_b[l] for a column that
-// writes t directly, else 1).
+// One wave (a workgroup of its own): slots [32 quarter, 32 quarter + 32) of
+// a column tile for 32 right-hand sides (group rh of RS).  Slot s is bytes
+// [8 s, 8 s + 8) of every tile row: half of group s / 2, i.e. 2 FP32 or 4
+// FP16/BF16 columns.  Lane l owns slot 32 quarter + l % 32 of row i + l / 32:
+// one v_mfma_f32_32x32x2_f32 per column q < CPL of the slot takes two rows
+// at a time (A: the lane's value of column q; B: the x rows i and i + 1 of
+// the 32 right-hand sides, one load for both).  DT >= 0: every slot has
+// format DT (CPL = its columns per slot); DT < 0: the tile holds runs of
+// several formats, CPL = 4 and an FP32 slot leaves columns 2 and 3 empty.
+// Rows go in batches of S steps (2S rows); with DB the next batch's loads
+// are in flight while this batch's MFMAs run.  wd, ws: the wave's LDS
+// tables of destination rows (in part, whose rows from t_row0 on are t) and
+// factors (s_b[l] for a column that writes t directly, else 1).
 template <int DT, int S, bool DB>
 __device__ __forceinline__ void colb_part(const ColBArgs& a, const ColTile& T, int quarter, int rh,
                                           int lane, int32_t* wd, float* ws) {
-  constexpr int SZ = dtype_size(DT), CPL = 8 / SZ;
-  const int ncols = T.ngroups * group_width(DT);
-  const int c0 = quarter * 32 * CPL;
-  if (c0 >= ncols) return;                          // uniform: nothing in this quarter
+  constexpr int CPL = DT == HM_F32 ? 2 : 4;
   const int l32 = lane & 31, hi = lane >> 5;
-  const int cb = c0 + CPL * l32;
-  const bool act = cb < ncols;                      // all CPL columns or none
-  if (lane < 32) {
-#pragma unroll
-    for (int q = 0; q < CPL; ++q) {
-      // row of part (partials, then t) the column's sum goes to, and its factor
-      const int32_t e = act ? a.dst[T.dst_off + cb + q] : kDstPad;
-      const bool direct = e <= -2;
-      wd[CPL * lane + q] = direct ? a.t_row0 + dst_t_index(e) : e;
-      ws[CPL * lane + q] = (direct && a.sigma) ? a.sigma[dst_t_index(e)] : 1.f;
-    }
+  const int sl = 32 * quarter + l32;
+  const bool act = sl < 2 * T.ngroups;
+  int dt, cps, col;                                  // format, columns, first tile column of the slot
+  if constexpr (DT >= 0) {
+    dt = DT;
+    cps = CPL;
+    col = sl * CPL;
+  } else {
+    const TileGroup tg = tile_group(T, act ? sl / 2 : 0);
+    dt = tg.dtype;
+    cps = group_width(dt) / 2;
+    col = tg.col + (sl % 2) * cps;
   }
-  __builtin_amdgcn_wave_barrier();
   f32x16 acc[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) acc[q] = (f32x16)(0.f);
-  const size_t rstride = (size_t)T.ld * SZ;
-  const uint8_t* base = a.store + T.data_off + (size_t)hi * rstride + (size_t)cb * SZ;
+  const size_t rstride = (size_t)T.ngroups * 16;
+  const uint8_t* base = a.store + T.data_off + (size_t)hi * rstride + (size_t)(act ? sl : 0) * 8;
   const float* xb = a.xr + ((size_t)T.x0 + hi) * a.RS + rh * 32 + l32;
   const int nr = T.nrows;
   // step k covers rows 2k, 2k + 1; lanes of a missing row give zeros
   const int nsteps = (nr + 1) / 2;
-  float an[S][CPL], bn[S];
+  float an[S][4], bn[S];
   auto issue = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < S; ++u) {
       const int r = 2 * (k0 + u) + hi;
       const bool ok = r < nr;
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) an[u][q] = 0.f;
-      if (act && ok) load8<DT>(base + (size_t)(2 * (k0 + u)) * rstride, an[u]);
+      for (int q = 0; q < 4; ++q) an[u][q] = 0.f;
+      if (act && ok) load_slot(base + (size_t)(2 * (k0 + u)) * rstride, dt, an[u]);
       bn[u] = ok ? xb[(size_t)(2 * (k0 + u)) * a.RS] : 0.f;
     }
   };
-  auto compute = [&](int k, const float (&av)[S][CPL], const float (&bv)[S]) {
+  auto compute = [&](int k, const float (&av)[S][4], const float (&bv)[S]) {
 #pragma unroll
     for (int u = 0; u < S; ++u) {
       if (k + u >= nsteps) break;                   // uniform across the wave
@@ -179,15 +180,20 @@ __device__ __forceinline__ void colb_part(const ColBArgs& a, const ColTile& T, i
       for (int q = 0; q < CPL; ++q) acc[q] = mfma32x2(av[u][q], bv[u], acc[q]);
     }
   };
+  // the first loads of the tile and the destinations of the lane's columns
+  // go out together; the factors and the LDS tables follow the main loop
+  if constexpr (DB) issue(0);
+  int32_t e[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) e[q] = (lane < 32 && act && q < cps) ? a.dst[T.dst_off + col + q] : kDstPad;
   if constexpr (DB) {
-    issue(0);
     for (int k = 0; k < nsteps; k += S) {
-      float ac[S][CPL], bc[S];
+      float ac[S][4], bc[S];
 #pragma unroll
       for (int u = 0; u < S; ++u) {
         bc[u] = bn[u];
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) ac[u][q] = an[u][q];
+        for (int q = 0; q < 4; ++q) ac[u][q] = an[u][q];
       }
       if (k + S < nsteps) issue(k + S);
       compute(k, ac, bc);
@@ -198,14 +204,24 @@ __device__ __forceinline__ void colb_part(const ColBArgs& a, const ColTile& T, i
       compute(k, an, bn);
     }
   }
+  if (lane < 32) {
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      // row of part (partials, then t) the column's sum goes to, and its factor
+      const bool direct = e[q] <= -2;
+      wd[CPL * lane + q] = direct ? a.t_row0 + dst_t_index(e[q]) : e[q];
+      ws[CPL * lane + q] = (direct && a.sigma) ? a.sigma[dst_t_index(e[q])] : 1.f;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
   const int j = rh * 32 + l32;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    const int col = CPL * mfma32x2_row(lane, v);    // first column of that D row
+    const int slot = mfma32x2_row(lane, v);         // the slot (D row) of this result
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
-      const int32_t e = wd[col + q];                // -1: padding or no column
-      if (e >= 0) a.part[(size_t)e * a.RS + j] = acc[q][v] * ws[col + q];
+      const int32_t e = wd[CPL * slot + q];          // -1: padding or no column
+      if (e >= 0) a.part[(size_t)e * a.RS + j] = acc[q][v] * ws[CPL * slot + q];
     }
   }
 }
@@ -217,8 +233,11 @@ __device__ __forceinline__ void colb_part(const ColBArgs& a, const ColTile& T, i
 constexpr int kColBSteps = COLB_STEPS;
 constexpr bool kColBDouble = COLB_DOUBLE;
 
-// Workgroup (one wave) w -> (tile, quarter, right-hand-side group).
-__global__ __launch_bounds__(64) void k_col_b(ColBArgs a) {
+// Workgroup (one wave) w -> (tile t0 + w / (4 RH), quarter, right-hand-side
+// group) over the tiles [t0, t1) of one class: one format DT, or DT < 0
+// for tiles with runs of several formats.
+template <int DT>
+__global__ __launch_bounds__(64) void k_col_b(ColBArgs a, int64_t t0, int64_t t1) {
   __shared__ int32_t sdst[128];
   __shared__ float ssig[128];
   const int lane = threadIdx.x;
@@ -226,15 +245,12 @@ __global__ __launch_bounds__(64) void k_col_b(ColBArgs a) {
   const int rh = (int)(w % a.RH);
   const int64_t rest = w / a.RH;
   const int quarter = (int)(rest & 3);
-  const int64_t ti = rest >> 2;
-  if (ti >= a.n_tiles) return;
+  const int64_t ti = t0 + (rest >> 2);
+  if (ti >= t1) return;
   const ColTile T = a.tiles[ti];
-  switch (T.dtype) {
-    case HM_F32: colb_part<HM_F32, kColBSteps, kColBDouble>(a, T, quarter, rh, lane, sdst, ssig); break;
-    case HM_F16: colb_part<HM_F16, kColBSteps, kColBDouble>(a, T, quarter, rh, lane, sdst, ssig); break;
-    case HM_BF16: colb_part<HM_BF16, kColBSteps, kColBDouble>(a, T, quarter, rh, lane, sdst, ssig); break;
-    default: break;
-  }
+  if (32 * quarter >= 2 * T.ngroups) return;         // uniform: nothing in this quarter
+  // 4-column slots: half the steps per batch (register budget)
+  colb_part<DT, DT == HM_F32 ? kColBSteps : kColBSteps / 2, kColBDouble>(a, T, quarter, rh, lane, sdst, ssig);
 }
 
 struct RedBArgs {
@@ -502,8 +518,17 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
       ColBArgs ca{st, reinterpret_cast<const ColTile*>(st + h.off_col_tiles),
                   reinterpret_cast<const int32_t*>(st + h.off_col_dst), xr, part,
                   (int32_t)(A.work_part_bytes / (int64_t)sizeof(float)), sigma, h.n_col_tiles, RS, RH};
-      const int64_t waves = h.n_col_tiles * 4 * RH;
-      hipLaunchKernelGGL(k_col_b, dim3((unsigned)waves), dim3(64), 0, s, ca);
+      // one launch per tile class (FP64 tiles do not occur with FP32 accumulation)
+      const int64_t* ce = h.tile_class_end;
+      auto grid = [&](int64_t t0, int64_t t1) { return dim3((unsigned)((t1 - t0) * 4 * RH)); };
+      if (ce[1] > ce[0])
+        hipLaunchKernelGGL(k_col_b<HM_F32>, grid(ce[0], ce[1]), dim3(64), 0, s, ca, ce[0], ce[1]);
+      if (ce[2] > ce[1])
+        hipLaunchKernelGGL(k_col_b<HM_F16>, grid(ce[1], ce[2]), dim3(64), 0, s, ca, ce[1], ce[2]);
+      if (ce[3] > ce[2])
+        hipLaunchKernelGGL(k_col_b<HM_BF16>, grid(ce[2], ce[3]), dim3(64), 0, s, ca, ce[2], ce[3]);
+      if (ce[4] > ce[3])
+        hipLaunchKernelGGL(k_col_b<-1>, grid(ce[3], ce[4]), dim3(64), 0, s, ca, ce[3], ce[4]);
       if (ev && r0 == 0) (void)hipEventRecord(ev[1], s);
       RedBArgs rb{reinterpret_cast<const TBlock*>(st + h.off_tblocks),
                   reinterpret_cast<const int32_t*>(st + h.off_owner), sigma, part, t, h.n_red_t, RS};

@@ -66,15 +66,34 @@ struct RowSection {      // 32 bytes
   int32_t pad_[3];
 };
 
-struct ColTile {         // 32 bytes: one wave streams nrows rows x ngroups*G columns
-  int64_t data_off;      // byte offset of the tile (row 0, first column)
-  int32_t ld;            // row stride inside the tile, in elements (= ngroups*G)
+struct ColTile {         // 32 bytes: nrows rows x ngroups 16-byte groups
+  int64_t data_off;      // byte offset of the tile (row 0, first group); row i at + 16 i ngroups
   int32_t nrows;         // rows of the column chunk (<= 512)
-  int32_t x0;            // first x index of the interval
-  int32_t dtype;
+  int32_t x0;            // first x index of the chunk
   int32_t ngroups;       // groups in this tile (<= 64)
   int32_t dst_off;       // first entry (int32 units) of this tile in the destination table
+  uint8_t dtype[4];      // storage format of run r of groups (formats in ascending order)
+  uint8_t end[4];        // end (exclusive) of run r, in groups; end[3] == ngroups
 };
+
+// Run, format and first column (in the tile's column order: run by run,
+// group by group) of group g of tile T (constant indices only, so that a
+// descriptor in registers stays there).
+struct TileGroup { int run, dtype, col; };
+inline constexpr TileGroup tile_group(const ColTile& T, int g) {
+  const int r = (g >= T.end[0]) + (g >= T.end[1]) + (g >= T.end[2]);
+  int col = 0, start = 0, dt = T.dtype[0];
+  for (int q = 0; q < 4; ++q) {                     // unrolled: constant indices
+    if (q == r) {
+      dt = T.dtype[q];
+      col += (g - start) * group_width(T.dtype[q]);
+    } else if (q < r) {
+      col += (T.end[q] - start) * group_width(T.dtype[q]);
+      start = T.end[q];
+    }
+  }
+  return TileGroup{r, dt, col};
+}
 
 // Destination of a column sum (one int32 per tile column): e >= 0 is the
 // partial e; e == -1 is a padding column; e <= -2 is t entry -e - 2 (the
@@ -109,7 +128,14 @@ struct StoreHeader {
   // the blocks inside one column chunk, [n_red_t, n_t), get t directly from
   // the column tiles
   int64_t n_red_t;
+  // column tiles by class, each class largest first: tiles of one storage
+  // format f (FP64, FP32, FP16, BF16) are [tile_class_end[f-1], tile_class_end[f]),
+  // tiles with runs of several formats [tile_class_end[3], tile_class_end[4])
+  int64_t tile_class_end[5];
 };
+
+// Class of a column tile: its format if it has one, else 4.
+inline constexpr int tile_class(const ColTile& T) { return T.end[0] == T.ngroups ? T.dtype[0] : 4; }
 
 constexpr uint64_t kStoreMagic = 0x484d53544f524532ull;  // "HMSTORE2"
 

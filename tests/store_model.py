@@ -22,8 +22,8 @@ RP = np.dtype([("src_off", "<i8"), ("row0", "<i4"), ("m", "<i4"), ("ncols", "<i4
                ("sec0", "<i4"), ("nsec", "<i4"), ("pad", "<i4")])
 RS = np.dtype([("data_off", "<i8"), ("dtype", "<i4"), ("ngroups", "<i4"), ("col0", "<i4"),
                ("pad", "<i4", (3,))])
-CT = np.dtype([("data_off", "<i8"), ("ld", "<i4"), ("nrows", "<i4"), ("x0", "<i4"),
-               ("dtype", "<i4"), ("ngroups", "<i4"), ("dst_off", "<i4")])
+CT = np.dtype([("data_off", "<i8"), ("nrows", "<i4"), ("x0", "<i4"), ("ngroups", "<i4"),
+               ("dst_off", "<i4"), ("dtype", "u1", (4,)), ("end", "u1", (4,))])
 TB = np.dtype([("pst", "<i4"), ("k", "<i4"), ("nseg", "<i4"), ("toff", "<i4")])
 G = {0: 2, 1: 4, 2: 8, 3: 8}
 SZ = {0: 8, 1: 4, 2: 2, 3: 2}
@@ -61,10 +61,19 @@ def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> n
     written = np.zeros(int(h["n_t"]), bool)
     dst_all = buf[h["off_col_dst"]:].view("<i4")
     for t in T["ct"]:
-        g, nr, ld, dt = G[int(t["dtype"])], int(t["nrows"]), int(t["ld"]), int(t["dtype"])
-        cols = int(t["ngroups"]) * g
-        rows = [decode(buf, int(t["data_off"]) + i * ld * SZ[dt], cols, dt) for i in range(nr)]
-        V = np.stack(rows)                                   # nr x cols
+        nr, ng = int(t["nrows"]), int(t["ngroups"])
+        # a tile row is ng 16-byte groups, in runs of one format each
+        raw = buf[int(t["data_off"]): int(t["data_off"]) + nr * ng * 16].reshape(nr, ng * 16)
+        parts, g0 = [], 0
+        for r in range(4):
+            e, dt = int(t["end"][r]), int(t["dtype"][r])
+            if e > g0:
+                block = np.ascontiguousarray(raw[:, 16 * g0: 16 * e]).reshape(-1)
+                parts.append(decode(block, 0, block.size // SZ[dt], dt).reshape(nr, -1))
+            g0 = e
+        assert g0 == ng
+        V = np.concatenate(parts, axis=1)                    # nr x cols (tile column order)
+        cols = V.shape[1]
         p = V.T @ x[int(t["x0"]): int(t["x0"]) + nr]
         d = dst_all[int(t["dst_off"]): int(t["dst_off"]) + cols]
         part[d[d >= 0]] = p[d >= 0]

@@ -139,11 +139,16 @@ def test_storage_conversion_bit_exact(mixed4k):
     hm.hm_plan_destroy(p)
 
 
-@pytest.mark.parametrize("which", ["f64", "mixed"])
+@pytest.mark.parametrize("which", ["f64", "mixed", "mixed16k"])
 def test_store_model_matches_oracle(which, f64_4k, mixed4k):
-    H = f64_4k if which == "f64" else mixed4k
+    """The packed store, read as its layout defines it, gives the oracle's
+    product.  At n = 16384 some blocks span several column chunks (partials
+    and their reduction); column tiles hold runs of several formats."""
+    H = {"f64": f64_4k, "mixed": mixed4k}.get(which) or hmgen.build_preset("sphere4k_mixed", n=16384)
     acc = hm.HM_F64 if which == "f64" else hm.HM_F32
     p, info, buf = _pack(H, acc)
+    if which == "mixed16k":
+        assert info["n_partials"] > 0
     x = hmgen.uniform_vector(H.n)
     y0 = hmgen.uniform_vector(H.n, seed=5)
     if which == "f64":
