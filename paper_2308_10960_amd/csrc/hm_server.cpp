@@ -1,17 +1,21 @@
 // Request loop of libhm: continuous batching of H-matrix-vector products
 // against device-resident matrices.
 //
-// Clients call hm_submit(matrix, X) from any thread; a scheduler thread
+// Clients call hm_submit(matrix, X) from any thread; a dispatcher thread
 //  * admits requests by device-memory budget: a batch's vectors and
 //    workspace are carved out of the caller's arena with a first-fit
 //    allocator, and a batch that does not fit waits for running ones to
 //    release memory;
 //  * batches queued requests of the same matrix (FIFO, up to the matrix's
 //    max_nrhs right-hand sides) into one hm_mvm_batch call;
-//  * keeps up to n_streams batches in flight, one per stream, so requests
-//    arriving while others run start as soon as a stream slot and memory
-//    free up (no waiting for the whole previous batch set);
-//  * copies results back, completes tickets, and records latency.
+//  * keeps up to n_streams batches in flight, one per stream slot, so
+//    requests arriving while others run start as soon as a slot and memory
+//    free up (no waiting for the whole previous batch set).
+// Each slot has a worker thread that gathers its batch's right-hand sides
+// into pinned memory, enqueues copy, product and copy-back on its stream,
+// waits for them, scatters the results into the clients' buffers and
+// completes the tickets (latency recorded at completion); the host copies
+// of different slots run in parallel, outside the server lock.
 // A request's result does not depend on the batch it lands in: every column
 // of a batch is computed by the same kernels in the same order.
 //
@@ -94,15 +98,18 @@ class Arena {
   std::map<size_t, size_t> free_;
 };
 
+enum class SlotState { kIdle, kAssigned, kRunning };
+
 struct Slot {
   hipStream_t stream = nullptr;
-  hipEvent_t done_ev = nullptr;
-  bool busy = false;
+  SlotState state = SlotState::kIdle;   // guarded by the server lock
+  bool fault = false;                   // injected failure for this batch
   std::vector<std::shared_ptr<Request>> reqs;
   size_t off = 0, bytes = 0;
   int32_t mat = 0, nrhs = 0;
-  void* pinned = nullptr;
+  void* pinned = nullptr;               // owned by the slot's worker
   size_t pinned_bytes = 0;
+  std::thread worker;
 };
 
 }  // namespace
@@ -113,7 +120,9 @@ struct hm_server {
   std::unique_ptr<Arena> arena;
   std::vector<Slot> slots;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_assign;
+  int device = 0;
+  bool stop_workers = false;
   std::deque<std::shared_ptr<Request>> queue;
   std::map<uint64_t, std::shared_ptr<Request>> tickets;
   uint64_t next_ticket = 1;
@@ -149,8 +158,10 @@ void finish(hm_server* S, const std::shared_ptr<Request>& q, hm_status st, Clock
   S->t_last = now;
 }
 
-// Enqueue one batch on a slot (lock held by caller).
-hm_status launch_batch(hm_server* S, Slot& sl) {
+// Run one batch on its slot (worker thread, server lock not held): gather
+// the right-hand sides into pinned memory, enqueue copy, product and
+// copy-back, wait, scatter the results.
+hm_status run_batch(hm_server* S, Slot& sl) {
   const hm_matrix* A = S->mats[sl.mat];
   const size_t vs = A->acc_dtype == HM_F64 ? 8 : 4;
   const int64_t nr = A->hdr.n_rows, nc = A->hdr.n_cols;
@@ -176,62 +187,59 @@ hm_status launch_batch(hm_server* S, Slot& sl) {
   uint8_t* dY = base + align256(xbytes);
   uint8_t* dW = dY + align256(ybytes);
   const size_t wbytes = (size_t)hm::batch_slots(A->acc_dtype, sl.nrhs) * A->work_bytes_per_rhs;
+  hm_status st = HM_OK;
   if (hipMemcpyAsync(dX, px, xbytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
       hipMemsetAsync(dY, 0, ybytes, sl.stream) != hipSuccess)
-    return HM_EDEVICE;
-  hm_status st = hm_mvm_batch(A, sl.nrhs, 1.0, dX, nc, dY, nr, dW, wbytes, sl.stream);
-  if (st) return st;
-  if (hipMemcpyAsync(px + xbytes, dY, ybytes, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
-      hipEventRecord(sl.done_ev, sl.stream) != hipSuccess)
-    return HM_EDEVICE;
+    st = HM_EDEVICE;
+  if (st == HM_OK) st = hm_mvm_batch(A, sl.nrhs, 1.0, dX, nc, dY, nr, dW, wbytes, sl.stream);
+  if (st == HM_OK && hipMemcpyAsync(px + xbytes, dY, ybytes, hipMemcpyDeviceToHost, sl.stream) != hipSuccess)
+    st = HM_EDEVICE;
+  if (hipStreamSynchronize(sl.stream) != hipSuccess && st == HM_OK) st = HM_EDEVICE;
+  if (st != HM_OK) return st;
+  const uint8_t* py = px + xbytes;
+  col = 0;
+  for (auto& q : sl.reqs) {
+    for (int32_t c = 0; c < q->nrhs; ++c)
+      std::memcpy((uint8_t*)q->hy + (size_t)c * q->ldy * vs, py + (size_t)(col + c) * nr * vs,
+                  (size_t)nr * vs);
+    col += q->nrhs;
+  }
   return HM_OK;
 }
 
-void complete_slot(hm_server* S, Slot& sl, hm_status st) {
-  const hm_matrix* A = S->mats[sl.mat];
-  const size_t vs = A->acc_dtype == HM_F64 ? 8 : 4;
-  const int64_t nr = A->hdr.n_rows, nc = A->hdr.n_cols;
-  const uint8_t* py = (const uint8_t*)sl.pinned + (size_t)nc * sl.nrhs * vs;
-  const auto now = Clock::now();
-  int32_t col = 0;
-  for (auto& q : sl.reqs) {
-    if (st == HM_OK)
-      for (int32_t c = 0; c < q->nrhs; ++c)
-        std::memcpy((uint8_t*)q->hy + (size_t)c * q->ldy * vs, py + (size_t)(col + c) * nr * vs,
-                    (size_t)nr * vs);
-    col += q->nrhs;
-    finish(S, q, st, now);
+void worker(hm_server* S, Slot* sl) {
+  (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    S->cv_assign.wait(lk, [&] { return sl->state == SlotState::kAssigned || S->stop_workers; });
+    if (sl->state != SlotState::kAssigned) break;
+    sl->state = SlotState::kRunning;
+    lk.unlock();
+    const hm_status st = sl->fault ? HM_EDEVICE : run_batch(S, *sl);
+    lk.lock();
+    const auto now = Clock::now();
+    for (auto& q : sl->reqs) finish(S, q, st, now);
+    S->arena->release(sl->off, sl->bytes);
+    sl->reqs.clear();
+    sl->state = SlotState::kIdle;
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
   }
-  S->arena->release(sl.off, sl.bytes);
-  sl.reqs.clear();
-  sl.busy = false;
 }
 
+// Dispatcher: forms batches and hands them to idle slots.
 void loop(hm_server* S) {
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
-    bool progressed = false;
-    // completions
+    bool assigned = false;
     for (auto& sl : S->slots) {
-      if (!sl.busy) continue;
-      hipError_t e = hipEventQuery(sl.done_ev);
-      if (e == hipErrorNotReady) continue;
-      complete_slot(S, sl, e == hipSuccess ? HM_OK : HM_EDEVICE);
-      progressed = true;
-    }
-    if (progressed) S->cv_done.notify_all();
-    // dispatch: fill free slots from the queue
-    bool any_busy = false;
-    for (auto& sl : S->slots) any_busy |= sl.busy;
-    for (auto& sl : S->slots) {
-      if (sl.busy || S->queue.empty()) continue;
+      if (sl.state != SlotState::kIdle || S->queue.empty()) continue;
       auto head = S->queue.front();
       const hm_matrix* A = S->mats[head->mat];
       if (footprint(A, head->nrhs) > S->arena->size()) {   // can never fit
         S->queue.pop_front();
         finish(S, head, HM_ENOMEM, Clock::now());
         S->cv_done.notify_all();
-        progressed = true;
         continue;
       }
       // gather same-matrix requests in FIFO order up to max_nrhs
@@ -264,29 +272,17 @@ void loop(hm_server* S) {
       sl.bytes = footprint(A, r);
       sl.mat = head->mat;
       sl.nrhs = r;
-      sl.busy = true;
       ++S->batches;
-      hm_status st = HM_OK;
-      if (S->fault_every > 0 && S->batches % S->fault_every == 0) st = HM_EDEVICE;
-      else st = launch_batch(S, sl);
-      if (st != HM_OK) {
-        (void)hipStreamSynchronize(sl.stream);
-        complete_slot(S, sl, st);
-        S->cv_done.notify_all();
-      }
-      progressed = true;
-      any_busy = true;
+      sl.fault = S->fault_every > 0 && S->batches % S->fault_every == 0;
+      sl.state = SlotState::kAssigned;
+      assigned = true;
     }
+    if (assigned) S->cv_assign.notify_all();
+    bool any_busy = false;
+    for (auto& sl : S->slots) any_busy |= sl.state != SlotState::kIdle;
     if (S->stop && S->queue.empty() && !any_busy) break;
-    if (!progressed) {
-      if (any_busy) {
-        lk.unlock();
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
-        lk.lock();
-      } else {
-        S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
-      }
-    }
+    // woken by a submission, a completed batch or a stop (bounded wait as a backstop)
+    S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
   }
 }
 
@@ -309,15 +305,11 @@ hm_status hm_server_create(hm_matrix* const* mats, int32_t n_mats, void* d_arena
   S->arena_base = (uint8_t*)d_arena;
   S->arena = std::make_unique<Arena>(arena_bytes / 256 * 256);
   S->slots.resize(n_streams);
-  for (int32_t i = 0; i < n_streams; ++i) {
-    S->slots[i].stream = (hipStream_t)streams[i];
-    if (hipEventCreateWithFlags(&S->slots[i].done_ev, hipEventDisableTiming) != hipSuccess) {
-      for (int32_t j = 0; j < i; ++j) (void)hipEventDestroy(S->slots[j].done_ev);
-      return fail(HM_EDEVICE, "event creation failed");
-    }
-  }
+  for (int32_t i = 0; i < n_streams; ++i) S->slots[i].stream = (hipStream_t)streams[i];
+  S->device = mats[0]->device;
   if (const char* f = std::getenv("HM_SERVER_FAULT_EVERY")) S->fault_every = std::atoll(f);
   hm_server* raw = S.release();
+  for (auto& sl : raw->slots) sl.worker = std::thread(worker, raw, &sl);
   raw->thread = std::thread(loop, raw);
   *out = raw;
   return hm::ok();
@@ -398,9 +390,14 @@ void hm_server_destroy(hm_server* s) {
     s->stop = true;
   }
   s->cv_work.notify_all();
-  if (s->thread.joinable()) s->thread.join();
+  if (s->thread.joinable()) s->thread.join();       // queue drained, every slot idle
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop_workers = true;
+  }
+  s->cv_assign.notify_all();
   for (auto& sl : s->slots) {
-    if (sl.done_ev) (void)hipEventDestroy(sl.done_ev);
+    if (sl.worker.joinable()) sl.worker.join();
     if (sl.pinned) (void)hipHostFree(sl.pinned);
   }
   delete s;
