@@ -73,8 +73,10 @@ def test_cube1m_batched_sampled_rows():
     absf = [(np.abs(a), None if b is None else np.abs(b), s) for a, b, s in dec]
     scale = oracle.hmvm_multi(H, np.abs(X), factors=absf, blocks=blk)[rows]
     Ys = Y[rows]
-    # rigorous elementwise FP32 bound (K = all summands of a row, nested)
-    K = H.n + int(np.sum(np.where(H.adm[blk] != 0, H.rank[blk], 0)))
+    # rigorous elementwise FP32 bound: K bounds the roundings on any path into
+    # a sampled output (n column terms, the ranks and the number of the
+    # leaves that cover its row, 8 for product, s_b, alpha and the update)
+    K = H.n + int(np.sum(np.where(H.adm[blk] != 0, H.rank[blk], 0))) + int(blk.size) + 8
     gam = K * U32 / (1 - K * U32)
     assert np.all(np.abs(Ys - ref) <= gam * scale)
     rel_dec = np.linalg.norm(Ys - ref) / np.linalg.norm(ref)

@@ -57,6 +57,21 @@ def abs_bound(H, x, factors=None):
     return oracle.hmvm(H, np.abs(x), factors=fac)
 
 
+def fp32_depth(H):
+    """Bound on the number of roundings on any path into one output entry:
+    y_i sums, over the leaves covering row i, their dense row or U_i t with
+    t_l = sum_j V_jl x_j; every path meets at most n column terms, the
+    ranks of the low-rank leaves covering row i, one addition per leaf and
+    a few roundings of its own (product, s_b, alpha, the update of y: 8).
+    gamma_K (|A| |x|) then bounds the error for any order of summation."""
+    n = H.n
+    acc = np.zeros(n + 1)
+    lr = np.asarray(H.adm) != 0
+    np.add.at(acc, np.asarray(H.rb), np.where(lr, H.rank, 0) + 1)
+    np.add.at(acc, np.asarray(H.re), -(np.where(lr, H.rank, 0) + 1))
+    return int(n + np.cumsum(acc)[:n].max()) + 8
+
+
 def check_f64(y, ref, scale, tol=F64_TOL):
     rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
     say(f"relative error {rel:.3e}")
@@ -188,8 +203,8 @@ def _mixed(H, name):
     dec = oracle.decoded_factors(H, sigma_dtype=oracle.F32)
     ref_dec = oracle.hmvm(H, x, factors=dec)
     truth = oracle.hmvm(H, x)
-    # rigorous FP32 summation bound: |err| <= gamma_K * (|A_dec| |x|), K = longest sum
-    K = 4096 + 64
+    # rigorous FP32 summation bound: |err| <= gamma_K * (|A_dec| |x|)
+    K = fp32_depth(H)
     gam = K * U32 / (1 - K * U32)
     scale = abs_bound(H, x, dec)
     err = np.abs(y - ref_dec)
@@ -233,7 +248,7 @@ def test_batched_f32_mfma(name):
     Y0 = hmgen.gaussian_block(H.n, 70, seed=7).astype(np.float32).astype(np.float64)
     Y = _batch(D, X, -0.5, Y0)
     ref = oracle.hmvm_multi(H, X, Y0, alpha=-0.5, factors=dec)
-    K = 4096 + 64
+    K = fp32_depth(H)
     gam = K * U32 / (1 - K * U32)
     worst = 0.0
     for c in range(70):
