@@ -427,6 +427,8 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
     ColPanelHost& Cp = P->cps[q];
     Cp.x0 = chunks[q].first;
     Cp.nrows = (int32_t)(chunks[q].second - chunks[q].first);
+    if (Cp.nrows < 1 || Cp.nrows > kSegRows)           // the kernels stage a chunk's x in LDS
+      return fail(HM_EINVAL, "internal error: column chunk of %d rows", Cp.nrows);
     for (int64_t c = ccnt[q]; c < ccnt[q + 1]; ++c) {
       const int32_t i = ccover[c];
       const auto& b = P->blocks[i];

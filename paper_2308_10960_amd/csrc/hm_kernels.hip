@@ -112,14 +112,16 @@ struct ColArgs {
 
 // One workgroup streams one column tile.  Lane l of every wave owns the
 // columns of group l; the tile's rows go to the four waves in interleaved
-// batches of 8 (wave w takes batches w, w + 4, ...), x of 64 rows at a time
-// sits in one register per lane and is broadcast by readlane.  The four
-// waves' sums are added in a fixed order through LDS (red: 4 x 64 x 8), and
-// wave 0 writes each column's sum to its destination (a partial, or t).
-// DT >= 0: every group of the tile has format DT; DT < 0: the tile holds
-// runs of several formats and each lane decodes its own (T.dtype, T.end).
+// batches of 8 (wave w takes rows 32 j + 8 w + [0, 8) for j = 0, 1, ...),
+// and the loads of a wave's next batch are in flight while it computes the
+// current one.  x of the tile's rows is staged in LDS once (xs) and read
+// as a broadcast.  The four waves' sums are added in a fixed order through
+// LDS (red: 4 x 64 x 8), and wave 0 writes each column's sum to its
+// destination (a partial, or t).  DT >= 0: every group of the tile has
+// format DT; DT < 0: the tile holds runs of several formats and each lane
+// decodes its own (T.dtype, T.end).
 template <typename AccT, int DT>
-__device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, AccT* red) {
+__device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, AccT* red, AccT* xs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool act = lane < T.ngroups;
   const TileGroup tg = tile_group(T, act ? lane : 0);
@@ -128,34 +130,43 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = AccT(0);
   const int rstride = T.ngroups;                    // 16-byte groups per tile row
+  const int nrows = T.nrows;
   const u32x4* p = reinterpret_cast<const u32x4*>(a.store + T.data_off) + lane;
-  for (int i0 = 0; i0 < T.nrows; i0 += 64) {
-    const int nr = min(64, T.nrows - i0);
-    const AccT xv = lane < nr ? a.x[T.x0 + i0 + lane] : AccT(0);
-    for (int i = 8 * wave; i < nr; i += 32) {
-      u32x4 r[8];
+  const int nb = nrows > 8 * wave ? (nrows - 8 * wave + 31) / 32 : 0;   // this wave's batches
+  u32x4 rn[8];
+  auto issue = [&](int j) {
+    const int r0 = 32 * j + 8 * wave;
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (act && i + u < nr) r[u] = ld16(p + (size_t)(i0 + i + u) * rstride);
+    for (int u = 0; u < 8; ++u)
+      if (act && r0 + u < nrows) rn[u] = ld16(p + (size_t)(r0 + u) * rstride);
+  };
+  if (nb > 0) issue(0);
+  for (int i = threadIdx.x; i < nrows; i += 256) xs[i] = a.x[T.x0 + i];
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    u32x4 rc[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (i + u < nr) {                           // uniform across the wave
-          const AccT xi = bcast(xv, i + u);
-          if (act) {
-            if constexpr (DT >= 0) {
-              axpy_group<AccT, DT>(r[u], xi, acc);
-            } else if (dt == HM_F32) {
-              axpy_group<AccT, HM_F32>(r[u], xi, acc);
-            } else if (dt == HM_F16) {
-              axpy_group<AccT, HM_F16>(r[u], xi, acc);
-            } else if (dt == HM_BF16) {
-              axpy_group<AccT, HM_BF16>(r[u], xi, acc);
-            } else {
-              if constexpr (sizeof(AccT) == 8) axpy_group<AccT, HM_F64>(r[u], xi, acc);
-            }
+    for (int u = 0; u < 8; ++u) rc[u] = rn[u];
+    if (j + 1 < nb) issue(j + 1);
+    const int r0 = 32 * j + 8 * wave;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (r0 + u < nrows) {                         // uniform across the wave
+        const AccT xi = xs[r0 + u];
+        if (act) {
+          if constexpr (DT >= 0) {
+            axpy_group<AccT, DT>(rc[u], xi, acc);
+          } else if (dt == HM_F32) {
+            axpy_group<AccT, HM_F32>(rc[u], xi, acc);
+          } else if (dt == HM_F16) {
+            axpy_group<AccT, HM_F16>(rc[u], xi, acc);
+          } else if (dt == HM_BF16) {
+            axpy_group<AccT, HM_BF16>(rc[u], xi, acc);
+          } else {
+            if constexpr (sizeof(AccT) == 8) axpy_group<AccT, HM_F64>(rc[u], xi, acc);
           }
         }
-    }
+      }
   }
   constexpr int GW = DT >= 0 ? group_width(DT) : 8;   // red stride per lane
 #pragma unroll
@@ -183,25 +194,26 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
 }
 
 // A whole workgroup on tile ti (it synchronizes).  red: 4 * 64 * 8 values
-// (four waves x 64 lanes x at most 8 columns per lane).  MIXED: the tile
+// (four waves x 64 lanes x at most 8 columns per lane); xs: kSegRows
+// values (x of the tile's rows).  MIXED: the tile
 // may hold several formats (tiles from n_tiles_uniform on); else it holds
 // one (the format is dispatched once per tile).
 template <typename AccT, bool MIXED = true>
-__device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti, AccT* red) {
+__device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti, AccT* red, AccT* xs) {
   const ColTile T = a.tiles[ti];
   if constexpr (MIXED) {
     if (T.end[0] < T.ngroups) {                     // several formats in the tile
-      col_tile<AccT, -1>(a, T, red);
+      col_tile<AccT, -1>(a, T, red, xs);
       return;
     }
   }
   switch (T.dtype[0]) {
     case HM_F64:
-      if constexpr (sizeof(AccT) == 8) col_tile<AccT, HM_F64>(a, T, red);
+      if constexpr (sizeof(AccT) == 8) col_tile<AccT, HM_F64>(a, T, red, xs);
       break;
-    case HM_F32: col_tile<AccT, HM_F32>(a, T, red); break;
-    case HM_F16: col_tile<AccT, HM_F16>(a, T, red); break;
-    default: col_tile<AccT, HM_BF16>(a, T, red); break;
+    case HM_F32: col_tile<AccT, HM_F32>(a, T, red, xs); break;
+    case HM_F16: col_tile<AccT, HM_F16>(a, T, red, xs); break;
+    default: col_tile<AccT, HM_BF16>(a, T, red, xs); break;
   }
 }
 
@@ -354,6 +366,7 @@ __global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, 
   static_assert(CAP >= 4 * 64 * 8, "staging buffer doubles as the tile reduction buffer");
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
+  __shared__ AccT pxs[kSegRows];
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     if (it != blockIdx.x) __syncthreads();          // LDS of the previous item
     const int item = order[it];
@@ -361,7 +374,7 @@ __global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, 
       const RowPanel P = ra.rp[item];
       row_panel_part<AccT, CAP, U>(ra, P, 0, P.nsec_dense, 0, dense_slot_end(ra, P), zs, red);
     } else {
-      col_tile_any<AccT>(ca, -(int64_t)item - 1, zs);
+      col_tile_any<AccT>(ca, -(int64_t)item - 1, zs, pxs);
     }
   }
 }
@@ -384,9 +397,10 @@ __global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* ord
 template <typename AccT, bool MIXED>
 __global__ __launch_bounds__(256, MIXED ? 3 : 4) void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
   __shared__ AccT cred[4 * 64 * 8];
+  __shared__ AccT cxs[kSegRows];
   for (int64_t it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
     if (it != t0 + blockIdx.x) __syncthreads();
-    col_tile_any<AccT, MIXED>(ca, it, cred);
+    col_tile_any<AccT, MIXED>(ca, it, cred, cxs);
   }
 }
 
