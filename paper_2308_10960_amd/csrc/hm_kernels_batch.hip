@@ -134,7 +134,7 @@ __device__ __forceinline__ void load_slot(const uint8_t* p, int dt, float (&v)[4
 // tables of destination rows (in part, whose rows from t_row0 on are t) and
 // factors (s_b[l] for a column that writes t directly, else 1).
 template <int DT, int S, bool DB>
-__device__ __forceinline__ void colb_part(const ColBArgs& a, const ColTile& T, int quarter, int rh,
+__device__ __forceinline__ void colb32_part(const ColBArgs& a, const ColTile& T, int quarter, int rh,
                                           int lane, int32_t* wd, float* ws) {
   constexpr int CPL = DT == HM_F32 ? 2 : 4;
   const int l32 = lane & 31, hi = lane >> 5;
@@ -226,6 +226,128 @@ __device__ __forceinline__ void colb_part(const ColBArgs& a, const ColTile& T, i
   }
 }
 
+// D (16 x 16) += A (16 x 4) B (4 x 16) on v_mfma_f32_16x16x4_f32: lane l
+// gives A[l % 16][l / 16] and B[l / 16][l % 16]; D[i][j] is in lane
+// j + 16 (i / 4), register i % 4.
+__device__ __forceinline__ f32x4 mfma16x4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// One wave (a workgroup of its own): slots [16 s16, 16 s16 + 16) of a column
+// tile for 32 right-hand sides (group rh of RS).  Slot s is bytes [8 s, 8 s
+// + 8) of every tile row: half of group s / 2, i.e. 2 FP32 or 4 FP16/BF16
+// columns.  Lane l owns slot 16 s16 + l % 16 of row 4 k + l / 16 in step k:
+// one v_mfma_f32_16x16x4_f32 per column q < CPL of the slot and per half of
+// the 32 right-hand sides takes four rows at a time (A: the lane's value of
+// column q; B: one value of the x rows 4k..4k+3 per lane, one load per
+// half).  DT >= 0: every slot has format DT (CPL = its columns per slot);
+// DT < 0: the tile holds runs of several formats, CPL = 4 and an FP32 slot
+// leaves columns 2 and 3 empty.  Rows go in batches of S steps; with DB the
+// next batch's loads are in flight while this batch's MFMAs run.  wd, ws:
+// the wave's LDS tables of destination rows (in part, whose rows from
+// t_row0 on are t) and factors (s_b[l] for a column that writes t directly,
+// else 1).
+template <int DT, int S, bool DB>
+__device__ __forceinline__ void colb16_part(const ColBArgs& a, const ColTile& T, int s16, int rh,
+                                          int lane, int32_t* wd, float* ws) {
+  constexpr int CPL = DT == HM_F32 ? 2 : 4;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int sl = 16 * s16 + l16;
+  const bool act = sl < 2 * T.ngroups;
+  int dt, cps, col;                                  // format, columns, first tile column of the slot
+  if constexpr (DT >= 0) {
+    dt = DT;
+    cps = CPL;
+    col = sl * CPL;
+  } else {
+    const TileGroup tg = tile_group(T, act ? sl / 2 : 0);
+    dt = tg.dtype;
+    cps = group_width(dt) / 2;
+    col = tg.col + (sl % 2) * cps;
+  }
+  f32x4 acc[CPL][2];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q][0] = acc[q][1] = (f32x4)(0.f);
+  const size_t rstride = (size_t)T.ngroups * 16;
+  const uint8_t* base = a.store + T.data_off + (size_t)kq * rstride + (size_t)(act ? sl : 0) * 8;
+  const float* xb = a.xr + ((size_t)T.x0 + kq) * a.RS + rh * 32 + l16;
+  const int nr = T.nrows;
+  // step k covers rows 4k .. 4k + 3; lanes of a missing row give zeros
+  const int nsteps = (nr + 3) / 4;
+  float an[S][4], bn[S][2];
+  auto issue = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      const int r = 4 * (k0 + u) + kq;
+      const bool ok = r < nr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) an[u][q] = 0.f;
+      if (act && ok) load_slot(base + (size_t)(4 * (k0 + u)) * rstride, dt, an[u]);
+      bn[u][0] = ok ? xb[(size_t)(4 * (k0 + u)) * a.RS] : 0.f;
+      bn[u][1] = ok ? xb[(size_t)(4 * (k0 + u)) * a.RS + 16] : 0.f;
+    }
+  };
+  auto compute = [&](int k, const float (&av)[S][4], const float (&bv)[S][2]) {
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      if (k + u >= nsteps) break;                   // uniform across the wave
+#pragma unroll
+      for (int q = 0; q < CPL; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[q][h] = mfma16x4(av[u][q], bv[u][h], acc[q][h]);
+    }
+  };
+  // the first loads of the tile and the destinations of the lane's columns
+  // go out together; the factors and the LDS tables follow the main loop
+  if constexpr (DB) issue(0);
+  int32_t e[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) e[q] = (lane < 16 && act && q < cps) ? a.dst[T.dst_off + col + q] : kDstPad;
+  if constexpr (DB) {
+    for (int k = 0; k < nsteps; k += S) {
+      float ac[S][4], bc[S][2];
+#pragma unroll
+      for (int u = 0; u < S; ++u) {
+        bc[u][0] = bn[u][0];
+        bc[u][1] = bn[u][1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ac[u][q] = an[u][q];
+      }
+      if (k + S < nsteps) issue(k + S);
+      compute(k, ac, bc);
+    }
+  } else {
+    for (int k = 0; k < nsteps; k += S) {
+      issue(k);
+      compute(k, an, bn);
+    }
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      // row of part (partials, then t) the column's sum goes to, and its factor
+      const bool direct = e[q] <= -2;
+      wd[CPL * lane + q] = direct ? a.t_row0 + dst_t_index(e[q]) : e[q];
+      ws[CPL * lane + q] = (direct && a.sigma) ? a.sigma[dst_t_index(e[q])] : 1.f;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int slot = 4 * kq + v;                    // the slot (D row) of acc[.][.][v]
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int32_t e2 = wd[CPL * slot + q];        // -1: padding or no column
+      if (e2 >= 0) {
+        float* out = a.part + (size_t)e2 * a.RS + rh * 32 + l16;
+        const float f = ws[CPL * slot + q];
+        out[0] = acc[q][0][v] * f;
+        out[16] = acc[q][1][v] * f;
+      }
+    }
+  }
+}
+
 #ifndef COLB_STEPS
 #define COLB_STEPS 4
 #define COLB_DOUBLE true
@@ -233,13 +355,12 @@ __device__ __forceinline__ void colb_part(const ColBArgs& a, const ColTile& T, i
 constexpr int kColBSteps = COLB_STEPS;
 constexpr bool kColBDouble = COLB_DOUBLE;
 
-// Workgroup (one wave) w -> (tile t0 + w / (4 RH), quarter, right-hand-side
-// group) over the tiles [t0, t1) of one class: one format DT, or DT < 0
-// for tiles with runs of several formats.
-template <int DT>
-__global__ __launch_bounds__(64) void k_col_b(ColBArgs a, int64_t t0, int64_t t1) {
-  __shared__ int32_t sdst[128];
-  __shared__ float ssig[128];
+// Workgroup (one wave) w -> (tile t0 + w / (4 RH), quarter of its slots,
+// right-hand-side group) over the one-format FP32 tiles [t0, t1): 32 slots
+// per wave, so each x row loaded serves the most columns.
+__global__ __launch_bounds__(64) void k_col_b32(ColBArgs a, int64_t t0, int64_t t1) {
+  __shared__ int32_t sdst[64];
+  __shared__ float ssig[64];
   const int lane = threadIdx.x;
   const int64_t w = blockIdx.x;
   const int rh = (int)(w % a.RH);
@@ -249,8 +370,27 @@ __global__ __launch_bounds__(64) void k_col_b(ColBArgs a, int64_t t0, int64_t t1
   if (ti >= t1) return;
   const ColTile T = a.tiles[ti];
   if (32 * quarter >= 2 * T.ngroups) return;         // uniform: nothing in this quarter
-  // 4-column slots: half the steps per batch (register budget)
-  colb_part<DT, DT == HM_F32 ? kColBSteps : kColBSteps / 2, kColBDouble>(a, T, quarter, rh, lane, sdst, ssig);
+  colb32_part<HM_F32, kColBSteps, kColBDouble>(a, T, quarter, rh, lane, sdst, ssig);
+}
+
+// Workgroup (one wave) w -> (tile t0 + w / (8 RH), sixteenth of its slots,
+// right-hand-side group) over the tiles [t0, t1) of one class: one format
+// DT, or DT < 0 for tiles with runs of several formats.  16 slots per wave
+// halve the MFMA work lost on the partly filled last part of a narrow tile.
+template <int DT>
+__global__ __launch_bounds__(64) void k_col_b16(ColBArgs a, int64_t t0, int64_t t1) {
+  __shared__ int32_t sdst[64];
+  __shared__ float ssig[64];
+  const int lane = threadIdx.x;
+  const int64_t w = blockIdx.x;
+  const int rh = (int)(w % a.RH);
+  const int64_t rest = w / a.RH;
+  const int s16 = (int)(rest & 7);
+  const int64_t ti = t0 + (rest >> 3);
+  if (ti >= t1) return;
+  const ColTile T = a.tiles[ti];
+  if (16 * s16 >= 2 * T.ngroups) return;             // uniform: nothing in this part
+  colb16_part<DT, kColBSteps, kColBDouble>(a, T, s16, rh, lane, sdst, ssig);
 }
 
 struct RedBArgs {
@@ -520,15 +660,15 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
                   (int32_t)(A.work_part_bytes / (int64_t)sizeof(float)), sigma, h.n_col_tiles, RS, RH};
       // one launch per tile class (FP64 tiles do not occur with FP32 accumulation)
       const int64_t* ce = h.tile_class_end;
-      auto grid = [&](int64_t t0, int64_t t1) { return dim3((unsigned)((t1 - t0) * 4 * RH)); };
+      auto grid = [&](int64_t t0, int64_t t1, int parts) { return dim3((unsigned)((t1 - t0) * parts * RH)); };
       if (ce[1] > ce[0])
-        hipLaunchKernelGGL(k_col_b<HM_F32>, grid(ce[0], ce[1]), dim3(64), 0, s, ca, ce[0], ce[1]);
+        hipLaunchKernelGGL(k_col_b32, grid(ce[0], ce[1], 4), dim3(64), 0, s, ca, ce[0], ce[1]);
       if (ce[2] > ce[1])
-        hipLaunchKernelGGL(k_col_b<HM_F16>, grid(ce[1], ce[2]), dim3(64), 0, s, ca, ce[1], ce[2]);
+        hipLaunchKernelGGL(k_col_b16<HM_F16>, grid(ce[1], ce[2], 8), dim3(64), 0, s, ca, ce[1], ce[2]);
       if (ce[3] > ce[2])
-        hipLaunchKernelGGL(k_col_b<HM_BF16>, grid(ce[2], ce[3]), dim3(64), 0, s, ca, ce[2], ce[3]);
+        hipLaunchKernelGGL(k_col_b16<HM_BF16>, grid(ce[2], ce[3], 8), dim3(64), 0, s, ca, ce[2], ce[3]);
       if (ce[4] > ce[3])
-        hipLaunchKernelGGL(k_col_b<-1>, grid(ce[3], ce[4]), dim3(64), 0, s, ca, ce[3], ce[4]);
+        hipLaunchKernelGGL(k_col_b16<-1>, grid(ce[3], ce[4], 8), dim3(64), 0, s, ca, ce[3], ce[4]);
       if (ev && r0 == 0) (void)hipEventRecord(ev[1], s);
       RedBArgs rb{reinterpret_cast<const TBlock*>(st + h.off_tblocks),
                   reinterpret_cast<const int32_t*>(st + h.off_owner), sigma, part, t, h.n_red_t, RS};
