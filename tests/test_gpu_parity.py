@@ -268,6 +268,32 @@ def test_batched_f32_mfma(name):
     D.close()
 
 
+@pytest.mark.parametrize("fmt", [hm.HM_F16, hm.HM_BF16])
+def test_uniform_16bit_formats(fmt):
+    """Every block stored in one 16-bit format (so every column tile has one
+    format: the FP16 and BF16 tile kernels of both paths): single and
+    batched products against the decoded oracle within the rigorous FP32
+    bound, batch independence bitwise."""
+    H = hmgen.build_preset("sphere4k_mixed")
+    H.set_uniform_dtype(fmt)
+    dec = oracle.decoded_factors(H, sigma_dtype=oracle.F32)
+    K = fp32_depth(H)
+    gam = K * U32 / (1 - K * U32)
+    D = DeviceHMatrix(H, hm.HM_F32, max_nrhs=40)
+    x = hmgen.uniform_vector(H.n).astype(np.float32).astype(np.float64)
+    y = run(D, x)
+    ref = oracle.hmvm(H, x, factors=dec)
+    assert np.all(np.abs(y - ref) <= gam * abs_bound(H, x, dec))
+    X = hmgen.gaussian_block(H.n, 40).astype(np.float32).astype(np.float64)
+    Y = _batch(D, X, 0.5)
+    refX = oracle.hmvm_multi(H, X, alpha=0.5, factors=dec)
+    for c in (0, 17, 39):
+        assert np.all(np.abs(Y[:, c] - refX[:, c]) <= gam * 0.5 * abs_bound(H, X[:, c], dec)), c
+    np.testing.assert_array_equal(_batch(D, X[:, [17]], 0.5)[:, 0], Y[:, 17])
+    say(f"format {fmt}: rel {np.linalg.norm(y - ref) / np.linalg.norm(ref):.2e}")
+    D.close()
+
+
 def test_launch_variants_and_tune_cache(sphere4k, tmp_path):
     """Every schedule/unroll meets parity; unroll depth never changes a bit;
     the tune cache written by the tuner is read back by hm_build_plan."""

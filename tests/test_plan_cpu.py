@@ -139,12 +139,19 @@ def test_storage_conversion_bit_exact(mixed4k):
     hm.hm_plan_destroy(p)
 
 
-@pytest.mark.parametrize("which", ["f64", "mixed", "mixed16k"])
+@pytest.mark.parametrize("which", ["f64", "mixed", "mixed16k", "bf16"])
 def test_store_model_matches_oracle(which, f64_4k, mixed4k):
     """The packed store, read as its layout defines it, gives the oracle's
     product.  At n = 16384 some blocks span several column chunks (partials
-    and their reduction); column tiles hold runs of several formats."""
-    H = {"f64": f64_4k, "mixed": mixed4k}.get(which) or hmgen.build_preset("sphere4k_mixed", n=16384)
+    and their reduction); mixed column tiles hold runs of several formats;
+    "bf16" stores every block in BF16 (one-format BF16 tiles)."""
+    if which == "mixed16k":
+        H = hmgen.build_preset("sphere4k_mixed", n=16384)
+    elif which == "bf16":
+        H = hmgen.build_preset("sphere4k_mixed")
+        H.set_uniform_dtype(hm.HM_BF16)
+    else:
+        H = {"f64": f64_4k, "mixed": mixed4k}[which]
     acc = hm.HM_F64 if which == "f64" else hm.HM_F32
     p, info, buf = _pack(H, acc)
     if which == "mixed16k":
