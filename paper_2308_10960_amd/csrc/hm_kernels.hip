@@ -195,9 +195,9 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
 
 // A whole workgroup on tile ti (it synchronizes).  red: 4 * 64 * 8 values
 // (four waves x 64 lanes x at most 8 columns per lane); xs: kSegRows
-// values (x of the tile's rows).  MIXED: the tile
-// may hold several formats (tiles from n_tiles_uniform on); else it holds
-// one (the format is dispatched once per tile).
+// values (x of the tile's rows).  MIXED: the tile may hold several formats
+// (the multi-format tile class); else it holds one (the format is
+// dispatched once per tile).
 template <typename AccT, bool MIXED = true>
 __device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti, AccT* red, AccT* xs) {
   const ColTile T = a.tiles[ti];

@@ -26,30 +26,13 @@ namespace {
 
 // ================================================================ batch (MFMA)
 //
-// Several right-hand sides with FP32 accumulation on v_mfma_f32_32x32x1_2b_f32.
-// In that instruction lane l supplies A_b[l%32][0] and B_b[0][l%32] of block
-// b = l/32, and result D_b[i][j] sits in lane j + 32*((i/4)%2), register
-// 16*b + 4*(i/8) + i%4.  With the row panels' lane = row layout a lane's
-// panel value is exactly its A operand (block 0 = rows 0-31, block 1 = rows
-// 32-63) and the B operand is one value of the source row z[k][0..31] per
-// lane; the column tiles use the same instruction with rows and columns
-// exchanged (A = four columns of V per lane).  Right-hand sides go 32 at a
-// time; every result column depends only on its own right-hand side, so a
-// column's result is the same whatever else is in the batch.
-
-typedef float f32x32 __attribute__((ext_vector_type(32)));
-
-__device__ __forceinline__ f32x32 mfma32(float a, float b, f32x32 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x1f32(a, b, c, 0, 0, 0);
-}
-
-// Column (right-hand side within a group of 32) of the results in lane l.
-__device__ __forceinline__ int l32of(int lane) { return lane & 31; }
-
-// Row (0..63) of the 64-row A operand held by result register v of lane l.
-__device__ __forceinline__ int mfma_row(int lane, int v) {
-  return 32 * (v >> 4) + 8 * ((v & 15) >> 2) + 4 * (lane >> 5) + (v & 3);
-}
+// Several right-hand sides with FP32 accumulation on the matrix cores:
+// v_mfma_f32_32x32x2_f32 (row panels; FP32 column tiles) and
+// v_mfma_f32_16x16x4_f32 (16-bit and multi-format column tiles).  Operand
+// and result layouts are stated beside the wrappers below.  Right-hand
+// sides go 32 at a time; every result column depends only on its own
+// right-hand side, so a column's result is the same whatever else is in the
+// batch.
 
 // X (column-major, leading dimension ldx) -> Xr (n x RS row-major, zero-padded).
 __global__ __launch_bounds__(256) void k_xpose(const float* __restrict__ X, int64_t ldx, int n,
@@ -348,12 +331,10 @@ __device__ __forceinline__ void colb16_part(const ColBArgs& a, const ColTile& T,
   }
 }
 
-#ifndef COLB_STEPS
-#define COLB_STEPS 4
-#define COLB_DOUBLE true
-#endif
-constexpr int kColBSteps = COLB_STEPS;
-constexpr bool kColBDouble = COLB_DOUBLE;
+// Column kernels: steps per batch of row loads, and the next batch's loads
+// in flight during the current one (measured best).
+constexpr int kColBSteps = 4;
+constexpr bool kColBDouble = true;
 
 // Workgroup (one wave) w -> (tile t0 + w / (4 RH), quarter of its slots,
 // right-hand-side group) over the one-format FP32 tiles [t0, t1): 32 slots
