@@ -796,10 +796,10 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
     }
     dsto += Cp.ncols;
   }
-  // tiles largest first (longest-processing-time order against the tail)
-  // (grouped by class: each class can run in a launch of its own).  FP64
-  // tiles are near-uniform in size and stream best in store order; the
-  // other classes vary more and go largest first.
+  // tile order, grouped by class (each class runs in a launch of its own):
+  // FP64 tiles are near-uniform in size and stream best in store order; the
+  // other classes vary more and go largest first (longest-processing-time
+  // order against the tail)
   std::stable_sort(ct, ct + H.n_col_tiles, [](const ColTile& x, const ColTile& y) {
     const int cx = tile_class(x), cy = tile_class(y);
     if (cx != cy) return cx < cy;
