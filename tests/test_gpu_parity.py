@@ -144,6 +144,18 @@ def test_degenerate_partitions(case):
     x = hmgen.uniform_vector(H.n, seed=2)
     check_f64(run(D, x), oracle.hmvm(H, x), abs_bound(H, x))
     D.close()
+    # the same partition in FP32 storage through the batched (MFMA) path
+    H.set_uniform_dtype(hmm.DT_F32)
+    D = DeviceHMatrix(H, hm.HM_F32, max_nrhs=3)
+    dec = oracle.decoded_factors(H, sigma_dtype=oracle.F32)
+    X = hmgen.gaussian_block(H.n, 3).astype(np.float32).astype(np.float64)
+    Y = _batch(D, X)
+    ref = oracle.hmvm_multi(H, X, factors=dec)
+    K = fp32_depth(H)
+    gam = K * U32 / (1 - K * U32)
+    for c in range(3):
+        assert np.all(np.abs(Y[:, c] - ref[:, c]) <= gam * abs_bound(H, X[:, c], dec) + 1e-30), c
+    D.close()
 
 
 def test_ragged_leaf_sizes_and_eta():
