@@ -107,9 +107,15 @@ typedef struct hm_server hm_server;
 /* Block scheduler (host only).  Validates the block table -- shapes, ranks,
  * groups, dtypes, and that the leaves tile [0,n_rows) x [0,n_cols) exactly
  * once, the defining property of the block tree's leaf set (Sec. 2.1) --
- * then groups every block's rows by elementary row interval and columns by
- * elementary column interval into dtype-homogeneous panels and work lists.
- * Copies what it needs from `blocks`.  opts may be NULL (F64, 1 RHS). */
+ * then lays out the store: every block's rows, cut by elementary row
+ * interval (<= 64 rows), form row panels with sections by kind and storage
+ * format; the columns of the low-rank blocks, cut by column chunk (the
+ * sub-clusters of <= 512 rows recovered from the nested block ranges), form
+ * column panels whose 16-byte groups of all formats are cut into tiles of
+ * 64 groups; plus work orders and reduction tables.  Copies what it needs
+ * from `blocks`.  opts may be NULL (F64, 1 RHS).  Errors: HM_EINVAL,
+ * HM_ESHAPE, HM_EDTYPE (the table), HM_EPARTITION (the leaves do not tile
+ * the matrix exactly once), HM_ENOMEM (sizes beyond 32-bit indices). */
 hm_status hm_build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks,
                         int64_t n_blocks, const hm_plan_opts* opts, hm_plan** out);
 hm_status hm_plan_info(const hm_plan* p, hm_plan_info_t* out);
@@ -125,11 +131,17 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
 /* Device block store.  Converts every factor from FP64 to its storage dtype
  * with round-to-nearest-even (rounded once, directly from FP64), packs it
  * into the plan's panel layout with its descriptors, and copies the result
- * to d_store (device, >= store_bytes, 256-byte aligned) on `stream`; the
- * call returns after the copy has completed.  Per block b (host, FP64,
- * column-major): a[b] = D_b (m x n_b) or U_b / W_b (m x k); bf[b] = NULL or
- * V_b / X_b (n_b x k); s[b] = NULL or s_b (k values, when has_sigma).
- * Converting each block after assembly follows Sec. 5.3. */
+ * to d_store (device, >= store_bytes, 256-byte aligned, on the current
+ * device) on `stream`; the call returns after the copy has completed.  Per
+ * block b (host, FP64, column-major): a[b] = D_b (m x n_b) or U_b / W_b
+ * (m x k); bf[b] = NULL or V_b / X_b (n_b x k); s[b] = NULL or s_b (k
+ * values, when has_sigma).  The factor data is packed and copied in windows
+ * (256 MiB; the environment variable HM_UPLOAD_WINDOW_BYTES, >= 4096,
+ * overrides) through two pinned host buffers, so the host memory used
+ * beyond the caller's factors is the descriptor tables plus two windows.
+ * Converting each block after assembly follows Sec. 5.3.  Errors: HM_EINVAL
+ * (NULL or missing factor pointers, alignment), HM_ENOMEM (store too small,
+ * pinned staging), HM_EDEVICE (no usable device, copy failure). */
 hm_status hm_upload(const hm_plan* p, const double* const* a, const double* const* bf,
                     const double* const* s, void* d_store, size_t store_bytes, void* stream,
                     hm_matrix** out);
@@ -228,26 +240,42 @@ hm_status hm_matrix_tune_key(const hm_matrix* A, char* buf, size_t len);
  * occur for real data; it keeps the reads from being removed). */
 hm_status hm_stream_read(const void* d_buf, size_t bytes, void* d_out, void* stream);
 
-/* Request loop with continuous batching over device-resident matrices.
- * mats: matrices to serve (borrowed).  d_arena: device memory (arena_bytes)
- * from which request vectors and workspaces are carved; a request is
+/* Request loop with continuous batching over device-resident matrices
+ * (FP32 accumulation; requests of one matrix are batched into hm_mvm_batch
+ * calls, whose results do not depend on the batch).
+ * mats: matrices to serve (borrowed; all on the current device).  d_arena:
+ * device memory (arena_bytes, 256-byte aligned) from which each batch's
+ * vectors and workspace are carved by a first-fit allocator; a batch is
  * admitted when its footprint fits in the free part of the arena (HBM-budget
- * admission) and otherwise waits.  streams: n_streams HIP streams the loop
- * may use concurrently (borrowed).  A host thread batches queued requests
- * of the same matrix into one hm_mvm_batch call per stream slot. */
+ * admission) and otherwise waits; a request that can never fit completes
+ * with HM_ENOMEM.  streams: n_streams HIP streams (borrowed), one per slot.
+ * A dispatcher thread batches queued requests of the same matrix (FIFO, up
+ * to its max_nrhs) and hands each batch to an idle slot; the slot's worker
+ * thread gathers the right-hand sides into pinned host memory, runs copy,
+ * product and copy-back on its stream, scatters the results and completes
+ * the tickets.  Test hook: the environment variable HM_SERVER_FAULT_EVERY=N
+ * (read here) fails every N-th batch with HM_EDEVICE before it is enqueued.
+ * Errors: HM_EINVAL (arguments, alignment). */
 hm_status hm_server_create(hm_matrix* const* mats, int32_t n_mats, void* d_arena,
                            size_t arena_bytes, void* const* streams, int32_t n_streams,
                            hm_server** out);
 /* Queue Y := A_mat X (Y overwritten) for host buffers X (n_cols x nrhs,
  * leading dimension ldx) and Y (n_rows x nrhs, ldy) in the matrix's
- * vec_dtype; both must stay valid until the ticket completes. */
+ * vec_dtype; both must stay valid until the ticket completes.  Thread-safe.
+ * Errors: HM_EINVAL (arguments), HM_ESTATE (server stopping), HM_EBUSY
+ * (queue full). */
 hm_status hm_submit(hm_server* s, int32_t mat, int32_t nrhs, const void* h_X, int64_t ldx,
                     void* h_Y, int64_t ldy, uint64_t* ticket);
+/* Whether a ticket has completed and with which status (HM_ESTATE for an
+ * unknown ticket); hm_wait blocks up to timeout_us (< 0: no limit) and
+ * returns HM_ETIMEOUT if the ticket is still running. */
 hm_status hm_poll(hm_server* s, uint64_t ticket, int32_t* done, hm_status* result);
 hm_status hm_wait(hm_server* s, uint64_t ticket, int64_t timeout_us, hm_status* result);
 /* Latency percentiles (microseconds, completion minus submission) and
  * throughput (right-hand sides completed per second) since creation. */
 hm_status hm_server_stats(hm_server* s, double* p50_us, double* p99_us, double* matvecs_per_s);
+/* Serves every queued request, then stops the threads and frees the
+ * server's pinned memory (the arena and streams stay the caller's). */
 void hm_server_destroy(hm_server* s);
 
 /* Text of the last error on the calling thread (valid until the next hm_*
