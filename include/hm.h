@@ -240,9 +240,10 @@ hm_status hm_matrix_tune_key(const hm_matrix* A, char* buf, size_t len);
  * occur for real data; it keeps the reads from being removed). */
 hm_status hm_stream_read(const void* d_buf, size_t bytes, void* d_out, void* stream);
 
-/* Request loop with continuous batching over device-resident matrices
- * (FP32 accumulation; requests of one matrix are batched into hm_mvm_batch
- * calls, whose results do not depend on the batch).
+/* Request loop with continuous batching over device-resident matrices:
+ * requests of one matrix are batched into hm_mvm_batch calls, so a
+ * request's result does not depend on the batch it lands in (FP32: bitwise
+ * by construction; FP64: each column is computed as hm_mvm computes it).
  * mats: matrices to serve (borrowed; all on the current device).  d_arena:
  * device memory (arena_bytes, 256-byte aligned) from which each batch's
  * vectors and workspace are carved by a first-fit allocator; a batch is
