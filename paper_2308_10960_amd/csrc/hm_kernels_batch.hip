@@ -6,9 +6,10 @@
 //  k_col_b    far field, phase 1: column tiles as MFMA tiles, partial
 //             products per column chunk;
 //  k_reduce_b t_b = s_b * (sum of the partials in chunk order) per column;
-//  k_row_b    near field and far field, phase 2: row panels as the A operand
-//             of v_mfma_f32_32x32x2_f32 (column pairs exchanged between
-//             lane halves by v_permlane32_swap), source rows as the B
+//  k_row_b    near field and far field, phase 2: row panels in 16-row
+//             blocks as the A operand of v_mfma_f32_16x16x4_f32 (sets of 4
+//             columns transposed across the 16-lane groups by
+//             v_permlane32_swap / v_permlane16_swap), source rows as the B
 //             operand straight from memory, a fixed-order four-wave
 //             reduction, one update of Y per row.
 // Every sum has a fixed order, so results are bitwise reproducible and do not
@@ -27,8 +28,8 @@ namespace {
 // ================================================================ batch (MFMA)
 //
 // Several right-hand sides with FP32 accumulation on the matrix cores:
-// v_mfma_f32_32x32x2_f32 (row panels; FP32 column tiles) and
-// v_mfma_f32_16x16x4_f32 (16-bit and multi-format column tiles).  Operand
+// v_mfma_f32_32x32x2_f32 (FP32 column tiles) and v_mfma_f32_16x16x4_f32
+// (16-bit and multi-format column tiles; row panels).  Operand
 // and result layouts are stated beside the wrappers below.  Right-hand
 // sides go 32 at a time; every result column depends only on its own
 // right-hand side, so a column's result is the same whatever else is in the
@@ -448,27 +449,44 @@ __device__ __forceinline__ void decode_any(int dt, u32x4 r, float (&v)[8]) {
   }
 }
 
-// One section of a row panel for the groups g = wave, wave + 4, ...: per
-// group a 16-byte load of the panel (lane = row, G columns).  Columns go in
-// pairs: v_permlane32_swap turns the pair (c, c+1) into the A operands of
-// rows 0-31 (lanes 0-31: column c, lanes 32-63: column c+1) and of rows
-// 32-63; one load brings the two source rows (lanes 0-31: the source of
-// column c, lanes 32-63: that of column c+1) as the B operand.  Panels of at
-// most 32 rows skip the second MFMA.  Groups go in steps of U; the loads of
-// the next step are in flight while this step's MFMAs run, and the source
-// slots of the step after that are read (scalar loads) meanwhile.
-template <int NH, int U>
+// 4 x 4 transpose across the four 16-lane groups: afterwards register q of
+// lane 16 c + i holds what register c of lane 16 q + i held (two
+// v_permlane32_swap, then two v_permlane16_swap).
+__device__ __forceinline__ void xpose16x4(float& v0, float& v1, float& v2, float& v3) {
+  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v0), __float_as_uint(v2), false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v1), __float_as_uint(v3), false, false);
+  const auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+  const auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+  v0 = __uint_as_float(c[0]);
+  v1 = __uint_as_float(c[1]);
+  v2 = __uint_as_float(d[0]);
+  v3 = __uint_as_float(d[1]);
+}
+
+// One section of a row panel of at most 16 NB rows for the groups g = wave,
+// wave + 4, ...: per group a 16-byte load of the panel (lane = row, G
+// columns).  Columns go in sets of 4: the transpose above turns the set's
+// values of rows 16 q .. 16 q + 15 into the A operand of
+// v_mfma_f32_16x16x4_f32 for row block q (lane 16 k + i: row 16 q + i,
+// column k of the set).  The B operand of half h of the right-hand sides
+// holds, in lane 16 k + j, value NV j + h of the source row of column k, so
+// one load of NV = RS / 16 consecutive values per lane brings all halves.
+// Groups go in steps of U; the loads of the next step are in flight while
+// this step's MFMAs run, and the source slots of the step after that are
+// read (scalar loads) meanwhile.
+template <int NH, int U, int NB>
 __device__ __forceinline__ void rowb_section(const RowBArgs& a, const RowSection& S, int m,
                                              const int32_t* src, int lane, int wave,
-                                             f32x16 (&top)[NH], f32x16 (&bot)[NH]) {
-  constexpr int RS = 32 * NH;
+                                             f32x4 (&acc)[NB][2 * NH]) {
+  constexpr int RS = 32 * NH, NV = 2 * NH;
+  typedef float fv __attribute__((ext_vector_type(NV)));
   const int dt = S.dtype, G = group_width(dt);
   const u32x4* p = reinterpret_cast<const u32x4*>(a.store + S.data_off) + lane;
   const int32_t* sc = src + S.col0;                // source slot of every column of the section
-  const bool act = lane < m, two = m > 32;
-  const int ng = S.ngroups, l32 = lane & 31, hi = lane >> 5;
+  const bool act = lane < m;
+  const int ng = S.ngroups, k = lane >> 4, j = lane & 15;
   u32x4 an[U];
-  float bn[U][4][NH];                              // B operands of up to 4 column pairs
+  fv bn[U][2];                                     // B operands of up to 2 sets of 4 columns
   int sn[U][8];                                    // source slots of the step after this one
   auto load_slots = [&](int g0) {
 #pragma unroll
@@ -490,13 +508,14 @@ __device__ __forceinline__ void rowb_section(const RowBArgs& a, const RowSection
       if (gg >= ng) break;                          // uniform across the wave
       an[u] = act ? ld16(p + (size_t)gg * m) : (u32x4)(0u);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (2 * q < G) {
-          const float* r0 = srow(sn[u][2 * q]);
-          const float* r1 = srow(sn[u][2 * q + 1]);
-          const float* row = hi ? r1 : r0;
-#pragma unroll
-          for (int h = 0; h < NH; ++h) bn[u][q][h] = row[32 * h + l32];
+      for (int s = 0; s < 2; ++s) {
+        if (4 * s < G) {
+          const float* r0 = srow(sn[u][4 * s]);
+          const float* r1 = srow(sn[u][4 * s + 1]);
+          const float* r2 = srow(sn[u][4 * s + 2]);
+          const float* r3 = srow(sn[u][4 * s + 3]);
+          const float* row = (k & 2) ? ((k & 1) ? r3 : r2) : ((k & 1) ? r1 : r0);
+          bn[u][s] = *reinterpret_cast<const fv*>(row + NV * j);
         }
       }
     }
@@ -506,14 +525,12 @@ __device__ __forceinline__ void rowb_section(const RowBArgs& a, const RowSection
   load_slots(wave + 4 * U);
   for (int g = wave; g < ng; g += 4 * U) {
     u32x4 ac[U];
-    float bc[U][4][NH];
+    fv bc[U][2];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       ac[u] = an[u];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int h = 0; h < NH; ++h) bc[u][q][h] = bn[u][q][h];
+      bc[u][0] = bn[u][0];
+      bc[u][1] = bn[u][1];
     }
     issue(g + 4 * U);
     load_slots(g + 8 * U);
@@ -523,16 +540,13 @@ __device__ __forceinline__ void rowb_section(const RowBArgs& a, const RowSection
       float v[8];
       decode_any(dt, ac[u], v);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (2 * q < G) {
-          const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * q]),
-                                                           __float_as_uint(v[2 * q + 1]), false, false);
-          const float at = __uint_as_float(sw[0]), ab = __uint_as_float(sw[1]);
+      for (int s = 0; s < 2; ++s) {
+        if (4 * s < G) {
+          xpose16x4(v[4 * s], v[4 * s + 1], v[4 * s + 2], v[4 * s + 3]);
 #pragma unroll
-          for (int h = 0; h < NH; ++h) {
-            top[h] = mfma32x2(at, bc[u][q][h], top[h]);
-            if (two) bot[h] = mfma32x2(ab, bc[u][q][h], bot[h]);
-          }
+          for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int h = 0; h < NV; ++h) acc[q][h] = mfma16x4(v[4 * s + q], bc[u][s][h], acc[q][h]);
         }
       }
     }
@@ -543,48 +557,45 @@ __device__ __forceinline__ void rowb_section(const RowBArgs& a, const RowSection
 // cost occupancy).
 constexpr int kRowBStep = 2;
 
-// One workgroup per row panel: the four waves take interleaved groups of
-// every section, then their sums are added in a fixed order through LDS
-// ((w0 + w2) + (w1 + w3)) and each row of Y is updated once.
-template <int NH>
-__global__ __launch_bounds__(256) void k_row_b(RowBArgs a) {
-  constexpr int RS = 32 * NH;
-  __shared__ float red[2 * 64 * RS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-  const int pi = panel_of(a.order, a.n_panels, blockIdx.x);
-  if (pi < 0) return;                               // uniform: whole workgroup
-  const RowPanel P = a.rp[pi];
-  f32x16 top[NH], bot[NH];
+// A row panel of at most 16 NB rows: the four waves take interleaved groups
+// of every section, then their sums are added in a fixed order through LDS
+// ((w0 + w2) + (w1 + w3)) and each row of Y is updated once.  red: 2 x 64
+// rows of RS + 1 values (the padding keeps the row-wise reads of the update
+// free of bank conflicts).
+template <int NH, int NB>
+__device__ __forceinline__ void rowb_panel(const RowBArgs& a, const RowPanel& P, float* red,
+                                           int tid, int lane, int wave) {
+  constexpr int RS = 32 * NH, NV = 2 * NH, RP = RS + 1;
+  f32x4 acc[NB][NV];
 #pragma unroll
-  for (int h = 0; h < NH; ++h) top[h] = bot[h] = (f32x16)(0.f);
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int h = 0; h < NV; ++h) acc[q][h] = (f32x4)(0.f);
   const int32_t* src = a.src + P.src_off;
   for (int qs = 0; qs < P.nsec; ++qs) {
     const RowSection S = a.rs[P.sec0 + qs];
-    if (S.dtype != HM_F64) rowb_section<NH, kRowBStep>(a, S, P.m, src, lane, wave, top, bot);
+    if (S.dtype != HM_F64) rowb_section<NH, kRowBStep, NB>(a, S, P.m, src, lane, wave, acc);
   }
-  // fixed-order sum of the four waves through LDS: waves 2 and 3 store,
-  // waves 0 and 1 add (w0 + w2, w1 + w3), wave 1 stores, wave 0 adds and
-  // stores the panel's sums; then every thread updates rows of Y (row-contiguous)
-  const int l32 = lane & 31;
+  // acc[q][h] register v of lane 16 k + j: row 16 q + 4 k + v, right-hand side NV j + h.
+  // Waves 2 and 3 store, waves 0 and 1 add (w0 + w2, w1 + w3), wave 1
+  // stores, wave 0 adds and stores the panel's sums; then every thread
+  // updates rows of Y (row-contiguous).
+  const int k = lane >> 4, j = lane & 15;
   auto put = [&](int slot) {
 #pragma unroll
-    for (int h = 0; h < NH; ++h)
+    for (int q = 0; q < NB; ++q)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int r = mfma32x2_row(lane, v);
-        red[(size_t)(slot * 64 + r) * RS + h * 32 + l32] = top[h][v];
-        red[(size_t)(slot * 64 + 32 + r) * RS + h * 32 + l32] = bot[h][v];
-      }
+      for (int h = 0; h < NV; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(slot * 64 + 16 * q + 4 * k + v) * RP + NV * j + h] = acc[q][h][v];
   };
   auto add = [&](int slot) {
 #pragma unroll
-    for (int h = 0; h < NH; ++h)
+    for (int q = 0; q < NB; ++q)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int r = mfma32x2_row(lane, v);
-        top[h][v] += red[(size_t)(slot * 64 + r) * RS + h * 32 + l32];
-        bot[h][v] += red[(size_t)(slot * 64 + 32 + r) * RS + h * 32 + l32];
-      }
+      for (int h = 0; h < NV; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[q][h][v] += red[(slot * 64 + 16 * q + 4 * k + v) * RP + NV * j + h];
   };
   if (wave >= 2) put(wave - 2);
   __syncthreads();
@@ -597,12 +608,29 @@ __global__ __launch_bounds__(256) void k_row_b(RowBArgs a) {
     put(0);
   }
   __syncthreads();
-  for (int e = tid; e < 64 * RS; e += 256) {
-    const int R = e & 63, j = e >> 6;
-    if (R < P.m && j < a.nrhs) {
-      float* yp = a.Y + (size_t)j * a.ldy + P.row0 + R;
-      *yp += a.alpha * red[(size_t)R * RS + j];
+  for (int e = tid; e < 16 * NB * RS; e += 256) {
+    const int R = e % (16 * NB), c = e / (16 * NB);
+    if (R < P.m && c < a.nrhs) {
+      float* yp = a.Y + (size_t)c * a.ldy + P.row0 + R;
+      *yp += a.alpha * red[R * RP + c];
     }
+  }
+}
+
+// One workgroup per row panel, specialised on its number of 16-row blocks.
+template <int NH>
+__global__ __launch_bounds__(256) void k_row_b(RowBArgs a) {
+  constexpr int RS = 32 * NH;
+  __shared__ float red[2 * 64 * (RS + 1)];
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+  const int pi = panel_of(a.order, a.n_panels, blockIdx.x);
+  if (pi < 0) return;                               // uniform: whole workgroup
+  const RowPanel P = a.rp[pi];
+  switch ((P.m + 15) >> 4) {                        // uniform: whole workgroup
+    case 1: rowb_panel<NH, 1>(a, P, red, tid, lane, wave); break;
+    case 2: rowb_panel<NH, 2>(a, P, red, tid, lane, wave); break;
+    case 3: rowb_panel<NH, 3>(a, P, red, tid, lane, wave); break;
+    default: rowb_panel<NH, 4>(a, P, red, tid, lane, wave); break;
   }
 }
 
