@@ -44,7 +44,7 @@ def kernel_bytes(H, info, vs, R=1, schedule=0):
     m = (H.re - H.rb).astype(np.float64)
     nb = (H.ce - H.cb).astype(np.float64)
     dense = H.adm == 0
-    sz = np.array([8, 4, 2, 2], np.float64)
+    sz = np.array([8, 4, 2, 2, 4, 5, 6], np.float64)    # bytes per value, by storage format
     d_bytes = float((m * nb * sz[H.group_dtype[:, 0]])[dense].sum())
     gcols = H.group_cols.astype(np.float64)
     gbytes = (gcols * sz[H.group_dtype]).sum(1)          # bytes per row of U / V
@@ -239,8 +239,11 @@ def main():
     H = hmgen.build_preset(args.workload, n=args.n or None)
     st = H.stats()
     log("built in %.1fs: %s" % (H.build_seconds, st))
-    mixed = p["dtype"] != "f64"
+    mixed = p["dtype"] not in ("f64", "dfl")        # DFL storage accumulates in FP64
     acc = hm.HM_F32 if mixed else hm.HM_F64
+    storage = p["dtype"]
+    if storage == "dfl":
+        storage = hmgen.hmatrix.DT_NAMES[hmgen.dfl_format(p["eps"])]
     vs = 4 if mixed else 8
     stream = torch.cuda.Stream()
     cache = None if args.no_tune_cache or not os.path.exists(args.tune_cache) else args.tune_cache
@@ -384,8 +387,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": f"{p['geometry']}-{p['kernel']} n={H.n} eps={p['eps']} "
-                               f"{p['dtype']} {R}rhs leaf64 eta2",
-                   "n": H.n, "eps": p["eps"], "storage": p["dtype"], "nrhs": R,
+                               f"{storage} {R}rhs leaf64 eta2",
+                   "n": H.n, "eps": p["eps"], "storage": storage, "nrhs": R,
                    "matvecs_per_s": round(R / (ms_per_step * 1e-3), 1),
                    "blocks": st["blocks"], "dense_blocks": st["dense_blocks"],
                    "lowrank_blocks": st["lowrank_blocks"], "mean_rank": round(st["mean_rank"], 2),

@@ -17,8 +17,28 @@ import numpy as np
 from .geometry import mean_nn_distance
 
 DT_F64, DT_F32, DT_F16, DT_BF16 = 0, 1, 2, 3
-DT_BYTES = {DT_F64: 8, DT_F32: 4, DT_F16: 2, DT_BF16: 2}
-DT_NAMES = {DT_F64: "f64", DT_F32: "f32", DT_F16: "f16", DT_BF16: "bf16"}
+DT_DFL32, DT_DFL40, DT_DFL48 = 4, 5, 6
+DT_BYTES = {DT_F64: 8, DT_F32: 4, DT_F16: 2, DT_BF16: 2, DT_DFL32: 4, DT_DFL40: 5, DT_DFL48: 6}
+DT_NAMES = {DT_F64: "f64", DT_F32: "f32", DT_F16: "f16", DT_BF16: "bf16",
+            DT_DFL32: "dfl32", DT_DFL40: "dfl40", DT_DFL48: "dfl48"}
+
+
+def dfl_mantissa_bits(eps: float) -> int:
+    """Mantissa bits m_eps for accuracy eps (Sec. 3.2 leaves the rule to the
+    accuracy; read here as the least m with unit roundoff 2^-(m+1) <= eps/2,
+    i.e. m = ceil(log2(1/eps)))."""
+    if not 0 < eps < 1:
+        raise ValueError("eps must be in (0, 1)")
+    return int(math.ceil(-math.log2(eps)))
+
+
+def dfl_format(eps: float) -> int:
+    """DFL storage format for accuracy eps (Sec. 3.2): 1 sign + 11 exponent +
+    m_eps mantissa bits, mantissa increased to a whole number of bytes; 8
+    bytes is FP64 itself.  Provided: 4, 5 and 6 bytes (fewer bytes take
+    DFL32, 7 bytes take FP64)."""
+    nbytes = -(-(1 + 11 + dfl_mantissa_bits(eps)) // 8)
+    return {4: DT_DFL32, 5: DT_DFL40, 6: DT_DFL48}.get(max(nbytes, 4), DT_F64)
 
 KERNEL_LAPLACE, KERNEL_EXP, KERNEL_SEPARABLE = 0, 1, 2
 

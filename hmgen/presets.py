@@ -14,7 +14,7 @@ standard admissibility with eta = 2.
 from __future__ import annotations
 
 from .geometry import fibonacci_sphere, cube_points
-from .hmatrix import build_hmatrix, KERNEL_LAPLACE, KERNEL_EXP, DT_F64, DT_F32
+from .hmatrix import build_hmatrix, dfl_format, KERNEL_LAPLACE, KERNEL_EXP, DT_F64, DT_F32
 
 PRESETS = {
     # small parity case
@@ -30,6 +30,11 @@ PRESETS = {
     # small mixed case for parity
     "sphere4k_mixed": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-6, dtype="mixed"),
     "cube4k": dict(geometry="cube", n=4096, kernel="exp", eps=1e-6, dtype="f32"),
+    # byte-aligned truncated FP64 storage (DFL, Sec. 3.2), FP64 accumulation:
+    # eps = 1e-6 -> DFL32, eps = 1e-8 -> DFL40
+    "sphere256k_dfl": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-6, dtype="dfl"),
+    "sphere256k_e8_dfl": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-8, dtype="dfl"),
+    "sphere4k_dfl": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-6, dtype="dfl"),
 }
 
 SEED_POINTS, SEED_X, SEED_RHS, SEED_REQUESTS = 0, 1, 2, 3
@@ -63,6 +68,8 @@ def build_preset(name: str, *, n: int | None = None, eps: float | None = None,
                       nthreads=nthreads)
     if mixed:
         H.select_precision(MIXED_TOL / 2)
+    elif dtype == "dfl":
+        H.set_uniform_dtype(dfl_format(eps))
     else:
         H.set_uniform_dtype(DT_F64 if dtype == "f64" else DT_F32)
     H.dtype_mode = dtype

@@ -52,7 +52,17 @@ typedef int32_t hm_status;
 #define HM_ESTATE (-8)      /* object in the wrong state (e.g. server stopped, unknown ticket) */
 #define HM_ETIMEOUT (-9)    /* hm_wait timed out */
 
-typedef enum { HM_F64 = 0, HM_F32 = 1, HM_F16 = 2, HM_BF16 = 3 } hm_dtype;
+/* Storage formats.  F64, F32, F16, BF16: the IEEE-754 binary formats of
+ * Table 1.  DFL32, DFL40, DFL48: the byte-aligned truncated formats with the
+ * 11 exponent bits of FP64 (DFL, Sec. 3.2): the leading 4, 5 or 6 bytes of
+ * the FP64 encoding (sign, exponent, 20 / 28 / 36 mantissa bits), rounded to
+ * nearest even from FP64; they decode exactly to FP64.  The number of
+ * formats is HM_NUM_DTYPES. */
+typedef enum {
+  HM_F64 = 0, HM_F32 = 1, HM_F16 = 2, HM_BF16 = 3,
+  HM_DFL32 = 4, HM_DFL40 = 5, HM_DFL48 = 6
+} hm_dtype;
+#define HM_NUM_DTYPES 7
 typedef enum { HM_DENSE = 0, HM_LOWRANK = 1 } hm_kind;
 
 /* One leaf block b = tau x sigma of the block tree (Sec. 2.1).
@@ -73,7 +83,9 @@ typedef struct {
 /* acc_dtype: HM_F64 or HM_F32, the accumulation type of every sum.
  * vec_dtype: must equal acc_dtype (x, y, X, Y are stored in it).
  * Storage dtypes allowed: any with HM_F64 accumulation; F32/F16/BF16 with
- * HM_F32 accumulation.
+ * HM_F32 accumulation.  A plan whose low-rank groups use DFL40 or DFL48
+ * stores every low-rank group in that one format (dense blocks may use any
+ * allowed format); otherwise hm_build_plan fails with HM_EDTYPE.
  * max_nrhs: largest nrhs passed to hm_mvm_batch (>= 1); sizes the workspace.
  * tune: 0 = built-in launch parameters; 1 = read tune_cache, a text file
  * written by the tuner with one "key params" line per kind of matrix (see
@@ -97,7 +109,7 @@ typedef struct {
   size_t store_bytes, work_bytes_per_rhs;
   double alg_bytes, alg_flops, overhead_bytes;
   int64_t n_dense, n_lowrank, n_row_panels, n_col_tiles, n_partials, n_t;
-  size_t bytes_by_dtype[4];
+  size_t bytes_by_dtype[HM_NUM_DTYPES];
 } hm_plan_info_t;
 
 typedef struct hm_plan hm_plan;
@@ -123,10 +135,13 @@ void hm_plan_destroy(hm_plan* p);
 
 /* Where entry (i, j) of a block's first factor (which = 0: D_b or U_b / W_b,
  * j < n_b resp. k) or second factor (which = 1: V_b / X_b, i < n_b, j < k)
- * lives in the store: byte offset and storage dtype.  For tests of the
- * packing and conversion done by hm_upload. */
+ * lives in the store: byte offset and storage dtype.  For DFL formats the
+ * offset is that of the value's leading 4 bytes (a little-endian 32-bit
+ * word); for DFL40 / DFL48 its remaining 1 / 2 bytes (bits 31..24 / 31..16
+ * of the FP64 encoding) are at lo_offset, else lo_offset = 0.  lo_offset
+ * may be NULL.  For tests of the packing and conversion done by hm_upload. */
 hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t i, int64_t j,
-                         size_t* byte_offset, int32_t* dtype);
+                         size_t* byte_offset, int32_t* dtype, size_t* lo_offset);
 
 /* Device block store.  Converts every factor from FP64 to its storage dtype
  * with round-to-nearest-even (rounded once, directly from FP64), packs it

@@ -7,7 +7,9 @@ Format rounding (for the mixed-precision "decoded" oracle) follows the
 IEEE-754 binary formats of Table 1 with round-to-nearest-even applied once,
 directly from FP64:
   FP32 and FP16 use numpy's own conversions (correctly rounded from double);
-  BF16 (1-8-7, Table 1) is rounded here from its definition.
+  BF16 (1-8-7, Table 1) is rounded here from its definition;
+  DFL (Sec. 3.2: FP64's sign and 11 exponent bits, the mantissa cut to make
+  a whole number of bytes) is rounded here from its definition.
 Parity pins for every function live in tests/test_oracle_*.py.
 """
 
@@ -26,6 +28,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
+DFL32, DFL40, DFL48 = 4, 5, 6
+DFL_BYTES = {DFL32: 4, DFL40: 5, DFL48: 6}
 
 # Table 1: unit roundoff u = 2^-(m+1) for m explicit mantissa bits.
 UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "tf32": 2.0 ** -11,
@@ -85,9 +89,34 @@ def round_bf16(x) -> np.ndarray:
     return out
 
 
+def round_dfl(x, nbytes: int) -> np.ndarray:
+    """RNE of FP64 values to the DFL format of nbytes bytes (Sec. 3.2).
+
+    Written from the format definition: sign and the 11 exponent bits of
+    FP64, m = 8 nbytes - 12 explicit mantissa bits, so the kept significand
+    has m + 1 bits, the smallest normal exponent is -1022 as in FP64 and
+    subnormals are spaced 2^(-1022 - m); values that round beyond FP64's
+    largest finite exponent become infinite.  nbytes = 8 is FP64 itself.
+    """
+    m = 8 * nbytes - 12
+    x = np.asarray(x, dtype=np.float64)
+    out = x.copy()
+    fin = np.isfinite(x) & (x != 0)
+    xf = x[fin]
+    _, e = np.frexp(xf)                          # |x| = f 2^e, f in [0.5, 1)
+    lsb = np.maximum(e - 1, -1022) - m           # exponent of the last kept bit
+    q = np.rint(np.ldexp(xf, -lsb))              # rint: ties to even
+    with np.errstate(over="ignore"):
+        r = np.ldexp(q, lsb)                     # inf beyond the largest finite value
+    out[fin] = r
+    return out
+
+
 def round_to(x, dt: int) -> np.ndarray:
     if dt == F64:
         return np.asarray(x, dtype=np.float64)
+    if dt in DFL_BYTES:
+        return round_dfl(x, DFL_BYTES[dt])
     if dt == F32:
         return round_f32(x)
     if dt == F16:

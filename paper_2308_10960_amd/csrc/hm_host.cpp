@@ -84,12 +84,39 @@ static uint16_t round_bits(double d, int man_bits, int bias, int exp_max_field) 
 uint16_t f64_to_f16(double d) { return round_bits(d, 10, 15, 31); }
 uint16_t f64_to_bf16(double d) { return round_bits(d, 7, 127, 255); }
 
+// DFL (Sec. 3.2): the leading nbytes bytes of the FP64 encoding, rounded to
+// nearest even on the bit pattern (a carry out of the mantissa moves into
+// the exponent, as the rounding of the value requires).  Returns the
+// rounded encoding with the dropped bits zero.
+static uint64_t dfl_bits(double v, int nbytes) {
+  uint64_t b;
+  std::memcpy(&b, &v, 8);
+  const int drop = 64 - 8 * nbytes;
+  if (((b >> 52) & 0x7ff) == 0x7ff)                // Inf stays Inf; NaN stays a (quiet) NaN
+    return (b & ~((1ull << drop) - 1)) | ((b & ((1ull << 52) - 1)) ? (1ull << 51) : 0);
+  uint64_t kept = b >> drop;
+  const uint64_t rem = b & ((1ull << drop) - 1), half = 1ull << (drop - 1);
+  if (rem > half || (rem == half && (kept & 1))) ++kept;
+  return kept << drop;
+}
+
+// A DFL value: its leading 4 bytes (the high word of the encoding) at hi;
+// for DFL40 / DFL48 bits 31..24 / 31..16 at lo.
+static inline void put_dfl(uint8_t* hi, uint8_t* lo, int dt, double v) {
+  const uint64_t r = dfl_bits(v, value_bytes(dt));
+  const uint32_t w = (uint32_t)(r >> 32);
+  std::memcpy(hi, &w, 4);
+  if (dt == kDtDfl40) { const uint8_t q = (uint8_t)(r >> 24); std::memcpy(lo, &q, 1); }
+  if (dt == kDtDfl48) { const uint16_t q = (uint16_t)(r >> 16); std::memcpy(lo, &q, 2); }
+}
+
 static inline void put(uint8_t* dst, int dt, double v) {
   switch (dt) {
     case HM_F64: std::memcpy(dst, &v, 8); break;
     case HM_F32: { float f = (float)v; std::memcpy(dst, &f, 4); break; }
     case HM_F16: { uint16_t h = f64_to_f16(v); std::memcpy(dst, &h, 2); break; }
-    default: { uint16_t h = f64_to_bf16(v); std::memcpy(dst, &h, 2); break; }
+    case HM_BF16: { uint16_t h = f64_to_bf16(v); std::memcpy(dst, &h, 2); break; }
+    default: put_dfl(dst, nullptr, HM_DFL32, v); break;   // callers of put: no low-byte plane
   }
 }
 
@@ -105,8 +132,8 @@ static hm_status validate_block(const hm_block_desc& b, int64_t i, int64_t n_row
   if (b.row_end - b.row_begin > INT32_MAX / 2 || b.col_end - b.col_begin > INT32_MAX / 2)
     return fail(HM_ESHAPE, "block %lld too large", (long long)i);
   auto dt_ok = [&](int dt) {
-    if (dt < HM_F64 || dt > HM_BF16) return false;
-    if (acc == HM_F32 && dt == HM_F64) return false;
+    if (dt < HM_F64 || dt >= kNumDtypes) return false;
+    if (acc == HM_F32 && (dt == HM_F64 || is_dfl(dt))) return false;
     return true;
   };
   if (b.kind == HM_DENSE) {
@@ -156,11 +183,26 @@ static void split_intervals(const std::vector<int64_t>& bp, int cap, std::vector
 // The panel's groups (run by run) are stored tile by tile (tiles of 64
 // groups, the last one narrower); inside a tile, row i holds the tile's
 // groups contiguously, so a tile row is one contiguous block.
+// Low-byte plane bytes per group element of a column panel: a panel with a
+// DFL40 / DFL48 run holds only that run (plans store every low-rank group in
+// such a format, if any group uses it).
+static int panel_lo(const ColPanelHost& Cp) { return Cp.secs.empty() ? 0 : lo_bytes(Cp.secs.front().dtype); }
+
 static int64_t col_elem_offset(const ColPanelHost& Cp, const ColSectionHost& S, int64_t i, int64_t sc) {
   const int G = group_width(S.dtype), sz = dtype_size(S.dtype);
   const int64_t g = S.g0 + sc / G, t = g / kTileGroups, gl = g % kTileGroups;
   const int64_t ngt = std::min<int64_t>(kTileGroups, Cp.ngroups - t * kTileGroups);
-  return Cp.data_off + t * kTileGroups * 16 * (int64_t)Cp.nrows + (i * ngt + gl) * 16 + (sc % G) * sz;
+  return Cp.data_off + t * kTileGroups * (16 + panel_lo(Cp)) * (int64_t)Cp.nrows + (i * ngt + gl) * 16 +
+         (sc % G) * sz;
+}
+
+// Byte offset of the low-byte part of that element (formats with lo_bytes > 0).
+static int64_t col_lo_offset(const ColPanelHost& Cp, const ColSectionHost& S, int64_t i, int64_t sc) {
+  const int G = group_width(S.dtype), L = lo_bytes(S.dtype);
+  const int64_t g = S.g0 + sc / G, t = g / kTileGroups, gl = g % kTileGroups;
+  const int64_t ngt = std::min<int64_t>(kTileGroups, Cp.ngroups - t * kTileGroups);
+  return Cp.data_off + t * kTileGroups * (16 + L) * (int64_t)Cp.nrows + 16 * ngt * (int64_t)Cp.nrows +
+         (i * ngt + gl) * L + (sc % G) * (L / 4);
 }
 
 hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks, int64_t nb,
@@ -188,6 +230,24 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
   for (int64_t i = 0; i < nb; ++i) {
     hm_status st = validate_block(P->blocks[i], i, n_rows, n_cols, acc);
     if (st) return st;
+  }
+  {
+    // a format with a low-byte plane in the column tiles must be the format
+    // of every low-rank group (its tiles then never hold other formats)
+    int lo_fmt = -1;
+    for (auto& b : P->blocks)
+      if (b.kind == HM_LOWRANK)
+        for (int g = 0; g < b.ngroups; ++g)
+          if (b.group_cols[g] > 0 && lo_bytes(b.group_dtype[g]) > 0) lo_fmt = b.group_dtype[g];
+    if (lo_fmt >= 0)
+      for (int64_t i = 0; i < nb; ++i) {
+        const auto& b = P->blocks[i];
+        if (b.kind == HM_LOWRANK)
+          for (int g = 0; g < b.ngroups; ++g)
+            if (b.group_cols[g] > 0 && b.group_dtype[g] != lo_fmt)
+              return fail(HM_EDTYPE, "block %lld: low-rank groups in format %d and %d (DFL40 / DFL48 "
+                          "must be the format of every low-rank group)", (long long)i, b.group_dtype[g], lo_fmt);
+      }
   }
 
   // ---- elementary row intervals and the tiling proof
@@ -387,7 +447,7 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
     // section starts at a multiple of 8 source slots
     int32_t slot = 0;
     for (int kind = 0; kind < 2; ++kind)
-      for (int dt = 0; dt < 4; ++dt) {
+      for (int dt = 0; dt < kNumDtypes; ++dt) {
         int32_t cols = 0;
         for (auto& s : segs)
           if (s.kind == kind && s.dtype == dt) { s.seccol = cols; cols += s.ncols; }
@@ -444,7 +504,7 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
         c0 += b.group_cols[g];
       }
     }
-    for (int dt = 0; dt < 4; ++dt) {             // one run per format, formats ascending
+    for (int dt = 0; dt < kNumDtypes; ++dt) {    // one run per format, formats ascending
       int32_t cols = 0;
       for (auto& s : Cp.segs)
         if (s.dtype == dt) { s.seccol = cols; cols += s.ncols; }
@@ -501,7 +561,7 @@ static bool parse_launch(const char* text, LaunchParams& lp) {
 // right-hand sides (their products run the multi-right-hand-side kernels).
 static std::string tune_key(int acc, const size_t* bytes_by_dtype, int64_t n_rows, int max_nrhs) {
   int mask = 0;
-  for (int d = 0; d < 4; ++d) if (bytes_by_dtype[d]) mask |= 1 << d;
+  for (int d = 0; d < kNumDtypes; ++d) if (bytes_by_dtype[d]) mask |= 1 << d;
   int lg = 0;
   while ((int64_t(1) << (lg + 1)) <= n_rows) ++lg;
   char buf[64];
@@ -554,7 +614,7 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   H.n_col_tiles = ntiles;
   {
     // tiles per class (one format, or several: runs of a panel that meet in a tile)
-    int64_t cnt[5] = {0, 0, 0, 0, 0};
+    int64_t cnt[kNumDtypes + 1] = {};
     for (auto& Cp : P->cps)
       for (int32_t g0 = 0; g0 < Cp.ngroups; g0 += kTileGroups) {
         const int32_t g1 = std::min(Cp.ngroups, g0 + kTileGroups);
@@ -563,10 +623,10 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
           const int32_t a = S.g0, b = S.g0 + S.ld / group_width(S.dtype);
           if (std::max(a, g0) < std::min(b, g1)) { ++runs; fmt = S.dtype; }
         }
-        ++cnt[runs == 1 ? fmt : 4];
+        ++cnt[runs == 1 ? fmt : kNumDtypes];
       }
     int64_t acc_end = 0;
-    for (int c = 0; c < 5; ++c) H.tile_class_end[c] = (acc_end += cnt[c]);
+    for (int c = 0; c <= kNumDtypes; ++c) H.tile_class_end[c] = (acc_end += cnt[c]);
   }
 
   int64_t off = align_up(sizeof(StoreHeader), kAlign);
@@ -597,30 +657,30 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   // data: row sections, then column sections
   int64_t src_off = 0;
   double factor_bytes = 0, pad_bytes = 0;
-  for (int d = 0; d < 4; ++d) P->bytes_by_dtype[d] = 0;
+  for (int d = 0; d < kNumDtypes; ++d) P->bytes_by_dtype[d] = 0;
   for (auto& R : P->rps) {
     R.src_off = src_off;
     src_off += R.ncols;
     for (auto& S : R.secs) {
-      const int64_t bytes = (int64_t)S.ngroups * R.m * 16;
+      const int64_t bytes = (int64_t)S.ngroups * R.m * (16 + lo_bytes(S.dtype));
       S.data_off = take(bytes);
       int64_t real = 0;
       for (auto& s : R.segs)
         if (s.dtype == S.dtype && s.kind == S.kind) real += s.ncols;
-      const int64_t real_bytes = real * R.m * dtype_size(S.dtype);
+      const int64_t real_bytes = real * R.m * value_bytes(S.dtype);
       factor_bytes += (double)real_bytes;
       pad_bytes += (double)(bytes - real_bytes);
       P->bytes_by_dtype[S.dtype] += (size_t)real_bytes;
     }
   }
   for (auto& Cp : P->cps) {
-    Cp.data_off = take((int64_t)Cp.ngroups * 16 * Cp.nrows);
+    Cp.data_off = take((int64_t)Cp.ngroups * (16 + panel_lo(Cp)) * Cp.nrows);
     for (auto& S : Cp.secs) {
-      const int64_t bytes = (int64_t)S.ld * Cp.nrows * dtype_size(S.dtype);
+      const int64_t bytes = (int64_t)S.ld * Cp.nrows * value_bytes(S.dtype);
       int64_t real = 0;
       for (auto& s : Cp.segs)
         if (s.dtype == S.dtype) real += s.ncols;
-      const int64_t real_bytes = real * Cp.nrows * dtype_size(S.dtype);
+      const int64_t real_bytes = real * Cp.nrows * value_bytes(S.dtype);
       factor_bytes += (double)real_bytes;
       pad_bytes += (double)(bytes - real_bytes);
       P->bytes_by_dtype[S.dtype] += (size_t)real_bytes;
@@ -724,7 +784,7 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
     std::iota(ord.begin(), ord.end(), 0);
     auto bytes = [&](int32_t p) {
       int64_t s = 0;
-      for (auto& S : P->rps[p].secs) s += (int64_t)S.ngroups * P->rps[p].m;
+      for (auto& S : P->rps[p].secs) s += (int64_t)S.ngroups * P->rps[p].m * (16 + lo_bytes(S.dtype));
       return s;
     };
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return bytes(x) > bytes(y); });
@@ -733,7 +793,7 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
     auto part_bytes = [&](int32_t p, int kind) {
       int64_t s = 0;
       for (auto& S : P->rps[p].secs)
-        if (S.kind == kind) s += (int64_t)S.ngroups * P->rps[p].m * 16;
+        if (S.kind == kind) s += (int64_t)S.ngroups * P->rps[p].m * (16 + lo_bytes(S.dtype));
       return s;
     };
     std::vector<int32_t> dense, upart;
@@ -773,7 +833,7 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
     for (int32_t g0 = 0; g0 < Cp.ngroups; g0 += kTileGroups) {
       ColTile& T = ct[tile++];
       const int32_t ngt = std::min(kTileGroups, Cp.ngroups - g0);
-      T.data_off = Cp.data_off + (int64_t)g0 * 16 * Cp.nrows;   // tiles stored one after another
+      T.data_off = Cp.data_off + (int64_t)g0 * (16 + panel_lo(Cp)) * Cp.nrows;   // tiles one after another
       T.nrows = Cp.nrows;
       T.x0 = (int32_t)Cp.x0;
       T.ngroups = ngt;
@@ -797,13 +857,14 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
     dsto += Cp.ncols;
   }
   // tile order, grouped by class (each class runs in a launch of its own):
-  // FP64 tiles are near-uniform in size and stream best in store order; the
-  // other classes vary more and go largest first (longest-processing-time
-  // order against the tail)
+  // FP64 and DFL tiles (formats of the FP64-accumulation plans) are
+  // near-uniform in size and stream best in store order; the other classes
+  // vary more and go largest first (longest-processing-time order against
+  // the tail)
   std::stable_sort(ct, ct + H.n_col_tiles, [](const ColTile& x, const ColTile& y) {
     const int cx = tile_class(x), cy = tile_class(y);
     if (cx != cy) return cx < cy;
-    if (cx == HM_F64) return x.data_off < y.data_off;
+    if (cx == HM_F64 || is_dfl(cx)) return x.data_off < y.data_off;
     return (int64_t)x.nrows * x.ngroups > (int64_t)y.nrows * y.ngroups;
   });
   // reduction tables
@@ -844,14 +905,14 @@ void pack_job_range(const hm_plan* P, size_t j, int64_t* lo, int64_t* hi) {
   };
   if (j < nrp) {
     const RowPanelHost& R = P->rps[j];
-    span(R.secs, [&](const RowSectionHost& S) { return (int64_t)S.ngroups * R.m * 16; });
+    span(R.secs, [&](const RowSectionHost& S) { return (int64_t)S.ngroups * R.m * (16 + lo_bytes(S.dtype)); });
   } else {
     const ColPanelHost& Cp = P->cps[j - nrp];
     if (Cp.ngroups == 0) {
       *lo = *hi = -1;
     } else {
       *lo = Cp.data_off;
-      *hi = align_up(Cp.data_off + (int64_t)Cp.ngroups * 16 * Cp.nrows, kAlign);
+      *hi = align_up(Cp.data_off + (int64_t)Cp.ngroups * (16 + panel_lo(Cp)) * Cp.nrows, kAlign);
     }
   }
 }
@@ -878,12 +939,19 @@ void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf
           const int64_t r_local = R.row0 - b.row_begin;
           const double* A = a[sg.block];
           uint8_t* base = at(S->data_off);
+          const int L = lo_bytes(S->dtype);
+          uint8_t* lo_base = base + (int64_t)16 * S->ngroups * R.m;   // low-byte plane (DFL40 / DFL48)
           for (int32_t c = 0; c < sg.ncols; ++c) {
             const int32_t sc = sg.seccol + c;
             const int32_t g = sc / G, cc = sc % G;
             const double* col = A + (int64_t)(sg.c_first + c) * mb + r_local;
-            for (int32_t i = 0; i < R.m; ++i)
-              put(base + (((int64_t)g * R.m + i) * G + cc) * sz, S->dtype, col[i]);
+            for (int32_t i = 0; i < R.m; ++i) {
+              uint8_t* hi = base + (((int64_t)g * R.m + i) * G + cc) * sz;
+              if (is_dfl(S->dtype))
+                put_dfl(hi, lo_base + ((int64_t)g * R.m + i) * L + cc * (L / 4), S->dtype, col[i]);
+              else
+                put(hi, S->dtype, col[i]);
+            }
           }
         }
       } else {
@@ -891,15 +959,20 @@ void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf
         for (auto& sg : Cp.segs) {
           const ColSectionHost* S = nullptr;
           for (auto& x : Cp.secs) if (x.dtype == sg.dtype) S = &x;
-          const int sz = dtype_size(S->dtype);
           const auto& b = P->blocks[sg.block];
           const int64_t nbk = b.col_end - b.col_begin;
           const int64_t c_local = Cp.x0 - b.col_begin;
           const double* V = bf[sg.block];
+          const bool lo = lo_bytes(S->dtype) > 0;
           for (int32_t c = 0; c < sg.ncols; ++c) {
             const double* col = V + (int64_t)(sg.c_first + c) * nbk + c_local;
-            for (int32_t i = 0; i < Cp.nrows; ++i)
-              put(at(col_elem_offset(Cp, *S, i, sg.seccol + c)), S->dtype, col[i]);
+            for (int32_t i = 0; i < Cp.nrows; ++i) {
+              uint8_t* hi = at(col_elem_offset(Cp, *S, i, sg.seccol + c));
+              if (is_dfl(S->dtype))
+                put_dfl(hi, lo ? at(col_lo_offset(Cp, *S, i, sg.seccol + c)) : nullptr, S->dtype, col[i]);
+              else
+                put(hi, S->dtype, col[i]);
+            }
           }
         }
       }
@@ -956,15 +1029,16 @@ hm_status hm_plan_info(const hm_plan* p, hm_plan_info_t* out) {
   out->n_col_tiles = p->hdr.n_col_tiles;
   out->n_partials = p->n_partials;
   out->n_t = p->n_t;
-  for (int d = 0; d < 4; ++d) out->bytes_by_dtype[d] = p->bytes_by_dtype[d];
+  for (int d = 0; d < kNumDtypes; ++d) out->bytes_by_dtype[d] = p->bytes_by_dtype[d];
   return ok();
 }
 
 void hm_plan_destroy(hm_plan* p) { delete p; }
 
 hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t i, int64_t j,
-                         size_t* byte_offset, int32_t* dtype) {
+                         size_t* byte_offset, int32_t* dtype, size_t* lo_offset) {
   if (!p || !byte_offset || !dtype) return fail(HM_EINVAL, "NULL argument");
+  if (lo_offset) *lo_offset = 0;
   if (block < 0 || block >= (int64_t)p->blocks.size()) return fail(HM_EINVAL, "block out of range");
   const auto& b = p->blocks[block];
   const int64_t m = b.row_end - b.row_begin, n = b.col_end - b.col_begin;
@@ -978,10 +1052,12 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
       if (sg.block == block && j >= sg.c_first && j < sg.c_first + sg.ncols) {
         for (auto& S : R.secs)
           if (S.dtype == sg.dtype && S.kind == sg.kind) {
-            const int G = group_width(S.dtype);
+            const int G = group_width(S.dtype), L = lo_bytes(S.dtype);
             const int64_t sc = sg.seccol + (j - sg.c_first);
-            *byte_offset = (size_t)(S.data_off + (((sc / G) * R.m + (row - R.row0)) * G + sc % G) *
-                                                     dtype_size(S.dtype));
+            const int64_t e = (sc / G) * R.m + (row - R.row0);      // group element
+            *byte_offset = (size_t)(S.data_off + (e * G + sc % G) * dtype_size(S.dtype));
+            if (lo_offset && L)
+              *lo_offset = (size_t)(S.data_off + (int64_t)16 * S.ngroups * R.m + e * L + (sc % G) * (L / 4));
             *dtype = S.dtype;
             return ok();
           }
@@ -1004,6 +1080,8 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
         for (auto& S : Cp.secs)
           if (S.dtype == sg.dtype) {
             *byte_offset = (size_t)col_elem_offset(Cp, S, col - Cp.x0, sg.seccol + (j - sg.c_first));
+            if (lo_offset && lo_bytes(S.dtype))
+              *lo_offset = (size_t)col_lo_offset(Cp, S, col - Cp.x0, sg.seccol + (j - sg.c_first));
             *dtype = S.dtype;
             return ok();
           }

@@ -93,7 +93,7 @@ struct hm_plan {
   int64_t work_part_bytes = 0, work_t_bytes = 0, work_x_bytes = 0;
   double factor_bytes = 0, alg_bytes = 0, alg_flops = 0, overhead_bytes = 0;
   int64_t n_dense = 0, n_lowrank = 0;
-  size_t bytes_by_dtype[4] = {0, 0, 0, 0};
+  size_t bytes_by_dtype[hm::kNumDtypes] = {};
   hm::LaunchParams launch;
 };
 
@@ -116,7 +116,7 @@ struct hm_matrix {
   int32_t acc_dtype = 0, max_nrhs = 1;
   int32_t device = 0, n_cu = 256;       // device of the store and its compute units
   hm::LaunchParams launch;
-  size_t bytes_by_dtype[4] = {0, 0, 0, 0};
+  size_t bytes_by_dtype[hm::kNumDtypes] = {};
 };
 
 namespace hm {

@@ -21,8 +21,9 @@
 // Either schedule may run as persistent grids that loop over the items.
 //
 // Every sum has a fixed order, so results are bitwise reproducible and no
-// atomics touch y.  Storage formats (FP64/FP32/FP16/BF16, Table 1) are
-// decoded to the accumulation type in registers.
+// atomics touch y.  Storage formats (FP64/FP32/FP16/BF16, Table 1; the
+// byte-aligned DFL formats, Sec. 3.2) are decoded to the accumulation type
+// in registers.
 
 #include <algorithm>
 
@@ -34,10 +35,38 @@
 namespace hm {
 namespace {
 
-// acc += sum_c v[c] * z[c] over one 16-byte group of storage format DT.
+// Value c of a DFL group element: r[c] is the high word of its FP64
+// encoding; lo is the element's low-byte plane entry (DFL40: byte c holds
+// bits 31..24; DFL48: 16-bit half c holds bits 31..16).  Exact.
+template <int DT>
+__device__ __forceinline__ double dfl_value(u32x4 r, u32x2 lo, int c) {
+  unsigned low = 0;
+  if constexpr (DT == kDtDfl40) low = ((lo[0] >> (8 * c)) & 0xffu) << 24;
+  if constexpr (DT == kDtDfl48) low = ((lo[c >> 1] >> (16 * (c & 1))) & 0xffffu) << 16;
+  return __longlong_as_double((long long)(((unsigned long long)r[c] << 32) | low));
+}
+
+// The low-byte plane entry idx of a DFL40 / DFL48 region at p (zero for the
+// other formats, which have none).
+template <int DT>
+__device__ __forceinline__ u32x2 ld_lo(const uint8_t* p, int64_t idx) {
+  if constexpr (DT == kDtDfl40) {
+    return u32x2{__builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p) + idx), 0u};
+  } else if constexpr (DT == kDtDfl48) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p) + idx);
+  } else {
+    return (u32x2)(0u);
+  }
+}
+
+// acc += sum_c v[c] * z[c] over one 16-byte group of storage format DT
+// (lo: its low-byte plane entry, DFL40 / DFL48 only).
 template <typename AccT, int DT>
-__device__ __forceinline__ AccT dot_group(u32x4 r, const AccT* __restrict__ z, AccT acc) {
-  if constexpr (DT == HM_F64) {
+__device__ __forceinline__ AccT dot_group(u32x4 r, u32x2 lo, const AccT* __restrict__ z, AccT acc) {
+  if constexpr (is_dfl(DT)) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc = fmaT((AccT)dfl_value<DT>(r, lo, c), z[c], acc);
+  } else if constexpr (DT == HM_F64) {
     const f64x2 v = __builtin_bit_cast(f64x2, r);
     acc = fmaT((AccT)v.x, z[0], acc);
     acc = fmaT((AccT)v.y, z[1], acc);
@@ -63,8 +92,11 @@ __device__ __forceinline__ AccT dot_group(u32x4 r, const AccT* __restrict__ z, A
 
 // acc[c] += v[c] * xi for the G columns of one 16-byte group.
 template <typename AccT, int DT>
-__device__ __forceinline__ void axpy_group(u32x4 r, AccT xi, AccT* acc) {
-  if constexpr (DT == HM_F64) {
+__device__ __forceinline__ void axpy_group(u32x4 r, u32x2 lo, AccT xi, AccT* acc) {
+  if constexpr (is_dfl(DT)) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = fmaT((AccT)dfl_value<DT>(r, lo, c), xi, acc[c]);
+  } else if constexpr (DT == HM_F64) {
     const f64x2 v = __builtin_bit_cast(f64x2, r);
     acc[0] = fmaT((AccT)v.x, xi, acc[0]);
     acc[1] = fmaT((AccT)v.y, xi, acc[1]);
@@ -119,8 +151,8 @@ struct ColArgs {
 // LDS (red: 4 x 64 x 8), and wave 0 writes each column's sum to its
 // destination (a partial, or t).  DT >= 0: every group of the tile has
 // format DT; DT < 0: the tile holds runs of several formats and each lane
-// decodes its own (T.dtype, T.end).
-template <typename AccT, int DT>
+// decodes its own (T.dtype, T.end); DFL: such a tile may hold DFL32 runs.
+template <typename AccT, int DT, bool DFL = false>
 __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, AccT* red, AccT* xs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool act = lane < T.ngroups;
@@ -132,21 +164,31 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
   const int rstride = T.ngroups;                    // 16-byte groups per tile row
   const int nrows = T.nrows;
   const u32x4* p = reinterpret_cast<const u32x4*>(a.store + T.data_off) + lane;
+  // low-byte plane (DFL40 / DFL48 tiles, which hold that one format)
+  const uint8_t* lop = a.store + T.data_off + (int64_t)16 * nrows * rstride;
   const int nb = nrows > 8 * wave ? (nrows - 8 * wave + 31) / 32 : 0;   // this wave's batches
   u32x4 rn[8];
+  u32x2 ln[8];
   auto issue = [&](int j) {
     const int r0 = 32 * j + 8 * wave;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (act && r0 + u < nrows) rn[u] = ld16(p + (size_t)(r0 + u) * rstride);
+      if (act && r0 + u < nrows) {
+        rn[u] = ld16(p + (size_t)(r0 + u) * rstride);
+        ln[u] = ld_lo<DT>(lop, (int64_t)(r0 + u) * rstride + lane);
+      }
   };
   if (nb > 0) issue(0);
   for (int i = threadIdx.x; i < nrows; i += 256) xs[i] = a.x[T.x0 + i];
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
     u32x4 rc[8];
+    u32x2 lc[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) rc[u] = rn[u];
+    for (int u = 0; u < 8; ++u) {
+      rc[u] = rn[u];
+      lc[u] = ln[u];
+    }
     if (j + 1 < nb) issue(j + 1);
     const int r0 = 32 * j + 8 * wave;
 #pragma unroll
@@ -155,15 +197,18 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
         const AccT xi = xs[r0 + u];
         if (act) {
           if constexpr (DT >= 0) {
-            axpy_group<AccT, DT>(rc[u], xi, acc);
+            axpy_group<AccT, DT>(rc[u], lc[u], xi, acc);
           } else if (dt == HM_F32) {
-            axpy_group<AccT, HM_F32>(rc[u], xi, acc);
+            axpy_group<AccT, HM_F32>(rc[u], lc[u], xi, acc);
           } else if (dt == HM_F16) {
-            axpy_group<AccT, HM_F16>(rc[u], xi, acc);
+            axpy_group<AccT, HM_F16>(rc[u], lc[u], xi, acc);
           } else if (dt == HM_BF16) {
-            axpy_group<AccT, HM_BF16>(rc[u], xi, acc);
-          } else {
-            if constexpr (sizeof(AccT) == 8) axpy_group<AccT, HM_F64>(rc[u], xi, acc);
+            axpy_group<AccT, HM_BF16>(rc[u], lc[u], xi, acc);
+          } else if constexpr (sizeof(AccT) == 8) {
+            // FP64-accumulation formats; a several-format tile never holds
+            // a format with a low-byte plane
+            if (DFL && dt == kDtDfl32) axpy_group<AccT, kDtDfl32>(rc[u], lc[u], xi, acc);
+            else axpy_group<AccT, HM_F64>(rc[u], lc[u], xi, acc);
           }
         }
       }
@@ -193,27 +238,42 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
   }
 }
 
+// Tile kinds one instantiation decodes (a bit set; launches go per tile
+// class, so that the FP64 / IEEE paths carry no code of the DFL formats).
+constexpr int kColIeee = 1;     // one-format tiles of FP64, FP32, FP16, BF16
+constexpr int kColMulti = 2;    // several-format tiles
+constexpr int kColDfl = 4;      // one-format DFL tiles, and DFL32 runs in several-format tiles
+
 // A whole workgroup on tile ti (it synchronizes).  red: 4 * 64 * 8 values
 // (four waves x 64 lanes x at most 8 columns per lane); xs: kSegRows
-// values (x of the tile's rows).  MIXED: the tile may hold several formats
-// (the multi-format tile class); else it holds one (the format is
-// dispatched once per tile).
-template <typename AccT, bool MIXED = true>
+// values (x of the tile's rows).
+template <typename AccT, int KIND>
 __device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti, AccT* red, AccT* xs) {
   const ColTile T = a.tiles[ti];
-  if constexpr (MIXED) {
+  constexpr bool dfl = (KIND & kColDfl) && sizeof(AccT) == 8;
+  if constexpr ((KIND & kColMulti) != 0) {
     if (T.end[0] < T.ngroups) {                     // several formats in the tile
-      col_tile<AccT, -1>(a, T, red, xs);
+      col_tile<AccT, -1, dfl>(a, T, red, xs);
       return;
     }
   }
-  switch (T.dtype[0]) {
-    case HM_F64:
-      if constexpr (sizeof(AccT) == 8) col_tile<AccT, HM_F64>(a, T, red, xs);
-      break;
-    case HM_F32: col_tile<AccT, HM_F32>(a, T, red, xs); break;
-    case HM_F16: col_tile<AccT, HM_F16>(a, T, red, xs); break;
-    default: col_tile<AccT, HM_BF16>(a, T, red, xs); break;
+  if constexpr (dfl) {
+    switch (T.dtype[0]) {
+      case kDtDfl32: col_tile<AccT, kDtDfl32>(a, T, red, xs); return;
+      case kDtDfl40: col_tile<AccT, kDtDfl40>(a, T, red, xs); return;
+      case kDtDfl48: col_tile<AccT, kDtDfl48>(a, T, red, xs); return;
+      default: break;
+    }
+  }
+  if constexpr ((KIND & kColIeee) != 0) {
+    switch (T.dtype[0]) {
+      case HM_F64:
+        if constexpr (sizeof(AccT) == 8) col_tile<AccT, HM_F64>(a, T, red, xs);
+        break;
+      case HM_F32: col_tile<AccT, HM_F32>(a, T, red, xs); break;
+      case HM_F16: col_tile<AccT, HM_F16>(a, T, red, xs); break;
+      default: col_tile<AccT, HM_BF16>(a, T, red, xs); break;
+    }
   }
 }
 
@@ -286,21 +346,28 @@ struct RowArgs {
   int32_t n_cols;
 };
 
+// Groups [g_lo, g_hi) of a section at base (its low-byte plane, if any, at
+// lo_base), groups g_lo + wave, + 4, ... for this wave.
 template <typename AccT, int DT, int U>
-__device__ __forceinline__ AccT row_section(const uint8_t* base, int m, int g_lo, int g_hi,
-                                            const AccT* z, int lane, int wave, AccT acc) {
+__device__ __forceinline__ AccT row_section(const uint8_t* base, const uint8_t* lo_base, int m, int g_lo,
+                                            int g_hi, const AccT* z, int lane, int wave, AccT acc) {
   constexpr int G = group_width(DT);
   const u32x4* p = reinterpret_cast<const u32x4*>(base) + lane;
   int g = g_lo + wave;
   // U groups per wave in flight, all loads issued before the arithmetic
   for (; g + 4 * (U - 1) < g_hi; g += 4 * U) {
     u32x4 r[U];
+    u32x2 l[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) r[u] = ld16(p + (size_t)(g + 4 * u) * m);
+    for (int u = 0; u < U; ++u) {
+      r[u] = ld16(p + (size_t)(g + 4 * u) * m);
+      l[u] = ld_lo<DT>(lo_base, (int64_t)(g + 4 * u) * m + lane);
+    }
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc = dot_group<AccT, DT>(r[u], z + (g + 4 * u) * G, acc);
+    for (int u = 0; u < U; ++u) acc = dot_group<AccT, DT>(r[u], l[u], z + (g + 4 * u) * G, acc);
   }
-  for (; g < g_hi; g += 4) acc = dot_group<AccT, DT>(ld16(p + (size_t)g * m), z + g * G, acc);
+  for (; g < g_hi; g += 4)
+    acc = dot_group<AccT, DT>(ld16(p + (size_t)g * m), ld_lo<DT>(lo_base, (int64_t)g * m + lane), z + g * G, acc);
   return acc;
 }
 
@@ -308,7 +375,8 @@ __device__ __forceinline__ AccT row_section(const uint8_t* base, int m, int g_lo
 // sources staged in LDS by chunks of CAP slots, four waves stream the groups,
 // a fixed-order LDS reduction, then one update of the panel's rows of y.
 // Called by whole workgroups (it synchronizes).
-template <typename AccT, int CAP, int U>
+// DFL: the store holds DFL sections (decoded only by such instantiations).
+template <typename AccT, int CAP, int U, bool DFL>
 __device__ __forceinline__ void row_panel_part(const RowArgs<AccT>& a, const RowPanel& P,
                                                int q_begin, int q_end, int s_begin, int s_end,
                                                AccT* zs, AccT (*red)[64]) {
@@ -330,15 +398,32 @@ __device__ __forceinline__ void row_panel_part(const RowArgs<AccT>& a, const Row
         const int g_hi = min(S.ngroups, max(0, c_hi - S.col0) / G);
         if (g_hi <= g_lo) continue;
         const uint8_t* base = a.store + S.data_off;
+        const uint8_t* lob = base + (int64_t)16 * S.ngroups * P.m;   // low-byte plane (DFL40 / DFL48)
         const AccT* z = zs + (S.col0 - c_lo);
         switch (S.dtype) {
-          case HM_F64:
-            if constexpr (sizeof(AccT) == 8)
-              acc = row_section<AccT, HM_F64, U>(base, P.m, g_lo, g_hi, z, lane, wave, acc);
+          case HM_F32: acc = row_section<AccT, HM_F32, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc); break;
+          case HM_F16: acc = row_section<AccT, HM_F16, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc); break;
+          case HM_BF16: acc = row_section<AccT, HM_BF16, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc); break;
+          default:                                  // FP64-accumulation formats
+            if constexpr (sizeof(AccT) == 8 && !DFL) {
+              acc = row_section<AccT, HM_F64, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
+            } else if constexpr (sizeof(AccT) == 8) {
+              switch (S.dtype) {
+                case HM_F64:
+                  acc = row_section<AccT, HM_F64, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
+                  break;
+                case kDtDfl32:
+                  acc = row_section<AccT, kDtDfl32, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
+                  break;
+                case kDtDfl40:
+                  acc = row_section<AccT, kDtDfl40, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
+                  break;
+                default:
+                  acc = row_section<AccT, kDtDfl48, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
+                  break;
+              }
+            }
             break;
-          case HM_F32: acc = row_section<AccT, HM_F32, U>(base, P.m, g_lo, g_hi, z, lane, wave, acc); break;
-          case HM_F16: acc = row_section<AccT, HM_F16, U>(base, P.m, g_lo, g_hi, z, lane, wave, acc); break;
-          default: acc = row_section<AccT, HM_BF16, U>(base, P.m, g_lo, g_hi, z, lane, wave, acc); break;
         }
       }
     }
@@ -360,7 +445,7 @@ __device__ __forceinline__ int dense_slot_end(const RowArgs<AccT>& a, const RowP
 
 // Phase 1: the dense parts of the row panels and the column tiles in one
 // grouped launch.  Entry >= 0: a row panel; entry < 0: column tile -entry-1.
-template <typename AccT, int CAP, int U>
+template <typename AccT, int CAP, int U, bool DFL>
 __global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, const int32_t* order,
                                             int64_t n_items) {
   static_assert(CAP >= 4 * 64 * 8, "staging buffer doubles as the tile reduction buffer");
@@ -372,39 +457,39 @@ __global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, 
     const int item = order[it];
     if (item >= 0) {
       const RowPanel P = ra.rp[item];
-      row_panel_part<AccT, CAP, U>(ra, P, 0, P.nsec_dense, 0, dense_slot_end(ra, P), zs, red);
+      row_panel_part<AccT, CAP, U, DFL>(ra, P, 0, P.nsec_dense, 0, dense_slot_end(ra, P), zs, red);
     } else {
-      col_tile_any<AccT>(ca, -(int64_t)item - 1, zs, pxs);
+      col_tile_any<AccT, kColIeee | kColMulti | (DFL ? kColDfl : 0)>(ca, -(int64_t)item - 1, zs, pxs);
     }
   }
 }
 
 // Phase 2: the U sections of the row panels (after t is complete).
-template <typename AccT, int CAP, int U>
+template <typename AccT, int CAP, int U, bool DFL>
 __global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* order, int64_t n_items) {
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     if (it != blockIdx.x) __syncthreads();
     const RowPanel P = ra.rp[order[it]];
-    row_panel_part<AccT, CAP, U>(ra, P, P.nsec_dense, P.nsec, dense_slot_end(ra, P), P.ncols, zs, red);
+    row_panel_part<AccT, CAP, U, DFL>(ra, P, P.nsec_dense, P.nsec, dense_slot_end(ra, P), P.ncols, zs, red);
   }
 }
 
 // Schedule 0: all column tiles (one per workgroup item), then whole row
 // panels (dense and U sections in one pass).
-// Tiles [t0, t1): MIXED = false for the one-format tiles, true for the rest.
-template <typename AccT, bool MIXED>
-__global__ __launch_bounds__(256, MIXED ? 3 : 4) void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
+// Tiles [t0, t1) of the classes KIND decodes.
+template <typename AccT, int KIND>
+__global__ __launch_bounds__(256, KIND == kColIeee ? 4 : 3) void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
   __shared__ AccT cred[4 * 64 * 8];
   __shared__ AccT cxs[kSegRows];
   for (int64_t it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
     if (it != t0 + blockIdx.x) __syncthreads();
-    col_tile_any<AccT, MIXED>(ca, it, cred, cxs);
+    col_tile_any<AccT, KIND>(ca, it, cred, cxs);
   }
 }
 
-template <typename AccT, int CAP, int U>
+template <typename AccT, int CAP, int U, bool DFL>
 __global__ __launch_bounds__(256) void k_row(RowArgs<AccT> ra, const int32_t* order, int64_t n_panels,
                                              int64_t n_items) {
   __shared__ AccT zs[CAP];
@@ -414,7 +499,7 @@ __global__ __launch_bounds__(256) void k_row(RowArgs<AccT> ra, const int32_t* or
     if (pi < 0) continue;                           // uniform: whole workgroup
     __syncthreads();                                // LDS of the previous item
     const RowPanel P = ra.rp[pi];
-    row_panel_part<AccT, CAP, U>(ra, P, 0, P.nsec, 0, P.ncols, zs, red);
+    row_panel_part<AccT, CAP, U, DFL>(ra, P, 0, P.nsec, 0, P.ncols, zs, red);
   }
 }
 
@@ -440,7 +525,7 @@ __global__ __launch_bounds__(256) void k_stream_read(const u32x4* __restrict__ p
 
 // ---------------------------------------------------------------- launch
 
-template <typename AccT, int U>
+template <typename AccT, int U, bool DFL>
 hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void* y, void* work,
                           hipStream_t s, hipEvent_t* ev) {
   const StoreHeader& h = A.hdr;
@@ -463,16 +548,23 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
   if (ev) (void)hipEventRecord(ev[0], s);
   if (grouped) {
     if (h.n_p1 > 0)
-      hipLaunchKernelGGL((k_p1<AccT, CAP, U>), dim3(item_grid(h.n_p1, ps, ncu)), dim3(256), 0, s, ra,
+      hipLaunchKernelGGL((k_p1<AccT, CAP, U, DFL>), dim3(item_grid(h.n_p1, ps, ncu)), dim3(256), 0, s, ra,
                          ca, reinterpret_cast<const int32_t*>(st + h.off_p1_order), h.n_p1);
   } else {
-    const int64_t nu = h.tile_class_end[3], nm = h.n_col_tiles - nu;
-    if (nu > 0)
-      hipLaunchKernelGGL((k_col<AccT, false>), dim3(item_grid(nu, ps, ncu)), dim3(256), 0, s, ca,
-                         int64_t(0), nu);
+    // classes: one-format IEEE tiles [0, ce[3]), one-format DFL tiles
+    // [ce[3], ce[6]), several-format tiles [ce[6], ce[7])
+    const int64_t* ce = h.tile_class_end;
+    const int64_t ni = ce[HM_BF16], nd = ce[kNumDtypes - 1] - ni, nm = h.n_col_tiles - ce[kNumDtypes - 1];
+    if (ni > 0)
+      hipLaunchKernelGGL((k_col<AccT, kColIeee>), dim3(item_grid(ni, ps, ncu)), dim3(256), 0, s, ca,
+                         int64_t(0), ni);
+    if constexpr (DFL)
+      if (nd > 0)
+        hipLaunchKernelGGL((k_col<AccT, kColDfl>), dim3(item_grid(nd, ps, ncu)), dim3(256), 0, s, ca, ni,
+                           ce[kNumDtypes - 1]);
     if (nm > 0)
-      hipLaunchKernelGGL((k_col<AccT, true>), dim3(item_grid(nm, ps, ncu)), dim3(256), 0, s, ca, nu,
-                         h.n_col_tiles);
+      hipLaunchKernelGGL((k_col<AccT, kColMulti | (DFL ? kColDfl : 0)>), dim3(item_grid(nm, ps, ncu)),
+                         dim3(256), 0, s, ca, ce[kNumDtypes - 1], h.n_col_tiles);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
   if (h.n_col_tiles > 0) {
@@ -485,12 +577,12 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
   if (ev) (void)hipEventRecord(ev[2], s);
   if (grouped) {
     if (h.n_p2 > 0)
-      hipLaunchKernelGGL((k_p2<AccT, CAP, U>), dim3(item_grid(h.n_p2, ps, ncu)), dim3(256), 0, s, ra,
+      hipLaunchKernelGGL((k_p2<AccT, CAP, U, DFL>), dim3(item_grid(h.n_p2, ps, ncu)), dim3(256), 0, s, ra,
                          reinterpret_cast<const int32_t*>(st + h.off_p2_order), h.n_p2);
   } else if (h.n_row_panels > 0) {
     const bool xcd = A.launch.order == 1;
     const int64_t items = panel_items(xcd, h.n_row_panels);
-    hipLaunchKernelGGL((k_row<AccT, CAP, U>), dim3(item_grid(items, ps, ncu)), dim3(256), 0, s, ra,
+    hipLaunchKernelGGL((k_row<AccT, CAP, U, DFL>), dim3(item_grid(items, ps, ncu)), dim3(256), 0, s, ra,
                        xcd ? nullptr : reinterpret_cast<const int32_t*>(st + h.off_row_order),
                        h.n_row_panels, items);
   }
@@ -498,11 +590,19 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
   return hipGetLastError();
 }
 
+// DFL instantiations (FP64 accumulation only) run when the store holds DFL bytes.
 template <typename AccT>
 hipError_t launch_typed(const hm_matrix& A, double alpha, const void* x, void* y, void* work,
                         hipStream_t s, hipEvent_t* ev) {
-  return A.launch.row_unroll >= 8 ? launch_typed_u<AccT, 8>(A, alpha, x, y, work, s, ev)
-                                  : launch_typed_u<AccT, 4>(A, alpha, x, y, work, s, ev);
+  if constexpr (sizeof(AccT) == 8) {
+    bool dfl = false;
+    for (int d = kDtDfl32; d <= kDtDfl48; ++d) dfl = dfl || A.bytes_by_dtype[d] > 0;
+    if (dfl)
+      return A.launch.row_unroll >= 8 ? launch_typed_u<AccT, 8, true>(A, alpha, x, y, work, s, ev)
+                                      : launch_typed_u<AccT, 4, true>(A, alpha, x, y, work, s, ev);
+  }
+  return A.launch.row_unroll >= 8 ? launch_typed_u<AccT, 8, false>(A, alpha, x, y, work, s, ev)
+                                  : launch_typed_u<AccT, 4, false>(A, alpha, x, y, work, s, ev);
 }
 
 }  // namespace

@@ -667,7 +667,7 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
       ColBArgs ca{st, reinterpret_cast<const ColTile*>(st + h.off_col_tiles),
                   reinterpret_cast<const int32_t*>(st + h.off_col_dst), xr, part,
                   (int32_t)(A.work_part_bytes / (int64_t)sizeof(float)), sigma, h.n_col_tiles, RS, RH};
-      // one launch per tile class (FP64 tiles do not occur with FP32 accumulation)
+      // one launch per tile class
       const int64_t* ce = h.tile_class_end;
       auto grid = [&](int64_t t0, int64_t t1, int parts) { return dim3((unsigned)((t1 - t0) * parts * RH)); };
       if (ce[1] > ce[0])
@@ -676,8 +676,10 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
         hipLaunchKernelGGL(k_col_b16<HM_F16>, grid(ce[1], ce[2], 8), dim3(64), 0, s, ca, ce[1], ce[2]);
       if (ce[3] > ce[2])
         hipLaunchKernelGGL(k_col_b16<HM_BF16>, grid(ce[2], ce[3], 8), dim3(64), 0, s, ca, ce[2], ce[3]);
-      if (ce[4] > ce[3])
-        hipLaunchKernelGGL(k_col_b16<-1>, grid(ce[3], ce[4], 8), dim3(64), 0, s, ca, ce[3], ce[4]);
+      // (FP64 and DFL tiles, classes 0 and 4..6, do not occur with FP32 accumulation)
+      constexpr int M = kNumDtypes;
+      if (ce[M] > ce[M - 1])
+        hipLaunchKernelGGL(k_col_b16<-1>, grid(ce[M - 1], ce[M], 8), dim3(64), 0, s, ca, ce[M - 1], ce[M]);
       if (ev && r0 == 0) (void)hipEventRecord(ev[1], s);
       RedBArgs rb{reinterpret_cast<const TBlock*>(st + h.off_tblocks),
                   reinterpret_cast<const int32_t*>(st + h.off_owner), sigma, part, t, h.n_red_t, RS};

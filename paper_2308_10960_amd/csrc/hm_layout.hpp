@@ -11,7 +11,10 @@
 //    (source x[sigma]) and the k columns of U_b / W_b (source t_b).  The
 //    panel is stored per storage dtype ("section") in column groups of G
 //    columns, element (i, c) of group g at ((g*m + i)*G + c): one 16-byte
-//    load per lane (lane = row) covers G columns.  The kernel owns y[rho]:
+//    load per lane (lane = row) covers G columns.  A section of a format
+//    with a low-byte plane (DFL40, DFL48) has that plane after its groups:
+//    the low bytes of group element (g, i) at 16 ngroups m + L (g*m + i),
+//    L = lo_bytes (one more 4- or 8-byte load per lane).  The kernel owns y[rho]:
 //    y[rho] += alpha * P_rho z_rho, with z the gathered sources.
 //  * Column tiles.  The rows of every V_b / X_b are cut into chunks kappa of
 //    at most 512 rows: sigma_b itself if small, else its largest sub-clusters
@@ -22,7 +25,11 @@
 //    another; inside a tile the rows follow each other, each holding the
 //    tile's groups contiguously, so a wave (lane = group) streams one
 //    contiguous block and accumulates its G columns over the rows:
-//    partial(b, kappa, l) = sum_{i in kappa} V_b[i, l] x[i].
+//    partial(b, kappa, l) = sum_{i in kappa} V_b[i, l] x[i].  A tile of a
+//    format with a low-byte plane (only ever a one-format tile: such a
+//    format is then the format of every low-rank group) has the plane after
+//    its rows: the low bytes of row i, group g at 16 nrows ngroups +
+//    L (i ngroups + g).
 //  * Reduction.  t_b[l] = s_b[l] * sum over the chunks of sigma_b of the
 //    partials, in ascending chunk order.
 //  * Single-RHS schedule: phase 1 streams the dense sections of the row
@@ -45,9 +52,22 @@ constexpr int kTileGroups = 64;     // column groups per column tile (one per la
 constexpr int kLargeSeg = 16;       // blocks with more intervals reduce per workgroup
 constexpr int kAlign = 256;
 
-// Columns per 16-byte group for a storage dtype (F64, F32, F16, BF16).
-inline constexpr int group_width(int dt) { return dt == 0 ? 2 : dt == 1 ? 4 : 8; }
-inline constexpr int dtype_size(int dt) { return dt == 0 ? 8 : dt == 1 ? 4 : 2; }
+// Storage formats (hm_dtype): F64, F32, F16, BF16, DFL32, DFL40, DFL48.
+constexpr int kNumDtypes = 7;
+constexpr int kDtDfl32 = 4, kDtDfl40 = 5, kDtDfl48 = 6;
+
+// Columns per 16-byte group for a storage dtype.  A DFL value keeps its
+// leading 4 bytes (the high 32-bit word of its FP64 encoding) in the group.
+inline constexpr int group_width(int dt) { return dt == 0 ? 2 : (dt == 2 || dt == 3) ? 8 : 4; }
+// Bytes per value inside the 16-byte groups.
+inline constexpr int dtype_size(int dt) { return dt == 0 ? 8 : (dt == 2 || dt == 3) ? 2 : 4; }
+// DFL40 / DFL48 keep the rest of each value (1 / 2 bytes: bits 31..24 /
+// 31..16 of the encoding) in a low-byte plane: lo_bytes per 16-byte group
+// element (4 values), 0 for the other formats.
+inline constexpr int lo_bytes(int dt) { return dt == kDtDfl40 ? 4 : dt == kDtDfl48 ? 8 : 0; }
+// Stored bytes per value.
+inline constexpr int value_bytes(int dt) { return dtype_size(dt) + lo_bytes(dt) / 4; }
+inline constexpr bool is_dfl(int dt) { return dt >= kDtDfl32 && dt <= kDtDfl48; }
 
 struct RowPanel {        // 32 bytes
   int64_t src_off;       // first entry (int32 units) in the row-source table
@@ -68,6 +88,7 @@ struct RowSection {      // 32 bytes
 
 struct ColTile {         // 32 bytes: nrows rows x ngroups 16-byte groups
   int64_t data_off;      // byte offset of the tile (row 0, first group); row i at + 16 i ngroups
+                         // (low-byte plane, if any, from + 16 nrows ngroups)
   int32_t nrows;         // rows of the column chunk (<= 512)
   int32_t x0;            // first x index of the chunk
   int32_t ngroups;       // groups in this tile (<= 64)
@@ -128,15 +149,18 @@ struct StoreHeader {
   // the blocks inside one column chunk, [n_red_t, n_t), get t directly from
   // the column tiles
   int64_t n_red_t;
-  // column tiles by class, each class largest first: tiles of one storage
-  // format f (FP64, FP32, FP16, BF16) are [tile_class_end[f-1], tile_class_end[f]),
-  // tiles with runs of several formats [tile_class_end[3], tile_class_end[4])
-  int64_t tile_class_end[5];
+  // column tiles by class: tiles of one storage format f are
+  // [tile_class_end[f-1], tile_class_end[f]) (tile_class_end[-1] = 0), tiles
+  // with runs of several formats [tile_class_end[kNumDtypes-1],
+  // tile_class_end[kNumDtypes])
+  int64_t tile_class_end[kNumDtypes + 1];
 };
 
-// Class of a column tile: its format if it has one, else 4.
-inline constexpr int tile_class(const ColTile& T) { return T.end[0] == T.ngroups ? T.dtype[0] : 4; }
+// Class of a column tile: its format if it has one, else kNumDtypes.
+inline constexpr int tile_class(const ColTile& T) {
+  return T.end[0] == T.ngroups ? T.dtype[0] : kNumDtypes;
+}
 
-constexpr uint64_t kStoreMagic = 0x484d53544f524532ull;  // "HMSTORE2"
+constexpr uint64_t kStoreMagic = 0x484d53544f524533ull;  // "HMSTORE3"
 
 }  // namespace hm

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libhm.so")
 HM_OK, HM_EINVAL, HM_EPARTITION, HM_ESHAPE, HM_EDTYPE = 0, -1, -2, -3, -4
 HM_ENOMEM, HM_EDEVICE, HM_EBUSY, HM_ESTATE, HM_ETIMEOUT = -5, -6, -7, -8, -9
 HM_F64, HM_F32, HM_F16, HM_BF16 = 0, 1, 2, 3
+HM_DFL32, HM_DFL40, HM_DFL48 = 4, 5, 6
+HM_NUM_DTYPES = 7
 HM_DENSE, HM_LOWRANK = 0, 1
 
 STATUS_NAMES = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_EPARTITION", -3: "HM_ESHAPE",
@@ -43,7 +45,7 @@ class PlanInfo(C.Structure):
                 ("overhead_bytes", C.c_double), ("n_dense", C.c_int64),
                 ("n_lowrank", C.c_int64), ("n_row_panels", C.c_int64),
                 ("n_col_tiles", C.c_int64), ("n_partials", C.c_int64), ("n_t", C.c_int64),
-                ("bytes_by_dtype", C.c_size_t * 4)]
+                ("bytes_by_dtype", C.c_size_t * HM_NUM_DTYPES)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "bytes_by_dtype"}
@@ -64,7 +66,7 @@ PROTOTYPES = {
     "hm_build_plan": (_i32, [_i64, _i64, _vp, _i64, _P(PlanOpts), _P(_vp)]),
     "hm_plan_info": (_i32, [_vp, _P(PlanInfo)]),
     "hm_plan_destroy": (None, [_vp]),
-    "hm_plan_locate": (_i32, [_vp, _i64, _i32, _i64, _i64, _P(_sz), _P(_i32)]),
+    "hm_plan_locate": (_i32, [_vp, _i64, _i32, _i64, _i64, _P(_sz), _P(_i32), _P(_sz)]),
     "hm_upload": (_i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp, _P(_vp)]),
     "hm_matrix_destroy": (None, [_vp]),
     "hm_pack_host": (_i32, [_vp, _vp, _vp, _vp, _vp, _sz]),
@@ -166,11 +168,13 @@ def hm_plan_destroy(plan: int) -> None:
     lib().hm_plan_destroy(plan)
 
 
-def hm_plan_locate(plan: int, block: int, which: int, i: int, j: int):
-    off, dt = C.c_size_t(), C.c_int32()
-    _check(lib().hm_plan_locate(plan, block, which, i, j, C.byref(off), C.byref(dt)),
+def hm_plan_locate(plan: int, block: int, which: int, i: int, j: int, lo: bool = False):
+    """(byte offset, dtype) of a stored factor entry; with lo=True also the
+    offset of its low bytes (DFL40 / DFL48; 0 for the other formats)."""
+    off, dt, lo_off = C.c_size_t(), C.c_int32(), C.c_size_t()
+    _check(lib().hm_plan_locate(plan, block, which, i, j, C.byref(off), C.byref(dt), C.byref(lo_off)),
            "hm_plan_locate")
-    return off.value, dt.value
+    return (off.value, dt.value, lo_off.value) if lo else (off.value, dt.value)
 
 
 def hm_upload(plan: int, a_ptrs: np.ndarray, b_ptrs: np.ndarray, s_ptrs: np.ndarray | None,

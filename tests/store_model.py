@@ -25,8 +25,18 @@ RS = np.dtype([("data_off", "<i8"), ("dtype", "<i4"), ("ngroups", "<i4"), ("col0
 CT = np.dtype([("data_off", "<i8"), ("nrows", "<i4"), ("x0", "<i4"), ("ngroups", "<i4"),
                ("dst_off", "<i4"), ("dtype", "u1", (4,)), ("end", "u1", (4,))])
 TB = np.dtype([("pst", "<i4"), ("k", "<i4"), ("nseg", "<i4"), ("toff", "<i4")])
-G = {0: 2, 1: 4, 2: 8, 3: 8}
-SZ = {0: 8, 1: 4, 2: 2, 3: 2}
+G = {0: 2, 1: 4, 2: 8, 3: 8, 4: 4, 5: 4, 6: 4}
+SZ = {0: 8, 1: 4, 2: 2, 3: 2, 4: 4, 5: 4, 6: 4}      # bytes per value inside the 16-byte groups
+LO = {5: (1, 24), 6: (2, 16)}                        # DFL40 / DFL48: low bytes per value, bit position
+
+
+def decode_dfl(hi: np.ndarray, lo, dt: int) -> np.ndarray:
+    """DFL values from the high words of their FP64 encodings (uint32) and,
+    for DFL40 / DFL48, their low bytes (uint8 / uint16 arrays of the same shape)."""
+    bits = hi.astype(np.uint64) << np.uint64(32)
+    if dt in LO:
+        bits |= lo.astype(np.uint64) << np.uint64(LO[dt][1])
+    return bits.view("<f8")
 
 
 def decode(buf: np.ndarray, off: int, count: int, dt: int) -> np.ndarray:
@@ -63,13 +73,23 @@ def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> n
     for t in T["ct"]:
         nr, ng = int(t["nrows"]), int(t["ngroups"])
         # a tile row is ng 16-byte groups, in runs of one format each
-        raw = buf[int(t["data_off"]): int(t["data_off"]) + nr * ng * 16].reshape(nr, ng * 16)
+        d0 = int(t["data_off"])
+        raw = buf[d0: d0 + nr * ng * 16].reshape(nr, ng * 16)
         parts, g0 = [], 0
         for r in range(4):
             e, dt = int(t["end"][r]), int(t["dtype"][r])
             if e > g0:
                 block = np.ascontiguousarray(raw[:, 16 * g0: 16 * e]).reshape(-1)
-                parts.append(decode(block, 0, block.size // SZ[dt], dt).reshape(nr, -1))
+                if dt >= 4:
+                    lo = None
+                    if dt in LO:                             # low-byte plane after the rows (one-format tile)
+                        assert g0 == 0 and e == ng
+                        nb = LO[dt][0]
+                        lo = np.ascontiguousarray(buf[d0 + nr * ng * 16: d0 + nr * ng * (16 + 4 * nb)])
+                        lo = lo.view("<u1" if nb == 1 else "<u2")
+                    parts.append(decode_dfl(block.view("<u4"), lo, dt).reshape(nr, -1))
+                else:
+                    parts.append(decode(block, 0, block.size // SZ[dt], dt).reshape(nr, -1))
             g0 = e
         assert g0 == ng
         V = np.concatenate(parts, axis=1)                    # nr x cols (tile column order)
@@ -105,7 +125,17 @@ def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> n
         for s in T["rs"][int(p["sec0"]): int(p["sec0"]) + int(p["nsec"])]:
             dt, ng, c0 = int(s["dtype"]), int(s["ngroups"]), int(s["col0"])
             g = G[dt]
-            vals = decode(buf, int(s["data_off"]), ng * m * g, dt).reshape(ng, m, g)
+            d0 = int(s["data_off"])
+            if dt >= 4:
+                hi = np.ascontiguousarray(buf[d0: d0 + ng * m * 16]).view("<u4")
+                lo = None
+                if dt in LO:                                 # low-byte plane after the groups
+                    nb = LO[dt][0]
+                    lo = np.ascontiguousarray(buf[d0 + ng * m * 16: d0 + ng * m * (16 + 4 * nb)])
+                    lo = lo.view("<u1" if nb == 1 else "<u2")
+                vals = decode_dfl(hi, lo, dt).reshape(ng, m, g)
+            else:
+                vals = decode(buf, d0, ng * m * g, dt).reshape(ng, m, g)
             M = vals.transpose(1, 0, 2).reshape(m, ng * g)       # m x cols
             acc += M @ z[src[c0: c0 + ng * g]]
         y[int(p["row0"]): int(p["row0"]) + m] += alpha * acc

@@ -105,3 +105,79 @@ def test_generator_and_oracle_rounding_agree(fmt):
         a = ORACLE_ROUND[fmt](x)
     b = gen_round(x, FMT_DT[fmt])
     np.testing.assert_array_equal(a, b)
+
+
+# ------------------------------------------------------------------ DFL (Sec. 3.2)
+
+def _dfl_by_bits(x: np.ndarray, nbytes: int) -> np.ndarray:
+    """Independent form of DFL rounding: keep the leading nbytes bytes of
+    each FP64 encoding, rounding the dropped bits to nearest, ties to the
+    even kept pattern, with integer arithmetic on the bit pattern (a carry
+    runs into the exponent field)."""
+    b = np.ascontiguousarray(x, dtype=np.float64).view(np.uint64).astype(object)
+    drop = 64 - 8 * nbytes
+    out = []
+    for v in b:
+        kept, rem, half = v >> drop, v & ((1 << drop) - 1), 1 << (drop - 1)
+        if rem > half or (rem == half and kept & 1):
+            kept += 1
+        out.append((kept << drop) & ((1 << 64) - 1))
+    return np.array(out, dtype=np.uint64).view(np.float64)
+
+
+@pytest.mark.parametrize("nbytes", [4, 5, 6])
+def test_dfl_matches_bit_pattern_rounding(nbytes):
+    """round_dfl (frexp / rint, from the value) equals rounding of the bit
+    pattern, over magnitudes from FP64 subnormals to near the largest finite
+    value and over exact ties."""
+    rng = np.random.default_rng(nbytes)
+    x = rng.standard_normal(3000) * np.exp2(rng.integers(-1060, 1000, 3000).astype(float))
+    m = 8 * nbytes - 12
+    # exact ties: kept pattern odd and even, dropped part exactly one half
+    k = rng.integers(1 << m, 1 << (m + 1), 400).astype(float)
+    ties = np.ldexp(k + 0.5, rng.integers(-900, 900, 400) - m) * rng.choice([-1.0, 1.0], 400)
+    x = np.concatenate([x, ties, [5e-324, -5e-324, 2.2250738585072014e-308, 1.7976931348623157e308]])
+    x = x[np.isfinite(x)]
+    got = oracle.round_to(x, {4: oracle.DFL32, 5: oracle.DFL40, 6: oracle.DFL48}[nbytes])
+    want = _dfl_by_bits(x, nbytes)
+    both_inf = np.isinf(got) & np.isinf(want) & (np.sign(got) == np.sign(want))
+    assert np.array_equal(got[~both_inf].view(np.uint64), want[~both_inf].view(np.uint64))
+
+
+def test_dfl_definition_cases():
+    """Hand-worked DFL32 values (20 explicit mantissa bits, FP64 exponent)."""
+    r = lambda v: float(oracle.round_dfl(np.array([v]), 4)[0])
+    u = 2.0 ** -20                                   # spacing of the kept mantissa at 1
+    assert r(1 + u / 2) == 1.0                       # tie, kept pattern even: down
+    assert r(1 + 3 * u / 2) == 1 + 2 * u             # tie, kept pattern odd: up to even
+    assert r(1 + u / 2 + 2.0 ** -52) == 1 + u        # just above the tie: up
+    assert r(-(1 + u / 2)) == -1.0                   # sign carried, same rule
+    assert r(2 - 2.0 ** -30) == 2.0                  # carry into the exponent
+    assert r(1e300) == pytest.approx(1e300, rel=2.0 ** -21)   # FP64 range kept (BF16 / FP32 would overflow)
+    assert r(1e-300) == pytest.approx(1e-300, rel=2.0 ** -21)
+    assert oracle.round_dfl(np.array([0.1]), 8)[0] == 0.1     # 8 bytes: FP64 itself
+
+
+@pytest.mark.parametrize("nbytes", [4, 5, 6])
+def test_dfl_unit_roundoff(nbytes):
+    """|fl(x) - x| <= 2^-(m+1) |x| for normal x, m = 8 nbytes - 12, and the
+    bound is reached (to within 1%) on random values."""
+    m = 8 * nbytes - 12
+    rng = np.random.default_rng(7)
+    x = rng.uniform(0.5, 1.0, 200000) * np.exp2(rng.integers(-500, 500, 200000).astype(float))
+    rel = np.abs(oracle.round_dfl(x, nbytes) - x) / np.abs(x)
+    assert rel.max() <= 2.0 ** -(m + 1)
+    assert rel.max() >= 0.99 * 2.0 ** -(m + 1)
+
+
+def test_dfl_format_choice():
+    """Sec. 3.2: 1 + 11 + m_eps bits, the mantissa increased to fill whole
+    bytes; m_eps = ceil(log2(1/eps)) (the reading used here)."""
+    import hmgen
+    for eps, m, nbytes in ((1e-6, 20, 4), (1e-8, 27, 5), (1e-10, 34, 6), (1e-4, 14, 4)):
+        assert hmgen.dfl_mantissa_bits(eps) == m
+        assert (1 + 11 + m + 7) // 8 == max(nbytes, (1 + 11 + m + 7) // 8)
+        assert hmgen.dfl_format(eps) == {4: oracle.DFL32, 5: oracle.DFL40, 6: oracle.DFL48}[nbytes]
+        # the kept mantissa's unit roundoff meets eps / 2
+        assert 2.0 ** -(8 * nbytes - 12 + 1) <= eps / 2
+    assert hmgen.dfl_format(1e-12) == oracle.F64                 # 7 bytes: FP64 instead

@@ -139,26 +139,103 @@ def test_storage_conversion_bit_exact(mixed4k):
     hm.hm_plan_destroy(p)
 
 
-@pytest.mark.parametrize("which", ["f64", "mixed", "mixed16k", "bf16"])
+def _set_dtypes(H, dense_dt: int, lr_dt: int) -> None:
+    """Dense blocks in dense_dt, every low-rank block (one group) in lr_dt."""
+    H.set_uniform_dtype(lr_dt)
+    H.group_dtype[H.adm == 0, 0] = dense_dt
+
+
+@pytest.mark.parametrize("dense_dt,lr_dt", [(hm.HM_DFL32, hm.HM_DFL32), (hm.HM_DFL40, hm.HM_DFL40),
+                                            (hm.HM_DFL48, hm.HM_DFL48), (hm.HM_DFL48, hm.HM_DFL32)])
+def test_dfl_conversion_bit_exact(dense_dt, lr_dt):
+    """DFL entries sit at the offsets hm_plan_locate reports: the high word
+    of the encoding of the oracle's rounded value, and its low byte(s) in the
+    low-byte plane (DFL40: bits 31..24, DFL48: bits 31..16)."""
+    H = hmgen.build_preset("sphere4k")
+    _set_dtypes(H, dense_dt, lr_dt)
+    p, info, buf = _pack(H, hm.HM_F64)
+    rng = np.random.default_rng(1)
+    seen = set()
+    for bi in rng.choice(H.nblocks, 300, replace=False):
+        a, b, s = H.factors(bi)
+        for which, F in ((0, a), (1, b)):
+            if F is None or F.size == 0:
+                continue
+            for _ in range(6):
+                i, j = int(rng.integers(F.shape[0])), int(rng.integers(F.shape[1]))
+                off, dt, lo_off = hm.hm_plan_locate(p, int(bi), which, i, j, lo=True)
+                assert dt == (lr_dt if H.adm[bi] else dense_dt)
+                bits = int(oracle.round_to(np.array([F[i, j]]), dt).view("<u8")[0])
+                assert int(buf[off: off + 4].view("<u4")[0]) == bits >> 32, (bi, which, i, j)
+                if dt == hm.HM_DFL40:
+                    assert int(buf[lo_off]) == (bits >> 24) & 0xff
+                elif dt == hm.HM_DFL48:
+                    assert int(buf[lo_off: lo_off + 2].view("<u2")[0]) == (bits >> 16) & 0xffff
+                else:
+                    assert lo_off == 0
+                assert bits & ((1 << (64 - 8 * {4: 4, 5: 5, 6: 6}[dt])) - 1) == 0
+                seen.add(dt)
+    assert seen == {dense_dt, lr_dt}
+    per_value = {hm.HM_DFL32: 4, hm.HM_DFL40: 5, hm.HM_DFL48: 6}
+    for dt in seen:
+        assert info["bytes_by_dtype"][dt] > 0 and info["bytes_by_dtype"][dt] % per_value[dt] == 0
+    hm.hm_plan_destroy(p)
+
+
+def test_dfl_plan_rules():
+    """DFL needs FP64 accumulation; DFL40 / DFL48 low-rank groups admit no
+    other low-rank format in the plan."""
+    H = hmgen.build_preset("sphere4k")
+    _set_dtypes(H, hm.HM_F64, hm.HM_DFL32)
+    with pytest.raises(hm.HMError) as e:
+        hm.hm_build_plan(H.n, H.n, blocks_from_table(H), hm.HM_F32)
+    assert e.value.status == hm.HM_EDTYPE
+    for lo_fmt in (hm.HM_DFL40, hm.HM_DFL48):
+        _set_dtypes(H, hm.HM_F64, lo_fmt)
+        lr = np.flatnonzero((H.adm != 0) & (H.rank > 0))
+        H.group_dtype[lr[len(lr) // 2], 0] = hm.HM_DFL32
+        with pytest.raises(hm.HMError) as e:
+            hm.hm_build_plan(H.n, H.n, blocks_from_table(H), hm.HM_F64)
+        assert e.value.status == hm.HM_EDTYPE
+    # dense blocks may use any format beside them
+    _set_dtypes(H, hm.HM_DFL32, hm.HM_DFL40)
+    hm.hm_plan_destroy(hm.hm_build_plan(H.n, H.n, blocks_from_table(H), hm.HM_F64))
+
+
+@pytest.mark.parametrize("which", ["f64", "mixed", "mixed16k", "bf16", "dfl32", "dfl40_16k", "dfl48",
+                                   "dfl_mix"])
 def test_store_model_matches_oracle(which, f64_4k, mixed4k):
     """The packed store, read as its layout defines it, gives the oracle's
     product.  At n = 16384 some blocks span several column chunks (partials
     and their reduction); mixed column tiles hold runs of several formats;
-    "bf16" stores every block in BF16 (one-format BF16 tiles)."""
+    "bf16" stores every block in BF16 (one-format BF16 tiles); "dfl*" store
+    DFL formats with FP64 accumulation (low-byte planes in row sections and
+    tiles; "dfl_mix": dense DFL48 and FP64 beside low-rank DFL32, whose
+    tiles are one-format)."""
     if which == "mixed16k":
         H = hmgen.build_preset("sphere4k_mixed", n=16384)
     elif which == "bf16":
         H = hmgen.build_preset("sphere4k_mixed")
         H.set_uniform_dtype(hm.HM_BF16)
+    elif which.startswith("dfl"):
+        H = hmgen.build_preset("sphere4k", n=16384 if which.endswith("16k") else None)
+        if which == "dfl_mix":
+            _set_dtypes(H, hm.HM_DFL48, hm.HM_DFL32)
+            dense = np.flatnonzero(H.adm == 0)
+            H.group_dtype[dense[::3], 0] = hm.HM_F64
+        else:
+            H.set_uniform_dtype({"dfl32": hm.HM_DFL32, "dfl40_16k": hm.HM_DFL40, "dfl48": hm.HM_DFL48}[which])
     else:
         H = {"f64": f64_4k, "mixed": mixed4k}[which]
-    acc = hm.HM_F64 if which == "f64" else hm.HM_F32
+    acc = hm.HM_F64 if which == "f64" or which.startswith("dfl") else hm.HM_F32
     p, info, buf = _pack(H, acc)
-    if which == "mixed16k":
+    if which.endswith("16k"):
         assert info["n_partials"] > 0
     x = hmgen.uniform_vector(H.n)
     y0 = hmgen.uniform_vector(H.n, seed=5)
-    if which == "f64":
+    if which.startswith("dfl"):
+        ref = oracle.hmvm(H, x, y0, alpha=0.75, factors=oracle.decoded_factors(H, sigma_dtype=oracle.F64))
+    elif which == "f64":
         ref = oracle.hmvm(H, x, y0, alpha=0.75)
     else:
         ref = oracle.hmvm(H, x, y0, alpha=0.75,
