@@ -7,7 +7,8 @@ evaluated on the DFL-rounded factors to the FP64 bar (relative 2-norm error
 FP64 product the error is the storage rounding, stated and bounded by the
 format's unit roundoff.  Layouts: one format everywhere (DFL32, DFL40 with
 partials at n = 16384, DFL48), dense blocks in DFL48 and FP64 beside
-low-rank DFL32; both schedules, persistent grids and a graph replay; the
+low-rank DFL32, and FP32 storage (BFL at 4 bytes) under FP64 accumulation;
+both schedules, persistent grids and a graph replay; the
 full n = 2^18 sizes at eps 1e-6 (DFL32) and 1e-8 (DFL40).
 """
 
@@ -63,6 +64,11 @@ def layout(name):
         H.group_dtype[dense, 0] = hm.HM_DFL48
         H.group_dtype[dense[::3], 0] = hm.HM_F64
         return H, 2.0 ** -(MANT[hm.HM_DFL32] + 1)
+    if name == "bfl32":
+        # BFL at 4 bytes (8 exponent bits, 23 mantissa bits) is FP32 storage
+        H = hmgen.build_preset("sphere4k")
+        H.set_uniform_dtype(hm.HM_F32)
+        return H, 2.0 ** -24
     dt = {"dfl32": hm.HM_DFL32, "dfl40_16k": hm.HM_DFL40, "dfl48": hm.HM_DFL48}[name]
     H = hmgen.build_preset("sphere4k", n=16384 if name.endswith("16k") else None)
     H.set_uniform_dtype(dt)
@@ -76,7 +82,7 @@ def check(y, ref, scale, what):
     assert np.all(np.abs(y - ref) <= 1e-13 * scale + 1e-300)
 
 
-@pytest.mark.parametrize("name", ["dfl32", "dfl40_16k", "dfl48", "dfl_mix"])
+@pytest.mark.parametrize("name", ["dfl32", "dfl40_16k", "dfl48", "dfl_mix", "bfl32"])
 def test_dfl_parity(name):
     H, u = layout(name)
     say("layout", name, "n", H.n)
