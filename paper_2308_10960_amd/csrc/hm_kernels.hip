@@ -247,9 +247,14 @@ constexpr int kColDfl = 4;      // one-format DFL tiles, and DFL32 runs in sever
 // A whole workgroup on tile ti (it synchronizes).  red: 4 * 64 * 8 values
 // (four waves x 64 lanes x at most 8 columns per lane); xs: kSegRows
 // values (x of the tile's rows).
-template <typename AccT, int KIND>
+// DT >= 0: every tile has that one format.
+template <typename AccT, int KIND, int DT = -1>
 __device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti, AccT* red, AccT* xs) {
   const ColTile T = a.tiles[ti];
+  if constexpr (DT >= 0) {
+    col_tile<AccT, DT>(a, T, red, xs);
+    return;
+  }
   constexpr bool dfl = (KIND & kColDfl) && sizeof(AccT) == 8;
   if constexpr ((KIND & kColMulti) != 0) {
     if (T.end[0] < T.ngroups) {                     // several formats in the tile
@@ -478,14 +483,17 @@ __global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* ord
 
 // Schedule 0: all column tiles (one per workgroup item), then whole row
 // panels (dense and U sections in one pass).
-// Tiles [t0, t1) of the classes KIND decodes.
-template <typename AccT, int KIND>
-__global__ __launch_bounds__(256, KIND == kColIeee ? 4 : 3) void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
+// Tiles [t0, t1) of the classes KIND decodes (DT >= 0: the one-format
+// class DT).  Four workgroups per CU, three where the registers need it
+// (several-format tiles; DFL40 / DFL48 with their low-byte loads).
+template <typename AccT, int KIND, int DT = -1>
+__global__ __launch_bounds__(256, (KIND == kColIeee || DT == kDtDfl32) ? 4 : 3)
+void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
   __shared__ AccT cred[4 * 64 * 8];
   __shared__ AccT cxs[kSegRows];
   for (int64_t it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
     if (it != t0 + blockIdx.x) __syncthreads();
-    col_tile_any<AccT, KIND>(ca, it, cred, cxs);
+    col_tile_any<AccT, KIND, DT>(ca, it, cred, cxs);
   }
 }
 
@@ -558,10 +566,17 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
     if (ni > 0)
       hipLaunchKernelGGL((k_col<AccT, kColIeee>), dim3(item_grid(ni, ps, ncu)), dim3(256), 0, s, ca,
                          int64_t(0), ni);
-    if constexpr (DFL)
-      if (nd > 0)
-        hipLaunchKernelGGL((k_col<AccT, kColDfl>), dim3(item_grid(nd, ps, ncu)), dim3(256), 0, s, ca, ni,
-                           ce[kNumDtypes - 1]);
+    if constexpr (DFL && sizeof(AccT) == 8) {
+      if (nd > 0) {                                 // one launch per DFL class
+        auto cls = [&](auto kern, int c) {
+          const int64_t t0 = ce[c - 1], n = ce[c] - t0;
+          if (n > 0) hipLaunchKernelGGL(kern, dim3(item_grid(n, ps, ncu)), dim3(256), 0, s, ca, t0, ce[c]);
+        };
+        cls(k_col<AccT, kColDfl, kDtDfl32>, kDtDfl32);
+        cls(k_col<AccT, kColDfl, kDtDfl40>, kDtDfl40);
+        cls(k_col<AccT, kColDfl, kDtDfl48>, kDtDfl48);
+      }
+    }
     if (nm > 0)
       hipLaunchKernelGGL((k_col<AccT, kColMulti | (DFL ? kColDfl : 0)>), dim3(item_grid(nm, ps, ncu)),
                          dim3(256), 0, s, ca, ce[kNumDtypes - 1], h.n_col_tiles);
