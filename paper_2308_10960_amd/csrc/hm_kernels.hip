@@ -7,9 +7,10 @@
 // Schedule 0:
 //  k_col     far field, phase 1: one workgroup per column tile streams the
 //            rows of V_b restricted to a column chunk, for all low-rank
-//            blocks covering it (lane = group of columns, x broadcast by
-//            readlane), and writes one partial dot product per column (for
-//            a block inside one chunk that sum, times s_b[l], is t_b[l]);
+//            blocks covering it (lane = group of columns, x of the chunk
+//            staged in LDS and read as a broadcast), and writes one partial
+//            dot product per column (for a block inside one chunk that sum,
+//            times s_b[l], is t_b[l]);
 //  k_reduce  t_b[l] = s_b[l] * sum of the block's partials in chunk order,
 //            for the blocks over several chunks;
 //  k_row     near field and far field, phase 2: one workgroup per row panel
@@ -115,17 +116,6 @@ __device__ __forceinline__ void axpy_group(u32x4 r, u32x2 lo, AccT xi, AccT* acc
       acc[2 * c + 1] = fmaT((AccT)__uint_as_float(r[c] & 0xffff0000u), xi, acc[2 * c + 1]);
     }
   }
-}
-
-// Value of lane i of v (i uniform across the wave).
-__device__ __forceinline__ float bcast(float v, int i) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
-}
-__device__ __forceinline__ double bcast(double v, int i) {
-  const unsigned long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffu), i);
-  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), i);
-  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 // ---------------------------------------------------------------- column tiles
