@@ -44,7 +44,7 @@ def kernel_bytes(H, info, vs, R=1, schedule=0):
     m = (H.re - H.rb).astype(np.float64)
     nb = (H.ce - H.cb).astype(np.float64)
     dense = H.adm == 0
-    sz = np.array([8, 4, 2, 2, 4, 5, 6], np.float64)    # bytes per value, by storage format
+    sz = np.array([8, 4, 2, 2, 4, 5, 6, 2, 3], np.float64)    # bytes per value, by storage format
     d_bytes = float((m * nb * sz[H.group_dtype[:, 0]])[dense].sum())
     gcols = H.group_cols.astype(np.float64)
     gbytes = (gcols * sz[H.group_dtype]).sum(1)          # bytes per row of U / V
@@ -239,11 +239,13 @@ def main():
     H = hmgen.build_preset(args.workload, n=args.n or None)
     st = H.stats()
     log("built in %.1fs: %s" % (H.build_seconds, st))
-    mixed = p["dtype"] not in ("f64", "dfl")        # DFL storage accumulates in FP64
+    mixed = p["dtype"] not in ("f64", "dfl", "aplr")   # DFL storage accumulates in FP64
     acc = hm.HM_F32 if mixed else hm.HM_F64
     storage = p["dtype"]
     if storage == "dfl":
         storage = hmgen.hmatrix.DT_NAMES[hmgen.dfl_format(p["eps"])]
+    elif storage == "aplr":
+        storage = "aplr-dfl"
     vs = 4 if mixed else 8
     stream = torch.cuda.Stream()
     cache = None if args.no_tune_cache or not os.path.exists(args.tune_cache) else args.tune_cache

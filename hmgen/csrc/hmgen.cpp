@@ -423,18 +423,39 @@ double round_fmt(double x, int p, int emin, double fmax) {
   return y;
 }
 
-enum Dt : int32_t { DT_F64 = 0, DT_F32 = 1, DT_F16 = 2, DT_BF16 = 3 };
+enum Dt : int32_t {
+  DT_F64 = 0, DT_F32 = 1, DT_F16 = 2, DT_BF16 = 3,
+  DT_DFL32 = 4, DT_DFL40 = 5, DT_DFL48 = 6, DT_DFL16 = 7, DT_DFL24 = 8
+};
+
+// Bytes of a DFL format (Sec. 3.2: FP64's sign and exponent, the mantissa
+// cut to whole bytes), 0 for the others.
+int dfl_nbytes(int dt) {
+  switch (dt) {
+    case DT_DFL16: return 2;
+    case DT_DFL24: return 3;
+    case DT_DFL32: return 4;
+    case DT_DFL40: return 5;
+    case DT_DFL48: return 6;
+    default: return 0;
+  }
+}
 
 double rnd(double x, int dt) {
   switch (dt) {
     case DT_F32: return round_fmt(x, 24, -126, 3.4028234663852886e38);
     case DT_F16: return round_fmt(x, 11, -14, 65504.0);
     case DT_BF16: return round_fmt(x, 8, -126, 3.3895313892515355e38);
-    default: return x;
+    default:
+      if (int nb = dfl_nbytes(dt)) return round_fmt(x, 8 * nb - 11, -1022, 1.7976931348623157e308);
+      return x;
   }
 }
 
-int dt_bytes(int dt) { return dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : 2; }
+int dt_bytes(int dt) {
+  if (int nb = dfl_nbytes(dt)) return nb;
+  return dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : 2;
+}
 
 }  // namespace
 
@@ -684,6 +705,113 @@ int hmg_select_precision(const hmg_tree* t, double tol, int32_t allow_f64, int32
         if (ng == 4) { bad.fetch_add(1); break; }
         gd[ng] = fmt[c]; gc[ng] = 0; ++ng;
       }
+      gc[ng - 1] += 1;
+    }
+    ngroups[bi] = ng;
+    if (err_bound) err_bound[bi] = total;
+  }
+  return bad.load();
+}
+
+// Adaptive per-column precision (APLR, Sec. 3.3) over the DFL formats, for
+// FP64 accumulation with s_b kept in FP64.  Every block is held to
+// ||M_b - M^_b||_F <= tol ||M_b||_F.  Dense blocks take the narrowest DFL
+// format whose exact error meets it, else FP64.  Low-rank blocks: columns go
+// from the smallest singular value up, each to the narrowest format (DFL16,
+// DFL24, DFL32, DFL40, DFL48, FP64) that is at least as wide as the next
+// column's and whose exact error (as in hmg_select_precision, with s exact)
+// fits what is left of the budget; formats then rise towards the large
+// singular values, and the narrowest groups are widened until at most 4
+// remain.  err_bound: the sum of the exact column errors (a bound by the
+// triangle inequality).
+int hmg_select_precision_dfl(const hmg_tree* t, double tol, int32_t* ngroups, int32_t* group_cols,
+                             int32_t* group_dtype, double* err_bound) {
+  static const int kWidth[6] = {DT_DFL16, DT_DFL24, DT_DFL32, DT_DFL40, DT_DFL48, DT_F64};
+  const int64_t nb = (int64_t)t->blocks.size();
+  std::atomic<int> bad{0};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t bi = 0; bi < nb; ++bi) {
+    const Block& b = t->blocks[bi];
+    const int64_t m = b.re - b.rb, n = b.ce - b.cb;
+    int32_t* gc = &group_cols[4 * bi];
+    int32_t* gd = &group_dtype[4 * bi];
+    for (int q = 0; q < 4; ++q) { gc[q] = 0; gd[q] = 0; }
+    if (!b.adm) {
+      double nrm2 = 0;
+      for (double v : b.a) nrm2 += v * v;
+      const double budget = tol * std::sqrt(nrm2);
+      int chosen = DT_F64;
+      double chosen_err = 0;
+      for (int w = 0; w < 5; ++w) {
+        double e2 = 0;
+        for (double v : b.a) { const double r = rnd(v, kWidth[w]); e2 += (v - r) * (v - r); }
+        if (std::sqrt(e2) <= budget) { chosen = kWidth[w]; chosen_err = std::sqrt(e2); break; }
+      }
+      ngroups[bi] = 1; gc[0] = 0; gd[0] = chosen;
+      if (err_bound) err_bound[bi] = chosen_err;
+      continue;
+    }
+    const int k = b.rank;
+    if (k == 0) { ngroups[bi] = 1; gc[0] = 0; gd[0] = DT_DFL16; if (err_bound) err_bound[bi] = 0; continue; }
+    if (b.s.empty()) { bad.fetch_add(1); ngroups[bi] = 0; continue; }
+    double nrm2 = 0;
+    for (double s : b.s) nrm2 += s * s;
+    const double budget = tol * std::sqrt(nrm2);
+    // exact Frobenius error of column c's term s w x^T with w and x rounded
+    // to format dt and s exact: |a x^T + s w^ d^T|, a = s (w - w^), d = x - x^
+    auto col_err = [&](int c, int dt) {
+      const double* w = &b.a[(size_t)c * m];
+      const double* x = &b.b[(size_t)c * n];
+      const double s = b.s[c];
+      double aa = 0, xx = 0, wh2 = 0, dd = 0, aw = 0, xd = 0;
+      for (int64_t i = 0; i < m; ++i) {
+        const double wh = rnd(w[i], dt), a = s * (w[i] - wh);
+        aa += a * a; wh2 += wh * wh; aw += a * wh;
+      }
+      for (int64_t i = 0; i < n; ++i) {
+        const double xh = rnd(x[i], dt), d = x[i] - xh;
+        xx += x[i] * x[i]; dd += d * d; xd += x[i] * d;
+      }
+      const double e2 = aa * xx + s * s * wh2 * dd + 2.0 * s * aw * xd;
+      return std::sqrt(std::max(e2, 0.0));
+    };
+    std::vector<int> wi(k, 5);                      // width index per column
+    std::vector<double> err(k, 0.0);
+    double room = budget;
+    int lo = 0;                                     // narrowest width allowed (the next column's)
+    for (int c = k - 1; c >= 0; --c) {
+      int w = lo;
+      for (; w < 5; ++w) {
+        const double e = col_err(c, kWidth[w]);
+        if (e <= room) { err[c] = e; room -= e; break; }
+      }
+      wi[c] = w;                                    // w == 5: FP64, no error
+      lo = w;
+    }
+    // at most 4 groups: widen the narrowest groups (less error, still in budget)
+    for (;;) {
+      int distinct = 0, narrowest = 6;
+      for (int w = 0; w < 6; ++w) {
+        bool any = false;
+        for (int c = 0; c < k; ++c) any = any || wi[c] == w;
+        if (any) { ++distinct; narrowest = std::min(narrowest, w); }
+      }
+      if (distinct <= 4) break;
+      int next = narrowest + 1;
+      for (;; ++next) {
+        bool any = false;
+        for (int c = 0; c < k; ++c) any = any || wi[c] == next;
+        if (any) break;
+      }
+      for (int c = 0; c < k; ++c)
+        if (wi[c] == narrowest) { wi[c] = next; err[c] = next == 5 ? 0.0 : col_err(c, kWidth[next]); }
+    }
+    double total = 0;
+    for (int c = 0; c < k; ++c) total += err[c];
+    int ng = 0;
+    for (int c = 0; c < k; ++c) {
+      const int dt = kWidth[wi[c]];
+      if (ng == 0 || gd[ng - 1] != dt) { gd[ng] = dt; gc[ng] = 0; ++ng; }
       gc[ng - 1] += 1;
     }
     ngroups[bi] = ng;

@@ -17,10 +17,11 @@ import numpy as np
 from .geometry import mean_nn_distance
 
 DT_F64, DT_F32, DT_F16, DT_BF16 = 0, 1, 2, 3
-DT_DFL32, DT_DFL40, DT_DFL48 = 4, 5, 6
-DT_BYTES = {DT_F64: 8, DT_F32: 4, DT_F16: 2, DT_BF16: 2, DT_DFL32: 4, DT_DFL40: 5, DT_DFL48: 6}
+DT_DFL32, DT_DFL40, DT_DFL48, DT_DFL16, DT_DFL24 = 4, 5, 6, 7, 8
+DT_BYTES = {DT_F64: 8, DT_F32: 4, DT_F16: 2, DT_BF16: 2, DT_DFL32: 4, DT_DFL40: 5, DT_DFL48: 6,
+            DT_DFL16: 2, DT_DFL24: 3}
 DT_NAMES = {DT_F64: "f64", DT_F32: "f32", DT_F16: "f16", DT_BF16: "bf16",
-            DT_DFL32: "dfl32", DT_DFL40: "dfl40", DT_DFL48: "dfl48"}
+            DT_DFL32: "dfl32", DT_DFL40: "dfl40", DT_DFL48: "dfl48", DT_DFL16: "dfl16", DT_DFL24: "dfl24"}
 
 
 def dfl_mantissa_bits(eps: float) -> int:
@@ -81,6 +82,8 @@ def lib():
     L.hmg_eval.argtypes = [vp, _i64p, _i64p, C.c_int64, _f64p]
     L.hmg_select_precision.argtypes = [vp, C.c_double, C.c_int32, _i32p, _i32p, _i32p, _f64p]
     L.hmg_select_precision.restype = C.c_int
+    L.hmg_select_precision_dfl.argtypes = [vp, C.c_double, _i32p, _i32p, _i32p, _f64p]
+    L.hmg_select_precision_dfl.restype = C.c_int
     L.hmg_round.argtypes = [_f64p, C.c_int64, C.c_int32, _f64p]
     L.hmg_truncate.argtypes = [_f64p, _f64p, C.c_int64, C.c_int64, C.c_int32, C.c_double,
                                _f64p, _f64p, _f64p]
@@ -177,6 +180,21 @@ class HMatrix:
         self.store_err_bound = np.zeros(nb)
         bad = lib().hmg_select_precision(
             C.c_void_p(self.handle), tol, int(allow_f64), self.ngroups,
+            self.group_cols.reshape(-1), self.group_dtype.reshape(-1), self.store_err_bound)
+        return int(bad)
+
+    def select_precision_dfl(self, tol: float) -> int:
+        """Per-column DFL formats (APLR over DFL16 ... DFL48, FP64), s kept
+        in FP64 (see hmg_select_precision_dfl)."""
+        if not self.keep_sigma:
+            raise ValueError("precision selection needs keep_sigma=True")
+        nb = self.nblocks
+        self.ngroups = np.zeros(nb, np.int32)
+        self.group_cols = np.zeros((nb, 4), np.int32)
+        self.group_dtype = np.zeros((nb, 4), np.int32)
+        self.store_err_bound = np.zeros(nb)
+        bad = lib().hmg_select_precision_dfl(
+            C.c_void_p(self.handle), tol, self.ngroups,
             self.group_cols.reshape(-1), self.group_dtype.reshape(-1), self.store_err_bound)
         return int(bad)
 

@@ -35,6 +35,11 @@ PRESETS = {
     "sphere256k_dfl": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-6, dtype="dfl"),
     "sphere256k_e8_dfl": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-8, dtype="dfl"),
     "sphere4k_dfl": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-6, dtype="dfl"),
+    # adaptive per-column precision over the DFL formats (APLR, Sec. 3.3),
+    # FP64 accumulation, every block within eps / 2 of its own norm
+    "sphere256k_aplr": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-6, dtype="aplr"),
+    "sphere256k_e8_aplr": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-8, dtype="aplr"),
+    "sphere4k_aplr": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-8, dtype="aplr"),
 }
 
 SEED_POINTS, SEED_X, SEED_RHS, SEED_REQUESTS = 0, 1, 2, 3
@@ -64,10 +69,12 @@ def build_preset(name: str, *, n: int | None = None, eps: float | None = None,
     pts = make_points(p["geometry"], n)
     kern = KERNEL_LAPLACE if p["kernel"] == "laplace" else KERNEL_EXP
     mixed = dtype == "mixed"
-    H = build_hmatrix(pts, kern, leaf=leaf, eta=eta, eps=eps, keep_sigma=mixed,
+    H = build_hmatrix(pts, kern, leaf=leaf, eta=eta, eps=eps, keep_sigma=mixed or dtype == "aplr",
                       nthreads=nthreads)
     if mixed:
         H.select_precision(MIXED_TOL / 2)
+    elif dtype == "aplr":
+        H.select_precision_dfl(eps / 2)
     elif dtype == "dfl":
         H.set_uniform_dtype(dfl_format(eps))
     else:

@@ -53,16 +53,16 @@ typedef int32_t hm_status;
 #define HM_ETIMEOUT (-9)    /* hm_wait timed out */
 
 /* Storage formats.  F64, F32, F16, BF16: the IEEE-754 binary formats of
- * Table 1.  DFL32, DFL40, DFL48: the byte-aligned truncated formats with the
- * 11 exponent bits of FP64 (DFL, Sec. 3.2): the leading 4, 5 or 6 bytes of
- * the FP64 encoding (sign, exponent, 20 / 28 / 36 mantissa bits), rounded to
- * nearest even from FP64; they decode exactly to FP64.  The number of
- * formats is HM_NUM_DTYPES. */
+ * Table 1.  DFL16 ... DFL48: the byte-aligned truncated formats with the 11
+ * exponent bits of FP64 (DFL, Sec. 3.2): the leading 2, 3, 4, 5 or 6 bytes
+ * of the FP64 encoding (sign, exponent, 4 / 12 / 20 / 28 / 36 mantissa
+ * bits), rounded to nearest even from FP64; they decode exactly to FP64.
+ * The number of formats is HM_NUM_DTYPES. */
 typedef enum {
   HM_F64 = 0, HM_F32 = 1, HM_F16 = 2, HM_BF16 = 3,
-  HM_DFL32 = 4, HM_DFL40 = 5, HM_DFL48 = 6
+  HM_DFL32 = 4, HM_DFL40 = 5, HM_DFL48 = 6, HM_DFL16 = 7, HM_DFL24 = 8
 } hm_dtype;
-#define HM_NUM_DTYPES 7
+#define HM_NUM_DTYPES 9
 typedef enum { HM_DENSE = 0, HM_LOWRANK = 1 } hm_kind;
 
 /* One leaf block b = tau x sigma of the block tree (Sec. 2.1).
@@ -83,9 +83,7 @@ typedef struct {
 /* acc_dtype: HM_F64 or HM_F32, the accumulation type of every sum.
  * vec_dtype: must equal acc_dtype (x, y, X, Y are stored in it).
  * Storage dtypes allowed: any with HM_F64 accumulation; F32/F16/BF16 with
- * HM_F32 accumulation.  A plan whose low-rank groups use DFL40 or DFL48
- * stores every low-rank group in that one format (dense blocks may use any
- * allowed format); otherwise hm_build_plan fails with HM_EDTYPE.
+ * HM_F32 accumulation (DFL formats need HM_F64 accumulation).
  * max_nrhs: largest nrhs passed to hm_mvm_batch (>= 1); sizes the workspace.
  * tune: 0 = built-in launch parameters; 1 = read tune_cache, a text file
  * written by the tuner with one "key params" line per kind of matrix (see
@@ -136,10 +134,11 @@ void hm_plan_destroy(hm_plan* p);
 /* Where entry (i, j) of a block's first factor (which = 0: D_b or U_b / W_b,
  * j < n_b resp. k) or second factor (which = 1: V_b / X_b, i < n_b, j < k)
  * lives in the store: byte offset and storage dtype.  For DFL formats the
- * offset is that of the value's leading 4 bytes (a little-endian 32-bit
- * word); for DFL40 / DFL48 its remaining 1 / 2 bytes (bits 31..24 / 31..16
- * of the FP64 encoding) are at lo_offset, else lo_offset = 0.  lo_offset
- * may be NULL.  For tests of the packing and conversion done by hm_upload. */
+ * offset is that of the value's leading 4 bytes (DFL32 / 40 / 48: a
+ * little-endian 32-bit word) or 2 bytes (DFL16 / 24: a 16-bit word); for
+ * DFL40 / DFL48 / DFL24 its remaining 1 / 2 / 1 bytes (bits 31..24 /
+ * 31..16 / 47..40 of the FP64 encoding) are at lo_offset, else lo_offset =
+ * 0.  lo_offset may be NULL.  For tests of the packing and conversion done by hm_upload. */
 hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t i, int64_t j,
                          size_t* byte_offset, int32_t* dtype, size_t* lo_offset);
 

@@ -28,8 +28,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
-DFL32, DFL40, DFL48 = 4, 5, 6
-DFL_BYTES = {DFL32: 4, DFL40: 5, DFL48: 6}
+DFL32, DFL40, DFL48, DFL16, DFL24 = 4, 5, 6, 7, 8
+DFL_BYTES = {DFL32: 4, DFL40: 5, DFL48: 6, DFL16: 2, DFL24: 3}
 
 # Table 1: unit roundoff u = 2^-(m+1) for m explicit mantissa bits.
 UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "tf32": 2.0 ** -11,

@@ -100,14 +100,21 @@ static uint64_t dfl_bits(double v, int nbytes) {
   return kept << drop;
 }
 
-// A DFL value: its leading 4 bytes (the high word of the encoding) at hi;
-// for DFL40 / DFL48 bits 31..24 / 31..16 at lo.
+// A DFL value: its leading 4 bytes (DFL32 / 40 / 48: the high word of the
+// encoding) or 2 bytes (DFL16 / 24) at hi; for DFL40 / DFL48 / DFL24 bits
+// 31..24 / 31..16 / 47..40 at lo.
 static inline void put_dfl(uint8_t* hi, uint8_t* lo, int dt, double v) {
   const uint64_t r = dfl_bits(v, value_bytes(dt));
-  const uint32_t w = (uint32_t)(r >> 32);
-  std::memcpy(hi, &w, 4);
+  if (dtype_size(dt) == 4) {
+    const uint32_t w = (uint32_t)(r >> 32);
+    std::memcpy(hi, &w, 4);
+  } else {
+    const uint16_t w = (uint16_t)(r >> 48);
+    std::memcpy(hi, &w, 2);
+  }
   if (dt == kDtDfl40) { const uint8_t q = (uint8_t)(r >> 24); std::memcpy(lo, &q, 1); }
   if (dt == kDtDfl48) { const uint16_t q = (uint16_t)(r >> 16); std::memcpy(lo, &q, 2); }
+  if (dt == kDtDfl24) { const uint8_t q = (uint8_t)(r >> 40); std::memcpy(lo, &q, 1); }
 }
 
 static inline void put(uint8_t* dst, int dt, double v) {
@@ -183,26 +190,57 @@ static void split_intervals(const std::vector<int64_t>& bp, int cap, std::vector
 // The panel's groups (run by run) are stored tile by tile (tiles of 64
 // groups, the last one narrower); inside a tile, row i holds the tile's
 // groups contiguously, so a tile row is one contiguous block.
-// Low-byte plane bytes per group element of a column panel: a panel with a
-// DFL40 / DFL48 run holds only that run (plans store every low-rank group in
-// such a format, if any group uses it).
-static int panel_lo(const ColPanelHost& Cp) { return Cp.secs.empty() ? 0 : lo_bytes(Cp.secs.front().dtype); }
+// Cuts a column panel's group sequence (its runs, in order) into tiles of
+// at most kTileGroups groups and at most 4 runs (the tile descriptor's
+// limit).  A tile's low-byte plane has one entry of tile_lo[t] bytes (the
+// largest lo_bytes of its runs; 0: none) per row and group; groups of a
+// format without one leave theirs unused.  Fills tile_g0 / tile_off /
+// tile_lo.
+static void cut_tiles(ColPanelHost& Cp) {
+  Cp.tile_g0.assign(1, 0);
+  Cp.tile_off.assign(1, 0);
+  Cp.tile_lo.clear();
+  int32_t open = 0, runs = 0, L = 0;                // the open tile: groups, runs, entry bytes
+  auto close = [&]() {
+    Cp.tile_g0.push_back(Cp.tile_g0.back() + open);
+    Cp.tile_off.push_back(Cp.tile_off.back() + (int64_t)open * Cp.nrows * (16 + L));
+    Cp.tile_lo.push_back(L);
+    open = runs = L = 0;
+  };
+  for (auto& S : Cp.secs) {
+    const int32_t n = S.ld / group_width(S.dtype);
+    for (int32_t g = 0; g < n;) {
+      if (runs == 4) close();
+      const int32_t take = std::min(kTileGroups - open, n - g);
+      open += take;
+      g += take;
+      ++runs;
+      L = std::max(L, lo_bytes(S.dtype));
+      if (open == kTileGroups) close();
+    }
+  }
+  if (open > 0) close();
+}
+
+// Tile of group g of column panel Cp.
+static int64_t tile_of(const ColPanelHost& Cp, int64_t g) {
+  return std::upper_bound(Cp.tile_g0.begin(), Cp.tile_g0.end(), (int32_t)g) - Cp.tile_g0.begin() - 1;
+}
 
 static int64_t col_elem_offset(const ColPanelHost& Cp, const ColSectionHost& S, int64_t i, int64_t sc) {
   const int G = group_width(S.dtype), sz = dtype_size(S.dtype);
-  const int64_t g = S.g0 + sc / G, t = g / kTileGroups, gl = g % kTileGroups;
-  const int64_t ngt = std::min<int64_t>(kTileGroups, Cp.ngroups - t * kTileGroups);
-  return Cp.data_off + t * kTileGroups * (16 + panel_lo(Cp)) * (int64_t)Cp.nrows + (i * ngt + gl) * 16 +
-         (sc % G) * sz;
+  const int64_t g = S.g0 + sc / G, t = tile_of(Cp, g), gl = g - Cp.tile_g0[t];
+  const int64_t ngt = Cp.tile_g0[t + 1] - Cp.tile_g0[t];
+  return Cp.data_off + Cp.tile_off[t] + (i * ngt + gl) * 16 + (sc % G) * sz;
 }
 
 // Byte offset of the low-byte part of that element (formats with lo_bytes > 0).
 static int64_t col_lo_offset(const ColPanelHost& Cp, const ColSectionHost& S, int64_t i, int64_t sc) {
   const int G = group_width(S.dtype), L = lo_bytes(S.dtype);
-  const int64_t g = S.g0 + sc / G, t = g / kTileGroups, gl = g % kTileGroups;
-  const int64_t ngt = std::min<int64_t>(kTileGroups, Cp.ngroups - t * kTileGroups);
-  return Cp.data_off + t * kTileGroups * (16 + L) * (int64_t)Cp.nrows + 16 * ngt * (int64_t)Cp.nrows +
-         (i * ngt + gl) * L + (sc % G) * (L / 4);
+  const int64_t g = S.g0 + sc / G, t = tile_of(Cp, g), gl = g - Cp.tile_g0[t];
+  const int64_t ngt = Cp.tile_g0[t + 1] - Cp.tile_g0[t];
+  return Cp.data_off + Cp.tile_off[t] + 16 * ngt * (int64_t)Cp.nrows + (i * ngt + gl) * Cp.tile_lo[t] +
+         (sc % G) * (L / G);
 }
 
 hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks, int64_t nb,
@@ -230,24 +268,6 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
   for (int64_t i = 0; i < nb; ++i) {
     hm_status st = validate_block(P->blocks[i], i, n_rows, n_cols, acc);
     if (st) return st;
-  }
-  {
-    // a format with a low-byte plane in the column tiles must be the format
-    // of every low-rank group (its tiles then never hold other formats)
-    int lo_fmt = -1;
-    for (auto& b : P->blocks)
-      if (b.kind == HM_LOWRANK)
-        for (int g = 0; g < b.ngroups; ++g)
-          if (b.group_cols[g] > 0 && lo_bytes(b.group_dtype[g]) > 0) lo_fmt = b.group_dtype[g];
-    if (lo_fmt >= 0)
-      for (int64_t i = 0; i < nb; ++i) {
-        const auto& b = P->blocks[i];
-        if (b.kind == HM_LOWRANK)
-          for (int g = 0; g < b.ngroups; ++g)
-            if (b.group_cols[g] > 0 && b.group_dtype[g] != lo_fmt)
-              return fail(HM_EDTYPE, "block %lld: low-rank groups in format %d and %d (DFL40 / DFL48 "
-                          "must be the format of every low-rank group)", (long long)i, b.group_dtype[g], lo_fmt);
-      }
   }
 
   // ---- elementary row intervals and the tiling proof
@@ -519,6 +539,7 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
       Cp.ncols += S.ld;
       Cp.secs.push_back(S);
     }
+    cut_tiles(Cp);
   }
 
   hm_status st = layout_store(P.release(), out);
@@ -608,7 +629,7 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   H.n_row_sections = nsec;
   int64_t ntiles = 0, ndst = 0;
   for (auto& Cp : P->cps) {
-    ntiles += (Cp.ngroups + kTileGroups - 1) / kTileGroups;
+    ntiles += (int64_t)Cp.tile_lo.size();
     ndst += Cp.ncols;
   }
   H.n_col_tiles = ntiles;
@@ -616,8 +637,8 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
     // tiles per class (one format, or several: runs of a panel that meet in a tile)
     int64_t cnt[kNumDtypes + 1] = {};
     for (auto& Cp : P->cps)
-      for (int32_t g0 = 0; g0 < Cp.ngroups; g0 += kTileGroups) {
-        const int32_t g1 = std::min(Cp.ngroups, g0 + kTileGroups);
+      for (size_t t = 0; t < Cp.tile_lo.size(); ++t) {
+        const int32_t g0 = Cp.tile_g0[t], g1 = Cp.tile_g0[t + 1];
         int runs = 0, fmt = 0;
         for (auto& S : Cp.secs) {
           const int32_t a = S.g0, b = S.g0 + S.ld / group_width(S.dtype);
@@ -674,7 +695,7 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
     }
   }
   for (auto& Cp : P->cps) {
-    Cp.data_off = take((int64_t)Cp.ngroups * (16 + panel_lo(Cp)) * Cp.nrows);
+    Cp.data_off = take(Cp.tile_off.back());
     for (auto& S : Cp.secs) {
       const int64_t bytes = (int64_t)S.ld * Cp.nrows * value_bytes(S.dtype);
       int64_t real = 0;
@@ -830,10 +851,10 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
       for (int32_t c = 0; c < sg.ncols; ++c)
         dst[S->c0 + sg.seccol + c] = sg.direct ? dst_direct(sg.src0 + c) : sg.src0 + c;
     }
-    for (int32_t g0 = 0; g0 < Cp.ngroups; g0 += kTileGroups) {
+    for (size_t ti = 0; ti < Cp.tile_lo.size(); ++ti) {
       ColTile& T = ct[tile++];
-      const int32_t ngt = std::min(kTileGroups, Cp.ngroups - g0);
-      T.data_off = Cp.data_off + (int64_t)g0 * (16 + panel_lo(Cp)) * Cp.nrows;   // tiles one after another
+      const int32_t g0 = Cp.tile_g0[ti], ngt = Cp.tile_g0[ti + 1] - g0;
+      T.data_off = Cp.data_off + Cp.tile_off[ti];   // tiles one after another
       T.nrows = Cp.nrows;
       T.x0 = (int32_t)Cp.x0;
       T.ngroups = ngt;
@@ -843,6 +864,7 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
         const int32_t G = group_width(S.dtype);
         const int32_t lo = std::max(S.g0, g0), hi = std::min(S.g0 + S.ld / G, g0 + ngt);
         if (hi <= lo) continue;
+        if (nr == 4) return fail(HM_EINVAL, "internal error: column tile with more than 4 runs");
         if (first_col < 0) first_col = S.c0 + (lo - S.g0) * G;
         T.dtype[nr] = (uint8_t)S.dtype;
         T.end[nr] = (uint8_t)(hi - g0);
@@ -912,7 +934,7 @@ void pack_job_range(const hm_plan* P, size_t j, int64_t* lo, int64_t* hi) {
       *lo = *hi = -1;
     } else {
       *lo = Cp.data_off;
-      *hi = align_up(Cp.data_off + (int64_t)Cp.ngroups * (16 + panel_lo(Cp)) * Cp.nrows, kAlign);
+      *hi = align_up(Cp.data_off + Cp.tile_off.back(), kAlign);
     }
   }
 }
@@ -948,7 +970,7 @@ void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf
             for (int32_t i = 0; i < R.m; ++i) {
               uint8_t* hi = base + (((int64_t)g * R.m + i) * G + cc) * sz;
               if (is_dfl(S->dtype))
-                put_dfl(hi, lo_base + ((int64_t)g * R.m + i) * L + cc * (L / 4), S->dtype, col[i]);
+                put_dfl(hi, lo_base + ((int64_t)g * R.m + i) * L + cc * (L / G), S->dtype, col[i]);
               else
                 put(hi, S->dtype, col[i]);
             }
@@ -1057,7 +1079,7 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
             const int64_t e = (sc / G) * R.m + (row - R.row0);      // group element
             *byte_offset = (size_t)(S.data_off + (e * G + sc % G) * dtype_size(S.dtype));
             if (lo_offset && L)
-              *lo_offset = (size_t)(S.data_off + (int64_t)16 * S.ngroups * R.m + e * L + (sc % G) * (L / 4));
+              *lo_offset = (size_t)(S.data_off + (int64_t)16 * S.ngroups * R.m + e * L + (sc % G) * (L / G));
             *dtype = S.dtype;
             return ok();
           }

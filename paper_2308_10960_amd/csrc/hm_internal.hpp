@@ -62,6 +62,10 @@ struct RowPanelHost {
 // columns (a multiple of the group width) of one format, from group g0 and
 // from column c0 of the panel's column order.
 struct ColSectionHost { int32_t dtype = 0, ld = 0, g0 = 0, c0 = 0; };
+// Its groups are cut into tiles of at most kTileGroups groups; a run of a
+// format with a low-byte plane gets tiles of its own (tile t: groups
+// [tile_g0[t], tile_g0[t+1]), bytes from data_off + tile_off[t], low-byte
+// plane entry size tile_lo[t]).
 struct ColPanelHost {
   int64_t x0 = 0;
   int32_t nrows = 0;
@@ -69,6 +73,9 @@ struct ColPanelHost {
   int64_t data_off = 0;
   std::vector<Seg> segs;
   std::vector<ColSectionHost> secs;  // the runs, by format
+  std::vector<int32_t> tile_g0;      // n_tiles + 1 entries
+  std::vector<int64_t> tile_off;     // n_tiles + 1 entries (the last: the panel's bytes)
+  std::vector<int32_t> tile_lo;      // n_tiles entries
 };
 
 }  // namespace hm

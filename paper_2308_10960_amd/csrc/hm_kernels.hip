@@ -36,24 +36,32 @@
 namespace hm {
 namespace {
 
-// Value c of a DFL group element: r[c] is the high word of its FP64
-// encoding; lo is the element's low-byte plane entry (DFL40: byte c holds
-// bits 31..24; DFL48: 16-bit half c holds bits 31..16).  Exact.
+// Value c of a DFL group element, exact.  DFL32 / 40 / 48: r[c] is the
+// high word of its FP64 encoding, and the element's low-byte plane entry lo
+// holds bits 31..24 in byte c (DFL40) or bits 31..16 in 16-bit half c
+// (DFL48).  DFL16 / 24: 16-bit half c of r holds bits 63..48, and byte c of
+// lo bits 47..40 (DFL24); the low word is zero.
 template <int DT>
 __device__ __forceinline__ double dfl_value(u32x4 r, u32x2 lo, int c) {
-  unsigned low = 0;
-  if constexpr (DT == kDtDfl40) low = ((lo[0] >> (8 * c)) & 0xffu) << 24;
-  if constexpr (DT == kDtDfl48) low = ((lo[c >> 1] >> (16 * (c & 1))) & 0xffffu) << 16;
-  return __longlong_as_double((long long)(((unsigned long long)r[c] << 32) | low));
+  unsigned hi, low = 0;
+  if constexpr (DT == kDtDfl16 || DT == kDtDfl24) {
+    hi = ((r[c >> 1] >> (16 * (c & 1))) & 0xffffu) << 16;
+    if constexpr (DT == kDtDfl24) hi |= ((lo[c >> 2] >> (8 * (c & 3))) & 0xffu) << 8;
+  } else {
+    hi = r[c];
+    if constexpr (DT == kDtDfl40) low = ((lo[0] >> (8 * c)) & 0xffu) << 24;
+    if constexpr (DT == kDtDfl48) low = ((lo[c >> 1] >> (16 * (c & 1))) & 0xffffu) << 16;
+  }
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | low));
 }
 
-// The low-byte plane entry idx of a DFL40 / DFL48 region at p (zero for the
-// other formats, which have none).
+// The low-byte plane entry idx of a DFL40 / DFL48 / DFL24 region at p
+// (zero for the other formats, which have none).
 template <int DT>
 __device__ __forceinline__ u32x2 ld_lo(const uint8_t* p, int64_t idx) {
   if constexpr (DT == kDtDfl40) {
     return u32x2{__builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p) + idx), 0u};
-  } else if constexpr (DT == kDtDfl48) {
+  } else if constexpr (DT == kDtDfl48 || DT == kDtDfl24) {
     return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p) + idx);
   } else {
     return (u32x2)(0u);
@@ -66,7 +74,7 @@ template <typename AccT, int DT>
 __device__ __forceinline__ AccT dot_group(u32x4 r, u32x2 lo, const AccT* __restrict__ z, AccT acc) {
   if constexpr (is_dfl(DT)) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc = fmaT((AccT)dfl_value<DT>(r, lo, c), z[c], acc);
+    for (int c = 0; c < group_width(DT); ++c) acc = fmaT((AccT)dfl_value<DT>(r, lo, c), z[c], acc);
   } else if constexpr (DT == HM_F64) {
     const f64x2 v = __builtin_bit_cast(f64x2, r);
     acc = fmaT((AccT)v.x, z[0], acc);
@@ -96,7 +104,7 @@ template <typename AccT, int DT>
 __device__ __forceinline__ void axpy_group(u32x4 r, u32x2 lo, AccT xi, AccT* acc) {
   if constexpr (is_dfl(DT)) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = fmaT((AccT)dfl_value<DT>(r, lo, c), xi, acc[c]);
+    for (int c = 0; c < group_width(DT); ++c) acc[c] = fmaT((AccT)dfl_value<DT>(r, lo, c), xi, acc[c]);
   } else if constexpr (DT == HM_F64) {
     const f64x2 v = __builtin_bit_cast(f64x2, r);
     acc[0] = fmaT((AccT)v.x, xi, acc[0]);
@@ -141,7 +149,7 @@ struct ColArgs {
 // LDS (red: 4 x 64 x 8), and wave 0 writes each column's sum to its
 // destination (a partial, or t).  DT >= 0: every group of the tile has
 // format DT; DT < 0: the tile holds runs of several formats and each lane
-// decodes its own (T.dtype, T.end); DFL: such a tile may hold DFL32 runs.
+// decodes its own (T.dtype, T.end); DFL: such a tile may hold DFL runs.
 template <typename AccT, int DT, bool DFL = false>
 __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, AccT* red, AccT* xs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -154,8 +162,11 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
   const int rstride = T.ngroups;                    // 16-byte groups per tile row
   const int nrows = T.nrows;
   const u32x4* p = reinterpret_cast<const u32x4*>(a.store + T.data_off) + lane;
-  // low-byte plane (DFL40 / DFL48 tiles, which hold that one format)
+  // low-byte plane: entries of lo_bytes(DT) bytes in a one-format tile; of
+  // Lt bytes in a several-format one (read by the lanes whose format has one)
   const uint8_t* lop = a.store + T.data_off + (int64_t)16 * nrows * rstride;
+  const int Lt = DT < 0 && DFL ? tile_lo_bytes(T) : 0;
+  const bool hlo = DT < 0 && DFL && lo_bytes(dt) > 0;
   const int nb = nrows > 8 * wave ? (nrows - 8 * wave + 31) / 32 : 0;   // this wave's batches
   u32x4 rn[8];
   u32x2 ln[8];
@@ -165,7 +176,14 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
     for (int u = 0; u < 8; ++u)
       if (act && r0 + u < nrows) {
         rn[u] = ld16(p + (size_t)(r0 + u) * rstride);
-        ln[u] = ld_lo<DT>(lop, (int64_t)(r0 + u) * rstride + lane);
+        if constexpr (DT >= 0) {
+          ln[u] = ld_lo<DT>(lop, (int64_t)(r0 + u) * rstride + lane);
+        } else if constexpr (DFL) {
+          if (hlo) {
+            const int64_t e = (int64_t)(r0 + u) * rstride + lane;
+            ln[u] = Lt == 8 ? ld_lo<kDtDfl48>(lop, e) : ld_lo<kDtDfl40>(lop, e);
+          }
+        }
       }
   };
   if (nb > 0) issue(0);
@@ -195,9 +213,12 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
           } else if (dt == HM_BF16) {
             axpy_group<AccT, HM_BF16>(rc[u], lc[u], xi, acc);
           } else if constexpr (sizeof(AccT) == 8) {
-            // FP64-accumulation formats; a several-format tile never holds
-            // a format with a low-byte plane
+            // FP64-accumulation formats
             if (DFL && dt == kDtDfl32) axpy_group<AccT, kDtDfl32>(rc[u], lc[u], xi, acc);
+            else if (DFL && dt == kDtDfl16) axpy_group<AccT, kDtDfl16>(rc[u], lc[u], xi, acc);
+            else if (DFL && dt == kDtDfl24) axpy_group<AccT, kDtDfl24>(rc[u], lc[u], xi, acc);
+            else if (DFL && dt == kDtDfl40) axpy_group<AccT, kDtDfl40>(rc[u], lc[u], xi, acc);
+            else if (DFL && dt == kDtDfl48) axpy_group<AccT, kDtDfl48>(rc[u], lc[u], xi, acc);
             else axpy_group<AccT, HM_F64>(rc[u], lc[u], xi, acc);
           }
         }
@@ -232,7 +253,7 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
 // class, so that the FP64 / IEEE paths carry no code of the DFL formats).
 constexpr int kColIeee = 1;     // one-format tiles of FP64, FP32, FP16, BF16
 constexpr int kColMulti = 2;    // several-format tiles
-constexpr int kColDfl = 4;      // one-format DFL tiles, and DFL32 runs in several-format tiles
+constexpr int kColDfl = 4;      // one-format DFL tiles, and DFL runs in several-format tiles
 
 // A whole workgroup on tile ti (it synchronizes).  red: 4 * 64 * 8 values
 // (four waves x 64 lanes x at most 8 columns per lane); xs: kSegRows
@@ -257,6 +278,8 @@ __device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti,
       case kDtDfl32: col_tile<AccT, kDtDfl32>(a, T, red, xs); return;
       case kDtDfl40: col_tile<AccT, kDtDfl40>(a, T, red, xs); return;
       case kDtDfl48: col_tile<AccT, kDtDfl48>(a, T, red, xs); return;
+      case kDtDfl16: col_tile<AccT, kDtDfl16>(a, T, red, xs); return;
+      case kDtDfl24: col_tile<AccT, kDtDfl24>(a, T, red, xs); return;
       default: break;
     }
   }
@@ -413,6 +436,12 @@ __device__ __forceinline__ void row_panel_part(const RowArgs<AccT>& a, const Row
                 case kDtDfl40:
                   acc = row_section<AccT, kDtDfl40, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
                   break;
+                case kDtDfl16:
+                  acc = row_section<AccT, kDtDfl16, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
+                  break;
+                case kDtDfl24:
+                  acc = row_section<AccT, kDtDfl24, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
+                  break;
                 default:
                   acc = row_section<AccT, kDtDfl48, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
                   break;
@@ -475,9 +504,9 @@ __global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* ord
 // panels (dense and U sections in one pass).
 // Tiles [t0, t1) of the classes KIND decodes (DT >= 0: the one-format
 // class DT).  Four workgroups per CU, three where the registers need it
-// (several-format tiles; DFL40 / DFL48 with their low-byte loads).
+// (several-format tiles; the DFL formats with low-byte loads).
 template <typename AccT, int KIND, int DT = -1>
-__global__ __launch_bounds__(256, (KIND == kColIeee || DT == kDtDfl32) ? 4 : 3)
+__global__ __launch_bounds__(256, (KIND == kColIeee || DT == kDtDfl32 || DT == kDtDfl16) ? 4 : 3)
 void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
   __shared__ AccT cred[4 * 64 * 8];
   __shared__ AccT cxs[kSegRows];
@@ -550,7 +579,7 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
                          ca, reinterpret_cast<const int32_t*>(st + h.off_p1_order), h.n_p1);
   } else {
     // classes: one-format IEEE tiles [0, ce[3]), one-format DFL tiles
-    // [ce[3], ce[6]), several-format tiles [ce[6], ce[7])
+    // [ce[3], ce[8]), several-format tiles [ce[8], ce[9])
     const int64_t* ce = h.tile_class_end;
     const int64_t ni = ce[HM_BF16], nd = ce[kNumDtypes - 1] - ni, nm = h.n_col_tiles - ce[kNumDtypes - 1];
     if (ni > 0)
@@ -565,6 +594,8 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
         cls(k_col<AccT, kColDfl, kDtDfl32>, kDtDfl32);
         cls(k_col<AccT, kColDfl, kDtDfl40>, kDtDfl40);
         cls(k_col<AccT, kColDfl, kDtDfl48>, kDtDfl48);
+        cls(k_col<AccT, kColDfl, kDtDfl16>, kDtDfl16);
+        cls(k_col<AccT, kColDfl, kDtDfl24>, kDtDfl24);
       }
     }
     if (nm > 0)
@@ -601,7 +632,7 @@ hipError_t launch_typed(const hm_matrix& A, double alpha, const void* x, void* y
                         hipStream_t s, hipEvent_t* ev) {
   if constexpr (sizeof(AccT) == 8) {
     bool dfl = false;
-    for (int d = kDtDfl32; d <= kDtDfl48; ++d) dfl = dfl || A.bytes_by_dtype[d] > 0;
+    for (int d = 0; d < kNumDtypes; ++d) dfl = dfl || (is_dfl(d) && A.bytes_by_dtype[d] > 0);
     if (dfl)
       return A.launch.row_unroll >= 8 ? launch_typed_u<AccT, 8, true>(A, alpha, x, y, work, s, ev)
                                       : launch_typed_u<AccT, 4, true>(A, alpha, x, y, work, s, ev);

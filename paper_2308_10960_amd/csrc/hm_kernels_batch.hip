@@ -676,7 +676,7 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
         hipLaunchKernelGGL(k_col_b16<HM_F16>, grid(ce[1], ce[2], 8), dim3(64), 0, s, ca, ce[1], ce[2]);
       if (ce[3] > ce[2])
         hipLaunchKernelGGL(k_col_b16<HM_BF16>, grid(ce[2], ce[3], 8), dim3(64), 0, s, ca, ce[2], ce[3]);
-      // (FP64 and DFL tiles, classes 0 and 4..6, do not occur with FP32 accumulation)
+      // (FP64 and DFL tiles, classes 0 and 4..8, do not occur with FP32 accumulation)
       constexpr int M = kNumDtypes;
       if (ce[M] > ce[M - 1])
         hipLaunchKernelGGL(k_col_b16<-1>, grid(ce[M - 1], ce[M], 8), dim3(64), 0, s, ca, ce[M - 1], ce[M]);

@@ -25,11 +25,11 @@
 //    another; inside a tile the rows follow each other, each holding the
 //    tile's groups contiguously, so a wave (lane = group) streams one
 //    contiguous block and accumulates its G columns over the rows:
-//    partial(b, kappa, l) = sum_{i in kappa} V_b[i, l] x[i].  A tile of a
-//    format with a low-byte plane (only ever a one-format tile: such a
-//    format is then the format of every low-rank group) has the plane after
-//    its rows: the low bytes of row i, group g at 16 nrows ngroups +
-//    L (i ngroups + g).
+//    partial(b, kappa, l) = sum_{i in kappa} V_b[i, l] x[i].  A tile with
+//    runs of formats with a low-byte plane has the plane after its rows: the
+//    low bytes of row i, group g at 16 nrows ngroups + L (i ngroups + g),
+//    L = the largest lo_bytes of its runs (entries of groups of the other
+//    formats are unused).
 //  * Reduction.  t_b[l] = s_b[l] * sum over the chunks of sigma_b of the
 //    partials, in ascending chunk order.
 //  * Single-RHS schedule: phase 1 streams the dense sections of the row
@@ -52,22 +52,26 @@ constexpr int kTileGroups = 64;     // column groups per column tile (one per la
 constexpr int kLargeSeg = 16;       // blocks with more intervals reduce per workgroup
 constexpr int kAlign = 256;
 
-// Storage formats (hm_dtype): F64, F32, F16, BF16, DFL32, DFL40, DFL48.
-constexpr int kNumDtypes = 7;
-constexpr int kDtDfl32 = 4, kDtDfl40 = 5, kDtDfl48 = 6;
+// Storage formats (hm_dtype): F64, F32, F16, BF16, DFL32, DFL40, DFL48,
+// DFL16, DFL24.
+constexpr int kNumDtypes = 9;
+constexpr int kDtDfl32 = 4, kDtDfl40 = 5, kDtDfl48 = 6, kDtDfl16 = 7, kDtDfl24 = 8;
 
 // Columns per 16-byte group for a storage dtype.  A DFL value keeps its
-// leading 4 bytes (the high 32-bit word of its FP64 encoding) in the group.
-inline constexpr int group_width(int dt) { return dt == 0 ? 2 : (dt == 2 || dt == 3) ? 8 : 4; }
+// leading 4 bytes (DFL32 / 40 / 48: the high 32-bit word of its FP64
+// encoding) or 2 bytes (DFL16 / 24: the high 16 bits) in the group.
+inline constexpr int group_width(int dt) {
+  return dt == 0 ? 2 : (dt == 2 || dt == 3 || dt == kDtDfl16 || dt == kDtDfl24) ? 8 : 4;
+}
 // Bytes per value inside the 16-byte groups.
-inline constexpr int dtype_size(int dt) { return dt == 0 ? 8 : (dt == 2 || dt == 3) ? 2 : 4; }
-// DFL40 / DFL48 keep the rest of each value (1 / 2 bytes: bits 31..24 /
-// 31..16 of the encoding) in a low-byte plane: lo_bytes per 16-byte group
-// element (4 values), 0 for the other formats.
-inline constexpr int lo_bytes(int dt) { return dt == kDtDfl40 ? 4 : dt == kDtDfl48 ? 8 : 0; }
+inline constexpr int dtype_size(int dt) { return 16 / group_width(dt); }
+// DFL40 / DFL48 / DFL24 keep the rest of each value (1 / 2 / 1 bytes: bits
+// 31..24 / 31..16 / 47..40 of the encoding) in a low-byte plane: lo_bytes
+// per 16-byte group element (4, 8 or 8 values), 0 for the other formats.
+inline constexpr int lo_bytes(int dt) { return dt == kDtDfl40 ? 4 : (dt == kDtDfl48 || dt == kDtDfl24) ? 8 : 0; }
 // Stored bytes per value.
-inline constexpr int value_bytes(int dt) { return dtype_size(dt) + lo_bytes(dt) / 4; }
-inline constexpr bool is_dfl(int dt) { return dt >= kDtDfl32 && dt <= kDtDfl48; }
+inline constexpr int value_bytes(int dt) { return dtype_size(dt) + lo_bytes(dt) / group_width(dt); }
+inline constexpr bool is_dfl(int dt) { return dt >= kDtDfl32 && dt <= kDtDfl24; }
 
 struct RowPanel {        // 32 bytes
   int64_t src_off;       // first entry (int32 units) in the row-source table
@@ -155,6 +159,13 @@ struct StoreHeader {
   // tile_class_end[kNumDtypes])
   int64_t tile_class_end[kNumDtypes + 1];
 };
+
+// Low-byte plane entry bytes of a tile: the largest lo_bytes of its runs.
+inline constexpr int tile_lo_bytes(const ColTile& T) {
+  int L = 0;
+  for (int q = 0; q < 4; ++q) L = L > lo_bytes(T.dtype[q]) ? L : lo_bytes(T.dtype[q]);
+  return L;
+}
 
 // Class of a column tile: its format if it has one, else kNumDtypes.
 inline constexpr int tile_class(const ColTile& T) {

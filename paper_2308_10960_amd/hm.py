@@ -19,8 +19,8 @@ LIB_PATH = os.path.join(HERE, "libhm.so")
 HM_OK, HM_EINVAL, HM_EPARTITION, HM_ESHAPE, HM_EDTYPE = 0, -1, -2, -3, -4
 HM_ENOMEM, HM_EDEVICE, HM_EBUSY, HM_ESTATE, HM_ETIMEOUT = -5, -6, -7, -8, -9
 HM_F64, HM_F32, HM_F16, HM_BF16 = 0, 1, 2, 3
-HM_DFL32, HM_DFL40, HM_DFL48 = 4, 5, 6
-HM_NUM_DTYPES = 7
+HM_DFL32, HM_DFL40, HM_DFL48, HM_DFL16, HM_DFL24 = 4, 5, 6, 7, 8
+HM_NUM_DTYPES = 9
 HM_DENSE, HM_LOWRANK = 0, 1
 
 STATUS_NAMES = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_EPARTITION", -3: "HM_ESHAPE",

@@ -25,15 +25,16 @@ RS = np.dtype([("data_off", "<i8"), ("dtype", "<i4"), ("ngroups", "<i4"), ("col0
 CT = np.dtype([("data_off", "<i8"), ("nrows", "<i4"), ("x0", "<i4"), ("ngroups", "<i4"),
                ("dst_off", "<i4"), ("dtype", "u1", (4,)), ("end", "u1", (4,))])
 TB = np.dtype([("pst", "<i4"), ("k", "<i4"), ("nseg", "<i4"), ("toff", "<i4")])
-G = {0: 2, 1: 4, 2: 8, 3: 8, 4: 4, 5: 4, 6: 4}
-SZ = {0: 8, 1: 4, 2: 2, 3: 2, 4: 4, 5: 4, 6: 4}      # bytes per value inside the 16-byte groups
-LO = {5: (1, 24), 6: (2, 16)}                        # DFL40 / DFL48: low bytes per value, bit position
+G = {0: 2, 1: 4, 2: 8, 3: 8, 4: 4, 5: 4, 6: 4, 7: 8, 8: 8}
+SZ = {0: 8, 1: 4, 2: 2, 3: 2, 4: 4, 5: 4, 6: 4, 7: 2, 8: 2}   # bytes per value inside the 16-byte groups
+LO = {5: (1, 24), 6: (2, 16), 8: (1, 40)}       # low bytes per value, bit position (DFL40 / 48 / 24)
 
 
 def decode_dfl(hi: np.ndarray, lo, dt: int) -> np.ndarray:
-    """DFL values from the high words of their FP64 encodings (uint32) and,
-    for DFL40 / DFL48, their low bytes (uint8 / uint16 arrays of the same shape)."""
-    bits = hi.astype(np.uint64) << np.uint64(32)
+    """DFL values from the leading words of their FP64 encodings (uint32 for
+    DFL32 / 40 / 48, uint16 for DFL16 / 24) and, for DFL40 / 48 / 24, their
+    low bytes (uint8 / uint16 arrays of the same shape)."""
+    bits = hi.astype(np.uint64) << np.uint64(64 - 8 * SZ[dt])
     if dt in LO:
         bits |= lo.astype(np.uint64) << np.uint64(LO[dt][1])
     return bits.view("<f8")
@@ -75,6 +76,10 @@ def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> n
         # a tile row is ng 16-byte groups, in runs of one format each
         d0 = int(t["data_off"])
         raw = buf[d0: d0 + nr * ng * 16].reshape(nr, ng * 16)
+        # low-byte plane after the rows: one entry of Lt bytes per row and
+        # group (the largest entry of the tile's formats)
+        Lt = max(G[int(d)] * LO[int(d)][0] if int(d) in LO else 0 for d in t["dtype"])
+        plane = buf[d0 + nr * ng * 16: d0 + nr * ng * (16 + Lt)].reshape(nr, ng, Lt) if Lt else None
         parts, g0 = [], 0
         for r in range(4):
             e, dt = int(t["end"][r]), int(t["dtype"][r])
@@ -82,12 +87,11 @@ def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> n
                 block = np.ascontiguousarray(raw[:, 16 * g0: 16 * e]).reshape(-1)
                 if dt >= 4:
                     lo = None
-                    if dt in LO:                             # low-byte plane after the rows (one-format tile)
-                        assert g0 == 0 and e == ng
+                    if dt in LO:
                         nb = LO[dt][0]
-                        lo = np.ascontiguousarray(buf[d0 + nr * ng * 16: d0 + nr * ng * (16 + 4 * nb)])
+                        lo = np.ascontiguousarray(plane[:, g0:e, : G[dt] * nb]).reshape(-1)
                         lo = lo.view("<u1" if nb == 1 else "<u2")
-                    parts.append(decode_dfl(block.view("<u4"), lo, dt).reshape(nr, -1))
+                    parts.append(decode_dfl(block.view("<u4" if SZ[dt] == 4 else "<u2"), lo, dt).reshape(nr, -1))
                 else:
                     parts.append(decode(block, 0, block.size // SZ[dt], dt).reshape(nr, -1))
             g0 = e
@@ -127,11 +131,11 @@ def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> n
             g = G[dt]
             d0 = int(s["data_off"])
             if dt >= 4:
-                hi = np.ascontiguousarray(buf[d0: d0 + ng * m * 16]).view("<u4")
+                hi = np.ascontiguousarray(buf[d0: d0 + ng * m * 16]).view("<u4" if SZ[dt] == 4 else "<u2")
                 lo = None
                 if dt in LO:                                 # low-byte plane after the groups
                     nb = LO[dt][0]
-                    lo = np.ascontiguousarray(buf[d0 + ng * m * 16: d0 + ng * m * (16 + 4 * nb)])
+                    lo = np.ascontiguousarray(buf[d0 + ng * m * 16: d0 + ng * m * (16 + G[dt] * nb)])
                     lo = lo.view("<u1" if nb == 1 else "<u2")
                 vals = decode_dfl(hi, lo, dt).reshape(ng, m, g)
             else:

@@ -127,6 +127,40 @@ def test_precision_groups_are_well_formed():
     assert np.mean(has16) > 0.5
 
 
+def test_aplr_dfl_selection_meets_block_budget():
+    """APLR over the DFL formats (Sec. 3.3): every block's storage error,
+    recomputed with the oracle's own DFL rounding on the dense block, is
+    within tol ||M_b||_F; groups are contiguous, at most 4, widening towards
+    the large singular values; the budget is not met trivially (narrow
+    formats are used)."""
+    import oracle
+    H = hmgen.build_preset("sphere4k_aplr")
+    tol = hmgen.preset("sphere4k_aplr")["eps"] / 2
+    width = [hm.DT_DFL16, hm.DT_DFL24, hm.DT_DFL32, hm.DT_DFL40, hm.DT_DFL48, hm.DT_F64]
+    dec = oracle.decoded_factors(H, sigma_dtype=oracle.F64)
+    used = set()
+    for i in range(H.nblocks):
+        a, b, s = H.factors(i)
+        da, db, ds = dec[i]
+        g = int(H.ngroups[i])
+        dts = [int(d) for d in H.group_dtype[i][:g]]
+        used |= set(dts)
+        assert all(d in width for d in dts)
+        if not H.adm[i]:
+            assert g == 1
+            M, Md = np.asarray(a), np.asarray(da)
+        else:
+            if int(H.rank[i]) == 0:
+                continue
+            assert H.group_cols[i][:g].sum() == H.rank[i] and g <= 4
+            assert [width.index(d) for d in dts] == sorted((width.index(d) for d in dts), reverse=True)
+            np.testing.assert_array_equal(ds, s)                 # s kept in FP64
+            M = (np.asarray(a) * s) @ np.asarray(b).T
+            Md = (np.asarray(da) * ds) @ np.asarray(db).T
+        assert np.linalg.norm(M - Md) <= tol * np.linalg.norm(M) * (1 + 1e-9), i
+    assert {hm.DT_DFL16, hm.DT_DFL24} <= used
+
+
 def test_fill_in_shares_equals_fill_at_once(capsys):
     """Filling the leaves in 16 shares (with progress lines) gives the same
     ranks and factors, bit for bit, as one fill."""

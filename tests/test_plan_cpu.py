@@ -17,7 +17,7 @@ import hmgen
 import oracle
 from paper_2308_10960_amd import hm, blocks_from_table
 from conftest import ROOT
-from store_model import model_mvm, SZ
+from store_model import model_mvm, SZ, tables
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -78,7 +78,7 @@ def test_rejects_malformed_tables():
     _expect(hm.HM_ESHAPE, b)                              # rank > min(m, n)
     b = t.copy(); b["group_cols"][1][0] = 2
     _expect(hm.HM_ESHAPE, b)                              # groups do not sum to rank
-    b = t.copy(); b["group_dtype"][0][0] = 7
+    b = t.copy(); b["group_dtype"][0][0] = hm.HM_NUM_DTYPES
     _expect(hm.HM_EDTYPE, b)                              # unknown dtype
     _expect(hm.HM_EDTYPE, t, acc=hm.HM_F32)               # FP64 storage, FP32 accumulation
     b = t.copy(); b["kind"][1] = 5
@@ -145,12 +145,39 @@ def _set_dtypes(H, dense_dt: int, lr_dt: int) -> None:
     H.group_dtype[H.adm == 0, 0] = dense_dt
 
 
+DFL_NBYTES = {hm.HM_DFL16: 2, hm.HM_DFL24: 3, hm.HM_DFL32: 4, hm.HM_DFL40: 5, hm.HM_DFL48: 6}
+
+
+def _aplr_like(H, formats, seed=0):
+    """Every low-rank block split into up to 4 column groups with formats
+    drawn from `formats` (dense blocks too, one format each)."""
+    rng = np.random.default_rng(seed)
+    H.set_uniform_dtype(formats[0])
+    for i in range(H.nblocks):
+        if not H.adm[i]:
+            H.group_dtype[i, 0] = formats[rng.integers(len(formats))]
+            continue
+        k = int(H.rank[i])
+        if k == 0:
+            continue
+        ng = int(rng.integers(1, min(4, k) + 1))
+        cuts = np.sort(rng.choice(np.arange(1, k), ng - 1, replace=False)) if ng > 1 else np.array([], int)
+        sizes = np.diff(np.concatenate([[0], cuts, [k]]))
+        H.ngroups[i] = ng
+        H.group_cols[i, :] = 0
+        H.group_cols[i, :ng] = sizes
+        H.group_dtype[i, :] = 0
+        H.group_dtype[i, :ng] = [formats[j] for j in rng.integers(len(formats), size=ng)]
+
+
 @pytest.mark.parametrize("dense_dt,lr_dt", [(hm.HM_DFL32, hm.HM_DFL32), (hm.HM_DFL40, hm.HM_DFL40),
-                                            (hm.HM_DFL48, hm.HM_DFL48), (hm.HM_DFL48, hm.HM_DFL32)])
+                                            (hm.HM_DFL48, hm.HM_DFL48), (hm.HM_DFL48, hm.HM_DFL32),
+                                            (hm.HM_DFL16, hm.HM_DFL24), (hm.HM_DFL24, hm.HM_DFL16)])
 def test_dfl_conversion_bit_exact(dense_dt, lr_dt):
-    """DFL entries sit at the offsets hm_plan_locate reports: the high word
-    of the encoding of the oracle's rounded value, and its low byte(s) in the
-    low-byte plane (DFL40: bits 31..24, DFL48: bits 31..16)."""
+    """DFL entries sit at the offsets hm_plan_locate reports: the leading
+    word of the encoding of the oracle's rounded value (32 bits, or 16 for
+    DFL16 / 24), and its low byte(s) in the low-byte plane (DFL40: bits
+    31..24, DFL48: bits 31..16, DFL24: bits 47..40)."""
     H = hmgen.build_preset("sphere4k")
     _set_dtypes(H, dense_dt, lr_dt)
     p, info, buf = _pack(H, hm.HM_F64)
@@ -166,44 +193,49 @@ def test_dfl_conversion_bit_exact(dense_dt, lr_dt):
                 off, dt, lo_off = hm.hm_plan_locate(p, int(bi), which, i, j, lo=True)
                 assert dt == (lr_dt if H.adm[bi] else dense_dt)
                 bits = int(oracle.round_to(np.array([F[i, j]]), dt).view("<u8")[0])
-                assert int(buf[off: off + 4].view("<u4")[0]) == bits >> 32, (bi, which, i, j)
+                if dt in (hm.HM_DFL16, hm.HM_DFL24):
+                    assert int(buf[off: off + 2].view("<u2")[0]) == bits >> 48, (bi, which, i, j)
+                else:
+                    assert int(buf[off: off + 4].view("<u4")[0]) == bits >> 32, (bi, which, i, j)
                 if dt == hm.HM_DFL40:
                     assert int(buf[lo_off]) == (bits >> 24) & 0xff
                 elif dt == hm.HM_DFL48:
                     assert int(buf[lo_off: lo_off + 2].view("<u2")[0]) == (bits >> 16) & 0xffff
+                elif dt == hm.HM_DFL24:
+                    assert int(buf[lo_off]) == (bits >> 40) & 0xff
                 else:
                     assert lo_off == 0
-                assert bits & ((1 << (64 - 8 * {4: 4, 5: 5, 6: 6}[dt])) - 1) == 0
+                assert bits & ((1 << (64 - 8 * DFL_NBYTES[dt])) - 1) == 0
                 seen.add(dt)
     assert seen == {dense_dt, lr_dt}
-    per_value = {hm.HM_DFL32: 4, hm.HM_DFL40: 5, hm.HM_DFL48: 6}
     for dt in seen:
-        assert info["bytes_by_dtype"][dt] > 0 and info["bytes_by_dtype"][dt] % per_value[dt] == 0
+        assert info["bytes_by_dtype"][dt] > 0 and info["bytes_by_dtype"][dt] % DFL_NBYTES[dt] == 0
     hm.hm_plan_destroy(p)
 
 
 def test_dfl_plan_rules():
-    """DFL needs FP64 accumulation; DFL40 / DFL48 low-rank groups admit no
-    other low-rank format in the plan."""
+    """DFL needs FP64 accumulation; any mix of formats is allowed, and
+    several-format column tiles hold formats with and without a low-byte
+    plane."""
     H = hmgen.build_preset("sphere4k")
     _set_dtypes(H, hm.HM_F64, hm.HM_DFL32)
     with pytest.raises(hm.HMError) as e:
         hm.hm_build_plan(H.n, H.n, blocks_from_table(H), hm.HM_F32)
     assert e.value.status == hm.HM_EDTYPE
-    for lo_fmt in (hm.HM_DFL40, hm.HM_DFL48):
-        _set_dtypes(H, hm.HM_F64, lo_fmt)
-        lr = np.flatnonzero((H.adm != 0) & (H.rank > 0))
-        H.group_dtype[lr[len(lr) // 2], 0] = hm.HM_DFL32
-        with pytest.raises(hm.HMError) as e:
-            hm.hm_build_plan(H.n, H.n, blocks_from_table(H), hm.HM_F64)
-        assert e.value.status == hm.HM_EDTYPE
-    # dense blocks may use any format beside them
-    _set_dtypes(H, hm.HM_DFL32, hm.HM_DFL40)
-    hm.hm_plan_destroy(hm.hm_build_plan(H.n, H.n, blocks_from_table(H), hm.HM_F64))
+    _aplr_like(H, [hm.HM_F64, hm.HM_DFL16, hm.HM_DFL24, hm.HM_DFL32, hm.HM_DFL40, hm.HM_DFL48])
+    p, info, buf = _pack(H, hm.HM_F64)
+    h, T = tables(buf)
+    lo_fmts = {hm.HM_DFL24, hm.HM_DFL40, hm.HM_DFL48}
+    n_mixed_lo = 0
+    for t in T["ct"]:
+        runs = [int(t["dtype"][r]) for r in range(4) if int(t["end"][r]) > (int(t["end"][r - 1]) if r else 0)]
+        n_mixed_lo += len(runs) > 1 and bool(lo_fmts & set(runs)) and bool(set(runs) - lo_fmts)
+    assert n_mixed_lo > 0
+    hm.hm_plan_destroy(p)
 
 
 @pytest.mark.parametrize("which", ["f64", "mixed", "mixed16k", "bf16", "dfl32", "dfl40_16k", "dfl48",
-                                   "dfl_mix"])
+                                   "dfl_mix", "dfl_any_16k", "dfl16", "dfl24", "aplr"])
 def test_store_model_matches_oracle(which, f64_4k, mixed4k):
     """The packed store, read as its layout defines it, gives the oracle's
     product.  At n = 16384 some blocks span several column chunks (partials
@@ -217,23 +249,28 @@ def test_store_model_matches_oracle(which, f64_4k, mixed4k):
     elif which == "bf16":
         H = hmgen.build_preset("sphere4k_mixed")
         H.set_uniform_dtype(hm.HM_BF16)
+    elif which == "aplr":
+        H = hmgen.build_preset("sphere4k_aplr")
     elif which.startswith("dfl"):
         H = hmgen.build_preset("sphere4k", n=16384 if which.endswith("16k") else None)
         if which == "dfl_mix":
             _set_dtypes(H, hm.HM_DFL48, hm.HM_DFL32)
             dense = np.flatnonzero(H.adm == 0)
             H.group_dtype[dense[::3], 0] = hm.HM_F64
+        elif which == "dfl_any_16k":
+            _aplr_like(H, [hm.HM_F64, hm.HM_DFL16, hm.HM_DFL24, hm.HM_DFL32, hm.HM_DFL40, hm.HM_DFL48], seed=3)
         else:
-            H.set_uniform_dtype({"dfl32": hm.HM_DFL32, "dfl40_16k": hm.HM_DFL40, "dfl48": hm.HM_DFL48}[which])
+            H.set_uniform_dtype({"dfl32": hm.HM_DFL32, "dfl40_16k": hm.HM_DFL40, "dfl48": hm.HM_DFL48,
+                                 "dfl16": hm.HM_DFL16, "dfl24": hm.HM_DFL24}[which])
     else:
         H = {"f64": f64_4k, "mixed": mixed4k}[which]
-    acc = hm.HM_F64 if which == "f64" or which.startswith("dfl") else hm.HM_F32
+    acc = hm.HM_F64 if which in ("f64", "aplr") or which.startswith("dfl") else hm.HM_F32
     p, info, buf = _pack(H, acc)
     if which.endswith("16k"):
         assert info["n_partials"] > 0
     x = hmgen.uniform_vector(H.n)
     y0 = hmgen.uniform_vector(H.n, seed=5)
-    if which.startswith("dfl"):
+    if which.startswith("dfl") or which == "aplr":
         ref = oracle.hmvm(H, x, y0, alpha=0.75, factors=oracle.decoded_factors(H, sigma_dtype=oracle.F64))
     elif which == "f64":
         ref = oracle.hmvm(H, x, y0, alpha=0.75)
