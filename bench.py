@@ -249,35 +249,54 @@ def main():
     vs = 4 if mixed else 8
     stream = torch.cuda.Stream()
     cache = None if args.no_tune_cache or not os.path.exists(args.tune_cache) else args.tune_cache
-    with torch.cuda.stream(stream):
-        D = DeviceHMatrix(H, acc, stream=stream, max_nrhs=args.nrhs, tune_cache=cache)
-    info = D.info
-    log("uploaded: store %.3f GB, alg %.3f GB" % (info["store_bytes"] / 1e9, info["alg_bytes"] / 1e9))
     R = args.nrhs
-    if R == 1:
-        x = D.vector(hmgen.uniform_vector(H.n, seed=hmgen.presets.SEED_X))
-        y = D.vector()
-        step = lambda: D.mvm(x, y, 1.0, stream=stream)
-    else:
+
+    def build(chunk=0, tile=0, use_cache=True):
+        with torch.cuda.stream(stream):
+            return DeviceHMatrix(H, acc, stream=stream, max_nrhs=R, tune_cache=cache if use_cache else None,
+                                 chunk_rows=chunk, tile_groups=tile)
+
+    if R > 1:
         Xh = hmgen.gaussian_block(H.n, R, seed=hmgen.presets.SEED_RHS)
-        X = torch.from_numpy(np.ascontiguousarray(Xh.T)).to(D.vec_torch).cuda()
+        X = torch.from_numpy(np.ascontiguousarray(Xh.T)).to(
+            torch.float64 if acc == hm.HM_F64 else torch.float32).cuda()
         Y = torch.zeros_like(X)
-        x = X[0]
-        step = lambda: hm.hm_mvm_batch(D.handle, R, 1.0, X, H.n, Y, H.n, D.work, D.work.numel(),
-                                       stream)
+
+    def make_step(D):
+        """One product of D and its vectors (x, y)."""
+        if R == 1:
+            xv = D.vector(hmgen.uniform_vector(H.n, seed=hmgen.presets.SEED_X))
+            yv = D.vector()
+            return (lambda: D.mvm(xv, yv, 1.0, stream=stream)), xv, yv
+        return (lambda: hm.hm_mvm_batch(D.handle, R, 1.0, X, H.n, Y, H.n, D.work, D.work.numel(),
+                                        stream)), X[0], Y
+
+    D = build()
+    step, x, y = make_step(D)
     torch.cuda.synchronize()
 
     key = hm.hm_matrix_tune_key(D.handle)
     if args.tune:
         from paper_2308_10960_amd import tune
         best, times = tune.tune(D, step, tune.CANDIDATES if R == 1 else tune.BATCH_CANDIDATES)
-        tune.write_cache(args.tune_cache, key, best)
+        shape, shape_times = tune.tune_shape(lambda c, t: build(c, t, use_cache=False),
+                                             lambda Dc: make_step(Dc)[0], best)
+        chosen = f"{best} chunk={shape[0]} tile={shape[1]}"
+        tune.write_cache(args.tune_cache, key, chosen)
+        cache = args.tune_cache
+        D.close()
+        D = build()                                 # the tuned launch parameters and tile shape
+        step, x, y = make_step(D)
+        torch.cuda.synchronize()
         tuned = {"source": "autotuner, this run (written to the tune cache)", "key": key,
-                 "chosen": best, "avg_ms": {k: round(v, 5) for k, v in times.items()}}
+                 "chosen": chosen, "avg_ms": {k: round(v, 5) for k, v in times.items()},
+                 "shape_avg_ms": {f"chunk={c} tile={t}": round(v, 5) for (c, t), v in shape_times.items()}}
     else:
         tuned = {"source": "tune cache" if cache else "built-in", "key": key,
                  "chosen": hm.hm_matrix_get_launch(D.handle)}
     log("launch parameters:", tuned)
+    info = D.info
+    log("uploaded: store %.3f GB, alg %.3f GB" % (info["store_bytes"] / 1e9, info["alg_bytes"] / 1e9))
 
     for _ in range(args.warmup):
         step()

@@ -88,10 +88,17 @@ typedef struct {
  * tune: 0 = built-in launch parameters; 1 = read tune_cache, a text file
  * written by the tuner with one "key params" line per kind of matrix (see
  * hm_matrix_tune_key and hm_matrix_set_launch); a key that is missing
- * falls back to the built-ins.  tune_cache may be NULL when tune = 0. */
+ * falls back to the built-ins.  tune_cache may be NULL when tune = 0.
+ * chunk_rows, tile_groups: the column-tile shape.  The rows of every V_b
+ * are cut into chunks of at most chunk_rows rows (64 .. 512), and a chunk's
+ * columns into tiles of at most tile_groups 16-byte groups (8 .. 64).  0
+ * takes the value from the tune cache line of this kind of matrix (keys
+ * "chunk" and "tile"), else the built-ins 512 and 64.  Results depend on
+ * the shape only by rounding (the partial sums are cut differently). */
 typedef struct {
   int32_t acc_dtype, vec_dtype, max_nrhs, tune;
   const char* tune_cache;
+  int32_t chunk_rows, tile_groups;
 } hm_plan_opts;
 
 /* Sizes and byte accounting of a plan (all counts exact).
@@ -224,7 +231,10 @@ hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls);
 
 /* Launch parameters of one matrix, as text
  * "schedule=S unroll=U order=O persist=P" (any subset of the keys; the
- * built-in choice is schedule=0 unroll=8 order=1 persist=0):
+ * built-in choice is schedule=0 unroll=8 order=1 persist=0; the text
+ * hm_matrix_get_launch writes, and a tune cache line, also name the plan's
+ * tile shape, "chunk=C tile=G", which hm_matrix_set_launch accepts only
+ * with the plan's own values):
  *   schedule 0: column tiles, partial reduction, whole row panels;
  *   schedule 1: one grouped launch of the dense row-panel sections with the
  *               column tiles, the reduction, then the U sections;

@@ -196,7 +196,7 @@ static void split_intervals(const std::vector<int64_t>& bp, int cap, std::vector
 // largest lo_bytes of its runs; 0: none) per row and group; groups of a
 // format without one leave theirs unused.  Fills tile_g0 / tile_off /
 // tile_lo.
-static void cut_tiles(ColPanelHost& Cp) {
+static void cut_tiles(ColPanelHost& Cp, int32_t tile_groups) {
   Cp.tile_g0.assign(1, 0);
   Cp.tile_off.assign(1, 0);
   Cp.tile_lo.clear();
@@ -211,12 +211,12 @@ static void cut_tiles(ColPanelHost& Cp) {
     const int32_t n = S.ld / group_width(S.dtype);
     for (int32_t g = 0; g < n;) {
       if (runs == 4) close();
-      const int32_t take = std::min(kTileGroups - open, n - g);
+      const int32_t take = std::min(tile_groups - open, n - g);
       open += take;
       g += take;
       ++runs;
       L = std::max(L, lo_bytes(S.dtype));
-      if (open == kTileGroups) close();
+      if (open == tile_groups) close();
     }
   }
   if (open > 0) close();
@@ -250,7 +250,7 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
   if (n_rows <= 0 || n_cols <= 0 || n_rows > INT32_MAX / 4 || n_cols > INT32_MAX / 4)
     return fail(HM_EINVAL, "bad matrix size %lld x %lld", (long long)n_rows, (long long)n_cols);
   if (nb <= 0 || !blocks) return fail(HM_EINVAL, "empty block table");
-  hm_plan_opts opts{HM_F64, HM_F64, 1, 0, nullptr};
+  hm_plan_opts opts{HM_F64, HM_F64, 1, 0, nullptr, 0, 0};
   if (o) opts = *o;
   if (opts.acc_dtype != HM_F64 && opts.acc_dtype != HM_F32)
     return fail(HM_EDTYPE, "acc_dtype must be HM_F64 or HM_F32");
@@ -269,6 +269,18 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
     hm_status st = validate_block(P->blocks[i], i, n_rows, n_cols, acc);
     if (st) return st;
   }
+  // launch parameters and tile shape of this kind of matrix from the tune
+  // cache, then the tile shape the caller gives
+  if (opts.tune && !P->tune_path.empty()) read_tune_cache(P.get());
+  if (opts.chunk_rows < 0 || opts.tile_groups < 0) return fail(HM_EINVAL, "negative tile shape");
+  P->chunk_rows = opts.chunk_rows ? opts.chunk_rows : P->launch.chunk ? P->launch.chunk : kSegRows;
+  P->tile_groups = opts.tile_groups ? opts.tile_groups : P->launch.tile ? P->launch.tile : kTileGroups;
+  if (P->chunk_rows < kMaxTileRows || P->chunk_rows > kSegRows)
+    return fail(HM_EINVAL, "chunk_rows %d outside [%d, %d]", P->chunk_rows, kMaxTileRows, kSegRows);
+  if (P->tile_groups < 8 || P->tile_groups > kTileGroups)
+    return fail(HM_EINVAL, "tile_groups %d outside [8, %d]", P->tile_groups, kTileGroups);
+  P->launch.chunk = P->chunk_rows;
+  P->launch.tile = P->tile_groups;
 
   // ---- elementary row intervals and the tiling proof
   std::vector<int64_t> rbp;
@@ -314,8 +326,8 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
 
   // ---- low-rank blocks: column chunks, t and partial offsets
   // The rows of each V_b are cut into chunks: sigma_b itself when it has at
-  // most kSegRows rows, else the largest sub-ranges of sigma_b with at most
-  // kSegRows rows among the block ranges (for a block tree these are the
+  // most chunk_rows rows, else the largest sub-ranges of sigma_b with at most
+  // chunk_rows rows among the block ranges (for a block tree these are the
   // clusters of the cluster tree), recursively.  A range that has no
   // sub-ranges covering it, or a family of ranges that is not nested, falls
   // back to near-equal pieces of at most 64 rows.  Equal ranges always get
@@ -364,7 +376,7 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
   };
   std::function<void(int64_t, int64_t, std::vector<int32_t>&)> chunk_range =
       [&](int64_t b0, int64_t e0, std::vector<int32_t>& out) {
-        if (e0 - b0 <= kSegRows) { out.push_back(add_chunk(b0, e0)); return; }
+        if (e0 - b0 <= P->chunk_rows) { out.push_back(add_chunk(b0, e0)); return; }
         const int32_t r = laminar ? find_range(b0, e0) : -1;
         if (r >= 0 && !kids[r].empty()) {
           int64_t covered = b0;
@@ -539,12 +551,10 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
       Cp.ncols += S.ld;
       Cp.secs.push_back(S);
     }
-    cut_tiles(Cp);
+    cut_tiles(Cp, P->tile_groups);
   }
 
-  hm_status st = layout_store(P.release(), out);
-  if (st == HM_OK && (*out)->opts.tune && !(*out)->tune_path.empty()) read_tune_cache(*out);
-  return st;
+  return layout_store(P.release(), out);
 }
 
 // ------------------------------------------------------------------ tuning
@@ -570,6 +580,8 @@ static bool parse_launch(const char* text, LaunchParams& lp) {
     else if (k == "unroll" && (v == 4 || v == 8)) r.row_unroll = (int)v;
     else if (k == "order" && (v == 0 || v == 1)) r.order = (int)v;
     else if (k == "persist" && (v == 0 || v == 1 || v == 2 || v == 4 || v == 8)) r.persist = (int)v;
+    else if (k == "chunk" && v >= kMaxTileRows && v <= kSegRows) r.chunk = (int)v;
+    else if (k == "tile" && v >= 8 && v <= kTileGroups) r.tile = (int)v;
     else return false;
     i = j;
   }
@@ -580,20 +592,36 @@ static bool parse_launch(const char* text, LaunchParams& lp) {
 // Kind of matrix a tuned choice applies to: accumulation type, storage
 // formats present, size class, and "-batch" for plans made for several
 // right-hand sides (their products run the multi-right-hand-side kernels).
-static std::string tune_key(int acc, const size_t* bytes_by_dtype, int64_t n_rows, int max_nrhs) {
-  int mask = 0;
-  for (int d = 0; d < kNumDtypes; ++d) if (bytes_by_dtype[d]) mask |= 1 << d;
+static std::string tune_key_mask(int acc, int mask, int64_t n_rows, int max_nrhs) {
   int lg = 0;
   while ((int64_t(1) << (lg + 1)) <= n_rows) ++lg;
   char buf[64];
   std::snprintf(buf, sizeof buf, "acc%d-fmt%d-n2^%d%s", acc, mask, lg, max_nrhs > 1 ? "-batch" : "");
   return buf;
 }
+static std::string tune_key(int acc, const size_t* bytes_by_dtype, int64_t n_rows, int max_nrhs) {
+  int mask = 0;
+  for (int d = 0; d < kNumDtypes; ++d) if (bytes_by_dtype[d]) mask |= 1 << d;
+  return tune_key_mask(acc, mask, n_rows, max_nrhs);
+}
+
+// The formats a plan's blocks store values in (the formats with stored
+// bytes once it is laid out).
+static int format_mask(const hm_plan* P) {
+  int mask = 0;
+  for (auto& b : P->blocks) {
+    if (b.kind == HM_DENSE) mask |= 1 << b.group_dtype[0];
+    else
+      for (int g = 0; g < b.ngroups; ++g)
+        if (b.group_cols[g] > 0) mask |= 1 << b.group_dtype[g];
+  }
+  return mask;
+}
 
 void read_tune_cache(hm_plan* P) {
   FILE* f = std::fopen(P->tune_path.c_str(), "r");
   if (!f) return;
-  const std::string key = tune_key(P->opts.acc_dtype, P->bytes_by_dtype, P->n_rows, P->opts.max_nrhs);
+  const std::string key = tune_key_mask(P->opts.acc_dtype, format_mask(P), P->n_rows, P->opts.max_nrhs);
   char line[512];
   while (std::fgets(line, sizeof line, f)) {
     std::string l(line);
@@ -1403,14 +1431,16 @@ hm_status hm_matrix_set_launch(hm_matrix* A, const char* params) {
   if (!A || !params) return fail(HM_EINVAL, "NULL argument");
   LaunchParams lp = A->launch;
   if (!parse_launch(params, lp)) return fail(HM_EINVAL, "bad launch parameters '%s'", params);
+  if (lp.chunk != A->launch.chunk || lp.tile != A->launch.tile)
+    return fail(HM_EINVAL, "the tile shape (chunk, tile) is the plan's; set it when the plan is built");
   A->launch = lp;
   return ok();
 }
 
 hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len) {
   if (!A || !buf || len == 0) return fail(HM_EINVAL, "NULL argument");
-  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d persist=%d", A->launch.schedule,
-                A->launch.row_unroll, A->launch.order, A->launch.persist);
+  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d persist=%d chunk=%d tile=%d", A->launch.schedule,
+                A->launch.row_unroll, A->launch.order, A->launch.persist, A->launch.chunk, A->launch.tile);
   return ok();
 }
 

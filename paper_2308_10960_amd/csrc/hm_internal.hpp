@@ -21,11 +21,15 @@ namespace hm {
 //           contiguous ranges, one per XCD (whole-panel kernels).
 //  persist 0: one workgroup per work item; P > 0: persistent grids of at
 //           most P workgroups per CU looping over the items (single RHS).
+//  chunk, tile: the plan's column-tile shape (rows per column chunk, groups
+//           per tile); 0 = not given.
 struct LaunchParams {
   int schedule = 0;
   int row_unroll = 8;
   int order = 1;
   int persist = 0;
+  int chunk = 0;
+  int tile = 0;
 };
 
 struct BlockInfo {
@@ -95,6 +99,7 @@ struct hm_plan {
   int64_t n_t = 0, n_partials = 0, n_large = 0, n_large_t = 0, n_red_t = 0;
   int32_t has_sigma = 0;
   hm::StoreHeader hdr{};
+  int32_t chunk_rows = hm::kSegRows, tile_groups = hm::kTileGroups;   // column-tile shape
   size_t store_bytes = 0, meta_bytes = 0, work_bytes_per_rhs = 0;
   int64_t work_part_off = 0, work_t_off = 0;
   int64_t work_part_bytes = 0, work_t_bytes = 0, work_x_bytes = 0;

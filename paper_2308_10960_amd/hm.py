@@ -36,7 +36,8 @@ BLOCK_DTYPE = np.dtype([("row_begin", "<i8"), ("row_end", "<i8"), ("col_begin", 
 
 class PlanOpts(C.Structure):
     _fields_ = [("acc_dtype", C.c_int32), ("vec_dtype", C.c_int32), ("max_nrhs", C.c_int32),
-                ("tune", C.c_int32), ("tune_cache", C.c_char_p)]
+                ("tune", C.c_int32), ("tune_cache", C.c_char_p), ("chunk_rows", C.c_int32),
+                ("tile_groups", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -148,10 +149,12 @@ def make_blocks(rb, re, cb, ce, kind, rank, ngroups, group_cols, group_dtype, ha
 
 
 def hm_build_plan(n_rows: int, n_cols: int, blocks: np.ndarray, acc_dtype: int = HM_F64,
-                  max_nrhs: int = 1, tune_cache: str | None = None) -> int:
+                  max_nrhs: int = 1, tune_cache: str | None = None, chunk_rows: int = 0,
+                  tile_groups: int = 0) -> int:
+    """chunk_rows, tile_groups: the column-tile shape (0: tune cache or built-in)."""
     blocks = np.ascontiguousarray(blocks, dtype=BLOCK_DTYPE)
     opts = PlanOpts(acc_dtype, acc_dtype, max_nrhs, 1 if tune_cache else 0,
-                    tune_cache.encode() if tune_cache else None)
+                    tune_cache.encode() if tune_cache else None, chunk_rows, tile_groups)
     out = C.c_void_p()
     _check(lib().hm_build_plan(n_rows, n_cols, blocks.ctypes.data, blocks.shape[0],
                                C.byref(opts), C.byref(out)), "hm_build_plan")

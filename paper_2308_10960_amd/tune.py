@@ -1,10 +1,12 @@
 """Autotuner of the launch parameters (schedule, unroll depth, panel order,
-persistent grids).
+persistent grids) and of the column-tile shape (rows per column chunk,
+groups per tile).
 
-For one device-resident matrix it times every candidate with the library's
-own HIP-event kernel timing, keeps the fastest, and can store the choice in
-a tune cache (one "key params" line per kind of matrix) that hm_build_plan
-reads when the plan is built with tune=1.
+For one device-resident matrix it times every launch candidate with the
+library's own HIP-event kernel timing and keeps the fastest; tile shapes
+change the store layout, so each shape candidate is a plan and an upload of
+its own.  The choice goes into a tune cache (one "key params" line per kind
+of matrix) that hm_build_plan reads when the plan is built with tune=1.
 """
 
 from __future__ import annotations
@@ -19,6 +21,8 @@ CANDIDATES = ["schedule=0 unroll=4 order=0 persist=0", "schedule=0 unroll=8 orde
               "schedule=1 unroll=8 order=0 persist=0", "schedule=1 unroll=8 order=0 persist=8"]
 # the batched path only depends on the row-panel order
 BATCH_CANDIDATES = ["schedule=0 unroll=8 order=0 persist=0", "schedule=0 unroll=8 order=1 persist=0"]
+# column-tile shapes (chunk rows, tile groups)
+SHAPE_CANDIDATES = [(512, 64), (256, 64), (128, 64), (512, 32), (256, 32)]
 
 
 def _time(D, step, reps: int) -> float:
@@ -45,6 +49,29 @@ def tune(D, step, candidates=CANDIDATES, reps: int = 10, warmup: int = 3):
     best = min(times, key=times.get)
     hm.hm_matrix_set_launch(D.handle, best)
     return best, times
+
+
+def tune_shape(make, step_of, launch: str, candidates=SHAPE_CANDIDATES, reps: int = 10,
+               warmup: int = 3):
+    """Time every tile shape: ``make(chunk, tile)`` builds and uploads the
+    matrix with that shape, ``step_of(D)`` returns one product of it.  Each
+    runs with the launch parameters ``launch``.  Returns (best (chunk, tile),
+    {shape: ms}); the matrices are released."""
+    import torch
+    times = {}
+    for chunk, tile in candidates:
+        D = make(chunk, tile)
+        try:
+            hm.hm_matrix_set_launch(D.handle, launch)
+            step = step_of(D)
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            times[(chunk, tile)] = _time(D, step, reps)
+        finally:
+            D.close()
+            torch.cuda.empty_cache()
+    return min(times, key=times.get), times
 
 
 def write_cache(path: str, key: str, params: str) -> None:

@@ -335,3 +335,44 @@ def test_nonsquare_random_partition():
     ref = A @ x
     assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
     hm.hm_plan_destroy(p)
+
+
+@pytest.mark.parametrize("chunk,tile", [(128, 16), (64, 8), (256, 64)])
+def test_tile_shape_options(chunk, tile, tmp_path):
+    """The column-tile shape (rows per chunk, groups per tile) changes the
+    layout but not the product: the packed store, read as its layout
+    defines it, gives the oracle's result; every tile respects the shape."""
+    H = hmgen.build_preset("sphere4k", n=16384)
+    blocks = blocks_from_table(H)
+    p = hm.hm_build_plan(H.n, H.n, blocks, hm.HM_F64, chunk_rows=chunk, tile_groups=tile)
+    info = hm.hm_plan_info(p)
+    buf = np.zeros(info["store_bytes"], np.uint8)
+    hm.hm_pack_host(p, H.a_ptr, H.b_ptr, None, buf)
+    h, T = tables(buf)
+    assert T["ct"]["nrows"].max() <= chunk and T["ct"]["ngroups"].max() <= tile
+    x = hmgen.uniform_vector(H.n)
+    ref = oracle.hmvm(H, x)
+    y = model_mvm(buf, x, np.zeros(H.n), 1.0)
+    assert np.linalg.norm(y - ref) <= 1e-13 * np.linalg.norm(ref)
+    hm.hm_plan_destroy(p)
+
+
+def test_tile_shape_from_tune_cache_and_limits(tmp_path):
+    H = hmgen.build_preset("sphere4k")
+    blocks = blocks_from_table(H)
+    for bad in ((32, 0), (1024, 0), (0, 4), (0, 65)):
+        with pytest.raises(hm.HMError) as e:
+            hm.hm_build_plan(H.n, H.n, blocks, hm.HM_F64, chunk_rows=bad[0], tile_groups=bad[1])
+        assert e.value.status == hm.HM_EINVAL
+    default = hm.hm_plan_info(p0 := hm.hm_build_plan(H.n, H.n, blocks, hm.HM_F64))["n_col_tiles"]
+    hm.hm_plan_destroy(p0)
+    # a cache line for this kind of matrix sets the shape; explicit options win
+    cache = tmp_path / "tune.txt"
+    cache.write_text("acc0-fmt1-n2^12 schedule=0 unroll=8 order=1 persist=0 chunk=128 tile=16\n")
+    p1 = hm.hm_build_plan(H.n, H.n, blocks, hm.HM_F64, tune_cache=str(cache))
+    p2 = hm.hm_build_plan(H.n, H.n, blocks, hm.HM_F64, tune_cache=str(cache), chunk_rows=128, tile_groups=16)
+    p3 = hm.hm_build_plan(H.n, H.n, blocks, hm.HM_F64, tune_cache=str(cache), chunk_rows=512, tile_groups=64)
+    n1, n2, n3 = (hm.hm_plan_info(p)["n_col_tiles"] for p in (p1, p2, p3))
+    assert n1 == n2 > default == n3
+    for p in (p1, p2, p3):
+        hm.hm_plan_destroy(p)
