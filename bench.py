@@ -195,6 +195,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1,
                     help="right-hand sides per product (> 1: hm_mvm_batch; reported separately)")
     ap.add_argument("--n", type=int, default=0, help="override the workload size (not the default line)")
+    ap.add_argument("--dtype", default=None, help="override the workload's storage (f64, f32, mixed, dfl, aplr)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner on this matrix before the timed region and store its "
                          "choice in the tune cache (default: read the cache, no tuning)")
@@ -235,8 +236,10 @@ def main():
                           "launches": max(1, args.steps)}), flush=True)
         return
     p = hmgen.preset(args.workload)
+    if args.dtype:
+        p["dtype"] = args.dtype
     log("building", args.workload, p)
-    H = hmgen.build_preset(args.workload, n=args.n or None)
+    H = hmgen.build_preset(args.workload, n=args.n or None, dtype=p["dtype"])
     st = H.stats()
     log("built in %.1fs: %s" % (H.build_seconds, st))
     mixed = p["dtype"] not in ("f64", "dfl", "aplr")   # DFL storage accumulates in FP64

@@ -252,8 +252,9 @@ hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls);
  * to y in two steps, so it differs from schedule 0 by rounding only.  Each
  * choice is deterministic.  hm_matrix_tune_key writes the key under which the
  * tuner stores the best choice for matrices of this kind (accumulation type,
- * storage formats present, size class, and whether the plan was made for
- * several right-hand sides) into buf (NUL-terminated, <= len). */
+ * storage formats present, size class, rank class = floor(log2) of the mean
+ * rank of the low-rank blocks, and whether the plan was made for several
+ * right-hand sides) into buf (NUL-terminated, <= len). */
 hm_status hm_matrix_set_launch(hm_matrix* A, const char* params);
 hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len);
 hm_status hm_matrix_tune_key(const hm_matrix* A, char* buf, size_t len);

@@ -243,6 +243,8 @@ static int64_t col_lo_offset(const ColPanelHost& Cp, const ColSectionHost& S, in
          (sc % G) * (L / G);
 }
 
+static int rank_class(const hm_plan* P);
+
 hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks, int64_t nb,
                      const hm_plan_opts* o, hm_plan** out) {
   if (!out) return fail(HM_EINVAL, "out is NULL");
@@ -271,6 +273,7 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
   }
   // launch parameters and tile shape of this kind of matrix from the tune
   // cache, then the tile shape the caller gives
+  P->rank_class = rank_class(P.get());
   if (opts.tune && !P->tune_path.empty()) read_tune_cache(P.get());
   if (opts.chunk_rows < 0 || opts.tile_groups < 0) return fail(HM_EINVAL, "negative tile shape");
   P->chunk_rows = opts.chunk_rows ? opts.chunk_rows : P->launch.chunk ? P->launch.chunk : kSegRows;
@@ -590,19 +593,35 @@ static bool parse_launch(const char* text, LaunchParams& lp) {
 }
 
 // Kind of matrix a tuned choice applies to: accumulation type, storage
-// formats present, size class, and "-batch" for plans made for several
-// right-hand sides (their products run the multi-right-hand-side kernels).
-static std::string tune_key_mask(int acc, int mask, int64_t n_rows, int max_nrhs) {
+// formats present, size class, rank class (floor(log2) of the mean rank of
+// the low-rank blocks), and "-batch" for plans made for several right-hand
+// sides (their products run the multi-right-hand-side kernels).
+static std::string tune_key_mask(int acc, int mask, int64_t n_rows, int rank_class, int max_nrhs) {
   int lg = 0;
   while ((int64_t(1) << (lg + 1)) <= n_rows) ++lg;
   char buf[64];
-  std::snprintf(buf, sizeof buf, "acc%d-fmt%d-n2^%d%s", acc, mask, lg, max_nrhs > 1 ? "-batch" : "");
+  std::snprintf(buf, sizeof buf, "acc%d-fmt%d-n2^%d-r%d%s", acc, mask, lg, rank_class,
+                max_nrhs > 1 ? "-batch" : "");
   return buf;
 }
-static std::string tune_key(int acc, const size_t* bytes_by_dtype, int64_t n_rows, int max_nrhs) {
+static std::string tune_key(int acc, const size_t* bytes_by_dtype, int64_t n_rows, int rank_class,
+                            int max_nrhs) {
   int mask = 0;
   for (int d = 0; d < kNumDtypes; ++d) if (bytes_by_dtype[d]) mask |= 1 << d;
-  return tune_key_mask(acc, mask, n_rows, max_nrhs);
+  return tune_key_mask(acc, mask, n_rows, rank_class, max_nrhs);
+}
+
+// floor(log2) of the mean rank of the low-rank blocks of nonzero rank (0
+// when there are none).
+static int rank_class(const hm_plan* P) {
+  double sum = 0;
+  int64_t cnt = 0;
+  for (auto& b : P->blocks)
+    if (b.kind == HM_LOWRANK && b.rank > 0) { sum += b.rank; ++cnt; }
+  int c = 0;
+  if (cnt > 0)
+    while (std::ldexp(1.0, c + 1) <= sum / (double)cnt) ++c;
+  return c;
 }
 
 // The formats a plan's blocks store values in (the formats with stored
@@ -621,7 +640,8 @@ static int format_mask(const hm_plan* P) {
 void read_tune_cache(hm_plan* P) {
   FILE* f = std::fopen(P->tune_path.c_str(), "r");
   if (!f) return;
-  const std::string key = tune_key_mask(P->opts.acc_dtype, format_mask(P), P->n_rows, P->opts.max_nrhs);
+  const std::string key =
+      tune_key_mask(P->opts.acc_dtype, format_mask(P), P->n_rows, P->rank_class, P->opts.max_nrhs);
   char line[512];
   while (std::fgets(line, sizeof line, f)) {
     std::string l(line);
@@ -1265,6 +1285,7 @@ hm_status hm_upload(const hm_plan* p, const double* const* a, const double* cons
   M->acc_dtype = p->opts.acc_dtype;
   M->max_nrhs = p->opts.max_nrhs;
   M->launch = p->launch;
+  M->rank_class = p->rank_class;
   M->device = dev;
   M->n_cu = ncu;
   std::memcpy(M->bytes_by_dtype, p->bytes_by_dtype, sizeof M->bytes_by_dtype);
@@ -1447,7 +1468,7 @@ hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len) {
 hm_status hm_matrix_tune_key(const hm_matrix* A, char* buf, size_t len) {
   if (!A || !buf || len == 0) return fail(HM_EINVAL, "NULL argument");
   std::snprintf(buf, len, "%s",
-                tune_key(A->acc_dtype, A->bytes_by_dtype, A->hdr.n_rows, A->max_nrhs).c_str());
+                tune_key(A->acc_dtype, A->bytes_by_dtype, A->hdr.n_rows, A->rank_class, A->max_nrhs).c_str());
   return ok();
 }
 

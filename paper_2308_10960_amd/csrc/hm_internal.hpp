@@ -100,6 +100,7 @@ struct hm_plan {
   int32_t has_sigma = 0;
   hm::StoreHeader hdr{};
   int32_t chunk_rows = hm::kSegRows, tile_groups = hm::kTileGroups;   // column-tile shape
+  int32_t rank_class = 0;                 // floor(log2) of the mean low-rank rank (tune key)
   size_t store_bytes = 0, meta_bytes = 0, work_bytes_per_rhs = 0;
   int64_t work_part_off = 0, work_t_off = 0;
   int64_t work_part_bytes = 0, work_t_bytes = 0, work_x_bytes = 0;
@@ -127,6 +128,7 @@ struct hm_matrix {
   int64_t work_part_bytes = 0, work_t_bytes = 0, work_x_bytes = 0;
   int32_t acc_dtype = 0, max_nrhs = 1;
   int32_t device = 0, n_cu = 256;       // device of the store and its compute units
+  int32_t rank_class = 0;               // of its plan (tune key)
   hm::LaunchParams launch;
   size_t bytes_by_dtype[hm::kNumDtypes] = {};
 };

@@ -22,7 +22,7 @@ CANDIDATES = ["schedule=0 unroll=4 order=0 persist=0", "schedule=0 unroll=8 orde
 # the batched path only depends on the row-panel order
 BATCH_CANDIDATES = ["schedule=0 unroll=8 order=0 persist=0", "schedule=0 unroll=8 order=1 persist=0"]
 # column-tile shapes (chunk rows, tile groups)
-SHAPE_CANDIDATES = [(512, 64), (256, 64), (128, 64), (512, 32), (256, 32)]
+SHAPE_CANDIDATES = [(512, 64), (256, 64), (128, 64), (64, 64), (512, 32), (256, 32)]
 
 
 def _time(D, step, reps: int) -> float:

@@ -368,7 +368,10 @@ def test_tile_shape_from_tune_cache_and_limits(tmp_path):
     hm.hm_plan_destroy(p0)
     # a cache line for this kind of matrix sets the shape; explicit options win
     cache = tmp_path / "tune.txt"
-    cache.write_text("acc0-fmt1-n2^12 schedule=0 unroll=8 order=1 persist=0 chunk=128 tile=16\n")
+    # key: FP64 accumulation, FP64 storage, n = 2^12, rank class = floor(log2 mean rank)
+    lr = (H.adm != 0) & (H.rank > 0)
+    rc = int(np.floor(np.log2(H.rank[lr].mean())))
+    cache.write_text(f"acc0-fmt1-n2^12-r{rc} schedule=0 unroll=8 order=1 persist=0 chunk=128 tile=16\n")
     p1 = hm.hm_build_plan(H.n, H.n, blocks, hm.HM_F64, tune_cache=str(cache))
     p2 = hm.hm_build_plan(H.n, H.n, blocks, hm.HM_F64, tune_cache=str(cache), chunk_rows=128, tile_groups=16)
     p3 = hm.hm_build_plan(H.n, H.n, blocks, hm.HM_F64, tune_cache=str(cache), chunk_rows=512, tile_groups=64)
