@@ -176,3 +176,70 @@ def test_dfl_full_size(name):
     eps = hmgen.preset(name)["eps"]
     assert rel_truth <= eps
     D.close()
+
+
+def _random_layout(seed):
+    """Random per-group formats (all nine with FP64 accumulation, the 16/32-bit
+    IEEE ones with FP32) and a random column-tile shape, n = 16384."""
+    rng = np.random.default_rng(seed)
+    H = hmgen.build_preset("sphere4k_mixed", n=16384)
+    acc = hm.HM_F64 if seed % 2 else hm.HM_F32
+    fmts = ([hm.HM_F64, hm.HM_F32, hm.HM_F16, hm.HM_BF16, hm.HM_DFL16, hm.HM_DFL24, hm.HM_DFL32,
+             hm.HM_DFL40, hm.HM_DFL48] if acc == hm.HM_F64 else [hm.HM_F32, hm.HM_F16, hm.HM_BF16])
+    H.set_uniform_dtype(fmts[0])
+    for i in range(H.nblocks):
+        if not H.adm[i]:
+            H.group_dtype[i, 0] = fmts[rng.integers(len(fmts))]
+            continue
+        k = int(H.rank[i])
+        if k == 0:
+            continue
+        ng = int(rng.integers(1, min(4, k) + 1))
+        cuts = np.sort(rng.choice(np.arange(1, k), ng - 1, replace=False)) if ng > 1 else np.array([], int)
+        sizes = np.diff(np.concatenate([[0], cuts, [k]]))
+        H.ngroups[i] = ng
+        H.group_cols[i, :] = 0
+        H.group_cols[i, :ng] = sizes
+        H.group_dtype[i, :] = 0
+        H.group_dtype[i, :ng] = [fmts[j] for j in rng.integers(len(fmts), size=ng)]
+    return H, acc, int(rng.integers(64, 513)), int(rng.integers(8, 65))
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_random_layouts(seed):
+    """The kernels on random format mixes and tile shapes: FP64 accumulation
+    to the FP64 bar against the oracle on the rounded factors, both
+    schedules; FP32 accumulation within the rigorous FP32 bound, single and
+    batched (32 right-hand sides)."""
+    from test_gpu_parity import fp32_depth
+    H, acc, chunk, tile = _random_layout(seed)
+    say("seed", seed, "acc", acc, "chunk", chunk, "tile", tile)
+    D = DeviceHMatrix(H, acc, max_nrhs=32 if acc == hm.HM_F32 else 1, chunk_rows=chunk, tile_groups=tile)
+    x = hmgen.uniform_vector(H.n)
+    if acc == hm.HM_F32:
+        x = x.astype(np.float32).astype(np.float64)
+    dec = oracle.decoded_factors(H, sigma_dtype=oracle.F64 if acc == hm.HM_F64 else oracle.F32)
+    ref = oracle.hmvm(H, x, factors=dec)
+    scale = abs_bound(H, x, dec)
+    if acc == hm.HM_F64:
+        for sched in (0, 1):
+            hm.hm_matrix_set_launch(D.handle, f"schedule={sched}")
+            check(run(D, x), ref, scale, f"random seed {seed} schedule {sched}")
+    else:
+        K = fp32_depth(H)
+        gam = K * 2.0 ** -24 / (1 - K * 2.0 ** -24)
+        y = run(D, x)
+        assert np.all(np.abs(y - ref) <= gam * scale)
+        R = 32
+        X = np.stack([hmgen.uniform_vector(H.n, seed=40 + j).astype(np.float32) for j in range(R)])
+        Xd = torch.from_numpy(X).cuda()
+        Yd = torch.zeros_like(Xd)
+        hm.hm_mvm_batch(D.handle, R, 1.0, Xd, H.n, Yd, H.n, D.work, D.work.numel())
+        torch.cuda.synchronize()
+        Y = Yd.cpu().numpy().astype(np.float64)
+        for j in (0, 17, 31):
+            xj = X[j].astype(np.float64)
+            rj = oracle.hmvm(H, xj, factors=dec)
+            assert np.all(np.abs(Y[j] - rj) <= gam * abs_bound(H, xj, dec)), j
+        say(f"random seed {seed}: FP32 single and batched within gamma_K")
+    D.close()

@@ -379,3 +379,37 @@ def test_tile_shape_from_tune_cache_and_limits(tmp_path):
     assert n1 == n2 > default == n3
     for p in (p1, p2, p3):
         hm.hm_plan_destroy(p)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_random_layouts_match_oracle(seed):
+    """Random tile shapes with random per-group formats (all nine with FP64
+    accumulation; the 16/32-bit IEEE formats with FP32 accumulation), over
+    several column chunks: the packed store, read as its layout defines it,
+    gives the oracle's product on the rounded factors, and every tile keeps
+    the descriptor's limits."""
+    rng = np.random.default_rng(seed)
+    H = hmgen.build_preset("sphere4k_mixed", n=16384)
+    chunk, tile = int(rng.integers(64, 513)), int(rng.integers(8, 65))
+    acc = hm.HM_F64 if seed % 2 else hm.HM_F32
+    fmts = ([hm.HM_F64, hm.HM_F32, hm.HM_F16, hm.HM_BF16, hm.HM_DFL16, hm.HM_DFL24, hm.HM_DFL32,
+             hm.HM_DFL40, hm.HM_DFL48] if acc == hm.HM_F64 else [hm.HM_F32, hm.HM_F16, hm.HM_BF16])
+    _aplr_like(H, fmts, seed=seed)
+    blocks = blocks_from_table(H)
+    p = hm.hm_build_plan(H.n, H.n, blocks, acc, chunk_rows=chunk, tile_groups=tile)
+    info = hm.hm_plan_info(p)
+    buf = np.zeros(info["store_bytes"], np.uint8)
+    hm.hm_pack_host(p, H.a_ptr, H.b_ptr, H.s_ptr, buf)
+    h, T = tables(buf)
+    ct = T["ct"]
+    assert ct["nrows"].max() <= chunk and ct["ngroups"].max() <= tile
+    assert np.all(ct["end"][:, 3] == ct["ngroups"])
+    assert info["n_partials"] > 0
+    x = hmgen.uniform_vector(H.n)
+    if acc == hm.HM_F32:
+        x = x.astype(np.float32).astype(np.float64)
+    sig = oracle.F64 if acc == hm.HM_F64 else oracle.F32
+    ref = oracle.hmvm(H, x, factors=oracle.decoded_factors(H, sigma_dtype=sig))
+    y = model_mvm(buf, x, np.zeros(H.n), 1.0)
+    assert np.linalg.norm(y - ref) <= 1e-13 * np.linalg.norm(ref)
+    hm.hm_plan_destroy(p)
