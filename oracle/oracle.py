@@ -9,7 +9,10 @@ directly from FP64:
   FP32 and FP16 use numpy's own conversions (correctly rounded from double);
   BF16 (1-8-7, Table 1) is rounded here from its definition;
   DFL (Sec. 3.2: FP64's sign and 11 exponent bits, the mantissa cut to make
-  a whole number of bytes) is rounded here from its definition.
+  a whole number of bytes) is rounded here from its definition;
+  AFLP (Sec. 3.2: per data block, values scaled and shifted by 1, only the
+  exponent bits the block's range needs, the mantissa filling the bytes)
+  is rounded here from its definition, one data block per call.
 Parity pins for every function live in tests/test_oracle_*.py.
 """
 
@@ -30,6 +33,8 @@ _lib = None
 F64, F32, F16, BF16 = 0, 1, 2, 3
 DFL32, DFL40, DFL48, DFL16, DFL24 = 4, 5, 6, 7, 8
 DFL_BYTES = {DFL32: 4, DFL40: 5, DFL48: 6, DFL16: 2, DFL24: 3}
+AFLP16, AFLP24, AFLP32, AFLP40, AFLP48 = 9, 10, 11, 12, 13
+AFLP_BYTES = {AFLP16: 2, AFLP24: 3, AFLP32: 4, AFLP40: 5, AFLP48: 6}
 
 # Table 1: unit roundoff u = 2^-(m+1) for m explicit mantissa bits.
 UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "tf32": 2.0 ** -11,
@@ -112,11 +117,71 @@ def round_dfl(x, nbytes: int) -> np.ndarray:
     return out
 
 
+def _rne_bits(d: np.ndarray, m: int) -> np.ndarray:
+    """RNE of positive normal FP64 values to m explicit mantissa bits."""
+    _, e = np.frexp(d)                           # d = f 2^e, f in [0.5, 1)
+    lsb = e - 1 - m
+    return np.ldexp(np.rint(np.ldexp(d, -lsb)), lsb)
+
+
+def aflp_params(x, nbytes: int):
+    """(k, e, m) of one AFLP data block of nbytes-byte values (Sec. 3.2).
+
+    The block's nonzero magnitudes are scaled by 2^-k (2^k the power of two
+    at or below the smallest of them) and shifted by 1, so they lie in
+    [2, 2R + 1) with R = largest / smallest.  The exponent field holds the
+    binary exponent j >= 1 of such a value; j = 0, the binade [1, 2), is
+    the code of zero.  e is the fewest bits whose 2^e exponents hold every
+    rounded value of the block, and m = 8 nbytes - 1 - e explicit mantissa
+    bits fill the bytes.  A block without nonzeros gives
+    (0, 0, 8 nbytes - 1).  Raises ValueError for values that are not finite
+    or a range that needs more than 10 exponent bits.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    if not np.all(np.isfinite(x)):
+        raise ValueError("AFLP: values must be finite")
+    a = np.abs(x[x != 0])
+    if a.size == 0:
+        return 0, 0, 8 * nbytes - 1
+    k = int(np.frexp(a.min())[1]) - 1            # 2^k <= min < 2^(k+1)
+    with np.errstate(over="ignore"):
+        dmax = np.ldexp(a.max(), -k) + 1.0
+    if not np.isfinite(dmax):
+        raise ValueError("AFLP: dynamic range too large")
+    top = int(np.frexp(dmax)[1]) - 1             # exponent of the largest shifted value (>= 1)
+    e = top.bit_length()                         # buckets 0 .. top need e bits
+    while True:
+        m = 8 * nbytes - 1 - e
+        if e > 10 or m < 1:
+            raise ValueError(f"AFLP: a range of 2^{top} does not fit {nbytes} bytes")
+        top_r = int(np.frexp(_rne_bits(np.array([dmax]), m)[0])[1]) - 1
+        if top_r < 2 ** e:                       # rounding up may open the next bucket
+            return k, e, m
+        e += 1
+
+
+def round_aflp(x, nbytes: int) -> np.ndarray:
+    """AFLP rounding of one data block x (any shape) to nbytes-byte values
+    (Sec. 3.2): d = |v| 2^-k + 1 rounded to nearest even with m explicit
+    mantissa bits (k, m from aflp_params), stored value sign(v) (d - 1) 2^k;
+    zeros stay zero."""
+    x = np.asarray(x, dtype=np.float64)
+    k, e, m = aflp_params(x, nbytes)
+    out = np.zeros_like(x)
+    nz = x != 0
+    d = np.ldexp(np.abs(x[nz]), -k) + 1.0
+    out[nz] = np.copysign(np.ldexp(_rne_bits(d, m) - 1.0, k), x[nz])
+    return out
+
+
 def round_to(x, dt: int) -> np.ndarray:
+    """x rounded to storage format dt (for AFLP, x is one data block)."""
     if dt == F64:
         return np.asarray(x, dtype=np.float64)
     if dt in DFL_BYTES:
         return round_dfl(x, DFL_BYTES[dt])
+    if dt in AFLP_BYTES:
+        return round_aflp(x, AFLP_BYTES[dt])
     if dt == F32:
         return round_f32(x)
     if dt == F16:

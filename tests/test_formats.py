@@ -181,3 +181,111 @@ def test_dfl_format_choice():
         # the kept mantissa's unit roundoff meets eps / 2
         assert 2.0 ** -(8 * nbytes - 12 + 1) <= eps / 2
     assert hmgen.dfl_format(1e-12) == oracle.F64                 # 7 bytes: FP64 instead
+
+
+# ------------------------------------------------------------------ AFLP (Sec. 3.2)
+
+def test_aflp_worked_examples():
+    """Exponent bits by hand: values shifted to d = |v| / 2^k + 1; the
+    exponent field spans the binary exponents 0 .. top of d (0 is zero's
+    code), so e = bit length of top, unless rounding the largest d opens
+    the next binade."""
+    p = lambda v, nb: oracle.aflp_params(np.array(v, dtype=float), nb)
+    assert p([1.0, 6.0], 3) == (0, 2, 21)            # d in [2, 7]: top 2
+    assert p([1.0, 7.0], 3) == (0, 2, 21)            # d = 8: top 3 still fits two bits
+    assert p([1.0, 15.0], 3) == (0, 3, 20)           # d = 16: top 4 needs three
+    assert p([1.0, 1000.0], 3) == (0, 4, 19)         # d = 1001: top 9
+    assert p([-3.0, 0.75, 0.0], 4) == (-1, 2, 29)    # 2^-1 <= 0.75; d = 3 / 0.5 + 1 = 7; zero ignored
+    # rounding the largest value up opens a binade: d = 15.9999 needs 16 at
+    # 13 mantissa bits (spacing 2^-10), so one more exponent bit
+    assert p([1.0, 14.9999], 2) == (0, 3, 12)
+    assert p([1.0, 14.99], 2) == (0, 2, 13)          # 15.99 stays below 16
+    # the same value decoded: d rounds to 16 at 12 bits, v = (16 - 1) 2^0
+    assert oracle.round_aflp(np.array([1.0, 14.9999]), 2)[1] == 15.0
+    assert p([0.0, -0.0], 2) == (0, 0, 15)           # no nonzeros
+    assert p([3.0], 4) == (1, 1, 30)                 # one value: d = 2.5
+
+
+@pytest.mark.parametrize("nbytes", [2, 3, 4, 5, 6])
+def test_aflp_unit_binade_is_fixed_point(nbytes):
+    """Special case in closed form: a block whose magnitudes lie in [1, 2)
+    has k = 0, e = 1 and m = 8 nbytes - 2, and AFLP rounding is then
+    rounding to the fixed-point grid of step 2^-(m-1), ties to even.
+    The inputs lie on FP64's grid at 2 (multiples of 2^-51), so d = |v| + 1
+    is exact."""
+    rng = np.random.default_rng(nbytes)
+    m = 8 * nbytes - 2
+    q = rng.integers(0, 2 ** 51, 4000)
+    mag = 1.0 + q.astype(np.float64) * 2.0 ** -51
+    mag = np.concatenate([[1.0], mag[mag < 1.75]])
+    # exact ties on the step 2^-(m-1): odd and even neighbours
+    t = rng.integers(2 ** (m - 1), int(1.7 * 2 ** (m - 1)), 300)
+    mag = np.concatenate([mag, (t + 0.5) * 2.0 ** -(m - 1)])
+    x = mag * rng.choice([-1.0, 1.0], mag.size)
+    assert oracle.aflp_params(x, nbytes) == (0, 1, m)
+    want = np.copysign(np.rint(mag * 2.0 ** (m - 1)) * 2.0 ** -(m - 1), x)
+    np.testing.assert_array_equal(oracle.round_aflp(x, nbytes), want)
+
+
+def _aflp_block(rng, n, decades):
+    """Signed values with magnitudes log-uniform over `decades` decades,
+    a few exact zeros."""
+    x = rng.choice([-1.0, 1.0], n) * 10.0 ** rng.uniform(-decades, 0, n) * 10.0 ** rng.uniform(-5, 5)
+    x[rng.integers(0, n, 3)] = 0.0
+    return x
+
+
+@pytest.mark.parametrize("nbytes", [2, 3, 4, 5, 6])
+def test_aflp_error_bound_and_layout(nbytes):
+    """|v - fl(v)| <= (2^-(m+1) + 2^-52) (|v| + 2^k) with 2^k at or below the
+    smallest nonzero magnitude; 1 + e + m fills the bytes; zeros stay zero,
+    signs are kept; e is the fewest bits: with e - 1 of them the largest
+    rounded value falls outside the field."""
+    rng = np.random.default_rng(100 + nbytes)
+    for decades in (0.5, 3, 12, 60):
+        x = _aflp_block(rng, 3000, decades)
+        k, e, m = oracle.aflp_params(x, nbytes)
+        assert 1 + e + m == 8 * nbytes
+        nzm = np.abs(x[x != 0]).min()
+        assert 2.0 ** k <= nzm < 2.0 ** (k + 1)
+        r = oracle.round_aflp(x, nbytes)
+        assert np.all(r[x == 0] == 0)
+        assert np.all(np.sign(r) == np.sign(x))
+        bound = (2.0 ** -(m + 1) + 2.0 ** -52) * (np.abs(x) + 2.0 ** k)
+        assert np.all(np.abs(r - x) <= bound)
+        np.testing.assert_array_equal(oracle.round_aflp(-x, nbytes), -r)
+        # minimality of e, from Python floats: the largest shifted value
+        # rounded to m + 1 mantissa bits has binary exponent >= 2^(e-1)
+        if e >= 1:
+            import math
+            dmax = math.ldexp(float(np.abs(x).max()), -k) + 1.0
+            f, ex = math.frexp(dmax)
+            dr = math.ldexp(round(math.ldexp(f, m + 2)), ex - m - 2)
+            assert math.frexp(dr)[1] - 1 >= 2 ** (e - 1)
+
+
+def test_aflp_nearest_code_brute_force():
+    """Every rounded value is a code of the block's format and is the code
+    nearest to the input (all 2^15 magnitudes of a 2-byte format listed)."""
+    rng = np.random.default_rng(5)
+    for decades in (1, 4, 9):
+        x = _aflp_block(rng, 1500, decades)
+        k, e, m = oracle.aflp_params(x, 2)
+        j = np.arange(1, 2 ** e, dtype=np.float64)[:, None]
+        f = np.arange(2 ** m, dtype=np.float64)[None, :]
+        codes = np.sort(np.concatenate([[0.0], ((2.0 ** j * (1 + f * 2.0 ** -m) - 1) * 2.0 ** k).ravel()]))
+        r = np.abs(oracle.round_aflp(x, 2))
+        a = np.abs(x)
+        pos = np.searchsorted(codes, r)
+        assert np.all(codes[np.minimum(pos, codes.size - 1)] == r)
+        i = np.clip(np.searchsorted(codes, a), 1, codes.size - 1)
+        best = np.minimum(np.abs(codes[i] - a), np.abs(codes[i - 1] - a))
+        assert np.all(np.abs(r - a) <= best + 2.0 ** -52 * (a + 2.0 ** k))
+
+
+def test_aflp_rejects_unrepresentable_blocks():
+    with pytest.raises(ValueError):
+        oracle.aflp_params(np.array([1.0, np.inf]), 4)
+    with pytest.raises(ValueError):
+        oracle.aflp_params(np.array([1e-300, 1e300]), 4)      # shifted range overflows
+    np.testing.assert_array_equal(oracle.round_aflp(np.zeros(5), 3), np.zeros(5))
