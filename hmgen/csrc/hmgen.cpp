@@ -457,6 +457,36 @@ int dt_bytes(int dt) {
   return dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : 2;
 }
 
+// Explicit mantissa bits an AFLP data block of nbytes-byte values keeps
+// (Sec. 3.2): values scaled by the power of two 2^k at or below the smallest
+// nonzero magnitude and shifted by 1 (d = |v| 2^-k + 1 >= 2); the exponent
+// field takes the fewest bits e that hold the binary exponent of every
+// rounded d, the mantissa the rest of the bytes, 8 nbytes - 1 - e.  -1 when
+// no e <= 10 fits.
+int aflp_mantissa(const double* v, size_t n, int nbytes) {
+  double mn = HUGE_VAL, mx = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const double a = std::fabs(v[i]);
+    if (a > 0) { mn = std::min(mn, a); mx = std::max(mx, a); }
+  }
+  if (mx == 0) return 8 * nbytes - 1;
+  const int k = std::ilogb(mn);                      // 2^k <= mn < 2^(k+1)
+  const double dmax = std::ldexp(mx, -k) + 1.0;
+  if (!std::isfinite(dmax)) return -1;
+  const int top = std::ilogb(dmax);
+  int e = 0;
+  while ((1 << e) <= top) ++e;
+  for (; e <= 10; ++e) {
+    const int m = 8 * nbytes - 1 - e;
+    if (m < 1) return -1;
+    // dmax rounded to m mantissa bits (nearest, ties to even)
+    const double q = std::ldexp(dmax, m - top);
+    double r = std::nearbyint(q);
+    if (std::ilogb(std::ldexp(r, top - m)) < (1 << e)) return m;
+  }
+  return -1;
+}
+
 }  // namespace
 
 // ====================================================================== C API
@@ -724,6 +754,34 @@ int hmg_select_precision(const hmg_tree* t, double tol, int32_t allow_f64, int32
 // singular values, and the narrowest groups are widened until at most 4
 // remain.  err_bound: the sum of the exact column errors (a bound by the
 // triangle inequality).
+// AFLP storage per block (one format for all its columns): the fewest bytes
+// B in 2 .. 6 whose AFLP mantissa reaches mant_bits for every data block of
+// the block (D_b; U_b and V_b share B), as AFLP16 ... AFLP48 (9 .. 13); FP64
+// where no B does.  Returns the number of blocks left in FP64.
+int hmg_select_aflp(const hmg_tree* t, int mant_bits, int32_t* ngroups, int32_t* group_cols,
+                    int32_t* group_dtype) {
+  const int64_t nb = (int64_t)t->blocks.size();
+  std::atomic<int> f64{0};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t bi = 0; bi < nb; ++bi) {
+    const Block& b = t->blocks[bi];
+    int32_t* gc = &group_cols[4 * bi];
+    int32_t* gd = &group_dtype[4 * bi];
+    for (int q = 0; q < 4; ++q) { gc[q] = 0; gd[q] = 0; }
+    ngroups[bi] = 1;
+    gc[0] = b.adm ? b.rank : 0;
+    int chosen = DT_F64;
+    for (int B = 2; B <= 6; ++B) {
+      bool fits = aflp_mantissa(b.a.data(), b.a.size(), B) >= mant_bits;
+      if (fits && b.adm) fits = aflp_mantissa(b.b.data(), b.b.size(), B) >= mant_bits;
+      if (fits) { chosen = 9 + (B - 2); break; }
+    }
+    if (chosen == DT_F64) f64.fetch_add(1);
+    gd[0] = chosen;
+  }
+  return f64.load();
+}
+
 int hmg_select_precision_dfl(const hmg_tree* t, double tol, int32_t* ngroups, int32_t* group_cols,
                              int32_t* group_dtype, double* err_bound) {
   static const int kWidth[6] = {DT_DFL16, DT_DFL24, DT_DFL32, DT_DFL40, DT_DFL48, DT_F64};

@@ -18,10 +18,13 @@ from .geometry import mean_nn_distance
 
 DT_F64, DT_F32, DT_F16, DT_BF16 = 0, 1, 2, 3
 DT_DFL32, DT_DFL40, DT_DFL48, DT_DFL16, DT_DFL24 = 4, 5, 6, 7, 8
+DT_AFLP16, DT_AFLP24, DT_AFLP32, DT_AFLP40, DT_AFLP48 = 9, 10, 11, 12, 13
 DT_BYTES = {DT_F64: 8, DT_F32: 4, DT_F16: 2, DT_BF16: 2, DT_DFL32: 4, DT_DFL40: 5, DT_DFL48: 6,
-            DT_DFL16: 2, DT_DFL24: 3}
+            DT_DFL16: 2, DT_DFL24: 3, DT_AFLP16: 2, DT_AFLP24: 3, DT_AFLP32: 4, DT_AFLP40: 5, DT_AFLP48: 6}
 DT_NAMES = {DT_F64: "f64", DT_F32: "f32", DT_F16: "f16", DT_BF16: "bf16",
-            DT_DFL32: "dfl32", DT_DFL40: "dfl40", DT_DFL48: "dfl48", DT_DFL16: "dfl16", DT_DFL24: "dfl24"}
+            DT_DFL32: "dfl32", DT_DFL40: "dfl40", DT_DFL48: "dfl48", DT_DFL16: "dfl16", DT_DFL24: "dfl24",
+            DT_AFLP16: "aflp16", DT_AFLP24: "aflp24", DT_AFLP32: "aflp32", DT_AFLP40: "aflp40",
+            DT_AFLP48: "aflp48"}
 
 
 def dfl_mantissa_bits(eps: float) -> int:
@@ -84,6 +87,8 @@ def lib():
     L.hmg_select_precision.restype = C.c_int
     L.hmg_select_precision_dfl.argtypes = [vp, C.c_double, _i32p, _i32p, _i32p, _f64p]
     L.hmg_select_precision_dfl.restype = C.c_int
+    L.hmg_select_aflp.argtypes = [vp, C.c_int, _i32p, _i32p, _i32p]
+    L.hmg_select_aflp.restype = C.c_int
     L.hmg_round.argtypes = [_f64p, C.c_int64, C.c_int32, _f64p]
     L.hmg_truncate.argtypes = [_f64p, _f64p, C.c_int64, C.c_int64, C.c_int32, C.c_double,
                                _f64p, _f64p, _f64p]
@@ -197,6 +202,18 @@ class HMatrix:
             C.c_void_p(self.handle), tol, self.ngroups,
             self.group_cols.reshape(-1), self.group_dtype.reshape(-1), self.store_err_bound)
         return int(bad)
+
+    def select_aflp(self, eps: float) -> int:
+        """AFLP storage (Sec. 3.2) per block: the fewest bytes whose AFLP
+        mantissa keeps m_eps = dfl_mantissa_bits(eps) bits for every data
+        block of the block (see hmg_select_aflp).  Returns the number of
+        blocks left in FP64."""
+        nb = self.nblocks
+        self.ngroups = np.zeros(nb, np.int32)
+        self.group_cols = np.zeros((nb, 4), np.int32)
+        self.group_dtype = np.zeros((nb, 4), np.int32)
+        return int(lib().hmg_select_aflp(C.c_void_p(self.handle), dfl_mantissa_bits(eps), self.ngroups,
+                                         self.group_cols.reshape(-1), self.group_dtype.reshape(-1)))
 
     def set_uniform_dtype(self, dt: int) -> None:
         """Store every block (all columns) in one format."""

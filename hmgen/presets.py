@@ -40,6 +40,11 @@ PRESETS = {
     "sphere256k_aplr": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-6, dtype="aplr"),
     "sphere256k_e8_aplr": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-8, dtype="aplr"),
     "sphere4k_aplr": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-8, dtype="aplr"),
+    # adaptive-exponent byte-aligned storage (AFLP, Sec. 3.2) per block,
+    # FP64 accumulation: the fewest bytes keeping m_eps mantissa bits
+    "sphere256k_aflp": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-6, dtype="aflp"),
+    "sphere256k_e8_aflp": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-8, dtype="aflp"),
+    "sphere4k_aflp": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-6, dtype="aflp"),
 }
 
 SEED_POINTS, SEED_X, SEED_RHS, SEED_REQUESTS = 0, 1, 2, 3
@@ -77,6 +82,8 @@ def build_preset(name: str, *, n: int | None = None, eps: float | None = None,
         H.select_precision_dfl(eps / 2)
     elif dtype == "dfl":
         H.set_uniform_dtype(dfl_format(eps))
+    elif dtype == "aflp":
+        H.select_aflp(eps)
     else:
         H.set_uniform_dtype(DT_F64 if dtype == "f64" else DT_F32)
     H.dtype_mode = dtype

@@ -57,12 +57,22 @@ typedef int32_t hm_status;
  * exponent bits of FP64 (DFL, Sec. 3.2): the leading 2, 3, 4, 5 or 6 bytes
  * of the FP64 encoding (sign, exponent, 4 / 12 / 20 / 28 / 36 mantissa
  * bits), rounded to nearest even from FP64; they decode exactly to FP64.
+ * AFLP16 ... AFLP48: the byte-aligned adaptive formats of Sec. 3.2 in 2 ..
+ * 6 bytes, per data block (a dense block, or the columns of one column
+ * group of U_b, or of V_b): values scaled by 2^-k (2^k the power of two at
+ * or below the block's smallest nonzero magnitude) and shifted by 1, so
+ * d = |v| 2^-k + 1 >= 2; the code holds the sign, the e exponent bits the
+ * block's range of d needs (its binary exponents 1 .. 2^e - 1; 0 codes
+ * zero) and 8 B - 1 - e mantissa bits of d rounded to nearest even; the
+ * stored value sign(v) (d - 1) 2^k.  hm_upload derives k and e from the
+ * data.  The DFL and AFLP formats need HM_F64 accumulation.
  * The number of formats is HM_NUM_DTYPES. */
 typedef enum {
   HM_F64 = 0, HM_F32 = 1, HM_F16 = 2, HM_BF16 = 3,
-  HM_DFL32 = 4, HM_DFL40 = 5, HM_DFL48 = 6, HM_DFL16 = 7, HM_DFL24 = 8
+  HM_DFL32 = 4, HM_DFL40 = 5, HM_DFL48 = 6, HM_DFL16 = 7, HM_DFL24 = 8,
+  HM_AFLP16 = 9, HM_AFLP24 = 10, HM_AFLP32 = 11, HM_AFLP40 = 12, HM_AFLP48 = 13
 } hm_dtype;
-#define HM_NUM_DTYPES 9
+#define HM_NUM_DTYPES 14
 typedef enum { HM_DENSE = 0, HM_LOWRANK = 1 } hm_kind;
 
 /* One leaf block b = tau x sigma of the block tree (Sec. 2.1).
@@ -83,7 +93,7 @@ typedef struct {
 /* acc_dtype: HM_F64 or HM_F32, the accumulation type of every sum.
  * vec_dtype: must equal acc_dtype (x, y, X, Y are stored in it).
  * Storage dtypes allowed: any with HM_F64 accumulation; F32/F16/BF16 with
- * HM_F32 accumulation (DFL formats need HM_F64 accumulation).
+ * HM_F32 accumulation (DFL and AFLP formats need HM_F64 accumulation).
  * max_nrhs: largest nrhs passed to hm_mvm_batch (>= 1); sizes the workspace.
  * tune: 0 = built-in launch parameters; 1 = read tune_cache, a text file
  * written by the tuner with one "key params" line per kind of matrix (see
@@ -145,7 +155,9 @@ void hm_plan_destroy(hm_plan* p);
  * little-endian 32-bit word) or 2 bytes (DFL16 / 24: a 16-bit word); for
  * DFL40 / DFL48 / DFL24 its remaining 1 / 2 / 1 bytes (bits 31..24 /
  * 31..16 / 47..40 of the FP64 encoding) are at lo_offset, else lo_offset =
- * 0.  lo_offset may be NULL.  For tests of the packing and conversion done by hm_upload. */
+ * 0.  AFLP values sit like the DFL values of the same byte count (their
+ * left-aligned code in place of the FP64 encoding).  lo_offset may be NULL.
+ * For tests of the packing and conversion done by hm_upload. */
 hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t i, int64_t j,
                          size_t* byte_offset, int32_t* dtype, size_t* lo_offset);
 
@@ -161,7 +173,9 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
  * overrides) through two pinned host buffers, so the host memory used
  * beyond the caller's factors is the descriptor tables plus two windows.
  * Converting each block after assembly follows Sec. 5.3.  Errors: HM_EINVAL
- * (NULL or missing factor pointers, alignment), HM_ENOMEM (store too small,
+ * (NULL or missing factor pointers, alignment, an AFLP data block with a
+ * value that is not finite or a range whose exponents need more than 10
+ * bits or leave no mantissa bit), HM_ENOMEM (store too small,
  * pinned staging), HM_EDEVICE (no usable device, copy failure). */
 hm_status hm_upload(const hm_plan* p, const double* const* a, const double* const* bf,
                     const double* const* s, void* d_store, size_t store_bytes, void* stream,

@@ -100,11 +100,64 @@ static uint64_t dfl_bits(double v, int nbytes) {
   return kept << drop;
 }
 
-// A DFL value: its leading 4 bytes (DFL32 / 40 / 48: the high word of the
-// encoding) or 2 bytes (DFL16 / 24) at hi; for DFL40 / DFL48 / DFL24 bits
-// 31..24 / 31..16 / 47..40 at lo.
-static inline void put_dfl(uint8_t* hi, uint8_t* lo, int dt, double v) {
-  const uint64_t r = dfl_bits(v, value_bytes(dt));
+// AFLP (Sec. 3.2) parameter of one data block of nbytes-byte values (the
+// n values v[i * inc], i < n; see aflp_param): k with 2^k at or below the
+// smallest nonzero magnitude, and the fewest exponent bits e whose field
+// holds the binary exponent of every rounded d = |v| 2^-k + 1.  Fails for
+// values that are not finite or a range that needs more than 10 bits.
+static uint64_t rne_mantissa(uint64_t bits, int m) {   // positive normal FP64, m explicit bits
+  const int drop = 52 - m;
+  uint64_t kept = bits >> drop;
+  const uint64_t rem = bits & ((1ull << drop) - 1), half = 1ull << (drop - 1);
+  if (rem > half || (rem == half && (kept & 1))) ++kept;   // a carry moves into the exponent
+  return kept << drop;
+}
+static bool aflp_block_param(const double* v, int64_t rows, int64_t cols, int64_t ld, int nbytes, int32_t* out) {
+  double mn = HUGE_VAL, mx = 0;
+  for (int64_t j = 0; j < cols; ++j)
+    for (int64_t i = 0; i < rows; ++i) {
+      const double a = std::fabs(v[j * ld + i]);
+      if (!std::isfinite(a)) return false;
+      if (a > 0) { mn = std::min(mn, a); mx = std::max(mx, a); }
+    }
+  if (mx == 0) { *out = aflp_param(0, 0); return true; }
+  int k;
+  (void)std::frexp(mn, &k);
+  k -= 1;                                          // 2^k <= mn < 2^(k+1)
+  const double dmax = std::ldexp(mx, -k) + 1.0;
+  if (!std::isfinite(dmax)) return false;
+  uint64_t b;
+  std::memcpy(&b, &dmax, 8);
+  const int top = (int)(b >> 52) - 1023;           // binary exponent of the largest d (>= 1)
+  int e = 0;
+  while ((1 << e) <= top) ++e;
+  for (;; ++e) {
+    const int m = 8 * nbytes - 1 - e;
+    if (e > 10 || m < 1) return false;
+    if ((int)(rne_mantissa(b, m) >> 52) - 1023 < (1 << e)) break;
+  }
+  *out = aflp_param(k, e);
+  return true;
+}
+
+// The left-aligned 64-bit AFLP code of v (sign, e exponent bits, m mantissa
+// bits of the rounded d; the low 64 - 8 nbytes bits zero).
+static uint64_t aflp_code(double v, int32_t prm, int nbytes) {
+  if (v == 0) return 0;
+  const int k = aflp_scale_exp(prm), sh = aflp_shift(prm), e = 11 - sh, m = 8 * nbytes - 1 - e;
+  const double d = std::ldexp(std::fabs(v), -k) + 1.0;
+  uint64_t b;
+  std::memcpy(&b, &d, 8);
+  const uint64_t mag = (rne_mantissa(b, m) - 0x3ff0000000000000ull) << sh;
+  return (std::signbit(v) ? 1ull << 63 : 0) | mag;
+}
+
+// A left-aligned 64-bit code r of a DFL or AFLP value: its leading 4 bytes
+// (32 / 40 / 48-bit formats: the high word) or 2 bytes (16 / 24-bit
+// formats) at hi; for the 40 / 48 / 24-bit formats bits 31..24 / 31..16 /
+// 47..40 at lo.
+static inline void put_code(uint8_t* hi, uint8_t* lo, int dt, uint64_t r) {
+  dt = storage_dt(dt);
   if (dtype_size(dt) == 4) {
     const uint32_t w = (uint32_t)(r >> 32);
     std::memcpy(hi, &w, 4);
@@ -115,6 +168,10 @@ static inline void put_dfl(uint8_t* hi, uint8_t* lo, int dt, double v) {
   if (dt == kDtDfl40) { const uint8_t q = (uint8_t)(r >> 24); std::memcpy(lo, &q, 1); }
   if (dt == kDtDfl48) { const uint16_t q = (uint16_t)(r >> 16); std::memcpy(lo, &q, 2); }
   if (dt == kDtDfl24) { const uint8_t q = (uint8_t)(r >> 40); std::memcpy(lo, &q, 1); }
+}
+
+static inline void put_dfl(uint8_t* hi, uint8_t* lo, int dt, double v) {
+  put_code(hi, lo, dt, dfl_bits(v, value_bytes(dt)));
 }
 
 static inline void put(uint8_t* dst, int dt, double v) {
@@ -140,7 +197,7 @@ static hm_status validate_block(const hm_block_desc& b, int64_t i, int64_t n_row
     return fail(HM_ESHAPE, "block %lld too large", (long long)i);
   auto dt_ok = [&](int dt) {
     if (dt < HM_F64 || dt >= kNumDtypes) return false;
-    if (acc == HM_F32 && (dt == HM_F64 || is_dfl(dt))) return false;
+    if (acc == HM_F32 && (dt == HM_F64 || is_dfl(dt) || is_aflp(dt))) return false;
     return true;
   };
   if (b.kind == HM_DENSE) {
@@ -721,6 +778,10 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   }
   H.off_p1_order = take(H.n_p1 * 4);
   H.off_p2_order = take(H.n_p2 * 4);
+  for (auto& b : P->blocks)
+    for (int g = 0; g < b.ngroups; ++g) H.has_aflp |= is_aflp(b.group_dtype[g]);
+  H.off_row_aflp = take(H.has_aflp ? nsrc * 4 : 0);
+  H.off_col_aflp = take(H.has_aflp ? ndst * 4 : 0);
   const int64_t meta_end = off;
 
   // data: row sections, then column sections
@@ -786,7 +847,7 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
   P->alg_flops = flops;
   P->n_dense = nd;
   P->n_lowrank = nl;
-  P->overhead_bytes = (double)(nsrc + ndst) * 4 + pad_bytes +
+  P->overhead_bytes = (double)(nsrc + ndst) * (H.has_aflp ? 8 : 4) + pad_bytes +
                       (double)H.n_row_panels * (sizeof(RowPanel) + 4) + nsec * sizeof(RowSection) +
                       ntiles * sizeof(ColTile) + H.n_tblocks * sizeof(TBlock) +
                       (double)H.n_t * 4 + 2.0 * P->n_partials * acc_sz +
@@ -799,13 +860,35 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
 
 static const double* fac(const double* const* arr, int64_t i) { return arr ? arr[i] : nullptr; }
 
-// Header and descriptor tables: bytes [0, meta_bytes) of the store.
-hm_status pack_meta(const hm_plan* P, const double* const* a, const double* const* bf,
-                    const double* const* s, uint8_t* buf) {
-  const StoreHeader& H = P->hdr;
-  std::memcpy(buf, &H, sizeof H);
-  const int acc_sz = P->opts.acc_dtype == HM_F64 ? 8 : 4;
-  // check that every needed factor pointer is present
+// Column group of column c of block b (its first group for a dense block).
+static int group_of(const hm_block_desc& b, int64_t c) {
+  int64_t end = 0;
+  for (int g = 0; g < b.ngroups; ++g)
+    if (c < (end += b.group_cols[g])) return g;
+  return 0;
+}
+
+// Runs f(i) for i in [0, n) on the process's CPU share.
+static void parallel_for(size_t n, const std::function<void(size_t)>& f) {
+  unsigned nthr = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) {    // the process's CPU share, if stated
+    const int v = std::atoi(e);
+    if (v > 0) nthr = std::min(nthr, (unsigned)v);
+  }
+  nthr = (unsigned)std::min<size_t>(nthr, std::max<size_t>(1, n));
+  std::atomic<size_t> next{0};
+  auto worker = [&]() {
+    for (size_t i; (i = next.fetch_add(1)) < n;) f(i);
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nthr; ++t) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+}
+
+// Every factor pointer a block needs is present.
+static hm_status check_factors(const hm_plan* P, const double* const* a, const double* const* bf,
+                               const double* const* s) {
   for (size_t i = 0; i < P->blocks.size(); ++i) {
     const auto& b = P->blocks[i];
     if (!fac(a, (int64_t)i) && (b.kind == HM_DENSE || b.rank > 0))
@@ -815,6 +898,63 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
     if (b.kind == HM_LOWRANK && b.rank > 0 && b.has_sigma && !fac(s, (int64_t)i))
       return fail(HM_EINVAL, "block %zu: missing singular values", i);
   }
+  return HM_OK;
+}
+
+hm_status AflpTable::build(const hm_plan* P, const double* const* a, const double* const* bf) {
+  base.assign(P->blocks.size(), -1);
+  int64_t n = 0;
+  for (size_t i = 0; i < P->blocks.size(); ++i) {
+    const auto& b = P->blocks[i];
+    bool any = false;
+    for (int g = 0; g < b.ngroups; ++g) any |= is_aflp(b.group_dtype[g]);
+    if (!any) continue;
+    if (b.kind == HM_LOWRANK && b.rank == 0) continue;
+    base[i] = n;
+    n += b.kind == HM_DENSE ? 1 : 2 * b.ngroups;
+  }
+  prm.assign((size_t)n, 0);
+  std::atomic<int64_t> bad{-1};
+  parallel_for(P->blocks.size(), [&](size_t i) {
+    if (base[i] < 0) return;
+    const auto& b = P->blocks[i];
+    const int64_t m = b.row_end - b.row_begin, nb = b.col_end - b.col_begin;
+    bool good = true;
+    if (b.kind == HM_DENSE) {
+      good = aflp_block_param(a[i], m, nb, m, value_bytes(b.group_dtype[0]), &prm[base[i]]);
+    } else {
+      int64_t c0 = 0;
+      for (int g = 0; g < b.ngroups && good; ++g) {
+        const int dt = b.group_dtype[g];
+        const int64_t kc = b.group_cols[g];
+        if (is_aflp(dt) && kc > 0)
+          good = aflp_block_param(a[i] + c0 * m, m, kc, m, value_bytes(dt), &prm[base[i] + g]) &&
+                 aflp_block_param(bf[i] + c0 * nb, nb, kc, nb, value_bytes(dt), &prm[base[i] + b.ngroups + g]);
+        c0 += kc;
+      }
+    }
+    if (!good) bad.store((int64_t)i);
+  });
+  if (bad.load() >= 0)
+    return fail(HM_EINVAL, "block %lld: AFLP needs finite values whose range fits its bytes",
+                (long long)bad.load());
+  return HM_OK;
+}
+
+int32_t AflpTable::get(const hm_plan* P, int64_t block, int which, int64_t col) const {
+  const auto& b = P->blocks[block];
+  if (base[block] < 0) return 0;
+  if (b.kind == HM_DENSE) return prm[base[block]];
+  return prm[base[block] + which * b.ngroups + group_of(b, col)];
+}
+
+// Header and descriptor tables: bytes [0, meta_bytes) of the store.
+hm_status pack_meta(const hm_plan* P, const double* const* a, const double* const* bf,
+                    const double* const* s, const AflpTable& T, uint8_t* buf) {
+  const StoreHeader& H = P->hdr;
+  std::memcpy(buf, &H, sizeof H);
+  const int acc_sz = P->opts.acc_dtype == HM_F64 ? 8 : 4;
+  if (hm_status st = check_factors(P, a, bf, s)) return st;
   // descriptor tables
   auto* rp = reinterpret_cast<RowPanel*>(buf + H.off_row_panels);
   auto* rs = reinterpret_cast<RowSection*>(buf + H.off_row_sections);
@@ -841,10 +981,14 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
     }
     int32_t* src = rsrc + R.src_off;
     for (int32_t c = 0; c < R.ncols; ++c) src[c] = 0;   // padding slots read x[0] (times 0)
+    int32_t* ra = H.has_aflp ? reinterpret_cast<int32_t*>(buf + H.off_row_aflp) + R.src_off : nullptr;
+    if (ra) for (int32_t c = 0; c < R.ncols; ++c) ra[c] = 0;
     for (auto& sg : R.segs) {
       const RowSectionHost* S = nullptr;
       for (auto& x : R.secs) if (x.dtype == sg.dtype && x.kind == sg.kind) S = &x;
       for (int32_t c = 0; c < sg.ncols; ++c) src[S->col0 + sg.seccol + c] = sg.src0 + c;
+      if (ra && is_aflp(sg.dtype))
+        for (int32_t c = 0; c < sg.ncols; ++c) ra[S->col0 + sg.seccol + c] = T.get(P, sg.block, 0, sg.c_first + c);
     }
   }
   // launch order of row panels: largest first (longest-processing-time order)
@@ -893,11 +1037,15 @@ hm_status pack_meta(const hm_plan* P, const double* const* a, const double* cons
   for (auto& Cp : P->cps) {
     int32_t* dst = cdst + dsto;
     for (int32_t c = 0; c < Cp.ncols; ++c) dst[c] = kDstPad;
+    int32_t* ca = H.has_aflp ? reinterpret_cast<int32_t*>(buf + H.off_col_aflp) + dsto : nullptr;
+    if (ca) for (int32_t c = 0; c < Cp.ncols; ++c) ca[c] = 0;
     for (auto& sg : Cp.segs) {
       const ColSectionHost* S = nullptr;
       for (auto& x : Cp.secs) if (x.dtype == sg.dtype) S = &x;
       for (int32_t c = 0; c < sg.ncols; ++c)
         dst[S->c0 + sg.seccol + c] = sg.direct ? dst_direct(sg.src0 + c) : sg.src0 + c;
+      if (ca && is_aflp(sg.dtype))
+        for (int32_t c = 0; c < sg.ncols; ++c) ca[S->c0 + sg.seccol + c] = T.get(P, sg.block, 1, sg.c_first + c);
     }
     for (size_t ti = 0; ti < Cp.tile_lo.size(); ++ti) {
       ColTile& T = ct[tile++];
@@ -989,8 +1137,8 @@ void pack_job_range(const hm_plan* P, size_t j, int64_t* lo, int64_t* hi) {
 
 // Factor data of packing jobs [j_begin, j_end), in parallel; store byte o
 // goes to out[o - out_off] (out covers the jobs' byte ranges).
-void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf, size_t j_begin,
-               size_t j_end, uint8_t* out, int64_t out_off) {
+void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf, const AflpTable& T,
+               size_t j_begin, size_t j_end, uint8_t* out, int64_t out_off) {
   auto at = [&](int64_t o) { return out + (o - out_off); };
   const size_t nrp = P->rps.size();
   std::atomic<size_t> next{j_begin};
@@ -1015,10 +1163,14 @@ void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf
             const int32_t sc = sg.seccol + c;
             const int32_t g = sc / G, cc = sc % G;
             const double* col = A + (int64_t)(sg.c_first + c) * mb + r_local;
+            const int32_t prm = is_aflp(S->dtype) ? T.get(P, sg.block, 0, sg.c_first + c) : 0;
             for (int32_t i = 0; i < R.m; ++i) {
               uint8_t* hi = base + (((int64_t)g * R.m + i) * G + cc) * sz;
+              uint8_t* lo = lo_base + ((int64_t)g * R.m + i) * L + cc * (L / G);
               if (is_dfl(S->dtype))
-                put_dfl(hi, lo_base + ((int64_t)g * R.m + i) * L + cc * (L / G), S->dtype, col[i]);
+                put_dfl(hi, lo, S->dtype, col[i]);
+              else if (is_aflp(S->dtype))
+                put_code(hi, lo, S->dtype, aflp_code(col[i], prm, value_bytes(S->dtype)));
               else
                 put(hi, S->dtype, col[i]);
             }
@@ -1036,10 +1188,14 @@ void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf
           const bool lo = lo_bytes(S->dtype) > 0;
           for (int32_t c = 0; c < sg.ncols; ++c) {
             const double* col = V + (int64_t)(sg.c_first + c) * nbk + c_local;
+            const int32_t prm = is_aflp(S->dtype) ? T.get(P, sg.block, 1, sg.c_first + c) : 0;
             for (int32_t i = 0; i < Cp.nrows; ++i) {
               uint8_t* hi = at(col_elem_offset(Cp, *S, i, sg.seccol + c));
+              uint8_t* lp = lo ? at(col_lo_offset(Cp, *S, i, sg.seccol + c)) : nullptr;
               if (is_dfl(S->dtype))
-                put_dfl(hi, lo ? at(col_lo_offset(Cp, *S, i, sg.seccol + c)) : nullptr, S->dtype, col[i]);
+                put_dfl(hi, lp, S->dtype, col[i]);
+              else if (is_aflp(S->dtype))
+                put_code(hi, lp, S->dtype, aflp_code(col[i], prm, value_bytes(S->dtype)));
               else
                 put(hi, S->dtype, col[i]);
             }
@@ -1062,8 +1218,11 @@ void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf
 
 hm_status pack_store(const hm_plan* P, const double* const* a, const double* const* bf,
                      const double* const* s, uint8_t* buf) {
-  if (hm_status st = pack_meta(P, a, bf, s, buf)) return st;
-  pack_jobs(P, a, bf, 0, pack_jobs_count(P), buf, 0);
+  AflpTable T;
+  if (hm_status st = check_factors(P, a, bf, s)) return st;
+  if (hm_status st = T.build(P, a, bf)) return st;
+  if (hm_status st = pack_meta(P, a, bf, s, T, buf)) return st;
+  pack_jobs(P, a, bf, T, 0, pack_jobs_count(P), buf, 0);
   return HM_OK;
 }
 
@@ -1174,7 +1333,7 @@ static size_t upload_window_bytes() {
 // Factor data of the store, packed window by window into two pinned host
 // buffers and copied on `hs` while the next window is packed.
 static hm_status upload_factor_data(const hm_plan* p, const double* const* a, const double* const* bf,
-                                    uint8_t* d_store, hipStream_t hs) {
+                                    const AflpTable& aflp, uint8_t* d_store, hipStream_t hs) {
   const size_t njobs = pack_jobs_count(p);
   int64_t max_job = 0;
   for (size_t j = 0; j < njobs; ++j) {
@@ -1217,7 +1376,7 @@ static hm_status upload_factor_data(const hm_plan* p, const double* const* a, co
       break;
     }
     std::memset(stage[b], 0, (size_t)(hi - lo));
-    pack_jobs(p, a, bf, j, j2, stage[b], lo);
+    pack_jobs(p, a, bf, aflp, j, j2, stage[b], lo);
     if (hi > lo && (hipMemcpyAsync(d_store + lo, stage[b], (size_t)(hi - lo), hipMemcpyHostToDevice, hs) !=
                         hipSuccess ||
                     hipEventRecord(done[b], hs) != hipSuccess)) {
@@ -1251,12 +1410,15 @@ hm_status hm_upload(const hm_plan* p, const double* const* a, const double* cons
     return fail(HM_EDEVICE, "no usable HIP device");
   hipStream_t hs = (hipStream_t)stream;
   // header and tables (validates the factor pointers), then the factor data
+  AflpTable aflp;
   {
     std::vector<uint8_t> meta;
     hm_status st;
     try {
       meta.assign(p->meta_bytes, 0);
-      st = pack_meta(p, a, bf, s, meta.data());
+      st = check_factors(p, a, bf, s);
+      if (!st) st = aflp.build(p, a, bf);
+      if (!st) st = pack_meta(p, a, bf, s, aflp, meta.data());
     } catch (...) {
       st = fail(HM_ENOMEM, "packing failed");
     }
@@ -1267,7 +1429,7 @@ hm_status hm_upload(const hm_plan* p, const double* const* a, const double* cons
   }
   hm_status st;
   try {
-    st = upload_factor_data(p, a, bf, (uint8_t*)d_store, hs);
+    st = upload_factor_data(p, a, bf, aflp, (uint8_t*)d_store, hs);
   } catch (...) {
     st = fail(HM_ENOMEM, "packing failed");
   }

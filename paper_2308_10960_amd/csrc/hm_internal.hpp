@@ -143,6 +143,19 @@ inline int batch_slots(int acc_dtype, int nrhs) {
 }
 hm_status fail(hm_status code, const char* fmt, ...);
 hm_status ok();
+
+// AFLP parameters (aflp_param) of the data blocks of a plan's factors:
+// block b's dense block at prm[base[b]], the columns of its column group g
+// of U_b at prm[base[b] + g] and of V_b at prm[base[b] + ngroups + g]
+// (base[b] = -1: the block has no AFLP data).  Built from the factor data
+// before packing.
+struct AflpTable {
+  std::vector<int64_t> base;
+  std::vector<int32_t> prm;
+  hm_status build(const hm_plan* P, const double* const* a, const double* const* bf);
+  // parameter of column col of factor `which` (0: D_b / U_b, 1: V_b) of block
+  int32_t get(const hm_plan* P, int64_t block, int which, int64_t col) const;
+};
 hm_status layout_store(hm_plan* P, hm_plan** out);
 void read_tune_cache(hm_plan* P);
 uint16_t f64_to_f16(double d);

@@ -23,8 +23,8 @@
 //
 // Every sum has a fixed order, so results are bitwise reproducible and no
 // atomics touch y.  Storage formats (FP64/FP32/FP16/BF16, Table 1; the
-// byte-aligned DFL formats, Sec. 3.2) are decoded to the accumulation type
-// in registers.
+// byte-aligned DFL and AFLP formats, Sec. 3.2) are decoded to the
+// accumulation type in registers.
 
 #include <algorithm>
 
@@ -36,13 +36,13 @@
 namespace hm {
 namespace {
 
-// Value c of a DFL group element, exact.  DFL32 / 40 / 48: r[c] is the
+// FP64 encoding of value c of a DFL group element (exact).  DFL32 / 40 / 48: r[c] is the
 // high word of its FP64 encoding, and the element's low-byte plane entry lo
 // holds bits 31..24 in byte c (DFL40) or bits 31..16 in 16-bit half c
 // (DFL48).  DFL16 / 24: 16-bit half c of r holds bits 63..48, and byte c of
 // lo bits 47..40 (DFL24); the low word is zero.
 template <int DT>
-__device__ __forceinline__ double dfl_value(u32x4 r, u32x2 lo, int c) {
+__device__ __forceinline__ unsigned long long dfl_bits(u32x4 r, u32x2 lo, int c) {
   unsigned hi, low = 0;
   if constexpr (DT == kDtDfl16 || DT == kDtDfl24) {
     hi = ((r[c >> 1] >> (16 * (c & 1))) & 0xffffu) << 16;
@@ -52,16 +52,33 @@ __device__ __forceinline__ double dfl_value(u32x4 r, u32x2 lo, int c) {
     if constexpr (DT == kDtDfl40) low = ((lo[0] >> (8 * c)) & 0xffu) << 24;
     if constexpr (DT == kDtDfl48) low = ((lo[c >> 1] >> (16 * (c & 1))) & 0xffffu) << 16;
   }
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | low));
+  return ((unsigned long long)hi << 32) | low;
+}
+
+template <int DT>
+__device__ __forceinline__ double dfl_value(u32x4 r, u32x2 lo, int c) {
+  return __longlong_as_double((long long)dfl_bits<DT>(r, lo, c));
+}
+
+// sign(P) (d - 1) of an AFLP element (the scale 2^k is applied outside):
+// the code P, left-aligned like a DFL encoding of the same bytes, gives d's
+// FP64 bits as ((P & ~sign) >> sh) + bits(1.0), sh = 11 - e; d - 1 is
+// exact.  The zero code gives d = 1.
+template <int DT>
+__device__ __forceinline__ double aflp_value(u32x4 r, u32x2 lo, int c, unsigned sh) {
+  const unsigned long long P = dfl_bits<storage_dt(DT)>(r, lo, c);
+  const unsigned long long d = ((P & 0x7fffffffffffffffull) >> sh) + 0x3ff0000000000000ull;
+  const double w = __longlong_as_double((long long)d) - 1.0;
+  return __longlong_as_double(__double_as_longlong(w) | (long long)(P & 0x8000000000000000ull));
 }
 
 // The low-byte plane entry idx of a DFL40 / DFL48 / DFL24 region at p
 // (zero for the other formats, which have none).
 template <int DT>
 __device__ __forceinline__ u32x2 ld_lo(const uint8_t* p, int64_t idx) {
-  if constexpr (DT == kDtDfl40) {
+  if constexpr (storage_dt(DT) == kDtDfl40) {
     return u32x2{__builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p) + idx), 0u};
-  } else if constexpr (DT == kDtDfl48 || DT == kDtDfl24) {
+  } else if constexpr (storage_dt(DT) == kDtDfl48 || storage_dt(DT) == kDtDfl24) {
     return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p) + idx);
   } else {
     return (u32x2)(0u);
@@ -69,10 +86,26 @@ __device__ __forceinline__ u32x2 ld_lo(const uint8_t* p, int64_t idx) {
 }
 
 // acc += sum_c v[c] * z[c] over one 16-byte group of storage format DT
-// (lo: its low-byte plane entry, DFL40 / DFL48 only).
+// (lo: its low-byte plane entry, 40 / 48 / 24-bit formats only; AFLP: sh
+// the columns' shifts, z already scaled by the columns' 2^k).
 template <typename AccT, int DT>
-__device__ __forceinline__ AccT dot_group(u32x4 r, u32x2 lo, const AccT* __restrict__ z, AccT acc) {
-  if constexpr (is_dfl(DT)) {
+__device__ __forceinline__ AccT dot_group(u32x4 r, u32x2 lo, const AccT* __restrict__ z,
+                                          const uint8_t* __restrict__ sh, AccT acc) {
+  if constexpr (is_aflp(DT)) {
+    constexpr int G = group_width(DT);
+    unsigned s[G];
+    if constexpr (G == 4) {
+      const unsigned w = *reinterpret_cast<const unsigned*>(sh);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s[c] = (w >> (8 * c)) & 0xffu;
+    } else {
+      const u32x2 w = *reinterpret_cast<const u32x2*>(sh);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) s[c] = (w[c >> 2] >> (8 * (c & 3))) & 0xffu;
+    }
+#pragma unroll
+    for (int c = 0; c < G; ++c) acc = fmaT((AccT)aflp_value<DT>(r, lo, c, s[c]), z[c], acc);
+  } else if constexpr (is_dfl(DT)) {
 #pragma unroll
     for (int c = 0; c < group_width(DT); ++c) acc = fmaT((AccT)dfl_value<DT>(r, lo, c), z[c], acc);
   } else if constexpr (DT == HM_F64) {
@@ -99,10 +132,14 @@ __device__ __forceinline__ AccT dot_group(u32x4 r, u32x2 lo, const AccT* __restr
   return acc;
 }
 
-// acc[c] += v[c] * xi for the G columns of one 16-byte group.
+// acc[c] += v[c] * xi for the G columns of one 16-byte group (AFLP: sh the
+// columns' shifts; the sums are scaled by the columns' 2^k afterwards).
 template <typename AccT, int DT>
-__device__ __forceinline__ void axpy_group(u32x4 r, u32x2 lo, AccT xi, AccT* acc) {
-  if constexpr (is_dfl(DT)) {
+__device__ __forceinline__ void axpy_group(u32x4 r, u32x2 lo, AccT xi, AccT* acc, const unsigned* sh) {
+  if constexpr (is_aflp(DT)) {
+#pragma unroll
+    for (int c = 0; c < group_width(DT); ++c) acc[c] = fmaT((AccT)aflp_value<DT>(r, lo, c, sh[c]), xi, acc[c]);
+  } else if constexpr (is_dfl(DT)) {
 #pragma unroll
     for (int c = 0; c < group_width(DT); ++c) acc[c] = fmaT((AccT)dfl_value<DT>(r, lo, c), xi, acc[c]);
   } else if constexpr (DT == HM_F64) {
@@ -137,6 +174,7 @@ struct ColArgs {
   AccT* part;
   AccT* t;                // column sums of blocks inside one chunk go here
   const AccT* sigma;      // nullptr when no block keeps singular values
+  const int32_t* aflp;    // aflp_param per tile column (beside dst); nullptr: no AFLP data
   int64_t n_tiles;
 };
 
@@ -149,13 +187,28 @@ struct ColArgs {
 // LDS (red: 4 x 64 x 8), and wave 0 writes each column's sum to its
 // destination (a partial, or t).  DT >= 0: every group of the tile has
 // format DT; DT < 0: the tile holds runs of several formats and each lane
-// decodes its own (T.dtype, T.end); DFL: such a tile may hold DFL runs.
-template <typename AccT, int DT, bool DFL = false>
+// decodes its own (T.dtype, T.end); DFL / AFLP: such a tile may hold DFL /
+// AFLP runs.  An AFLP lane keeps its columns' shifts in registers and
+// scales its sums by the columns' 2^k before they are written.
+template <typename AccT, int DT, bool DFL = false, bool AFLP = false>
 __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, AccT* red, AccT* xs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool act = lane < T.ngroups;
   const TileGroup tg = tile_group(T, act ? lane : 0);
   const int dt = DT >= 0 ? DT : tg.dtype;
+  constexpr bool kAflp = DT >= 0 ? is_aflp(DT) : AFLP;
+  constexpr int GW = DT >= 0 ? group_width(DT) : 8;   // columns per lane (at most)
+  unsigned sh[GW];
+#pragma unroll
+  for (int c = 0; c < GW; ++c) sh[c] = 0;
+  if constexpr (kAflp) {
+    if (act && is_aflp(dt)) {
+      const int G = group_width(dt);
+#pragma unroll
+      for (int c = 0; c < GW; ++c)
+        if (c < G) sh[c] = aflp_shift(a.aflp[T.dst_off + tg.col + c]);
+    }
+  }
   AccT acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = AccT(0);
@@ -165,8 +218,9 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
   // low-byte plane: entries of lo_bytes(DT) bytes in a one-format tile; of
   // Lt bytes in a several-format one (read by the lanes whose format has one)
   const uint8_t* lop = a.store + T.data_off + (int64_t)16 * nrows * rstride;
-  const int Lt = DT < 0 && DFL ? tile_lo_bytes(T) : 0;
-  const bool hlo = DT < 0 && DFL && lo_bytes(dt) > 0;
+  constexpr bool LOW = DFL || AFLP;                // several-format tiles: runs with low bytes
+  const int Lt = DT < 0 && LOW ? tile_lo_bytes(T) : 0;
+  const bool hlo = DT < 0 && LOW && lo_bytes(dt) > 0;
   const int nb = nrows > 8 * wave ? (nrows - 8 * wave + 31) / 32 : 0;   // this wave's batches
   u32x4 rn[8];
   u32x2 ln[8];
@@ -178,7 +232,7 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
         rn[u] = ld16(p + (size_t)(r0 + u) * rstride);
         if constexpr (DT >= 0) {
           ln[u] = ld_lo<DT>(lop, (int64_t)(r0 + u) * rstride + lane);
-        } else if constexpr (DFL) {
+        } else if constexpr (LOW) {
           if (hlo) {
             const int64_t e = (int64_t)(r0 + u) * rstride + lane;
             ln[u] = Lt == 8 ? ld_lo<kDtDfl48>(lop, e) : ld_lo<kDtDfl40>(lop, e);
@@ -205,28 +259,32 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
         const AccT xi = xs[r0 + u];
         if (act) {
           if constexpr (DT >= 0) {
-            axpy_group<AccT, DT>(rc[u], lc[u], xi, acc);
+            axpy_group<AccT, DT>(rc[u], lc[u], xi, acc, sh);
           } else if (dt == HM_F32) {
-            axpy_group<AccT, HM_F32>(rc[u], lc[u], xi, acc);
+            axpy_group<AccT, HM_F32>(rc[u], lc[u], xi, acc, sh);
           } else if (dt == HM_F16) {
-            axpy_group<AccT, HM_F16>(rc[u], lc[u], xi, acc);
+            axpy_group<AccT, HM_F16>(rc[u], lc[u], xi, acc, sh);
           } else if (dt == HM_BF16) {
-            axpy_group<AccT, HM_BF16>(rc[u], lc[u], xi, acc);
+            axpy_group<AccT, HM_BF16>(rc[u], lc[u], xi, acc, sh);
           } else if constexpr (sizeof(AccT) == 8) {
             // FP64-accumulation formats
-            if (DFL && dt == kDtDfl32) axpy_group<AccT, kDtDfl32>(rc[u], lc[u], xi, acc);
-            else if (DFL && dt == kDtDfl16) axpy_group<AccT, kDtDfl16>(rc[u], lc[u], xi, acc);
-            else if (DFL && dt == kDtDfl24) axpy_group<AccT, kDtDfl24>(rc[u], lc[u], xi, acc);
-            else if (DFL && dt == kDtDfl40) axpy_group<AccT, kDtDfl40>(rc[u], lc[u], xi, acc);
-            else if (DFL && dt == kDtDfl48) axpy_group<AccT, kDtDfl48>(rc[u], lc[u], xi, acc);
-            else axpy_group<AccT, HM_F64>(rc[u], lc[u], xi, acc);
+            if (DFL && dt == kDtDfl32) axpy_group<AccT, kDtDfl32>(rc[u], lc[u], xi, acc, sh);
+            else if (DFL && dt == kDtDfl16) axpy_group<AccT, kDtDfl16>(rc[u], lc[u], xi, acc, sh);
+            else if (DFL && dt == kDtDfl24) axpy_group<AccT, kDtDfl24>(rc[u], lc[u], xi, acc, sh);
+            else if (DFL && dt == kDtDfl40) axpy_group<AccT, kDtDfl40>(rc[u], lc[u], xi, acc, sh);
+            else if (DFL && dt == kDtDfl48) axpy_group<AccT, kDtDfl48>(rc[u], lc[u], xi, acc, sh);
+            else if (AFLP && dt == kDtAflp32) axpy_group<AccT, kDtAflp32>(rc[u], lc[u], xi, acc, sh);
+            else if (AFLP && dt == kDtAflp16) axpy_group<AccT, kDtAflp16>(rc[u], lc[u], xi, acc, sh);
+            else if (AFLP && dt == kDtAflp24) axpy_group<AccT, kDtAflp24>(rc[u], lc[u], xi, acc, sh);
+            else if (AFLP && dt == kDtAflp40) axpy_group<AccT, kDtAflp40>(rc[u], lc[u], xi, acc, sh);
+            else if (AFLP && dt == kDtAflp48) axpy_group<AccT, kDtAflp48>(rc[u], lc[u], xi, acc, sh);
+            else axpy_group<AccT, HM_F64>(rc[u], lc[u], xi, acc, sh);
           }
         }
       }
   }
-  constexpr int GW = DT >= 0 ? group_width(DT) : 8;   // red stride per lane
 #pragma unroll
-  for (int c = 0; c < GW; ++c) red[(wave * 64 + lane) * GW + c] = acc[c];
+  for (int c = 0; c < GW; ++c) red[(wave * 64 + lane) * GW + c] = acc[c];   // red stride GW per lane
   __syncthreads();
   if (wave == 0 && act) {
     const int G = group_width(dt);
@@ -237,10 +295,21 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
     for (int c = 0; c < GW; ++c) d[c] = c < G ? a.dst[T.dst_off + tg.col + c] : kDstPad;
 #pragma unroll
     for (int c = 0; c < GW; ++c) f[c] = (d[c] <= -2 && a.sigma) ? a.sigma[dst_t_index(d[c])] : AccT(1);
+    int ks[GW];                                     // AFLP: the columns' scale exponents
+#pragma unroll
+    for (int c = 0; c < GW; ++c) ks[c] = 0;
+    if constexpr (kAflp) {
+      if (is_aflp(dt)) {
+#pragma unroll
+        for (int c = 0; c < GW; ++c)
+          if (c < G) ks[c] = aflp_scale_exp(a.aflp[T.dst_off + tg.col + c]);
+      }
+    }
 #pragma unroll
     for (int c = 0; c < GW; ++c) {
-      const AccT sum = (red[lane * GW + c] + red[(64 + lane) * GW + c]) +
-                       (red[(128 + lane) * GW + c] + red[(192 + lane) * GW + c]);
+      AccT sum = (red[lane * GW + c] + red[(64 + lane) * GW + c]) +
+                 (red[(128 + lane) * GW + c] + red[(192 + lane) * GW + c]);
+      if constexpr (kAflp) sum = ldexp(sum, ks[c]);     // exact: a power of two
       if (d[c] >= 0)
         a.part[d[c]] = sum;
       else if (d[c] != kDstPad)
@@ -254,6 +323,7 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
 constexpr int kColIeee = 1;     // one-format tiles of FP64, FP32, FP16, BF16
 constexpr int kColMulti = 2;    // several-format tiles
 constexpr int kColDfl = 4;      // one-format DFL tiles, and DFL runs in several-format tiles
+constexpr int kColAflp = 8;     // AFLP runs in several-format tiles
 
 // A whole workgroup on tile ti (it synchronizes).  red: 4 * 64 * 8 values
 // (four waves x 64 lanes x at most 8 columns per lane); xs: kSegRows
@@ -267,10 +337,21 @@ __device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti,
     return;
   }
   constexpr bool dfl = (KIND & kColDfl) && sizeof(AccT) == 8;
+  constexpr bool aflp = (KIND & kColAflp) && sizeof(AccT) == 8;
   if constexpr ((KIND & kColMulti) != 0) {
     if (T.end[0] < T.ngroups) {                     // several formats in the tile
-      col_tile<AccT, -1, dfl>(a, T, red, xs);
+      col_tile<AccT, -1, dfl, aflp>(a, T, red, xs);
       return;
+    }
+  }
+  if constexpr (aflp) {
+    switch (T.dtype[0]) {
+      case kDtAflp32: col_tile<AccT, kDtAflp32>(a, T, red, xs); return;
+      case kDtAflp40: col_tile<AccT, kDtAflp40>(a, T, red, xs); return;
+      case kDtAflp48: col_tile<AccT, kDtAflp48>(a, T, red, xs); return;
+      case kDtAflp16: col_tile<AccT, kDtAflp16>(a, T, red, xs); return;
+      case kDtAflp24: col_tile<AccT, kDtAflp24>(a, T, red, xs); return;
+      default: break;
     }
   }
   if constexpr (dfl) {
@@ -362,13 +443,19 @@ struct RowArgs {
   AccT* y;
   AccT alpha;
   int32_t n_cols;
+  const int32_t* aflp;    // aflp_param per source slot (beside src); nullptr: no AFLP data
 };
+
+// Formats a row-panel instantiation decodes besides FP64 / FP32 / FP16 /
+// BF16 (a bit set; FP64 accumulation only).
+constexpr int kXfDfl = 1, kXfAflp = 2;
 
 // Groups [g_lo, g_hi) of a section at base (its low-byte plane, if any, at
 // lo_base), groups g_lo + wave, + 4, ... for this wave.
 template <typename AccT, int DT, int U>
 __device__ __forceinline__ AccT row_section(const uint8_t* base, const uint8_t* lo_base, int m, int g_lo,
-                                            int g_hi, const AccT* z, int lane, int wave, AccT acc) {
+                                            int g_hi, const AccT* z, const uint8_t* shz, int lane, int wave,
+                                            AccT acc) {
   constexpr int G = group_width(DT);
   const u32x4* p = reinterpret_cast<const u32x4*>(base) + lane;
   int g = g_lo + wave;
@@ -382,10 +469,12 @@ __device__ __forceinline__ AccT row_section(const uint8_t* base, const uint8_t* 
       l[u] = ld_lo<DT>(lo_base, (int64_t)(g + 4 * u) * m + lane);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc = dot_group<AccT, DT>(r[u], l[u], z + (g + 4 * u) * G, acc);
+    for (int u = 0; u < U; ++u)
+      acc = dot_group<AccT, DT>(r[u], l[u], z + (g + 4 * u) * G, shz + (g + 4 * u) * G, acc);
   }
   for (; g < g_hi; g += 4)
-    acc = dot_group<AccT, DT>(ld16(p + (size_t)g * m), ld_lo<DT>(lo_base, (int64_t)g * m + lane), z + g * G, acc);
+    acc = dot_group<AccT, DT>(ld16(p + (size_t)g * m), ld_lo<DT>(lo_base, (int64_t)g * m + lane), z + g * G,
+                              shz + g * G, acc);
   return acc;
 }
 
@@ -393,11 +482,13 @@ __device__ __forceinline__ AccT row_section(const uint8_t* base, const uint8_t* 
 // sources staged in LDS by chunks of CAP slots, four waves stream the groups,
 // a fixed-order LDS reduction, then one update of the panel's rows of y.
 // Called by whole workgroups (it synchronizes).
-// DFL: the store holds DFL sections (decoded only by such instantiations).
-template <typename AccT, int CAP, int U, bool DFL>
+// XF: the store holds DFL / AFLP sections (decoded only by such
+// instantiations).  AFLP: a slot's source is staged times its column's 2^k
+// (exact) and its shift beside it (shs, CAP bytes).
+template <typename AccT, int CAP, int U, int XF>
 __device__ __forceinline__ void row_panel_part(const RowArgs<AccT>& a, const RowPanel& P,
                                                int q_begin, int q_end, int s_begin, int s_end,
-                                               AccT* zs, AccT (*red)[64]) {
+                                               AccT* zs, AccT (*red)[64], uint8_t* shs) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   AccT acc = AccT(0);
   const int32_t* src = a.src + P.src_off;
@@ -405,7 +496,13 @@ __device__ __forceinline__ void row_panel_part(const RowArgs<AccT>& a, const Row
     const int c_hi = min(s_end, c_lo + CAP);
     for (int c = c_lo + tid; c < c_hi; c += 256) {
       const int s = src[c];
-      zs[c - c_lo] = s < a.n_cols ? a.x[s] : a.t[s - a.n_cols];
+      AccT z = s < a.n_cols ? a.x[s] : a.t[s - a.n_cols];
+      if constexpr ((XF & kXfAflp) != 0) {
+        const int32_t q = a.aflp[P.src_off + c];
+        z = ldexp(z, aflp_scale_exp(q));
+        shs[c - c_lo] = (uint8_t)aflp_shift(q);
+      }
+      zs[c - c_lo] = z;
     }
     __syncthreads();
     if (lane < P.m) {
@@ -416,39 +513,35 @@ __device__ __forceinline__ void row_panel_part(const RowArgs<AccT>& a, const Row
         const int g_hi = min(S.ngroups, max(0, c_hi - S.col0) / G);
         if (g_hi <= g_lo) continue;
         const uint8_t* base = a.store + S.data_off;
-        const uint8_t* lob = base + (int64_t)16 * S.ngroups * P.m;   // low-byte plane (DFL40 / DFL48)
+        const uint8_t* lob = base + (int64_t)16 * S.ngroups * P.m;   // low-byte plane (40 / 48 / 24 bits)
         const AccT* z = zs + (S.col0 - c_lo);
+        const uint8_t* sz = shs + (S.col0 - c_lo);
+#define HM_ROW_SECTION(D) acc = row_section<AccT, D, U>(base, lob, P.m, g_lo, g_hi, z, sz, lane, wave, acc)
         switch (S.dtype) {
-          case HM_F32: acc = row_section<AccT, HM_F32, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc); break;
-          case HM_F16: acc = row_section<AccT, HM_F16, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc); break;
-          case HM_BF16: acc = row_section<AccT, HM_BF16, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc); break;
+          case HM_F32: HM_ROW_SECTION(HM_F32); break;
+          case HM_F16: HM_ROW_SECTION(HM_F16); break;
+          case HM_BF16: HM_ROW_SECTION(HM_BF16); break;
           default:                                  // FP64-accumulation formats
-            if constexpr (sizeof(AccT) == 8 && !DFL) {
-              acc = row_section<AccT, HM_F64, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
+            if constexpr (sizeof(AccT) == 8 && XF == 0) {
+              HM_ROW_SECTION(HM_F64);
             } else if constexpr (sizeof(AccT) == 8) {
               switch (S.dtype) {
-                case HM_F64:
-                  acc = row_section<AccT, HM_F64, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
-                  break;
-                case kDtDfl32:
-                  acc = row_section<AccT, kDtDfl32, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
-                  break;
-                case kDtDfl40:
-                  acc = row_section<AccT, kDtDfl40, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
-                  break;
-                case kDtDfl16:
-                  acc = row_section<AccT, kDtDfl16, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
-                  break;
-                case kDtDfl24:
-                  acc = row_section<AccT, kDtDfl24, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
-                  break;
-                default:
-                  acc = row_section<AccT, kDtDfl48, U>(base, lob, P.m, g_lo, g_hi, z, lane, wave, acc);
-                  break;
+                case HM_F64: HM_ROW_SECTION(HM_F64); break;
+                case kDtDfl32: if constexpr ((XF & kXfDfl) != 0) HM_ROW_SECTION(kDtDfl32); break;
+                case kDtDfl40: if constexpr ((XF & kXfDfl) != 0) HM_ROW_SECTION(kDtDfl40); break;
+                case kDtDfl16: if constexpr ((XF & kXfDfl) != 0) HM_ROW_SECTION(kDtDfl16); break;
+                case kDtDfl24: if constexpr ((XF & kXfDfl) != 0) HM_ROW_SECTION(kDtDfl24); break;
+                case kDtDfl48: if constexpr ((XF & kXfDfl) != 0) HM_ROW_SECTION(kDtDfl48); break;
+                case kDtAflp32: if constexpr ((XF & kXfAflp) != 0) HM_ROW_SECTION(kDtAflp32); break;
+                case kDtAflp40: if constexpr ((XF & kXfAflp) != 0) HM_ROW_SECTION(kDtAflp40); break;
+                case kDtAflp16: if constexpr ((XF & kXfAflp) != 0) HM_ROW_SECTION(kDtAflp16); break;
+                case kDtAflp24: if constexpr ((XF & kXfAflp) != 0) HM_ROW_SECTION(kDtAflp24); break;
+                default: if constexpr ((XF & kXfAflp) != 0) HM_ROW_SECTION(kDtAflp48); break;
               }
             }
             break;
         }
+#undef HM_ROW_SECTION
       }
     }
     __syncthreads();
@@ -469,34 +562,39 @@ __device__ __forceinline__ int dense_slot_end(const RowArgs<AccT>& a, const RowP
 
 // Phase 1: the dense parts of the row panels and the column tiles in one
 // grouped launch.  Entry >= 0: a row panel; entry < 0: column tile -entry-1.
-template <typename AccT, int CAP, int U, bool DFL>
+template <typename AccT, int CAP, int U, int XF>
 __global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, const int32_t* order,
                                             int64_t n_items) {
   static_assert(CAP >= 4 * 64 * 8, "staging buffer doubles as the tile reduction buffer");
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
   __shared__ AccT pxs[kSegRows];
+  __shared__ __align__(16) uint8_t shs[(XF & kXfAflp) ? CAP : 8];
+  constexpr int KIND =
+      kColIeee | kColMulti | ((XF & kXfDfl) ? kColDfl : 0) | ((XF & kXfAflp) ? kColAflp : 0);
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     if (it != blockIdx.x) __syncthreads();          // LDS of the previous item
     const int item = order[it];
     if (item >= 0) {
       const RowPanel P = ra.rp[item];
-      row_panel_part<AccT, CAP, U, DFL>(ra, P, 0, P.nsec_dense, 0, dense_slot_end(ra, P), zs, red);
+      row_panel_part<AccT, CAP, U, XF>(ra, P, 0, P.nsec_dense, 0, dense_slot_end(ra, P), zs, red, shs);
     } else {
-      col_tile_any<AccT, kColIeee | kColMulti | (DFL ? kColDfl : 0)>(ca, -(int64_t)item - 1, zs, pxs);
+      col_tile_any<AccT, KIND>(ca, -(int64_t)item - 1, zs, pxs);
     }
   }
 }
 
 // Phase 2: the U sections of the row panels (after t is complete).
-template <typename AccT, int CAP, int U, bool DFL>
+template <typename AccT, int CAP, int U, int XF>
 __global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* order, int64_t n_items) {
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
+  __shared__ __align__(16) uint8_t shs[(XF & kXfAflp) ? CAP : 8];
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     if (it != blockIdx.x) __syncthreads();
     const RowPanel P = ra.rp[order[it]];
-    row_panel_part<AccT, CAP, U, DFL>(ra, P, P.nsec_dense, P.nsec, dense_slot_end(ra, P), P.ncols, zs, red);
+    row_panel_part<AccT, CAP, U, XF>(ra, P, P.nsec_dense, P.nsec, dense_slot_end(ra, P), P.ncols, zs, red,
+                                     shs);
   }
 }
 
@@ -516,17 +614,18 @@ void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
   }
 }
 
-template <typename AccT, int CAP, int U, bool DFL>
+template <typename AccT, int CAP, int U, int XF>
 __global__ __launch_bounds__(256) void k_row(RowArgs<AccT> ra, const int32_t* order, int64_t n_panels,
                                              int64_t n_items) {
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
+  __shared__ __align__(16) uint8_t shs[(XF & kXfAflp) ? CAP : 8];
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int pi = panel_of(order, n_panels, it);
     if (pi < 0) continue;                           // uniform: whole workgroup
     __syncthreads();                                // LDS of the previous item
     const RowPanel P = ra.rp[pi];
-    row_panel_part<AccT, CAP, U, DFL>(ra, P, 0, P.nsec, 0, P.ncols, zs, red);
+    row_panel_part<AccT, CAP, U, XF>(ra, P, 0, P.nsec, 0, P.ncols, zs, red, shs);
   }
 }
 
@@ -552,7 +651,7 @@ __global__ __launch_bounds__(256) void k_stream_read(const u32x4* __restrict__ p
 
 // ---------------------------------------------------------------- launch
 
-template <typename AccT, int U, bool DFL>
+template <typename AccT, int U, int XF>
 hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void* y, void* work,
                           hipStream_t s, hipEvent_t* ev) {
   const StoreHeader& h = A.hdr;
@@ -565,42 +664,52 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
                    reinterpret_cast<const RowSection*>(st + h.off_row_sections),
                    reinterpret_cast<const int32_t*>(st + h.off_row_src),
                    reinterpret_cast<const AccT*>(x), t, reinterpret_cast<AccT*>(y), (AccT)alpha,
-                   (int32_t)h.n_cols};
+                   (int32_t)h.n_cols,
+                   h.has_aflp ? reinterpret_cast<const int32_t*>(st + h.off_row_aflp) : nullptr};
   const AccT* sigma = h.has_sigma ? reinterpret_cast<const AccT*>(st + h.off_sigma) : nullptr;
   ColArgs<AccT> ca{st, reinterpret_cast<const ColTile*>(st + h.off_col_tiles),
                    reinterpret_cast<const int32_t*>(st + h.off_col_dst),
-                   reinterpret_cast<const AccT*>(x), part, t, sigma, h.n_col_tiles};
+                   reinterpret_cast<const AccT*>(x), part, t, sigma,
+                   h.has_aflp ? reinterpret_cast<const int32_t*>(st + h.off_col_aflp) : nullptr,
+                   h.n_col_tiles};
   const bool grouped = A.launch.schedule == 1;
   const int ps = A.launch.persist, ncu = A.n_cu;
   if (ev) (void)hipEventRecord(ev[0], s);
   if (grouped) {
     if (h.n_p1 > 0)
-      hipLaunchKernelGGL((k_p1<AccT, CAP, U, DFL>), dim3(item_grid(h.n_p1, ps, ncu)), dim3(256), 0, s, ra,
+      hipLaunchKernelGGL((k_p1<AccT, CAP, U, XF>), dim3(item_grid(h.n_p1, ps, ncu)), dim3(256), 0, s, ra,
                          ca, reinterpret_cast<const int32_t*>(st + h.off_p1_order), h.n_p1);
   } else {
     // classes: one-format IEEE tiles [0, ce[3]), one-format DFL tiles
-    // [ce[3], ce[8]), several-format tiles [ce[8], ce[9])
+    // [ce[3], ce[8]), one-format AFLP tiles [ce[8], ce[13]), several-format
+    // tiles [ce[13], ce[14])
     const int64_t* ce = h.tile_class_end;
-    const int64_t ni = ce[HM_BF16], nd = ce[kNumDtypes - 1] - ni, nm = h.n_col_tiles - ce[kNumDtypes - 1];
+    const int64_t ni = ce[HM_BF16], nm = h.n_col_tiles - ce[kNumDtypes - 1];
     if (ni > 0)
       hipLaunchKernelGGL((k_col<AccT, kColIeee>), dim3(item_grid(ni, ps, ncu)), dim3(256), 0, s, ca,
                          int64_t(0), ni);
-    if constexpr (DFL && sizeof(AccT) == 8) {
-      if (nd > 0) {                                 // one launch per DFL class
-        auto cls = [&](auto kern, int c) {
-          const int64_t t0 = ce[c - 1], n = ce[c] - t0;
-          if (n > 0) hipLaunchKernelGGL(kern, dim3(item_grid(n, ps, ncu)), dim3(256), 0, s, ca, t0, ce[c]);
-        };
-        cls(k_col<AccT, kColDfl, kDtDfl32>, kDtDfl32);
-        cls(k_col<AccT, kColDfl, kDtDfl40>, kDtDfl40);
-        cls(k_col<AccT, kColDfl, kDtDfl48>, kDtDfl48);
-        cls(k_col<AccT, kColDfl, kDtDfl16>, kDtDfl16);
-        cls(k_col<AccT, kColDfl, kDtDfl24>, kDtDfl24);
-      }
+    auto cls = [&](auto kern, int c) {              // one launch per class
+      const int64_t t0 = ce[c - 1], n = ce[c] - t0;
+      if (n > 0) hipLaunchKernelGGL(kern, dim3(item_grid(n, ps, ncu)), dim3(256), 0, s, ca, t0, ce[c]);
+    };
+    if constexpr ((XF & kXfDfl) != 0 && sizeof(AccT) == 8) {
+      cls(k_col<AccT, kColDfl, kDtDfl32>, kDtDfl32);
+      cls(k_col<AccT, kColDfl, kDtDfl40>, kDtDfl40);
+      cls(k_col<AccT, kColDfl, kDtDfl48>, kDtDfl48);
+      cls(k_col<AccT, kColDfl, kDtDfl16>, kDtDfl16);
+      cls(k_col<AccT, kColDfl, kDtDfl24>, kDtDfl24);
     }
+    if constexpr ((XF & kXfAflp) != 0 && sizeof(AccT) == 8) {
+      cls(k_col<AccT, kColAflp, kDtAflp16>, kDtAflp16);
+      cls(k_col<AccT, kColAflp, kDtAflp24>, kDtAflp24);
+      cls(k_col<AccT, kColAflp, kDtAflp32>, kDtAflp32);
+      cls(k_col<AccT, kColAflp, kDtAflp40>, kDtAflp40);
+      cls(k_col<AccT, kColAflp, kDtAflp48>, kDtAflp48);
+    }
+    constexpr int KM = kColMulti | ((XF & kXfDfl) ? kColDfl : 0) | ((XF & kXfAflp) ? kColAflp : 0);
     if (nm > 0)
-      hipLaunchKernelGGL((k_col<AccT, kColMulti | (DFL ? kColDfl : 0)>), dim3(item_grid(nm, ps, ncu)),
-                         dim3(256), 0, s, ca, ce[kNumDtypes - 1], h.n_col_tiles);
+      hipLaunchKernelGGL((k_col<AccT, KM>), dim3(item_grid(nm, ps, ncu)), dim3(256), 0, s, ca,
+                         ce[kNumDtypes - 1], h.n_col_tiles);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
   if (h.n_col_tiles > 0) {
@@ -613,12 +722,12 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
   if (ev) (void)hipEventRecord(ev[2], s);
   if (grouped) {
     if (h.n_p2 > 0)
-      hipLaunchKernelGGL((k_p2<AccT, CAP, U, DFL>), dim3(item_grid(h.n_p2, ps, ncu)), dim3(256), 0, s, ra,
+      hipLaunchKernelGGL((k_p2<AccT, CAP, U, XF>), dim3(item_grid(h.n_p2, ps, ncu)), dim3(256), 0, s, ra,
                          reinterpret_cast<const int32_t*>(st + h.off_p2_order), h.n_p2);
   } else if (h.n_row_panels > 0) {
     const bool xcd = A.launch.order == 1;
     const int64_t items = panel_items(xcd, h.n_row_panels);
-    hipLaunchKernelGGL((k_row<AccT, CAP, U, DFL>), dim3(item_grid(items, ps, ncu)), dim3(256), 0, s, ra,
+    hipLaunchKernelGGL((k_row<AccT, CAP, U, XF>), dim3(item_grid(items, ps, ncu)), dim3(256), 0, s, ra,
                        xcd ? nullptr : reinterpret_cast<const int32_t*>(st + h.off_row_order),
                        h.n_row_panels, items);
   }
@@ -626,19 +735,28 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
   return hipGetLastError();
 }
 
-// DFL instantiations (FP64 accumulation only) run when the store holds DFL bytes.
+// DFL / AFLP instantiations (FP64 accumulation only) run when the store
+// holds such bytes (the AFLP ones decode the DFL formats too).
 template <typename AccT>
 hipError_t launch_typed(const hm_matrix& A, double alpha, const void* x, void* y, void* work,
                         hipStream_t s, hipEvent_t* ev) {
+  const bool u8 = A.launch.row_unroll >= 8;
   if constexpr (sizeof(AccT) == 8) {
-    bool dfl = false;
-    for (int d = 0; d < kNumDtypes; ++d) dfl = dfl || (is_dfl(d) && A.bytes_by_dtype[d] > 0);
+    bool dfl = false, aflp = false;
+    for (int d = 0; d < kNumDtypes; ++d) {
+      dfl = dfl || (is_dfl(d) && A.bytes_by_dtype[d] > 0);
+      aflp = aflp || (is_aflp(d) && A.bytes_by_dtype[d] > 0);
+    }
+    constexpr int kAll = kXfDfl | kXfAflp;
+    if (aflp)
+      return u8 ? launch_typed_u<AccT, 8, kAll>(A, alpha, x, y, work, s, ev)
+                : launch_typed_u<AccT, 4, kAll>(A, alpha, x, y, work, s, ev);
     if (dfl)
-      return A.launch.row_unroll >= 8 ? launch_typed_u<AccT, 8, true>(A, alpha, x, y, work, s, ev)
-                                      : launch_typed_u<AccT, 4, true>(A, alpha, x, y, work, s, ev);
+      return u8 ? launch_typed_u<AccT, 8, kXfDfl>(A, alpha, x, y, work, s, ev)
+                : launch_typed_u<AccT, 4, kXfDfl>(A, alpha, x, y, work, s, ev);
   }
-  return A.launch.row_unroll >= 8 ? launch_typed_u<AccT, 8, false>(A, alpha, x, y, work, s, ev)
-                                  : launch_typed_u<AccT, 4, false>(A, alpha, x, y, work, s, ev);
+  return u8 ? launch_typed_u<AccT, 8, 0>(A, alpha, x, y, work, s, ev)
+            : launch_typed_u<AccT, 4, 0>(A, alpha, x, y, work, s, ev);
 }
 
 }  // namespace

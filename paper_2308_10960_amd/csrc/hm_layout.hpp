@@ -29,7 +29,9 @@
 //    runs of formats with a low-byte plane has the plane after its rows: the
 //    low bytes of row i, group g at 16 nrows ngroups + L (i ngroups + g),
 //    L = the largest lo_bytes of its runs (entries of groups of the other
-//    formats are unused).
+//    formats are unused).  AFLP values are stored like DFL values of the
+//    same byte count; their per-column decode parameters sit in tables
+//    beside the row-source and destination tables.
 //  * Reduction.  t_b[l] = s_b[l] * sum over the chunks of sigma_b of the
 //    partials, in ascending chunk order.
 //  * Single-RHS schedule: phase 1 streams the dense sections of the row
@@ -53,25 +55,51 @@ constexpr int kLargeSeg = 16;       // blocks with more intervals reduce per wor
 constexpr int kAlign = 256;
 
 // Storage formats (hm_dtype): F64, F32, F16, BF16, DFL32, DFL40, DFL48,
-// DFL16, DFL24.
-constexpr int kNumDtypes = 9;
+// DFL16, DFL24, AFLP16, AFLP24, AFLP32, AFLP40, AFLP48.
+constexpr int kNumDtypes = 14;
 constexpr int kDtDfl32 = 4, kDtDfl40 = 5, kDtDfl48 = 6, kDtDfl16 = 7, kDtDfl24 = 8;
+constexpr int kDtAflp16 = 9, kDtAflp24 = 10, kDtAflp32 = 11, kDtAflp40 = 12, kDtAflp48 = 13;
+
+inline constexpr bool is_dfl(int dt) { return dt >= kDtDfl32 && dt <= kDtDfl24; }
+inline constexpr bool is_aflp(int dt) { return dt >= kDtAflp16 && dt <= kDtAflp48; }
+// AFLP values of B bytes are stored like the DFL values of B bytes (a
+// left-aligned B-byte code split into the same leading and low parts).
+inline constexpr int storage_dt(int dt) {
+  return dt == kDtAflp16 ? kDtDfl16 : dt == kDtAflp24 ? kDtDfl24 : dt == kDtAflp32 ? kDtDfl32
+       : dt == kDtAflp40 ? kDtDfl40 : dt == kDtAflp48 ? kDtDfl48 : dt;
+}
 
 // Columns per 16-byte group for a storage dtype.  A DFL value keeps its
 // leading 4 bytes (DFL32 / 40 / 48: the high 32-bit word of its FP64
 // encoding) or 2 bytes (DFL16 / 24: the high 16 bits) in the group.
 inline constexpr int group_width(int dt) {
-  return dt == 0 ? 2 : (dt == 2 || dt == 3 || dt == kDtDfl16 || dt == kDtDfl24) ? 8 : 4;
+  return dt == 0 ? 2 : (dt == 2 || dt == 3 || storage_dt(dt) == kDtDfl16 || storage_dt(dt) == kDtDfl24) ? 8 : 4;
 }
 // Bytes per value inside the 16-byte groups.
 inline constexpr int dtype_size(int dt) { return 16 / group_width(dt); }
 // DFL40 / DFL48 / DFL24 keep the rest of each value (1 / 2 / 1 bytes: bits
 // 31..24 / 31..16 / 47..40 of the encoding) in a low-byte plane: lo_bytes
 // per 16-byte group element (4, 8 or 8 values), 0 for the other formats.
-inline constexpr int lo_bytes(int dt) { return dt == kDtDfl40 ? 4 : (dt == kDtDfl48 || dt == kDtDfl24) ? 8 : 0; }
+inline constexpr int lo_bytes(int dt) {
+  return storage_dt(dt) == kDtDfl40 ? 4 : (storage_dt(dt) == kDtDfl48 || storage_dt(dt) == kDtDfl24) ? 8 : 0;
+}
 // Stored bytes per value.
 inline constexpr int value_bytes(int dt) { return dtype_size(dt) + lo_bytes(dt) / group_width(dt); }
-inline constexpr bool is_dfl(int dt) { return dt >= kDtDfl32 && dt <= kDtDfl24; }
+
+// AFLP (Sec. 3.2) of one data block (a dense block, or the columns of one
+// column group of U_b or of V_b): with 2^k the power of two at or below the
+// block's smallest nonzero magnitude, a value v is stored through
+// d = |v| 2^-k + 1 >= 2 rounded to m mantissa bits: a B-byte code holding
+// the sign, e bits of the binary exponent of d (1 .. 2^e - 1; 0 is the code
+// of zero, d = 1) and the m = 8B - 1 - e leading mantissa bits of d.  With
+// the code left-aligned in 64 bits (P, as a DFL encoding), the decoded value
+// is sign(P) (d - 1) 2^k with d the FP64 number of bits
+// ((P & ~sign) >> (11 - e)) + bits(1.0).  Per column, the store keeps
+// aflp_param(k, e): the kernels scale by 2^k where it is exact (x and t
+// gathered for a row panel, a column tile's sums) and decode d - 1.
+inline constexpr int32_t aflp_param(int k, int e) { return k * 256 + (11 - e); }
+inline constexpr int aflp_scale_exp(int32_t p) { return p >> 8; }    // k (arithmetic shift)
+inline constexpr int aflp_shift(int32_t p) { return p & 0xff; }      // 11 - e
 
 struct RowPanel {        // 32 bytes
   int64_t src_off;       // first entry (int32 units) in the row-source table
@@ -153,6 +181,11 @@ struct StoreHeader {
   // the blocks inside one column chunk, [n_red_t, n_t), get t directly from
   // the column tiles
   int64_t n_red_t;
+  // AFLP: one aflp_param per row-source slot (off_row_aflp, n_row_src
+  // entries, parallel to the row-source table) and per column-tile column
+  // (off_col_aflp, parallel to the destination table); 0 for the columns of
+  // other formats.  has_aflp = 0: no AFLP data and no such tables.
+  int64_t has_aflp, off_row_aflp, off_col_aflp;
   // column tiles by class: tiles of one storage format f are
   // [tile_class_end[f-1], tile_class_end[f]) (tile_class_end[-1] = 0), tiles
   // with runs of several formats [tile_class_end[kNumDtypes-1],
@@ -172,6 +205,6 @@ inline constexpr int tile_class(const ColTile& T) {
   return T.end[0] == T.ngroups ? T.dtype[0] : kNumDtypes;
 }
 
-constexpr uint64_t kStoreMagic = 0x484d53544f524533ull;  // "HMSTORE3"
+constexpr uint64_t kStoreMagic = 0x484d53544f524534ull;  // "HMSTORE4"
 
 }  // namespace hm

@@ -1,6 +1,6 @@
-"""GPU parity of the byte-aligned truncated FP64 storage formats (DFL,
-Sec. 3.2) with FP64 accumulation, through the C-ABI, one format per matrix
-or chosen per column (APLR, Sec. 3.3).
+"""GPU parity of the byte-aligned storage formats of Sec. 3.2 (truncated
+FP64: DFL; adaptive exponent: AFLP) with FP64 accumulation, through the
+C-ABI, one format per matrix or block, or chosen per column (APLR, Sec. 3.3).
 
 The kernels decode DFL exactly to FP64, so the product must match the oracle
 evaluated on the DFL-rounded factors to the FP64 bar (relative 2-norm error
@@ -9,8 +9,10 @@ FP64 product the error is the storage rounding, stated and bounded by the
 format's unit roundoff.  Layouts: one format everywhere (DFL32, DFL40 with
 partials at n = 16384, DFL48), dense blocks in DFL48 and FP64 beside
 low-rank DFL32, and FP32 storage (BFL at 4 bytes) under FP64 accumulation;
-both schedules, persistent grids and a graph replay; the
-full n = 2^18 sizes at eps 1e-6 (DFL32; APLR) and 1e-8 (DFL40; APLR).
+AFLP per block (sphere4k_aflp), and AFLP of every width beside DFL32 and
+FP64 in column groups with partials at n = 16384; both schedules,
+persistent grids and a graph replay; the full n = 2^18 sizes at eps 1e-6
+(DFL32; APLR; AFLP) and 1e-8 (DFL40; APLR; AFLP).
 """
 
 import os
@@ -56,10 +58,46 @@ def abs_bound(H, x, factors):
     return oracle.hmvm(H, np.abs(x), factors=fac)
 
 
+AFLP = {hm.HM_AFLP16: 2, hm.HM_AFLP24: 3, hm.HM_AFLP32: 4, hm.HM_AFLP40: 5, hm.HM_AFLP48: 6}
+
+
+def aflp_bound(H):
+    """4 x the largest relative rounding error of H's data blocks: 2^-m for
+    an AFLP block of m mantissa bits (|v - fl(v)| <= 2^-(m+1) (|v| + 2^k)
+    with 2^k <= |v|), the unit roundoff for DFL / FP64."""
+    worst = 2.0 ** -53
+    for i in range(H.nblocks):
+        a, b, _ = H.factors(i)
+        c0 = 0
+        for g in range(int(H.ngroups[i])):
+            dt = int(H.group_dtype[i, g])
+            kc = int(H.group_cols[i, g]) if H.adm[i] else a.shape[1]
+            for F in (a, b):
+                if F is None or kc == 0:
+                    continue
+                blk = F[:, c0:c0 + kc]
+                if dt in AFLP:
+                    worst = max(worst, 2.0 ** -oracle.aflp_params(blk, AFLP[dt])[2])
+                elif dt in MANT:
+                    worst = max(worst, 2.0 ** -(MANT[dt] + 1))
+            c0 += kc
+    return 4 * worst
+
+
 def layout(name):
     """(H, bound on the relative error against the unrounded FP64 product:
     4 x the largest unit roundoff of its formats, or for APLR eps) for a
-    named DFL layout."""
+    named DFL or AFLP layout."""
+    if name == "aflp":
+        H = hmgen.build_preset("sphere4k_aflp")
+        return H, aflp_bound(H)
+    if name == "aflp_any_16k":
+        # AFLP of every width beside DFL32 and FP64, in up to 4 column
+        # groups per block, at n = 16384 (partials)
+        H = hmgen.build_preset("sphere4k", n=16384, eps=1e-10)
+        _groups(H, [hm.HM_F64, hm.HM_DFL32, hm.HM_AFLP16, hm.HM_AFLP24, hm.HM_AFLP32, hm.HM_AFLP40,
+                    hm.HM_AFLP48], np.random.default_rng(4))
+        return H, aflp_bound(H)
     if name == "aplr":
         # per-column formats from DFL16 to FP64, every block within eps / 2
         H = hmgen.build_preset("sphere4k_aplr")
@@ -89,12 +127,13 @@ def check(y, ref, scale, what):
     assert np.all(np.abs(y - ref) <= 1e-13 * scale + 1e-300)
 
 
-@pytest.mark.parametrize("name", ["dfl32", "dfl40_16k", "dfl48", "dfl_mix", "bfl32", "aplr"])
+@pytest.mark.parametrize("name", ["dfl32", "dfl40_16k", "dfl48", "dfl_mix", "bfl32", "aplr", "aflp",
+                                  "aflp_any_16k"])
 def test_dfl_parity(name):
     H, bound = layout(name)
     say("layout", name, "n", H.n)
     D = DeviceHMatrix(H, hm.HM_F64)
-    if name == "dfl40_16k":
+    if name.endswith("_16k"):
         assert D.info["n_partials"] > 0
     x = hmgen.uniform_vector(H.n)
     y0 = hmgen.uniform_vector(H.n, seed=9)
@@ -150,7 +189,7 @@ def test_dfl_graph_replay():
 
 
 @pytest.mark.parametrize("name", ["sphere256k_dfl", "sphere256k_e8_dfl", "sphere256k_aplr",
-                                  "sphere256k_e8_aplr"])
+                                  "sphere256k_e8_aplr", "sphere256k_aflp", "sphere256k_e8_aflp"])
 def test_dfl_full_size(name):
     say("building", name)
     H = hmgen.build_preset(name)
@@ -178,14 +217,9 @@ def test_dfl_full_size(name):
     D.close()
 
 
-def _random_layout(seed):
-    """Random per-group formats (all nine with FP64 accumulation, the 16/32-bit
-    IEEE ones with FP32) and a random column-tile shape, n = 16384."""
-    rng = np.random.default_rng(seed)
-    H = hmgen.build_preset("sphere4k_mixed", n=16384)
-    acc = hm.HM_F64 if seed % 2 else hm.HM_F32
-    fmts = ([hm.HM_F64, hm.HM_F32, hm.HM_F16, hm.HM_BF16, hm.HM_DFL16, hm.HM_DFL24, hm.HM_DFL32,
-             hm.HM_DFL40, hm.HM_DFL48] if acc == hm.HM_F64 else [hm.HM_F32, hm.HM_F16, hm.HM_BF16])
+def _groups(H, fmts, rng):
+    """Every low-rank block split into up to 4 column groups with formats
+    drawn from fmts (dense blocks one format each)."""
     H.set_uniform_dtype(fmts[0])
     for i in range(H.nblocks):
         if not H.adm[i]:
@@ -202,6 +236,18 @@ def _random_layout(seed):
         H.group_cols[i, :ng] = sizes
         H.group_dtype[i, :] = 0
         H.group_dtype[i, :ng] = [fmts[j] for j in rng.integers(len(fmts), size=ng)]
+
+
+def _random_layout(seed):
+    """Random per-group formats (all fourteen with FP64 accumulation, the
+    16/32-bit IEEE ones with FP32) and a random column-tile shape, n = 16384."""
+    rng = np.random.default_rng(seed)
+    H = hmgen.build_preset("sphere4k_mixed", n=16384)
+    acc = hm.HM_F64 if seed % 2 else hm.HM_F32
+    fmts = ([hm.HM_F64, hm.HM_F32, hm.HM_F16, hm.HM_BF16, hm.HM_DFL16, hm.HM_DFL24, hm.HM_DFL32,
+             hm.HM_DFL40, hm.HM_DFL48, hm.HM_AFLP16, hm.HM_AFLP24, hm.HM_AFLP32, hm.HM_AFLP40, hm.HM_AFLP48]
+            if acc == hm.HM_F64 else [hm.HM_F32, hm.HM_F16, hm.HM_BF16])
+    _groups(H, fmts, rng)
     return H, acc, int(rng.integers(64, 513)), int(rng.integers(8, 65))
 
 
