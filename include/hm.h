@@ -273,6 +273,21 @@ hm_status hm_matrix_set_launch(hm_matrix* A, const char* params);
 hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len);
 hm_status hm_matrix_tune_key(const hm_matrix* A, char* buf, size_t len);
 
+/* Reorders vectors between the caller's index order and the cluster order
+ * every product uses (the cluster tree orders the index set, Sec. 2.1; the
+ * block table's ranges are in cluster order).  Not part of a product.
+ * d_perm: device int64[n], perm[i] = caller index of cluster position i (a
+ * permutation of [0, n)).  direction 0: out[i] = in[perm[i]] (into cluster
+ * order); 1: out[perm[i]] = in[i] (back).  nvec vectors, column-major with
+ * leading dimensions ld_in, ld_out >= n; dtype HM_F64 or HM_F32 (in and out
+ * alike).  in and out must not overlap.  A perm entry outside [0, n) is
+ * never dereferenced: direction 0 writes NaN at that position, direction 1
+ * writes nothing for it.  Stream-ordered; returns after enqueueing.
+ * Errors: HM_EINVAL (NULL pointers, n < 1, nvec < 1, ld < n, direction),
+ * HM_EDTYPE (dtype), HM_EDEVICE (launch failure). */
+hm_status hm_permute(const int64_t* d_perm, int64_t n, int32_t dtype, int32_t direction, int32_t nvec,
+                     const void* d_in, int64_t ld_in, void* d_out, int64_t ld_out, void* stream);
+
 /* Streaming-read probe for measurement: reads `bytes` (a multiple of 16) of
  * device memory at d_buf with the 16-byte loads the kernels use, on stream.
  * d_out: device memory of >= 4 bytes (written only in a case that does not

@@ -23,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-HIP_SOURCES = ["hm_kernels.hip", "hm_kernels_batch.hip"]
+HIP_SOURCES = ["hm_kernels.hip", "hm_kernels_batch.hip", "hm_kernels_util.hip"]
 HOST_SOURCES = ["hm_host.cpp", "hm_server.cpp"]
 
 

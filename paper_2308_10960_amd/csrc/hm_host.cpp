@@ -1642,6 +1642,20 @@ hm_status hm_stream_read(const void* d_buf, size_t bytes, void* d_out, void* str
   return ok();
 }
 
+hm_status hm_permute(const int64_t* d_perm, int64_t n, int32_t dtype, int32_t direction, int32_t nvec,
+                     const void* d_in, int64_t ld_in, void* d_out, int64_t ld_out, void* stream) {
+  if (!d_perm || !d_in || !d_out) return fail(HM_EINVAL, "NULL argument");
+  if (n < 1 || nvec < 1 || ld_in < n || ld_out < n)
+    return fail(HM_EINVAL, "bad sizes n=%lld nvec=%d ld_in=%lld ld_out=%lld", (long long)n, nvec,
+                (long long)ld_in, (long long)ld_out);
+  if (direction != 0 && direction != 1) return fail(HM_EINVAL, "direction must be 0 or 1");
+  if (dtype != HM_F64 && dtype != HM_F32) return fail(HM_EDTYPE, "dtype must be HM_F64 or HM_F32");
+  hipError_t e = launch_permute(d_perm, n, dtype == HM_F64 ? 8 : 4, direction, nvec, d_in, ld_in, d_out, ld_out,
+                                (hipStream_t)stream);
+  if (e != hipSuccess) return fail(HM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
 const char* hm_last_error(void) { return hm::g_err.c_str(); }
 
 }  // extern "C"

@@ -83,6 +83,7 @@ PROTOTYPES = {
     "hm_matrix_get_launch": (_i32, [_vp, C.c_char_p, _sz]),
     "hm_matrix_tune_key": (_i32, [_vp, C.c_char_p, _sz]),
     "hm_stream_read": (_i32, [_vp, _sz, _vp, _vp]),
+    "hm_permute": (_i32, [_vp, _i64, _i32, _i32, _i32, _vp, _i64, _vp, _i64, _vp]),
     "hm_server_create": (_i32, [_P(_vp), _i32, _vp, _sz, _P(_vp), _i32, _P(_vp)]),
     "hm_submit": (_i32, [_vp, _i32, _i32, _vp, _i64, _vp, _i64, _P(C.c_uint64)]),
     "hm_poll": (_i32, [_vp, C.c_uint64, _P(_i32), _P(_i32)]),
@@ -259,6 +260,12 @@ def hm_matrix_tune_key(mat: int) -> str:
     buf = C.create_string_buffer(128)
     _check(lib().hm_matrix_tune_key(mat, buf, 128), "hm_matrix_tune_key")
     return buf.value.decode()
+
+
+def hm_permute(d_perm, n: int, dtype: int, direction: int, nvec: int, d_in, ld_in: int, d_out, ld_out: int,
+               stream=None) -> None:
+    _check(lib().hm_permute(_ptr(d_perm), n, dtype, direction, nvec, _ptr(d_in), ld_in, _ptr(d_out), ld_out,
+                            _stream(stream)), "hm_permute")
 
 
 def hm_stream_read(d_buf, nbytes: int, d_out, stream=None) -> None:

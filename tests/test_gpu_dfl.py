@@ -163,10 +163,11 @@ def test_dfl_parity(name):
     D.close()
 
 
-def test_dfl_graph_replay():
-    """A captured single-RHS product of a DFL store replays bit for bit like
-    the eager call, also with eager work between the replays."""
-    H, _ = layout("dfl_mix")
+@pytest.mark.parametrize("name", ["dfl_mix", "aflp_any_16k"])
+def test_dfl_graph_replay(name):
+    """A captured single-RHS product of a DFL / AFLP store replays bit for
+    bit like the eager call, also with eager work between the replays."""
+    H, _ = layout(name)
     D = DeviceHMatrix(H, hm.HM_F64)
     x = hmgen.uniform_vector(H.n)
     xd = D.vector(x)
@@ -185,6 +186,23 @@ def test_dfl_graph_replay():
             run(D, x)                                   # eager work in between
     finally:
         hm.hm_graph_destroy(g)
+    D.close()
+
+
+def test_aflp_batch_equals_single():
+    """hm_mvm_batch on an AFLP store (FP64 accumulation: right-hand sides
+    one by one) gives each column bit for bit as hm_mvm does."""
+    H, _ = layout("aflp")
+    D = DeviceHMatrix(H, hm.HM_F64, max_nrhs=3)
+    X = np.stack([hmgen.uniform_vector(H.n, seed=20 + j) for j in range(3)])
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.zeros_like(Xd)
+    hm.hm_mvm_batch(D.handle, 3, 0.5, Xd, H.n, Yd, H.n, D.work, D.work.numel())
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy()
+    for j in range(3):
+        y = run(D, X[j], alpha=0.5)
+        np.testing.assert_array_equal(Y[j], y)
     D.close()
 
 
