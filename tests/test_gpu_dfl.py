@@ -98,6 +98,10 @@ def layout(name):
         _groups(H, [hm.HM_F64, hm.HM_DFL32, hm.HM_AFLP16, hm.HM_AFLP24, hm.HM_AFLP32, hm.HM_AFLP40,
                     hm.HM_AFLP48], np.random.default_rng(4))
         return H, aflp_bound(H)
+    if name == "aflp_zeros":
+        H, _ = layout("aflp")
+        _plant_zeros(H)
+        return H, aflp_bound(H)
     if name == "aplr":
         # per-column formats from DFL16 to FP64, every block within eps / 2
         H = hmgen.build_preset("sphere4k_aplr")
@@ -128,7 +132,7 @@ def check(y, ref, scale, what):
 
 
 @pytest.mark.parametrize("name", ["dfl32", "dfl40_16k", "dfl48", "dfl_mix", "bfl32", "aplr", "aflp",
-                                  "aflp_any_16k"])
+                                  "aflp_any_16k", "aflp_zeros"])
 def test_dfl_parity(name):
     H, bound = layout(name)
     say("layout", name, "n", H.n)
@@ -233,6 +237,20 @@ def test_dfl_full_size(name):
     eps = hmgen.preset(name)["eps"]
     assert rel_truth <= eps
     D.close()
+
+
+def _plant_zeros(H, seed=6):
+    """Exact zeros in the factors (the AFLP zero code): 10% of the entries
+    of every fifth block, one whole dense block and one whole V_b."""
+    rng = np.random.default_rng(seed)
+    dense = np.flatnonzero(H.adm == 0)
+    lowr = np.flatnonzero((H.adm != 0) & (H.rank > 0))
+    for i in range(0, H.nblocks, 5):
+        for F in H.factors(i)[:2]:
+            if F is not None and F.size:
+                F[rng.random(F.shape) < 0.1] = 0.0
+    H.factors(int(dense[3]))[0][:] = 0.0
+    H.factors(int(lowr[7]))[1][:] = 0.0
 
 
 def _groups(H, fmts, rng):

@@ -305,7 +305,7 @@ def test_dfl_plan_rules():
 
 @pytest.mark.parametrize("which", ["f64", "mixed", "mixed16k", "bf16", "dfl32", "dfl40_16k", "dfl48",
                                    "dfl_mix", "dfl_any_16k", "dfl16", "dfl24", "aplr", "aflp",
-                                   "aflp_any_16k"])
+                                   "aflp_any_16k", "aflp_zeros"])
 def test_store_model_matches_oracle(which, f64_4k, mixed4k):
     """The packed store, read as its layout defines it, gives the oracle's
     product.  At n = 16384 some blocks span several column chunks (partials
@@ -321,8 +321,15 @@ def test_store_model_matches_oracle(which, f64_4k, mixed4k):
         H.set_uniform_dtype(hm.HM_BF16)
     elif which == "aplr":
         H = hmgen.build_preset("sphere4k_aplr")
-    elif which == "aflp":
+    elif which in ("aflp", "aflp_zeros"):
         H = hmgen.build_preset("sphere4k_aflp")
+        if which == "aflp_zeros":                      # the zero code, an all-zero data block
+            rng = np.random.default_rng(6)
+            for i in range(0, H.nblocks, 5):
+                for F in H.factors(i)[:2]:
+                    if F is not None and F.size:
+                        F[rng.random(F.shape) < 0.1] = 0.0
+            H.factors(int(np.flatnonzero(H.adm == 0)[3]))[0][:] = 0.0
     elif which == "aflp_any_16k":
         H = hmgen.build_preset("sphere4k", n=16384, eps=1e-10)
         _aplr_like(H, [hm.HM_F64, hm.HM_DFL32, hm.HM_AFLP16, hm.HM_AFLP24, hm.HM_AFLP32, hm.HM_AFLP40,
