@@ -914,6 +914,7 @@ hm_status AflpTable::build(const hm_plan* P, const double* const* a, const doubl
     n += b.kind == HM_DENSE ? 1 : 2 * b.ngroups;
   }
   prm.assign((size_t)n, 0);
+  if (n == 0) return HM_OK;                        // no AFLP data
   std::atomic<int64_t> bad{-1};
   parallel_for(P->blocks.size(), [&](size_t i) {
     if (base[i] < 0) return;
