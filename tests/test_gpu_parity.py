@@ -144,6 +144,14 @@ def test_degenerate_partitions(case):
     x = hmgen.uniform_vector(H.n, seed=2)
     check_f64(run(D, x), oracle.hmvm(H, x), abs_bound(H, x))
     D.close()
+    # the same partition in the byte-aligned formats (FP64 accumulation):
+    # 2-byte AFLP (data blocks down to one value) and 3-byte DFL
+    for dt in (hm.HM_AFLP16, hm.HM_DFL24):
+        H.set_uniform_dtype(dt)
+        D = DeviceHMatrix(H, hm.HM_F64)
+        dec = oracle.decoded_factors(H, sigma_dtype=oracle.F64)
+        check_f64(run(D, x), oracle.hmvm(H, x, factors=dec), abs_bound(H, x, dec))
+        D.close()
     # the same partition in FP32 storage through the batched (MFMA) path
     H.set_uniform_dtype(hmm.DT_F32)
     D = DeviceHMatrix(H, hm.HM_F32, max_nrhs=3)
