@@ -69,7 +69,9 @@ __device__ __forceinline__ double aflp_value(u32x4 r, u32x2 lo, int c, unsigned 
   const unsigned long long P = dfl_bits<storage_dt(DT)>(r, lo, c);
   const unsigned long long d = ((P & 0x7fffffffffffffffull) >> sh) + 0x3ff0000000000000ull;
   const double w = __longlong_as_double((long long)d) - 1.0;
-  return __longlong_as_double(__double_as_longlong(w) | (long long)(P & 0x8000000000000000ull));
+  // P's sign into w's high word (one bit-field insert)
+  const unsigned hi = ((unsigned)(P >> 32) & 0x80000000u) | ((unsigned)__double2hiint(w) & 0x7fffffffu);
+  return __hiloint2double((int)hi, __double2loint(w));
 }
 
 // The low-byte plane entry idx of a DFL40 / DFL48 / DFL24 region at p
@@ -87,21 +89,18 @@ __device__ __forceinline__ u32x2 ld_lo(const uint8_t* p, int64_t idx) {
 
 // acc += sum_c v[c] * z[c] over one 16-byte group of storage format DT
 // (lo: its low-byte plane entry, 40 / 48 / 24-bit formats only; AFLP: sh
-// the columns' shifts, z already scaled by the columns' 2^k).
+// the columns' shifts, 16-byte aligned, z already scaled by the columns' 2^k).
 template <typename AccT, int DT>
 __device__ __forceinline__ AccT dot_group(u32x4 r, u32x2 lo, const AccT* __restrict__ z,
-                                          const uint8_t* __restrict__ sh, AccT acc) {
+                                          const uint32_t* __restrict__ sh, AccT acc) {
   if constexpr (is_aflp(DT)) {
     constexpr int G = group_width(DT);
     unsigned s[G];
-    if constexpr (G == 4) {
-      const unsigned w = *reinterpret_cast<const unsigned*>(sh);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) s[c] = (w >> (8 * c)) & 0xffu;
-    } else {
-      const u32x2 w = *reinterpret_cast<const u32x2*>(sh);
+    for (int q = 0; q < G / 4; ++q) {
+      const u32x4 w = *reinterpret_cast<const u32x4*>(sh + 4 * q);
 #pragma unroll
-      for (int c = 0; c < 8; ++c) s[c] = (w[c >> 2] >> (8 * (c & 3))) & 0xffu;
+      for (int c = 0; c < 4; ++c) s[4 * q + c] = w[c];
     }
 #pragma unroll
     for (int c = 0; c < G; ++c) acc = fmaT((AccT)aflp_value<DT>(r, lo, c, s[c]), z[c], acc);
@@ -454,7 +453,7 @@ constexpr int kXfDfl = 1, kXfAflp = 2;
 // lo_base), groups g_lo + wave, + 4, ... for this wave.
 template <typename AccT, int DT, int U>
 __device__ __forceinline__ AccT row_section(const uint8_t* base, const uint8_t* lo_base, int m, int g_lo,
-                                            int g_hi, const AccT* z, const uint8_t* shz, int lane, int wave,
+                                            int g_hi, const AccT* z, const uint32_t* shz, int lane, int wave,
                                             AccT acc) {
   constexpr int G = group_width(DT);
   const u32x4* p = reinterpret_cast<const u32x4*>(base) + lane;
@@ -484,11 +483,11 @@ __device__ __forceinline__ AccT row_section(const uint8_t* base, const uint8_t* 
 // Called by whole workgroups (it synchronizes).
 // XF: the store holds DFL / AFLP sections (decoded only by such
 // instantiations).  AFLP: a slot's source is staged times its column's 2^k
-// (exact) and its shift beside it (shs, CAP bytes).
+// (exact) and its shift beside it (shs, CAP words).
 template <typename AccT, int CAP, int U, int XF>
 __device__ __forceinline__ void row_panel_part(const RowArgs<AccT>& a, const RowPanel& P,
                                                int q_begin, int q_end, int s_begin, int s_end,
-                                               AccT* zs, AccT (*red)[64], uint8_t* shs) {
+                                               AccT* zs, AccT (*red)[64], uint32_t* shs) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   AccT acc = AccT(0);
   const int32_t* src = a.src + P.src_off;
@@ -500,7 +499,7 @@ __device__ __forceinline__ void row_panel_part(const RowArgs<AccT>& a, const Row
       if constexpr ((XF & kXfAflp) != 0) {
         const int32_t q = a.aflp[P.src_off + c];
         z = ldexp(z, aflp_scale_exp(q));
-        shs[c - c_lo] = (uint8_t)aflp_shift(q);
+        shs[c - c_lo] = (uint32_t)aflp_shift(q);
       }
       zs[c - c_lo] = z;
     }
@@ -515,7 +514,7 @@ __device__ __forceinline__ void row_panel_part(const RowArgs<AccT>& a, const Row
         const uint8_t* base = a.store + S.data_off;
         const uint8_t* lob = base + (int64_t)16 * S.ngroups * P.m;   // low-byte plane (40 / 48 / 24 bits)
         const AccT* z = zs + (S.col0 - c_lo);
-        const uint8_t* sz = shs + (S.col0 - c_lo);
+        const uint32_t* sz = shs + (S.col0 - c_lo);
 #define HM_ROW_SECTION(D) acc = row_section<AccT, D, U>(base, lob, P.m, g_lo, g_hi, z, sz, lane, wave, acc)
         switch (S.dtype) {
           case HM_F32: HM_ROW_SECTION(HM_F32); break;
@@ -569,7 +568,7 @@ __global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, 
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
   __shared__ AccT pxs[kSegRows];
-  __shared__ __align__(16) uint8_t shs[(XF & kXfAflp) ? CAP : 8];
+  __shared__ __align__(16) uint32_t shs[(XF & kXfAflp) ? CAP : 4];
   constexpr int KIND =
       kColIeee | kColMulti | ((XF & kXfDfl) ? kColDfl : 0) | ((XF & kXfAflp) ? kColAflp : 0);
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -589,7 +588,7 @@ template <typename AccT, int CAP, int U, int XF>
 __global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* order, int64_t n_items) {
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
-  __shared__ __align__(16) uint8_t shs[(XF & kXfAflp) ? CAP : 8];
+  __shared__ __align__(16) uint32_t shs[(XF & kXfAflp) ? CAP : 4];
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     if (it != blockIdx.x) __syncthreads();
     const RowPanel P = ra.rp[order[it]];
@@ -619,7 +618,7 @@ __global__ __launch_bounds__(256) void k_row(RowArgs<AccT> ra, const int32_t* or
                                              int64_t n_items) {
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
-  __shared__ __align__(16) uint8_t shs[(XF & kXfAflp) ? CAP : 8];
+  __shared__ __align__(16) uint32_t shs[(XF & kXfAflp) ? CAP : 4];
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int pi = panel_of(order, n_panels, it);
     if (pi < 0) continue;                           // uniform: whole workgroup
@@ -748,9 +747,12 @@ hipError_t launch_typed(const hm_matrix& A, double alpha, const void* x, void* y
       aflp = aflp || (is_aflp(d) && A.bytes_by_dtype[d] > 0);
     }
     constexpr int kAll = kXfDfl | kXfAflp;
-    if (aflp)
+    if (aflp && dfl)
       return u8 ? launch_typed_u<AccT, 8, kAll>(A, alpha, x, y, work, s, ev)
                 : launch_typed_u<AccT, 4, kAll>(A, alpha, x, y, work, s, ev);
+    if (aflp)
+      return u8 ? launch_typed_u<AccT, 8, kXfAflp>(A, alpha, x, y, work, s, ev)
+                : launch_typed_u<AccT, 4, kXfAflp>(A, alpha, x, y, work, s, ev);
     if (dfl)
       return u8 ? launch_typed_u<AccT, 8, kXfDfl>(A, alpha, x, y, work, s, ev)
                 : launch_typed_u<AccT, 4, kXfDfl>(A, alpha, x, y, work, s, ev);

@@ -16,6 +16,7 @@ import os
 from . import hm
 
 CANDIDATES = ["schedule=0 unroll=4 order=0 persist=0", "schedule=0 unroll=8 order=0 persist=0",
+              "schedule=0 unroll=4 order=1 persist=0",
               "schedule=0 unroll=8 order=1 persist=0", "schedule=0 unroll=8 order=1 persist=4",
               "schedule=0 unroll=8 order=1 persist=8", "schedule=1 unroll=4 order=0 persist=0",
               "schedule=1 unroll=8 order=0 persist=0", "schedule=1 unroll=8 order=0 persist=8"]
