@@ -114,11 +114,13 @@ def test_sphere4k_f64(sphere4k):
 def test_store_upload_matches_host_packing(sphere4k, window, monkeypatch):
     """The device store equals the host packing byte for byte, also when the
     upload streams the factor data in many small windows (the window grows
-    to the largest packing job where that is larger)."""
+    to the largest packing job where that is larger); for AFLP the data
+    blocks' parameters, derived once, serve every window."""
     if window is not None:
         monkeypatch.setenv("HM_UPLOAD_WINDOW_BYTES", str(window))
     for name, H, acc in [("sphere4k", sphere4k, hm.HM_F64),
-                         ("sphere4k_mixed", hmgen.build_preset("sphere4k_mixed"), hm.HM_F32)]:
+                         ("sphere4k_mixed", hmgen.build_preset("sphere4k_mixed"), hm.HM_F32),
+                         ("sphere4k_aflp", hmgen.build_preset("sphere4k_aflp"), hm.HM_F64)]:
         say("upload", name, window)
         D = DeviceHMatrix(H, acc)
         buf = np.zeros(D.info["store_bytes"], np.uint8)
