@@ -12,7 +12,9 @@ directly from FP64:
   a whole number of bytes) is rounded here from its definition;
   AFLP (Sec. 3.2: per data block, values scaled and shifted by 1, only the
   exponent bits the block's range needs, the mantissa filling the bytes)
-  is rounded here from its definition, one data block per call.
+  is rounded here from its definition, one data block per call;
+  BFL (Sec. 3.2: FP32's sign and 8 exponent bits, the mantissa filling
+  whole bytes) is rounded here from its definition.
 Parity pins for every function live in tests/test_oracle_*.py.
 """
 
@@ -35,6 +37,8 @@ DFL32, DFL40, DFL48, DFL16, DFL24 = 4, 5, 6, 7, 8
 DFL_BYTES = {DFL32: 4, DFL40: 5, DFL48: 6, DFL16: 2, DFL24: 3}
 AFLP16, AFLP24, AFLP32, AFLP40, AFLP48 = 9, 10, 11, 12, 13
 AFLP_BYTES = {AFLP16: 2, AFLP24: 3, AFLP32: 4, AFLP40: 5, AFLP48: 6}
+BFL24, BFL40, BFL48 = 14, 15, 16
+BFL_BYTES = {BFL24: 3, BFL40: 5, BFL48: 6}
 
 # Table 1: unit roundoff u = 2^-(m+1) for m explicit mantissa bits.
 UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "tf32": 2.0 ** -11,
@@ -117,6 +121,31 @@ def round_dfl(x, nbytes: int) -> np.ndarray:
     return out
 
 
+def round_bfl(x, nbytes: int) -> np.ndarray:
+    """RNE of FP64 values to the BFL format of nbytes bytes (Sec. 3.2).
+
+    Written from the format definition: sign, FP32's 8 exponent bits (bias
+    127) and m = 8 nbytes - 9 explicit mantissa bits; 2 and 4 bytes are
+    BF16 and FP32.  Reading: magnitudes that round below the smallest normal
+    value 2^-126 become zero (no subnormals), and values that round beyond
+    the largest finite value raise ValueError (no infinities).
+    """
+    m = 8 * nbytes - 9
+    x = np.asarray(x, dtype=np.float64)
+    if not np.all(np.isfinite(x)):
+        raise ValueError("BFL: values must be finite")
+    out = np.zeros_like(x)
+    nz = x != 0
+    xf = x[nz]
+    _, e = np.frexp(xf)                          # |x| = f 2^e, f in [0.5, 1)
+    lsb = e - 1 - m                              # exponent of the last kept bit
+    r = np.ldexp(np.rint(np.ldexp(xf, -lsb)), lsb)
+    if np.any(np.abs(r) >= 2.0 ** 128):
+        raise ValueError("BFL: value beyond the largest finite value")
+    out[nz] = np.where(np.abs(r) < 2.0 ** -126, 0.0, r)
+    return out
+
+
 def _rne_bits(d: np.ndarray, m: int) -> np.ndarray:
     """RNE of positive normal FP64 values to m explicit mantissa bits."""
     _, e = np.frexp(d)                           # d = f 2^e, f in [0.5, 1)
@@ -182,6 +211,8 @@ def round_to(x, dt: int) -> np.ndarray:
         return round_dfl(x, DFL_BYTES[dt])
     if dt in AFLP_BYTES:
         return round_aflp(x, AFLP_BYTES[dt])
+    if dt in BFL_BYTES:
+        return round_bfl(x, BFL_BYTES[dt])
     if dt == F32:
         return round_f32(x)
     if dt == F16:

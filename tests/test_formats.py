@@ -289,3 +289,68 @@ def test_aflp_rejects_unrepresentable_blocks():
     with pytest.raises(ValueError):
         oracle.aflp_params(np.array([1e-300, 1e300]), 4)      # shifted range overflows
     np.testing.assert_array_equal(oracle.round_aflp(np.zeros(5), 3), np.zeros(5))
+
+
+# ------------------------------------------------------------------ BFL (Sec. 3.2)
+
+def _keep_top_bits(x: np.ndarray, m: int) -> np.ndarray:
+    """Independent rounding of FP64 values to m explicit mantissa bits on
+    the bit pattern (integer RNE of the dropped bits; a carry runs into the
+    exponent): the significand rounding of any binary format with m bits,
+    whatever its exponent range, for values inside that range."""
+    b = np.ascontiguousarray(x, dtype=np.float64).view(np.uint64).astype(object)
+    drop = 52 - m
+    out = []
+    for v in b:
+        kept, rem, half = v >> drop, v & ((1 << drop) - 1), 1 << (drop - 1)
+        if rem > half or (rem == half and kept & 1):
+            kept += 1
+        out.append((kept << drop) & ((1 << 64) - 1))
+    return np.array(out, dtype=np.uint64).view(np.float64)
+
+
+def test_bfl_four_bytes_is_fp32():
+    """BFL at 4 bytes (8 exponent, 23 mantissa bits) is FP32: equal to
+    numpy's correctly rounded float32 conversion over FP32's normal range."""
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(20000) * np.exp2(rng.integers(-120, 120, 20000).astype(float))
+    x = x[np.abs(x) >= 2.0 ** -126]                  # FP32's normal range (subnormals flush)
+    want = x.astype(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(oracle.round_bfl(x, 4), want)
+
+
+@pytest.mark.parametrize("nbytes", [2, 3, 5, 6])
+def test_bfl_matches_bit_pattern_rounding(nbytes):
+    """Inside FP32's normal range BFL rounding equals rounding the FP64 bit
+    pattern to m = 8 nbytes - 9 mantissa bits (exact ties included)."""
+    m = 8 * nbytes - 9
+    rng = np.random.default_rng(nbytes + 30)
+    x = rng.standard_normal(3000) * np.exp2(rng.integers(-110, 110, 3000).astype(float))
+    k = rng.integers(1 << m, 1 << (m + 1), 300).astype(float)
+    ties = np.ldexp(k + 0.5, rng.integers(-100, 100, 300) - m) * rng.choice([-1.0, 1.0], 300)
+    x = np.concatenate([x, ties])
+    got = oracle.round_bfl(x, nbytes)
+    assert np.array_equal(got.view(np.uint64), _keep_top_bits(x, m).view(np.uint64))
+    rel = np.abs(got - x) / np.abs(x)
+    assert rel.max() <= 2.0 ** -(m + 1)
+
+
+def test_bfl_definition_cases():
+    """FP32's exponent range at every width: 2^-126 is the smallest value
+    kept (a value that rounds up to it is kept, smaller ones flush to zero),
+    and values rounding to 2^128 or beyond are rejected; 40 bits carry 31
+    mantissa bits."""
+    r = lambda v, nb=5: float(oracle.round_bfl(np.array([v]), nb)[0])
+    tiny = 2.0 ** -126
+    assert r(tiny) == tiny and r(-tiny) == -tiny
+    assert r(tiny * (1 - 2.0 ** -40)) == tiny                     # rounds up into the normal range
+    assert r(tiny * 0.75) == 0.0 and r(1e-300) == 0.0
+    assert r(1 + 2.0 ** -31) == 1 + 2.0 ** -31                    # 31 explicit bits at 5 bytes
+    assert r(1 + 2.0 ** -32) == 1.0                               # tie, even: down
+    assert r(1 + 3 * 2.0 ** -32) == 1 + 2.0 ** -30                # tie, odd: up
+    assert r(3e38, 6) == pytest.approx(3e38, rel=2.0 ** -39)
+    with pytest.raises(ValueError):
+        oracle.round_bfl(np.array([3.5e38]), 5)                   # beyond FP32's range
+    with pytest.raises(ValueError):
+        oracle.round_bfl(np.array([np.nan]), 3)
+    assert oracle.round_to(np.array([0.1]), oracle.BFL40)[0] == r(0.1)
