@@ -44,7 +44,7 @@ def kernel_bytes(H, info, vs, R=1, schedule=0):
     m = (H.re - H.rb).astype(np.float64)
     nb = (H.ce - H.cb).astype(np.float64)
     dense = H.adm == 0
-    sz = np.array([8, 4, 2, 2, 4, 5, 6, 2, 3, 2, 3, 4, 5, 6], np.float64)   # bytes per value, by format
+    sz = np.array([8, 4, 2, 2, 4, 5, 6, 2, 3, 2, 3, 4, 5, 6, 3, 5, 6], np.float64)   # bytes per value, by format
     d_bytes = float((m * nb * sz[H.group_dtype[:, 0]])[dense].sum())
     gcols = H.group_cols.astype(np.float64)
     gbytes = (gcols * sz[H.group_dtype]).sum(1)          # bytes per row of U / V
@@ -196,7 +196,7 @@ def main():
                     help="right-hand sides per product (> 1: hm_mvm_batch; reported separately)")
     ap.add_argument("--n", type=int, default=0, help="override the workload size (not the default line)")
     ap.add_argument("--dtype", default=None,
-                    help="override the workload's storage (f64, f32, mixed, dfl, aplr, aflp)")
+                    help="override the workload's storage (f64, f32, mixed, dfl, aplr, aflp, bfl)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner on this matrix before the timed region and store its "
                          "choice in the tune cache (default: read the cache, no tuning)")
@@ -243,7 +243,7 @@ def main():
     H = hmgen.build_preset(args.workload, n=args.n or None, dtype=p["dtype"])
     st = H.stats()
     log("built in %.1fs: %s" % (H.build_seconds, st))
-    mixed = p["dtype"] not in ("f64", "dfl", "aplr", "aflp")   # DFL / AFLP storage accumulates in FP64
+    mixed = p["dtype"] not in ("f64", "dfl", "aplr", "aflp", "bfl")   # the byte-aligned formats accumulate in FP64
     acc = hm.HM_F32 if mixed else hm.HM_F64
     storage = p["dtype"]
     if storage == "dfl":
@@ -252,6 +252,8 @@ def main():
         storage = "aplr-dfl"
     elif storage == "aflp":
         storage = "aflp-per-block"
+    elif storage == "bfl":
+        storage = hmgen.hmatrix.DT_NAMES[hmgen.bfl_format(p["eps"])]
     vs = 4 if mixed else 8
     stream = torch.cuda.Stream()
     cache = None if args.no_tune_cache or not os.path.exists(args.tune_cache) else args.tune_cache

@@ -14,13 +14,13 @@ share code with each other.
 
 from .geometry import fibonacci_sphere, cube_points, mean_nn_distance
 from .hmatrix import (HMatrix, build_hmatrix, DT_F64, DT_F32, DT_F16, DT_BF16, DT_DFL32, DT_DFL40,
-                      DT_DFL48, dfl_mantissa_bits, dfl_format)
+                      DT_DFL48, dfl_mantissa_bits, dfl_format, bfl_format)
 from .presets import PRESETS, preset, build_preset
 from .vectors import uniform_vector, gaussian_block
 
 __all__ = [
     "fibonacci_sphere", "cube_points", "mean_nn_distance",
     "HMatrix", "build_hmatrix", "DT_F64", "DT_F32", "DT_F16", "DT_BF16", "DT_DFL32", "DT_DFL40",
-    "DT_DFL48", "dfl_mantissa_bits", "dfl_format",
+    "DT_DFL48", "dfl_mantissa_bits", "dfl_format", "bfl_format",
     "PRESETS", "preset", "build_preset", "uniform_vector", "gaussian_block",
 ]

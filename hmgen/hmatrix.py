@@ -19,12 +19,14 @@ from .geometry import mean_nn_distance
 DT_F64, DT_F32, DT_F16, DT_BF16 = 0, 1, 2, 3
 DT_DFL32, DT_DFL40, DT_DFL48, DT_DFL16, DT_DFL24 = 4, 5, 6, 7, 8
 DT_AFLP16, DT_AFLP24, DT_AFLP32, DT_AFLP40, DT_AFLP48 = 9, 10, 11, 12, 13
+DT_BFL24, DT_BFL40, DT_BFL48 = 14, 15, 16
 DT_BYTES = {DT_F64: 8, DT_F32: 4, DT_F16: 2, DT_BF16: 2, DT_DFL32: 4, DT_DFL40: 5, DT_DFL48: 6,
-            DT_DFL16: 2, DT_DFL24: 3, DT_AFLP16: 2, DT_AFLP24: 3, DT_AFLP32: 4, DT_AFLP40: 5, DT_AFLP48: 6}
+            DT_DFL16: 2, DT_DFL24: 3, DT_AFLP16: 2, DT_AFLP24: 3, DT_AFLP32: 4, DT_AFLP40: 5, DT_AFLP48: 6,
+            DT_BFL24: 3, DT_BFL40: 5, DT_BFL48: 6}
 DT_NAMES = {DT_F64: "f64", DT_F32: "f32", DT_F16: "f16", DT_BF16: "bf16",
             DT_DFL32: "dfl32", DT_DFL40: "dfl40", DT_DFL48: "dfl48", DT_DFL16: "dfl16", DT_DFL24: "dfl24",
             DT_AFLP16: "aflp16", DT_AFLP24: "aflp24", DT_AFLP32: "aflp32", DT_AFLP40: "aflp40",
-            DT_AFLP48: "aflp48"}
+            DT_AFLP48: "aflp48", DT_BFL24: "bfl24", DT_BFL40: "bfl40", DT_BFL48: "bfl48"}
 
 
 def dfl_mantissa_bits(eps: float) -> int:
@@ -43,6 +45,14 @@ def dfl_format(eps: float) -> int:
     DFL32, 7 bytes take FP64)."""
     nbytes = -(-(1 + 11 + dfl_mantissa_bits(eps)) // 8)
     return {4: DT_DFL32, 5: DT_DFL40, 6: DT_DFL48}.get(max(nbytes, 4), DT_F64)
+
+def bfl_format(eps: float) -> int:
+    """BFL storage format for accuracy eps (Sec. 3.2): 1 sign + 8 exponent +
+    m_eps mantissa bits, the mantissa increased to whole bytes; 2 and 4
+    bytes are BF16 and FP32, 3 / 5 / 6 bytes BFL24 / 40 / 48, 7 bytes take
+    FP64."""
+    nbytes = -(-(1 + 8 + dfl_mantissa_bits(eps)) // 8)
+    return {2: DT_BF16, 3: DT_BFL24, 4: DT_F32, 5: DT_BFL40, 6: DT_BFL48}.get(nbytes, DT_F64)
 
 KERNEL_LAPLACE, KERNEL_EXP, KERNEL_SEPARABLE = 0, 1, 2
 

@@ -14,7 +14,7 @@ standard admissibility with eta = 2.
 from __future__ import annotations
 
 from .geometry import fibonacci_sphere, cube_points
-from .hmatrix import build_hmatrix, dfl_format, KERNEL_LAPLACE, KERNEL_EXP, DT_F64, DT_F32
+from .hmatrix import build_hmatrix, dfl_format, bfl_format, KERNEL_LAPLACE, KERNEL_EXP, DT_F64, DT_F32
 
 PRESETS = {
     # small parity case
@@ -45,6 +45,10 @@ PRESETS = {
     "sphere256k_aflp": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-6, dtype="aflp"),
     "sphere256k_e8_aflp": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-8, dtype="aflp"),
     "sphere4k_aflp": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-6, dtype="aflp"),
+    # FP32's exponent with the mantissa filling whole bytes (BFL, Sec. 3.2),
+    # FP64 accumulation: eps = 1e-8 -> BFL40 (eps = 1e-6 gives FP32 itself)
+    "sphere256k_e8_bfl": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-8, dtype="bfl"),
+    "sphere4k_bfl": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-8, dtype="bfl"),
 }
 
 SEED_POINTS, SEED_X, SEED_RHS, SEED_REQUESTS = 0, 1, 2, 3
@@ -84,6 +88,8 @@ def build_preset(name: str, *, n: int | None = None, eps: float | None = None,
         H.set_uniform_dtype(dfl_format(eps))
     elif dtype == "aflp":
         H.select_aflp(eps)
+    elif dtype == "bfl":
+        H.set_uniform_dtype(bfl_format(eps))
     else:
         H.set_uniform_dtype(DT_F64 if dtype == "f64" else DT_F32)
     H.dtype_mode = dtype

@@ -65,14 +65,20 @@ typedef int32_t hm_status;
  * block's range of d needs (its binary exponents 1 .. 2^e - 1; 0 codes
  * zero) and 8 B - 1 - e mantissa bits of d rounded to nearest even; the
  * stored value sign(v) (d - 1) 2^k.  hm_upload derives k and e from the
- * data.  The DFL and AFLP formats need HM_F64 accumulation.
+ * data.  BFL24, BFL40, BFL48: the byte-aligned formats with FP32's 8
+ * exponent bits (BFL, Sec. 3.2) in 3, 5 or 6 bytes (15 / 31 / 39 mantissa
+ * bits), rounded to nearest even from FP64; magnitudes below 2^-126 are
+ * stored as zero, and hm_upload rejects values that round beyond FP32's
+ * range.  BFL in 2 and 4 bytes is BF16 and FP32.  The DFL, AFLP and BFL
+ * formats need HM_F64 accumulation.
  * The number of formats is HM_NUM_DTYPES. */
 typedef enum {
   HM_F64 = 0, HM_F32 = 1, HM_F16 = 2, HM_BF16 = 3,
   HM_DFL32 = 4, HM_DFL40 = 5, HM_DFL48 = 6, HM_DFL16 = 7, HM_DFL24 = 8,
-  HM_AFLP16 = 9, HM_AFLP24 = 10, HM_AFLP32 = 11, HM_AFLP40 = 12, HM_AFLP48 = 13
+  HM_AFLP16 = 9, HM_AFLP24 = 10, HM_AFLP32 = 11, HM_AFLP40 = 12, HM_AFLP48 = 13,
+  HM_BFL24 = 14, HM_BFL40 = 15, HM_BFL48 = 16
 } hm_dtype;
-#define HM_NUM_DTYPES 14
+#define HM_NUM_DTYPES 17
 typedef enum { HM_DENSE = 0, HM_LOWRANK = 1 } hm_kind;
 
 /* One leaf block b = tau x sigma of the block tree (Sec. 2.1).
@@ -93,7 +99,7 @@ typedef struct {
 /* acc_dtype: HM_F64 or HM_F32, the accumulation type of every sum.
  * vec_dtype: must equal acc_dtype (x, y, X, Y are stored in it).
  * Storage dtypes allowed: any with HM_F64 accumulation; F32/F16/BF16 with
- * HM_F32 accumulation (DFL and AFLP formats need HM_F64 accumulation).
+ * HM_F32 accumulation (DFL, AFLP and BFL formats need HM_F64 accumulation).
  * max_nrhs: largest nrhs passed to hm_mvm_batch (>= 1); sizes the workspace.
  * tune: 0 = built-in launch parameters; 1 = read tune_cache, a text file
  * written by the tuner with one "key params" line per kind of matrix (see
@@ -155,7 +161,7 @@ void hm_plan_destroy(hm_plan* p);
  * little-endian 32-bit word) or 2 bytes (DFL16 / 24: a 16-bit word); for
  * DFL40 / DFL48 / DFL24 its remaining 1 / 2 / 1 bytes (bits 31..24 /
  * 31..16 / 47..40 of the FP64 encoding) are at lo_offset, else lo_offset =
- * 0.  AFLP values sit like the DFL values of the same byte count (their
+ * 0.  AFLP and BFL values sit like the DFL values of the same byte count (their
  * left-aligned code in place of the FP64 encoding).  lo_offset may be NULL.
  * For tests of the packing and conversion done by hm_upload. */
 hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t i, int64_t j,
@@ -175,7 +181,8 @@ hm_status hm_plan_locate(const hm_plan* p, int64_t block, int32_t which, int64_t
  * Converting each block after assembly follows Sec. 5.3.  Errors: HM_EINVAL
  * (NULL or missing factor pointers, alignment, an AFLP data block with a
  * value that is not finite or a range whose exponents need more than 10
- * bits or leave no mantissa bit), HM_ENOMEM (store too small,
+ * bits or leave no mantissa bit; a BFL value that is not finite or rounds
+ * beyond FP32's range), HM_ENOMEM (store too small,
  * pinned staging), HM_EDEVICE (no usable device, copy failure). */
 hm_status hm_upload(const hm_plan* p, const double* const* a, const double* const* bf,
                     const double* const* s, void* d_store, size_t store_bytes, void* stream,

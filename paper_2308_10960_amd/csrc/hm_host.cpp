@@ -152,7 +152,23 @@ static uint64_t aflp_code(double v, int32_t prm, int nbytes) {
   return (std::signbit(v) ? 1ull << 63 : 0) | mag;
 }
 
-// A left-aligned 64-bit code r of a DFL or AFLP value: its leading 4 bytes
+// The left-aligned 64-bit BFL code of v in nbytes bytes (see kBflRebias);
+// false for a value that is not finite or rounds to 2^128 or beyond.
+static bool bfl_code(double v, int nbytes, uint64_t* out) {
+  if (!std::isfinite(v)) return false;
+  uint64_t b;
+  std::memcpy(&b, &v, 8);
+  const uint64_t sign = b & (1ull << 63), mag = b & ~(1ull << 63);
+  *out = 0;
+  if (mag == 0) return true;
+  const uint64_t r = rne_mantissa(mag, 8 * nbytes - 9);
+  const int e8 = (int)(r >> 52) - 896;             // FP32's biased exponent
+  if (e8 >= 255) return false;
+  if (e8 >= 1) *out = sign | ((r - kBflRebias) << 3);
+  return true;                                     // below 2^-126: zero
+}
+
+// A left-aligned 64-bit code r of a DFL, AFLP or BFL value: its leading 4 bytes
 // (32 / 40 / 48-bit formats: the high word) or 2 bytes (16 / 24-bit
 // formats) at hi; for the 40 / 48 / 24-bit formats bits 31..24 / 31..16 /
 // 47..40 at lo.
@@ -168,6 +184,12 @@ static inline void put_code(uint8_t* hi, uint8_t* lo, int dt, uint64_t r) {
   if (dt == kDtDfl40) { const uint8_t q = (uint8_t)(r >> 24); std::memcpy(lo, &q, 1); }
   if (dt == kDtDfl48) { const uint16_t q = (uint16_t)(r >> 16); std::memcpy(lo, &q, 2); }
   if (dt == kDtDfl24) { const uint8_t q = (uint8_t)(r >> 40); std::memcpy(lo, &q, 1); }
+}
+
+// The BFL code of a value the pre-pass has checked (see bfl_code).
+static inline uint64_t bfl_or_zero(double v, int nbytes) {
+  uint64_t c;
+  return bfl_code(v, nbytes, &c) ? c : 0;
 }
 
 static inline void put_dfl(uint8_t* hi, uint8_t* lo, int dt, double v) {
@@ -197,7 +219,7 @@ static hm_status validate_block(const hm_block_desc& b, int64_t i, int64_t n_row
     return fail(HM_ESHAPE, "block %lld too large", (long long)i);
   auto dt_ok = [&](int dt) {
     if (dt < HM_F64 || dt >= kNumDtypes) return false;
-    if (acc == HM_F32 && (dt == HM_F64 || is_dfl(dt) || is_aflp(dt))) return false;
+    if (acc == HM_F32 && (dt == HM_F64 || is_dfl(dt) || is_aflp(dt) || is_bfl(dt))) return false;
     return true;
   };
   if (b.kind == HM_DENSE) {
@@ -901,8 +923,41 @@ static hm_status check_factors(const hm_plan* P, const double* const* a, const d
   return HM_OK;
 }
 
+// Every BFL value of block b (its BFL column groups) can be encoded.
+static bool bfl_block_ok(const hm_block_desc& b, const double* a, const double* bf) {
+  const int64_t m = b.row_end - b.row_begin, nb = b.col_end - b.col_begin;
+  auto ok = [](const double* v, int64_t n, int dt) {
+    uint64_t c;
+    for (int64_t i = 0; i < n; ++i)
+      if (!bfl_code(v[i], value_bytes(dt), &c)) return false;
+    return true;
+  };
+  if (b.kind == HM_DENSE) return !is_bfl(b.group_dtype[0]) || ok(a, m * nb, b.group_dtype[0]);
+  int64_t c0 = 0;
+  for (int g = 0; g < b.ngroups; ++g) {
+    const int dt = b.group_dtype[g];
+    const int64_t kc = b.group_cols[g];
+    if (is_bfl(dt) && kc > 0 && !(ok(a + c0 * m, m * kc, dt) && ok(bf + c0 * nb, nb * kc, dt))) return false;
+    c0 += kc;
+  }
+  return true;
+}
+
 hm_status AflpTable::build(const hm_plan* P, const double* const* a, const double* const* bf) {
   base.assign(P->blocks.size(), -1);
+  bool any_bfl = false;
+  for (auto& b : P->blocks)
+    for (int g = 0; g < b.ngroups; ++g) any_bfl |= is_bfl(b.group_dtype[g]);
+  if (any_bfl) {                                   // BFL data in range (checked before any packing)
+    std::atomic<int64_t> bad{-1};
+    parallel_for(P->blocks.size(), [&](size_t i) {
+      const auto& b = P->blocks[i];
+      if ((b.kind == HM_DENSE || b.rank > 0) && !bfl_block_ok(b, a[i], b.kind == HM_DENSE ? nullptr : bf[i]))
+        bad.store((int64_t)i);
+    });
+    if (bad.load() >= 0)
+      return fail(HM_EINVAL, "block %lld: BFL needs finite values within FP32's range", (long long)bad.load());
+  }
   int64_t n = 0;
   for (size_t i = 0; i < P->blocks.size(); ++i) {
     const auto& b = P->blocks[i];
@@ -1172,6 +1227,8 @@ void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf
                 put_dfl(hi, lo, S->dtype, col[i]);
               else if (is_aflp(S->dtype))
                 put_code(hi, lo, S->dtype, aflp_code(col[i], prm, value_bytes(S->dtype)));
+              else if (is_bfl(S->dtype))
+                put_code(hi, lo, S->dtype, bfl_or_zero(col[i], value_bytes(S->dtype)));
               else
                 put(hi, S->dtype, col[i]);
             }
@@ -1197,6 +1254,8 @@ void pack_jobs(const hm_plan* P, const double* const* a, const double* const* bf
                 put_dfl(hi, lp, S->dtype, col[i]);
               else if (is_aflp(S->dtype))
                 put_code(hi, lp, S->dtype, aflp_code(col[i], prm, value_bytes(S->dtype)));
+              else if (is_bfl(S->dtype))
+                put_code(hi, lp, S->dtype, bfl_or_zero(col[i], value_bytes(S->dtype)));
               else
                 put(hi, S->dtype, col[i]);
             }

@@ -23,7 +23,7 @@
 //
 // Every sum has a fixed order, so results are bitwise reproducible and no
 // atomics touch y.  Storage formats (FP64/FP32/FP16/BF16, Table 1; the
-// byte-aligned DFL and AFLP formats, Sec. 3.2) are decoded to the
+// byte-aligned DFL, AFLP and BFL formats, Sec. 3.2) are decoded to the
 // accumulation type in registers.
 
 #include <algorithm>
@@ -74,6 +74,17 @@ __device__ __forceinline__ double aflp_value(u32x4 r, u32x2 lo, int c, unsigned 
   return __hiloint2double((int)hi, __double2loint(w));
 }
 
+// A BFL element (exact): the code P, left-aligned like a DFL encoding of
+// the same bytes, holds FP32's sign, exponent and leading mantissa bits;
+// moved down 3 bits and rebiased it is the FP64 value; P = 0 is zero.
+template <int DT>
+__device__ __forceinline__ double bfl_value(u32x4 r, u32x2 lo, int c) {
+  const unsigned long long P = dfl_bits<storage_dt(DT)>(r, lo, c);
+  const unsigned long long mag = P & 0x7fffffffffffffffull;
+  const unsigned long long d = mag ? (((mag >> 3) + kBflRebias) | (P & 0x8000000000000000ull)) : 0ull;
+  return __longlong_as_double((long long)d);
+}
+
 // The low-byte plane entry idx of a DFL40 / DFL48 / DFL24 region at p
 // (zero for the other formats, which have none).
 template <int DT>
@@ -104,6 +115,9 @@ __device__ __forceinline__ AccT dot_group(u32x4 r, u32x2 lo, const AccT* __restr
     }
 #pragma unroll
     for (int c = 0; c < G; ++c) acc = fmaT((AccT)aflp_value<DT>(r, lo, c, s[c]), z[c], acc);
+  } else if constexpr (is_bfl(DT)) {
+#pragma unroll
+    for (int c = 0; c < group_width(DT); ++c) acc = fmaT((AccT)bfl_value<DT>(r, lo, c), z[c], acc);
   } else if constexpr (is_dfl(DT)) {
 #pragma unroll
     for (int c = 0; c < group_width(DT); ++c) acc = fmaT((AccT)dfl_value<DT>(r, lo, c), z[c], acc);
@@ -138,6 +152,9 @@ __device__ __forceinline__ void axpy_group(u32x4 r, u32x2 lo, AccT xi, AccT* acc
   if constexpr (is_aflp(DT)) {
 #pragma unroll
     for (int c = 0; c < group_width(DT); ++c) acc[c] = fmaT((AccT)aflp_value<DT>(r, lo, c, sh[c]), xi, acc[c]);
+  } else if constexpr (is_bfl(DT)) {
+#pragma unroll
+    for (int c = 0; c < group_width(DT); ++c) acc[c] = fmaT((AccT)bfl_value<DT>(r, lo, c), xi, acc[c]);
   } else if constexpr (is_dfl(DT)) {
 #pragma unroll
     for (int c = 0; c < group_width(DT); ++c) acc[c] = fmaT((AccT)dfl_value<DT>(r, lo, c), xi, acc[c]);
@@ -186,10 +203,10 @@ struct ColArgs {
 // LDS (red: 4 x 64 x 8), and wave 0 writes each column's sum to its
 // destination (a partial, or t).  DT >= 0: every group of the tile has
 // format DT; DT < 0: the tile holds runs of several formats and each lane
-// decodes its own (T.dtype, T.end); DFL / AFLP: such a tile may hold DFL /
-// AFLP runs.  An AFLP lane keeps its columns' shifts in registers and
+// decodes its own (T.dtype, T.end); DFL / AFLP / BFL: such a tile may hold
+// runs of those formats.  An AFLP lane keeps its columns' shifts in registers and
 // scales its sums by the columns' 2^k before they are written.
-template <typename AccT, int DT, bool DFL = false, bool AFLP = false>
+template <typename AccT, int DT, bool DFL = false, bool AFLP = false, bool BFL = false>
 __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, AccT* red, AccT* xs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool act = lane < T.ngroups;
@@ -217,7 +234,7 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
   // low-byte plane: entries of lo_bytes(DT) bytes in a one-format tile; of
   // Lt bytes in a several-format one (read by the lanes whose format has one)
   const uint8_t* lop = a.store + T.data_off + (int64_t)16 * nrows * rstride;
-  constexpr bool LOW = DFL || AFLP;                // several-format tiles: runs with low bytes
+  constexpr bool LOW = DFL || AFLP || BFL;         // several-format tiles: runs with low bytes
   const int Lt = DT < 0 && LOW ? tile_lo_bytes(T) : 0;
   const bool hlo = DT < 0 && LOW && lo_bytes(dt) > 0;
   const int nb = nrows > 8 * wave ? (nrows - 8 * wave + 31) / 32 : 0;   // this wave's batches
@@ -277,6 +294,9 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
             else if (AFLP && dt == kDtAflp24) axpy_group<AccT, kDtAflp24>(rc[u], lc[u], xi, acc, sh);
             else if (AFLP && dt == kDtAflp40) axpy_group<AccT, kDtAflp40>(rc[u], lc[u], xi, acc, sh);
             else if (AFLP && dt == kDtAflp48) axpy_group<AccT, kDtAflp48>(rc[u], lc[u], xi, acc, sh);
+            else if (BFL && dt == kDtBfl40) axpy_group<AccT, kDtBfl40>(rc[u], lc[u], xi, acc, sh);
+            else if (BFL && dt == kDtBfl48) axpy_group<AccT, kDtBfl48>(rc[u], lc[u], xi, acc, sh);
+            else if (BFL && dt == kDtBfl24) axpy_group<AccT, kDtBfl24>(rc[u], lc[u], xi, acc, sh);
             else axpy_group<AccT, HM_F64>(rc[u], lc[u], xi, acc, sh);
           }
         }
@@ -323,6 +343,7 @@ constexpr int kColIeee = 1;     // one-format tiles of FP64, FP32, FP16, BF16
 constexpr int kColMulti = 2;    // several-format tiles
 constexpr int kColDfl = 4;      // one-format DFL tiles, and DFL runs in several-format tiles
 constexpr int kColAflp = 8;     // AFLP runs in several-format tiles
+constexpr int kColBfl = 16;     // BFL runs in several-format tiles
 
 // A whole workgroup on tile ti (it synchronizes).  red: 4 * 64 * 8 values
 // (four waves x 64 lanes x at most 8 columns per lane); xs: kSegRows
@@ -337,10 +358,19 @@ __device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti,
   }
   constexpr bool dfl = (KIND & kColDfl) && sizeof(AccT) == 8;
   constexpr bool aflp = (KIND & kColAflp) && sizeof(AccT) == 8;
+  constexpr bool bfl = (KIND & kColBfl) && sizeof(AccT) == 8;
   if constexpr ((KIND & kColMulti) != 0) {
     if (T.end[0] < T.ngroups) {                     // several formats in the tile
-      col_tile<AccT, -1, dfl, aflp>(a, T, red, xs);
+      col_tile<AccT, -1, dfl, aflp, bfl>(a, T, red, xs);
       return;
+    }
+  }
+  if constexpr (bfl) {
+    switch (T.dtype[0]) {
+      case kDtBfl24: col_tile<AccT, kDtBfl24>(a, T, red, xs); return;
+      case kDtBfl40: col_tile<AccT, kDtBfl40>(a, T, red, xs); return;
+      case kDtBfl48: col_tile<AccT, kDtBfl48>(a, T, red, xs); return;
+      default: break;
     }
   }
   if constexpr (aflp) {
@@ -447,7 +477,7 @@ struct RowArgs {
 
 // Formats a row-panel instantiation decodes besides FP64 / FP32 / FP16 /
 // BF16 (a bit set; FP64 accumulation only).
-constexpr int kXfDfl = 1, kXfAflp = 2;
+constexpr int kXfDfl = 1, kXfAflp = 2, kXfBfl = 4;
 
 // Groups [g_lo, g_hi) of a section at base (its low-byte plane, if any, at
 // lo_base), groups g_lo + wave, + 4, ... for this wave.
@@ -535,7 +565,10 @@ __device__ __forceinline__ void row_panel_part(const RowArgs<AccT>& a, const Row
                 case kDtAflp40: if constexpr ((XF & kXfAflp) != 0) HM_ROW_SECTION(kDtAflp40); break;
                 case kDtAflp16: if constexpr ((XF & kXfAflp) != 0) HM_ROW_SECTION(kDtAflp16); break;
                 case kDtAflp24: if constexpr ((XF & kXfAflp) != 0) HM_ROW_SECTION(kDtAflp24); break;
-                default: if constexpr ((XF & kXfAflp) != 0) HM_ROW_SECTION(kDtAflp48); break;
+                case kDtAflp48: if constexpr ((XF & kXfAflp) != 0) HM_ROW_SECTION(kDtAflp48); break;
+                case kDtBfl40: if constexpr ((XF & kXfBfl) != 0) HM_ROW_SECTION(kDtBfl40); break;
+                case kDtBfl48: if constexpr ((XF & kXfBfl) != 0) HM_ROW_SECTION(kDtBfl48); break;
+                default: if constexpr ((XF & kXfBfl) != 0) HM_ROW_SECTION(kDtBfl24); break;
               }
             }
             break;
@@ -569,8 +602,8 @@ __global__ __launch_bounds__(256) void k_p1(RowArgs<AccT> ra, ColArgs<AccT> ca, 
   __shared__ AccT red[4][64];
   __shared__ AccT pxs[kSegRows];
   __shared__ __align__(16) uint32_t shs[(XF & kXfAflp) ? CAP : 4];
-  constexpr int KIND =
-      kColIeee | kColMulti | ((XF & kXfDfl) ? kColDfl : 0) | ((XF & kXfAflp) ? kColAflp : 0);
+  constexpr int KIND = kColIeee | kColMulti | ((XF & kXfDfl) ? kColDfl : 0) | ((XF & kXfAflp) ? kColAflp : 0) |
+                       ((XF & kXfBfl) ? kColBfl : 0);
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     if (it != blockIdx.x) __syncthreads();          // LDS of the previous item
     const int item = order[it];
@@ -680,8 +713,8 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
                          ca, reinterpret_cast<const int32_t*>(st + h.off_p1_order), h.n_p1);
   } else {
     // classes: one-format IEEE tiles [0, ce[3]), one-format DFL tiles
-    // [ce[3], ce[8]), one-format AFLP tiles [ce[8], ce[13]), several-format
-    // tiles [ce[13], ce[14])
+    // [ce[3], ce[8]), one-format AFLP tiles [ce[8], ce[13]), one-format BFL
+    // tiles [ce[13], ce[16]), several-format tiles [ce[16], ce[17])
     const int64_t* ce = h.tile_class_end;
     const int64_t ni = ce[HM_BF16], nm = h.n_col_tiles - ce[kNumDtypes - 1];
     if (ni > 0)
@@ -705,7 +738,13 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
       cls(k_col<AccT, kColAflp, kDtAflp40>, kDtAflp40);
       cls(k_col<AccT, kColAflp, kDtAflp48>, kDtAflp48);
     }
-    constexpr int KM = kColMulti | ((XF & kXfDfl) ? kColDfl : 0) | ((XF & kXfAflp) ? kColAflp : 0);
+    if constexpr ((XF & kXfBfl) != 0 && sizeof(AccT) == 8) {
+      cls(k_col<AccT, kColBfl, kDtBfl24>, kDtBfl24);
+      cls(k_col<AccT, kColBfl, kDtBfl40>, kDtBfl40);
+      cls(k_col<AccT, kColBfl, kDtBfl48>, kDtBfl48);
+    }
+    constexpr int KM = kColMulti | ((XF & kXfDfl) ? kColDfl : 0) | ((XF & kXfAflp) ? kColAflp : 0) |
+                       ((XF & kXfBfl) ? kColBfl : 0);
     if (nm > 0)
       hipLaunchKernelGGL((k_col<AccT, KM>), dim3(item_grid(nm, ps, ncu)), dim3(256), 0, s, ca,
                          ce[kNumDtypes - 1], h.n_col_tiles);
@@ -734,22 +773,30 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
   return hipGetLastError();
 }
 
-// DFL / AFLP instantiations (FP64 accumulation only) run when the store
-// holds such bytes (the AFLP ones decode the DFL formats too).
+// DFL / AFLP / BFL instantiations (FP64 accumulation only) run when the
+// store holds such bytes; a store with several of these families runs
+// instantiations that decode all of them present.
 template <typename AccT>
 hipError_t launch_typed(const hm_matrix& A, double alpha, const void* x, void* y, void* work,
                         hipStream_t s, hipEvent_t* ev) {
   const bool u8 = A.launch.row_unroll >= 8;
   if constexpr (sizeof(AccT) == 8) {
-    bool dfl = false, aflp = false;
+    bool dfl = false, aflp = false, bfl = false;
     for (int d = 0; d < kNumDtypes; ++d) {
       dfl = dfl || (is_dfl(d) && A.bytes_by_dtype[d] > 0);
       aflp = aflp || (is_aflp(d) && A.bytes_by_dtype[d] > 0);
+      bfl = bfl || (is_bfl(d) && A.bytes_by_dtype[d] > 0);
     }
-    constexpr int kAll = kXfDfl | kXfAflp;
-    if (aflp && dfl)
+    constexpr int kAll = kXfDfl | kXfAflp | kXfBfl;
+    if (bfl && (dfl || aflp))
       return u8 ? launch_typed_u<AccT, 8, kAll>(A, alpha, x, y, work, s, ev)
                 : launch_typed_u<AccT, 4, kAll>(A, alpha, x, y, work, s, ev);
+    if (bfl)
+      return u8 ? launch_typed_u<AccT, 8, kXfBfl>(A, alpha, x, y, work, s, ev)
+                : launch_typed_u<AccT, 4, kXfBfl>(A, alpha, x, y, work, s, ev);
+    if (aflp && dfl)
+      return u8 ? launch_typed_u<AccT, 8, kXfDfl | kXfAflp>(A, alpha, x, y, work, s, ev)
+                : launch_typed_u<AccT, 4, kXfDfl | kXfAflp>(A, alpha, x, y, work, s, ev);
     if (aflp)
       return u8 ? launch_typed_u<AccT, 8, kXfAflp>(A, alpha, x, y, work, s, ev)
                 : launch_typed_u<AccT, 4, kXfAflp>(A, alpha, x, y, work, s, ev);

@@ -55,18 +55,21 @@ constexpr int kLargeSeg = 16;       // blocks with more intervals reduce per wor
 constexpr int kAlign = 256;
 
 // Storage formats (hm_dtype): F64, F32, F16, BF16, DFL32, DFL40, DFL48,
-// DFL16, DFL24, AFLP16, AFLP24, AFLP32, AFLP40, AFLP48.
-constexpr int kNumDtypes = 14;
+// DFL16, DFL24, AFLP16, AFLP24, AFLP32, AFLP40, AFLP48, BFL24, BFL40, BFL48.
+constexpr int kNumDtypes = 17;
 constexpr int kDtDfl32 = 4, kDtDfl40 = 5, kDtDfl48 = 6, kDtDfl16 = 7, kDtDfl24 = 8;
 constexpr int kDtAflp16 = 9, kDtAflp24 = 10, kDtAflp32 = 11, kDtAflp40 = 12, kDtAflp48 = 13;
+constexpr int kDtBfl24 = 14, kDtBfl40 = 15, kDtBfl48 = 16;
 
 inline constexpr bool is_dfl(int dt) { return dt >= kDtDfl32 && dt <= kDtDfl24; }
 inline constexpr bool is_aflp(int dt) { return dt >= kDtAflp16 && dt <= kDtAflp48; }
-// AFLP values of B bytes are stored like the DFL values of B bytes (a
-// left-aligned B-byte code split into the same leading and low parts).
+inline constexpr bool is_bfl(int dt) { return dt >= kDtBfl24 && dt <= kDtBfl48; }
+// AFLP and BFL values of B bytes are stored like the DFL values of B bytes
+// (a left-aligned B-byte code split into the same leading and low parts).
 inline constexpr int storage_dt(int dt) {
   return dt == kDtAflp16 ? kDtDfl16 : dt == kDtAflp24 ? kDtDfl24 : dt == kDtAflp32 ? kDtDfl32
-       : dt == kDtAflp40 ? kDtDfl40 : dt == kDtAflp48 ? kDtDfl48 : dt;
+       : dt == kDtAflp40 ? kDtDfl40 : dt == kDtAflp48 ? kDtDfl48 : dt == kDtBfl24 ? kDtDfl24
+       : dt == kDtBfl40 ? kDtDfl40 : dt == kDtBfl48 ? kDtDfl48 : dt;
 }
 
 // Columns per 16-byte group for a storage dtype.  A DFL value keeps its
@@ -100,6 +103,14 @@ inline constexpr int value_bytes(int dt) { return dtype_size(dt) + lo_bytes(dt) 
 inline constexpr int32_t aflp_param(int k, int e) { return k * 256 + (11 - e); }
 inline constexpr int aflp_scale_exp(int32_t p) { return p >> 8; }    // k (arithmetic shift)
 inline constexpr int aflp_shift(int32_t p) { return p & 0xff; }      // 11 - e
+
+// BFL (Sec. 3.2): FP32's sign and 8 exponent bits (bias 127) and the
+// 8B - 9 leading mantissa bits of a value, rounded to nearest even from
+// FP64; B = 2 and 4 are BF16 and FP32, stored as such.  With the code
+// left-aligned in 64 bits (P), a nonzero value is the FP64 number of bits
+// ((P & ~sign) >> 3) + (896 << 52), sign from P (896 = 1023 - 127); P = 0
+// is zero (magnitudes below 2^-126 are stored as zero).
+constexpr unsigned long long kBflRebias = 896ull << 52;
 
 struct RowPanel {        // 32 bytes
   int64_t src_off;       // first entry (int32 units) in the row-source table
@@ -205,6 +216,6 @@ inline constexpr int tile_class(const ColTile& T) {
   return T.end[0] == T.ngroups ? T.dtype[0] : kNumDtypes;
 }
 
-constexpr uint64_t kStoreMagic = 0x484d53544f524534ull;  // "HMSTORE4"
+constexpr uint64_t kStoreMagic = 0x484d53544f524535ull;  // "HMSTORE5"
 
 }  // namespace hm

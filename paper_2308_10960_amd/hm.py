@@ -21,7 +21,8 @@ HM_ENOMEM, HM_EDEVICE, HM_EBUSY, HM_ESTATE, HM_ETIMEOUT = -5, -6, -7, -8, -9
 HM_F64, HM_F32, HM_F16, HM_BF16 = 0, 1, 2, 3
 HM_DFL32, HM_DFL40, HM_DFL48, HM_DFL16, HM_DFL24 = 4, 5, 6, 7, 8
 HM_AFLP16, HM_AFLP24, HM_AFLP32, HM_AFLP40, HM_AFLP48 = 9, 10, 11, 12, 13
-HM_NUM_DTYPES = 14
+HM_BFL24, HM_BFL40, HM_BFL48 = 14, 15, 16
+HM_NUM_DTYPES = 17
 HM_DENSE, HM_LOWRANK = 0, 1
 
 STATUS_NAMES = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_EPARTITION", -3: "HM_ESHAPE",

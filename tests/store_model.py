@@ -26,12 +26,26 @@ RS = np.dtype([("data_off", "<i8"), ("dtype", "<i4"), ("ngroups", "<i4"), ("col0
 CT = np.dtype([("data_off", "<i8"), ("nrows", "<i4"), ("x0", "<i4"), ("ngroups", "<i4"),
                ("dst_off", "<i4"), ("dtype", "u1", (4,)), ("end", "u1", (4,))])
 TB = np.dtype([("pst", "<i4"), ("k", "<i4"), ("nseg", "<i4"), ("toff", "<i4")])
-G = {0: 2, 1: 4, 2: 8, 3: 8, 4: 4, 5: 4, 6: 4, 7: 8, 8: 8, 9: 8, 10: 8, 11: 4, 12: 4, 13: 4}
+G = {0: 2, 1: 4, 2: 8, 3: 8, 4: 4, 5: 4, 6: 4, 7: 8, 8: 8, 9: 8, 10: 8, 11: 4, 12: 4, 13: 4, 14: 8, 15: 4, 16: 4}
 # bytes per value inside the 16-byte groups
-SZ = {0: 8, 1: 4, 2: 2, 3: 2, 4: 4, 5: 4, 6: 4, 7: 2, 8: 2, 9: 2, 10: 2, 11: 4, 12: 4, 13: 4}
+SZ = {0: 8, 1: 4, 2: 2, 3: 2, 4: 4, 5: 4, 6: 4, 7: 2, 8: 2, 9: 2, 10: 2, 11: 4, 12: 4, 13: 4, 14: 2, 15: 4, 16: 4}
 # low bytes per value, bit position (DFL40 / 48 / 24, AFLP24 / 40 / 48)
-LO = {5: (1, 24), 6: (2, 16), 8: (1, 40), 10: (1, 40), 12: (1, 24), 13: (2, 16)}
+LO = {5: (1, 24), 6: (2, 16), 8: (1, 40), 10: (1, 40), 12: (1, 24), 13: (2, 16), 14: (1, 40), 15: (1, 24),
+      16: (2, 16)}
 AFLP_BYTES = {9: 2, 10: 3, 11: 4, 12: 5, 13: 6}
+BFL_BYTES = {14: 3, 15: 5, 16: 6}
+
+
+def decode_bfl(code: np.ndarray, nbytes: int) -> np.ndarray:
+    """BFL values from left-aligned 64-bit codes: sign, 8 exponent bits E
+    (bias 127) and m = 8 nbytes - 9 fraction bits; 2^(E-127) (1 + f 2^-m),
+    and zero for E = 0."""
+    m = 8 * nbytes - 9
+    c = code >> np.uint64(64 - 8 * nbytes)
+    sign = np.where((c >> np.uint64(8 * nbytes - 1)) & np.uint64(1), -1.0, 1.0)
+    E = ((c >> np.uint64(m)) & np.uint64(255)).astype(np.int64)
+    f = (c & ((np.uint64(1) << np.uint64(m)) - np.uint64(1))).astype(np.float64)
+    return np.where(E == 0, 0.0, sign * np.ldexp(1.0 + np.ldexp(f, -m), E - 127))
 
 
 def decode_aflp(code: np.ndarray, prm: np.ndarray, nbytes: int) -> np.ndarray:
@@ -129,6 +143,8 @@ def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> n
                         prm = T["col_aflp"][c0: c0 + (e - g0) * G[dt]]
                         parts.append(decode_aflp(dfl_code(hi, lo, dt).reshape(nr, -1), prm[None, :],
                                                  AFLP_BYTES[dt]))
+                    elif dt in BFL_BYTES:
+                        parts.append(decode_bfl(dfl_code(hi, lo, dt), BFL_BYTES[dt]).reshape(nr, -1))
                     else:
                         parts.append(decode_dfl(hi, lo, dt).reshape(nr, -1))
                 else:
@@ -181,6 +197,8 @@ def model_mvm(buf: np.ndarray, x: np.ndarray, y0: np.ndarray, alpha: float) -> n
                     s0 = int(p["src_off"]) + c0
                     prm = T["row_aflp"][s0: s0 + ng * g].reshape(ng, 1, g)
                     vals = decode_aflp(dfl_code(hi, lo, dt).reshape(ng, m, g), prm, AFLP_BYTES[dt])
+                elif dt in BFL_BYTES:
+                    vals = decode_bfl(dfl_code(hi, lo, dt), BFL_BYTES[dt]).reshape(ng, m, g)
                 else:
                     vals = decode_dfl(hi, lo, dt).reshape(ng, m, g)
             else:

@@ -354,3 +354,14 @@ def test_bfl_definition_cases():
     with pytest.raises(ValueError):
         oracle.round_bfl(np.array([np.nan]), 3)
     assert oracle.round_to(np.array([0.1]), oracle.BFL40)[0] == r(0.1)
+
+
+def test_bfl_format_choice():
+    """Sec. 3.2: 1 + 8 + m_eps bits, the mantissa increased to whole bytes
+    (m_eps as for DFL); 2 and 4 bytes are BF16 and FP32."""
+    import hmgen
+    from hmgen.hmatrix import DT_BF16, DT_F32, DT_BFL24, DT_BFL40, DT_BFL48, DT_F64
+    for eps, dt in ((1e-2, DT_BF16), (1e-4, DT_BFL24), (1e-6, DT_F32), (1e-8, DT_BFL40), (1e-10, DT_BFL48),
+                    (1e-13, DT_F64)):
+        assert hmgen.bfl_format(eps) == dt, eps
+    assert (DT_BFL24, DT_BFL40, DT_BFL48) == (oracle.BFL24, oracle.BFL40, oracle.BFL48)

@@ -1,6 +1,6 @@
 """GPU parity of the byte-aligned storage formats of Sec. 3.2 (truncated
-FP64: DFL; adaptive exponent: AFLP) with FP64 accumulation, through the
-C-ABI, one format per matrix or block, or chosen per column (APLR, Sec. 3.3).
+FP64: DFL; adaptive exponent: AFLP; FP32's exponent: BFL) with FP64
+accumulation, through the C-ABI, one format per matrix or block, or chosen per column (APLR, Sec. 3.3).
 
 The kernels decode DFL exactly to FP64, so the product must match the oracle
 evaluated on the DFL-rounded factors to the FP64 bar (relative 2-norm error
@@ -59,6 +59,7 @@ def abs_bound(H, x, factors):
 
 
 AFLP = {hm.HM_AFLP16: 2, hm.HM_AFLP24: 3, hm.HM_AFLP32: 4, hm.HM_AFLP40: 5, hm.HM_AFLP48: 6}
+BFL_MANT = {hm.HM_BFL24: 15, hm.HM_BFL40: 31, hm.HM_BFL48: 39, hm.HM_F32: 23}
 
 
 def aflp_bound(H):
@@ -78,6 +79,8 @@ def aflp_bound(H):
                 blk = F[:, c0:c0 + kc]
                 if dt in AFLP:
                     worst = max(worst, 2.0 ** -oracle.aflp_params(blk, AFLP[dt])[2])
+                elif dt in BFL_MANT:
+                    worst = max(worst, 2.0 ** -(BFL_MANT[dt] + 1))
                 elif dt in MANT:
                     worst = max(worst, 2.0 ** -(MANT[dt] + 1))
             c0 += kc
@@ -97,6 +100,16 @@ def layout(name):
         H = hmgen.build_preset("sphere4k", n=16384, eps=1e-10)
         _groups(H, [hm.HM_F64, hm.HM_DFL32, hm.HM_AFLP16, hm.HM_AFLP24, hm.HM_AFLP32, hm.HM_AFLP40,
                     hm.HM_AFLP48], np.random.default_rng(4))
+        return H, aflp_bound(H)
+    if name == "bfl40":
+        H = hmgen.build_preset("sphere4k_bfl")
+        return H, 4 * 2.0 ** -32
+    if name == "bfl_any_16k":
+        # BFL of every width beside DFL40, AFLP32, FP32 and FP64 in column
+        # groups, at n = 16384 (partials)
+        H = hmgen.build_preset("sphere4k", n=16384, eps=1e-10)
+        _groups(H, [hm.HM_F64, hm.HM_BFL24, hm.HM_BFL40, hm.HM_BFL48, hm.HM_DFL40, hm.HM_AFLP32, hm.HM_F32],
+                np.random.default_rng(8))
         return H, aflp_bound(H)
     if name == "aflp_zeros":
         H, _ = layout("aflp")
@@ -132,7 +145,7 @@ def check(y, ref, scale, what):
 
 
 @pytest.mark.parametrize("name", ["dfl32", "dfl40_16k", "dfl48", "dfl_mix", "bfl32", "aplr", "aflp",
-                                  "aflp_any_16k", "aflp_zeros"])
+                                  "aflp_any_16k", "aflp_zeros", "bfl40", "bfl_any_16k"])
 def test_dfl_parity(name):
     H, bound = layout(name)
     say("layout", name, "n", H.n)
@@ -211,7 +224,8 @@ def test_aflp_batch_equals_single():
 
 
 @pytest.mark.parametrize("name", ["sphere256k_dfl", "sphere256k_e8_dfl", "sphere256k_aplr",
-                                  "sphere256k_e8_aplr", "sphere256k_aflp", "sphere256k_e8_aflp"])
+                                  "sphere256k_e8_aplr", "sphere256k_aflp", "sphere256k_e8_aflp",
+                                  "sphere256k_e8_bfl"])
 def test_dfl_full_size(name):
     say("building", name)
     H = hmgen.build_preset(name)
@@ -219,6 +233,8 @@ def test_dfl_full_size(name):
     if name.endswith("_dfl"):
         assert np.all(H.group_dtype[:, 0] == {"sphere256k_dfl": hm.HM_DFL32,
                                               "sphere256k_e8_dfl": hm.HM_DFL40}[name])
+    if name.endswith("_bfl"):
+        assert np.all(H.group_dtype[:, 0] == hm.HM_BFL40)
     D = DeviceHMatrix(H, hm.HM_F64)
     say("uploaded", D.info["store_bytes"])
     x = hmgen.uniform_vector(H.n)
@@ -275,13 +291,14 @@ def _groups(H, fmts, rng):
 
 
 def _random_layout(seed):
-    """Random per-group formats (all fourteen with FP64 accumulation, the
+    """Random per-group formats (all seventeen with FP64 accumulation, the
     16/32-bit IEEE ones with FP32) and a random column-tile shape, n = 16384."""
     rng = np.random.default_rng(seed)
     H = hmgen.build_preset("sphere4k_mixed", n=16384)
     acc = hm.HM_F64 if seed % 2 else hm.HM_F32
     fmts = ([hm.HM_F64, hm.HM_F32, hm.HM_F16, hm.HM_BF16, hm.HM_DFL16, hm.HM_DFL24, hm.HM_DFL32,
-             hm.HM_DFL40, hm.HM_DFL48, hm.HM_AFLP16, hm.HM_AFLP24, hm.HM_AFLP32, hm.HM_AFLP40, hm.HM_AFLP48]
+             hm.HM_DFL40, hm.HM_DFL48, hm.HM_AFLP16, hm.HM_AFLP24, hm.HM_AFLP32, hm.HM_AFLP40, hm.HM_AFLP48,
+             hm.HM_BFL24, hm.HM_BFL40, hm.HM_BFL48]
             if acc == hm.HM_F64 else [hm.HM_F32, hm.HM_F16, hm.HM_BF16])
     _groups(H, fmts, rng)
     return H, acc, int(rng.integers(64, 513)), int(rng.integers(8, 65))

@@ -17,7 +17,7 @@ import hmgen
 import oracle
 from paper_2308_10960_amd import hm, blocks_from_table
 from conftest import ROOT
-from store_model import model_mvm, SZ, tables, decode_aflp
+from store_model import model_mvm, SZ, tables, decode_aflp, decode_bfl
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -258,6 +258,67 @@ def test_aflp_conversion_bit_exact(dense_dt, lr_dt):
     hm.hm_plan_destroy(p)
 
 
+BFL_NBYTES = {hm.HM_BFL24: 3, hm.HM_BFL40: 5, hm.HM_BFL48: 6}
+
+
+@pytest.mark.parametrize("dense_dt,lr_dt", [(hm.HM_BFL40, hm.HM_BFL40), (hm.HM_BFL48, hm.HM_BFL24),
+                                            (hm.HM_BFL24, hm.HM_BFL48)])
+def test_bfl_conversion_bit_exact(dense_dt, lr_dt):
+    """BFL entries sit at the offsets hm_plan_locate reports, stored like
+    the DFL value of the same bytes; their code, read by its fields, is the
+    oracle's rounded value bit for bit."""
+    H = hmgen.build_preset("sphere4k")
+    _set_dtypes(H, dense_dt, lr_dt)
+    p, info, buf = _pack(H, hm.HM_F64)
+    rng = np.random.default_rng(3)
+    seen = set()
+    for bi in rng.choice(H.nblocks, 200, replace=False):
+        a, b, s = H.factors(bi)
+        for which, F in ((0, a), (1, b)):
+            if F is None or F.size == 0:
+                continue
+            dt = lr_dt if H.adm[bi] else dense_dt
+            nb = BFL_NBYTES[dt]
+            for _ in range(6):
+                i, j = int(rng.integers(F.shape[0])), int(rng.integers(F.shape[1]))
+                off, got_dt, lo_off = hm.hm_plan_locate(p, int(bi), which, i, j, lo=True)
+                assert got_dt == dt
+                if nb == 3:
+                    code = (int(buf[off: off + 2].view("<u2")[0]) << 48) | (int(buf[lo_off]) << 40)
+                else:
+                    code = int(buf[off: off + 4].view("<u4")[0]) << 32
+                    code |= (int(buf[lo_off]) << 24) if nb == 5 else (int(buf[lo_off: lo_off + 2].view("<u2")[0]) << 16)
+                v = decode_bfl(np.array([code], np.uint64), nb)[0]
+                assert v == oracle.round_bfl(np.array([F[i, j]]), nb)[0], (bi, which, i, j)
+                seen.add(dt)
+    assert seen == {dense_dt, lr_dt}
+    hm.hm_plan_destroy(p)
+
+
+def test_bfl_plan_rules():
+    """BFL needs FP64 accumulation; a value beyond FP32's range cannot be
+    stored (HM_EINVAL from the packer)."""
+    H = hmgen.build_preset("sphere4k")
+    _set_dtypes(H, hm.HM_F64, hm.HM_BFL40)
+    with pytest.raises(hm.HMError) as e:
+        hm.hm_build_plan(H.n, H.n, blocks_from_table(H), hm.HM_F32)
+    assert e.value.status == hm.HM_EDTYPE
+    _set_dtypes(H, hm.HM_BFL24, hm.HM_F64)
+    bi = int(np.flatnonzero(H.adm == 0)[0])
+    D, _, _ = H.factors(bi)
+    keep = float(D[0, 0])
+    D[0, 0] = 1e39
+    try:
+        p = hm.hm_build_plan(H.n, H.n, blocks_from_table(H), hm.HM_F64)
+        buf = np.zeros(hm.hm_plan_info(p)["store_bytes"], np.uint8)
+        with pytest.raises(hm.HMError) as e:
+            hm.hm_pack_host(p, H.a_ptr, H.b_ptr, H.s_ptr, buf)
+        assert e.value.status == hm.HM_EINVAL and "BFL" in str(e.value)
+        hm.hm_plan_destroy(p)
+    finally:
+        D[0, 0] = keep
+
+
 def test_aflp_plan_rules():
     """AFLP needs FP64 accumulation; a block whose values are not finite
     cannot be encoded (HM_EINVAL from the packer)."""
@@ -305,7 +366,7 @@ def test_dfl_plan_rules():
 
 @pytest.mark.parametrize("which", ["f64", "mixed", "mixed16k", "bf16", "dfl32", "dfl40_16k", "dfl48",
                                    "dfl_mix", "dfl_any_16k", "dfl16", "dfl24", "aplr", "aflp",
-                                   "aflp_any_16k", "aflp_zeros"])
+                                   "aflp_any_16k", "aflp_zeros", "bfl40", "bfl_any_16k"])
 def test_store_model_matches_oracle(which, f64_4k, mixed4k):
     """The packed store, read as its layout defines it, gives the oracle's
     product.  At n = 16384 some blocks span several column chunks (partials
@@ -330,6 +391,12 @@ def test_store_model_matches_oracle(which, f64_4k, mixed4k):
                     if F is not None and F.size:
                         F[rng.random(F.shape) < 0.1] = 0.0
             H.factors(int(np.flatnonzero(H.adm == 0)[3]))[0][:] = 0.0
+    elif which == "bfl40":
+        H = hmgen.build_preset("sphere4k_bfl")
+    elif which == "bfl_any_16k":
+        H = hmgen.build_preset("sphere4k", n=16384, eps=1e-10)
+        _aplr_like(H, [hm.HM_F64, hm.HM_BFL24, hm.HM_BFL40, hm.HM_BFL48, hm.HM_DFL40, hm.HM_AFLP32,
+                       hm.HM_F32], seed=8)
     elif which == "aflp_any_16k":
         H = hmgen.build_preset("sphere4k", n=16384, eps=1e-10)
         _aplr_like(H, [hm.HM_F64, hm.HM_DFL32, hm.HM_AFLP16, hm.HM_AFLP24, hm.HM_AFLP32, hm.HM_AFLP40,
@@ -347,7 +414,7 @@ def test_store_model_matches_oracle(which, f64_4k, mixed4k):
                                  "dfl16": hm.HM_DFL16, "dfl24": hm.HM_DFL24}[which])
     else:
         H = {"f64": f64_4k, "mixed": mixed4k}[which]
-    fp64 = which in ("f64", "aplr") or which.startswith("dfl") or which.startswith("aflp")
+    fp64 = which in ("f64", "aplr") or which.startswith(("dfl", "aflp", "bfl"))
     acc = hm.HM_F64 if fp64 else hm.HM_F32
     p, info, buf = _pack(H, acc)
     if which.endswith("16k"):
@@ -467,7 +534,7 @@ def test_tile_shape_from_tune_cache_and_limits(tmp_path):
 
 @pytest.mark.parametrize("seed", [11, 12, 13])
 def test_random_layouts_match_oracle(seed):
-    """Random tile shapes with random per-group formats (all fourteen with
+    """Random tile shapes with random per-group formats (all seventeen with
     FP64 accumulation; the 16/32-bit IEEE formats with FP32 accumulation), over
     several column chunks: the packed store, read as its layout defines it,
     gives the oracle's product on the rounded factors, and every tile keeps
@@ -477,7 +544,8 @@ def test_random_layouts_match_oracle(seed):
     chunk, tile = int(rng.integers(64, 513)), int(rng.integers(8, 65))
     acc = hm.HM_F64 if seed % 2 else hm.HM_F32
     fmts = ([hm.HM_F64, hm.HM_F32, hm.HM_F16, hm.HM_BF16, hm.HM_DFL16, hm.HM_DFL24, hm.HM_DFL32,
-             hm.HM_DFL40, hm.HM_DFL48, hm.HM_AFLP16, hm.HM_AFLP24, hm.HM_AFLP32, hm.HM_AFLP40, hm.HM_AFLP48]
+             hm.HM_DFL40, hm.HM_DFL48, hm.HM_AFLP16, hm.HM_AFLP24, hm.HM_AFLP32, hm.HM_AFLP40, hm.HM_AFLP48,
+             hm.HM_BFL24, hm.HM_BFL40, hm.HM_BFL48]
             if acc == hm.HM_F64 else [hm.HM_F32, hm.HM_F16, hm.HM_BF16])
     _aplr_like(H, fmts, seed=seed)
     blocks = blocks_from_table(H)
