@@ -365,3 +365,61 @@ def test_bfl_format_choice():
                     (1e-13, DT_F64)):
         assert hmgen.bfl_format(eps) == dt, eps
     assert (DT_BFL24, DT_BFL40, DT_BFL48) == (oracle.BFL24, oracle.BFL40, oracle.BFL48)
+
+
+def _aflp_variant(x, nbytes, shift=1.0, pow2_scale=True, e_delta=0):
+    """AFLP rounding re-done with knobs for planted mistakes: the shift added
+    after scaling, the scale (a power of two, or the smallest magnitude
+    itself) and an error in the exponent bit count.  With the defaults it
+    must reproduce oracle.round_aflp."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x[x != 0])
+    k = int(np.frexp(a.min())[1]) - 1
+    scale = 2.0 ** k if pow2_scale else a.min()
+    e = oracle.aflp_params(x, nbytes)[1] + e_delta
+    m = 8 * nbytes - 1 - e
+    out = np.zeros_like(x)
+    nz = x != 0
+    d = np.abs(x[nz]) / scale + shift
+    _, ex = np.frexp(d)
+    lsb = ex - 1 - m
+    dr = np.ldexp(np.rint(np.ldexp(d, -lsb)), lsb)
+    # a field of e bits holds binary exponents below 2^e: larger ones saturate
+    dr = np.minimum(dr, np.ldexp(2.0 - 2.0 ** -m, 2 ** e - 1))
+    out[nz] = np.copysign((dr - shift) * scale, x[nz])
+    return out
+
+
+def test_aflp_planted_mistakes_are_caught():
+    """Plausible mistakes in AFLP rounding (no shift by 1, the smallest
+    magnitude as the scale, one exponent bit too few) each break a pin:
+    the unit-binade closed form, the error bound, or the nearest-code
+    brute force."""
+    rng = np.random.default_rng(9)
+    m2 = 8 * 3 - 2
+    unit = 1.0 + rng.integers(0, 2 ** 51, 500).astype(np.float64) * 2.0 ** -51
+    unit = unit[unit < 1.75] * rng.choice([-1.0, 1.0], unit[unit < 1.75].size)
+    closed = np.copysign(np.rint(np.abs(unit) * 2.0 ** (m2 - 1)) * 2.0 ** -(m2 - 1), unit)
+    wide = _aflp_block(rng, 1500, 9)
+    k, e, m = oracle.aflp_params(wide, 2)
+    bound = (2.0 ** -(m + 1) + 2.0 ** -52) * (np.abs(wide) + 2.0 ** k)
+
+    def codebook_ok(r):
+        j = np.arange(1, 2 ** e, dtype=np.float64)[:, None]
+        f = np.arange(2 ** m, dtype=np.float64)[None, :]
+        codes = np.sort(np.concatenate([[0.0], ((2.0 ** j * (1 + f * 2.0 ** -m) - 1) * 2.0 ** k).ravel()]))
+        r = np.abs(r)
+        pos = np.minimum(np.searchsorted(codes, r), codes.size - 1)
+        return bool(np.all(codes[pos] == r))
+
+    def pins_hold(fn):
+        return (np.array_equal(fn(unit, 3), closed) and np.all(np.abs(fn(wide, 2) - wide) <= bound)
+                and codebook_ok(fn(wide, 2)))
+
+    # the knob-free variant is the oracle, and it passes
+    np.testing.assert_array_equal(_aflp_variant(wide, 2), oracle.round_aflp(wide, 2))
+    assert pins_hold(lambda v, nb: oracle.round_aflp(v, nb))
+    for mistake in (lambda v, nb: _aflp_variant(v, nb, shift=0.0),
+                    lambda v, nb: _aflp_variant(v, nb, pow2_scale=False),
+                    lambda v, nb: _aflp_variant(v, nb, e_delta=-1)):
+        assert not pins_hold(mistake)
