@@ -75,14 +75,15 @@ __device__ __forceinline__ double aflp_value(u32x4 r, u32x2 lo, int c, unsigned 
 }
 
 // A BFL element (exact): the code P, left-aligned like a DFL encoding of
-// the same bytes, holds FP32's sign, exponent and leading mantissa bits;
-// moved down 3 bits and rebiased it is the FP64 value; P = 0 is zero.
+// the same bytes, holds FP32's sign, exponent E and leading mantissa bits.
+// With the magnitude moved down 3 bits it is the normal FP64 number
+// 2^(E - 1023) (1.f) (E >= 1), and 0 for the zero code; times 2^896 (exact)
+// it is the value, with no test for zero.
 template <int DT>
 __device__ __forceinline__ double bfl_value(u32x4 r, u32x2 lo, int c) {
   const unsigned long long P = dfl_bits<storage_dt(DT)>(r, lo, c);
-  const unsigned long long mag = P & 0x7fffffffffffffffull;
-  const unsigned long long d = mag ? (((mag >> 3) + kBflRebias) | (P & 0x8000000000000000ull)) : 0ull;
-  return __longlong_as_double((long long)d);
+  const unsigned long long q = ((P & 0x7fffffffffffffffull) >> 3) | (P & 0x8000000000000000ull);
+  return __longlong_as_double((long long)q) * 0x1p896;
 }
 
 // The low-byte plane entry idx of a DFL40 / DFL48 / DFL24 region at p
