@@ -214,7 +214,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the row-panel sharding over GPUs is described in DESIGN.md, not built)",
+              "(sharding the row panels over GPUs, with one all-gather of x, is designed but not built)",
               file=sys.stderr)
         sys.exit(2)
 
