@@ -213,7 +213,7 @@ def main():
                     help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
               "(sharding the row panels over GPUs, with one all-gather of x, is designed but not built)",
               file=sys.stderr)
         sys.exit(2)
