@@ -423,3 +423,20 @@ def test_aflp_planted_mistakes_are_caught():
                     lambda v, nb: _aflp_variant(v, nb, pow2_scale=False),
                     lambda v, nb: _aflp_variant(v, nb, e_delta=-1)):
         assert not pins_hold(mistake)
+
+
+@pytest.mark.parametrize("kind,nbytes", [("dfl", 3), ("dfl", 5), ("bfl", 3), ("bfl", 5), ("bfl", 6),
+                                         ("aflp", 2), ("aflp", 4), ("aflp", 6)])
+def test_byte_aligned_rounding_invariants(kind, nbytes):
+    """Properties of any round-to-nearest: monotone (x <= y gives
+    fl(x) <= fl(y)), idempotent (rounded values round to themselves; for
+    AFLP with the block's own parameters unchanged) and odd."""
+    fn = {"dfl": oracle.round_dfl, "bfl": oracle.round_bfl, "aflp": oracle.round_aflp}[kind]
+    rng = np.random.default_rng(nbytes + len(kind))
+    x = np.sort(rng.choice([-1.0, 1.0], 4000) * 10.0 ** rng.uniform(-12, 12, 4000))
+    r = fn(x, nbytes)
+    assert np.all(np.diff(r) >= 0)
+    np.testing.assert_array_equal(fn(r, nbytes), r)
+    np.testing.assert_array_equal(fn(-x, nbytes), -r)
+    if kind == "aflp":
+        assert oracle.aflp_params(r, nbytes) == oracle.aflp_params(x, nbytes)
