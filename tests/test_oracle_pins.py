@@ -9,7 +9,10 @@ P5 kernel identity: the Matern covariance of Sec. 5.1 at nu = 1/2 is exp(-d/l).
 P7 linearity, y += semantics, x = 0.
 P8 physics: Laplace on the unit sphere with x = 1 has row sums ~ n/(4 pi).
 Plus: the decoded (mixed-precision) oracle stays within the block-relative
-storage accuracy, and planted mistakes are caught by these pins.
+storage accuracy, and planted mistakes are caught by these pins.  P1 and P2
+also run on matrices whose low-rank leaves keep s (W diag(s) X^T, Sec. 3.3),
+so the oracle's s step is pinned: s applied twice, a neighbouring column's s
+or s ignored each break them.
 """
 
 import math
@@ -254,3 +257,99 @@ def test_planted_mistakes_are_caught():
     bad.ce[i] -= 1
     y = oracle.hmvm(bad, x)
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) > 1e-6
+
+
+# ---------------------------------------------------------------- the sigma step
+# Low-rank leaves kept in the form W diag(s) X^T (Sec. 3.3): the oracle scales
+# t = X^T x by s before applying W.  These pins run on matrices built with s
+# kept, so that a mistake in that step (s applied twice, a neighbouring
+# column's s, s ignored) moves the result far outside every bound.
+
+@pytest.fixture(scope="module")
+def sphere4k_sigma():
+    pts = hmgen.fibonacci_sphere(4096)
+    return hm.build_hmatrix(pts, hm.KERNEL_LAPLACE, leaf=64, eta=2.0, eps=1e-6, keep_sigma=True)
+
+
+def _sigma_spread(H):
+    """Largest ratio between neighbouring singular values of one leaf, and
+    the largest |log s|: a pin on the s step is only as sharp as these."""
+    spread, scale = 1.0, 0.0
+    for i in np.flatnonzero(H.adm):
+        _, _, s = H.factors(i)
+        if s.size > 1:
+            spread = max(spread, float(np.max(s[:-1] / s[1:])))
+        if s.size:
+            scale = max(scale, float(np.max(np.abs(np.log(s)))))
+    return spread, scale
+
+
+def test_p1_brute_force_bound_sigma_form(sphere4k_sigma):
+    """P1 on a matrix whose low-rank leaves carry s: the product is within
+    2 eps |A|_F |x| of the dense kernel matrix, and every leaf's
+    W diag(s) X^T within 2 eps of its block."""
+    H = sphere4k_sigma
+    assert H.keep_sigma
+    spread, scale = _sigma_spread(H)
+    assert spread > 10 and scale > 3          # s far from 1 and far from its neighbours
+    A = dense_kernel(H)
+    x = hmgen.uniform_vector(H.n)
+    y = oracle.hmvm(H, x)
+    assert np.linalg.norm(y - A @ x) <= 2 * H.eps * np.linalg.norm(A) * np.linalg.norm(x)
+    worst = 0.0
+    for i in np.flatnonzero(H.adm):
+        W, X, s = H.factors(i)
+        Ab = A[H.rb[i]:H.re[i], H.cb[i]:H.ce[i]]
+        worst = max(worst, np.linalg.norm(Ab - (W * s) @ X.T) / np.linalg.norm(Ab))
+        # W and X are orthonormal (Alg. 1), so s carries the whole scale
+        np.testing.assert_allclose(W.T @ W, np.eye(W.shape[1]), atol=1e-12)
+        np.testing.assert_allclose(X.T @ X, np.eye(X.shape[1]), atol=1e-12)
+    assert worst <= 2 * H.eps
+
+
+@pytest.mark.parametrize("name", ["sphere4k_mixed", "sphere4k_aplr"])
+def test_p2_dense_assembly_sigma_form(name):
+    """P2 on the mixed-precision and APLR matrices (s kept): the densely
+    assembled matrix times x equals the oracle, both for the unrounded
+    factors and for the decoded ones the parity tests use."""
+    H = hmgen.build_preset(name)
+    assert H.keep_sigma
+    sig = oracle.F32 if name.endswith("mixed") else oracle.F64
+    dec = oracle.decoded_factors(H, sigma_dtype=sig)
+    x = hmgen.uniform_vector(H.n, seed=7)
+    for factors in (None, dec):
+        ref = assemble(H, factors) @ x
+        y = oracle.hmvm(H, x, factors=factors)
+        assert np.linalg.norm(y - ref) <= 1e-13 * np.linalg.norm(ref)
+    # the decoded s really differs from the unrounded one (FP32) where it should
+    if sig == oracle.F32:
+        i = int(np.flatnonzero(H.adm)[0])
+        assert np.any(dec[i][2] != H.factors(i)[2])
+
+
+def test_planted_sigma_mistakes_are_caught(sphere4k_sigma):
+    """An oracle that applies s twice, takes the neighbouring column's s or
+    ignores s computes the correct product of mutated s; each such product
+    breaks P1's bound and P2's assembly of the true factors."""
+    H = sphere4k_sigma
+    A = dense_kernel(H)
+    x = hmgen.uniform_vector(H.n, seed=8)
+    ref = assemble(H) @ x
+    bound = 2 * H.eps * np.linalg.norm(A) * np.linalg.norm(x)
+    base = [tuple(None if v is None else np.array(v, order="F") for v in H.factors(i))
+            for i in range(H.nblocks)]
+    assert np.linalg.norm(oracle.hmvm(H, x, factors=base) - ref) <= 1e-13 * np.linalg.norm(ref)
+
+    def with_sigma(fn):
+        return [t if t[2] is None else (t[0], t[1], np.ascontiguousarray(fn(t[2]))) for t in base]
+
+    mistakes = {
+        "twice": lambda s: s * s,
+        "next column": lambda s: np.roll(s, -1),
+        "previous column": lambda s: np.roll(s, 1),
+        "ignored": lambda s: np.ones_like(s),
+    }
+    for what, fn in mistakes.items():
+        y = oracle.hmvm(H, x, factors=with_sigma(fn))
+        assert np.linalg.norm(y - A @ x) > bound, what
+        assert np.linalg.norm(y - ref) > 1e-3 * np.linalg.norm(ref), what
