@@ -108,8 +108,11 @@ def read_traffic(kernel, workload):
     return d.get("bytes_per_launch")
 
 
-SERVE_SET = [("sphere", 16384), ("cube", 16384), ("sphere", 32768), ("cube", 32768),
-             ("sphere", 65536), ("cube", 65536), ("sphere", 131072), ("cube", 131072)]
+# the 8 resident matrices of the request loop: sphere-Laplace and cube-exp
+# kernels, n from 2^14 to 2^20 (the n = 2^20 cube, 111 s of host construction
+# and 137 GB of host memory, is replaced by its n = 2^18 instance)
+SERVE_SET = [("sphere", 16384), ("cube", 16384), ("sphere", 65536), ("cube", 65536),
+             ("sphere", 262144), ("cube", 131072), ("sphere", 1048576), ("cube", 262144)]
 
 
 def serve_bench(args, torch, hmgen, hm, DeviceHMatrix):
@@ -118,47 +121,64 @@ def serve_bench(args, torch, hmgen, hm, DeviceHMatrix):
     First a closed-loop burst measures the saturation rate; then open-loop
     Poisson streams at 0.5, 0.8 and 0.95 x that rate give p50 / p99 latency
     (the 0.8 point is the headline)."""
-    mats, Ds = [], []
+    sizes, Ds = [], []
     for geo, n in SERVE_SET:
         name = "sphere4k_mixed" if geo == "sphere" else "cube4k"
         H = hmgen.build_preset(name, n=n, dtype="mixed")
-        mats.append(H)
         cache = None if args.no_tune_cache or not os.path.exists(args.tune_cache) else args.tune_cache
         Ds.append(DeviceHMatrix(H, hm.HM_F32, max_nrhs=64, tune_cache=cache))
+        torch.cuda.synchronize()
+        sizes.append(H.n)
         log(f"serve: built {geo} n={n} in {H.build_seconds:.1f}s, store {Ds[-1].info['store_bytes'] / 1e9:.2f} GB")
+        del H                                     # the host factors are no longer needed
     arena_bytes = args.serve_arena_gb << 30
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
     streams = [torch.cuda.Stream() for _ in range(args.serve_streams)]
     rng = np.random.default_rng(hmgen.presets.SEED_REQUESTS)
     # right-hand sides: one N(0,1) pool of 64 columns per matrix; a request of
     # r columns reads the first r (a contiguous column-major slice)
-    pool = [np.asfortranarray(rng.standard_normal((H.n, 64)).astype(np.float32)) for H in mats]
+    pool = [np.asfortranarray(rng.standard_normal((n, 64)).astype(np.float32)) for n in sizes]
+
+    # results: a ring of OUT_RING output buffers per matrix; a request reuses
+    # the buffer of the request OUT_RING places before it on the same
+    # matrix, after waiting for that one (host memory stays bounded)
+    OUT_RING = 24
+    outbuf = [[None] * OUT_RING for _ in sizes]
 
     def make(count):
         reqs = []
         for _ in range(count):
-            m = int(rng.integers(len(mats)))
+            m = int(rng.integers(len(sizes)))
             r = int(rng.integers(1, 65))
-            reqs.append((m, r, pool[m][:, :r], np.zeros((mats[m].n, r), np.float32, order="F")))
+            reqs.append((m, r, pool[m][:, :r]))
         return reqs
 
     def run(reqs, rate):
         s = hm.hm_server_create([D.handle for D in Ds], arena, arena_bytes, streams)
-        tickets = []
+        last = [[None] * OUT_RING for _ in sizes]
+        count = [0] * len(sizes)
+        res = []
         t0 = time.perf_counter()
         gaps = rng.exponential(1.0 / rate, len(reqs)) if rate else np.zeros(len(reqs))
         t_next = t0
-        for (m, r, X, Y), g in zip(reqs, gaps):
+        for (m, r, X), g in zip(reqs, gaps):
+            j = count[m] % OUT_RING
+            count[m] += 1
+            if last[m][j] is not None:
+                res.append(hm.hm_wait(s, last[m][j], 600_000_000))
+            if outbuf[m][j] is None:
+                outbuf[m][j] = np.zeros((sizes[m], 64), np.float32, order="F")
+            Y = outbuf[m][j]
             t_next += g
             while time.perf_counter() < t_next:
                 pass
-            tickets.append(hm.hm_submit(s, m, r, X, X.shape[0], Y, Y.shape[0]))
-        res = [hm.hm_wait(s, t, 600_000_000) for t in tickets]
+            last[m][j] = hm.hm_submit(s, m, r, X, X.shape[0], Y, Y.shape[0])
+        res += [hm.hm_wait(s, t, 600_000_000) for row in last for t in row if t is not None]
         wall = time.perf_counter() - t0
         p50, p99, mps = hm.hm_server_stats(s)
         hm.hm_server_destroy(s)
-        assert all(r == hm.HM_OK for r in res), res
-        rhs = sum(r for _, r, _, _ in reqs)
+        assert len(res) == len(reqs) and all(r == hm.HM_OK for r in res), res
+        rhs = sum(r for _, r, _ in reqs)
         return {"p50_us": round(p50, 1), "p99_us": round(p99, 1), "matvecs_per_s": round(rhs / wall, 1),
                 "requests": len(reqs), "rhs": rhs, "wall_s": round(wall, 3)}
 
@@ -184,6 +204,43 @@ def serve_bench(args, torch, hmgen, hm, DeviceHMatrix):
     return out
 
 
+def host_threads() -> int:
+    """Host cores this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return min(n, int(env)) if env.isdigit() and int(env) > 0 else n
+
+
+def cpu_baseline(H, xh, alg_bytes, seconds):
+    """The CPU oracle timed on full single-RHS products of the same matrix:
+    the plain single-threaded loop (the pinned oracle, as it stands) until
+    ``seconds`` have passed and at least 3 runs, then its all-cores variant
+    (bitwise the same result) for at least 3 runs; medians."""
+    import oracle
+    single = []
+    while len(single) < 3 or sum(single) < seconds:
+        a = time.perf_counter()
+        oracle.hmvm(H, xh)
+        single.append(time.perf_counter() - a)
+    nthreads = host_threads()
+    multi, used = [], 0
+    while len(multi) < 3 or sum(multi) < seconds / 4:
+        a = time.perf_counter()
+        _, used = oracle.hmvm_omp(H, xh, nthreads=nthreads)
+        multi.append(time.perf_counter() - a)
+    t1, tn = float(np.median(single)), float(np.median(multi))
+    return {"value": round(alg_bytes / t1 / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "seconds_per_matvec": round(t1, 4), "runs": len(single),
+            "sample": f"median of {len(single)} full single-RHS products of the same n={H.n} matrix, "
+                      "single-threaded FP64 oracle",
+            "all_cores": {"value": round(alg_bytes / tn / 1e9, 3), "unit": "GB/s", "cores": used,
+                          "affinity_cpus": len(os.sched_getaffinity(0)),
+                          "seconds_per_matvec": round(tn, 4), "runs": len(multi),
+                          "sample": f"median of {len(multi)} full products, the oracle's all-cores variant "
+                                    "(OpenMP over row ranges, bitwise the single-threaded result)"}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,7 +253,7 @@ def main():
                     help="right-hand sides per product (> 1: hm_mvm_batch; reported separately)")
     ap.add_argument("--n", type=int, default=0, help="override the workload size (not the default line)")
     ap.add_argument("--dtype", default=None,
-                    help="override the workload's storage (f64, f32, mixed, dfl, aplr, aflp, bfl)")
+                    help="override the workload's storage (f64, f32, mixed, mixed64, dfl, aplr, aflp, bfl)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner on this matrix before the timed region and store its "
                          "choice in the tune cache (default: read the cache, no tuning)")
@@ -243,7 +300,8 @@ def main():
     H = hmgen.build_preset(args.workload, n=args.n or None, dtype=p["dtype"])
     st = H.stats()
     log("built in %.1fs: %s" % (H.build_seconds, st))
-    mixed = p["dtype"] not in ("f64", "dfl", "aplr", "aflp", "bfl")   # the byte-aligned formats accumulate in FP64
+    # the byte-aligned formats and the eps = 1e-8 mixed storage accumulate in FP64
+    mixed = p["dtype"] not in ("f64", "dfl", "aplr", "aflp", "bfl", "mixed64")
     acc = hm.HM_F32 if mixed else hm.HM_F64
     storage = p["dtype"]
     if storage == "dfl":
@@ -254,6 +312,8 @@ def main():
         storage = "aflp-per-block"
     elif storage == "bfl":
         storage = hmgen.hmatrix.DT_NAMES[hmgen.bfl_format(p["eps"])]
+    elif storage == "mixed64":
+        storage = "mixed-f64acc (dense f64, low-rank f32/f16/bf16)"
     vs = 4 if mixed else 8
     stream = torch.cuda.Stream()
     cache = None if args.no_tune_cache or not os.path.exists(args.tune_cache) else args.tune_cache
@@ -390,18 +450,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        xh = x.cpu().numpy().astype(np.float64)   # one right-hand side
-        runs, t_cpu = 0, 0.0
-        while runs == 0 or t_cpu < args.cpu_seconds:
-            a = time.perf_counter()
-            oracle.hmvm(H, xh)
-            t_cpu += time.perf_counter() - a
-            runs += 1
-        cpu = {"value": round(info["alg_bytes"] / (t_cpu / runs) / 1e9, 3), "unit": "GB/s", "cores": 1,
-               "kind": "oracle", "seconds_per_matvec": round(t_cpu / runs, 4),
-               "sample": f"{runs} full single-RHS products of the same n={H.n} matrix, "
-                         "single-threaded FP64 oracle"}
+        cpu = cpu_baseline(H, x.cpu().numpy().astype(np.float64), info["alg_bytes"], args.cpu_seconds)
         log("cpu baseline", cpu)
 
     serving = None

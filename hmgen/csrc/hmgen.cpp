@@ -633,12 +633,18 @@ void hmg_eval(const hmg_tree* t, const int64_t* rows, const int64_t* cols, int64
 // starting from all columns (and S) in FP32, columns are lowered from the
 // smallest singular value upward to FP16 (or BF16 where FP16 overflows)
 // while the sum of per-column errors stays within the budget; the sum is a
-// rigorous bound by the triangle inequality.  allow_f64 lets a block whose
-// FP32 error alone exceeds the budget fall back to FP64.
+// rigorous bound by the triangle inequality.
+// flags: bit 0 (allow FP64) lets a block whose FP32 error alone exceeds the
+// budget fall back to FP64; bit 1 (dense FP64) keeps every dense block in
+// FP64; bit 2 (s in FP64) prices the columns with s exact, for products
+// that accumulate in FP64 and keep s in FP64.
 // Output per block: ngroups, group_cols[4], group_dtype[4]; for low-rank
 // blocks the groups are in column order (largest singular values first).
-int hmg_select_precision(const hmg_tree* t, double tol, int32_t allow_f64, int32_t* ngroups,
+// Returns the number of blocks whose storage misses the budget (or that
+// need more than 4 column groups); 0 when every block meets it.
+int hmg_select_precision(const hmg_tree* t, double tol, int32_t flags, int32_t* ngroups,
                          int32_t* group_cols, int32_t* group_dtype, double* err_bound) {
+  const bool allow_f64 = flags & 1, dense_f64 = flags & 2, sigma_f64 = flags & 4;
   const int64_t nb = (int64_t)t->blocks.size();
   std::atomic<int> bad{0};
 #pragma omp parallel for schedule(dynamic, 16)
@@ -656,6 +662,7 @@ int hmg_select_precision(const hmg_tree* t, double tol, int32_t allow_f64, int32
       double chosen_err = 0;
       const int cands[3] = {DT_F16, DT_BF16, DT_F32};
       for (int dt : cands) {
+        if (dense_f64) break;
         double e2 = 0;
         bool fin = true;
         for (double v : b.a) {
@@ -665,7 +672,7 @@ int hmg_select_precision(const hmg_tree* t, double tol, int32_t allow_f64, int32
         }
         if (fin && std::sqrt(e2) <= budget) { chosen = dt; chosen_err = std::sqrt(e2); break; }
       }
-      if (chosen == DT_F64 && !allow_f64) {
+      if (chosen == DT_F64 && !allow_f64 && !dense_f64) {
         double e2 = 0;
         for (double v : b.a) { double r = rnd(v, DT_F32); e2 += (v - r) * (v - r); }
         chosen = DT_F32; chosen_err = std::sqrt(e2); bad.fetch_add(1);
@@ -687,7 +694,7 @@ int hmg_select_precision(const hmg_tree* t, double tol, int32_t allow_f64, int32
       const double* w = &b.a[(size_t)c * m];
       const double* x = &b.b[(size_t)c * n];
       const double s = b.s[c];
-      const double sh = dt == DT_F64 ? s : rnd(s, DT_F32);
+      const double sh = dt == DT_F64 || sigma_f64 ? s : rnd(s, DT_F32);
       double aa = 0, xx = 0, wh2 = 0, dd = 0, aw = 0, xd = 0;
       finite = true;
       for (int64_t i = 0; i < m; ++i) {

@@ -184,8 +184,13 @@ class HMatrix:
         return self.points[self.perm]
 
     # ------------------------------------------------------------ precision
-    def select_precision(self, tol: float, allow_f64: bool = False) -> int:
-        """Choose per-block storage formats (see hmg_select_precision)."""
+    def select_precision(self, tol: float, allow_f64: bool = False, dense_f64: bool = False,
+                         sigma_f64: bool = False) -> int:
+        """Choose per-block storage formats (see hmg_select_precision):
+        allow_f64 lets a low-rank block that FP32 cannot hold fall back to
+        FP64, dense_f64 keeps the dense blocks in FP64, sigma_f64 prices the
+        columns with s exact (s kept in FP64 by FP64-accumulating products).
+        Returns the number of blocks that miss the budget."""
         if not self.keep_sigma:
             raise ValueError("precision selection needs keep_sigma=True")
         nb = self.nblocks
@@ -194,7 +199,8 @@ class HMatrix:
         self.group_dtype = np.zeros((nb, 4), np.int32)
         self.store_err_bound = np.zeros(nb)
         bad = lib().hmg_select_precision(
-            C.c_void_p(self.handle), tol, int(allow_f64), self.ngroups,
+            C.c_void_p(self.handle), tol, int(allow_f64) | 2 * int(dense_f64) | 4 * int(sigma_f64),
+            self.ngroups,
             self.group_cols.reshape(-1), self.group_dtype.reshape(-1), self.store_err_bound)
         return int(bad)
 

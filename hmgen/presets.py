@@ -27,6 +27,11 @@ PRESETS = {
     "sphere256k_mixed": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-6, dtype="mixed"),
     # batched multi-RHS: n = 2^20 cube, FP32 factors, 32 right-hand sides
     "cube1m": dict(geometry="cube", n=1048576, kernel="exp", eps=1e-6, dtype="f32", nrhs=32),
+    # mixed-precision storage at eps = 1e-8 with FP64 accumulation: dense
+    # (near-field) blocks and y in FP64, low-rank column groups in
+    # FP32 / FP16 / BF16 within the stated 1e-6 result tolerance, s in FP64
+    "sphere256k_e8_mixed": dict(geometry="sphere", n=262144, kernel="laplace", eps=1e-8, dtype="mixed64"),
+    "sphere4k_e8_mixed": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-8, dtype="mixed64"),
     # small mixed case for parity
     "sphere4k_mixed": dict(geometry="sphere", n=4096, kernel="laplace", eps=1e-6, dtype="mixed"),
     "cube4k": dict(geometry="cube", n=4096, kernel="exp", eps=1e-6, dtype="f32"),
@@ -77,13 +82,16 @@ def build_preset(name: str, *, n: int | None = None, eps: float | None = None,
     dtype = p["dtype"] if dtype is None else dtype
     pts = make_points(p["geometry"], n)
     kern = KERNEL_LAPLACE if p["kernel"] == "laplace" else KERNEL_EXP
-    mixed = dtype == "mixed"
+    mixed = dtype in ("mixed", "mixed64")
     H = build_hmatrix(pts, kern, leaf=leaf, eta=eta, eps=eps, keep_sigma=mixed or dtype == "aplr",
                       nthreads=nthreads)
-    if mixed:
-        H.select_precision(MIXED_TOL / 2)
+    bad = 0
+    if dtype == "mixed":
+        bad = H.select_precision(MIXED_TOL / 2)
+    elif dtype == "mixed64":
+        bad = H.select_precision(MIXED_TOL / 2, dense_f64=True, sigma_f64=True)
     elif dtype == "aplr":
-        H.select_precision_dfl(eps / 2)
+        bad = H.select_precision_dfl(eps / 2)
     elif dtype == "dfl":
         H.set_uniform_dtype(dfl_format(eps))
     elif dtype == "aflp":
@@ -92,6 +100,9 @@ def build_preset(name: str, *, n: int | None = None, eps: float | None = None,
         H.set_uniform_dtype(bfl_format(eps))
     else:
         H.set_uniform_dtype(DT_F64 if dtype == "f64" else DT_F32)
+    if bad:
+        raise RuntimeError(f"{name} (n={n}, eps={eps}, {dtype}): {bad} blocks cannot be stored "
+                           "within their share of the error budget")
     H.dtype_mode = dtype
     H.preset = name
     return H

@@ -330,11 +330,17 @@ hm_status hm_submit(hm_server* s, int32_t mat, int32_t nrhs, const void* h_X, in
                     void* h_Y, int64_t ldy, uint64_t* ticket);
 /* Whether a ticket has completed and with which status (HM_ESTATE for an
  * unknown ticket); hm_wait blocks up to timeout_us (< 0: no limit) and
- * returns HM_ETIMEOUT if the ticket is still running. */
+ * returns HM_ETIMEOUT if the ticket is still running.  Once either call has
+ * reported a ticket done (hm_poll with *done = 1, or hm_wait returning
+ * HM_OK), the server forgets the ticket: later calls on it return
+ * HM_ESTATE.  A completed ticket that is never reported stays until the
+ * server is destroyed. */
 hm_status hm_poll(hm_server* s, uint64_t ticket, int32_t* done, hm_status* result);
 hm_status hm_wait(hm_server* s, uint64_t ticket, int64_t timeout_us, hm_status* result);
-/* Latency percentiles (microseconds, completion minus submission) and
- * throughput (right-hand sides completed per second) since creation. */
+/* Latency percentiles (microseconds, completion minus submission) over the
+ * most recent 2^20 completed requests, and throughput (right-hand sides
+ * completed per second, from the first submission to the last completion)
+ * since creation. */
 hm_status hm_server_stats(hm_server* s, double* p50_us, double* p99_us, double* matvecs_per_s);
 /* Serves every queued request, then stops the threads and frees the
  * server's pinned memory (the arena and streams stay the caller's). */

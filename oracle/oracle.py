@@ -31,6 +31,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
+# all-cores timing variant (bitwise equal to the plain loop; see hm_oracle_omp.c)
+_SRC_OMP = os.path.join(_HERE, "hm_oracle_omp.c")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_lib_omp = None
 
 F64, F32, F16, BF16 = 0, 1, 2, 3
 DFL32, DFL40, DFL48, DFL16, DFL24 = 4, 5, 6, 7, 8
@@ -226,10 +230,13 @@ def round_to(x, dt: int) -> np.ndarray:
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
+    cmd_omp = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-fopenmp", "-o", _LIB_OMP + ".tmp",
+               _SRC_OMP]
+    for c, out in ((cmd, _LIB), (cmd_omp, _LIB_OMP)):
+        if verbose:
+            print(" ".join(c), flush=True)
+        subprocess.run(c, check=True)
+        os.replace(out + ".tmp", out)
     return _LIB
 
 
@@ -310,6 +317,41 @@ def hmvm(H, x, y=None, alpha: float = 1.0, factors=None, n_rows=None, n_cols=Non
         raise RuntimeError(f"oracle_hmvm failed ({rc})")
     del keep
     return out
+
+
+def _load_omp():
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP):
+            build()
+        L = C.CDLL(_LIB_OMP)
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        L.oracle_hmvm_omp.argtypes = [C.c_int64, C.c_int64, C.c_int64, i64p, i64p, i64p, i64p,
+                                      i32p, i32p, u64p, u64p, u64p, C.c_double, f64p, f64p,
+                                      C.c_int32, C.c_int64]
+        L.oracle_hmvm_omp.restype = C.c_int
+        _lib_omp = L
+    return _lib_omp
+
+
+def hmvm_omp(H, x, y=None, alpha: float = 1.0, factors=None, nthreads: int = 0,
+             rows_per_task: int = 64):
+    """hmvm on all cores (OpenMP over ranges of rows, t_b per block first):
+    bitwise the result of hmvm for any thread count.  A timing variant, not
+    a second oracle.  Returns (y, threads used)."""
+    L = _load_omp()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(H.n) if y is None else np.array(y, dtype=np.float64, copy=True)
+    rb, re, cb, ce, kind, rank, ap, bp, sp, keep = _table(H, factors)
+    used = L.oracle_hmvm_omp(H.n, H.n, rb.shape[0], rb, re, cb, ce, kind, rank, ap, bp, sp,
+                             float(alpha), x, out, int(nthreads), int(rows_per_task))
+    if used < 1:
+        raise RuntimeError(f"oracle_hmvm_omp failed ({used})")
+    del keep
+    return out, int(used)
 
 
 def hmvm_multi(H, X, Y=None, alpha: float = 1.0, factors=None, blocks=None) -> np.ndarray:

@@ -128,8 +128,10 @@ struct hm_server {
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread thread;
-  // stats
+  // stats: latencies of the most recent kLatWindow completed requests (a ring)
+  static constexpr size_t kLatWindow = size_t(1) << 20;
   std::vector<double> lat_us;
+  size_t lat_next = 0;
   int64_t rhs_done = 0;
   Clock::time_point t_first{}, t_last{};
   bool have_first = false;
@@ -151,7 +153,10 @@ size_t footprint(const hm_matrix* A, int32_t r) {
 void finish(hm_server* S, const std::shared_ptr<Request>& q, hm_status st, Clock::time_point now) {
   q->result = st;
   q->done = true;
-  S->lat_us.push_back(std::chrono::duration<double, std::micro>(now - q->t_submit).count());
+  const double us = std::chrono::duration<double, std::micro>(now - q->t_submit).count();
+  if (S->lat_us.size() < hm_server::kLatWindow) S->lat_us.push_back(us);
+  else S->lat_us[S->lat_next] = us;
+  S->lat_next = (S->lat_next + 1) % hm_server::kLatWindow;
   if (st == HM_OK) S->rhs_done += q->nrhs;
   if (!S->have_first || q->t_submit < S->t_first) S->t_first = q->t_submit;
   S->have_first = true;
@@ -346,6 +351,7 @@ hm_status hm_poll(hm_server* s, uint64_t ticket, int32_t* done, hm_status* resul
   if (it == s->tickets.end()) return hm::fail(HM_ESTATE, "unknown ticket %llu", (unsigned long long)ticket);
   *done = it->second->done ? 1 : 0;
   if (result) *result = it->second->done ? it->second->result : HM_OK;
+  if (it->second->done) s->tickets.erase(it);       // reported: the ticket is released
   return hm::ok();
 }
 
@@ -361,13 +367,21 @@ hm_status hm_wait(hm_server* s, uint64_t ticket, int64_t timeout_us, hm_status* 
     return hm::fail(HM_ETIMEOUT, "ticket %llu not done after %lld us", (unsigned long long)ticket,
                     (long long)timeout_us);
   if (result) *result = q->result;
+  s->tickets.erase(ticket);                         // reported: the ticket is released
   return hm::ok();
 }
 
 hm_status hm_server_stats(hm_server* s, double* p50_us, double* p99_us, double* matvecs_per_s) {
   if (!s) return hm::fail(HM_EINVAL, "NULL argument");
-  std::lock_guard<std::mutex> g(s->mu);
-  std::vector<double> v = s->lat_us;
+  std::vector<double> v;
+  int64_t rhs_done = 0;
+  double secs = 0;
+  {
+    std::lock_guard<std::mutex> g(s->mu);     // copy under the lock, sort outside it
+    v = s->lat_us;
+    rhs_done = s->rhs_done;
+    secs = s->have_first ? std::chrono::duration<double>(s->t_last - s->t_first).count() : 0;
+  }
   auto pct = [&](double p) {
     if (v.empty()) return 0.0;
     size_t k = (size_t)std::min<double>((double)v.size() - 1, std::ceil(p * v.size()) - 1);
@@ -376,10 +390,7 @@ hm_status hm_server_stats(hm_server* s, double* p50_us, double* p99_us, double* 
   };
   if (p50_us) *p50_us = pct(0.50);
   if (p99_us) *p99_us = pct(0.99);
-  if (matvecs_per_s) {
-    double secs = s->have_first ? std::chrono::duration<double>(s->t_last - s->t_first).count() : 0;
-    *matvecs_per_s = secs > 0 ? s->rhs_done / secs : 0.0;
-  }
+  if (matvecs_per_s) *matvecs_per_s = secs > 0 ? rhs_done / secs : 0.0;
   return hm::ok();
 }
 

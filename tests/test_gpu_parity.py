@@ -238,13 +238,65 @@ def _mixed(H, name):
     D.close()
 
 
+def block_norms(H):
+    """Frobenius norm of every stored block (|s| for low-rank blocks kept as
+    W diag(s) X^T with orthonormal W, X)."""
+    out = np.zeros(H.nblocks)
+    for i in range(H.nblocks):
+        a, _, s = H.factors(i)
+        out[i] = np.linalg.norm(s) if H.adm[i] else np.linalg.norm(a)
+    return out
+
+
+def check_store_budget(H, tol):
+    """Every block's storage error bound within tol of its own norm."""
+    nrm = block_norms(H)
+    ratio = np.where(nrm > 0, H.store_err_bound / np.maximum(nrm, 1e-300), 0.0)
+    say(f"max storage error / block norm {ratio.max():.3e} (budget {tol:.1e})")
+    assert ratio.max() <= tol
+
+
 def test_mixed_sphere4k():
     _mixed(hmgen.build_preset("sphere4k_mixed"), "sphere4k_mixed")
 
 
 def test_mixed_full_size():
     say("building sphere256k_mixed")
-    _mixed(hmgen.build_preset("sphere256k_mixed"), "sphere256k_mixed")
+    H = hmgen.build_preset("sphere256k_mixed")
+    check_store_budget(H, hmgen.presets.MIXED_TOL / 2)
+    _mixed(H, "sphere256k_mixed")
+
+
+@pytest.mark.parametrize("name", ["sphere4k_e8_mixed", "sphere256k_e8_mixed"])
+def test_mixed_fp64_accumulation(name):
+    """The eps = 1e-8 matrix with FP64 kept only for the dense (near-field)
+    blocks, s and the accumulation of y, and the low-rank column groups in
+    FP32 / FP16 / BF16: the FP64 bar against the oracle on the decoded
+    factors, and the stated 1e-6 against the unrounded FP64 matrix."""
+    say("building", name)
+    H = hmgen.build_preset(name)
+    dense = H.adm == 0
+    assert np.all(H.group_dtype[dense, 0] == hm.HM_F64)
+    lr = np.flatnonzero(~dense)
+    used = np.concatenate([H.group_dtype[i, :H.ngroups[i]] for i in lr])
+    assert set(np.unique(used).tolist()) <= {hm.HM_F32, hm.HM_F16, hm.HM_BF16}
+    check_store_budget(H, hmgen.presets.MIXED_TOL / 2)
+    D = DeviceHMatrix(H, hm.HM_F64)
+    say("uploaded", D.info["store_bytes"], D.info["bytes_by_dtype"][:4])
+    x = hmgen.uniform_vector(H.n)
+    y = run(D, x)
+    dec = oracle.decoded_factors(H, sigma_dtype=oracle.F64)
+    ref = oracle.hmvm(H, x, factors=dec)
+    truth = oracle.hmvm(H, x)
+    rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    rel_truth = np.linalg.norm(y - truth) / np.linalg.norm(truth)
+    say(f"{name}: relative error vs decoded oracle {rel:.3e}, vs unrounded FP64 {rel_truth:.3e}")
+    assert rel <= F64_TOL
+    idx = np.random.default_rng(0).choice(H.n, min(H.n, 2000), replace=False)
+    scale = abs_bound(H, x, dec)
+    assert np.all(np.abs(y[idx] - ref[idx]) <= 1e-13 * scale[idx])
+    assert rel_truth <= 1e-6
+    D.close()
 
 
 def _batch(D, X, alpha=1.0, Y0=None):
