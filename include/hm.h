@@ -203,6 +203,24 @@ hm_status hm_pack_host(const hm_plan* p, const double* const* a, const double* c
 hm_status hm_mvm(const hm_matrix* A, double alpha, const void* d_x, void* d_y, void* d_work,
                  size_t work_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): hm_mvm
+ * with the workspace taken from a fixed array of HM_NOALLOC_SCRATCH_BYTES in
+ * device memory that the library holds, one copy per GPU, until the process
+ * ends.  Same arguments, kernels and result (bit for bit) as hm_mvm.  The
+ * call allocates nothing: no hipMalloc, hipFree or allocating library call;
+ * on the first call on a device it looks up that device's copy of the array.
+ * The current device must be the matrix's (else HM_EINVAL).  A matrix whose
+ * work_bytes_per_rhs exceeds HM_NOALLOC_SCRATCH_BYTES is rejected with
+ * HM_ENOMEM before anything is launched.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (two streams, or two host
+ * threads without stream ordering between them) race and give undefined
+ * results; calls ordered on one stream are safe.  The array keeps the last
+ * call's contents; the product writes every workspace entry it reads within
+ * the call, so nothing needs clearing. */
+#define HM_NOALLOC_SCRATCH_BYTES (64u << 20)
+hm_status hm_mvm_noalloc(const hm_matrix* A, double alpha, const void* d_x, void* d_y, void* stream);
+
 /* Y := Y + alpha A X for nrhs right-hand sides (1 <= nrhs <= max_nrhs).
  * X is n_cols x nrhs, Y is n_rows x nrhs, column-major with leading
  * dimensions ldx >= n_cols, ldy >= n_rows; X must not overlap Y.

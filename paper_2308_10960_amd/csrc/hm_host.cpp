@@ -1603,6 +1603,23 @@ hm_status hm_mvm(const hm_matrix* A, double alpha, const void* d_x, void* d_y, v
   return ok();
 }
 
+hm_status hm_mvm_noalloc(const hm_matrix* A, double alpha, const void* d_x, void* d_y, void* stream) {
+  if (!A || !d_x || !d_y) return fail(HM_EINVAL, "NULL argument");
+  if (A->work_bytes_per_rhs > (size_t)HM_NOALLOC_SCRATCH_BYTES)
+    return fail(HM_ENOMEM, "the product needs %zu bytes of workspace, above the fixed %zu of hm_mvm_noalloc",
+                A->work_bytes_per_rhs, (size_t)HM_NOALLOC_SCRATCH_BYTES);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != A->device)
+    return fail(HM_EINVAL, "the current device is not the matrix's device");
+  void* work = nullptr;
+  hipError_t e = scratch_address(dev, &work);
+  if (e != hipSuccess) return fail(HM_EDEVICE, "fixed workspace lookup failed: %s", hipGetErrorString(e));
+  if (hm_status st = check_mvm(A, d_x, d_y, work, HM_NOALLOC_SCRATCH_BYTES)) return st;
+  e = launch_mvm(*A, alpha, d_x, d_y, work, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(HM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
 hm_status hm_mvm_batch(const hm_matrix* A, int32_t nrhs, double alpha, const void* d_X,
                        int64_t ldx, void* d_Y, int64_t ldy, void* d_work, size_t work_bytes,
                        void* stream) {

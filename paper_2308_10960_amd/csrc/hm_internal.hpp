@@ -168,6 +168,9 @@ hipError_t launch_mvm(const hm_matrix& A, double alpha, const void* x, void* y, 
 hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const void* X, int64_t ldx,
                             void* Y, int64_t ldy, void* work, hipStream_t s, bool profile = true);
 hipError_t launch_stream_read(const void* buf, size_t bytes, void* out, hipStream_t s);
+// Device address of the fixed workspace of hm_mvm_noalloc on `device`, which
+// must be the current device (looked up on the first call per device).
+hipError_t scratch_address(int device, void** out);
 hipError_t launch_permute(const int64_t* perm, int64_t n, int elem_bytes, int direction, int nvec, const void* in,
                           int64_t ld_in, void* out, int64_t ld_out, hipStream_t s);
 }  // namespace hm

@@ -27,6 +27,7 @@
 // accumulation type in registers.
 
 #include <algorithm>
+#include <mutex>
 
 #include <hip/hip_runtime.h>
 
@@ -817,6 +818,34 @@ hipError_t launch_mvm(const hm_matrix& A, double alpha, const void* x, void* y, 
     ev = &A.prof.ev[4 * (size_t)A.prof.calls++];
   return A.acc_dtype == HM_F64 ? launch_typed<double>(A, alpha, x, y, work, s, ev)
                                : launch_typed<float>(A, alpha, x, y, work, s, ev);
+}
+
+// Fixed workspace of hm_mvm_noalloc, for callers that cannot allocate device
+// memory: one copy of this array on every GPU the library runs on, held
+// until the process ends.  In host code the name `scratch` denotes a
+// host-side stand-in, not device memory, so it is never passed to a kernel
+// or a copy: host code uses the device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current and kept
+// here.  The product writes every partial sum and t entry it reads within
+// the same call, so the array needs no clearing between calls.
+static __device__ __align__(256) uint8_t scratch[HM_NOALLOC_SCRATCH_BYTES];
+
+hipError_t scratch_address(int device, void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_stream_read(const void* buf, size_t bytes, void* out, hipStream_t s) {

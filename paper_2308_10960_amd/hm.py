@@ -23,6 +23,7 @@ HM_DFL32, HM_DFL40, HM_DFL48, HM_DFL16, HM_DFL24 = 4, 5, 6, 7, 8
 HM_AFLP16, HM_AFLP24, HM_AFLP32, HM_AFLP40, HM_AFLP48 = 9, 10, 11, 12, 13
 HM_BFL24, HM_BFL40, HM_BFL48 = 14, 15, 16
 HM_NUM_DTYPES = 17
+HM_NOALLOC_SCRATCH_BYTES = 64 << 20      # fixed workspace of hm_mvm_noalloc (include/hm.h)
 HM_DENSE, HM_LOWRANK = 0, 1
 
 STATUS_NAMES = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_EPARTITION", -3: "HM_ESHAPE",
@@ -74,6 +75,7 @@ PROTOTYPES = {
     "hm_matrix_destroy": (None, [_vp]),
     "hm_pack_host": (_i32, [_vp, _vp, _vp, _vp, _vp, _sz]),
     "hm_mvm": (_i32, [_vp, _dbl, _vp, _vp, _vp, _sz, _vp]),
+    "hm_mvm_noalloc": (_i32, [_vp, _dbl, _vp, _vp, _vp]),
     "hm_mvm_batch": (_i32, [_vp, _i32, _dbl, _vp, _i64, _vp, _i64, _vp, _sz, _vp]),
     "hm_graph_create": (_i32, [_vp, _i32, _dbl, _vp, _i64, _vp, _i64, _vp, _sz, _P(_vp)]),
     "hm_graph_launch": (_i32, [_vp, _vp]),
@@ -211,6 +213,11 @@ def hm_matrix_destroy(mat: int) -> None:
 def hm_mvm(mat: int, alpha: float, d_x, d_y, d_work, work_bytes: int, stream=None) -> None:
     _check(lib().hm_mvm(mat, alpha, _ptr(d_x), _ptr(d_y), _ptr(d_work), work_bytes,
                         _stream(stream)), "hm_mvm")
+
+
+def hm_mvm_noalloc(mat: int, alpha: float, d_x, d_y, stream=None) -> None:
+    """hm_mvm with the library's fixed device workspace (no allocation)."""
+    _check(lib().hm_mvm_noalloc(mat, alpha, _ptr(d_x), _ptr(d_y), _stream(stream)), "hm_mvm_noalloc")
 
 
 def hm_mvm_batch(mat: int, nrhs: int, alpha: float, d_X, ldx: int, d_Y, ldy: int, d_work,
