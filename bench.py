@@ -136,13 +136,22 @@ def serve_bench(args, torch, hmgen, hm, DeviceHMatrix):
     streams = [torch.cuda.Stream() for _ in range(args.serve_streams)]
     rng = np.random.default_rng(hmgen.presets.SEED_REQUESTS)
     # right-hand sides: one N(0,1) pool of 64 columns per matrix; a request of
-    # r columns reads the first r (a contiguous column-major slice)
-    pool = [np.asfortranarray(rng.standard_normal((n, 64)).astype(np.float32)) for n in sizes]
+    # r columns reads the first r (a contiguous column-major slice).  Client
+    # buffers are page-locked (allocated pinned), so the request loop copies
+    # them to and from the device without staging.
+    def pinned(n):
+        return torch.empty((64, n), dtype=torch.float32, pin_memory=True).numpy().T   # (n, 64), column-major
+
+    pool = []
+    for n in sizes:
+        buf = pinned(n)
+        buf[:] = rng.standard_normal((n, 64)).astype(np.float32)
+        pool.append(buf)
 
     # results: a ring of OUT_RING output buffers per matrix; a request reuses
     # the buffer of the request OUT_RING places before it on the same
     # matrix, after waiting for that one (host memory stays bounded)
-    OUT_RING = 24
+    OUT_RING = 16
     outbuf = [[None] * OUT_RING for _ in sizes]
 
     def make(count):
@@ -167,7 +176,7 @@ def serve_bench(args, torch, hmgen, hm, DeviceHMatrix):
             if last[m][j] is not None:
                 res.append(hm.hm_wait(s, last[m][j], 600_000_000))
             if outbuf[m][j] is None:
-                outbuf[m][j] = np.zeros((sizes[m], 64), np.float32, order="F")
+                outbuf[m][j] = pinned(sizes[m])
             Y = outbuf[m][j]
             t_next += g
             while time.perf_counter() < t_next:
@@ -261,6 +270,13 @@ def main():
                     help="tune cache to read (and, with --tune, to update)")
     ap.add_argument("--no-tune-cache", action="store_true",
                     help="ignore the tune cache: built-in launch parameters")
+    ap.add_argument("--launch", default="",
+                    help="launch parameters applied after the tune cache (e.g. 'colb=1'); not the default line")
+    ap.add_argument("--build", choices=("host", "gpu"), default="host",
+                    help="construct the matrix's leaves on the host (default) or on the GPU (ACA and the "
+                         "truncation of Algorithm 1 in HIP kernels); --build-compare also times the other")
+    ap.add_argument("--build-compare", action="store_true",
+                    help="also construct the matrix the other way and report both times")
     ap.add_argument("--no-stream-probe", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load point")
@@ -296,10 +312,29 @@ def main():
     p = hmgen.preset(args.workload)
     if args.dtype:
         p["dtype"] = args.dtype
-    log("building", args.workload, p)
-    H = hmgen.build_preset(args.workload, n=args.n or None, dtype=p["dtype"])
+    log("building", args.workload, p, "leaves on the", args.build)
+    from paper_2308_10960_amd import construct
+
+    def make_matrix(where):
+        filler = (lambda T: construct.fill_gpu(T)) if where == "gpu" else None
+        return hmgen.build_preset(args.workload, n=args.n or None, dtype=p["dtype"], filler=filler)
+
+    H = make_matrix(args.build)
     st = H.stats()
     log("built in %.1fs: %s" % (H.build_seconds, st))
+    build_info = {"leaves_on": args.build, "seconds": round(H.build_seconds, 3),
+                  "host_threads": hmgen.hmatrix.default_threads()}
+    if args.build == "gpu":
+        build_info["gpu"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in H.fill_stats.items()}
+    if args.build_compare:
+        other = "host" if args.build == "gpu" else "gpu"
+        H2 = make_matrix(other)
+        build_info[f"{other}_seconds"] = round(H2.build_seconds, 3)
+        d = np.abs(H.rank.astype(np.int64) - H2.rank.astype(np.int64))
+        build_info["rank_diff_max"] = int(d.max())
+        build_info["rank_diff_leaves"] = int((d > 0).sum())
+        del H2
+    log("construction", build_info)
     # the byte-aligned formats and the eps = 1e-8 mixed storage accumulate in FP64
     mixed = p["dtype"] not in ("f64", "dfl", "aplr", "aflp", "bfl", "mixed64")
     acc = hm.HM_F32 if mixed else hm.HM_F64
@@ -344,6 +379,8 @@ def main():
     torch.cuda.synchronize()
 
     key = hm.hm_matrix_tune_key(D.handle)
+    if args.launch:
+        hm.hm_matrix_set_launch(D.handle, args.launch)
     if args.tune:
         from paper_2308_10960_amd import tune
         best, times = tune.tune(D, step, tune.CANDIDATES if R == 1 else tune.BATCH_CANDIDATES)
@@ -482,6 +519,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "serving": serving,
+        "construction": build_info,
     }
     print(json.dumps(out), flush=True)
     D.close()

@@ -603,6 +603,87 @@ int hmg_fill(hmg_tree* t, int32_t kernel, const double* params, double eps_aca, 
   return hmg_fill_part(t, kernel, params, eps_aca, eps, keep_sigma, nthreads, 0, 1);
 }
 
+// Kernel function and form of the leaves, for trees whose leaves are filled
+// elsewhere (hmg_set_factors) or one by one (hmg_fill_blocks).
+int hmg_set_kernel(hmg_tree* t, int32_t kernel, const double* params, int32_t keep_sigma) {
+  if (!t || kernel < 0 || kernel > 2) return -1;
+  t->kernel = kernel;
+  for (int i = 0; i < 4; ++i) t->kp[i] = params ? params[i] : 0.0;
+  t->keep_sigma = keep_sigma;
+  return 0;
+}
+
+// Copies computed factors into `count` leaves idx[q] (data movement only).
+// Leaf q's data start at buf + off[q]: a dense leaf's D (m x n); an
+// admissible leaf's U / W (m x rank[q]) at column stride m, V / X (n x
+// rank[q]) from off[q] + m cap[q], and with keep_sigma its s from
+// off[q] + (m + n) cap[q].
+int hmg_set_factors(hmg_tree* t, int64_t count, const int64_t* idx, const int32_t* rank, const double* buf,
+                    const int64_t* off, const int32_t* cap) {
+  if (!t) return -1;
+  const int64_t nb = (int64_t)t->blocks.size();
+  for (int64_t q = 0; q < count; ++q)
+    if (idx[q] < 0 || idx[q] >= nb || rank[q] < 0) return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t q = 0; q < count; ++q) {
+    Block& b = t->blocks[idx[q]];
+    const int64_t m = b.re - b.rb, n = b.ce - b.cb;
+    const double* p = buf + off[q];
+    b.b.clear();
+    b.s.clear();
+    if (!b.adm) {
+      b.a.assign(p, p + m * n);
+      b.rank = 0;
+      continue;
+    }
+    const int64_t k = rank[q], c = cap[q];
+    b.a.assign(p, p + m * k);
+    b.b.assign(p + m * c, p + m * c + n * k);
+    if (t->keep_sigma) b.s.assign(p + (m + n) * c, p + (m + n) * c + k);
+    b.rank = (int32_t)k;
+  }
+  return 0;
+}
+
+// Fills the leaves idx[0 .. count-1] on the host, as hmg_fill does, with the
+// kernel set by hmg_set_kernel.
+int hmg_fill_blocks(hmg_tree* t, int64_t count, const int64_t* idx, double eps_aca, double eps,
+                    int32_t nthreads) {
+  if (!t) return -1;
+  const int64_t nb = (int64_t)t->blocks.size();
+  for (int64_t q = 0; q < count; ++q)
+    if (idx[q] < 0 || idx[q] >= nb) return -1;
+  Eval ev{*t};
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+  {
+    std::vector<double> U, V, W, X, S;
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t q = 0; q < count; ++q) {
+      Block& b = t->blocks[idx[q]];
+      const int64_t m = b.re - b.rb, n = b.ce - b.cb;
+      b.a.clear(); b.b.clear(); b.s.clear();
+      if (!b.adm) {
+        b.a.resize((size_t)m * n);
+        for (int64_t j = 0; j < n; ++j)
+          for (int64_t i = 0; i < m; ++i) b.a[(size_t)j * m + i] = ev(b.rb + i, b.cb + j);
+        b.rank = 0;
+        continue;
+      }
+      int r = aca(ev, b.rb, m, b.cb, n, eps_aca, U, V);
+      int k = truncate(U, V, m, n, r, eps, W, X, S);
+      b.rank = k;
+      if (!t->keep_sigma)
+        for (int c = 0; c < k; ++c)
+          for (int64_t i = 0; i < m; ++i) W[(size_t)c * m + i] *= S[c];
+      b.a = W;
+      b.b = X;
+      if (t->keep_sigma) b.s = S;
+    }
+  }
+  return 0;
+}
+
 // Per-block factor pointers (0 where absent) as integers, for marshalling.
 void hmg_get_factor_ptrs(const hmg_tree* t, uint64_t* a, uint64_t* b, uint64_t* s) {
   for (size_t i = 0; i < t->blocks.size(); ++i) {

@@ -90,6 +90,12 @@ def lib():
     L.hmg_fill_part.argtypes = [vp, C.c_int32, _f64p, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                 C.c_int32, C.c_int32]
     L.hmg_fill_part.restype = C.c_int
+    L.hmg_set_kernel.argtypes = [vp, C.c_int32, _f64p, C.c_int32]
+    L.hmg_set_kernel.restype = C.c_int
+    L.hmg_set_factors.argtypes = [vp, C.c_int64, _i64p, _i32p, C.c_void_p, _i64p, _i32p]
+    L.hmg_set_factors.restype = C.c_int
+    L.hmg_fill_blocks.argtypes = [vp, C.c_int64, _i64p, C.c_double, C.c_double, C.c_int32]
+    L.hmg_fill_blocks.restype = C.c_int
     L.hmg_get_factor_ptrs.argtypes = [vp, _u64p, _u64p, _u64p]
     L.hmg_get_ranks.argtypes = [vp, _i32p]
     L.hmg_eval.argtypes = [vp, _i64p, _i64p, C.c_int64, _f64p]
@@ -183,6 +189,37 @@ class HMatrix:
     def points_cluster_order(self) -> np.ndarray:
         return self.points[self.perm]
 
+    # ------------------------------------------------------------ filling
+    def set_factors(self, idx, rank, buf: np.ndarray, off, cap) -> None:
+        """Copy factors computed elsewhere into the leaves idx (layout of
+        hmg_set_factors: per leaf, D or U at buf[off], V at off + m cap, s at
+        off + (m + n) cap), then refresh the ranks and factor pointers."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        rc = lib().hmg_set_factors(C.c_void_p(self.handle), idx.shape[0], idx,
+                                   np.ascontiguousarray(rank, dtype=np.int32), buf.ctypes.data,
+                                   np.ascontiguousarray(off, dtype=np.int64),
+                                   np.ascontiguousarray(cap, dtype=np.int32))
+        if rc != 0:
+            raise RuntimeError("hmg_set_factors failed")
+        self.refresh()
+
+    def fill_blocks(self, idx, eps_aca: float | None = None, nthreads: int | None = None) -> None:
+        """Fill the leaves idx on the host (ACA at eps_aca, default eps / 10,
+        then Algorithm 1 at eps)."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        rc = lib().hmg_fill_blocks(C.c_void_p(self.handle), idx.shape[0], idx,
+                                   self.eps / 10 if eps_aca is None else eps_aca, self.eps,
+                                   nthreads or default_threads())
+        if rc != 0:
+            raise RuntimeError("hmg_fill_blocks failed")
+        self.refresh()
+
+    def refresh(self) -> None:
+        """Re-read the ranks and factor pointers after the leaves changed."""
+        L = lib()
+        L.hmg_get_ranks(C.c_void_p(self.handle), self.rank)
+        L.hmg_get_factor_ptrs(C.c_void_p(self.handle), self.a_ptr, self.b_ptr, self.s_ptr)
+
     # ------------------------------------------------------------ precision
     def select_precision(self, tol: float, allow_f64: bool = False, dense_f64: bool = False,
                          sigma_f64: bool = False) -> int:
@@ -274,7 +311,7 @@ def default_threads() -> int:
 def build_hmatrix(points: np.ndarray, kernel: int, *, leaf: int = 64, eta: float = 2.0,
                   eps: float = 1e-6, eps_aca: float | None = None, keep_sigma: bool = False,
                   diag: float | None = None, length: float = 0.1, nthreads: int | None = None,
-                  kparams=None, progress: bool | None = None) -> HMatrix:
+                  kparams=None, progress: bool | None = None, fill: bool = True) -> HMatrix:
     """Construct the H-matrix of ``kernel`` over ``points`` (n x 3, FP64).
 
     kernel: KERNEL_LAPLACE (1/(4 pi r), diagonal 1/(4 pi h) with h the mean
@@ -282,7 +319,9 @@ def build_hmatrix(points: np.ndarray, kernel: int, *, leaf: int = 64, eta: float
     (exp(-r/length), diagonal + ``diag`` (default 1e-3)), KERNEL_SEPARABLE.
     ACA runs at ``eps_aca`` (default eps/10), then Algorithm 1 at ``eps``.
     With ``progress`` (default: n >= 2^19) the leaves are filled in 16 shares
-    and a line is printed after each.
+    and a line is printed after each.  With ``fill=False`` only the trees are
+    built and the kernel recorded: the leaves stay empty (rank 0) until
+    set_factors / fill_blocks fill them.
     """
     L = lib()
     pts = np.ascontiguousarray(points, dtype=np.float64)
@@ -305,6 +344,9 @@ def build_hmatrix(points: np.ndarray, kernel: int, *, leaf: int = 64, eta: float
     if progress is None:
         progress = n >= 2 ** 19
     nparts = 16 if progress else 1
+    if not fill:
+        nparts = 0
+        rc = L.hmg_set_kernel(handle, kernel, kparams, int(keep_sigma))
     for part in range(nparts):
         rc = L.hmg_fill_part(handle, kernel, kparams, eps / 10 if eps_aca is None else eps_aca, eps,
                              int(keep_sigma), nthr, part, nparts)

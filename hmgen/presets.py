@@ -13,6 +13,8 @@ standard admissibility with eta = 2.
 
 from __future__ import annotations
 
+import time
+
 from .geometry import fibonacci_sphere, cube_points
 from .hmatrix import build_hmatrix, dfl_format, bfl_format, KERNEL_LAPLACE, KERNEL_EXP, DT_F64, DT_F32
 
@@ -74,8 +76,10 @@ def make_points(geometry: str, n: int):
 
 def build_preset(name: str, *, n: int | None = None, eps: float | None = None,
                  dtype: str | None = None, nthreads: int | None = None, leaf: int = 64,
-                 eta: float = 2.0):
-    """Build a preset's H-matrix; n / eps / dtype override the preset."""
+                 eta: float = 2.0, filler=None):
+    """Build a preset's H-matrix; n / eps / dtype override the preset.
+    ``filler``: a callable that fills the leaves of the tree-only H-matrix
+    (e.g. on the GPU) instead of the host construction."""
     p = preset(name)
     n = p["n"] if n is None else n
     eps = p["eps"] if eps is None else eps
@@ -83,8 +87,12 @@ def build_preset(name: str, *, n: int | None = None, eps: float | None = None,
     pts = make_points(p["geometry"], n)
     kern = KERNEL_LAPLACE if p["kernel"] == "laplace" else KERNEL_EXP
     mixed = dtype in ("mixed", "mixed64")
+    t0 = time.perf_counter()
     H = build_hmatrix(pts, kern, leaf=leaf, eta=eta, eps=eps, keep_sigma=mixed or dtype == "aplr",
-                      nthreads=nthreads)
+                      nthreads=nthreads, fill=filler is None)
+    if filler is not None:
+        H.fill_stats = filler(H)
+        H.build_seconds = time.perf_counter() - t0
     bad = 0
     if dtype == "mixed":
         bad = H.select_precision(MIXED_TOL / 2)

@@ -664,6 +664,7 @@ static bool parse_launch(const char* text, LaunchParams& lp) {
     else if (k == "persist" && (v == 0 || v == 1 || v == 2 || v == 4 || v == 8)) r.persist = (int)v;
     else if (k == "chunk" && v >= kMaxTileRows && v <= kSegRows) r.chunk = (int)v;
     else if (k == "tile" && v >= 8 && v <= kTileGroups) r.tile = (int)v;
+    else if (k == "colb" && v >= 0 && v <= 3) r.colb = (int)v;
     else return false;
     i = j;
   }
@@ -1699,8 +1700,9 @@ hm_status hm_matrix_set_launch(hm_matrix* A, const char* params) {
 
 hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len) {
   if (!A || !buf || len == 0) return fail(HM_EINVAL, "NULL argument");
-  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d persist=%d chunk=%d tile=%d", A->launch.schedule,
-                A->launch.row_unroll, A->launch.order, A->launch.persist, A->launch.chunk, A->launch.tile);
+  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d persist=%d chunk=%d tile=%d colb=%d", A->launch.schedule,
+                A->launch.row_unroll, A->launch.order, A->launch.persist, A->launch.chunk, A->launch.tile,
+                A->launch.colb);
   return ok();
 }
 

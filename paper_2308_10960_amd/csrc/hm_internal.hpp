@@ -23,6 +23,9 @@ namespace hm {
 //           most P workgroups per CU looping over the items (single RHS).
 //  chunk, tile: the plan's column-tile shape (rows per column chunk, groups
 //           per tile); 0 = not given.
+//  colb: batched FP32 column tiles as 8-byte slots, 32 per wave (0: 4 row
+//           steps in flight, 2: 8), or as 16-byte groups, 32 per wave (1: 4
+//           steps, 3: 8).
 struct LaunchParams {
   int schedule = 0;
   int row_unroll = 8;
@@ -30,6 +33,7 @@ struct LaunchParams {
   int persist = 0;
   int chunk = 0;
   int tile = 0;
+  int colb = 0;
 };
 
 struct BlockInfo {

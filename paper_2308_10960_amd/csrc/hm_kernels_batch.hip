@@ -113,11 +113,11 @@ __device__ __forceinline__ void load_slot(const uint8_t* p, int dt, float (&v)[4
 // the 32 right-hand sides, one load for both).  DT >= 0: every slot has
 // format DT (CPL = its columns per slot); DT < 0: the tile holds runs of
 // several formats, CPL = 4 and an FP32 slot leaves columns 2 and 3 empty.
-// Rows go in batches of S steps (2S rows); with DB the next batch's loads
-// are in flight while this batch's MFMAs run.  wd, ws: the wave's LDS
-// tables of destination rows (in part, whose rows from t_row0 on are t) and
-// factors (s_b[l] for a column that writes t directly, else 1).
-template <int DT, int S, bool DB>
+// Rows go in batches of S steps (2S rows); the next batch's loads are in
+// flight while this batch's MFMAs run.  wd, ws: the wave's LDS tables of
+// destination rows (in part, whose rows from t_row0 on are t) and factors
+// (s_b[l] for a column that writes t directly, else 1).
+template <int DT, int S>
 __device__ __forceinline__ void colb32_part(const ColBArgs& a, const ColTile& T, int quarter, int rh,
                                           int lane, int32_t* wd, float* ws) {
   constexpr int CPL = DT == HM_F32 ? 2 : 4;
@@ -139,54 +139,50 @@ __device__ __forceinline__ void colb32_part(const ColBArgs& a, const ColTile& T,
 #pragma unroll
   for (int q = 0; q < CPL; ++q) acc[q] = (f32x16)(0.f);
   const size_t rstride = (size_t)T.ngroups * 16;
-  const uint8_t* base = a.store + T.data_off + (size_t)hi * rstride + (size_t)(act ? sl : 0) * 8;
-  const float* xb = a.xr + ((size_t)T.x0 + hi) * a.RS + rh * 32 + l32;
+  // row 0 of the lane's slot (slot 0 for a lane past the tile's slots)
+  const uint8_t* base = a.store + T.data_off + (size_t)(act ? sl : 0) * 8;
+  const float* xb = a.xr + (size_t)T.x0 * a.RS + rh * 32 + l32;
   const int nr = T.nrows;
   // step k covers rows 2k, 2k + 1; lanes of a missing row give zeros
   const int nsteps = (nr + 1) / 2;
-  float an[S][4], bn[S];
-  auto issue = [&](int k0) {
+  // Loads without branches (for one-format tiles): a row past the tile
+  // reads its last row and a lane past its slots reads slot 0.  At use, the
+  // x value of a row past the tile is replaced by zero, so its products add
+  // nothing; a lane past the slots fills only result rows that are never
+  // written.  (Masking at use, not at load, keeps the loads in flight.)
+  // Two buffers of S steps take turns: while one batch's MFMAs run, the
+  // next batch's loads are in flight into the other; the loop body has no
+  // branch, so the accumulators stay in their registers.
+  float a0[S][4], b0[S], a1[S][4], b1[S];
+  auto issue = [&](int k0, float (&an)[S][4], float (&bn)[S]) {
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-      const int r = 2 * (k0 + u) + hi;
-      const bool ok = r < nr;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) an[u][q] = 0.f;
-      if (act && ok) load_slot(base + (size_t)(2 * (k0 + u)) * rstride, dt, an[u]);
-      bn[u] = ok ? xb[(size_t)(2 * (k0 + u)) * a.RS] : 0.f;
+      const int rc = min(2 * (k0 + u) + hi, nr - 1);
+      load_slot(base + (size_t)rc * rstride, dt, an[u]);
+      bn[u] = xb[(size_t)rc * a.RS];
     }
   };
-  auto compute = [&](int k, const float (&av)[S][4], const float (&bv)[S]) {
+  auto compute = [&](int k0, const float (&an)[S][4], const float (&bn)[S]) {
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-      if (k + u >= nsteps) break;                   // uniform across the wave
+      const float b = 2 * (k0 + u) + hi < nr ? bn[u] : 0.f;
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) acc[q] = mfma32x2(av[u][q], bv[u], acc[q]);
+      for (int q = 0; q < CPL; ++q) acc[q] = mfma32x2(an[u][q], b, acc[q]);
     }
   };
   // the first loads of the tile and the destinations of the lane's columns
   // go out together; the factors and the LDS tables follow the main loop
-  if constexpr (DB) issue(0);
+  issue(0, a0, b0);
   int32_t e[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) e[q] = (lane < 32 && act && q < cps) ? a.dst[T.dst_off + col + q] : kDstPad;
-  if constexpr (DB) {
-    for (int k = 0; k < nsteps; k += S) {
-      float ac[S][4], bc[S];
-#pragma unroll
-      for (int u = 0; u < S; ++u) {
-        bc[u] = bn[u];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ac[u][q] = an[u][q];
-      }
-      if (k + S < nsteps) issue(k + S);
-      compute(k, ac, bc);
-    }
-  } else {
-    for (int k = 0; k < nsteps; k += S) {
-      issue(k);
-      compute(k, an, bn);
-    }
+  for (int k = 0; k < nsteps; k += 2 * S) {
+    issue(k + S, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(k, a0, b0);
+    issue(k + 2 * S, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(k + S, a1, b1);
   }
   if (lane < 32) {
 #pragma unroll
@@ -210,6 +206,86 @@ __device__ __forceinline__ void colb32_part(const ColBArgs& a, const ColTile& T,
   }
 }
 
+// One wave (a workgroup of its own): groups [32 half, 32 half + 32) of an
+// FP32 column tile for 32 right-hand sides (group rh of RS).  Lane l owns
+// group 32 half + l % 32 of row 2k + l / 32 in step k: one 16-byte load
+// brings its 4 columns, and one v_mfma_f32_32x32x2_f32 per column q takes
+// two rows at a time (A: the lane's value of column q; B: the x rows 2k and
+// 2k + 1 of the 32 right-hand sides, one load for both); D_q row i is
+// column 4 i + q of the half.  Against colb32_part each load is twice as
+// wide, so a wave keeps twice the bytes in flight.  Rows go in batches of S
+// steps, the next batch's loads in flight while this batch's MFMAs run.  wd,
+// ws: the wave's LDS tables of destination rows and factors (128 columns).
+template <int S>
+__device__ __forceinline__ void colb32g_part(const ColBArgs& a, const ColTile& T, int half, int rh, int lane,
+                                            int32_t* wd, float* ws) {
+  const int l32 = lane & 31, hi = lane >> 5;
+  const int g = 32 * half + l32;
+  const bool act = g < T.ngroups;
+  f32x16 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = (f32x16)(0.f);
+  // row 0 of the lane's group (group 0 for a lane past the tile's groups)
+  const u32x4* base = reinterpret_cast<const u32x4*>(a.store + T.data_off) + (act ? g : 0);
+  const float* xb = a.xr + (size_t)T.x0 * a.RS + rh * 32 + l32;
+  const int nr = T.nrows;
+  const int nsteps = (nr + 1) / 2;
+  // loads without branches, masked at use, in two buffers that take turns,
+  // as in colb32_part
+  f32x4 a0[S], a1[S];
+  float b0[S], b1[S];
+  auto issue = [&](int k0, f32x4 (&an)[S], float (&bn)[S]) {
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      const int rc = min(2 * (k0 + u) + hi, nr - 1);
+      an[u] = __builtin_bit_cast(f32x4, ld16(base + (size_t)rc * T.ngroups));
+      bn[u] = xb[(size_t)rc * a.RS];
+    }
+  };
+  auto compute = [&](int k0, const f32x4 (&an)[S], const float (&bn)[S]) {
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      const float b = 2 * (k0 + u) + hi < nr ? bn[u] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = mfma32x2(an[u][q], b, acc[q]);
+    }
+  };
+  issue(0, a0, b0);
+  int32_t e[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) e[q] = (lane < 32 && act) ? a.dst[T.dst_off + 4 * g + q] : kDstPad;
+  for (int k = 0; k < nsteps; k += 2 * S) {
+    issue(k + S, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(k, a0, b0);
+    issue(k + 2 * S, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(k + S, a1, b1);
+  }
+  if (lane < 32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool direct = e[q] <= -2;
+      wd[4 * lane + q] = direct ? a.t_row0 + dst_t_index(e[q]) : e[q];
+      ws[4 * lane + q] = (direct && a.sigma) ? a.sigma[dst_t_index(e[q])] : 1.f;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int j = rh * 32 + l32;
+  // one column q at a time (the scheduler barrier keeps the LDS reads of
+  // the tables from being hoisted for all 64 results at once)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = mfma32x2_row(lane, v);           // the group (D row) of this result
+      const int32_t d = wd[4 * i + q];               // -1: padding or no column
+      if (d >= 0) a.part[(size_t)d * a.RS + j] = acc[q][v] * ws[4 * i + q];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // D (16 x 16) += A (16 x 4) B (4 x 16) on v_mfma_f32_16x16x4_f32: lane l
 // gives A[l % 16][l / 16] and B[l / 16][l % 16]; D[i][j] is in lane
 // j + 16 (i / 4), register i % 4.
@@ -226,12 +302,11 @@ __device__ __forceinline__ f32x4 mfma16x4(float a, float b, f32x4 c) {
 // column q; B: one value of the x rows 4k..4k+3 per lane, one load per
 // half).  DT >= 0: every slot has format DT (CPL = its columns per slot);
 // DT < 0: the tile holds runs of several formats, CPL = 4 and an FP32 slot
-// leaves columns 2 and 3 empty.  Rows go in batches of S steps; with DB the
-// next batch's loads are in flight while this batch's MFMAs run.  wd, ws:
-// the wave's LDS tables of destination rows (in part, whose rows from
-// t_row0 on are t) and factors (s_b[l] for a column that writes t directly,
-// else 1).
-template <int DT, int S, bool DB>
+// leaves columns 2 and 3 empty.  Rows go in batches of S steps; the next
+// batch's loads are in flight while this batch's MFMAs run.  wd, ws: the
+// wave's LDS tables of destination rows (in part, whose rows from t_row0 on
+// are t) and factors (s_b[l] for a column that writes t directly, else 1).
+template <int DT, int S>
 __device__ __forceinline__ void colb16_part(const ColBArgs& a, const ColTile& T, int s16, int rh,
                                           int lane, int32_t* wd, float* ws) {
   constexpr int CPL = DT == HM_F32 ? 2 : 4;
@@ -253,58 +328,47 @@ __device__ __forceinline__ void colb16_part(const ColBArgs& a, const ColTile& T,
 #pragma unroll
   for (int q = 0; q < CPL; ++q) acc[q][0] = acc[q][1] = (f32x4)(0.f);
   const size_t rstride = (size_t)T.ngroups * 16;
-  const uint8_t* base = a.store + T.data_off + (size_t)kq * rstride + (size_t)(act ? sl : 0) * 8;
-  const float* xb = a.xr + ((size_t)T.x0 + kq) * a.RS + rh * 32 + l16;
+  // row 0 of the lane's slot (slot 0 for a lane past the tile's slots)
+  const uint8_t* base = a.store + T.data_off + (size_t)(act ? sl : 0) * 8;
+  const float* xb = a.xr + (size_t)T.x0 * a.RS + rh * 32 + l16;
   const int nr = T.nrows;
   // step k covers rows 4k .. 4k + 3; lanes of a missing row give zeros
   const int nsteps = (nr + 3) / 4;
-  float an[S][4], bn[S][2];
-  auto issue = [&](int k0) {
+  // loads without branches, masked at use, in two buffers that take turns,
+  // as in colb32_part
+  float a0[S][4], b0[S][2], a1[S][4], b1[S][2];
+  auto issue = [&](int k0, float (&an)[S][4], float (&bn)[S][2]) {
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-      const int r = 4 * (k0 + u) + kq;
-      const bool ok = r < nr;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) an[u][q] = 0.f;
-      if (act && ok) load_slot(base + (size_t)(4 * (k0 + u)) * rstride, dt, an[u]);
-      bn[u][0] = ok ? xb[(size_t)(4 * (k0 + u)) * a.RS] : 0.f;
-      bn[u][1] = ok ? xb[(size_t)(4 * (k0 + u)) * a.RS + 16] : 0.f;
+      const int rc = min(4 * (k0 + u) + kq, nr - 1);
+      load_slot(base + (size_t)rc * rstride, dt, an[u]);
+      bn[u][0] = xb[(size_t)rc * a.RS];
+      bn[u][1] = xb[(size_t)rc * a.RS + 16];
     }
   };
-  auto compute = [&](int k, const float (&av)[S][4], const float (&bv)[S][2]) {
+  auto compute = [&](int k0, const float (&an)[S][4], const float (&bn)[S][2]) {
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-      if (k + u >= nsteps) break;                   // uniform across the wave
+      const bool ok = 4 * (k0 + u) + kq < nr;
 #pragma unroll
       for (int q = 0; q < CPL; ++q)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) acc[q][h] = mfma16x4(av[u][q], bv[u][h], acc[q][h]);
+        for (int h = 0; h < 2; ++h) acc[q][h] = mfma16x4(an[u][q], ok ? bn[u][h] : 0.f, acc[q][h]);
     }
   };
   // the first loads of the tile and the destinations of the lane's columns
   // go out together; the factors and the LDS tables follow the main loop
-  if constexpr (DB) issue(0);
+  issue(0, a0, b0);
   int32_t e[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) e[q] = (lane < 16 && act && q < cps) ? a.dst[T.dst_off + col + q] : kDstPad;
-  if constexpr (DB) {
-    for (int k = 0; k < nsteps; k += S) {
-      float ac[S][4], bc[S][2];
-#pragma unroll
-      for (int u = 0; u < S; ++u) {
-        bc[u][0] = bn[u][0];
-        bc[u][1] = bn[u][1];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ac[u][q] = an[u][q];
-      }
-      if (k + S < nsteps) issue(k + S);
-      compute(k, ac, bc);
-    }
-  } else {
-    for (int k = 0; k < nsteps; k += S) {
-      issue(k);
-      compute(k, an, bn);
-    }
+  for (int k = 0; k < nsteps; k += 2 * S) {
+    issue(k + S, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(k, a0, b0);
+    issue(k + 2 * S, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(k + S, a1, b1);
   }
   if (lane < 16) {
 #pragma unroll
@@ -332,14 +396,13 @@ __device__ __forceinline__ void colb16_part(const ColBArgs& a, const ColTile& T,
   }
 }
 
-// Column kernels: steps per batch of row loads, and the next batch's loads
-// in flight during the current one (measured best).
+// Column kernels: steps per batch of row loads (measured best).
 constexpr int kColBSteps = 4;
-constexpr bool kColBDouble = true;
 
 // Workgroup (one wave) w -> (tile t0 + w / (4 RH), quarter of its slots,
 // right-hand-side group) over the one-format FP32 tiles [t0, t1): 32 slots
 // per wave, so each x row loaded serves the most columns.
+template <int S>
 __global__ __launch_bounds__(64) void k_col_b32(ColBArgs a, int64_t t0, int64_t t1) {
   __shared__ int32_t sdst[64];
   __shared__ float ssig[64];
@@ -352,7 +415,26 @@ __global__ __launch_bounds__(64) void k_col_b32(ColBArgs a, int64_t t0, int64_t 
   if (ti >= t1) return;
   const ColTile T = a.tiles[ti];
   if (32 * quarter >= 2 * T.ngroups) return;         // uniform: nothing in this quarter
-  colb32_part<HM_F32, kColBSteps, kColBDouble>(a, T, quarter, rh, lane, sdst, ssig);
+  colb32_part<HM_F32, S>(a, T, quarter, rh, lane, sdst, ssig);
+}
+
+// Workgroup (one wave) w -> (tile t0 + w / (2 RH), half of its groups,
+// right-hand-side group) over the one-format FP32 tiles [t0, t1): 32
+// 16-byte groups per wave (launch parameter colb = 1).
+template <int S>
+__global__ __launch_bounds__(64) void k_col_b32g(ColBArgs a, int64_t t0, int64_t t1) {
+  __shared__ int32_t sdst[128];
+  __shared__ float ssig[128];
+  const int lane = threadIdx.x;
+  const int64_t w = blockIdx.x;
+  const int rh = (int)(w % a.RH);
+  const int64_t rest = w / a.RH;
+  const int half = (int)(rest & 1);
+  const int64_t ti = t0 + (rest >> 1);
+  if (ti >= t1) return;
+  const ColTile T = a.tiles[ti];
+  if (32 * half >= T.ngroups) return;                // uniform: nothing in this half
+  colb32g_part<S>(a, T, half, rh, lane, sdst, ssig);
 }
 
 // Workgroup (one wave) w -> (tile t0 + w / (8 RH), sixteenth of its slots,
@@ -372,7 +454,7 @@ __global__ __launch_bounds__(64) void k_col_b16(ColBArgs a, int64_t t0, int64_t 
   if (ti >= t1) return;
   const ColTile T = a.tiles[ti];
   if (16 * s16 >= 2 * T.ngroups) return;             // uniform: nothing in this part
-  colb16_part<DT, kColBSteps, kColBDouble>(a, T, s16, rh, lane, sdst, ssig);
+  colb16_part<DT, kColBSteps>(a, T, s16, rh, lane, sdst, ssig);
 }
 
 struct RedBArgs {
@@ -430,13 +512,19 @@ struct RowBArgs {
 };
 
 // Decode one 16-byte group of storage format dt (FP32: 4 values; FP16 or
-// BF16: 8) into v.
-__device__ __forceinline__ void decode_any(int dt, u32x4 r, float (&v)[8]) {
-  if (dt == HM_F32) {
+// BF16: 8) into v: DT >= 0 fixes the format at compile time, DT < 0 takes
+// dt at run time.
+template <int DT>
+__device__ __forceinline__ void decode_group(int dt, u32x4 r, float (&v)[8]) {
+  if constexpr (DT < 0) {
+    if (dt == HM_F32) decode_group<HM_F32>(dt, r, v);
+    else if (dt == HM_F16) decode_group<HM_F16>(dt, r, v);
+    else decode_group<HM_BF16>(dt, r, v);
+  } else if constexpr (DT == HM_F32) {
     const f32x4 f = __builtin_bit_cast(f32x4, r);
 #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] = f[c];
-  } else if (dt == HM_F16) {
+  } else if constexpr (DT == HM_F16) {
     const f16x8 h = __builtin_bit_cast(f16x8, r);
 #pragma unroll
     for (int c = 0; c < 8; ++c) v[c] = (float)h[c];
@@ -463,36 +551,44 @@ __device__ __forceinline__ void xpose16x4(float& v0, float& v1, float& v2, float
   v3 = __uint_as_float(d[1]);
 }
 
-// One section of a row panel of at most 16 NB rows for the groups g = wave,
-// wave + 4, ...: per group a 16-byte load of the panel (lane = row, G
-// columns).  Columns go in sets of 4: the transpose above turns the set's
-// values of rows 16 q .. 16 q + 15 into the A operand of
-// v_mfma_f32_16x16x4_f32 for row block q (lane 16 k + i: row 16 q + i,
-// column k of the set).  The B operand of half h of the right-hand sides
-// holds, in lane 16 k + j, value NV j + h of the source row of column k, so
-// one load of NV = RS / 16 consecutive values per lane brings all halves.
-// Groups go in steps of U; the loads of the next step are in flight while
-// this step's MFMAs run, and the source slots of the step after that are
-// read (scalar loads) meanwhile.
-template <int NH, int U, int NB>
+// One section of a row panel of at most 16 NB rows, storage format DT (or,
+// for DT < 0, the section's own), for the groups g = wave, wave + 4, ...:
+// per group a 16-byte load of the panel (lane = row, G columns).  Columns
+// go in sets of 4: the transpose above turns the set's values of rows
+// 16 q .. 16 q + 15 into the A operand of v_mfma_f32_16x16x4_f32 for row
+// block q (lane 16 k + i: row 16 q + i, column k of the set).  The B
+// operand of half h of the right-hand sides holds, in lane 16 k + j, value
+// NV j + h of the source row of column k, so one load of NV = RS / 16
+// consecutive values per lane brings all halves.  Groups go in steps of U;
+// the loads of the next step are in flight while this step's MFMAs run,
+// and the source slots of the step after that are read (scalar loads)
+// meanwhile.
+// With the format fixed (DT >= 0) the loads have no branches: a group past
+// the section reads its last group, whose sources are replaced by zero at use
+// (its MFMAs add nothing), and a lane past the panel's rows reads row 0,
+// which fills only result rows that are never written; so the loop body is
+// one basic block and the accumulators stay in their registers.  With the
+// format taken at run time (sections of several formats, often of few
+// groups) the steps stop at the section's last group instead.
+template <int NH, int U, int NB, int DT>
 __device__ __forceinline__ void rowb_section(const RowBArgs& a, const RowSection& S, int m,
                                              const int32_t* src, int lane, int wave,
                                              f32x4 (&acc)[NB][2 * NH]) {
   constexpr int RS = 32 * NH, NV = 2 * NH;
+  constexpr bool kPad = DT >= 0;
+  const int dt = DT >= 0 ? DT : S.dtype;
+  const int G = DT >= 0 ? (DT == HM_F32 ? 4 : 8) : group_width(dt);
   typedef float fv __attribute__((ext_vector_type(NV)));
-  const int dt = S.dtype, G = group_width(dt);
-  const u32x4* p = reinterpret_cast<const u32x4*>(a.store + S.data_off) + lane;
-  const int32_t* sc = src + S.col0;                // source slot of every column of the section
   const bool act = lane < m;
+  const u32x4* p = reinterpret_cast<const u32x4*>(a.store + S.data_off) + (act ? lane : 0);
+  const int32_t* sc = src + S.col0;                // source slot of every column of the section
   const int ng = S.ngroups, k = lane >> 4, j = lane & 15;
-  u32x4 an[U];
-  fv bn[U][2];                                     // B operands of up to 2 sets of 4 columns
-  int sn[U][8];                                    // source slots of the step after this one
-  auto load_slots = [&](int g0) {
+  auto load_slots = [&](int g0, int (&sn)[U][8]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int gg = g0 + 4 * u;
-      if (gg >= ng) break;                          // uniform across the wave
+      int gg = g0 + 4 * u;
+      if constexpr (kPad) gg = min(gg, ng - 1);
+      else if (gg >= ng) break;                    // uniform across the wave
 #pragma unroll
       for (int c = 0; c < 8; ++c)
         if (c < G) sn[u][c] = sc[gg * G + c];
@@ -501,12 +597,16 @@ __device__ __forceinline__ void rowb_section(const RowBArgs& a, const RowSection
   auto srow = [&](int sl) {
     return sl < a.n_cols ? a.xr + (size_t)sl * RS : a.t + (size_t)(sl - a.n_cols) * RS;
   };
-  auto issue = [&](int g0) {
+  auto issue = [&](int g0, const int (&sn)[U][8], u32x4 (&an)[U], fv (&bn)[U][2]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int gg = g0 + 4 * u;
-      if (gg >= ng) break;                          // uniform across the wave
-      an[u] = act ? ld16(p + (size_t)gg * m) : (u32x4)(0u);
+      if constexpr (kPad) {
+        an[u] = ld16(p + (size_t)min(gg, ng - 1) * m);
+      } else {
+        if (gg >= ng) break;                        // uniform across the wave
+        an[u] = act ? ld16(p + (size_t)gg * m) : (u32x4)(0u);
+      }
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         if (4 * s < G) {
@@ -520,49 +620,76 @@ __device__ __forceinline__ void rowb_section(const RowBArgs& a, const RowSection
       }
     }
   };
-  load_slots(wave);
-  issue(wave);
-  load_slots(wave + 4 * U);
-  for (int g = wave; g < ng; g += 4 * U) {
-    u32x4 ac[U];
-    fv bc[U][2];
+  auto compute = [&](int g0, const u32x4 (&an)[U], const fv (&bn)[U][2]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ac[u] = an[u];
-      bc[u][0] = bn[u][0];
-      bc[u][1] = bn[u][1];
-    }
-    issue(g + 4 * U);
-    load_slots(g + 8 * U);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (g + 4 * u >= ng) break;                   // uniform across the wave
+      if constexpr (!kPad)
+        if (g0 + 4 * u >= ng) break;                // uniform across the wave
       float v[8];
-      decode_any(dt, ac[u], v);
+      decode_group<DT>(dt, an[u], v);
+      // a group past the section (padded steps): its sources are replaced by zero
+      const bool gok = !kPad || g0 + 4 * u < ng;
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         if (4 * s < G) {
           xpose16x4(v[4 * s], v[4 * s + 1], v[4 * s + 2], v[4 * s + 3]);
+          const fv b = gok ? bn[u][s] : (fv)(0.f);
 #pragma unroll
           for (int q = 0; q < NB; ++q)
 #pragma unroll
-            for (int h = 0; h < NV; ++h) acc[q][h] = mfma16x4(v[4 * s + q], bc[u][s][h], acc[q][h]);
+            for (int h = 0; h < NV; ++h) acc[q][h] = mfma16x4(v[4 * s + q], b[h], acc[q][h]);
         }
       }
+    }
+  };
+  u32x4 a0[U], a1[U];
+  fv b0[U][2], b1[U][2];                           // B operands of up to 2 sets of 4 columns
+  int s0[U][8], s1[U][8];                          // source slots, one step ahead of their loads
+  load_slots(wave, s0);
+  issue(wave, s0, a0, b0);
+  load_slots(wave + 4 * U, s1);
+  if constexpr (kPad) {
+    // two buffers take turns: while one step's MFMAs run, the next step's
+    // loads are in flight into the other
+    for (int g = wave; g < ng; g += 8 * U) {
+      issue(g + 4 * U, s1, a1, b1);
+      load_slots(g + 8 * U, s0);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(g, a0, b0);
+      issue(g + 8 * U, s0, a0, b0);
+      load_slots(g + 12 * U, s1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(g + 4 * U, a1, b1);
+    }
+  } else {
+    for (int g = wave; g < ng; g += 4 * U) {
+      u32x4 ac[U];
+      fv bc[U][2];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ac[u] = a0[u];
+        bc[u][0] = b0[u][0];
+        bc[u][1] = b0[u][1];
+      }
+      issue(g + 4 * U, s1, a0, b0);
+      load_slots(g + 8 * U, s1);
+      compute(g, ac, bc);
     }
   }
 }
 
-// Groups per pipeline step in k_row_b (2 measured fastest; deeper steps
-// cost occupancy).
+// Groups per pipeline step in k_row_b: 2 for sections of run-time formats
+// (measured fastest; deeper steps cost occupancy), kRowBStepF32 for the
+// FP32-only kernel.
 constexpr int kRowBStep = 2;
+constexpr int kRowBStepF32 = 3;
 
 // A row panel of at most 16 NB rows: the four waves take interleaved groups
 // of every section, then their sums are added in a fixed order through LDS
 // ((w0 + w2) + (w1 + w3)) and each row of Y is updated once.  red: 2 x 64
 // rows of RS + 1 values (the padding keeps the row-wise reads of the update
 // free of bank conflicts).
-template <int NH, int NB>
+template <int NH, int NB, int DT>
 __device__ __forceinline__ void rowb_panel(const RowBArgs& a, const RowPanel& P, float* red,
                                            int tid, int lane, int wave) {
   constexpr int RS = 32 * NH, NV = 2 * NH, RP = RS + 1;
@@ -574,7 +701,8 @@ __device__ __forceinline__ void rowb_panel(const RowBArgs& a, const RowPanel& P,
   const int32_t* src = a.src + P.src_off;
   for (int qs = 0; qs < P.nsec; ++qs) {
     const RowSection S = a.rs[P.sec0 + qs];
-    if (S.dtype != HM_F64) rowb_section<NH, kRowBStep, NB>(a, S, P.m, src, lane, wave, acc);
+    if (DT >= 0 || S.dtype != HM_F64)
+      rowb_section<NH, DT >= 0 ? kRowBStepF32 : kRowBStep, NB, DT>(a, S, P.m, src, lane, wave, acc);
   }
   // acc[q][h] register v of lane 16 k + j: row 16 q + 4 k + v, right-hand side NV j + h.
   // Waves 2 and 3 store, waves 0 and 1 add (w0 + w2, w1 + w3), wave 1
@@ -617,8 +745,10 @@ __device__ __forceinline__ void rowb_panel(const RowBArgs& a, const RowPanel& P,
   }
 }
 
-// One workgroup per row panel, specialised on its number of 16-row blocks.
-template <int NH>
+// One workgroup per row panel, specialised on its number of 16-row blocks,
+// and on the storage format when the store holds FP32 sections only (DT =
+// HM_F32; else DT = -1, the format of each section).
+template <int NH, int DT>
 __global__ __launch_bounds__(256) void k_row_b(RowBArgs a) {
   constexpr int RS = 32 * NH;
   __shared__ float red[2 * 64 * (RS + 1)];
@@ -627,10 +757,10 @@ __global__ __launch_bounds__(256) void k_row_b(RowBArgs a) {
   if (pi < 0) return;                               // uniform: whole workgroup
   const RowPanel P = a.rp[pi];
   switch ((P.m + 15) >> 4) {                        // uniform: whole workgroup
-    case 1: rowb_panel<NH, 1>(a, P, red, tid, lane, wave); break;
-    case 2: rowb_panel<NH, 2>(a, P, red, tid, lane, wave); break;
-    case 3: rowb_panel<NH, 3>(a, P, red, tid, lane, wave); break;
-    default: rowb_panel<NH, 4>(a, P, red, tid, lane, wave); break;
+    case 1: rowb_panel<NH, 1, DT>(a, P, red, tid, lane, wave); break;
+    case 2: rowb_panel<NH, 2, DT>(a, P, red, tid, lane, wave); break;
+    case 3: rowb_panel<NH, 3, DT>(a, P, red, tid, lane, wave); break;
+    default: rowb_panel<NH, 4, DT>(a, P, red, tid, lane, wave); break;
   }
 }
 
@@ -670,8 +800,14 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
       // one launch per tile class
       const int64_t* ce = h.tile_class_end;
       auto grid = [&](int64_t t0, int64_t t1, int parts) { return dim3((unsigned)((t1 - t0) * parts * RH)); };
-      if (ce[1] > ce[0])
-        hipLaunchKernelGGL(k_col_b32, grid(ce[0], ce[1], 4), dim3(64), 0, s, ca, ce[0], ce[1]);
+      if (ce[1] > ce[0]) {
+        switch (A.launch.colb) {
+          case 1: hipLaunchKernelGGL(k_col_b32g<kColBSteps>, grid(ce[0], ce[1], 2), dim3(64), 0, s, ca, ce[0], ce[1]); break;
+          case 2: hipLaunchKernelGGL(k_col_b32<2 * kColBSteps>, grid(ce[0], ce[1], 4), dim3(64), 0, s, ca, ce[0], ce[1]); break;
+          case 3: hipLaunchKernelGGL(k_col_b32g<2 * kColBSteps>, grid(ce[0], ce[1], 2), dim3(64), 0, s, ca, ce[0], ce[1]); break;
+          default: hipLaunchKernelGGL(k_col_b32<kColBSteps>, grid(ce[0], ce[1], 4), dim3(64), 0, s, ca, ce[0], ce[1]); break;
+        }
+      }
       if (ce[2] > ce[1])
         hipLaunchKernelGGL(k_col_b16<HM_F16>, grid(ce[1], ce[2], 8), dim3(64), 0, s, ca, ce[1], ce[2]);
       if (ce[3] > ce[2])
@@ -702,10 +838,16 @@ hipError_t launch_mvm_batch(const hm_matrix& A, int nrhs, double alpha, const vo
                 reinterpret_cast<const int32_t*>(st + h.off_row_src),
                 xr, t, Yc, ldy, (float)alpha, (int32_t)h.n_cols, nr};
     const unsigned grid = (unsigned)panel_items(xcd, h.n_row_panels);
-    if (RH == 1)
-      hipLaunchKernelGGL(k_row_b<1>, dim3(grid), dim3(256), 0, s, ra);
-    else
-      hipLaunchKernelGGL(k_row_b<2>, dim3(grid), dim3(256), 0, s, ra);
+    // FP32 sections only: the format-specialised row kernel
+    bool f32_only = A.bytes_by_dtype[HM_F32] > 0;
+    for (int d = 0; d < kNumDtypes; ++d) f32_only &= d == HM_F32 || A.bytes_by_dtype[d] == 0;
+    if (RH == 1) {
+      if (f32_only) hipLaunchKernelGGL((k_row_b<1, HM_F32>), dim3(grid), dim3(256), 0, s, ra);
+      else hipLaunchKernelGGL((k_row_b<1, -1>), dim3(grid), dim3(256), 0, s, ra);
+    } else {
+      if (f32_only) hipLaunchKernelGGL((k_row_b<2, HM_F32>), dim3(grid), dim3(256), 0, s, ra);
+      else hipLaunchKernelGGL((k_row_b<2, -1>), dim3(grid), dim3(256), 0, s, ra);
+    }
   }
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError();

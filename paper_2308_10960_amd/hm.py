@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhm.so")
+# HM_LIBRARY selects another build of the same library (the sanitized host
+# build of the CPU tests); the default is the in-tree libhm.so
+LIB_PATH = os.environ.get("HM_LIBRARY") or os.path.join(HERE, "libhm.so")
 
 HM_OK, HM_EINVAL, HM_EPARTITION, HM_ESHAPE, HM_EDTYPE = 0, -1, -2, -3, -4
 HM_ENOMEM, HM_EDEVICE, HM_EBUSY, HM_ESTATE, HM_ETIMEOUT = -5, -6, -7, -8, -9
@@ -94,6 +96,11 @@ PROTOTYPES = {
     "hm_server_stats": (_i32, [_vp, _P(_dbl), _P(_dbl), _P(_dbl)]),
     "hm_server_destroy": (None, [_vp]),
     "hm_last_error": (C.c_char_p, []),
+    # include/hm_construct.h
+    "hm_construct_layout": (_i32, [_vp, _i64, _P(_i64), _P(_i64)]),
+    "hm_construct_rank_limit": (_i32, [_P(_i32)]),
+    "hm_construct": (_i32, [_vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp, _sz, _vp, _sz, _vp, _vp]),
+    "hm_construct_pack": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
 }
 
 _lib = None
@@ -319,6 +326,47 @@ def hm_server_stats(server: int):
 
 def hm_server_destroy(server: int) -> None:
     lib().hm_server_destroy(server)
+
+
+# ------------------------------------------------------------ construction
+
+HM_KERNEL_LAPLACE, HM_KERNEL_EXP = 0, 1
+HM_CONSTRUCT_MAX_RANK = 128
+
+# hm_cblock as a numpy structured dtype (same layout as the C struct).
+CBLOCK_DTYPE = np.dtype([("rb", "<i8"), ("cb", "<i8"), ("m", "<i4"), ("n", "<i4"), ("adm", "<i4"),
+                         ("cap", "<i4"), ("out", "<i8"), ("scr", "<i8")], align=True)
+
+
+class ConstructOpts(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("keep_sigma", C.c_int32), ("params", C.c_double * 2),
+                ("eps_aca", C.c_double), ("eps", C.c_double)]
+
+
+def hm_construct_layout(blocks: np.ndarray):
+    """Sets cap (where 0), out and scr in place; returns (out doubles, scratch doubles)."""
+    assert blocks.dtype == CBLOCK_DTYPE and blocks.flags.c_contiguous
+    o, sc = C.c_int64(), C.c_int64()
+    _check(lib().hm_construct_layout(blocks.ctypes.data, blocks.shape[0], C.byref(o), C.byref(sc)),
+           "hm_construct_layout")
+    return o.value, sc.value
+
+
+def hm_construct_rank_limit() -> int:
+    r = C.c_int32()
+    _check(lib().hm_construct_rank_limit(C.byref(r)), "hm_construct_rank_limit")
+    return r.value
+
+
+def hm_construct(d_points, n_points: int, blocks: np.ndarray, d_desc, desc_bytes: int, kernel: int, params,
+                 eps_aca: float, eps: float, keep_sigma: bool, d_out, out_bytes: int, d_scr, scr_bytes: int,
+                 d_rank, stream=None) -> None:
+    assert blocks.dtype == CBLOCK_DTYPE and blocks.flags.c_contiguous
+    p = (C.c_double * 2)(*[float(v) for v in params[:2]])
+    opts = ConstructOpts(kernel, int(keep_sigma), p, eps_aca, eps)
+    _check(lib().hm_construct(_ptr(d_points), n_points, blocks.ctypes.data, blocks.shape[0], _ptr(d_desc),
+                              desc_bytes, C.byref(opts), _ptr(d_out), out_bytes, _ptr(d_scr), scr_bytes,
+                              _ptr(d_rank), _stream(stream)), "hm_construct")
 
 
 def hm_last_error() -> str:

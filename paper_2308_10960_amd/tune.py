@@ -20,8 +20,10 @@ CANDIDATES = ["schedule=0 unroll=4 order=0 persist=0", "schedule=0 unroll=8 orde
               "schedule=0 unroll=8 order=1 persist=0", "schedule=0 unroll=8 order=1 persist=4",
               "schedule=0 unroll=8 order=1 persist=8", "schedule=1 unroll=4 order=0 persist=0",
               "schedule=1 unroll=8 order=0 persist=0", "schedule=1 unroll=8 order=0 persist=8"]
-# the batched path only depends on the row-panel order
-BATCH_CANDIDATES = ["schedule=0 unroll=8 order=0 persist=0", "schedule=0 unroll=8 order=1 persist=0"]
+# the batched path: row-panel order, and FP32 column tiles as 8-byte slots
+# (colb=0) or 16-byte groups (colb=1) per lane; none changes a bit
+BATCH_CANDIDATES = ["schedule=0 unroll=8 order=0 persist=0 colb=0", "schedule=0 unroll=8 order=1 persist=0 colb=0",
+                    "schedule=0 unroll=8 order=0 persist=0 colb=1", "schedule=0 unroll=8 order=1 persist=0 colb=1"]
 # column-tile shapes (chunk rows, tile groups)
 SHAPE_CANDIDATES = [(512, 64), (256, 64), (128, 64), (64, 64), (512, 32), (256, 32)]
 

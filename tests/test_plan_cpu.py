@@ -28,7 +28,8 @@ def _lib_built():
 
 
 def test_exports_every_declared_symbol():
-    text = open(os.path.join(ROOT, "include", "hm.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = set(re.findall(r"\b(hm_[a-z_0-9]+)\s*\(", text))
     assert len(names) >= 16
