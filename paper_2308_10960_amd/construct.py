@@ -31,6 +31,8 @@ def _kernel_params(H):
 # ACA columns reserved per leaf in the first pass; leaves whose ACA needs
 # more run again with HM_CONSTRUCT_MAX_RANK columns
 FIRST_CAP = 48
+# doubles of the page-locked staging buffer for the copies to the host (1 GiB)
+STAGE = 1 << 27
 
 
 def _batches(order, need, budget):
@@ -65,7 +67,7 @@ def fill_gpu(H, eps_aca: float | None = None, budget_bytes: int = 48 << 30, devi
     budget_d = min(budget_bytes, free // 2) // 8
     host_left, gpu_s, copy_s = [], 0.0, 0.0
     nbatches, retried = 0, 0
-    h_packed = None
+    h_stage = None
     todo = np.argsort(-(m + n), kind="stable")             # large leaves first within a batch
     for cap_max in (FIRST_CAP, hm.HM_CONSTRUCT_MAX_RANK):
         if todo.size == 0:
@@ -110,11 +112,15 @@ def fill_gpu(H, eps_aca: float | None = None, budget_bytes: int = 48 << 30, devi
             hm._check(lib.hm_construct_pack(hm._ptr(d_desc), nb, hm._ptr(d_rank), hm._ptr(d_out),
                                             hm._ptr(d_off), hm._ptr(d_packed), d_packed.numel() * 8,
                                             hm._stream(stream)), "hm_construct_pack")
-            # device -> page-locked staging (full copy bandwidth), reused across batches
-            if h_packed is None or h_packed.numel() < d_packed.numel():
-                h_packed = torch.empty(d_packed.numel(), dtype=torch.float64, pin_memory=True)
-            h_packed[:d_packed.numel()].copy_(d_packed)
-            packed = h_packed.numpy()
+            # device -> host through a page-locked staging buffer of STAGE
+            # doubles (full copy bandwidth), reused across batches
+            if h_stage is None:
+                h_stage = torch.empty(STAGE, dtype=torch.float64, pin_memory=True)
+            packed = np.empty(max(total, 1))
+            for c0 in range(0, total, STAGE):
+                c1 = min(total, c0 + STAGE)
+                h_stage[:c1 - c0].copy_(d_packed[c0:c1])
+                packed[c0:c1] = h_stage[:c1 - c0].numpy()
             del d_packed, d_off
             sel = np.flatnonzero(ok)
             kk = np.where(adm[idx] == 1, np.maximum(rank, 0), 0)

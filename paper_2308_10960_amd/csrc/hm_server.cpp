@@ -11,11 +11,12 @@
 //  * keeps up to n_streams batches in flight, one per stream slot, so
 //    requests arriving while others run start as soon as a slot and memory
 //    free up (no waiting for the whole previous batch set).
-// Each slot has a worker thread that gathers its batch's right-hand sides
-// into pinned memory, enqueues copy, product and copy-back on its stream,
-// waits for them, scatters the results into the clients' buffers and
-// completes the tickets (latency recorded at completion); the host copies
-// of different slots run in parallel, outside the server lock.
+// Each slot has a worker thread that brings its batch's right-hand sides to
+// the device (directly from page-locked client buffers, else gathered
+// through its pinned staging buffer), enqueues product and copy-back on its
+// stream, waits for them, hands the results over and completes the tickets
+// (latency recorded at completion); the host work of different slots runs
+// in parallel, outside the server lock.
 // A request's result does not depend on the batch it lands in: every column
 // of a batch is computed by the same kernels in the same order.
 //
@@ -52,10 +53,29 @@ struct Request {
   int64_t ldx;
   void* hy;
   int64_t ldy;
+  bool x_pinned = false, y_pinned = false;   // page-locked client buffers: copied without staging
   Clock::time_point t_submit;
   bool done = false;
   hm_status result = HM_OK;
 };
+
+// Whether [p, p + bytes) lies in page-locked host memory the device can
+// reach directly (hipHostMalloc); a failed query (ordinary pageable memory)
+// is cleared so that it does not surface in a later call.
+bool host_pinned(const void* p, size_t bytes) {
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (at.type != hipMemoryTypeHost) return false;
+  hipPointerAttribute_t end{};
+  if (hipPointerGetAttributes(&end, static_cast<const uint8_t*>(p) + bytes - 1) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return end.type == hipMemoryTypeHost;
+}
 
 // First-fit allocator over [0, size) in 256-byte units.
 class Arena {
@@ -163,15 +183,21 @@ void finish(hm_server* S, const std::shared_ptr<Request>& q, hm_status st, Clock
   S->t_last = now;
 }
 
-// Run one batch on its slot (worker thread, server lock not held): gather
-// the right-hand sides into pinned memory, enqueue copy, product and
-// copy-back, wait, scatter the results.
+// Run one batch on its slot (worker thread, server lock not held): bring
+// the right-hand sides to the device, enqueue the product and the
+// copy-back, wait, and hand the results over.  A request in page-locked
+// client memory is copied by the device straight between its buffers and
+// its columns of the batch (2-D copies with the caller's leading
+// dimensions); the others go through the slot's pinned staging buffer
+// (gathered before, scattered after).
 hm_status run_batch(hm_server* S, Slot& sl) {
   const hm_matrix* A = S->mats[sl.mat];
   const size_t vs = A->acc_dtype == HM_F64 ? 8 : 4;
   const int64_t nr = A->hdr.n_rows, nc = A->hdr.n_cols;
   const size_t xbytes = (size_t)nc * sl.nrhs * vs, ybytes = (size_t)nr * sl.nrhs * vs;
-  if (sl.pinned_bytes < xbytes + ybytes) {
+  bool staged = false;
+  for (auto& q : sl.reqs) staged |= !q->x_pinned || !q->y_pinned;
+  if (staged && sl.pinned_bytes < xbytes + ybytes) {
     if (sl.pinned) (void)hipHostFree(sl.pinned);
     sl.pinned = nullptr;
     sl.pinned_bytes = 0;
@@ -180,33 +206,57 @@ hm_status run_batch(hm_server* S, Slot& sl) {
     sl.pinned_bytes = xbytes + ybytes;
   }
   uint8_t* px = (uint8_t*)sl.pinned;
-  int32_t col = 0;
-  for (auto& q : sl.reqs) {
-    for (int32_t c = 0; c < q->nrhs; ++c)
-      std::memcpy(px + (size_t)(col + c) * nc * vs, (const uint8_t*)q->hx + (size_t)c * q->ldx * vs,
-                  (size_t)nc * vs);
-    col += q->nrhs;
-  }
+  uint8_t* py = px ? px + xbytes : nullptr;
   uint8_t* base = S->arena_base + sl.off;
   uint8_t* dX = base;
   uint8_t* dY = base + align256(xbytes);
   uint8_t* dW = dY + align256(ybytes);
   const size_t wbytes = (size_t)hm::batch_slots(A->acc_dtype, sl.nrhs) * A->work_bytes_per_rhs;
   hm_status st = HM_OK;
-  if (hipMemcpyAsync(dX, px, xbytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
-      hipMemsetAsync(dY, 0, ybytes, sl.stream) != hipSuccess)
-    st = HM_EDEVICE;
+  auto ok = [&](hipError_t e) { if (e != hipSuccess && st == HM_OK) st = HM_EDEVICE; };
+  int32_t col = 0;
+  for (auto& q : sl.reqs) {
+    const size_t o = (size_t)col * nc * vs;
+    if (q->x_pinned) {
+      if (q->ldx == nc)
+        ok(hipMemcpyAsync(dX + o, q->hx, (size_t)nc * q->nrhs * vs, hipMemcpyHostToDevice, sl.stream));
+      else
+        for (int32_t c = 0; c < q->nrhs; ++c)
+          ok(hipMemcpyAsync(dX + o + (size_t)c * nc * vs, (const uint8_t*)q->hx + (size_t)c * q->ldx * vs,
+                            (size_t)nc * vs, hipMemcpyHostToDevice, sl.stream));
+    } else {
+      for (int32_t c = 0; c < q->nrhs; ++c)
+        std::memcpy(px + o + (size_t)c * nc * vs, (const uint8_t*)q->hx + (size_t)c * q->ldx * vs,
+                    (size_t)nc * vs);
+      ok(hipMemcpyAsync(dX + o, px + o, (size_t)nc * q->nrhs * vs, hipMemcpyHostToDevice, sl.stream));
+    }
+    col += q->nrhs;
+  }
+  ok(hipMemsetAsync(dY, 0, ybytes, sl.stream));
   if (st == HM_OK) st = hm_mvm_batch(A, sl.nrhs, 1.0, dX, nc, dY, nr, dW, wbytes, sl.stream);
-  if (st == HM_OK && hipMemcpyAsync(px + xbytes, dY, ybytes, hipMemcpyDeviceToHost, sl.stream) != hipSuccess)
-    st = HM_EDEVICE;
-  if (hipStreamSynchronize(sl.stream) != hipSuccess && st == HM_OK) st = HM_EDEVICE;
-  if (st != HM_OK) return st;
-  const uint8_t* py = px + xbytes;
   col = 0;
   for (auto& q : sl.reqs) {
-    for (int32_t c = 0; c < q->nrhs; ++c)
-      std::memcpy((uint8_t*)q->hy + (size_t)c * q->ldy * vs, py + (size_t)(col + c) * nr * vs,
-                  (size_t)nr * vs);
+    const size_t o = (size_t)col * nr * vs;
+    if (q->y_pinned) {
+      if (q->ldy == nr)
+        ok(hipMemcpyAsync(q->hy, dY + o, (size_t)nr * q->nrhs * vs, hipMemcpyDeviceToHost, sl.stream));
+      else
+        for (int32_t c = 0; c < q->nrhs; ++c)
+          ok(hipMemcpyAsync((uint8_t*)q->hy + (size_t)c * q->ldy * vs, dY + o + (size_t)c * nr * vs,
+                            (size_t)nr * vs, hipMemcpyDeviceToHost, sl.stream));
+    } else {
+      ok(hipMemcpyAsync(py + o, dY + o, (size_t)nr * q->nrhs * vs, hipMemcpyDeviceToHost, sl.stream));
+    }
+    col += q->nrhs;
+  }
+  if (hipStreamSynchronize(sl.stream) != hipSuccess && st == HM_OK) st = HM_EDEVICE;
+  if (st != HM_OK) return st;
+  col = 0;
+  for (auto& q : sl.reqs) {
+    if (!q->y_pinned)
+      for (int32_t c = 0; c < q->nrhs; ++c)
+        std::memcpy((uint8_t*)q->hy + (size_t)c * q->ldy * vs, py + (size_t)(col + c) * nr * vs,
+                    (size_t)nr * vs);
     col += q->nrhs;
   }
   return HM_OK;
@@ -331,6 +381,9 @@ hm_status hm_submit(hm_server* s, int32_t mat, int32_t nrhs, const void* h_X, in
   auto q = std::make_shared<Request>();
   q->mat = mat; q->nrhs = nrhs; q->hx = h_X; q->ldx = ldx; q->hy = h_Y; q->ldy = ldy;
   q->t_submit = Clock::now();
+  const size_t vs = A->acc_dtype == HM_F64 ? 8 : 4;
+  q->x_pinned = host_pinned(h_X, ((size_t)(nrhs - 1) * ldx + A->hdr.n_cols) * vs);
+  q->y_pinned = host_pinned(h_Y, ((size_t)(nrhs - 1) * ldy + A->hdr.n_rows) * vs);
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return fail(HM_ESTATE, "server is stopping");

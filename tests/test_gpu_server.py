@@ -121,6 +121,32 @@ def test_mix_equals_alone_full_size():
         D.close()
 
 
+def test_pinned_client_buffers(mats):
+    """Requests whose X and Y are page-locked (copied by the device without
+    staging, with their leading dimensions) give bitwise the results of the
+    same requests in pageable buffers."""
+    Hs, Ds = mats
+    reqs = _requests(Hs, 10, 4)
+    s, arena, _ = _server(Ds, 256 << 20, nstreams=2)
+    outs, tickets = _submit_all(s, reqs)
+    pin_in, pin_out, pin_t = [], [], []             # the buffers stay alive until their tickets end
+    for m, r, X in reqs:
+        n = Hs[m].n
+        ld = n + 37                                    # leading dimensions above n
+        Xp = torch.empty((r, ld), dtype=torch.float32, pin_memory=True).numpy()
+        Xp[:, :n] = X.T
+        Yp = torch.zeros((r, ld), dtype=torch.float32, pin_memory=True).numpy()
+        pin_in.append(Xp)
+        pin_out.append(Yp)
+        pin_t.append(hm.hm_submit(s, m, r, Xp, ld, Yp, ld))
+    for t in tickets + pin_t:
+        assert hm.hm_wait(s, t, 60_000_000) == hm.HM_OK
+    hm.hm_server_destroy(s)
+    for (m, r, X), Y, Yp in zip(reqs, outs, pin_out):
+        np.testing.assert_array_equal(Yp[:, :Hs[m].n].T, Y)
+        assert np.all(Yp[:, Hs[m].n:] == 0)             # nothing written past n
+
+
 def test_tiny_arena_queues(mats):
     Hs, Ds = mats
     reqs = _requests(Hs, 12, 1)
