@@ -186,6 +186,23 @@ class HMatrix:
         lib().hmg_eval(C.c_void_p(self.handle), rows, cols, rows.shape[0], out)
         return out
 
+    def tree(self) -> dict:
+        """The cluster tree (per cluster: begin, end, son0, son1, level;
+        sons -1 at a leaf; cluster 0 is the root) and the clusters (tau,
+        sigma) of every leaf of the block tree."""
+        L = lib()
+        h = C.c_void_p(self.handle)
+        nc = L.hmg_num_clusters(h)
+        beg, end = np.empty(nc, np.int64), np.empty(nc, np.int64)
+        son0, son1, level = (np.empty(nc, np.int32) for _ in range(3))
+        box = np.empty(6 * nc)
+        L.hmg_get_clusters(h, beg, end, son0, son1, level, box)
+        nb = self.nblocks
+        rb, re, cb, ce = (np.empty(nb, np.int64) for _ in range(4))
+        adm, tau, sig, rank = (np.empty(nb, np.int32) for _ in range(4))
+        L.hmg_get_blocks(h, rb, re, cb, ce, adm, tau, sig, rank)
+        return {"begin": beg, "end": end, "son0": son0, "son1": son1, "level": level, "tau": tau, "sigma": sig}
+
     def points_cluster_order(self) -> np.ndarray:
         return self.points[self.perm]
 
