@@ -250,6 +250,69 @@ def cpu_baseline(H, xh, alg_bytes, seconds):
                                     "(OpenMP over row ranges, bitwise the single-threaded result)"}}
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def lu_bench(args, torch, hmgen, hm):
+    """The H-LU factorisation with accumulated updates of the workload's
+    kernel matrix (sphere or cube, its eps) at n = --n (default 4096): the
+    GPU's time per factorisation over --steps fresh objects, the truncation
+    kernel's arithmetic rate against the FP64 peak, and the oracle's time on
+    the same matrix (one run, on all host cores numpy uses)."""
+    from paper_2308_10960_amd.lu import DeviceHLU
+    p = hmgen.preset(args.workload)
+    n = args.n or 4096
+    pts = hmgen.fibonacci_sphere(n) if p["geometry"] == "sphere" else hmgen.cube_points(n, 0)
+    kern = hmgen.hmatrix.KERNEL_LAPLACE if p["kernel"] == "laplace" else hmgen.hmatrix.KERNEL_EXP
+    H = hmgen.hmatrix.build_hmatrix(pts, kern, eps=p["eps"])
+    dt = hm.HM_F64 if args.lu_dtype == "f64" else hmgen.dfl_format(p["eps"])
+    log(f"H-LU of {p['geometry']} n={n} eps={p['eps']}: {H.nblocks} leaves, final leaves in {args.lu_dtype}")
+    steps = max(1, min(args.steps, 5))
+    times, st = [], None
+    for q in range(steps + 1):                         # the first is a warm-up
+        G = DeviceHLU(H)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = G.factor(p["eps"], dt)
+        t1 = time.perf_counter()
+        G.close()
+        if q > 0:
+            times.append(t1 - t0)
+        log(f"factorisation {q}: {t1 - t0:.3f}s")
+    G = DeviceHLU(H)
+    prof = G.factor(p["eps"], dt, profile=True)
+    G.close()
+    sec = float(np.median(times))
+    per = prof["trunc_flops"] / max(prof["timed_truncations"], 1)
+    avg_ms = prof["trunc_ms"] / max(prof["timed_truncations"], 1)
+    achieved = per / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    log("statistics", st, "profiled", prof)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import hlu as ohlu
+        t0 = time.perf_counter()
+        ohlu.HLU(H, p["eps"], dt=None if dt == hm.HM_F64 else dt).factor()
+        cs = time.perf_counter() - t0
+        cpu = {"value": round(cs, 3), "unit": "s", "cores": host_threads(), "kind": "oracle",
+               "sample": f"one factorisation of the same n={n} matrix by the numpy oracle (oracle/hlu.py)"}
+        log("oracle factorisation: %.2fs" % cs)
+    out = {"metric": "H-LU factorisation time (accumulated updates)", "value": round(sec, 4), "unit": "s",
+           "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": round(sec * 1e3, 3),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"hlu {p['geometry']}-{p['kernel']} n={n} eps={p['eps']} leaves {args.lu_dtype}",
+                      "n": n, "eps": p["eps"], "leaves": int(H.nblocks), "kernels": st["kernels"],
+                      "truncations": st["truncations"], "max_rank": st["max_rank"],
+                      "stored_bytes": st["stored_bytes"], "arena_peak": st["arena_peak"]},
+           "roofline": {"bound": "alu", "kernel": "k_trunc", "achieved": round(achieved, 4),
+                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 6),
+                        "traffic": None, "flops_per_launch": per, "avg_ms": round(avg_ms, 4),
+                        "share_of_factor_time": round(prof["trunc_ms"] / 1e3 / sec, 3) if sec > 0 else None},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +345,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per load point")
     ap.add_argument("--serve-arena-gb", type=int, default=16)
     ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--lu", action="store_true",
+                    help="time the H-LU factorisation (accumulated updates) of the workload's matrix at --n "
+                         "(default 4096) instead of the product, with the oracle's factorisation beside it")
+    ap.add_argument("--lu-dtype", default="f64", help="storage of the final L and U leaves: f64 or dfl")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -308,6 +375,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
                           "launches": max(1, args.steps)}), flush=True)
+        return
+    if args.lu:
+        lu_bench(args, torch, hmgen, hm)
         return
     p = hmgen.preset(args.workload)
     if args.dtype:
@@ -354,10 +424,10 @@ def main():
     cache = None if args.no_tune_cache or not os.path.exists(args.tune_cache) else args.tune_cache
     R = args.nrhs
 
-    def build(chunk=0, tile=0, use_cache=True):
+    def build(chunk=0, tile=0, mix=0, use_cache=True):
         with torch.cuda.stream(stream):
             return DeviceHMatrix(H, acc, stream=stream, max_nrhs=R, tune_cache=cache if use_cache else None,
-                                 chunk_rows=chunk, tile_groups=tile)
+                                 chunk_rows=chunk, tile_groups=tile, tile_mix=mix)
 
     if R > 1:
         Xh = hmgen.gaussian_block(H.n, R, seed=hmgen.presets.SEED_RHS)
@@ -384,9 +454,9 @@ def main():
     if args.tune:
         from paper_2308_10960_amd import tune
         best, times = tune.tune(D, step, tune.CANDIDATES if R == 1 else tune.BATCH_CANDIDATES)
-        shape, shape_times = tune.tune_shape(lambda c, t: build(c, t, use_cache=False),
+        shape, shape_times = tune.tune_shape(lambda c, t, mx: build(c, t, mx, use_cache=False),
                                              lambda Dc: make_step(Dc)[0], best)
-        chosen = f"{best} chunk={shape[0]} tile={shape[1]}"
+        chosen = f"{best} chunk={shape[0]} tile={shape[1]} tmix={shape[2] - 1}"
         tune.write_cache(args.tune_cache, key, chosen)
         cache = args.tune_cache
         D.close()
@@ -395,7 +465,8 @@ def main():
         torch.cuda.synchronize()
         tuned = {"source": "autotuner, this run (written to the tune cache)", "key": key,
                  "chosen": chosen, "avg_ms": {k: round(v, 5) for k, v in times.items()},
-                 "shape_avg_ms": {f"chunk={c} tile={t}": round(v, 5) for (c, t), v in shape_times.items()}}
+                 "shape_avg_ms": {f"chunk={c} tile={t} tmix={mx - 1}": round(v, 5)
+                                  for (c, t, mx), v in shape_times.items()}}
     else:
         tuned = {"source": "tune cache" if cache else "built-in", "key": key,
                  "chosen": hm.hm_matrix_get_launch(D.handle)}

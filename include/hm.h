@@ -109,12 +109,17 @@ typedef struct {
  * are cut into chunks of at most chunk_rows rows (64 .. 512), and a chunk's
  * columns into tiles of at most tile_groups 16-byte groups (8 .. 64).  0
  * takes the value from the tune cache line of this kind of matrix (keys
- * "chunk" and "tile"), else the built-ins 512 and 64.  Results depend on
- * the shape only by rounding (the partial sums are cut differently). */
+ * "chunk" and "tile"), else the built-ins 512 and 64.  tile_mix: 1 gives
+ * every tile one storage format (a chunk's columns of another format start
+ * a new tile), 2 lets a tile hold columns of up to four formats, 0 takes
+ * the tune cache's "tmix" (0 or 1 there), else the built-in one format per
+ * tile.  Results depend on the shape only by rounding (the partial sums are
+ * cut differently). */
 typedef struct {
   int32_t acc_dtype, vec_dtype, max_nrhs, tune;
   const char* tune_cache;
   int32_t chunk_rows, tile_groups;
+  int32_t tile_mix;
 } hm_plan_opts;
 
 /* Sizes and byte accounting of a plan (all counts exact).
@@ -272,8 +277,10 @@ hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls);
  * "schedule=S unroll=U order=O persist=P" (any subset of the keys; the
  * built-in choice is schedule=0 unroll=8 order=1 persist=0; the text
  * hm_matrix_get_launch writes, and a tune cache line, also name the plan's
- * tile shape, "chunk=C tile=G", which hm_matrix_set_launch accepts only
- * with the plan's own values):
+ * tile shape, "chunk=C tile=G tmix=M", which hm_matrix_set_launch accepts
+ * only with the plan's own values; tmix 0, the built-in, gives every column
+ * tile one storage format, tmix 1 lets a tile hold up to four; the
+ * batched column-tile variant "colb=B" (0 .. 3) is set the same way):
  *   schedule 0: column tiles, partial reduction, whole row panels;
  *   schedule 1: one grouped launch of the dense row-panel sections with the
  *               column tiles, the reduction, then the U sections;

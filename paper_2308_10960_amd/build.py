@@ -23,8 +23,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-HIP_SOURCES = ["hm_kernels.hip", "hm_kernels_batch.hip", "hm_kernels_util.hip", "hm_construct.hip"]
-HOST_SOURCES = ["hm_host.cpp", "hm_server.cpp", "hm_construct_host.cpp"]
+HIP_SOURCES = ["hm_kernels.hip", "hm_kernels_batch.hip", "hm_kernels_util.hip", "hm_construct.hip", "hm_lu.hip"]
+HOST_SOURCES = ["hm_host.cpp", "hm_server.cpp", "hm_construct_host.cpp", "hm_lu_host.cpp"]
 
 
 def _run(cmd, verbose):

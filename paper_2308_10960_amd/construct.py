@@ -112,19 +112,41 @@ def fill_gpu(H, eps_aca: float | None = None, budget_bytes: int = 48 << 30, devi
             hm._check(lib.hm_construct_pack(hm._ptr(d_desc), nb, hm._ptr(d_rank), hm._ptr(d_out),
                                             hm._ptr(d_off), hm._ptr(d_packed), d_packed.numel() * 8,
                                             hm._stream(stream)), "hm_construct_pack")
-            # device -> host through a page-locked staging buffer of STAGE
-            # doubles (full copy bandwidth), reused across batches
+            # device -> host in chunks of whole leaves through two page-locked
+            # buffers of STAGE doubles: the copy of one chunk runs while the
+            # host tree takes the leaves of the other
             if h_stage is None:
-                h_stage = torch.empty(STAGE, dtype=torch.float64, pin_memory=True)
-            packed = np.empty(max(total, 1))
-            for c0 in range(0, total, STAGE):
-                c1 = min(total, c0 + STAGE)
-                h_stage[:c1 - c0].copy_(d_packed[c0:c1])
-                packed[c0:c1] = h_stage[:c1 - c0].numpy()
-            del d_packed, d_off
+                h_stage = [torch.empty(STAGE, dtype=torch.float64, pin_memory=True) for _ in range(2)]
             sel = np.flatnonzero(ok)
             kk = np.where(adm[idx] == 1, np.maximum(rank, 0), 0)
-            H.set_factors(idx[sel], kk[sel], packed, off[sel], kk[sel])
+            chunks, q0 = [], 0
+            while q0 < sel.size:
+                q1 = q0 + 1
+                c0 = off[sel[q0]]
+                while q1 < sel.size and off[sel[q1]] + size[sel[q1]] - c0 <= STAGE:
+                    q1 += 1
+                chunks.append((q0, q1))
+                q0 = q1
+            pending = None
+            for ci in range(len(chunks) + 1):
+                if ci < len(chunks):
+                    q0, q1 = chunks[ci]
+                    c0 = int(off[sel[q0]])
+                    c1 = int(off[sel[q1 - 1]] + size[sel[q1 - 1]])
+                    if c1 - c0 > STAGE:
+                        raise RuntimeError(f"a leaf of {c1 - c0} doubles exceeds the staging buffer")
+                    buf = h_stage[ci % 2]
+                    buf[:c1 - c0].copy_(d_packed[c0:c1], non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record()
+                if pending is not None:
+                    pq0, pq1, pc0, pbuf, pev = pending
+                    pev.synchronize()
+                    part = sel[pq0:pq1]
+                    H.set_factors(idx[part], kk[part], pbuf.numpy(), off[part] - pc0, kk[part])
+                pending = (q0, q1, c0, buf, ev) if ci < len(chunks) else None
+            torch.cuda.synchronize()
+            del d_packed, d_off
             # ACA past its columns with room to grow: again with more; the rest to the host
             more = (rank == -1) & (cap[idx] < np.minimum(np.minimum(m[idx], n[idx]), hm.HM_CONSTRUCT_MAX_RANK))
             again.extend(idx[more].tolist())

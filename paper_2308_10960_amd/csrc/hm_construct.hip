@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/hm_construct.h"
+#include "hm_dense.hpp"
 #include "hm_internal.hpp"
 
 namespace hm {
@@ -55,26 +56,8 @@ __device__ __forceinline__ double kval(const CKern& K, const double* __restrict_
   return i == j ? v + K.p1 : v;
 }
 
-// Sum over the wave, the same value in every lane (lane 0's result).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return __shfl(v, 0, 64);
-}
-
-// Sum over the workgroup, the same value in every thread.  sred: kWaves
-// doubles of LDS; the call synchronizes twice.
-__device__ __forceinline__ double block_sum(double v, double* sred) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) sred[wave] = v;
-  __syncthreads();
-  double s = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) s += sred[w];
-  __syncthreads();
-  return s;
-}
+using dense::block_sum;
+using dense::wave_sum;
 
 // Argmax of v over the workgroup with the lowest index on ties (index -1
 // with value -1 where no thread has a candidate); the same result in every
@@ -220,87 +203,6 @@ __global__ __launch_bounds__(kThreads) void k_aca(const hm_cblock* __restrict__ 
   }
 }
 
-// Householder QR of A (m x r, column-major, m >= r) in place: R in the upper
-// triangle, the reflectors v_j (v_j[j] = 1 implied) below the diagonal, and
-// tau_j in tau (LDS), H_j = I - tau_j v_j v_j^T.  Thread t owns the rows
-// i = t (mod kThreads).  sred: kWaves x HM_CONSTRUCT_MAX_RANK doubles of LDS.
-__device__ void qr_inplace(double* A, int64_t m, int r, double* tau, double (*sred)[HM_CONSTRUCT_MAX_RANK],
-                           double* sv) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int k = 0; k < r; ++k) {
-    double* a = A + (int64_t)k * m;
-    const double akk = a[k];
-    double p = 0;
-    for (int64_t i = k + tid; i < m; i += kThreads) p += a[i] * a[i];
-    const double nrm = sqrt(block_sum(p, sv));
-    if (nrm == 0) {
-      if (tid == 0) tau[k] = 0;
-      __syncthreads();
-      continue;
-    }
-    const double alpha = akk > 0 ? -nrm : nrm;
-    const double v0 = akk - alpha;
-    const double tk = -v0 / alpha;
-    const bool own_k = (k % kThreads) == tid;
-    for (int64_t i = k + 1 + ((tid - (k + 1) % kThreads + kThreads) % kThreads); i < m; i += kThreads) a[i] /= v0;
-    if (own_k) a[k] = alpha;
-    if (tid == 0) tau[k] = tk;
-    // s_j = tau_k (c_j[k] + sum_{i > k} v[i] c_j[i]) for the later columns
-    for (int j = k + 1; j < r; ++j) {
-      const double* c = A + (int64_t)j * m;
-      double s = own_k ? c[k] : 0.0;
-      for (int64_t i = k + 1 + ((tid - (k + 1) % kThreads + kThreads) % kThreads); i < m; i += kThreads)
-        s += a[i] * c[i];
-      s = wave_sum(s);
-      if (lane == 0) sred[wave][j] = s;
-    }
-    __syncthreads();
-    for (int j = k + 1; j < r; ++j) {
-      double s = 0;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) s += sred[w][j];
-      s *= tk;
-      double* c = A + (int64_t)j * m;
-      if (own_k) c[k] -= s;
-      for (int64_t i = k + 1 + ((tid - (k + 1) % kThreads + kThreads) % kThreads); i < m; i += kThreads)
-        c[i] -= s * a[i];
-    }
-    __syncthreads();
-  }
-}
-
-// Z := H_0 H_1 ... H_{r-1} Z for Z (m x k, column-major), the reflectors of
-// qr_inplace in A and tau.
-__device__ void apply_q(const double* A, int64_t m, int r, const double* tau, double* Z, int k,
-                        double (*sred)[HM_CONSTRUCT_MAX_RANK]) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = r - 1; j >= 0; --j) {
-    const double tj = tau[j];
-    if (tj == 0) continue;
-    const double* v = A + (int64_t)j * m;
-    const bool own_j = (j % kThreads) == tid;
-    const int64_t i0 = j + 1 + ((tid - (j + 1) % kThreads + kThreads) % kThreads);
-    for (int c = 0; c < k; ++c) {
-      const double* z = Z + (int64_t)c * m;
-      double s = own_j ? z[j] : 0.0;
-      for (int64_t i = i0; i < m; i += kThreads) s += v[i] * z[i];
-      s = wave_sum(s);
-      if (lane == 0) sred[wave][c] = s;
-    }
-    __syncthreads();
-    for (int c = 0; c < k; ++c) {
-      double s = 0;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) s += sred[w][c];
-      s *= tj;
-      double* z = Z + (int64_t)c * m;
-      if (own_j) z[j] -= s;
-      for (int64_t i = i0; i < m; i += kThreads) z[i] -= s * v[i];
-    }
-    __syncthreads();
-  }
-}
-
 // Algorithm 1 on the ACA factors of one leaf whose ACA rank r lies in
 // (rlo, rhi] (the other leaves of the launch return at once).  LDS
 // (dynamic): the r x r matrix being orthogonalized (B, then U_s diag(S)) and
@@ -312,120 +214,21 @@ __global__ __launch_bounds__(kThreads) void k_recompress(const hm_cblock* __rest
                                                           const int32_t* __restrict__ aca_rank,
                                                           int32_t* __restrict__ rank) {
   extern __shared__ double dyn[];
-  __shared__ double sred[kWaves][HM_CONSTRUCT_MAX_RANK];
-  __shared__ double sv[kWaves];
-  __shared__ double tauU[HM_CONSTRUCT_MAX_RANK], tauV[HM_CONSTRUCT_MAX_RANK];
-  __shared__ double nrm[HM_CONSTRUCT_MAX_RANK], S[HM_CONSTRUCT_MAX_RANK];
-  __shared__ int ord[HM_CONSTRUCT_MAX_RANK];
-  __shared__ int keep;
+  __shared__ dense::TruncShared sh;
   const int64_t b = blockIdx.x;
   const int r = aca_rank[b];
   if (r <= rlo || r > rhi) return;                   // uniform: the whole workgroup
   const hm_cblock B = blocks[b];
-  const int tid = threadIdx.x, lane = tid & 63;
   const int64_t m = B.m, n = B.n;
   const int cap = B.cap;
   double* U = scr + B.scr;
   double* V = U + m * cap;
-  double* Am = dyn;
-  double* Vs = dyn + r * r;
-  qr_inplace(U, m, r, tauU, sred, sv);
-  qr_inplace(V, n, r, tauV, sred, sv);
-  // B = R_U R_V^T: B(i, j) = sum_{l >= max(i, j)} R_U(i, l) R_V(j, l)
-  for (int e = tid; e < r * r; e += kThreads) {
-    const int i = e % r, j = e / r;
-    double s = 0;
-    for (int l = std::max(i, j); l < r; ++l) s += U[(int64_t)l * m + i] * V[(int64_t)l * n + j];
-    Am[e] = s;
-    Vs[e] = i == j ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  // one-sided Jacobi on the columns of Am (first wave), cyclic pairs
-  if (tid < 64) {
-    for (int sweep = 0; sweep < 60; ++sweep) {
-      double off = 0;
-      for (int p = 0; p < r - 1; ++p)
-        for (int q = p + 1; q < r; ++q) {
-          double* ap = Am + p * r;
-          double* aq = Am + q * r;
-          double al = 0, be = 0, ga = 0;
-          for (int i = lane; i < r; i += 64) {
-            al += ap[i] * ap[i];
-            be += aq[i] * aq[i];
-            ga += ap[i] * aq[i];
-          }
-          al = wave_sum(al);
-          be = wave_sum(be);
-          ga = wave_sum(ga);
-          if (ga == 0) continue;
-          const double rel = fabs(ga) / sqrt(al * be);
-          if (!(rel > 1e-15)) continue;
-          off = std::max(off, rel);
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          double* vp = Vs + p * r;
-          double* vq = Vs + q * r;
-          for (int i = lane; i < r; i += 64) {
-            const double x = ap[i], y = aq[i];
-            ap[i] = c * x - s * y;
-            aq[i] = s * x + c * y;
-            const double u = vp[i], w = vq[i];
-            vp[i] = c * u - s * w;
-            vq[i] = s * u + c * w;
-          }
-        }
-      if (off <= 1e-15) break;
-    }
-  }
-  __syncthreads();
-  // singular values: column norms, sorted descending (stable)
-  for (int j = tid; j < r; j += kThreads) {
-    double s = 0;
-    for (int i = 0; i < r; ++i) s += Am[j * r + i] * Am[j * r + i];
-    nrm[j] = sqrt(s);
-  }
-  __syncthreads();
-  for (int j = tid; j < r; j += kThreads) {
-    int pos = 0;
-    for (int l = 0; l < r; ++l) pos += nrm[l] > nrm[j] || (nrm[l] == nrm[j] && l < j);
-    ord[pos] = j;
-    S[pos] = nrm[j];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double tot = 0;
-    for (int j = 0; j < r; ++j) tot += S[j] * S[j];
-    int k = r;
-    double tail = 0;
-    while (k > 0) {
-      const double t2 = tail + S[k - 1] * S[k - 1];
-      if (sqrt(t2) <= eps * sqrt(tot)) { tail = t2; --k; } else break;
-    }
-    keep = k;
-  }
-  __syncthreads();
-  const int k = keep;
   double* W = out + B.out;
   double* X = W + m * cap;
   double* sg = X + n * cap;
-  // W = Q_U [U_s(:, 1:k); 0], X = Q_V [V_s(:, 1:k); 0]
-  for (int c = 0; c < k; ++c) {
-    const int j = ord[c];
-    const double inv = S[c] > 0 ? 1.0 / S[c] : 0.0;
-    for (int64_t i = tid; i < m; i += kThreads) W[(int64_t)c * m + i] = i < r ? (S[c] > 0 ? Am[j * r + i] * inv : 0.0) : 0.0;
-    for (int64_t i = tid; i < n; i += kThreads) X[(int64_t)c * n + i] = i < r ? Vs[j * r + i] : 0.0;
-  }
-  __syncthreads();
-  apply_q(U, m, r, tauU, W, k, sred);
-  apply_q(V, n, r, tauV, X, k, sred);
-  for (int c = 0; c < k; ++c) {
-    if (tid == 0) sg[c] = S[c];
-    if (!keep_sigma)
-      for (int64_t i = tid; i < m; i += kThreads) W[(int64_t)c * m + i] *= S[c];
-  }
-  (void)lane;
-  if (tid == 0) rank[b] = k;
+  const int k = dense::truncate_core(U, m, V, n, r, eps, dyn, 2 * (int64_t)rhi * rhi, nullptr, sh, W, X, !keep_sigma,
+                                     sg);
+  if (threadIdx.x == 0) rank[b] = k;
 }
 
 // Packs the result of every leaf densely: leaf b's data at packed + off[b]

@@ -1,0 +1,517 @@
+// Device building blocks of the FP64 dense linear algebra that the GPU
+// construction (hm_construct.hip) and the H-LU (hm_lu.hip) share: workgroup
+// reductions, Householder QR in place, the application of its reflectors,
+// and the truncation core of Algorithm 1 (Sec. 2.2) on two factors whose
+// small SVD runs in LDS.
+//
+// Every routine is called by all kWThreads threads of one workgroup; every
+// reduction has a fixed order and broadcasts its result, so control flow
+// that depends on a reduced value is uniform across the workgroup.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace hm {
+namespace dense {
+
+constexpr int kWThreads = 256;
+constexpr int kWWaves = kWThreads / 64;
+constexpr int kMaxR = 256;    // widest factor pair the shared arrays hold
+
+// Sum over the wave, the same value in every lane (lane 0's result).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return __shfl(v, 0, 64);
+}
+
+// Sum over the workgroup, the same value in every thread.  sred: kWWaves
+// doubles of LDS; the call synchronizes twice.
+__device__ __forceinline__ double block_sum(double v, double* sred) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sred[wave] = v;
+  __syncthreads();
+  double s = 0;
+#pragma unroll
+  for (int w = 0; w < kWWaves; ++w) s += sred[w];
+  __syncthreads();
+  return s;
+}
+
+constexpr int kJB = 8;        // columns whose dot products one pass over the rows forms
+
+// Householder QR of A (m x r, column-major, m >= r) in place: R in the upper
+// triangle, the reflectors v_j (v_j[j] = 1 implied) below the diagonal, and
+// tau_j in tau (LDS), H_j = I - tau_j v_j v_j^T.  Thread t owns the rows
+// i = t (mod kWThreads).  The dot products of the reflector with the later
+// columns are formed kJB columns per pass over the rows, so that the loads
+// of several columns are in flight together.  sred: kWWaves x kMaxR doubles
+// of LDS.
+__device__ inline void qr_inplace(double* A, int64_t m, int r, double* tau, double (*sred)[kMaxR], double* sv) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k = 0; k < r; ++k) {
+    double* a = A + (int64_t)k * m;
+    const double akk = a[k];
+    double p = 0;
+    for (int64_t i = k + tid; i < m; i += kWThreads) p += a[i] * a[i];
+    const double nrm = sqrt(block_sum(p, sv));
+    if (nrm == 0) {
+      if (tid == 0) tau[k] = 0;
+      __syncthreads();
+      continue;
+    }
+    const double alpha = akk > 0 ? -nrm : nrm;
+    const double v0 = akk - alpha;
+    const double tk = -v0 / alpha;
+    const bool own_k = (k % kWThreads) == tid;
+    const int64_t i1 = k + 1 + ((tid - (k + 1) % kWThreads + kWThreads) % kWThreads);
+    for (int64_t i = i1; i < m; i += kWThreads) a[i] /= v0;
+    if (own_k) a[k] = alpha;
+    if (tid == 0) tau[k] = tk;
+    // s_j = tau_k (c_j[k] + sum_{i > k} v[i] c_j[i]) for the later columns
+    for (int j0 = k + 1; j0 < r; j0 += kJB) {
+      double s[kJB];
+#pragma unroll
+      for (int u = 0; u < kJB; ++u) s[u] = (own_k && j0 + u < r) ? A[(int64_t)(j0 + u) * m + k] : 0.0;
+      for (int64_t i = i1; i < m; i += kWThreads) {
+        const double ai = a[i];
+#pragma unroll
+        for (int u = 0; u < kJB; ++u)
+          if (j0 + u < r) s[u] += ai * A[(int64_t)(j0 + u) * m + i];
+      }
+#pragma unroll
+      for (int u = 0; u < kJB; ++u) {
+        const double t = wave_sum(s[u]);
+        if (lane == 0 && j0 + u < r) sred[wave][j0 + u] = t;
+      }
+    }
+    __syncthreads();
+    for (int j0 = k + 1; j0 < r; j0 += kJB) {
+      double f[kJB];
+#pragma unroll
+      for (int u = 0; u < kJB; ++u) {
+        double t = 0;
+#pragma unroll
+        for (int w = 0; w < kWWaves; ++w) t += j0 + u < r ? sred[w][j0 + u] : 0.0;
+        f[u] = t * tk;
+      }
+      if (own_k) {
+#pragma unroll
+        for (int u = 0; u < kJB; ++u)
+          if (j0 + u < r) A[(int64_t)(j0 + u) * m + k] -= f[u];
+      }
+      for (int64_t i = i1; i < m; i += kWThreads) {
+        const double ai = a[i];
+#pragma unroll
+        for (int u = 0; u < kJB; ++u)
+          if (j0 + u < r) A[(int64_t)(j0 + u) * m + i] -= f[u] * ai;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Z := H_0 H_1 ... H_{r-1} Z for Z (m x k, column-major, leading dimension
+// m), the reflectors of qr_inplace in A and tau; kJB columns of Z per pass.
+__device__ inline void apply_q(const double* A, int64_t m, int r, const double* tau, double* Z, int k,
+                               double (*sred)[kMaxR]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = r - 1; j >= 0; --j) {
+    const double tj = tau[j];
+    if (tj == 0) continue;
+    const double* v = A + (int64_t)j * m;
+    const bool own_j = (j % kWThreads) == tid;
+    const int64_t i0 = j + 1 + ((tid - (j + 1) % kWThreads + kWThreads) % kWThreads);
+    for (int c0 = 0; c0 < k; c0 += kJB) {
+      double s[kJB];
+#pragma unroll
+      for (int u = 0; u < kJB; ++u) s[u] = (own_j && c0 + u < k) ? Z[(int64_t)(c0 + u) * m + j] : 0.0;
+      for (int64_t i = i0; i < m; i += kWThreads) {
+        const double vi = v[i];
+#pragma unroll
+        for (int u = 0; u < kJB; ++u)
+          if (c0 + u < k) s[u] += vi * Z[(int64_t)(c0 + u) * m + i];
+      }
+#pragma unroll
+      for (int u = 0; u < kJB; ++u) {
+        const double t = wave_sum(s[u]);
+        if (lane == 0 && c0 + u < k) sred[wave][c0 + u] = t;
+      }
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < k; c0 += kJB) {
+      double f[kJB];
+#pragma unroll
+      for (int u = 0; u < kJB; ++u) {
+        double t = 0;
+#pragma unroll
+        for (int w = 0; w < kWWaves; ++w) t += c0 + u < k ? sred[w][c0 + u] : 0.0;
+        f[u] = t * tj;
+      }
+      if (own_j) {
+#pragma unroll
+        for (int u = 0; u < kJB; ++u)
+          if (c0 + u < k) Z[(int64_t)(c0 + u) * m + j] -= f[u];
+      }
+      for (int64_t i = i0; i < m; i += kWThreads) {
+        const double vi = v[i];
+#pragma unroll
+        for (int u = 0; u < kJB; ++u)
+          if (c0 + u < k) Z[(int64_t)(c0 + u) * m + i] -= f[u] * vi;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Householder QR of A (m x r, column-major, leading dimension lda, m >= r,
+// r <= kWThreads) in place, as qr_inplace, with one thread per column: the
+// owner of column k forms the reflector, then every later column's thread
+// applies it over the rows by itself (no cross-thread sums).  Meant for A in
+// LDS, where the reflector's entries are broadcast reads.
+__device__ inline void qr_cols(double* A, int lda, int m, int r, double* tau) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < r; ++k) {
+    double* a = A + k * lda;
+    if (tid == k) {
+      double p = 0;
+      for (int i = k; i < m; ++i) p += a[i] * a[i];
+      const double nrm = sqrt(p);
+      if (nrm == 0) {
+        tau[k] = 0;
+      } else {
+        const double akk = a[k];
+        const double alpha = akk > 0 ? -nrm : nrm;
+        const double v0 = akk - alpha;
+        const double iv = 1.0 / v0;
+        for (int i = k + 1; i < m; ++i) a[i] *= iv;
+        a[k] = alpha;
+        tau[k] = -v0 / alpha;
+      }
+    }
+    __syncthreads();
+    const double tk = tau[k];
+    if (tk != 0 && tid > k && tid < r) {
+      double* c = A + tid * lda;
+      double s = c[k];
+      for (int i = k + 1; i < m; ++i) s += a[i] * c[i];
+      s *= tk;
+      c[k] -= s;
+      for (int i = k + 1; i < m; ++i) c[i] -= s * a[i];
+    }
+    __syncthreads();
+  }
+}
+
+// Z := H_0 ... H_{r-1} Z (Z m x k, leading dimension ldz, k <= kWThreads)
+// with the reflectors of qr_cols / qr_inplace in A (leading dimension lda),
+// one thread per column of Z.
+__device__ inline void apply_q_cols(const double* A, int lda, int m, int r, const double* tau, double* Z, int ldz,
+                                    int k) {
+  const int tid = threadIdx.x;
+  if (tid < k) {
+    double* z = Z + tid * ldz;
+    for (int j = r - 1; j >= 0; --j) {
+      const double tj = tau[j];
+      if (tj == 0) continue;
+      const double* v = A + j * lda;
+      double s = z[j];
+      for (int i = j + 1; i < m; ++i) s += v[i] * z[i];
+      s *= tj;
+      z[j] -= s;
+      for (int i = j + 1; i < m; ++i) z[i] -= s * v[i];
+    }
+  }
+  __syncthreads();
+}
+
+// Copies a (rows x cols) between column-major arrays, workgroup-wide.
+__device__ inline void copy_mat(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols) {
+  for (int64_t e = threadIdx.x; e < rows * cols; e += kWThreads) dst[(e / rows) * ldd + e % rows] = src[(e / rows) * lds + e % rows];
+  __syncthreads();
+}
+
+// LDS the truncation core needs besides its two dynamic r x r matrices.
+struct TruncShared {
+  double sred[kWWaves][kMaxR];
+  double sv[kWWaves];
+  double tauU[kMaxR], tauV[kMaxR];
+  double nrm[kMaxR], S[kMaxR];
+  double offg[kWThreads / 16];
+  double tauB[kMaxR];
+  int ord[kMaxR];
+  int perm[kMaxR];
+  int keep;
+  int more;
+  int piv;
+};
+
+// Sum over the 16 lanes of a lane group (the group's lanes get the total).
+__device__ __forceinline__ double group16_sum(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
+// Algorithm 1 on U (m x r) and V (n x r), both column-major with leading
+// dimensions m and n, m >= r, n >= r, r <= kMaxR; U and V are overwritten
+// by their QR factors.  lds: lds_doubles doubles of LDS, which hold a
+// factor for its QR (one thread per column) when it fits, then the two
+// r x r matrices of the SVD when they fit (else gscr, 2 r^2 doubles of
+// global memory, holds them), then reflectors and result for the
+// application of Q.  W must hold m x r doubles and X n x r (they also serve
+// as scratch).  Householder QR
+// of U and V, B = R_U R_V^T, the SVD of B by a QR with column pivoting
+// (B P = Q_B R) and one-sided Jacobi on R^T (round-robin ordering: in each
+// round 16-lane groups rotate disjoint column pairs in parallel; the
+// pivoting grades R, so that few sweeps are needed), singular values
+// sorted descending (stable), k the smallest rank whose Frobenius tail is
+// <= eps times the whole; then W = Q_U U_s(:, 1:k) (times diag(S) when
+// fold), X = Q_V V_s(:, 1:k) written to W (m x k, leading dimension m) and
+// X (n x k, leading dimension n), S(1:k) to sg when sg is not null.
+// Returns k (the same in every thread).
+__device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, int r, double eps, double* lds,
+                                    int64_t lds_doubles, double* gscr, TruncShared& sh, double* W, double* X,
+                                    bool fold, double* sg) {
+  const int tid = threadIdx.x;
+  // QR of U and of V: in LDS, one thread per column, when the factor fits
+  auto qr = [&](double* F, int64_t rows, double* tau) {
+    const int ld = (int)(rows | 1);
+    if ((int64_t)ld * r <= lds_doubles && rows <= 4096) {
+      copy_mat(F, rows, lds, ld, rows, r);
+      qr_cols(lds, ld, (int)rows, r, tau);
+      copy_mat(lds, ld, F, rows, rows, r);
+    } else {
+      qr_inplace(F, rows, r, tau, sh.sred, sh.sv);
+    }
+  };
+  qr(U, m, sh.tauU);
+  qr(V, n, sh.tauV);
+  // the two r x r matrices of the SVD: in LDS when they fit, else in global scratch
+  double* Am = 2 * (int64_t)r * r <= lds_doubles ? lds : gscr;
+  double* Vs = Am + (int64_t)r * r;
+  // R_U -> Am, R_V -> Vs (upper triangles), then B = R_U R_V^T into W (r x r)
+  for (int e = tid; e < r * r; e += kWThreads) {
+    const int i = e % r, l = e / r;
+    Am[e] = i <= l ? U[(int64_t)l * m + i] : 0.0;
+    Vs[e] = i <= l ? V[(int64_t)l * n + i] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < r * r; e += kWThreads) {
+    const int i = e % r, j = e / r;
+    double s = 0;
+    for (int l = std::max(i, j); l < r; ++l) s += Am[l * r + i] * Vs[l * r + j];
+    W[e] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < r * r; e += kWThreads) Am[e] = W[e];
+  for (int j = tid; j < r; j += kWThreads) sh.perm[j] = j;
+  __syncthreads();
+  // QR with column pivoting of B (B P = Q_B R; in place in Am, one thread
+  // per column; the largest remaining column first, the lowest index on
+  // ties).  One-sided Jacobi on R^T then converges in a few sweeps, R being
+  // graded.
+  for (int k = 0; k < r; ++k) {
+    if (tid >= k && tid < r) {
+      double s2 = 0;
+      for (int i = k; i < r; ++i) s2 += Am[tid * r + i] * Am[tid * r + i];
+      sh.nrm[tid] = s2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int jb = k;
+      for (int j = k + 1; j < r; ++j)
+        if (sh.nrm[j] > sh.nrm[jb]) jb = j;
+      sh.piv = jb;
+      const int t = sh.perm[k];
+      sh.perm[k] = sh.perm[jb];
+      sh.perm[jb] = t;
+    }
+    __syncthreads();
+    const int jb = sh.piv;
+    if (jb != k)
+      for (int i = tid; i < r; i += kWThreads) {
+        const double t = Am[k * r + i];
+        Am[k * r + i] = Am[jb * r + i];
+        Am[jb * r + i] = t;
+      }
+    __syncthreads();
+    double* a = Am + k * r;
+    if (tid == k) {
+      const double nrm = sqrt(sh.nrm[jb]);
+      if (nrm == 0) {
+        sh.tauB[k] = 0;
+      } else {
+        const double akk = a[k];
+        const double alpha = akk > 0 ? -nrm : nrm;
+        const double v0 = akk - alpha;
+        const double iv = 1.0 / v0;
+        for (int i = k + 1; i < r; ++i) a[i] *= iv;
+        a[k] = alpha;
+        sh.tauB[k] = -v0 / alpha;
+      }
+    }
+    __syncthreads();
+    const double tk = sh.tauB[k];
+    if (tk != 0 && tid > k && tid < r) {
+      double* c = Am + tid * r;
+      double s = c[k];
+      for (int i = k + 1; i < r; ++i) s += a[i] * c[i];
+      s *= tk;
+      c[k] -= s;
+      for (int i = k + 1; i < r; ++i) c[i] -= s * a[i];
+    }
+    __syncthreads();
+  }
+  // reflectors of Q_B (and R) to X (r x r, leading dimension r), then
+  // Am := R^T (lower triangular), Vs := I
+  for (int e = tid; e < r * r; e += kWThreads) X[e] = Am[e];
+  __syncthreads();
+  for (int e = tid; e < r * r; e += kWThreads) {
+    const int i = e % r, j = e / r;                  // Am(i, j) = R(j, i)
+    Am[e] = j <= i ? X[i * r + j] : 0.0;
+    Vs[e] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // one-sided Jacobi on the columns of Am = R^T, round-robin pairs (R = r
+  // rounded up to even players; player R - 1 stays, the others rotate; a
+  // pair with the player r, when r is odd, is skipped); afterwards
+  // Am = R^T Vs has orthogonal columns
+  const int R = r + (r & 1);
+  const int grp = tid >> 4, gl = tid & 15, ngrp = kWThreads / 16;
+  // columns below 1e-16 |B|_F carry no singular value the truncation can
+  // see and only rounding noise: pairs with such a column are not rotated
+  double fro2 = 0;
+  for (int e = tid; e < r * r; e += kWThreads) fro2 += Am[e] * Am[e];
+  const double tiny = 1e-32 * block_sum(fro2, sh.sv);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0;
+    for (int t = 0; t + 1 < R; ++t) {
+      for (int pi = grp; pi < R / 2; pi += ngrp) {
+        int p, q;
+        if (pi == 0) {
+          p = t;
+          q = R - 1;
+        } else {
+          p = (t + pi) % (R - 1);
+          q = (t - pi + (R - 1)) % (R - 1);
+        }
+        if (p > q) { const int x = p; p = q; q = x; }
+        if (q >= r) continue;                        // the same for the whole group
+        double* ap = Am + p * r;
+        double* aq = Am + q * r;
+        double al = 0, be = 0, ga = 0;
+        for (int i = gl; i < r; i += 16) {
+          al += ap[i] * ap[i];
+          be += aq[i] * aq[i];
+          ga += ap[i] * aq[i];
+        }
+        al = group16_sum(al);
+        be = group16_sum(be);
+        ga = group16_sum(ga);
+        if (ga == 0 || al <= tiny || be <= tiny) continue;
+        const double rel = fabs(ga) / sqrt(al * be);
+        if (!(rel > 1e-15)) continue;
+        off = std::max(off, rel);
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+        double* vp = Vs + p * r;
+        double* vq = Vs + q * r;
+        for (int i = gl; i < r; i += 16) {
+          const double x = ap[i], y = aq[i];
+          ap[i] = c * x - sn * y;
+          aq[i] = sn * x + c * y;
+          const double u = vp[i], w = vq[i];
+          vp[i] = c * u - sn * w;
+          vq[i] = sn * u + c * w;
+        }
+      }
+      __syncthreads();
+    }
+    if (gl == 0) sh.offg[grp] = off;
+    __syncthreads();
+    if (tid == 0) {
+      double o = 0;
+      for (int g = 0; g < ngrp; ++g) o = std::max(o, sh.offg[g]);
+      sh.more = o > 1e-15;
+    }
+    __syncthreads();
+    if (!sh.more) break;
+    __syncthreads();
+  }
+  // singular values: column norms, sorted descending (stable)
+  for (int j = tid; j < r; j += kWThreads) {
+    double s2 = 0;
+    for (int i = 0; i < r; ++i) s2 += Am[j * r + i] * Am[j * r + i];
+    sh.nrm[j] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int j = tid; j < r; j += kWThreads) {
+    int pos = 0;
+    for (int l = 0; l < r; ++l) pos += sh.nrm[l] > sh.nrm[j] || (sh.nrm[l] == sh.nrm[j] && l < j);
+    sh.ord[pos] = j;
+    sh.S[pos] = sh.nrm[j];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0;
+    for (int j = 0; j < r; ++j) tot += sh.S[j] * sh.S[j];
+    int k = r;
+    double tail = 0;
+    while (k > 0) {
+      const double t2 = tail + sh.S[k - 1] * sh.S[k - 1];
+      if (sqrt(t2) <= eps * sqrt(tot)) { tail = t2; --k; } else break;
+    }
+    sh.keep = k;
+  }
+  __syncthreads();
+  const int k = sh.keep;
+  // B = (Q_B Vs) diag(S) (P Am / S)^T: the left singular vectors are Q_B
+  // applied to the columns of Vs (reflectors in X), the right ones the
+  // normalized columns of Am with their rows permuted back by P
+  apply_q_cols(X, r, r, r, sh.tauB, Vs, r, r);
+  // W = Q_U [left(:, 1:k); 0], X = Q_V [right(:, 1:k); 0]
+  for (int c = 0; c < k; ++c) {
+    const int j = sh.ord[c];
+    for (int64_t i = tid; i < m; i += kWThreads) W[(int64_t)c * m + i] = i < r ? Vs[j * r + i] : 0.0;
+  }
+  __syncthreads();                                  // the reflectors in X are read no more
+  for (int c = 0; c < k; ++c) {
+    const int j = sh.ord[c];
+    const double inv = sh.S[c] > 0 ? 1.0 / sh.S[c] : 0.0;
+    for (int64_t i = tid; i < n; i += kWThreads) X[(int64_t)c * n + i] = 0.0;
+    __syncthreads();
+    for (int i = tid; i < r; i += kWThreads) X[(int64_t)c * n + sh.perm[i]] = Am[j * r + i] * inv;
+  }
+  __syncthreads();
+  // W := Q_U W, X := Q_V X: reflectors and result in LDS, one thread per column, when they fit
+  auto applyq = [&](const double* F, int64_t rows, const double* tau, double* Z) {
+    const int ld = (int)(rows | 1);
+    if ((int64_t)ld * (r + k) <= lds_doubles && rows <= 4096) {
+      copy_mat(F, rows, lds, ld, rows, r);
+      copy_mat(Z, rows, lds + (int64_t)ld * r, ld, rows, k);
+      apply_q_cols(lds, ld, (int)rows, r, tau, lds + (int64_t)ld * r, ld, k);
+      copy_mat(lds + (int64_t)ld * r, ld, Z, rows, rows, k);
+    } else {
+      apply_q(F, rows, r, tau, Z, k, sh.sred);
+    }
+  };
+  applyq(U, m, sh.tauU, W);
+  applyq(V, n, sh.tauV, X);
+  for (int c = 0; c < k; ++c) {
+    if (sg && tid == 0) sg[c] = sh.S[c];
+    if (fold)
+      for (int64_t i = tid; i < m; i += kWThreads) W[(int64_t)c * m + i] *= sh.S[c];
+  }
+  __syncthreads();
+  return k;
+}
+
+}  // namespace dense
+}  // namespace hm

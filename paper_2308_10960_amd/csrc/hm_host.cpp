@@ -271,11 +271,11 @@ static void split_intervals(const std::vector<int64_t>& bp, int cap, std::vector
 // groups contiguously, so a tile row is one contiguous block.
 // Cuts a column panel's group sequence (its runs, in order) into tiles of
 // at most kTileGroups groups and at most 4 runs (the tile descriptor's
-// limit).  A tile's low-byte plane has one entry of tile_lo[t] bytes (the
+// limit); with one_format, every run starts a tile of its own.  A tile's low-byte plane has one entry of tile_lo[t] bytes (the
 // largest lo_bytes of its runs; 0: none) per row and group; groups of a
 // format without one leave theirs unused.  Fills tile_g0 / tile_off /
 // tile_lo.
-static void cut_tiles(ColPanelHost& Cp, int32_t tile_groups) {
+static void cut_tiles(ColPanelHost& Cp, int32_t tile_groups, bool one_format) {
   Cp.tile_g0.assign(1, 0);
   Cp.tile_off.assign(1, 0);
   Cp.tile_lo.clear();
@@ -288,6 +288,7 @@ static void cut_tiles(ColPanelHost& Cp, int32_t tile_groups) {
   };
   for (auto& S : Cp.secs) {
     const int32_t n = S.ld / group_width(S.dtype);
+    if (one_format && open > 0) close();
     for (int32_t g = 0; g < n;) {
       if (runs == 4) close();
       const int32_t take = std::min(tile_groups - open, n - g);
@@ -331,7 +332,7 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
   if (n_rows <= 0 || n_cols <= 0 || n_rows > INT32_MAX / 4 || n_cols > INT32_MAX / 4)
     return fail(HM_EINVAL, "bad matrix size %lld x %lld", (long long)n_rows, (long long)n_cols);
   if (nb <= 0 || !blocks) return fail(HM_EINVAL, "empty block table");
-  hm_plan_opts opts{HM_F64, HM_F64, 1, 0, nullptr, 0, 0};
+  hm_plan_opts opts{HM_F64, HM_F64, 1, 0, nullptr, 0, 0, 0};
   if (o) opts = *o;
   if (opts.acc_dtype != HM_F64 && opts.acc_dtype != HM_F32)
     return fail(HM_EDTYPE, "acc_dtype must be HM_F64 or HM_F32");
@@ -363,6 +364,8 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
     return fail(HM_EINVAL, "tile_groups %d outside [8, %d]", P->tile_groups, kTileGroups);
   P->launch.chunk = P->chunk_rows;
   P->launch.tile = P->tile_groups;
+  if (opts.tile_mix < 0 || opts.tile_mix > 2) return fail(HM_EINVAL, "tile_mix %d outside [0, 2]", opts.tile_mix);
+  if (opts.tile_mix) P->launch.tmix = opts.tile_mix - 1;
 
   // ---- elementary row intervals and the tiling proof
   std::vector<int64_t> rbp;
@@ -633,7 +636,7 @@ hm_status build_plan(int64_t n_rows, int64_t n_cols, const hm_block_desc* blocks
       Cp.ncols += S.ld;
       Cp.secs.push_back(S);
     }
-    cut_tiles(Cp, P->tile_groups);
+    cut_tiles(Cp, P->tile_groups, P->launch.tmix == 0);
   }
 
   return layout_store(P.release(), out);
@@ -665,6 +668,7 @@ static bool parse_launch(const char* text, LaunchParams& lp) {
     else if (k == "chunk" && v >= kMaxTileRows && v <= kSegRows) r.chunk = (int)v;
     else if (k == "tile" && v >= 8 && v <= kTileGroups) r.tile = (int)v;
     else if (k == "colb" && v >= 0 && v <= 3) r.colb = (int)v;
+    else if (k == "tmix" && (v == 0 || v == 1)) r.tmix = (int)v;
     else return false;
     i = j;
   }
@@ -1692,17 +1696,17 @@ hm_status hm_matrix_set_launch(hm_matrix* A, const char* params) {
   if (!A || !params) return fail(HM_EINVAL, "NULL argument");
   LaunchParams lp = A->launch;
   if (!parse_launch(params, lp)) return fail(HM_EINVAL, "bad launch parameters '%s'", params);
-  if (lp.chunk != A->launch.chunk || lp.tile != A->launch.tile)
-    return fail(HM_EINVAL, "the tile shape (chunk, tile) is the plan's; set it when the plan is built");
+  if (lp.chunk != A->launch.chunk || lp.tile != A->launch.tile || lp.tmix != A->launch.tmix)
+    return fail(HM_EINVAL, "the tile shape (chunk, tile, tmix) is the plan's; set it when the plan is built");
   A->launch = lp;
   return ok();
 }
 
 hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len) {
   if (!A || !buf || len == 0) return fail(HM_EINVAL, "NULL argument");
-  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d persist=%d chunk=%d tile=%d colb=%d", A->launch.schedule,
-                A->launch.row_unroll, A->launch.order, A->launch.persist, A->launch.chunk, A->launch.tile,
-                A->launch.colb);
+  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d persist=%d chunk=%d tile=%d colb=%d tmix=%d",
+                A->launch.schedule, A->launch.row_unroll, A->launch.order, A->launch.persist, A->launch.chunk,
+                A->launch.tile, A->launch.colb, A->launch.tmix);
   return ok();
 }
 

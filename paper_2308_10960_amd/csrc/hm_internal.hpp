@@ -26,6 +26,9 @@ namespace hm {
 //  colb: batched FP32 column tiles as 8-byte slots, 32 per wave (0: 4 row
 //           steps in flight, 2: 8), or as 16-byte groups, 32 per wave (1: 4
 //           steps, 3: 8).
+//  tmix: 0: every column tile holds one storage format (a chunk's runs of
+//           different formats start new tiles); 1: a tile may hold runs of
+//           up to four formats (part of the plan's tile shape).
 struct LaunchParams {
   int schedule = 0;
   int row_unroll = 8;
@@ -34,6 +37,7 @@ struct LaunchParams {
   int chunk = 0;
   int tile = 0;
   int colb = 0;
+  int tmix = 0;
 };
 
 struct BlockInfo {

@@ -196,12 +196,16 @@ struct ColArgs {
   int64_t n_tiles;
 };
 
-// One workgroup streams one column tile.  Lane l of every wave owns the
-// columns of group l; the tile's rows go to the four waves in interleaved
-// batches of 8 (wave w takes rows 32 j + 8 w + [0, 8) for j = 0, 1, ...),
-// and the loads of a wave's next batch are in flight while it computes the
-// current one.  x of the tile's rows is staged in LDS once (xs) and read
-// as a broadcast.  The four waves' sums are added in a fixed order through
+// One workgroup streams one column tile.  A narrow tile shares each wave
+// between RS = 64 / GP rows, GP the smallest power of two >= the tile's
+// groups: lane l owns the columns of group g = l % GP in the rows of
+// sub-row q = l / GP, so that one 16-byte load per lane covers RS tile
+// rows.  The tile's rows go to the four waves in interleaved batches
+// of 8 RS (wave w takes rows RS (32 j + 8 w) + [0, 8 RS) for j = 0, 1, ...,
+// row RS (32 j + 8 w + u) + q in step u), and the loads of a wave's next
+// batch are in flight while it computes the current one.  x of the tile's
+// rows is staged in LDS once (xs).  The RS sub-rows' sums are added by a
+// butterfly across the lanes, the four waves' sums in a fixed order through
 // LDS (red: 4 x 64 x 8), and wave 0 writes each column's sum to its
 // destination (a partial, or t).  DT >= 0: every group of the tile has
 // format DT; DT < 0: the tile holds runs of several formats and each lane
@@ -211,8 +215,12 @@ struct ColArgs {
 template <typename AccT, int DT, bool DFL = false, bool AFLP = false, bool BFL = false>
 __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, AccT* red, AccT* xs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool act = lane < T.ngroups;
-  const TileGroup tg = tile_group(T, act ? lane : 0);
+  const int ng = T.ngroups;
+  const int GP = ng <= 1 ? 1 : ng <= 2 ? 2 : ng <= 4 ? 4 : ng <= 8 ? 8 : ng <= 16 ? 16 : ng <= 32 ? 32 : 64;
+  const int RS = 64 / GP;                           // rows per wave-wide step (sub-rows)
+  const int g = lane & (GP - 1), q = lane / GP;     // group and sub-row of this lane
+  const bool act = g < T.ngroups;
+  const TileGroup tg = tile_group(T, act ? g : 0);
   const int dt = DT >= 0 ? DT : tg.dtype;
   constexpr bool kAflp = DT >= 0 ? is_aflp(DT) : AFLP;
   constexpr int GW = DT >= 0 ? group_width(DT) : 8;   // columns per lane (at most)
@@ -232,27 +240,28 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
   for (int c = 0; c < 8; ++c) acc[c] = AccT(0);
   const int rstride = T.ngroups;                    // 16-byte groups per tile row
   const int nrows = T.nrows;
-  const u32x4* p = reinterpret_cast<const u32x4*>(a.store + T.data_off) + lane;
+  const u32x4* p = reinterpret_cast<const u32x4*>(a.store + T.data_off) + g;
   // low-byte plane: entries of lo_bytes(DT) bytes in a one-format tile; of
   // Lt bytes in a several-format one (read by the lanes whose format has one)
   const uint8_t* lop = a.store + T.data_off + (int64_t)16 * nrows * rstride;
   constexpr bool LOW = DFL || AFLP || BFL;         // several-format tiles: runs with low bytes
   const int Lt = DT < 0 && LOW ? tile_lo_bytes(T) : 0;
   const bool hlo = DT < 0 && LOW && lo_bytes(dt) > 0;
-  const int nb = nrows > 8 * wave ? (nrows - 8 * wave + 31) / 32 : 0;   // this wave's batches
+  const int nb = nrows > 8 * RS * wave ? (nrows - 8 * RS * wave + 32 * RS - 1) / (32 * RS) : 0;   // this wave's batches
   u32x4 rn[8];
   u32x2 ln[8];
   auto issue = [&](int j) {
-    const int r0 = 32 * j + 8 * wave;
+    const int r0 = RS * (32 * j + 8 * wave) + q;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (act && r0 + u < nrows) {
-        rn[u] = ld16(p + (size_t)(r0 + u) * rstride);
+      if (act && r0 + RS * u < nrows) {
+        const int64_t row = r0 + RS * u;
+        rn[u] = ld16(p + (size_t)row * rstride);
         if constexpr (DT >= 0) {
-          ln[u] = ld_lo<DT>(lop, (int64_t)(r0 + u) * rstride + lane);
+          ln[u] = ld_lo<DT>(lop, row * rstride + g);
         } else if constexpr (LOW) {
           if (hlo) {
-            const int64_t e = (int64_t)(r0 + u) * rstride + lane;
+            const int64_t e = row * rstride + g;
             ln[u] = Lt == 8 ? ld_lo<kDtDfl48>(lop, e) : ld_lo<kDtDfl40>(lop, e);
           }
         }
@@ -270,11 +279,11 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
       lc[u] = ln[u];
     }
     if (j + 1 < nb) issue(j + 1);
-    const int r0 = 32 * j + 8 * wave;
+    const int r0 = RS * (32 * j + 8 * wave) + q;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (r0 + u < nrows) {                         // uniform across the wave
-        const AccT xi = xs[r0 + u];
+      if (r0 + RS * u < nrows) {                    // uniform across a sub-row
+        const AccT xi = xs[r0 + RS * u];
         if (act) {
           if constexpr (DT >= 0) {
             axpy_group<AccT, DT>(rc[u], lc[u], xi, acc, sh);
@@ -304,10 +313,15 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
         }
       }
   }
+  // sum over the sub-rows: a butterfly over the lanes of one group (fixed order)
+  for (int o = GP; o < 64; o <<= 1) {
+#pragma unroll
+    for (int c = 0; c < GW; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
+  }
 #pragma unroll
   for (int c = 0; c < GW; ++c) red[(wave * 64 + lane) * GW + c] = acc[c];   // red stride GW per lane
   __syncthreads();
-  if (wave == 0 && act) {
+  if (wave == 0 && q == 0 && act) {
     const int G = group_width(dt);
     // all destinations and factors first, then the stores
     int32_t d[GW];
@@ -328,8 +342,7 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
     }
 #pragma unroll
     for (int c = 0; c < GW; ++c) {
-      AccT sum = (red[lane * GW + c] + red[(64 + lane) * GW + c]) +
-                 (red[(128 + lane) * GW + c] + red[(192 + lane) * GW + c]);
+      AccT sum = (red[g * GW + c] + red[(64 + g) * GW + c]) + (red[(128 + g) * GW + c] + red[(192 + g) * GW + c]);
       if constexpr (kAflp) sum = ldexp(sum, ks[c]);     // exact: a power of two
       if (d[c] >= 0)
         a.part[d[c]] = sum;

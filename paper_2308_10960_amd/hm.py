@@ -28,9 +28,10 @@ HM_NUM_DTYPES = 17
 HM_NOALLOC_SCRATCH_BYTES = 64 << 20      # fixed workspace of hm_mvm_noalloc (include/hm.h)
 HM_DENSE, HM_LOWRANK = 0, 1
 
+HM_ERANK = -10
 STATUS_NAMES = {0: "HM_OK", -1: "HM_EINVAL", -2: "HM_EPARTITION", -3: "HM_ESHAPE",
                 -4: "HM_EDTYPE", -5: "HM_ENOMEM", -6: "HM_EDEVICE", -7: "HM_EBUSY",
-                -8: "HM_ESTATE", -9: "HM_ETIMEOUT"}
+                -8: "HM_ESTATE", -9: "HM_ETIMEOUT", -10: "HM_ERANK"}
 
 # hm_block_desc as a numpy structured dtype (same layout as the C struct).
 BLOCK_DTYPE = np.dtype([("row_begin", "<i8"), ("row_end", "<i8"), ("col_begin", "<i8"),
@@ -42,7 +43,7 @@ BLOCK_DTYPE = np.dtype([("row_begin", "<i8"), ("row_end", "<i8"), ("col_begin", 
 class PlanOpts(C.Structure):
     _fields_ = [("acc_dtype", C.c_int32), ("vec_dtype", C.c_int32), ("max_nrhs", C.c_int32),
                 ("tune", C.c_int32), ("tune_cache", C.c_char_p), ("chunk_rows", C.c_int32),
-                ("tile_groups", C.c_int32)]
+                ("tile_groups", C.c_int32), ("tile_mix", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -101,6 +102,14 @@ PROTOTYPES = {
     "hm_construct_rank_limit": (_i32, [_P(_i32)]),
     "hm_construct": (_i32, [_vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp, _sz, _vp, _sz, _vp, _vp]),
     "hm_construct_pack": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    # include/hm_lu.h
+    "hm_lu_create": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _P(_vp)]),
+    "hm_lu_factor": (_i32, [_vp, C.c_double, _i32, _vp]),
+    "hm_lu_solve": (_i32, [_vp, _vp, _i64, _i64, _vp]),
+    "hm_lu_leaf": (_i32, [_vp, _i64, _P(_i32), _vp, _sz, _vp, _sz]),
+    "hm_lu_stats_get": (_i32, [_vp, _vp]),
+    "hm_lu_profile": (_i32, [_vp, _i32]),
+    "hm_lu_destroy": (None, [_vp]),
 }
 
 _lib = None
@@ -162,11 +171,11 @@ def make_blocks(rb, re, cb, ce, kind, rank, ngroups, group_cols, group_dtype, ha
 
 def hm_build_plan(n_rows: int, n_cols: int, blocks: np.ndarray, acc_dtype: int = HM_F64,
                   max_nrhs: int = 1, tune_cache: str | None = None, chunk_rows: int = 0,
-                  tile_groups: int = 0) -> int:
-    """chunk_rows, tile_groups: the column-tile shape (0: tune cache or built-in)."""
+                  tile_groups: int = 0, tile_mix: int = 0) -> int:
+    """chunk_rows, tile_groups, tile_mix: the column-tile shape (0: tune cache or built-in)."""
     blocks = np.ascontiguousarray(blocks, dtype=BLOCK_DTYPE)
     opts = PlanOpts(acc_dtype, acc_dtype, max_nrhs, 1 if tune_cache else 0,
-                    tune_cache.encode() if tune_cache else None, chunk_rows, tile_groups)
+                    tune_cache.encode() if tune_cache else None, chunk_rows, tile_groups, tile_mix)
     out = C.c_void_p()
     _check(lib().hm_build_plan(n_rows, n_cols, blocks.ctypes.data, blocks.shape[0],
                                C.byref(opts), C.byref(out)), "hm_build_plan")
@@ -367,6 +376,75 @@ def hm_construct(d_points, n_points: int, blocks: np.ndarray, d_desc, desc_bytes
     _check(lib().hm_construct(_ptr(d_points), n_points, blocks.ctypes.data, blocks.shape[0], _ptr(d_desc),
                               desc_bytes, C.byref(opts), _ptr(d_out), out_bytes, _ptr(d_scr), scr_bytes,
                               _ptr(d_rank), _stream(stream)), "hm_construct")
+
+
+# ------------------------------------------------------------ H-LU
+
+HM_LU_MAX_RANK, HM_LU_MAX_LEAF = 256, 64
+
+
+class LuTree(C.Structure):
+    _fields_ = [("n_clusters", C.c_int64), ("begin", C.c_void_p), ("end", C.c_void_p),
+                ("son0", C.c_void_p), ("son1", C.c_void_p)]
+
+
+class LuStats(C.Structure):
+    _fields_ = [("kernels", C.c_int64), ("truncations", C.c_int64), ("max_rank", C.c_int32),
+                ("reserved", C.c_int32), ("factor_doubles", C.c_double), ("stored_bytes", C.c_double),
+                ("arena_peak", C.c_size_t), ("trunc_ms", C.c_double), ("trunc_flops", C.c_double),
+                ("timed_truncations", C.c_int64)]
+
+
+def hm_lu_create(begin, end, son0, son1, tau, sigma, kind, rank, a_ptrs, b_ptrs, arena_bytes: int) -> int:
+    """Host arrays (numpy); a_ptrs / b_ptrs: uint64 host addresses of each leaf's factors."""
+    arrs = [np.ascontiguousarray(begin, np.int64), np.ascontiguousarray(end, np.int64),
+            np.ascontiguousarray(son0, np.int32), np.ascontiguousarray(son1, np.int32)]
+    tree = LuTree(arrs[0].shape[0], *[a.ctypes.data for a in arrs])
+    leaf = [np.ascontiguousarray(v, np.int32) for v in (tau, sigma, kind, rank)]
+    ap = np.ascontiguousarray(a_ptrs, np.uint64)
+    bp = np.ascontiguousarray(b_ptrs, np.uint64)
+    out = C.c_void_p()
+    _check(lib().hm_lu_create(C.byref(tree), leaf[0].shape[0], *[v.ctypes.data for v in leaf], ap.ctypes.data,
+                              bp.ctypes.data, arena_bytes, C.byref(out)), "hm_lu_create")
+    return out.value
+
+
+def hm_lu_factor(F: int, eps: float, dtype: int = HM_F64, stream=None) -> None:
+    _check(lib().hm_lu_factor(F, eps, dtype, _stream(stream)), "hm_lu_factor")
+
+
+def hm_lu_solve(F: int, d_x, ld: int, nrhs: int, stream=None) -> None:
+    _check(lib().hm_lu_solve(F, _ptr(d_x), ld, nrhs, _stream(stream)), "hm_lu_solve")
+
+
+def hm_lu_leaf(F: int, i: int, m: int, n: int, dense: bool):
+    """Leaf i of the factors: the dense block, or (U, V) of the low-rank one."""
+    k = C.c_int32()
+    if dense:
+        a = np.empty(m * n)
+        _check(lib().hm_lu_leaf(F, i, C.byref(k), a.ctypes.data, a.size, None, 0), "hm_lu_leaf")
+        return a.reshape(n, m).T
+    st = lib().hm_lu_leaf(F, i, C.byref(k), None, 0, None, 0)
+    if st not in (HM_OK, HM_ENOMEM):
+        _check(st, "hm_lu_leaf")
+    r = k.value
+    a, b = np.empty(max(m * r, 1)), np.empty(max(n * r, 1))
+    _check(lib().hm_lu_leaf(F, i, C.byref(k), a.ctypes.data, a.size, b.ctypes.data, b.size), "hm_lu_leaf")
+    return a[:m * r].reshape(r, m).T, b[:n * r].reshape(r, n).T
+
+
+def hm_lu_stats_get(F: int) -> dict:
+    st = LuStats()
+    _check(lib().hm_lu_stats_get(F, C.byref(st)), "hm_lu_stats_get")
+    return {k: getattr(st, k) for k, _ in LuStats._fields_ if k != "reserved"}
+
+
+def hm_lu_profile(F: int, on: bool) -> None:
+    _check(lib().hm_lu_profile(F, int(on)), "hm_lu_profile")
+
+
+def hm_lu_destroy(F: int) -> None:
+    lib().hm_lu_destroy(F)
 
 
 def hm_last_error() -> str:

@@ -30,7 +30,8 @@ def blocks_from_table(T) -> np.ndarray:
 
 class DeviceHMatrix:
     def __init__(self, T, acc_dtype: int = hm.HM_F64, max_nrhs: int = 1, device="cuda",
-                 stream=None, tune_cache: str | None = None, chunk_rows: int = 0, tile_groups: int = 0):
+                 stream=None, tune_cache: str | None = None, chunk_rows: int = 0, tile_groups: int = 0,
+                 tile_mix: int = 0):
         import torch
         self.torch = torch
         self.n_rows = int(T.n)
@@ -40,7 +41,7 @@ class DeviceHMatrix:
         self.max_nrhs = max_nrhs
         self.blocks = blocks_from_table(T)
         self.plan = hm.hm_build_plan(self.n_rows, self.n_cols, self.blocks, acc_dtype, max_nrhs,
-                                     tune_cache, chunk_rows, tile_groups)
+                                     tune_cache, chunk_rows, tile_groups, tile_mix)
         self.info = hm.hm_plan_info(self.plan)
         self.store = torch.empty(self.info["store_bytes"], dtype=torch.uint8, device=device)
         s_ptr = T.s_ptr if getattr(T, "keep_sigma", False) else None

@@ -1,6 +1,6 @@
 """Autotuner of the launch parameters (schedule, unroll depth, panel order,
 persistent grids) and of the column-tile shape (rows per column chunk,
-groups per tile).
+groups per tile, one or several storage formats per tile).
 
 For one device-resident matrix it times every launch candidate with the
 library's own HIP-event kernel timing and keeps the fastest; tile shapes
@@ -24,8 +24,10 @@ CANDIDATES = ["schedule=0 unroll=4 order=0 persist=0", "schedule=0 unroll=8 orde
 # (colb=0) or 16-byte groups (colb=1) per lane; none changes a bit
 BATCH_CANDIDATES = ["schedule=0 unroll=8 order=0 persist=0 colb=0", "schedule=0 unroll=8 order=1 persist=0 colb=0",
                     "schedule=0 unroll=8 order=0 persist=0 colb=1", "schedule=0 unroll=8 order=1 persist=0 colb=1"]
-# column-tile shapes (chunk rows, tile groups)
-SHAPE_CANDIDATES = [(512, 64), (256, 64), (128, 64), (64, 64), (512, 32), (256, 32)]
+# column-tile shapes (chunk rows, tile groups, tile_mix: 1 one format per
+# tile, 2 up to four; the same store for a matrix of one format)
+SHAPE_CANDIDATES = [(512, 64, 1), (256, 64, 1), (128, 64, 1), (64, 64, 1), (512, 32, 1), (256, 32, 1),
+                    (512, 64, 2), (256, 64, 2), (128, 64, 2)]
 
 
 def _time(D, step, reps: int) -> float:
@@ -56,21 +58,21 @@ def tune(D, step, candidates=CANDIDATES, reps: int = 10, warmup: int = 3):
 
 def tune_shape(make, step_of, launch: str, candidates=SHAPE_CANDIDATES, reps: int = 10,
                warmup: int = 3):
-    """Time every tile shape: ``make(chunk, tile)`` builds and uploads the
-    matrix with that shape, ``step_of(D)`` returns one product of it.  Each
-    runs with the launch parameters ``launch``.  Returns (best (chunk, tile),
-    {shape: ms}); the matrices are released."""
+    """Time every tile shape: ``make(chunk, tile, mix)`` builds and uploads
+    the matrix with that shape, ``step_of(D)`` returns one product of it.
+    Each runs with the launch parameters ``launch``.  Returns (best (chunk,
+    tile, mix), {shape: ms}); the matrices are released."""
     import torch
     times = {}
-    for chunk, tile in candidates:
-        D = make(chunk, tile)
+    for chunk, tile, mix in candidates:
+        D = make(chunk, tile, mix)
         try:
             hm.hm_matrix_set_launch(D.handle, launch)
             step = step_of(D)
             for _ in range(warmup):
                 step()
             torch.cuda.synchronize()
-            times[(chunk, tile)] = _time(D, step, reps)
+            times[(chunk, tile, mix)] = _time(D, step, reps)
         finally:
             D.close()
             torch.cuda.empty_cache()

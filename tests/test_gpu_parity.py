@@ -383,7 +383,7 @@ def test_launch_variants_and_tune_cache(sphere4k, tmp_path):
     out = {}
     for c in tune.CANDIDATES:
         hm.hm_matrix_set_launch(D.handle, c)
-        assert hm.hm_matrix_get_launch(D.handle) == c + " chunk=512 tile=64 colb=0"
+        assert hm.hm_matrix_get_launch(D.handle) == c + " chunk=512 tile=64 colb=0 tmix=0"
         out[c] = run(D, x)
         check_f64(out[c], ref, scale)
     # within one schedule, unroll depth, order and persistence change no bit
@@ -400,13 +400,13 @@ def test_launch_variants_and_tune_cache(sphere4k, tmp_path):
     tune.write_cache(path, key, "schedule=1 unroll=8 order=0 persist=2")
     tune.write_cache(path, "acc9-fmt0-n2^0", "schedule=0 unroll=4")
     D2 = DeviceHMatrix(H, hm.HM_F64, tune_cache=path)
-    assert hm.hm_matrix_get_launch(D2.handle) == "schedule=1 unroll=8 order=0 persist=2 chunk=512 tile=64 colb=0"
+    assert hm.hm_matrix_get_launch(D2.handle) == "schedule=1 unroll=8 order=0 persist=2 chunk=512 tile=64 colb=0 tmix=0"
     D2.close()
     # a tuned tile shape: parity, and the shape is the plan's (set_launch
     # accepts only the plan's own)
     tune.write_cache(path, key, "schedule=0 unroll=8 order=1 persist=0 chunk=128 tile=16")
     D3 = DeviceHMatrix(H, hm.HM_F64, tune_cache=path)
-    assert hm.hm_matrix_get_launch(D3.handle) == "schedule=0 unroll=8 order=1 persist=0 chunk=128 tile=16 colb=0"
+    assert hm.hm_matrix_get_launch(D3.handle) == "schedule=0 unroll=8 order=1 persist=0 chunk=128 tile=16 colb=0 tmix=0"
     assert D3.info["n_col_tiles"] > D.info["n_col_tiles"]
     check_f64(run(D3, x), ref, scale)
     hm.hm_matrix_set_launch(D3.handle, "unroll=4 chunk=128 tile=16")

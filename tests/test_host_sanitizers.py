@@ -1,7 +1,8 @@
 """The host code of libhm (plan and store layout, packing and conversion,
-request-loop bookkeeping, construction host side) built with
+request-loop bookkeeping, construction host side, H-LU validation) built with
 AddressSanitizer and UndefinedBehaviorSanitizer, running the CPU tests of
-the plan and of the construction layout in a child process: any
+the plan, the construction layout and the H-LU object's validation in a
+child process: any
 out-of-bounds access, use after free, signed overflow or misaligned access
 in those paths aborts the child and fails this test.  No GPU."""
 
@@ -23,7 +24,8 @@ def test_host_code_under_asan_ubsan():
     env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_plan_cpu.py"),
-                        os.path.join(ROOT, "tests", "test_construct_cpu.py")],
+                        os.path.join(ROOT, "tests", "test_construct_cpu.py"),
+                        os.path.join(ROOT, "tests", "test_lu_cpu.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=1200)
     out = r.stdout + r.stderr
     assert "AddressSanitizer" not in out and "runtime error" not in out, out[-4000:]

@@ -102,9 +102,9 @@ def f64_4k():
     return hmgen.build_preset("sphere4k")
 
 
-def _pack(H, acc):
+def _pack(H, acc, tile_mix=0):
     blocks = blocks_from_table(H)
-    p = hm.hm_build_plan(H.n, H.n, blocks, acc)
+    p = hm.hm_build_plan(H.n, H.n, blocks, acc, tile_mix=tile_mix)
     info = hm.hm_plan_info(p)
     buf = np.zeros(info["store_bytes"], np.uint8)
     hm.hm_pack_host(p, H.a_ptr, H.b_ptr, H.s_ptr if H.keep_sigma else None, buf)
@@ -354,7 +354,7 @@ def test_dfl_plan_rules():
         hm.hm_build_plan(H.n, H.n, blocks_from_table(H), hm.HM_F32)
     assert e.value.status == hm.HM_EDTYPE
     _aplr_like(H, [hm.HM_F64, hm.HM_DFL16, hm.HM_DFL24, hm.HM_DFL32, hm.HM_DFL40, hm.HM_DFL48])
-    p, info, buf = _pack(H, hm.HM_F64)
+    p, info, buf = _pack(H, hm.HM_F64, tile_mix=2)
     h, T = tables(buf)
     lo_fmts = {hm.HM_DFL24, hm.HM_DFL40, hm.HM_DFL48}
     n_mixed_lo = 0
@@ -365,13 +365,16 @@ def test_dfl_plan_rules():
     hm.hm_plan_destroy(p)
 
 
+@pytest.mark.parametrize("tile_mix", [1, 2])
 @pytest.mark.parametrize("which", ["f64", "mixed", "mixed16k", "bf16", "dfl32", "dfl40_16k", "dfl48",
                                    "dfl_mix", "dfl_any_16k", "dfl16", "dfl24", "aplr", "aflp",
                                    "aflp_any_16k", "aflp_zeros", "bfl40", "bfl_any_16k"])
-def test_store_model_matches_oracle(which, f64_4k, mixed4k):
+def test_store_model_matches_oracle(which, tile_mix, f64_4k, mixed4k):
     """The packed store, read as its layout defines it, gives the oracle's
-    product.  At n = 16384 some blocks span several column chunks (partials
-    and their reduction); mixed column tiles hold runs of several formats;
+    product, with one format per column tile (tile_mix 1) and with up to
+    four (tile_mix 2).  At n = 16384 some blocks span several column chunks
+    (partials and their reduction); mixed column tiles hold runs of several
+    formats (tile_mix 2);
     "bf16" stores every block in BF16 (one-format BF16 tiles); "dfl*" store
     DFL formats with FP64 accumulation (low-byte planes in row sections and
     tiles; "dfl_mix": dense DFL48 and FP64 beside low-rank DFL32, whose
@@ -417,7 +420,7 @@ def test_store_model_matches_oracle(which, f64_4k, mixed4k):
         H = {"f64": f64_4k, "mixed": mixed4k}[which]
     fp64 = which in ("f64", "aplr") or which.startswith(("dfl", "aflp", "bfl"))
     acc = hm.HM_F64 if fp64 else hm.HM_F32
-    p, info, buf = _pack(H, acc)
+    p, info, buf = _pack(H, acc, tile_mix)
     if which.endswith("16k"):
         assert info["n_partials"] > 0
     x = hmgen.uniform_vector(H.n)
