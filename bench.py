@@ -97,7 +97,10 @@ def kernels_source_hash(kernel="k_row"):
 
 def read_traffic(kernel, workload):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+    were taken on the current kernel source; else None.  workload: the
+    preset name, with _n<n> when the size is overridden and _r<R> for R
+    right-hand sides (profiles/traffic_<kernel>_<workload>.json); a phase
+    of several launches (k_col over tile classes) holds their sum."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -501,7 +504,8 @@ def main():
     achieved = kb[dom] / (avg_ms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": read_traffic(dom, args.workload),
+                "traffic": read_traffic(dom, args.workload + (f"_n{args.n}" if args.n else "") +
+                                        (f"_r{R}" if R > 1 else "")),
                 "alg_bytes_per_launch": kb[dom], "avg_ms": round(avg_ms[dom], 5)}
     kernels = {k: {"avg_ms": round(avg_ms[k], 5), "alg_bytes": kb[k],
                    "gbs": round(kb[k] / (avg_ms[k] * 1e-3) / 1e9, 1) if avg_ms[k] > 0 else None}
