@@ -6,8 +6,14 @@
 // of the ranks), so nothing is read back until the factorisation ends.
 //
 // Device memory comes from one arena allocated at creation, handed out by a
-// first-fit allocator; a buffer freed here may be reused by kernels enqueued
-// later on the same stream, which run after every earlier kernel.
+// first-fit allocator.  Independent branches of the recursion (the two
+// triangular solves of an LU step, the two column or row halves of a solve)
+// run on streams of their own, forked from and joined back into the
+// caller's stream with events; so that no buffer is reused while another
+// stream may still read it, buffers and rank slots freed during the
+// factorisation return to the allocator only at its end.  The solve runs on
+// one stream and frees at once (a later kernel on that stream runs after
+// every earlier one).
 #include <algorithm>
 #include <array>
 #include <cstring>
@@ -29,6 +35,7 @@ using hm::lu::Dim;
 using hm::lu::Part;
 
 constexpr size_t kAlign = 256;
+constexpr int kForkStreams = 8;    // streams the forked branches of a factorisation take turns on
 
 struct Arena {
   char* base = nullptr;
@@ -55,8 +62,22 @@ struct Arena {
     }
     return nullptr;
   }
+  // While defer is set, released buffers are only collected (their memory
+  // may still be in use by kernels of another stream) and return to the
+  // free list at flush(), after every stream has finished.
+  bool defer = false;
+  std::vector<void*> deferred;
+  void flush() {
+    defer = false;
+    for (void* p : deferred) release(p);
+    deferred.clear();
+  }
   void release(void* p) {
     if (!p) return;
+    if (defer) {
+      deferred.push_back(p);
+      return;
+    }
     const size_t off = (size_t)((char*)p - base);
     auto lv = live_.find(off);
     if (lv == live_.end()) return;
@@ -122,8 +143,12 @@ struct hm_lu {
   Arena arena;
   int32_t* d_slots = nullptr;                    // rank slots; the last one is the error flag
   int32_t n_slots = 0;
-  std::vector<int32_t> free_slots;
-  hipStream_t s = nullptr;
+  std::vector<int32_t> free_slots, deferred_slots;
+  hipStream_t s = nullptr;                       // the stream work is enqueued on now
+  std::vector<hipStream_t> pool;                 // streams for forked branches
+  size_t next_stream = 0;
+  std::vector<hipEvent_t> fj;                    // fork / join events
+  size_t fj_used = 0;
   double eps = 0;
   int dtype = HM_F64;
   int mbits = 52;
@@ -161,16 +186,51 @@ struct hm_lu {
     free_slots.pop_back();
     return q;
   }
-  void chk(hipError_t e) {
+  void chk(hipError_t e) {             // a kernel launch
     ++kernels;
+    if (e != hipSuccess) throw DeviceError{e};
+  }
+  static void chk_api(hipError_t e) {   // any other enqueued call
     if (e != hipSuccess) throw DeviceError{e};
   }
   void drop(Term& T) {
     for (void* p : T.own) arena.release(p);
     T.own.clear();
-    if (T.slot >= 0) free_slots.push_back(T.slot);
+    if (T.slot >= 0) release_slot(T.slot);
     T.slot = -1;
     T.kind = 0;
+  }
+  void release_slot(int32_t q) {
+    if (arena.defer) deferred_slots.push_back(q);
+    else free_slots.push_back(q);
+  }
+
+  // ------------------------------------------------------------ streams
+  hipEvent_t event() {
+    if (fj_used == fj.size()) {
+      hipEvent_t e;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) throw DeviceError{hipErrorOutOfMemory};
+      fj.push_back(e);
+    }
+    return fj[fj_used++];
+  }
+  // A stream for a branch that may run beside the rest of the current
+  // stream's work: it starts after everything enqueued so far.
+  hipStream_t fork() {
+    if (pool.empty()) return s;
+    hipStream_t c = pool[next_stream++ % pool.size()];
+    if (c == s) c = pool[next_stream++ % pool.size()];
+    hipEvent_t e = event();
+    chk_api(hipEventRecord(e, s));
+    chk_api(hipStreamWaitEvent(c, e, 0));
+    return c;
+  }
+  // The current stream continues after everything enqueued on c so far.
+  void join(hipStream_t c) {
+    if (c == s) return;
+    hipEvent_t e = event();
+    chk_api(hipEventRecord(e, c));
+    chk_api(hipStreamWaitEvent(s, e, 0));
   }
 
   // ------------------------------------------------- block times dense panel
@@ -371,10 +431,10 @@ struct hm_lu {
         if (hipEventCreate(&e) != hipSuccess) throw DeviceError{hipErrorOutOfMemory};
         events.push_back(e);
       }
-      chk(hipEventRecord(events[2 * truncations], s));
+      chk_api(hipEventRecord(events[2 * truncations], s));
     }
     chk(hm::lu::trunc(p0, p1, m, n, eps, scr, W, X, rank_out, d_slots + n_slots, flog, s));
-    if (timed) chk(hipEventRecord(events[2 * truncations + 1], s));
+    if (timed) chk_api(hipEventRecord(events[2 * truncations + 1], s));
     ++truncations;
   }
 
@@ -559,7 +619,7 @@ struct hm_lu {
               d_slots + slot);
     arena.release(scr);
     arena.release(B.blk);
-    free_slots.push_back(B.slot);
+    release_slot(B.slot);
     B.blk = W;
     B.U = W;
     B.V = W + B.m * std::max<int64_t>(capo, 1);
@@ -593,8 +653,13 @@ struct hm_lu {
     split(t, t, acc, pend, sub);
     const int32_t t0 = son0[t], t1 = son1[t];
     lu(t0, std::move(sub[0][0].acc), std::move(sub[0][0].pend));
+    // the two solves are independent: U01 here, L10 on a forked stream
+    const hipStream_t here = s, c = fork();
     solve_l(t0, t1, std::move(sub[0][1].acc), std::move(sub[0][1].pend));
+    s = c;
     solve_u(t1, t0, std::move(sub[1][0].acc), std::move(sub[1][0].pend));
+    s = here;
+    join(c);
     sub[1][1].pend.push_back({t1, t0, t1});
     lu(t1, std::move(sub[1][1].acc), std::move(sub[1][1].pend));
     drop(acc);
@@ -614,11 +679,16 @@ struct hm_lu {
     split(t, s2, acc, pend, sub);
     const int32_t t0 = son0[t], t1 = son1[t];
     const int32_t ss[2] = {son0[s2], son1[s2]};
+    // the two column halves are independent: the second on a forked stream
+    const hipStream_t here = s, c = fork();
     for (int j = 0; j < 2; ++j) {
+      s = j == 0 ? here : c;
       solve_l(t0, ss[j], std::move(sub[0][j].acc), std::move(sub[0][j].pend));
       sub[1][j].pend.push_back({t1, t0, ss[j]});
       solve_l(t1, ss[j], std::move(sub[1][j].acc), std::move(sub[1][j].pend));
     }
+    s = here;
+    join(c);
     drop(acc);
   }
 
@@ -643,11 +713,16 @@ struct hm_lu {
     split(t, s2, acc, pend, sub);
     const int32_t s0 = son0[s2], s1 = son1[s2];
     const int32_t ts[2] = {son0[t], son1[t]};
+    // the two row halves are independent: the second on a forked stream
+    const hipStream_t here = s, c = fork();
     for (int i = 0; i < 2; ++i) {
+      s = i == 0 ? here : c;
       solve_u(ts[i], s0, std::move(sub[i][0].acc), std::move(sub[i][0].pend));
       sub[i][1].pend.push_back({ts[i], s0, s1});
       solve_u(ts[i], s1, std::move(sub[i][1].acc), std::move(sub[i][1].pend));
     }
+    s = here;
+    join(c);
     drop(acc);
   }
 };
@@ -798,22 +873,42 @@ hm_status hm_lu_factor(hm_lu* F, double eps, int32_t dtype, void* stream) {
     F->d_flog = (double*)F->arena.alloc((size_t)F->flog_cap * sizeof(double));
     if (!F->d_flog) F->flog_cap = 0;
   }
+  // streams for the forked branches (default priority), and deferred frees
+  F->pool.clear();
+  for (int q = 0; q < kForkStreams; ++q) {
+    hipStream_t c;
+    if (hipStreamCreateWithFlags(&c, hipStreamNonBlocking) != hipSuccess) break;
+    F->pool.push_back(c);
+  }
+  F->next_stream = 0;
+  F->fj_used = 0;
+  F->arena.defer = true;
+  auto finish = [&]() {                   // every stream done; frees and streams released
+    for (hipStream_t c : F->pool) (void)hipStreamSynchronize(c);
+    (void)hipStreamSynchronize(F->s);
+    for (hipStream_t c : F->pool) (void)hipStreamDestroy(c);
+    F->pool.clear();
+    F->arena.flush();
+    for (int32_t q : F->deferred_slots) F->free_slots.push_back(q);
+    F->deferred_slots.clear();
+  };
   try {
     F->lu(0, Term{0, F->n, F->n}, {});
   } catch (const OutOfMemory&) {
     F->broken = true;
-    (void)hipStreamSynchronize(F->s);
+    finish();
     return fail(HM_ENOMEM, "arena exhausted (peak %zu of %zu bytes)", F->arena.peak, F->arena.size);
   } catch (const DeviceError& e) {
     F->broken = true;
-    (void)hipStreamSynchronize(F->s);
+    finish();
     return fail(HM_EDEVICE, "launch: %s", hipGetErrorString(e.e));
   }
   int32_t err = 0;
-  if (hipMemcpyAsync(&err, F->d_slots + F->n_slots, 4, hipMemcpyDeviceToHost, F->s) != hipSuccess ||
-      hipStreamSynchronize(F->s) != hipSuccess) {
+  const hipError_t ce = hipMemcpyAsync(&err, F->d_slots + F->n_slots, 4, hipMemcpyDeviceToHost, F->s);
+  finish();
+  if (ce != hipSuccess || hipGetLastError() != hipSuccess) {
     F->broken = true;
-    return fail(HM_EDEVICE, "factorisation: %s", hipGetErrorString(hipGetLastError()));
+    return fail(HM_EDEVICE, "factorisation: %s", hipGetErrorString(ce));
   }
   if (err) {
     F->broken = true;
@@ -917,6 +1012,7 @@ hm_status hm_lu_profile(hm_lu* F, int32_t on) {
 void hm_lu_destroy(hm_lu* F) {
   if (!F) return;
   for (hipEvent_t e : F->events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : F->fj) (void)hipEventDestroy(e);
   if (F->mem) {
     (void)hipDeviceSynchronize();
     (void)hipFree(F->mem);

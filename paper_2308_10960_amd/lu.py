@@ -15,8 +15,11 @@ from . import hm
 class DeviceHLU:
     """The H-LU object of the H-matrix ``H`` on the current device.
 
-    ``arena_bytes``: device memory for the factors and all temporaries
-    (default: the larger of 2 GiB and 8 times the bytes of A's leaves)."""
+    ``arena_bytes``: device memory for the factors and all temporaries; the
+    factorisation frees its temporaries only at its end (its branches run
+    on several streams), so the default is generous: the larger of 16 GiB
+    and 2048 times the bytes of A's leaves, at most half of the free device
+    memory."""
 
     def __init__(self, H, arena_bytes: int | None = None):
         tr = H.tree()
@@ -35,7 +38,11 @@ class DeviceHLU:
         m = (H.re - H.rb).astype(np.int64)
         n = (H.ce - H.cb).astype(np.int64)
         leaf_bytes = int(np.where(kind == 1, (m + n) * np.maximum(rank, 1), m * n).sum()) * 8
-        self.arena_bytes = arena_bytes or max(2 << 30, 8 * leaf_bytes)
+        if not arena_bytes:
+            import torch
+            free, _ = torch.cuda.mem_get_info()
+            arena_bytes = min(max(16 << 30, 2048 * leaf_bytes), free // 2)
+        self.arena_bytes = arena_bytes
         self.n = int(H.n)
         self.m, self.nn, self.kind = m, n, kind
         self.handle = hm.hm_lu_create(tr["begin"], tr["end"], tr["son0"], tr["son1"], tr["tau"], tr["sigma"],
