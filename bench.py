@@ -458,8 +458,9 @@ def main():
         from paper_2308_10960_amd import tune
         best, times = tune.tune(D, step, tune.CANDIDATES if R == 1 else tune.BATCH_CANDIDATES)
         shape, shape_times = tune.tune_shape(lambda c, t, mx: build(c, t, mx, use_cache=False),
-                                             lambda Dc: make_step(Dc)[0], best)
-        chosen = f"{best} chunk={shape[0]} tile={shape[1]} tmix={shape[2] - 1}"
+                                             lambda Dc: make_step(Dc)[0], best,
+                                             variants=tune.COLW_VARIANTS if R == 1 else ("",))
+        chosen = f"{best} chunk={shape[0]} tile={shape[1]} tmix={shape[2] - 1} {shape[3]}".strip()
         tune.write_cache(args.tune_cache, key, chosen)
         cache = args.tune_cache
         D.close()
@@ -468,8 +469,8 @@ def main():
         torch.cuda.synchronize()
         tuned = {"source": "autotuner, this run (written to the tune cache)", "key": key,
                  "chosen": chosen, "avg_ms": {k: round(v, 5) for k, v in times.items()},
-                 "shape_avg_ms": {f"chunk={c} tile={t} tmix={mx - 1}": round(v, 5)
-                                  for (c, t, mx), v in shape_times.items()}}
+                 "shape_avg_ms": {f"chunk={c} tile={t} tmix={mx - 1} {w}".strip(): round(v, 5)
+                                  for (c, t, mx, w), v in shape_times.items()}}
     else:
         tuned = {"source": "tune cache" if cache else "built-in", "key": key,
                  "chosen": hm.hm_matrix_get_launch(D.handle)}

@@ -292,10 +292,16 @@ hm_status hm_profile_end(hm_matrix* A, double* ms, int64_t* calls);
  *   persist 0: one workgroup per work item (row panel, column tile);
  *   persist 1, 2, 4 or 8: single-right-hand-side kernels run persistent
  *            grids of at most that many workgroups per compute unit, each
- *            looping over work items in the same order.
+ *            looping over work items in the same order;
+ *   colw 0: single-right-hand-side column tiles (schedule 0) run a
+ *            workgroup per tile, its four waves taking turns over the tile's
+ *            rows; colw 2: a wave per tile; colw 1 (built in): a wave per tile
+ *            in the launch classes of small tiles (where a workgroup would
+ *            leave more than a quarter of its waves' turns idle).
  * Unroll depth, order and persistence do not change any sum's order (results
  * are identical bit for bit); schedule 1 adds the near-field and far-field parts
- * to y in two steps, so it differs from schedule 0 by rounding only.  Each
+ * to y in two steps, so it differs from schedule 0 by rounding only; colw
+ * changes the order in which a column tile's rows are added.  Each
  * choice is deterministic.  hm_matrix_tune_key writes the key under which the
  * tuner stores the best choice for matrices of this kind (accumulation type,
  * storage formats present, size class, rank class = floor(log2) of the mean

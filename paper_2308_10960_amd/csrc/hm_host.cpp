@@ -669,6 +669,7 @@ static bool parse_launch(const char* text, LaunchParams& lp) {
     else if (k == "tile" && v >= 8 && v <= kTileGroups) r.tile = (int)v;
     else if (k == "colb" && v >= 0 && v <= 3) r.colb = (int)v;
     else if (k == "tmix" && (v == 0 || v == 1)) r.tmix = (int)v;
+    else if (k == "colw" && v >= 0 && v <= 2) r.colw = (int)v;
     else return false;
     i = j;
   }
@@ -780,6 +781,32 @@ hm_status layout_store(hm_plan* Pp, hm_plan** out) {
       }
     int64_t acc_end = 0;
     for (int c = 0; c <= kNumDtypes; ++c) H.tile_class_end[c] = (acc_end += cnt[c]);
+  }
+  {
+    // launch classes of small tiles.  A tile of g groups is read in batches
+    // of 8 RS rows (RS = 64 / GP, GP the power of two >= g); a workgroup
+    // gives its four waves a batch each in turn, so a tile of b batches
+    // keeps 4 ceil(b / 4) wave slots busy for b batches of work.  A class
+    // where that wastes more than a quarter runs a wave per tile.
+    double work[kNumDtypes + 1] = {}, slots[kNumDtypes + 1] = {};
+    for (auto& Cp : P->cps)
+      for (size_t t = 0; t < Cp.tile_lo.size(); ++t) {
+        const int32_t g0 = Cp.tile_g0[t], g1 = Cp.tile_g0[t + 1];
+        int runs = 0, fmt = 0;
+        for (auto& S : Cp.secs) {
+          const int32_t a = S.g0, b = S.g0 + S.ld / group_width(S.dtype);
+          if (std::max(a, g0) < std::min(b, g1)) { ++runs; fmt = S.dtype; }
+        }
+        const int c = runs != 1 ? kNumDtypes : fmt <= HM_BF16 ? 0 : fmt;
+        int gp = 1;
+        while (gp < g1 - g0) gp *= 2;
+        const int64_t rs = 64 / gp, b = (Cp.nrows + 8 * rs - 1) / (8 * rs);
+        work[c] += (double)b;
+        slots[c] += 4.0 * (double)((b + 3) / 4);
+      }
+    P->col_wave = 0;
+    for (int c = 0; c <= kNumDtypes; ++c)
+      if (slots[c] > 0 && work[c] < 0.75 * slots[c]) P->col_wave |= 1u << c;
   }
 
   int64_t off = align_up(sizeof(StoreHeader), kAlign);
@@ -1516,6 +1543,7 @@ hm_status hm_upload(const hm_plan* p, const double* const* a, const double* cons
   M->device = dev;
   M->n_cu = ncu;
   std::memcpy(M->bytes_by_dtype, p->bytes_by_dtype, sizeof M->bytes_by_dtype);
+  M->col_wave = p->col_wave;
   *out = M;
   return ok();
 }
@@ -1704,9 +1732,9 @@ hm_status hm_matrix_set_launch(hm_matrix* A, const char* params) {
 
 hm_status hm_matrix_get_launch(const hm_matrix* A, char* buf, size_t len) {
   if (!A || !buf || len == 0) return fail(HM_EINVAL, "NULL argument");
-  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d persist=%d chunk=%d tile=%d colb=%d tmix=%d",
+  std::snprintf(buf, len, "schedule=%d unroll=%d order=%d persist=%d chunk=%d tile=%d colb=%d tmix=%d colw=%d",
                 A->launch.schedule, A->launch.row_unroll, A->launch.order, A->launch.persist, A->launch.chunk,
-                A->launch.tile, A->launch.colb, A->launch.tmix);
+                A->launch.tile, A->launch.colb, A->launch.tmix, A->launch.colw);
   return ok();
 }
 

@@ -38,6 +38,7 @@ struct LaunchParams {
   int tile = 0;
   int colb = 0;
   int tmix = 0;
+  int colw = 1;           // column tiles: 0 a workgroup per tile, 2 a wave per tile, 1 per launch class (col_wave)
 };
 
 struct BlockInfo {
@@ -116,6 +117,11 @@ struct hm_plan {
   int64_t n_dense = 0, n_lowrank = 0;
   size_t bytes_by_dtype[hm::kNumDtypes] = {};
   hm::LaunchParams launch;
+  // single-RHS column-tile launch classes whose tiles are small enough that
+  // a workgroup per tile would leave waves idle (bit 0: the one-format IEEE
+  // tiles; bit f: one-format tiles of DFL / AFLP / BFL format f; bit
+  // kNumDtypes: several-format tiles)
+  uint32_t col_wave = 0;
 };
 
 namespace hm {
@@ -139,6 +145,7 @@ struct hm_matrix {
   int32_t rank_class = 0;               // of its plan (tune key)
   hm::LaunchParams launch;
   size_t bytes_by_dtype[hm::kNumDtypes] = {};
+  uint32_t col_wave = 0;                // of its plan
 };
 
 namespace hm {

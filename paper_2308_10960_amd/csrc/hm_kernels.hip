@@ -183,6 +183,14 @@ __device__ __forceinline__ void axpy_group(u32x4 r, u32x2 lo, AccT xi, AccT* acc
 
 // ---------------------------------------------------------------- column tiles
 
+// Orders the LDS accesses of the calling wave's lanes: what a lane wrote
+// before is visible to every lane of the wave after (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename AccT>
 struct ColArgs {
   const uint8_t* store;
@@ -212,9 +220,13 @@ struct ColArgs {
 // decodes its own (T.dtype, T.end); DFL / AFLP / BFL: such a tile may hold
 // runs of those formats.  An AFLP lane keeps its columns' shifts in registers and
 // scales its sums by the columns' 2^k before they are written.
-template <typename AccT, int DT, bool DFL = false, bool AFLP = false, bool BFL = false>
+// WAVE: the calling wave streams the tile alone (all batches of 8 RS rows),
+// with xs its own kSegRows values of LDS, and its lanes of sub-row 0 write
+// the sums after the butterfly (no workgroup barrier; red unused).
+template <typename AccT, int DT, bool DFL = false, bool AFLP = false, bool BFL = false, bool WAVE = false>
 __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& T, AccT* red, AccT* xs) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = WAVE ? 1 : 4;                  // waves sharing the tile
+  const int lane = threadIdx.x & 63, wave = WAVE ? 0 : threadIdx.x >> 6;
   const int ng = T.ngroups;
   const int GP = ng <= 1 ? 1 : ng <= 2 ? 2 : ng <= 4 ? 4 : ng <= 8 ? 8 : ng <= 16 ? 16 : ng <= 32 ? 32 : 64;
   const int RS = 64 / GP;                           // rows per wave-wide step (sub-rows)
@@ -247,11 +259,11 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
   constexpr bool LOW = DFL || AFLP || BFL;         // several-format tiles: runs with low bytes
   const int Lt = DT < 0 && LOW ? tile_lo_bytes(T) : 0;
   const bool hlo = DT < 0 && LOW && lo_bytes(dt) > 0;
-  const int nb = nrows > 8 * RS * wave ? (nrows - 8 * RS * wave + 32 * RS - 1) / (32 * RS) : 0;   // this wave's batches
+  const int nb = nrows > 8 * RS * wave ? (nrows - 8 * RS * wave + 8 * NW * RS - 1) / (8 * NW * RS) : 0;   // this wave's batches
   u32x4 rn[8];
   u32x2 ln[8];
   auto issue = [&](int j) {
-    const int r0 = RS * (32 * j + 8 * wave) + q;
+    const int r0 = RS * (8 * NW * j + 8 * wave) + q;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (act && r0 + RS * u < nrows) {
@@ -268,8 +280,13 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
       }
   };
   if (nb > 0) issue(0);
-  for (int i = threadIdx.x; i < nrows; i += 256) xs[i] = a.x[T.x0 + i];
-  __syncthreads();
+  if constexpr (WAVE) {
+    for (int i = lane; i < nrows; i += 64) xs[i] = a.x[T.x0 + i];
+    wave_sync();
+  } else {
+    for (int i = threadIdx.x; i < nrows; i += 256) xs[i] = a.x[T.x0 + i];
+    __syncthreads();
+  }
   for (int j = 0; j < nb; ++j) {
     u32x4 rc[8];
     u32x2 lc[8];
@@ -279,7 +296,7 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
       lc[u] = ln[u];
     }
     if (j + 1 < nb) issue(j + 1);
-    const int r0 = RS * (32 * j + 8 * wave) + q;
+    const int r0 = RS * (8 * NW * j + 8 * wave) + q;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (r0 + RS * u < nrows) {                    // uniform across a sub-row
@@ -318,9 +335,11 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
 #pragma unroll
     for (int c = 0; c < GW; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
   }
+  if constexpr (!WAVE) {
 #pragma unroll
-  for (int c = 0; c < GW; ++c) red[(wave * 64 + lane) * GW + c] = acc[c];   // red stride GW per lane
-  __syncthreads();
+    for (int c = 0; c < GW; ++c) red[(wave * 64 + lane) * GW + c] = acc[c];   // red stride GW per lane
+    __syncthreads();
+  }
   if (wave == 0 && q == 0 && act) {
     const int G = group_width(dt);
     // all destinations and factors first, then the stores
@@ -342,7 +361,9 @@ __device__ __forceinline__ void col_tile(const ColArgs<AccT>& a, const ColTile& 
     }
 #pragma unroll
     for (int c = 0; c < GW; ++c) {
-      AccT sum = (red[g * GW + c] + red[(64 + g) * GW + c]) + (red[(128 + g) * GW + c] + red[(192 + g) * GW + c]);
+      AccT sum = acc[c];
+      if constexpr (!WAVE)
+        sum = (red[g * GW + c] + red[(64 + g) * GW + c]) + (red[(128 + g) * GW + c] + red[(192 + g) * GW + c]);
       if constexpr (kAflp) sum = ldexp(sum, ks[c]);     // exact: a power of two
       if (d[c] >= 0)
         a.part[d[c]] = sum;
@@ -364,11 +385,12 @@ constexpr int kColBfl = 16;     // BFL runs in several-format tiles
 // (four waves x 64 lanes x at most 8 columns per lane); xs: kSegRows
 // values (x of the tile's rows).
 // DT >= 0: every tile has that one format.
-template <typename AccT, int KIND, int DT = -1>
+// WAVE: the calling wave alone (col_tile).
+template <typename AccT, int KIND, int DT = -1, bool WAVE = false>
 __device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti, AccT* red, AccT* xs) {
   const ColTile T = a.tiles[ti];
   if constexpr (DT >= 0) {
-    col_tile<AccT, DT>(a, T, red, xs);
+    col_tile<AccT, DT, false, false, false, WAVE>(a, T, red, xs);
     return;
   }
   constexpr bool dfl = (KIND & kColDfl) && sizeof(AccT) == 8;
@@ -376,46 +398,46 @@ __device__ __forceinline__ void col_tile_any(const ColArgs<AccT>& a, int64_t ti,
   constexpr bool bfl = (KIND & kColBfl) && sizeof(AccT) == 8;
   if constexpr ((KIND & kColMulti) != 0) {
     if (T.end[0] < T.ngroups) {                     // several formats in the tile
-      col_tile<AccT, -1, dfl, aflp, bfl>(a, T, red, xs);
+      col_tile<AccT, -1, dfl, aflp, bfl, WAVE>(a, T, red, xs);
       return;
     }
   }
   if constexpr (bfl) {
     switch (T.dtype[0]) {
-      case kDtBfl24: col_tile<AccT, kDtBfl24>(a, T, red, xs); return;
-      case kDtBfl40: col_tile<AccT, kDtBfl40>(a, T, red, xs); return;
-      case kDtBfl48: col_tile<AccT, kDtBfl48>(a, T, red, xs); return;
+      case kDtBfl24: col_tile<AccT, kDtBfl24, false, false, false, WAVE>(a, T, red, xs); return;
+      case kDtBfl40: col_tile<AccT, kDtBfl40, false, false, false, WAVE>(a, T, red, xs); return;
+      case kDtBfl48: col_tile<AccT, kDtBfl48, false, false, false, WAVE>(a, T, red, xs); return;
       default: break;
     }
   }
   if constexpr (aflp) {
     switch (T.dtype[0]) {
-      case kDtAflp32: col_tile<AccT, kDtAflp32>(a, T, red, xs); return;
-      case kDtAflp40: col_tile<AccT, kDtAflp40>(a, T, red, xs); return;
-      case kDtAflp48: col_tile<AccT, kDtAflp48>(a, T, red, xs); return;
-      case kDtAflp16: col_tile<AccT, kDtAflp16>(a, T, red, xs); return;
-      case kDtAflp24: col_tile<AccT, kDtAflp24>(a, T, red, xs); return;
+      case kDtAflp32: col_tile<AccT, kDtAflp32, false, false, false, WAVE>(a, T, red, xs); return;
+      case kDtAflp40: col_tile<AccT, kDtAflp40, false, false, false, WAVE>(a, T, red, xs); return;
+      case kDtAflp48: col_tile<AccT, kDtAflp48, false, false, false, WAVE>(a, T, red, xs); return;
+      case kDtAflp16: col_tile<AccT, kDtAflp16, false, false, false, WAVE>(a, T, red, xs); return;
+      case kDtAflp24: col_tile<AccT, kDtAflp24, false, false, false, WAVE>(a, T, red, xs); return;
       default: break;
     }
   }
   if constexpr (dfl) {
     switch (T.dtype[0]) {
-      case kDtDfl32: col_tile<AccT, kDtDfl32>(a, T, red, xs); return;
-      case kDtDfl40: col_tile<AccT, kDtDfl40>(a, T, red, xs); return;
-      case kDtDfl48: col_tile<AccT, kDtDfl48>(a, T, red, xs); return;
-      case kDtDfl16: col_tile<AccT, kDtDfl16>(a, T, red, xs); return;
-      case kDtDfl24: col_tile<AccT, kDtDfl24>(a, T, red, xs); return;
+      case kDtDfl32: col_tile<AccT, kDtDfl32, false, false, false, WAVE>(a, T, red, xs); return;
+      case kDtDfl40: col_tile<AccT, kDtDfl40, false, false, false, WAVE>(a, T, red, xs); return;
+      case kDtDfl48: col_tile<AccT, kDtDfl48, false, false, false, WAVE>(a, T, red, xs); return;
+      case kDtDfl16: col_tile<AccT, kDtDfl16, false, false, false, WAVE>(a, T, red, xs); return;
+      case kDtDfl24: col_tile<AccT, kDtDfl24, false, false, false, WAVE>(a, T, red, xs); return;
       default: break;
     }
   }
   if constexpr ((KIND & kColIeee) != 0) {
     switch (T.dtype[0]) {
       case HM_F64:
-        if constexpr (sizeof(AccT) == 8) col_tile<AccT, HM_F64>(a, T, red, xs);
+        if constexpr (sizeof(AccT) == 8) col_tile<AccT, HM_F64, false, false, false, WAVE>(a, T, red, xs);
         break;
-      case HM_F32: col_tile<AccT, HM_F32>(a, T, red, xs); break;
-      case HM_F16: col_tile<AccT, HM_F16>(a, T, red, xs); break;
-      default: col_tile<AccT, HM_BF16>(a, T, red, xs); break;
+      case HM_F32: col_tile<AccT, HM_F32, false, false, false, WAVE>(a, T, red, xs); break;
+      case HM_F16: col_tile<AccT, HM_F16, false, false, false, WAVE>(a, T, red, xs); break;
+      default: col_tile<AccT, HM_BF16, false, false, false, WAVE>(a, T, red, xs); break;
     }
   }
 }
@@ -661,8 +683,25 @@ void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
   }
 }
 
+// The same tiles, one per wave: wave w of workgroup b takes tiles
+// t0 + 4 b + w, t0 + 4 (b + gridDim.x) + w, ...  For classes of small tiles,
+// whose rows one wave covers in a batch or two, where a workgroup per tile
+// would leave waves idle.
+template <typename AccT, int KIND, int DT = -1>
+__global__ __launch_bounds__(256, (KIND == kColIeee || DT == kDtDfl32 || DT == kDtDfl16) ? 4 : 3)
+void k_col_w(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
+  __shared__ AccT cxs[4][kSegRows];
+  const int wave = wave_id();
+  for (int64_t it = t0 + 4 * (int64_t)blockIdx.x + wave; it < t1; it += 4 * (int64_t)gridDim.x) {
+    wave_sync();                                    // xs of the wave's previous tile read
+    col_tile_any<AccT, KIND, DT, true>(ca, it, nullptr, cxs[wave]);
+  }
+}
+
+// U = 4: five workgroups per CU (fewer loads in flight per wave, more
+// panels in flight per CU); U = 8: as many as the registers allow.
 template <typename AccT, int CAP, int U, int XF>
-__global__ __launch_bounds__(256) void k_row(RowArgs<AccT> ra, const int32_t* order, int64_t n_panels,
+__global__ __launch_bounds__(256, U == 4 ? 5 : 1) void k_row(RowArgs<AccT> ra, const int32_t* order, int64_t n_panels,
                                              int64_t n_items) {
   __shared__ AccT zs[CAP];
   __shared__ AccT red[4][64];
@@ -730,39 +769,43 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
     // classes: one-format IEEE tiles [0, ce[3]), one-format DFL tiles
     // [ce[3], ce[8]), one-format AFLP tiles [ce[8], ce[13]), one-format BFL
     // tiles [ce[13], ce[16]), several-format tiles [ce[16], ce[17])
+    // (a wave per tile for the classes col_wave marks, or as colw says)
     const int64_t* ce = h.tile_class_end;
-    const int64_t ni = ce[HM_BF16], nm = h.n_col_tiles - ce[kNumDtypes - 1];
-    if (ni > 0)
-      hipLaunchKernelGGL((k_col<AccT, kColIeee>), dim3(item_grid(ni, ps, ncu)), dim3(256), 0, s, ca,
-                         int64_t(0), ni);
-    auto cls = [&](auto kern, int c) {              // one launch per class
-      const int64_t t0 = ce[c - 1], n = ce[c] - t0;
-      if (n > 0) hipLaunchKernelGGL(kern, dim3(item_grid(n, ps, ncu)), dim3(256), 0, s, ca, t0, ce[c]);
+    auto wave_mode = [&](int bit) {
+      return A.launch.colw == 2 || (A.launch.colw == 1 && ((A.col_wave >> bit) & 1u));
     };
+    auto run = [&](auto kern, auto kern_w, int bit, int64_t t0, int64_t t1) {
+      const int64_t n = t1 - t0;
+      if (n <= 0) return;
+      if (wave_mode(bit))
+        hipLaunchKernelGGL(kern_w, dim3(item_grid((n + 3) / 4, ps, ncu)), dim3(256), 0, s, ca, t0, t1);
+      else
+        hipLaunchKernelGGL(kern, dim3(item_grid(n, ps, ncu)), dim3(256), 0, s, ca, t0, t1);
+    };
+    run(k_col<AccT, kColIeee>, k_col_w<AccT, kColIeee>, 0, 0, ce[HM_BF16]);
+    auto cls = [&](auto kern, auto kern_w, int c) { run(kern, kern_w, c, ce[c - 1], ce[c]); };   // one launch per class
     if constexpr ((XF & kXfDfl) != 0 && sizeof(AccT) == 8) {
-      cls(k_col<AccT, kColDfl, kDtDfl32>, kDtDfl32);
-      cls(k_col<AccT, kColDfl, kDtDfl40>, kDtDfl40);
-      cls(k_col<AccT, kColDfl, kDtDfl48>, kDtDfl48);
-      cls(k_col<AccT, kColDfl, kDtDfl16>, kDtDfl16);
-      cls(k_col<AccT, kColDfl, kDtDfl24>, kDtDfl24);
+      cls(k_col<AccT, kColDfl, kDtDfl32>, k_col_w<AccT, kColDfl, kDtDfl32>, kDtDfl32);
+      cls(k_col<AccT, kColDfl, kDtDfl40>, k_col_w<AccT, kColDfl, kDtDfl40>, kDtDfl40);
+      cls(k_col<AccT, kColDfl, kDtDfl48>, k_col_w<AccT, kColDfl, kDtDfl48>, kDtDfl48);
+      cls(k_col<AccT, kColDfl, kDtDfl16>, k_col_w<AccT, kColDfl, kDtDfl16>, kDtDfl16);
+      cls(k_col<AccT, kColDfl, kDtDfl24>, k_col_w<AccT, kColDfl, kDtDfl24>, kDtDfl24);
     }
     if constexpr ((XF & kXfAflp) != 0 && sizeof(AccT) == 8) {
-      cls(k_col<AccT, kColAflp, kDtAflp16>, kDtAflp16);
-      cls(k_col<AccT, kColAflp, kDtAflp24>, kDtAflp24);
-      cls(k_col<AccT, kColAflp, kDtAflp32>, kDtAflp32);
-      cls(k_col<AccT, kColAflp, kDtAflp40>, kDtAflp40);
-      cls(k_col<AccT, kColAflp, kDtAflp48>, kDtAflp48);
+      cls(k_col<AccT, kColAflp, kDtAflp16>, k_col_w<AccT, kColAflp, kDtAflp16>, kDtAflp16);
+      cls(k_col<AccT, kColAflp, kDtAflp24>, k_col_w<AccT, kColAflp, kDtAflp24>, kDtAflp24);
+      cls(k_col<AccT, kColAflp, kDtAflp32>, k_col_w<AccT, kColAflp, kDtAflp32>, kDtAflp32);
+      cls(k_col<AccT, kColAflp, kDtAflp40>, k_col_w<AccT, kColAflp, kDtAflp40>, kDtAflp40);
+      cls(k_col<AccT, kColAflp, kDtAflp48>, k_col_w<AccT, kColAflp, kDtAflp48>, kDtAflp48);
     }
     if constexpr ((XF & kXfBfl) != 0 && sizeof(AccT) == 8) {
-      cls(k_col<AccT, kColBfl, kDtBfl24>, kDtBfl24);
-      cls(k_col<AccT, kColBfl, kDtBfl40>, kDtBfl40);
-      cls(k_col<AccT, kColBfl, kDtBfl48>, kDtBfl48);
+      cls(k_col<AccT, kColBfl, kDtBfl24>, k_col_w<AccT, kColBfl, kDtBfl24>, kDtBfl24);
+      cls(k_col<AccT, kColBfl, kDtBfl40>, k_col_w<AccT, kColBfl, kDtBfl40>, kDtBfl40);
+      cls(k_col<AccT, kColBfl, kDtBfl48>, k_col_w<AccT, kColBfl, kDtBfl48>, kDtBfl48);
     }
     constexpr int KM = kColMulti | ((XF & kXfDfl) ? kColDfl : 0) | ((XF & kXfAflp) ? kColAflp : 0) |
                        ((XF & kXfBfl) ? kColBfl : 0);
-    if (nm > 0)
-      hipLaunchKernelGGL((k_col<AccT, KM>), dim3(item_grid(nm, ps, ncu)), dim3(256), 0, s, ca,
-                         ce[kNumDtypes - 1], h.n_col_tiles);
+    run(k_col<AccT, KM>, k_col_w<AccT, KM>, kNumDtypes, ce[kNumDtypes - 1], h.n_col_tiles);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
   if (h.n_col_tiles > 0) {

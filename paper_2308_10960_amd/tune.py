@@ -1,6 +1,7 @@
 """Autotuner of the launch parameters (schedule, unroll depth, panel order,
 persistent grids) and of the column-tile shape (rows per column chunk,
-groups per tile, one or several storage formats per tile).
+groups per tile, one or several storage formats per tile) with the way
+column tiles are spread over waves.
 
 For one device-resident matrix it times every launch candidate with the
 library's own HIP-event kernel timing and keeps the fastest; tile shapes
@@ -28,6 +29,9 @@ BATCH_CANDIDATES = ["schedule=0 unroll=8 order=0 persist=0 colb=0", "schedule=0 
 # tile, 2 up to four; the same store for a matrix of one format)
 SHAPE_CANDIDATES = [(512, 64, 1), (256, 64, 1), (128, 64, 1), (64, 64, 1), (512, 32, 1), (256, 32, 1),
                     (512, 64, 2), (256, 64, 2), (128, 64, 2)]
+# single-RHS column tiles on a workgroup each, per launch class, or on a
+# wave each (timed for every shape: the best choice depends on tile size)
+COLW_VARIANTS = ("colw=0", "colw=1", "colw=2")
 
 
 def _time(D, step, reps: int) -> float:
@@ -56,23 +60,26 @@ def tune(D, step, candidates=CANDIDATES, reps: int = 10, warmup: int = 3):
     return best, times
 
 
-def tune_shape(make, step_of, launch: str, candidates=SHAPE_CANDIDATES, reps: int = 10,
+def tune_shape(make, step_of, launch: str, candidates=SHAPE_CANDIDATES, variants=("",), reps: int = 10,
                warmup: int = 3):
     """Time every tile shape: ``make(chunk, tile, mix)`` builds and uploads
     the matrix with that shape, ``step_of(D)`` returns one product of it.
-    Each runs with the launch parameters ``launch``.  Returns (best (chunk,
-    tile, mix), {shape: ms}); the matrices are released."""
+    Each runs with the launch parameters ``launch``, followed by each of
+    ``variants`` (extra launch parameters, "" for none).  Returns (best
+    (chunk, tile, mix, variant), {(chunk, tile, mix, variant): ms}); the
+    matrices are released."""
     import torch
     times = {}
     for chunk, tile, mix in candidates:
         D = make(chunk, tile, mix)
         try:
-            hm.hm_matrix_set_launch(D.handle, launch)
             step = step_of(D)
-            for _ in range(warmup):
-                step()
-            torch.cuda.synchronize()
-            times[(chunk, tile, mix)] = _time(D, step, reps)
+            for v in variants:
+                hm.hm_matrix_set_launch(D.handle, (launch + " " + v).strip())
+                for _ in range(warmup):
+                    step()
+                torch.cuda.synchronize()
+                times[(chunk, tile, mix, v)] = _time(D, step, reps)
         finally:
             D.close()
             torch.cuda.empty_cache()

@@ -170,6 +170,14 @@ def test_dfl_parity(name):
             say(c)
             hm.hm_matrix_set_launch(D.handle, c)
             np.testing.assert_array_equal(run(D, x, y0, 0.75), base[sched])
+    # column tiles on a workgroup each and on a wave each (persistent too)
+    for colw in (0, 2):
+        hm.hm_matrix_set_launch(D.handle, f"schedule=0 unroll=8 order=1 persist=0 colw={colw}")
+        y = run(D, x, y0, 0.75)
+        check(y, ref, scale, f"{name} colw={colw}")
+        hm.hm_matrix_set_launch(D.handle, "persist=2")
+        np.testing.assert_array_equal(run(D, x, y0, 0.75), y)
+    hm.hm_matrix_set_launch(D.handle, "persist=0 colw=1")
     # storage rounding against the unrounded FP64 product, bounded by the
     # unit roundoff of the formats (two rounded factors per low-rank term)
     truth = oracle.hmvm(H, x)

@@ -217,8 +217,11 @@ def test_full_size_f64(name):
     D.close()
 
 
-def _mixed(H, name):
+def _mixed(H, name, launch=None):
     D = DeviceHMatrix(H, hm.HM_F32)
+    if launch:
+        say(name, launch)
+        hm.hm_matrix_set_launch(D.handle, launch)
     x64 = hmgen.uniform_vector(H.n)
     x = x64.astype(np.float32).astype(np.float64)        # the vector the GPU sees
     y = run(D, x)
@@ -257,7 +260,10 @@ def check_store_budget(H, tol):
 
 
 def test_mixed_sphere4k():
-    _mixed(hmgen.build_preset("sphere4k_mixed"), "sphere4k_mixed")
+    H = hmgen.build_preset("sphere4k_mixed")
+    _mixed(H, "sphere4k_mixed")
+    for colw in (0, 2):                  # column tiles a workgroup / a wave each
+        _mixed(H, "sphere4k_mixed", f"colw={colw}")
 
 
 def test_mixed_full_size():
@@ -383,7 +389,7 @@ def test_launch_variants_and_tune_cache(sphere4k, tmp_path):
     out = {}
     for c in tune.CANDIDATES:
         hm.hm_matrix_set_launch(D.handle, c)
-        assert hm.hm_matrix_get_launch(D.handle) == c + " chunk=512 tile=64 colb=0 tmix=0"
+        assert hm.hm_matrix_get_launch(D.handle) == c + " chunk=512 tile=64 colb=0 tmix=0 colw=1"
         out[c] = run(D, x)
         check_f64(out[c], ref, scale)
     # within one schedule, unroll depth, order and persistence change no bit
@@ -400,13 +406,13 @@ def test_launch_variants_and_tune_cache(sphere4k, tmp_path):
     tune.write_cache(path, key, "schedule=1 unroll=8 order=0 persist=2")
     tune.write_cache(path, "acc9-fmt0-n2^0", "schedule=0 unroll=4")
     D2 = DeviceHMatrix(H, hm.HM_F64, tune_cache=path)
-    assert hm.hm_matrix_get_launch(D2.handle) == "schedule=1 unroll=8 order=0 persist=2 chunk=512 tile=64 colb=0 tmix=0"
+    assert hm.hm_matrix_get_launch(D2.handle) == "schedule=1 unroll=8 order=0 persist=2 chunk=512 tile=64 colb=0 tmix=0 colw=1"
     D2.close()
     # a tuned tile shape: parity, and the shape is the plan's (set_launch
     # accepts only the plan's own)
     tune.write_cache(path, key, "schedule=0 unroll=8 order=1 persist=0 chunk=128 tile=16")
     D3 = DeviceHMatrix(H, hm.HM_F64, tune_cache=path)
-    assert hm.hm_matrix_get_launch(D3.handle) == "schedule=0 unroll=8 order=1 persist=0 chunk=128 tile=16 colb=0 tmix=0"
+    assert hm.hm_matrix_get_launch(D3.handle) == "schedule=0 unroll=8 order=1 persist=0 chunk=128 tile=16 colb=0 tmix=0 colw=1"
     assert D3.info["n_col_tiles"] > D.info["n_col_tiles"]
     check_f64(run(D3, x), ref, scale)
     hm.hm_matrix_set_launch(D3.handle, "unroll=4 chunk=128 tile=16")
@@ -443,6 +449,37 @@ def test_persistent_grids_loop(sphere64k):
                 say(c)
                 hm.hm_matrix_set_launch(D.handle, c)
                 np.testing.assert_array_equal(run(D, x, y0, 0.75), base)
+    D.close()
+
+
+@pytest.mark.parametrize("chunk", [512, 64])
+def test_column_tile_wave_modes(sphere64k, chunk, tmp_path):
+    """Column tiles on a workgroup each (colw=0), on a wave each (colw=2)
+    or chosen per launch class (colw=1, built in), with 512- and 64-row
+    column chunks: parity with the oracle in each mode, and persistent grids,
+    where every wave loops over several tiles, give the plain launch's
+    result bit for bit."""
+    from paper_2308_10960_amd import tune
+    H = sphere64k
+    D = DeviceHMatrix(H, hm.HM_F64)
+    key = hm.hm_matrix_tune_key(D.handle)
+    D.close()
+    path = str(tmp_path / "tune.txt")
+    tune.write_cache(path, key, f"schedule=0 unroll=8 order=1 persist=0 chunk={chunk} tile=64")
+    D = DeviceHMatrix(H, hm.HM_F64, tune_cache=path)
+    assert D.info["n_col_tiles"] > 4 * 256           # persist=1: every wave loops
+    x = hmgen.uniform_vector(H.n)
+    y0 = hmgen.uniform_vector(H.n, seed=9)
+    ref = oracle.hmvm(H, x, y0, alpha=0.75)
+    scale = 0.75 * abs_bound(H, x) + np.abs(y0)
+    for colw in (0, 1, 2):
+        hm.hm_matrix_set_launch(D.handle, f"colw={colw} persist=0")
+        say(f"chunk={chunk} colw={colw}")
+        base = run(D, x, y0, 0.75)
+        check_f64(base, ref, scale)
+        for ps in (1, 2):
+            hm.hm_matrix_set_launch(D.handle, f"persist={ps}")
+            np.testing.assert_array_equal(run(D, x, y0, 0.75), base)
     D.close()
 
 
