@@ -672,8 +672,11 @@ __global__ __launch_bounds__(256) void k_p2(RowArgs<AccT> ra, const int32_t* ord
 // Tiles [t0, t1) of the classes KIND decodes (DT >= 0: the one-format
 // class DT).  Four workgroups per CU, three where the registers need it
 // (several-format tiles; the DFL formats with low-byte loads).
+constexpr int col_wgs(int kind, int dt) {
+  return (kind == kColIeee || dt == kDtDfl32 || dt == kDtDfl16) ? 4 : 3;
+}
 template <typename AccT, int KIND, int DT = -1>
-__global__ __launch_bounds__(256, (KIND == kColIeee || DT == kDtDfl32 || DT == kDtDfl16) ? 4 : 3)
+__global__ __launch_bounds__(256, col_wgs(KIND, DT))
 void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
   __shared__ AccT cred[4 * 64 * 8];
   __shared__ AccT cxs[kSegRows];
@@ -688,13 +691,28 @@ void k_col(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
 // whose rows one wave covers in a batch or two, where a workgroup per tile
 // would leave waves idle.
 template <typename AccT, int KIND, int DT = -1>
-__global__ __launch_bounds__(256, (KIND == kColIeee || DT == kDtDfl32 || DT == kDtDfl16) ? 4 : 3)
+__global__ __launch_bounds__(256, col_wgs(KIND, DT))
 void k_col_w(ColArgs<AccT> ca, int64_t t0, int64_t t1) {
   __shared__ AccT cxs[4][kSegRows];
   const int wave = wave_id();
   for (int64_t it = t0 + 4 * (int64_t)blockIdx.x + wave; it < t1; it += 4 * (int64_t)gridDim.x) {
     wave_sync();                                    // xs of the wave's previous tile read
     col_tile_any<AccT, KIND, DT, true>(ca, it, nullptr, cxs[wave]);
+  }
+}
+
+// Two neighbouring launch classes in one launch, a wave per tile: tiles
+// [t0, tm) of class (KA, DA), [tm, t1) of class (KB, DB).  One ramp and
+// tail instead of two where a store spreads its columns over many formats.
+template <typename AccT, int KA, int DA, int KB, int DB>
+__global__ __launch_bounds__(256, col_wgs(KA, DA) < col_wgs(KB, DB) ? col_wgs(KA, DA) : col_wgs(KB, DB))
+void k_col_w2(ColArgs<AccT> ca, int64_t t0, int64_t tm, int64_t t1) {
+  __shared__ AccT cxs[4][kSegRows];
+  const int wave = wave_id();
+  for (int64_t it = t0 + 4 * (int64_t)blockIdx.x + wave; it < t1; it += 4 * (int64_t)gridDim.x) {
+    wave_sync();                                    // xs of the wave's previous tile read
+    if (it < tm) col_tile_any<AccT, KA, DA, true>(ca, it, nullptr, cxs[wave]);
+    else col_tile_any<AccT, KB, DB, true>(ca, it, nullptr, cxs[wave]);
   }
 }
 
@@ -782,14 +800,30 @@ hipError_t launch_typed_u(const hm_matrix& A, double alpha, const void* x, void*
       else
         hipLaunchKernelGGL(kern, dim3(item_grid(n, ps, ncu)), dim3(256), 0, s, ca, t0, t1);
     };
-    run(k_col<AccT, kColIeee>, k_col_w<AccT, kColIeee>, 0, 0, ce[HM_BF16]);
+    // two neighbouring classes that both run a wave per tile and both have
+    // tiles share one launch (k_col_w2): classes bitA [a0, a1), bitB [a1, b1)
+    auto pair = [&](auto kern2, int bitA, int64_t a0, int64_t a1, int bitB, int64_t b1) {
+      if (a1 <= a0 || b1 <= a1 || !wave_mode(bitA) || !wave_mode(bitB)) return false;
+      hipLaunchKernelGGL(kern2, dim3(item_grid((b1 - a0 + 3) / 4, ps, ncu)), dim3(256), 0, s, ca, a0, a1, b1);
+      return true;
+    };
     auto cls = [&](auto kern, auto kern_w, int c) { run(kern, kern_w, c, ce[c - 1], ce[c]); };   // one launch per class
     if constexpr ((XF & kXfDfl) != 0 && sizeof(AccT) == 8) {
-      cls(k_col<AccT, kColDfl, kDtDfl32>, k_col_w<AccT, kColDfl, kDtDfl32>, kDtDfl32);
-      cls(k_col<AccT, kColDfl, kDtDfl40>, k_col_w<AccT, kColDfl, kDtDfl40>, kDtDfl40);
-      cls(k_col<AccT, kColDfl, kDtDfl48>, k_col_w<AccT, kColDfl, kDtDfl48>, kDtDfl48);
+      // DFL stores pair the IEEE class with DFL32 and DFL40 with DFL48 (a
+      // pair of DFL16 and DFL24 was slower: DFL16 would lose a workgroup per CU)
+      if (!pair(k_col_w2<AccT, kColIeee, -1, kColDfl, kDtDfl32>, 0, 0, ce[HM_BF16], kDtDfl32, ce[kDtDfl32])) {
+        run(k_col<AccT, kColIeee>, k_col_w<AccT, kColIeee>, 0, 0, ce[HM_BF16]);
+        cls(k_col<AccT, kColDfl, kDtDfl32>, k_col_w<AccT, kColDfl, kDtDfl32>, kDtDfl32);
+      }
+      if (!pair(k_col_w2<AccT, kColDfl, kDtDfl40, kColDfl, kDtDfl48>, kDtDfl40, ce[kDtDfl40 - 1], ce[kDtDfl40],
+                kDtDfl48, ce[kDtDfl48])) {
+        cls(k_col<AccT, kColDfl, kDtDfl40>, k_col_w<AccT, kColDfl, kDtDfl40>, kDtDfl40);
+        cls(k_col<AccT, kColDfl, kDtDfl48>, k_col_w<AccT, kColDfl, kDtDfl48>, kDtDfl48);
+      }
       cls(k_col<AccT, kColDfl, kDtDfl16>, k_col_w<AccT, kColDfl, kDtDfl16>, kDtDfl16);
       cls(k_col<AccT, kColDfl, kDtDfl24>, k_col_w<AccT, kColDfl, kDtDfl24>, kDtDfl24);
+    } else {
+      run(k_col<AccT, kColIeee>, k_col_w<AccT, kColIeee>, 0, 0, ce[HM_BF16]);
     }
     if constexpr ((XF & kXfAflp) != 0 && sizeof(AccT) == 8) {
       cls(k_col<AccT, kColAflp, kDtAflp16>, k_col_w<AccT, kColAflp, kDtAflp16>, kDtAflp16);
