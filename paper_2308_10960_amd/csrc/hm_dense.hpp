@@ -169,62 +169,78 @@ __device__ inline void apply_q(const double* A, int64_t m, int r, const double* 
   }
 }
 
-// Householder QR of A (m x r, column-major, leading dimension lda, m >= r,
-// r <= kWThreads) in place, as qr_inplace, with one thread per column: the
-// owner of column k forms the reflector, then every later column's thread
-// applies it over the rows by itself (no cross-thread sums).  Meant for A in
-// LDS, where the reflector's entries are broadcast reads.
-__device__ inline void qr_cols(double* A, int lda, int m, int r, double* tau) {
-  const int tid = threadIdx.x;
-  for (int k = 0; k < r; ++k) {
-    double* a = A + k * lda;
-    if (tid == k) {
-      double p = 0;
-      for (int i = k; i < m; ++i) p += a[i] * a[i];
-      const double nrm = sqrt(p);
-      if (nrm == 0) {
-        tau[k] = 0;
-      } else {
-        const double akk = a[k];
-        const double alpha = akk > 0 ? -nrm : nrm;
-        const double v0 = akk - alpha;
-        const double iv = 1.0 / v0;
-        for (int i = k + 1; i < m; ++i) a[i] *= iv;
-        a[k] = alpha;
-        tau[k] = -v0 / alpha;
-      }
-    }
-    __syncthreads();
-    const double tk = tau[k];
-    if (tk != 0 && tid > k && tid < r) {
-      double* c = A + tid * lda;
-      double s = c[k];
-      for (int i = k + 1; i < m; ++i) s += a[i] * c[i];
-      s *= tk;
-      c[k] -= s;
-      for (int i = k + 1; i < m; ++i) c[i] -= s * a[i];
-    }
-    __syncthreads();
-  }
+// Orders the LDS accesses of the calling wave's lanes (no workgroup barrier).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Z := H_0 ... H_{r-1} Z (Z m x k, leading dimension ldz, k <= kWThreads)
-// with the reflectors of qr_cols / qr_inplace in A (leading dimension lda),
-// one thread per column of Z.
-__device__ inline void apply_q_cols(const double* A, int lda, int m, int r, const double* tau, double* Z, int ldz,
-                                    int k) {
-  const int tid = threadIdx.x;
-  if (tid < k) {
-    double* z = Z + tid * ldz;
+// Householder QR of A (m x r, column-major, leading dimension lda, m >= r)
+// in place, in the convention of qr_inplace; meant for A in LDS.  Step k:
+// every wave forms the reflector of column k from the column's sum of
+// squares (a wave sum over the rows, the same value in every wave); wave w
+// applies it to the later columns j = k + 1 + w, k + 1 + w + kWWaves, ...,
+// its lanes over the rows with a wave sum per column; after the step's
+// barrier wave 0 scales column k to the reflector.  One barrier per step.
+__device__ inline void qr_waves(double* A, int lda, int m, int r, double* tau) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int k = 0; k < r; ++k) {
+    double* a = A + (int64_t)k * lda;
+    double p = 0;
+    for (int i = k + 1 + lane; i < m; i += 64) p += a[i] * a[i];
+    p = wave_sum(p);
+    const double akk = a[k];
+    const double nrm = sqrt(akk * akk + p);
+    double tk = 0, iv = 0, alpha = akk;
+    if (nrm != 0) {
+      alpha = akk > 0 ? -nrm : nrm;
+      const double v0 = akk - alpha;
+      iv = 1.0 / v0;
+      tk = -v0 / alpha;
+    }
+    if (tk != 0)
+      for (int j = k + 1 + w; j < r; j += kWWaves) {
+        double* c = A + (int64_t)j * lda;
+        double s = 0;
+        for (int i = k + 1 + lane; i < m; i += 64) s += a[i] * c[i];
+        s = (c[k] + wave_sum(s) * iv) * tk;
+        for (int i = k + 1 + lane; i < m; i += 64) c[i] -= s * (a[i] * iv);
+        if (lane == 0) c[k] -= s;
+      }
+    __syncthreads();
+    if (w == 0) {
+      if (tk != 0)
+        for (int i = k + 1 + lane; i < m; i += 64) a[i] *= iv;
+      if (lane == 0) {
+        a[k] = alpha;
+        tau[k] = tk;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Z := H_0 ... H_{r-1} Z (Z m x k, leading dimension ldz) with the
+// reflectors of qr_waves / qr_inplace in A (leading dimension lda): wave w
+// takes the columns w, w + kWWaves, ... of Z and applies the reflectors
+// r - 1, ..., 0 to each, its lanes over the rows (no workgroup barrier
+// between reflectors).
+__device__ inline void apply_q_waves(const double* A, int lda, int m, int r, const double* tau, double* Z, int ldz,
+                                     int k) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int c = w; c < k; c += kWWaves) {
+    double* z = Z + (int64_t)c * ldz;
     for (int j = r - 1; j >= 0; --j) {
       const double tj = tau[j];
       if (tj == 0) continue;
-      const double* v = A + j * lda;
-      double s = z[j];
-      for (int i = j + 1; i < m; ++i) s += v[i] * z[i];
-      s *= tj;
-      z[j] -= s;
-      for (int i = j + 1; i < m; ++i) z[i] -= s * v[i];
+      const double* v = A + (int64_t)j * lda;
+      double s = 0;
+      for (int i = j + 1 + lane; i < m; i += 64) s += v[i] * z[i];
+      s = (z[j] + wave_sum(s)) * tj;
+      for (int i = j + 1 + lane; i < m; i += 64) z[i] -= s * v[i];
+      if (lane == 0) z[j] -= s;
+      wave_fence();                                 // z as updated, for the next reflector
     }
   }
   __syncthreads();
@@ -261,10 +277,10 @@ __device__ __forceinline__ double group16_sum(double v) {
 // Algorithm 1 on U (m x r) and V (n x r), both column-major with leading
 // dimensions m and n, m >= r, n >= r, r <= kMaxR; U and V are overwritten
 // by their QR factors.  lds: lds_doubles doubles of LDS, which hold a
-// factor for its QR (one thread per column) when it fits, then the two
-// r x r matrices of the SVD when they fit (else gscr, 2 r^2 doubles of
-// global memory, holds them), then reflectors and result for the
-// application of Q.  W must hold m x r doubles and X n x r (they also serve
+// factor for its QR (qr_waves) when it fits, then the two r x r matrices
+// of the SVD when they fit (else gscr, 2 r^2 doubles of global memory,
+// holds them) and the reflectors of Q_B when a third fits (else X), then
+// reflectors and result for the application of Q.  W must hold m x r doubles and X n x r (they also serve
 // as scratch).  Householder QR
 // of U and V, B = R_U R_V^T, the SVD of B by a QR with column pivoting
 // (B P = Q_B R) and one-sided Jacobi on R^T (round-robin ordering: in each
@@ -279,12 +295,12 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
                                     int64_t lds_doubles, double* gscr, TruncShared& sh, double* W, double* X,
                                     bool fold, double* sg) {
   const int tid = threadIdx.x;
-  // QR of U and of V: in LDS, one thread per column, when the factor fits
+  // QR of U and of V: in LDS (qr_waves) when the factor fits
   auto qr = [&](double* F, int64_t rows, double* tau) {
     const int ld = (int)(rows | 1);
     if ((int64_t)ld * r <= lds_doubles && rows <= 4096) {
       copy_mat(F, rows, lds, ld, rows, r);
-      qr_cols(lds, ld, (int)rows, r, tau);
+      qr_waves(lds, ld, (int)rows, r, tau);
       copy_mat(lds, ld, F, rows, rows, r);
     } else {
       qr_inplace(F, rows, r, tau, sh.sred, sh.sv);
@@ -312,25 +328,38 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   for (int e = tid; e < r * r; e += kWThreads) Am[e] = W[e];
   for (int j = tid; j < r; j += kWThreads) sh.perm[j] = j;
   __syncthreads();
-  // QR with column pivoting of B (B P = Q_B R; in place in Am, one thread
-  // per column; the largest remaining column first, the lowest index on
-  // ties).  One-sided Jacobi on R^T then converges in a few sweeps, R being
-  // graded.
+  // QR with column pivoting of B (B P = Q_B R; in place in Am): the
+  // largest remaining column first, the lowest index on ties.  Column norms
+  // by wave sums (wave w the columns k + w, k + w + kWWaves, ...), the
+  // argmax by wave 0, then the step of qr_waves.  One-sided Jacobi on R^T
+  // then converges in a few sweeps, R being graded.
+  const int lane = tid & 63, wv = tid >> 6;
   for (int k = 0; k < r; ++k) {
-    if (tid >= k && tid < r) {
+    for (int j = k + wv; j < r; j += kWWaves) {
       double s2 = 0;
-      for (int i = k; i < r; ++i) s2 += Am[tid * r + i] * Am[tid * r + i];
-      sh.nrm[tid] = s2;
+      for (int i = k + lane; i < r; i += 64) s2 += Am[j * r + i] * Am[j * r + i];
+      s2 = wave_sum(s2);
+      if (lane == 0) sh.nrm[j] = s2;
     }
     __syncthreads();
-    if (tid == 0) {
-      int jb = k;
-      for (int j = k + 1; j < r; ++j)
-        if (sh.nrm[j] > sh.nrm[jb]) jb = j;
-      sh.piv = jb;
-      const int t = sh.perm[k];
-      sh.perm[k] = sh.perm[jb];
-      sh.perm[jb] = t;
+    if (wv == 0) {
+      double best = -1.0;
+      int bj = r;
+      for (int j = k + lane; j < r; j += 64)
+        if (sh.nrm[j] > best) { best = sh.nrm[j]; bj = j; }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oj = __shfl_xor(bj, o, 64);
+        if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+      }
+      if (lane == 0) {
+        const int jb = bj < r ? bj : k;
+        sh.piv = jb;
+        const int t = sh.perm[k];
+        sh.perm[k] = sh.perm[jb];
+        sh.perm[jb] = t;
+      }
     }
     __syncthreads();
     const int jb = sh.piv;
@@ -342,39 +371,44 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
       }
     __syncthreads();
     double* a = Am + k * r;
-    if (tid == k) {
-      const double nrm = sqrt(sh.nrm[jb]);
-      if (nrm == 0) {
-        sh.tauB[k] = 0;
-      } else {
-        const double akk = a[k];
-        const double alpha = akk > 0 ? -nrm : nrm;
-        const double v0 = akk - alpha;
-        const double iv = 1.0 / v0;
-        for (int i = k + 1; i < r; ++i) a[i] *= iv;
+    const double nrm = sqrt(sh.nrm[jb]);
+    const double akk = a[k];
+    double tk = 0, iv = 0, alpha = akk;
+    if (nrm != 0) {
+      alpha = akk > 0 ? -nrm : nrm;
+      const double v0 = akk - alpha;
+      iv = 1.0 / v0;
+      tk = -v0 / alpha;
+    }
+    if (tk != 0)
+      for (int j = k + 1 + wv; j < r; j += kWWaves) {
+        double* c = Am + j * r;
+        double s = 0;
+        for (int i = k + 1 + lane; i < r; i += 64) s += a[i] * c[i];
+        s = (c[k] + wave_sum(s) * iv) * tk;
+        for (int i = k + 1 + lane; i < r; i += 64) c[i] -= s * (a[i] * iv);
+        if (lane == 0) c[k] -= s;
+      }
+    __syncthreads();
+    if (wv == 0) {
+      if (tk != 0)
+        for (int i = k + 1 + lane; i < r; i += 64) a[i] *= iv;
+      if (lane == 0) {
         a[k] = alpha;
-        sh.tauB[k] = -v0 / alpha;
+        sh.tauB[k] = tk;
       }
     }
     __syncthreads();
-    const double tk = sh.tauB[k];
-    if (tk != 0 && tid > k && tid < r) {
-      double* c = Am + tid * r;
-      double s = c[k];
-      for (int i = k + 1; i < r; ++i) s += a[i] * c[i];
-      s *= tk;
-      c[k] -= s;
-      for (int i = k + 1; i < r; ++i) c[i] -= s * a[i];
-    }
-    __syncthreads();
   }
-  // reflectors of Q_B (and R) to X (r x r, leading dimension r), then
-  // Am := R^T (lower triangular), Vs := I
-  for (int e = tid; e < r * r; e += kWThreads) X[e] = Am[e];
+  // reflectors of Q_B (and R) to Qb (r x r, leading dimension r: in LDS
+  // after Am and Vs when there is room, else X), then Am := R^T (lower
+  // triangular), Vs := I
+  double* Qb = (Am == lds && 3 * (int64_t)r * r <= lds_doubles) ? lds + 2 * (int64_t)r * r : X;
+  for (int e = tid; e < r * r; e += kWThreads) Qb[e] = Am[e];
   __syncthreads();
   for (int e = tid; e < r * r; e += kWThreads) {
     const int i = e % r, j = e / r;                  // Am(i, j) = R(j, i)
-    Am[e] = j <= i ? X[i * r + j] : 0.0;
+    Am[e] = j <= i ? Qb[i * r + j] : 0.0;
     Vs[e] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -475,13 +509,13 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   // B = (Q_B Vs) diag(S) (P Am / S)^T: the left singular vectors are Q_B
   // applied to the columns of Vs (reflectors in X), the right ones the
   // normalized columns of Am with their rows permuted back by P
-  apply_q_cols(X, r, r, r, sh.tauB, Vs, r, r);
+  apply_q_waves(Qb, r, r, r, sh.tauB, Vs, r, r);
   // W = Q_U [left(:, 1:k); 0], X = Q_V [right(:, 1:k); 0]
   for (int c = 0; c < k; ++c) {
     const int j = sh.ord[c];
     for (int64_t i = tid; i < m; i += kWThreads) W[(int64_t)c * m + i] = i < r ? Vs[j * r + i] : 0.0;
   }
-  __syncthreads();                                  // the reflectors in X are read no more
+  __syncthreads();                                  // the reflectors in Qb are read no more
   for (int c = 0; c < k; ++c) {
     const int j = sh.ord[c];
     const double inv = sh.S[c] > 0 ? 1.0 / sh.S[c] : 0.0;
@@ -490,13 +524,13 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
     for (int i = tid; i < r; i += kWThreads) X[(int64_t)c * n + sh.perm[i]] = Am[j * r + i] * inv;
   }
   __syncthreads();
-  // W := Q_U W, X := Q_V X: reflectors and result in LDS, one thread per column, when they fit
+  // W := Q_U W, X := Q_V X: reflectors and result in LDS (apply_q_waves) when they fit
   auto applyq = [&](const double* F, int64_t rows, const double* tau, double* Z) {
     const int ld = (int)(rows | 1);
     if ((int64_t)ld * (r + k) <= lds_doubles && rows <= 4096) {
       copy_mat(F, rows, lds, ld, rows, r);
       copy_mat(Z, rows, lds + (int64_t)ld * r, ld, rows, k);
-      apply_q_cols(lds, ld, (int)rows, r, tau, lds + (int64_t)ld * r, ld, k);
+      apply_q_waves(lds, ld, (int)rows, r, tau, lds + (int64_t)ld * r, ld, k);
       copy_mat(lds + (int64_t)ld * r, ld, Z, rows, rows, k);
     } else {
       apply_q(F, rows, r, tau, Z, k, sh.sred);
