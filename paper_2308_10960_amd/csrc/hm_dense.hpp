@@ -22,11 +22,39 @@ constexpr int kWThreads = 256;
 constexpr int kWWaves = kWThreads / 64;
 constexpr int kMaxR = 256;    // widest factor pair the shared arrays hold
 
-// Sum over the wave, the same value in every lane (lane 0's result).
+// v of the lane that the DPP pattern CTRL names (rows in ROW_MASK; the lanes
+// of the other rows get 0).  Both 32-bit halves move the same way.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over each row of 16 lanes, the row's total in all its lanes: pairs
+// (quad_perm 1,0,3,2), quads (2,3,0,1), half rows (row_half_mirror), rows
+// (row_mirror).  Row-local, so rows of a wave that are inactive do not
+// matter.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_move<0xB1, 0xF>(v);
+  v += dpp_move<0x4E, 0xF>(v);
+  v += dpp_move<0x141, 0xF>(v);
+  v += dpp_move<0x140, 0xF>(v);
+  return v;
+}
+
+// Sum over the wave, the same value in every lane (a fixed order): the row
+// sums, then rows 0 + 1 and 2 + 3 by row_bcast15, all four rows by
+// row_bcast31 into lane 63, read back into every lane.  Every lane of the
+// wave must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return __shfl(v, 0, 64);
+  v = row16_sum(v);
+  v += dpp_move<0x142, 0xA>(v);
+  v += dpp_move<0x143, 0xC>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // Sum over the workgroup, the same value in every thread.  sred: kWWaves
@@ -267,12 +295,9 @@ struct TruncShared {
   int piv;
 };
 
-// Sum over the 16 lanes of a lane group (the group's lanes get the total).
-__device__ __forceinline__ double group16_sum(double v) {
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
-  return v;
-}
+// Sum over the 16 lanes of a lane group (a DPP row; the group's lanes get
+// the total).
+__device__ __forceinline__ double group16_sum(double v) { return row16_sum(v); }
 
 // Algorithm 1 on U (m x r) and V (n x r), both column-major with leading
 // dimensions m and n, m >= r, n >= r, r <= kMaxR; U and V are overwritten
