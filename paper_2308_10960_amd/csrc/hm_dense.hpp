@@ -456,9 +456,11 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
         if (pi == 0) {
           p = t;
           q = R - 1;
-        } else {
-          p = (t + pi) % (R - 1);
-          q = (t - pi + (R - 1)) % (R - 1);
+        } else {                                     // (t + pi) mod (R - 1), (t - pi) mod (R - 1)
+          p = t + pi;
+          if (p >= R - 1) p -= R - 1;
+          q = t - pi;
+          if (q < 0) q += R - 1;
         }
         if (p > q) { const int x = p; p = q; q = x; }
         if (q >= r) continue;                        // the same for the whole group
@@ -474,9 +476,8 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
         be = group16_sum(be);
         ga = group16_sum(ga);
         if (ga == 0 || al <= tiny || be <= tiny) continue;
-        const double rel = fabs(ga) / sqrt(al * be);
-        if (!(rel > 1e-15)) continue;
-        off = std::max(off, rel);
+        if (!(ga * ga > 1e-30 * (al * be))) continue;      // |ga| / sqrt(al be) <= 1e-15: converged
+        off = 1;                                            // a rotation in this sweep
         const double zeta = (be - al) / (2.0 * ga);
         const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
@@ -498,7 +499,7 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
     if (tid == 0) {
       double o = 0;
       for (int g = 0; g < ngrp; ++g) o = std::max(o, sh.offg[g]);
-      sh.more = o > 1e-15;
+      sh.more = o > 0;
     }
     __syncthreads();
     if (!sh.more) break;
