@@ -71,141 +71,19 @@ __device__ __forceinline__ double block_sum(double v, double* sred) {
   return s;
 }
 
-constexpr int kJB = 8;        // columns whose dot products one pass over the rows forms
-
-// Householder QR of A (m x r, column-major, m >= r) in place: R in the upper
-// triangle, the reflectors v_j (v_j[j] = 1 implied) below the diagonal, and
-// tau_j in tau (LDS), H_j = I - tau_j v_j v_j^T.  Thread t owns the rows
-// i = t (mod kWThreads).  The dot products of the reflector with the later
-// columns are formed kJB columns per pass over the rows, so that the loads
-// of several columns are in flight together.  sred: kWWaves x kMaxR doubles
-// of LDS.
-__device__ inline void qr_inplace(double* A, int64_t m, int r, double* tau, double (*sred)[kMaxR], double* sv) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int k = 0; k < r; ++k) {
-    double* a = A + (int64_t)k * m;
-    const double akk = a[k];
-    double p = 0;
-    for (int64_t i = k + tid; i < m; i += kWThreads) p += a[i] * a[i];
-    const double nrm = sqrt(block_sum(p, sv));
-    if (nrm == 0) {
-      if (tid == 0) tau[k] = 0;
-      __syncthreads();
-      continue;
-    }
-    const double alpha = akk > 0 ? -nrm : nrm;
-    const double v0 = akk - alpha;
-    const double tk = -v0 / alpha;
-    const bool own_k = (k % kWThreads) == tid;
-    const int64_t i1 = k + 1 + ((tid - (k + 1) % kWThreads + kWThreads) % kWThreads);
-    for (int64_t i = i1; i < m; i += kWThreads) a[i] /= v0;
-    if (own_k) a[k] = alpha;
-    if (tid == 0) tau[k] = tk;
-    // s_j = tau_k (c_j[k] + sum_{i > k} v[i] c_j[i]) for the later columns
-    for (int j0 = k + 1; j0 < r; j0 += kJB) {
-      double s[kJB];
-#pragma unroll
-      for (int u = 0; u < kJB; ++u) s[u] = (own_k && j0 + u < r) ? A[(int64_t)(j0 + u) * m + k] : 0.0;
-      for (int64_t i = i1; i < m; i += kWThreads) {
-        const double ai = a[i];
-#pragma unroll
-        for (int u = 0; u < kJB; ++u)
-          if (j0 + u < r) s[u] += ai * A[(int64_t)(j0 + u) * m + i];
-      }
-#pragma unroll
-      for (int u = 0; u < kJB; ++u) {
-        const double t = wave_sum(s[u]);
-        if (lane == 0 && j0 + u < r) sred[wave][j0 + u] = t;
-      }
-    }
-    __syncthreads();
-    for (int j0 = k + 1; j0 < r; j0 += kJB) {
-      double f[kJB];
-#pragma unroll
-      for (int u = 0; u < kJB; ++u) {
-        double t = 0;
-#pragma unroll
-        for (int w = 0; w < kWWaves; ++w) t += j0 + u < r ? sred[w][j0 + u] : 0.0;
-        f[u] = t * tk;
-      }
-      if (own_k) {
-#pragma unroll
-        for (int u = 0; u < kJB; ++u)
-          if (j0 + u < r) A[(int64_t)(j0 + u) * m + k] -= f[u];
-      }
-      for (int64_t i = i1; i < m; i += kWThreads) {
-        const double ai = a[i];
-#pragma unroll
-        for (int u = 0; u < kJB; ++u)
-          if (j0 + u < r) A[(int64_t)(j0 + u) * m + i] -= f[u] * ai;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Z := H_0 H_1 ... H_{r-1} Z for Z (m x k, column-major, leading dimension
-// m), the reflectors of qr_inplace in A and tau; kJB columns of Z per pass.
-__device__ inline void apply_q(const double* A, int64_t m, int r, const double* tau, double* Z, int k,
-                               double (*sred)[kMaxR]) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = r - 1; j >= 0; --j) {
-    const double tj = tau[j];
-    if (tj == 0) continue;
-    const double* v = A + (int64_t)j * m;
-    const bool own_j = (j % kWThreads) == tid;
-    const int64_t i0 = j + 1 + ((tid - (j + 1) % kWThreads + kWThreads) % kWThreads);
-    for (int c0 = 0; c0 < k; c0 += kJB) {
-      double s[kJB];
-#pragma unroll
-      for (int u = 0; u < kJB; ++u) s[u] = (own_j && c0 + u < k) ? Z[(int64_t)(c0 + u) * m + j] : 0.0;
-      for (int64_t i = i0; i < m; i += kWThreads) {
-        const double vi = v[i];
-#pragma unroll
-        for (int u = 0; u < kJB; ++u)
-          if (c0 + u < k) s[u] += vi * Z[(int64_t)(c0 + u) * m + i];
-      }
-#pragma unroll
-      for (int u = 0; u < kJB; ++u) {
-        const double t = wave_sum(s[u]);
-        if (lane == 0 && c0 + u < k) sred[wave][c0 + u] = t;
-      }
-    }
-    __syncthreads();
-    for (int c0 = 0; c0 < k; c0 += kJB) {
-      double f[kJB];
-#pragma unroll
-      for (int u = 0; u < kJB; ++u) {
-        double t = 0;
-#pragma unroll
-        for (int w = 0; w < kWWaves; ++w) t += c0 + u < k ? sred[w][c0 + u] : 0.0;
-        f[u] = t * tj;
-      }
-      if (own_j) {
-#pragma unroll
-        for (int u = 0; u < kJB; ++u)
-          if (c0 + u < k) Z[(int64_t)(c0 + u) * m + j] -= f[u];
-      }
-      for (int64_t i = i0; i < m; i += kWThreads) {
-        const double vi = v[i];
-#pragma unroll
-        for (int u = 0; u < kJB; ++u)
-          if (c0 + u < k) Z[(int64_t)(c0 + u) * m + i] -= f[u] * vi;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Orders the LDS accesses of the calling wave's lanes (no workgroup barrier).
+// Orders the memory accesses (LDS or global) of the calling wave's lanes:
+// what a lane wrote before is seen by every lane of the wave after (no
+// workgroup barrier).
 __device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // Householder QR of A (m x r, column-major, leading dimension lda, m >= r)
-// in place, in the convention of qr_inplace; meant for A in LDS.  Step k:
+// in place, in LDS or global memory: R in the upper triangle, the
+// reflectors v_j (v_j[j] = 1 implied) below the diagonal, and tau_j in tau
+// (LDS), H_j = I - tau_j v_j v_j^T.  Step k:
 // every wave forms the reflector of column k from the column's sum of
 // squares (a wave sum over the rows, the same value in every wave); wave w
 // applies it to the later columns j = k + 1 + w, k + 1 + w + kWWaves, ...,
@@ -249,8 +127,8 @@ __device__ inline void qr_waves(double* A, int lda, int m, int r, double* tau) {
   __syncthreads();
 }
 
-// Z := H_0 ... H_{r-1} Z (Z m x k, leading dimension ldz) with the
-// reflectors of qr_waves / qr_inplace in A (leading dimension lda): wave w
+// Z := H_0 ... H_{r-1} Z (Z m x k, leading dimension ldz; LDS or global
+// memory) with the reflectors of qr_waves in A (leading dimension lda): wave w
 // takes the columns w, w + kWWaves, ... of Z and applies the reflectors
 // r - 1, ..., 0 to each, its lanes over the rows (no workgroup barrier
 // between reflectors).
@@ -282,7 +160,6 @@ __device__ inline void copy_mat(const double* src, int64_t lds, double* dst, int
 
 // LDS the truncation core needs besides its two dynamic r x r matrices.
 struct TruncShared {
-  double sred[kWWaves][kMaxR];
   double sv[kWWaves];
   double tauU[kMaxR], tauV[kMaxR];
   double nrm[kMaxR], S[kMaxR];
@@ -328,7 +205,7 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
       qr_waves(lds, ld, (int)rows, r, tau);
       copy_mat(lds, ld, F, rows, rows, r);
     } else {
-      qr_inplace(F, rows, r, tau, sh.sred, sh.sv);
+      qr_waves(F, (int)rows, (int)rows, r, tau);      // in global memory
     }
   };
   qr(U, m, sh.tauU);
@@ -559,7 +436,7 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
       apply_q_waves(lds, ld, (int)rows, r, tau, lds + (int64_t)ld * r, ld, k);
       copy_mat(lds + (int64_t)ld * r, ld, Z, rows, rows, k);
     } else {
-      apply_q(F, rows, r, tau, Z, k, sh.sred);
+      apply_q_waves(F, (int)rows, (int)rows, r, tau, Z, (int)rows, k);   // in global memory
     }
   };
   applyq(U, m, sh.tauU, W);
