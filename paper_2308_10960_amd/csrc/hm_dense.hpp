@@ -131,12 +131,13 @@ __device__ inline void qr_waves(double* A, int lda, int m, int r, double* tau) {
 // memory) with the reflectors of qr_waves in A (leading dimension lda): wave w
 // takes the columns w, w + kWWaves, ... of Z and applies the reflectors
 // r - 1, ..., 0 to each, its lanes over the rows (no workgroup barrier
-// between reflectors).
+// between reflectors).  cols: when not null, column c of Z is column
+// cols[c] of the array at Z (only those columns are transformed).
 __device__ inline void apply_q_waves(const double* A, int lda, int m, int r, const double* tau, double* Z, int ldz,
-                                     int k) {
+                                     int k, const int* cols = nullptr) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int c = w; c < k; c += kWWaves) {
-    double* z = Z + (int64_t)c * ldz;
+    double* z = Z + (int64_t)(cols ? cols[c] : c) * ldz;
     for (int j = r - 1; j >= 0; --j) {
       const double tj = tau[j];
       if (tj == 0) continue;
@@ -410,9 +411,9 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   __syncthreads();
   const int k = sh.keep;
   // B = (Q_B Vs) diag(S) (P Am / S)^T: the left singular vectors are Q_B
-  // applied to the columns of Vs (reflectors in X), the right ones the
+  // applied to the columns of Vs (reflectors in Qb), the right ones the
   // normalized columns of Am with their rows permuted back by P
-  apply_q_waves(Qb, r, r, r, sh.tauB, Vs, r, r);
+  apply_q_waves(Qb, r, r, r, sh.tauB, Vs, r, k, sh.ord);      // the k kept columns only
   // W = Q_U [left(:, 1:k); 0], X = Q_V [right(:, 1:k); 0]
   for (int c = 0; c < k; ++c) {
     const int j = sh.ord[c];
