@@ -21,6 +21,7 @@ namespace dense {
 constexpr int kWThreads = 256;
 constexpr int kWWaves = kWThreads / 64;
 constexpr int kMaxR = 256;    // widest factor pair the shared arrays hold
+constexpr int kJacobiLanes = 8;   // lanes that rotate one column pair of the Jacobi step
 
 // v of the lane that the DPP pattern CTRL names (rows in ROW_MASK; the lanes
 // of the other rows get 0).  Both 32-bit halves move the same way.
@@ -164,7 +165,7 @@ struct TruncShared {
   double sv[kWWaves];
   double tauU[kMaxR], tauV[kMaxR];
   double nrm[kMaxR], S[kMaxR];
-  double offg[kWThreads / 16];
+  double offg[kWThreads / kJacobiLanes];
   double tauB[kMaxR];
   int ord[kMaxR];
   int perm[kMaxR];
@@ -173,9 +174,14 @@ struct TruncShared {
   int piv;
 };
 
-// Sum over the 16 lanes of a lane group (a DPP row; the group's lanes get
-// the total).
-__device__ __forceinline__ double group16_sum(double v) { return row16_sum(v); }
+// Sum over the 8 lanes of a Jacobi lane group (half a DPP row; the group's
+// lanes get the total): pairs, quads, then row_half_mirror.
+__device__ __forceinline__ double group_sum(double v) {
+  v += dpp_move<0xB1, 0xF>(v);
+  v += dpp_move<0x4E, 0xF>(v);
+  v += dpp_move<0x141, 0xF>(v);
+  return v;
+}
 
 // Algorithm 1 on U (m x r) and V (n x r), both column-major with leading
 // dimensions m and n, m >= r, n >= r, r <= kMaxR; U and V are overwritten
@@ -187,7 +193,7 @@ __device__ __forceinline__ double group16_sum(double v) { return row16_sum(v); }
 // as scratch).  Householder QR
 // of U and V, B = R_U R_V^T, the SVD of B by a QR with column pivoting
 // (B P = Q_B R) and one-sided Jacobi on R^T (round-robin ordering: in each
-// round 16-lane groups rotate disjoint column pairs in parallel; the
+// round 8-lane groups rotate disjoint column pairs in parallel; the
 // pivoting grades R, so that few sweeps are needed), singular values
 // sorted descending (stable), k the smallest rank whose Frobenius tail is
 // <= eps times the whole; then W = Q_U U_s(:, 1:k) (times diag(S) when
@@ -320,7 +326,7 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   // pair with the player r, when r is odd, is skipped); afterwards
   // Am = R^T Vs has orthogonal columns
   const int R = r + (r & 1);
-  const int grp = tid >> 4, gl = tid & 15, ngrp = kWThreads / 16;
+  const int grp = tid / kJacobiLanes, gl = tid % kJacobiLanes, ngrp = kWThreads / kJacobiLanes;
   // columns below 1e-16 |B|_F carry no singular value the truncation can
   // see and only rounding noise: pairs with such a column are not rotated
   double fro2 = 0;
@@ -345,14 +351,14 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
         double* ap = Am + p * r;
         double* aq = Am + q * r;
         double al = 0, be = 0, ga = 0;
-        for (int i = gl; i < r; i += 16) {
+        for (int i = gl; i < r; i += kJacobiLanes) {
           al += ap[i] * ap[i];
           be += aq[i] * aq[i];
           ga += ap[i] * aq[i];
         }
-        al = group16_sum(al);
-        be = group16_sum(be);
-        ga = group16_sum(ga);
+        al = group_sum(al);
+        be = group_sum(be);
+        ga = group_sum(ga);
         if (ga == 0 || al <= tiny || be <= tiny) continue;
         if (!(ga * ga > 1e-30 * (al * be))) continue;      // |ga| / sqrt(al be) <= 1e-15: converged
         off = 1;                                            // a rotation in this sweep
@@ -361,7 +367,7 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
         const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
         double* vp = Vs + p * r;
         double* vq = Vs + q * r;
-        for (int i = gl; i < r; i += 16) {
+        for (int i = gl; i < r; i += kJacobiLanes) {
           const double x = ap[i], y = aq[i];
           ap[i] = c * x - sn * y;
           aq[i] = sn * x + c * y;
