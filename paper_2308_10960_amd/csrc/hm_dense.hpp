@@ -240,7 +240,8 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   // QR with column pivoting of B (B P = Q_B R; in place in Am): the
   // largest remaining column first, the lowest index on ties.  Column norms
   // by wave sums (wave w the columns k + w, k + w + kWWaves, ...), the
-  // argmax by wave 0, then the step of qr_waves.  One-sided Jacobi on R^T
+  // argmax and the column swap by wave 0, then the step of qr_waves: three
+  // barriers per step.  One-sided Jacobi on R^T
   // then converges in a few sweeps, R being graded.
   const int lane = tid & 63, wv = tid >> 6;
   for (int k = 0; k < r; ++k) {
@@ -262,8 +263,15 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
         const int oj = __shfl_xor(bj, o, 64);
         if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
       }
+      // every lane holds the same (best, bj): max and the index rule are exact
+      const int jb = bj < r ? bj : k;
+      if (jb != k)
+        for (int i = lane; i < r; i += 64) {
+          const double t = Am[k * r + i];
+          Am[k * r + i] = Am[jb * r + i];
+          Am[jb * r + i] = t;
+        }
       if (lane == 0) {
-        const int jb = bj < r ? bj : k;
         sh.piv = jb;
         const int t = sh.perm[k];
         sh.perm[k] = sh.perm[jb];
@@ -272,13 +280,6 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
     }
     __syncthreads();
     const int jb = sh.piv;
-    if (jb != k)
-      for (int i = tid; i < r; i += kWThreads) {
-        const double t = Am[k * r + i];
-        Am[k * r + i] = Am[jb * r + i];
-        Am[jb * r + i] = t;
-      }
-    __syncthreads();
     double* a = Am + k * r;
     const double nrm = sqrt(sh.nrm[jb]);
     const double akk = a[k];
@@ -299,6 +300,8 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
         if (lane == 0) c[k] -= s;
       }
     __syncthreads();
+    // wave 0 scales column k to its reflector; the next step touches only
+    // the later columns, so no barrier before it
     if (wv == 0) {
       if (tk != 0)
         for (int i = k + 1 + lane; i < r; i += 64) a[i] *= iv;
@@ -307,8 +310,8 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
         sh.tauB[k] = tk;
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   // reflectors of Q_B (and R) to Qb (r x r, leading dimension r: in LDS
   // after Am and Vs when there is room, else X), then Am := R^T (lower
   // triangular), Vs := I
