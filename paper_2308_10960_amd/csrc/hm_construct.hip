@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_aca(const hm_cblock* __restrict__ 
       c = wave_sum(c);
       if (lane == 0) { sa[wave][l] = a; sb[wave][l] = c; }
     }
-    const double nu = block_sum(pu, sv), nv = block_sum(pv, sv);   // synchronizes: sa, sb complete
+    const double nu = block_sum<kWaves>(pu, sv), nv = block_sum<kWaves>(pv, sv);   // synchronizes: sa, sb complete
     double cross = 0;
     for (int l = 0; l < r; ++l) {
       double a = 0, c = 0;
@@ -204,11 +204,12 @@ __global__ __launch_bounds__(kThreads) void k_aca(const hm_cblock* __restrict__ 
 }
 
 // Algorithm 1 on the ACA factors of one leaf whose ACA rank r lies in
-// (rlo, rhi] (the other leaves of the launch return at once).  LDS
+// (rlo, rhi] (the other leaves of the launch return at once), one workgroup
+// of dense::kWThreads threads per leaf.  LDS
 // (dynamic): the r x r matrix being orthogonalized (B, then U_s diag(S)) and
 // V_s, both column-major with leading dimension r.  Output: W (m x k) at
 // out, X (n x k) at out + m cap, s (k) at out + (m + n) cap; rank = k.
-__global__ __launch_bounds__(kThreads) void k_recompress(const hm_cblock* __restrict__ blocks, int rlo, int rhi,
+__global__ __launch_bounds__(dense::kWThreads) void k_recompress(const hm_cblock* __restrict__ blocks, int rlo, int rhi,
                                                           double eps, int keep_sigma, double* __restrict__ out,
                                                           double* __restrict__ scr,
                                                           const int32_t* __restrict__ aca_rank,
@@ -305,7 +306,7 @@ hipError_t launch_construct(const hm_cblock* d_blocks, int64_t n_blocks, const d
   for (int c = 0; c < 3; ++c) {
     const int lo = bounds[c], hi = bounds[c + 1];
     if (hi <= lo) continue;
-    hipLaunchKernelGGL(k_recompress, grid, dim3(kThreads), (size_t)16 * hi * hi, s, d_blocks, lo, hi, o.eps,
+    hipLaunchKernelGGL(k_recompress, grid, dim3(dense::kWThreads), (size_t)16 * hi * hi, s, d_blocks, lo, hi, o.eps,
                        o.keep_sigma, d_out, d_scr, d_aca_rank, d_rank);
   }
   return hipGetLastError();

@@ -18,7 +18,7 @@
 namespace hm {
 namespace dense {
 
-constexpr int kWThreads = 256;
+constexpr int kWThreads = 512;
 constexpr int kWWaves = kWThreads / 64;
 constexpr int kMaxR = 256;    // widest factor pair the shared arrays hold
 constexpr int kJacobiLanes = 8;   // lanes that rotate one column pair of the Jacobi step
@@ -58,8 +58,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Sum over the workgroup, the same value in every thread.  sred: kWWaves
-// doubles of LDS; the call synchronizes twice.
+// Sum over a workgroup of NW waves, the same value in every thread.  sred:
+// NW doubles of LDS; the call synchronizes twice.
+template <int NW = kWWaves>
 __device__ __forceinline__ double block_sum(double v, double* sred) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -67,7 +68,7 @@ __device__ __forceinline__ double block_sum(double v, double* sred) {
   __syncthreads();
   double s = 0;
 #pragma unroll
-  for (int w = 0; w < kWWaves; ++w) s += sred[w];
+  for (int w = 0; w < NW; ++w) s += sred[w];
   __syncthreads();
   return s;
 }

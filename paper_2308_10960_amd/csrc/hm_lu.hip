@@ -33,6 +33,7 @@ namespace lu {
 namespace {
 
 constexpr int kT = 256;
+constexpr int kTT = dense::kWThreads;   // threads of the truncation kernel (the dense core's workgroup)
 
 __device__ __forceinline__ int64_t dval(const Dim& d) {
   return d.p ? (int64_t)max(0, min(*d.p, (int32_t)d.cap)) : d.v;
@@ -183,7 +184,7 @@ __device__ __forceinline__ double part_v(const Part& p, int64_t j, int64_t c) {
 // m), X (n x capo, ld n), rank_out = k.  A sum wider than kMaxTrunc after
 // the reduction to min(m, n) columns sets *err = 1 and rank 0 (the host
 // reports HM_ERANK).  Dynamic LDS: kTruncLds doubles.
-__global__ __launch_bounds__(kT) void k_trunc(Part p0, Part p1, int64_t m, int64_t n, double eps, double* scr,
+__global__ __launch_bounds__(kTT) void k_trunc(Part p0, Part p1, int64_t m, int64_t n, double eps, double* scr,
                                               double* __restrict__ W, double* __restrict__ X,
                                               int32_t* __restrict__ rank_out, int32_t* __restrict__ err,
                                               double* __restrict__ flog) {
@@ -194,11 +195,11 @@ __global__ __launch_bounds__(kT) void k_trunc(Part p0, Part p1, int64_t m, int64
   int64_t r = k0 + k1;
   double* U = scr;
   double* V = U + m * r;
-  for (int64_t e = tid; e < m * r; e += kT) {
+  for (int64_t e = tid; e < m * r; e += kTT) {
     const int64_t i = e % m, c = e / m;
     U[e] = c < k0 ? p0.sign * part_u(p0, i, c) : p1.sign * part_u(p1, i, c - k0);
   }
-  for (int64_t e = tid; e < n * r; e += kT) {
+  for (int64_t e = tid; e < n * r; e += kTT) {
     const int64_t j = e % n, c = e / n;
     V[e] = c < k0 ? part_v(p0, j, c) : part_v(p1, j, c - k0);
   }
@@ -207,26 +208,26 @@ __global__ __launch_bounds__(kT) void k_trunc(Part p0, Part p1, int64_t m, int64
     // the same matrix with min(m, n) columns: (I_m, V U^T) or (U V^T, I_n)
     double* P = V + n * r;
     if (m <= n) {
-      for (int64_t e = tid; e < n * m; e += kT) {
+      for (int64_t e = tid; e < n * m; e += kTT) {
         const int64_t j = e % n, i = e / n;
         double s = 0;
         for (int64_t c = 0; c < r; ++c) s += V[c * n + j] * U[c * m + i];
         P[e] = s;
       }
       __syncthreads();
-      for (int64_t e = tid; e < m * m; e += kT) U[e] = (e % m) == (e / m) ? 1.0 : 0.0;
-      for (int64_t e = tid; e < n * m; e += kT) V[e] = P[e];
+      for (int64_t e = tid; e < m * m; e += kTT) U[e] = (e % m) == (e / m) ? 1.0 : 0.0;
+      for (int64_t e = tid; e < n * m; e += kTT) V[e] = P[e];
       r = m;
     } else {
-      for (int64_t e = tid; e < m * n; e += kT) {
+      for (int64_t e = tid; e < m * n; e += kTT) {
         const int64_t i = e % m, j = e / m;
         double s = 0;
         for (int64_t c = 0; c < r; ++c) s += U[c * m + i] * V[c * n + j];
         P[e] = s;
       }
       __syncthreads();
-      for (int64_t e = tid; e < m * n; e += kT) U[e] = P[e];
-      for (int64_t e = tid; e < n * n; e += kT) V[e] = (e % n) == (e / n) ? 1.0 : 0.0;
+      for (int64_t e = tid; e < m * n; e += kTT) U[e] = P[e];
+      for (int64_t e = tid; e < n * n; e += kTT) V[e] = (e % n) == (e / n) ? 1.0 : 0.0;
       r = n;
     }
     __syncthreads();
@@ -320,7 +321,7 @@ hipError_t trsm(const double* D, int64_t ld, int m, int mode, double* Z, int64_t
 hipError_t trunc(const Part& p0, const Part& p1, int64_t m, int64_t n, double eps, double* scr, double* W,
                  double* X, int32_t* rank_out, int32_t* err, double* flog, hipStream_t s) {
   const size_t lds = (size_t)8 * kTruncLds;
-  hipLaunchKernelGGL(k_trunc, dim3(1), dim3(kT), lds, s, p0, p1, m, n, eps, scr, W, X, rank_out, err, flog);
+  hipLaunchKernelGGL(k_trunc, dim3(1), dim3(kTT), lds, s, p0, p1, m, n, eps, scr, W, X, rank_out, err, flog);
   return hipGetLastError();
 }
 
