@@ -18,7 +18,7 @@
 namespace hm {
 namespace dense {
 
-constexpr int kWThreads = 512;
+constexpr int kWThreads = 1024;
 constexpr int kWWaves = kWThreads / 64;
 constexpr int kMaxR = 256;    // widest factor pair the shared arrays hold
 constexpr int kJacobiLanes = 8;   // lanes that rotate one column pair of the Jacobi step
