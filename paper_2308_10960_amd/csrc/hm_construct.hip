@@ -41,6 +41,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kThreads = 256;
+constexpr int kRecompressThreads = 512;   // the truncation core's workgroup for the recompression
 constexpr int kWaves = kThreads / 64;
 
 struct CKern {
@@ -205,11 +206,11 @@ __global__ __launch_bounds__(kThreads) void k_aca(const hm_cblock* __restrict__ 
 
 // Algorithm 1 on the ACA factors of one leaf whose ACA rank r lies in
 // (rlo, rhi] (the other leaves of the launch return at once), one workgroup
-// of dense::kWThreads threads per leaf.  LDS
+// of kRecompressThreads threads per leaf.  LDS
 // (dynamic): the r x r matrix being orthogonalized (B, then U_s diag(S)) and
 // V_s, both column-major with leading dimension r.  Output: W (m x k) at
 // out, X (n x k) at out + m cap, s (k) at out + (m + n) cap; rank = k.
-__global__ __launch_bounds__(dense::kWThreads) void k_recompress(const hm_cblock* __restrict__ blocks, int rlo, int rhi,
+__global__ __launch_bounds__(kRecompressThreads) void k_recompress(const hm_cblock* __restrict__ blocks, int rlo, int rhi,
                                                           double eps, int keep_sigma, double* __restrict__ out,
                                                           double* __restrict__ scr,
                                                           const int32_t* __restrict__ aca_rank,
@@ -306,7 +307,7 @@ hipError_t launch_construct(const hm_cblock* d_blocks, int64_t n_blocks, const d
   for (int c = 0; c < 3; ++c) {
     const int lo = bounds[c], hi = bounds[c + 1];
     if (hi <= lo) continue;
-    hipLaunchKernelGGL(k_recompress, grid, dim3(dense::kWThreads), (size_t)16 * hi * hi, s, d_blocks, lo, hi, o.eps,
+    hipLaunchKernelGGL(k_recompress, grid, dim3(kRecompressThreads), (size_t)16 * hi * hi, s, d_blocks, lo, hi, o.eps,
                        o.keep_sigma, d_out, d_scr, d_aca_rank, d_rank);
   }
   return hipGetLastError();

@@ -4,9 +4,10 @@
 // and the truncation core of Algorithm 1 (Sec. 2.2) on two factors whose
 // small SVD runs in LDS.
 //
-// Every routine is called by all kWThreads threads of one workgroup; every
-// reduction has a fixed order and broadcasts its result, so control flow
-// that depends on a reduced value is uniform across the workgroup.
+// Every routine is called by all threads of one workgroup (a multiple of 64,
+// at most kWThreads); every reduction has a fixed order and broadcasts its
+// result, so control flow that depends on a reduced value is uniform across
+// the workgroup.
 #pragma once
 
 #include <algorithm>
@@ -18,10 +19,15 @@
 namespace hm {
 namespace dense {
 
-constexpr int kWThreads = 1024;
+constexpr int kWThreads = 1024;              // largest workgroup the routines below are called by
 constexpr int kWWaves = kWThreads / 64;
 constexpr int kMaxR = 256;    // widest factor pair the shared arrays hold
 constexpr int kJacobiLanes = 8;   // lanes that rotate one column pair of the Jacobi step
+
+// Threads and waves of the calling workgroup (at most kWThreads, a multiple
+// of 64): the routines below run on workgroups of any such size.
+__device__ __forceinline__ int nthreads() { return (int)blockDim.x; }
+__device__ __forceinline__ int nwaves() { return (int)blockDim.x >> 6; }
 
 // v of the lane that the DPP pattern CTRL names (rows in ROW_MASK; the lanes
 // of the other rows get 0).  Both 32-bit halves move the same way.
@@ -58,17 +64,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Sum over a workgroup of NW waves, the same value in every thread.  sred:
-// NW doubles of LDS; the call synchronizes twice.
-template <int NW = kWWaves>
+// Sum over a workgroup of NW waves (NW = 0: all of the calling workgroup's),
+// the same value in every thread.  sred: one double per wave of LDS; the call
+// synchronizes twice.
+template <int NW = 0>
 __device__ __forceinline__ double block_sum(double v, double* sred) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) sred[wave] = v;
   __syncthreads();
   double s = 0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) s += sred[w];
+  const int nw = NW > 0 ? NW : nwaves();            // NW = 0: the workgroup's waves
+  for (int w = 0; w < nw; ++w) s += sred[w];
   __syncthreads();
   return s;
 }
@@ -108,7 +115,7 @@ __device__ inline void qr_waves(double* A, int lda, int m, int r, double* tau) {
       tk = -v0 / alpha;
     }
     if (tk != 0)
-      for (int j = k + 1 + w; j < r; j += kWWaves) {
+      for (int j = k + 1 + w; j < r; j += nwaves()) {
         double* c = A + (int64_t)j * lda;
         double s = 0;
         for (int i = k + 1 + lane; i < m; i += 64) s += a[i] * c[i];
@@ -138,7 +145,7 @@ __device__ inline void qr_waves(double* A, int lda, int m, int r, double* tau) {
 __device__ inline void apply_q_waves(const double* A, int lda, int m, int r, const double* tau, double* Z, int ldz,
                                      int k, const int* cols = nullptr) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int c = w; c < k; c += kWWaves) {
+  for (int c = w; c < k; c += nwaves()) {
     double* z = Z + (int64_t)(cols ? cols[c] : c) * ldz;
     for (int j = r - 1; j >= 0; --j) {
       const double tj = tau[j];
@@ -157,7 +164,7 @@ __device__ inline void apply_q_waves(const double* A, int lda, int m, int r, con
 
 // Copies a (rows x cols) between column-major arrays, workgroup-wide.
 __device__ inline void copy_mat(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols) {
-  for (int64_t e = threadIdx.x; e < rows * cols; e += kWThreads) dst[(e / rows) * ldd + e % rows] = src[(e / rows) * lds + e % rows];
+  for (int64_t e = threadIdx.x; e < rows * cols; e += nthreads()) dst[(e / rows) * ldd + e % rows] = src[(e / rows) * lds + e % rows];
   __syncthreads();
 }
 
@@ -222,21 +229,21 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   double* Am = 2 * (int64_t)r * r <= lds_doubles ? lds : gscr;
   double* Vs = Am + (int64_t)r * r;
   // R_U -> Am, R_V -> Vs (upper triangles), then B = R_U R_V^T into W (r x r)
-  for (int e = tid; e < r * r; e += kWThreads) {
+  for (int e = tid; e < r * r; e += nthreads()) {
     const int i = e % r, l = e / r;
     Am[e] = i <= l ? U[(int64_t)l * m + i] : 0.0;
     Vs[e] = i <= l ? V[(int64_t)l * n + i] : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < r * r; e += kWThreads) {
+  for (int e = tid; e < r * r; e += nthreads()) {
     const int i = e % r, j = e / r;
     double s = 0;
     for (int l = std::max(i, j); l < r; ++l) s += Am[l * r + i] * Vs[l * r + j];
     W[e] = s;
   }
   __syncthreads();
-  for (int e = tid; e < r * r; e += kWThreads) Am[e] = W[e];
-  for (int j = tid; j < r; j += kWThreads) sh.perm[j] = j;
+  for (int e = tid; e < r * r; e += nthreads()) Am[e] = W[e];
+  for (int j = tid; j < r; j += nthreads()) sh.perm[j] = j;
   __syncthreads();
   // QR with column pivoting of B (B P = Q_B R; in place in Am): the
   // largest remaining column first, the lowest index on ties.  Column norms
@@ -246,7 +253,7 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   // then converges in a few sweeps, R being graded.
   const int lane = tid & 63, wv = tid >> 6;
   for (int k = 0; k < r; ++k) {
-    for (int j = k + wv; j < r; j += kWWaves) {
+    for (int j = k + wv; j < r; j += nwaves()) {
       double s2 = 0;
       for (int i = k + lane; i < r; i += 64) s2 += Am[j * r + i] * Am[j * r + i];
       s2 = wave_sum(s2);
@@ -292,7 +299,7 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
       tk = -v0 / alpha;
     }
     if (tk != 0)
-      for (int j = k + 1 + wv; j < r; j += kWWaves) {
+      for (int j = k + 1 + wv; j < r; j += nwaves()) {
         double* c = Am + j * r;
         double s = 0;
         for (int i = k + 1 + lane; i < r; i += 64) s += a[i] * c[i];
@@ -317,9 +324,9 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   // after Am and Vs when there is room, else X), then Am := R^T (lower
   // triangular), Vs := I
   double* Qb = (Am == lds && 3 * (int64_t)r * r <= lds_doubles) ? lds + 2 * (int64_t)r * r : X;
-  for (int e = tid; e < r * r; e += kWThreads) Qb[e] = Am[e];
+  for (int e = tid; e < r * r; e += nthreads()) Qb[e] = Am[e];
   __syncthreads();
-  for (int e = tid; e < r * r; e += kWThreads) {
+  for (int e = tid; e < r * r; e += nthreads()) {
     const int i = e % r, j = e / r;                  // Am(i, j) = R(j, i)
     Am[e] = j <= i ? Qb[i * r + j] : 0.0;
     Vs[e] = i == j ? 1.0 : 0.0;
@@ -330,11 +337,11 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   // pair with the player r, when r is odd, is skipped); afterwards
   // Am = R^T Vs has orthogonal columns
   const int R = r + (r & 1);
-  const int grp = tid / kJacobiLanes, gl = tid % kJacobiLanes, ngrp = kWThreads / kJacobiLanes;
+  const int grp = tid / kJacobiLanes, gl = tid % kJacobiLanes, ngrp = nthreads() / kJacobiLanes;
   // columns below 1e-16 |B|_F carry no singular value the truncation can
   // see and only rounding noise: pairs with such a column are not rotated
   double fro2 = 0;
-  for (int e = tid; e < r * r; e += kWThreads) fro2 += Am[e] * Am[e];
+  for (int e = tid; e < r * r; e += nthreads()) fro2 += Am[e] * Am[e];
   const double tiny = 1e-32 * block_sum(fro2, sh.sv);
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0;
@@ -394,13 +401,13 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
     __syncthreads();
   }
   // singular values: column norms, sorted descending (stable)
-  for (int j = tid; j < r; j += kWThreads) {
+  for (int j = tid; j < r; j += nthreads()) {
     double s2 = 0;
     for (int i = 0; i < r; ++i) s2 += Am[j * r + i] * Am[j * r + i];
     sh.nrm[j] = sqrt(s2);
   }
   __syncthreads();
-  for (int j = tid; j < r; j += kWThreads) {
+  for (int j = tid; j < r; j += nthreads()) {
     int pos = 0;
     for (int l = 0; l < r; ++l) pos += sh.nrm[l] > sh.nrm[j] || (sh.nrm[l] == sh.nrm[j] && l < j);
     sh.ord[pos] = j;
@@ -427,15 +434,15 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   // W = Q_U [left(:, 1:k); 0], X = Q_V [right(:, 1:k); 0]
   for (int c = 0; c < k; ++c) {
     const int j = sh.ord[c];
-    for (int64_t i = tid; i < m; i += kWThreads) W[(int64_t)c * m + i] = i < r ? Vs[j * r + i] : 0.0;
+    for (int64_t i = tid; i < m; i += nthreads()) W[(int64_t)c * m + i] = i < r ? Vs[j * r + i] : 0.0;
   }
   __syncthreads();                                  // the reflectors in Qb are read no more
   for (int c = 0; c < k; ++c) {
     const int j = sh.ord[c];
     const double inv = sh.S[c] > 0 ? 1.0 / sh.S[c] : 0.0;
-    for (int64_t i = tid; i < n; i += kWThreads) X[(int64_t)c * n + i] = 0.0;
+    for (int64_t i = tid; i < n; i += nthreads()) X[(int64_t)c * n + i] = 0.0;
     __syncthreads();
-    for (int i = tid; i < r; i += kWThreads) X[(int64_t)c * n + sh.perm[i]] = Am[j * r + i] * inv;
+    for (int i = tid; i < r; i += nthreads()) X[(int64_t)c * n + sh.perm[i]] = Am[j * r + i] * inv;
   }
   __syncthreads();
   // W := Q_U W, X := Q_V X: reflectors and result in LDS (apply_q_waves) when they fit
@@ -455,7 +462,7 @@ __device__ inline int truncate_core(double* U, int64_t m, double* V, int64_t n, 
   for (int c = 0; c < k; ++c) {
     if (sg && tid == 0) sg[c] = sh.S[c];
     if (fold)
-      for (int64_t i = tid; i < m; i += kWThreads) W[(int64_t)c * m + i] *= sh.S[c];
+      for (int64_t i = tid; i < m; i += nthreads()) W[(int64_t)c * m + i] *= sh.S[c];
   }
   __syncthreads();
   return k;
